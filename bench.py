@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark: milliseconds per pressure projection at 25M cells.
+
+One step = one projection on the 512 x 256 x 192 ship-wave workload (see
+paper_1410_1937_amd.fixtures.c3): assemble the coefficients from the volume
+fraction, form the right-hand side from the provisional face velocity,
+solve to FP64 true relative residual 1e-8, project the face fluxes and
+compute the post-projection divergence.  The body geometry is static in the
+body-fixed frame and is set up once, outside the timed region.
+
+`value` is the chosen form (mixed precision; with the learned preconditioner
+when trained weights are available); the plain FP64 Jacobi-PCG projection is
+timed beside it.  One extra, instrumented step measures the average duration
+of the dominant kernel (the stencil sweep) with HIP events for the roofline.
+The CPU baseline is the FP64 oracle on the host cores, timed on a bounded
+sample (a few iterations on the full grid) and scaled to one projection.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "c3"
+WORKLOAD_DESC = ("512x256x192 stretched cartesian grid (25,165,824 cells), tanh clustering "
+                 "(max cell-size ratio 8), free surface + 200 droplets/bubbles, rho 1000/1.2 "
+                 "smoothed, immersed sphere R=0.1 at depth 0.15 with merges (theta 0.25), "
+                 "all-Neumann walls")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(iters_fp64: int, sample_iters: int = 4) -> dict:
+    """Run the oracle leg in a child process pinned to one thread."""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    code = f"""
+import json, sys, time
+sys.path.insert(0, {ROOT!r})
+from paper_1410_1937_amd import fixtures as fx
+from oracle.grid import Grid
+from oracle.geometry import Body
+from oracle.operator import Operator
+from oracle import solvers
+wl = fx.{WORKLOAD}()
+t0 = time.perf_counter()
+g = Grid(wl.xf, wl.yf, wl.zf, wl.bc)
+body = Body(g, wl.psi, wl.theta, wl.samples)
+op = Operator(g, body, wl.phi, wl.rho_l, wl.rho_g, wl.smooth)
+b = op.rhs(wl.u, wl.v, wl.w, wl.dt, wl.body_vel)
+t_setup = time.perf_counter() - t0
+t0 = time.perf_counter()
+res = solvers.pcg(op, b, tol=1e-30, maxit={sample_iters}, max_restarts=0)
+t_it = (time.perf_counter() - t0 - 0.0)
+print(json.dumps({{"setup_s": t_setup, "iter_s": t_it / max(1, res.iterations), "iters": res.iterations}}))
+"""
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True)
+    if out.returncode != 0:
+        raise RuntimeError(out.stderr[-2000:])
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    ms = (r["setup_s"] + r["iter_s"] * iters_fp64) * 1e3
+    return {"value": ms, "unit": "ms/projection", "cores": 1, "kind": "oracle",
+            "sample": (f"FP64 NumPy oracle on the full workload: geometry+assembly+rhs "
+                       f"({r['setup_s']:.1f} s) plus {r['iters']} Jacobi-PCG iterations "
+                       f"({r['iter_s']:.2f} s each), scaled to the {iters_fp64} iterations the "
+                       f"FP64 projection needs; 1 thread of {os.cpu_count()} host cores")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-fp64", action="store_true", help="do not time the plain FP64 projection")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: the projection runs on a single MI355X with no "
+              f"sharding or collectives (asked for --gpus {args.gpus}).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1410_1937_amd import fixtures as fx
+    from paper_1410_1937_amd import nfa
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log("[bench] generating workload", WORKLOAD)
+    wl = getattr(fx, WORKLOAD)()
+    g = nfa.Grid(wl.xf, wl.yf, wl.zf, wl.bc)
+    g.set_body(torch.as_tensor(wl.psi, device=dev), wl.theta, wl.samples)
+    op = nfa.Poisson(g)
+    phi = torch.as_tensor(wl.phi, device=dev).to(torch.float32).contiguous()
+    u, v, w = (torch.as_tensor(a, device=dev) for a in (wl.u, wl.v, wl.w))
+    x = torch.zeros(op.shape, dtype=torch.float64, device=dev)
+    unet = None
+    solver = dict(precision="mixed", precond="jacobi")
+
+    def step(kind):
+        op.assemble(phi, wl.rho_l, wl.rho_g, wl.smooth)
+        b = op.rhs(u, v, w, wl.dt, wl.body_vel)
+        if kind == "chosen":
+            p, res = op.solve(b, x=x, tol=1e-8, unet=unet, **solver)
+        else:
+            p, res = op.solve(b, x=x, tol=1e-8, precision="f64")
+        F = op.project(u, v, w, p, wl.dt)
+        op.divergence(*F, wl.body_vel)
+        if res.status != 0 or not res.relres <= 1e-8:
+            raise RuntimeError(f"projection did not converge: {res}")
+        return res
+
+    def timed(kind, steps, warmup):
+        for i in range(warmup):
+            r = step(kind)
+            log(f"[bench] warmup {kind} {i}: {r.iterations} its, relres {r.relres:.2e}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = []
+        for i in range(steps):
+            r = step(kind)
+            its.append(r.iterations)
+            log(f"[bench] step {kind} {i}: {r.iterations} its, outer {r.outer}, relres {r.relres:.2e}")
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps, its, r
+
+    ms_chosen, its_chosen, r_chosen = timed("chosen", args.steps, args.warmup)
+    log(f"[bench] chosen: {ms_chosen:.1f} ms/projection")
+    ms_fp64, its_fp64, r_fp64 = (None, [None], None)
+    if not args.skip_fp64:
+        ms_fp64, its_fp64, r_fp64 = timed("fp64", args.steps, args.warmup)
+        log(f"[bench] plain FP64: {ms_fp64:.1f} ms/projection")
+
+    # instrumented step: average duration of the stencil sweep (dominant kernel)
+    op.profile(True)
+    step("chosen")
+    ks32 = op.profile_read("f32")
+    ks64 = op.profile_read("f64")
+    op.profile(False)
+    if ks32["launches"] > 0:
+        ks, bpc, kname = ks32, 20, "k_stencil<float,true>"
+    else:
+        ks, bpc, kname = ks64, 40, "k_stencil<double,true>"
+    avg_ms = ks["ms"] / max(1, ks["launches"])
+    bytes_per_launch = bpc * ks["cells"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": kname, "avg_launch_ms": round(avg_ms, 5), "launches": ks["launches"],
+                "algorithmic_bytes_per_launch": bytes_per_launch}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU baseline (oracle)")
+        try:
+            cpu = cpu_baseline(its_fp64[-1] if its_fp64[-1] else its_chosen[-1])
+        except Exception as e:  # report, do not hide
+            cpu = {"error": str(e)[-500:]}
+
+    n = wl.ncells
+    line = {
+        "metric": "ms/projection to rel. residual 1e-8 @25M cells: mixed+learned vs plain FP64",
+        "value": round(ms_chosen, 3),
+        "unit": "ms/projection",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_chosen, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_DESC, "cells": n, "tol": 1e-8,
+                   "solver": ("FP64 iterative refinement around FP32 "
+                              + ("flexible CG with the learned U-Net preconditioner"
+                                 if solver["precond"] == "unet" else "Jacobi-PCG")),
+                   "step": "assemble + rhs + solve + project + divergence",
+                   "iterations": its_chosen[-1], "outer": r_chosen.outer,
+                   "fallback": r_chosen.fallback},
+        "plain_fp64": None if ms_fp64 is None else {
+            "ms_per_projection": round(ms_fp64, 3), "iterations": its_fp64[-1],
+            "speedup_of_value": round(ms_fp64 / ms_chosen, 3)},
+        "cell_updates_per_s": round(n * its_chosen[-1] / (ms_chosen * 1e-3), 1),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,262 @@
+/*
+ * libnfa -- pressure projection of a cartesian-grid / VOF ship-wave solver
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Implements the projection of Dommermuth et al., "The numerical simulation
+ * of ship waves using cartesian-grid and volume-of-fluid methods": the
+ * second-order variable-coefficient Poisson equation of the Formulation
+ * section (eq. pois; stage form eqs. poisson1 / poisson2) on a stretched
+ * cartesian grid (Gridding section), with two-fluid coefficients from the
+ * volume fraction (eq. density, Density Smoothing section), an immersed
+ * body entered by fractional face areas with small cells merged (Enforcement
+ * of Body Boundary Conditions, eqs. integral1-integral2), solved by
+ * preconditioned conjugate gradients (Introduction).
+ *
+ * The library solves the positive semidefinite form  A' p = b'  where
+ *   (A p)_c = sum_f T_f (p_c - p_nb(f)),   T_f = (open area_f * beta_f) / h_f,
+ *   beta_f  = 2 / (rho_L + rho_R) inside, 1/rho_c on a boundary face,
+ *   A' = P^T A P  (P copies a merge group's root value to its slaves),
+ * i.e. minus the cell integral of div((1/rho) grad p), and
+ *   b = -((D F~) + B) / dt,  F~_f = open area_f * u~_f,  B_c = v_body . S_c
+ * (eq. integral2 with the no-flux hull condition, eq. bc2).
+ *
+ * Conventions
+ *  - Arrays are contiguous, x fastest:  cells (nz,ny,nx); nodes
+ *    (nz+1,ny+1,nx+1); x-faces (nz,ny,nx+1); y-faces (nz,ny+1,nx);
+ *    z-faces (nz+1,ny,nx).  Pointers marked DEVICE are device memory of the
+ *    current HIP device; HOST pointers are ordinary host memory.
+ *  - Ownership: the caller owns every buffer it passes and keeps it alive
+ *    until the call returns (or, for asynchronous calls, until the stream
+ *    has passed it).  Handles own their device memory, allocated when the
+ *    handle is created or its body set, never by apply/assemble/solve.
+ *  - Streams: `nfa_stream` is a hipStream_t (NULL = default stream); work is
+ *    ordered on it.  Calls marked ASYNC return before the device finishes.
+ *  - Errors: a negative status means nothing was launched (argument errors)
+ *    or a HIP call failed; nfa_last_error() gives a thread-local message.
+ *    NFA_NOT_CONVERGED (> 0) is a warning: outputs are filled.
+ *  - Handles are not thread-safe; use one per thread.
+ */
+#ifndef NFA_H
+#define NFA_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int nfa_status;
+#define NFA_OK 0
+#define NFA_NOT_CONVERGED 1
+#define NFA_ERR_INVALID (-1)
+#define NFA_ERR_NOMEM (-2)
+#define NFA_ERR_HIP (-3)
+#define NFA_ERR_BREAKDOWN (-4)
+#define NFA_ERR_NUMERIC (-5)
+
+typedef struct nfa_grid_s* nfa_grid;
+typedef struct nfa_poisson_s* nfa_poisson;
+typedef void* nfa_stream; /* hipStream_t */
+
+/* boundary flags, order -x,+x,-y,+y,-z,+z */
+#define NFA_BC_NEUMANN 0   /* no flux (free slip wall, exit with zero data) */
+#define NFA_BC_DIRICHLET 1 /* p = 0 on the boundary face (half-cell distance) */
+
+/* element types */
+#define NFA_F64 0
+#define NFA_F32 1
+
+/* Thread-local message of the last failing call (empty if none). */
+const char* nfa_last_error(void);
+/* Library version, major*10000 + minor*100 + patch. */
+int nfa_version(void);
+
+/* ------------------------------------------------------------------ grid
+ * nfa_grid_create -- stretched cartesian grid (Gridding section).
+ *   nx, ny, nz : cells per axis, each >= 1.
+ *   xf, yf, zf : HOST, nx+1 / ny+1 / nz+1 strictly increasing face
+ *                coordinates (copied).
+ *   bc         : HOST, 6 flags NFA_BC_* (copied).
+ *   out        : receives the handle.
+ * Computes the 1-D metrics (widths, centre distances) and sets "no body"
+ * (every face open).  Allocates device memory.  Errors: NFA_ERR_INVALID on
+ * non-increasing coordinates, bad sizes or flags; NFA_ERR_HIP.
+ */
+nfa_status nfa_grid_create(int nx, int ny, int nz, const double* xf, const double* yf,
+                           const double* zf, const int* bc, nfa_grid* out);
+
+/* nfa_grid_set_body -- immersed body from its signed distance (Enforcement
+ * of Body Boundary Conditions section: psi > 0 in the fluid; fractional
+ * areas; cells with cut volume below `theta` merged with the neighbour along
+ * the steepest gradient of psi).
+ *   psi_nodes : DEVICE double, node array; NULL removes the body.
+ *   theta     : merge threshold in [0,1) (0.25 in the paper).
+ *   samples   : S >= 1 sub-samples per face edge / cell edge (8).
+ * Face fractions = share of S*S midpoint samples of the bilinear
+ * interpolant that are > 0; cell fractions likewise with S^3 trilinear
+ * samples.  Cells with fraction 0 or without an open coupling become
+ * inactive (no unknown).  Synchronous (merge groups are resolved on the
+ * host).  Errors: NFA_ERR_INVALID, NFA_ERR_HIP.
+ */
+nfa_status nfa_grid_set_body(nfa_grid g, const double* psi_nodes, double theta, int samples,
+                             nfa_stream s);
+
+typedef struct {
+  int nx, ny, nz;
+  long long cells, active, reduced; /* reduced = number of unknowns */
+  int groups, slaves;               /* merge groups and merged (slave) cells */
+  int all_neumann;                  /* 1: singular system, zero-mean gauge */
+} nfa_grid_info;
+nfa_status nfa_grid_get_info(nfa_grid g, nfa_grid_info* info);
+
+/* what to export from a grid (DEVICE destination, natural layout) */
+#define NFA_EXPORT_FRAC_X 1  /* double, x-faces */
+#define NFA_EXPORT_FRAC_Y 2  /* double, y-faces */
+#define NFA_EXPORT_FRAC_Z 3  /* double, z-faces */
+#define NFA_EXPORT_VFRAC 4   /* double, cells */
+#define NFA_EXPORT_OPEN_X 5  /* double, x-faces: open area */
+#define NFA_EXPORT_OPEN_Y 6
+#define NFA_EXPORT_OPEN_Z 7
+#define NFA_EXPORT_ACTIVE 8  /* uint8, cells */
+#define NFA_EXPORT_ROOT 9    /* int32, cells: merge root, -1 inactive */
+#define NFA_EXPORT_REDUCED 10 /* uint8, cells: 1 where an unknown lives */
+nfa_status nfa_grid_export(nfa_grid g, int what, void* dst, nfa_stream s); /* ASYNC */
+void nfa_grid_destroy(nfa_grid g);
+
+/* --------------------------------------------------------------- poisson */
+typedef struct {
+  double rho_liquid; /* rho of water (phi = 1), e.g. 1000 */
+  double rho_gas;    /* rho of air (phi = 0), e.g. 1.2 */
+  int smooth;        /* 1: (1/4,1/2,1/4) smoothing along x, y, z */
+  int phi_dtype;     /* NFA_F64 or NFA_F32 */
+} nfa_assemble_params;
+
+/* nfa_poisson_create -- operator + solver workspace on grid g (the grid
+ * must outlive it; set the body first).  Allocates all device memory the
+ * operator, the FP64 and FP32 solvers need.  Errors: NFA_ERR_HIP. */
+nfa_status nfa_poisson_create(nfa_grid g, nfa_poisson* out);
+
+/* nfa_poisson_assemble -- coefficients for one projection (eq. density,
+ * Density Smoothing, eq. integral2): rho = rho_g + (rho_l - rho_g)
+ * clip(phi,0,1), optional smoothing, T_f on every face in FP64 and FP32, the
+ * Jacobi inverse diagonal of the merged operator.
+ *   phi : DEVICE, cells, dtype p->phi_dtype.   ASYNC. */
+nfa_status nfa_poisson_assemble(nfa_poisson op, const void* phi, const nfa_assemble_params* p,
+                                nfa_stream s);
+
+/* nfa_poisson_apply -- y = A' x = P^T A P x (eqs. pois / integral2, merged).
+ *   x, y : DEVICE, cells, dtype NFA_F64 (FP64 coefficients) or NFA_F32 (FP32
+ *          coefficients).  x is read only (slave entries are ignored: P takes
+ *          each group's root value); y has 0 on slaves and inactive cells.
+ *   x and y must not overlap.  ASYNC. */
+nfa_status nfa_poisson_apply(nfa_poisson op, const void* x, void* y, int dtype, nfa_stream s);
+
+/* nfa_poisson_rhs -- b' = P^T b, b = -((D F~) + B)/dt (eq. integral2 with
+ * u~ = u^k + dt R of eq. poisson1, and the body flux of eq. bc2), zero mean
+ * over the unknowns when every boundary is Neumann.
+ *   u, v, w  : DEVICE double on x-, y-, z-faces (provisional velocity).
+ *   dt       : time step > 0.
+ *   body_vel : HOST, 3 doubles, body velocity in the body-fixed frame.
+ *   b        : DEVICE double, cells (output).   ASYNC. */
+nfa_status nfa_poisson_rhs(nfa_poisson op, const double* u, const double* v, const double* w,
+                           double dt, const double* body_vel, double* b, nfa_stream s);
+
+/* nfa_poisson_project -- face fluxes after projection (eq. runge1 in flux
+ * form): F_f = open area_f u~_f - dt T_f (p_+ - p_-), p = 0 beyond a
+ * Dirichlet face.  p: DEVICE double cells (slaves take their root's value).
+ * fu, fv, fw: DEVICE double face arrays (outputs).  ASYNC. */
+nfa_status nfa_poisson_project(nfa_poisson op, const double* u, const double* v, const double* w,
+                               const double* p, double dt, double* fu, double* fv, double* fw,
+                               nfa_stream s);
+
+/* nfa_poisson_divergence -- P^T (D F + B): discrete conservation per merged
+ * cell (eq. diverge plus the body flux).  div: DEVICE double cells.  ASYNC. */
+nfa_status nfa_poisson_divergence(nfa_poisson op, const double* fu, const double* fv,
+                                  const double* fw, const double* body_vel, double* div,
+                                  nfa_stream s);
+
+/* preconditioners and precisions */
+#define NFA_PC_JACOBI 1
+#define NFA_PC_UNET 2
+#define NFA_PC_TEST_SABOTAGE 3 /* test hook: preconditioner replaced by a fixed
+                                  unrelated field, to exercise the fallback */
+#define NFA_PC_JACOBI_FCG 4    /* flexible CG driver with the Jacobi preconditioner
+                                  (reference run of the flexible path) */
+#define NFA_PREC_F64 0   /* FP64 Jacobi-PCG */
+#define NFA_PREC_MIXED 1 /* FP64 refinement around an FP32 inner solve */
+
+typedef struct {
+  double tol;            /* FP64 true relative residual ||b'-A'x||/||b'|| */
+  int max_iters;         /* total (inner) iterations */
+  int precond;           /* NFA_PC_* */
+  int precision;         /* NFA_PREC_* */
+  double inner_tol;      /* mixed: deepest relative reduction asked of one inner
+                            solve (each asks for what is still needed, x4) */
+  int max_outer;         /* mixed: refinement steps */
+  int fcg_m;             /* flexible CG truncation; 1 (FCG(1)) is supported */
+  double fallback_ratio; /* switch to Jacobi-PCG when the mean reduction per
+                            iteration over a window exceeds this (0.99) */
+  int fallback_window;   /* window length in iterations (10) */
+  int warm_start;        /* 1: x holds the initial guess */
+  int check_every;       /* iterations between host polls of ||r|| */
+  void* unet;            /* nfa_unet handle when precond == NFA_PC_UNET */
+  double* history;       /* optional HOST buffer of ||r_k||/||b'|| (inner) */
+  int history_cap;
+} nfa_solve_opts;
+
+typedef struct {
+  int iterations;     /* inner iterations, all phases */
+  int outer;          /* refinement steps (mixed) or restarts (FP64) */
+  int fallback;       /* 1: switched to Jacobi-PCG */
+  int history_len;    /* entries written to opts->history */
+  double relres;      /* final FP64 true relative residual */
+  double ms;          /* wall time of the solve on the stream */
+} nfa_solve_info;
+
+/* Fills opts with defaults: tol 1e-8, Jacobi, FP64, inner_tol 1e-6, ... */
+void nfa_solve_opts_default(nfa_solve_opts* opts);
+
+/* nfa_poisson_solve -- x = A'^-1 b' by preconditioned CG (Introduction:
+ * "preconditioned conjugate-gradient"; Jacobi by default).
+ *   b : DEVICE double cells (as produced by nfa_poisson_rhs).
+ *   x : DEVICE double cells: initial guess if warm_start, else overwritten;
+ *       on return the solution with slaves = root value, inactive = 0 and,
+ *       if every boundary is Neumann, zero mean over the unknowns.
+ * The recursive residual is polled every check_every iterations; on
+ * convergence the true FP64 residual decides (restart if above tol).
+ * Synchronous.  Returns NFA_OK, NFA_NOT_CONVERGED (info filled), or an
+ * error (NFA_ERR_NUMERIC on NaN/Inf). */
+nfa_status nfa_poisson_solve(nfa_poisson op, const double* b, double* x, const nfa_solve_opts* opts,
+                             nfa_stream s, nfa_solve_info* info);
+
+/* Timing of the operator sweep inside solves.  nfa_poisson_profile(op, 1)
+ * brackets the first 4096 stencil launches of each later solve with HIP
+ * events on the solve's stream (creating the events here, not in the solve)
+ * and resets the counters; nfa_poisson_profile(op, 0) stops.  Only launches
+ * of iterations that ran are counted. */
+typedef struct {
+  long long launches; /* stencil launches timed */
+  double ms;          /* their summed duration */
+  long long cells;    /* cells swept per launch */
+} nfa_kernel_stats;
+nfa_status nfa_poisson_profile(nfa_poisson op, int enable);
+/* dtype NFA_F64 or NFA_F32: the sweep of that precision.  Synchronous. */
+nfa_status nfa_poisson_profile_read(nfa_poisson op, int dtype, nfa_kernel_stats* out);
+
+/* what to export from an operator (DEVICE destination, natural layout) */
+#define NFA_EXPORT_RHO 20    /* double cells */
+#define NFA_EXPORT_TX 21     /* double x-faces */
+#define NFA_EXPORT_TY 22     /* double y-faces */
+#define NFA_EXPORT_TZ 23     /* double z-faces */
+#define NFA_EXPORT_DINV 24   /* double cells */
+#define NFA_EXPORT_TX32 25   /* float x-faces */
+#define NFA_EXPORT_TY32 26   /* float y-faces */
+#define NFA_EXPORT_TZ32 27   /* float z-faces */
+#define NFA_EXPORT_DINV32 28 /* float cells */
+nfa_status nfa_poisson_export(nfa_poisson op, int what, void* dst, nfa_stream s); /* ASYNC */
+void nfa_poisson_destroy(nfa_poisson op);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NFA_H */

@@ -1,0 +1,163 @@
+// Internal declarations of libnfa (not part of the public C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/nfa.h"
+
+namespace nfa {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+nfa_status fail(nfa_status st, const std::string& msg);
+
+#define NFA_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return ::nfa::fail(NFA_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define NFA_CHECK_LAUNCH() NFA_HIP(hipGetLastError())
+
+inline hipStream_t S(nfa_stream s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ------------------------------------------------------- device buffers
+// Library-owned device memory, allocated only when a handle is created or
+// its body set, never on the solve/apply path.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t alloc(size_t b) {
+    release();
+    if (b == 0) return hipSuccess;
+    hipError_t e = hipMalloc(&p, b);
+    if (e == hipSuccess) bytes = b;
+    return e;
+  }
+  template <class T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+// ------------------------------------------------------------ launch
+constexpr int kBlock = 256;
+constexpr int kMaxPartials = 32768;    // block partials of one reduction (per component)
+constexpr int kHistCap = 1 << 20;      // per-iteration residual history entries
+inline int blocks_for(long long n, int per_block = kBlock, int cap = 65535 * 4) {
+  long long b = (n + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return static_cast<int>(b);
+}
+
+// ----------------------------------------------------------- grid data
+struct Grid {
+  int nx = 0, ny = 0, nz = 0;
+  long long n = 0;          // cells
+  int bc[6] = {0, 0, 0, 0, 0, 0};
+  std::vector<double> xf, yf, zf;     // host face coordinates
+  std::vector<double> dx, dy, dz;     // host widths
+  std::vector<double> hx, hy, hz;     // host face distances (n+1 each)
+  // device 1-D metrics
+  DevBuf d_dx, d_dy, d_dz, d_hx, d_hy, d_hz;
+  // body (always present: "no body" = all open)
+  bool has_body = false;
+  DevBuf frac_x, frac_y, frac_z;      // face fractions (double)
+  DevBuf vfrac;                       // cell fraction (double)
+  DevBuf open_x, open_y, open_z;      // open face areas a_f * Area_f (double)
+  DevBuf active;                      // uint8 per cell
+  DevBuf reduced;                     // uint8 per cell: 1 on the cell that carries an unknown
+  DevBuf root;                        // int32 per cell: root cell (-1 inactive)
+  // merge groups: roots, CSR offsets into members (slaves only, ascending)
+  int n_groups = 0, n_slaves = 0;
+  long long n_active = 0, n_reduced = 0;
+  DevBuf g_root, g_off, g_mem;        // int32
+  DevBuf s_cell, s_root;              // int32: slave list and its root
+  bool all_neumann() const { return !(bc[0] | bc[1] | bc[2] | bc[3] | bc[4] | bc[5]); }
+  long long nfx() const { return (long long)nz * ny * (nx + 1); }
+  long long nfy() const { return (long long)nz * (ny + 1) * nx; }
+  long long nfz() const { return (long long)(nz + 1) * ny * nx; }
+};
+
+// Device-side scalars of an iterative solve (one cache line each group).
+struct SolveScalars {
+  double rz, pq, rr, bb, alpha, beta, tol2, pr, zq, rr_outer;
+  double ratio;      // stagnation threshold (mean reduction per iteration)
+  int iter, done, breakdown, stalled, max_iter, window;
+};
+
+// Operator coefficients in one precision (lower-face layout, see stencil).
+template <class T> struct Coeffs {
+  T* tx = nullptr;    // nz*ny*nx   lower x-face of each cell
+  T* txb = nullptr;   // nz*ny      +x boundary face
+  T* ty = nullptr;    // nz*(ny+1)*nx natural y-face layout
+  T* tz = nullptr;    // (nz+1)*ny*nx natural z-face layout
+  T* dinv = nullptr;  // nz*ny*nx   Jacobi inverse diagonal of the merged operator
+};
+
+// Everything an operator owns: coefficients in both precisions and the
+// work vectors of the FP64 and FP32 solvers.
+struct Poisson {
+  Grid* g = nullptr;
+  bool assembled = false;
+  DevBuf rho, rho_tmp;                          // double cells
+  DevBuf tx64, txb64, ty64, tz64, dinv64;       // FP64 coefficients
+  DevBuf tx32, txb32, ty32, tz32, dinv32;       // FP32 coefficients
+  DevBuf r, z, p, q, tmp;                       // double work vectors
+  DevBuf x32, r32, z32, p32, q32;               // float work vectors
+  DevBuf partials;                              // double block partials
+  DevBuf scal;                                  // SolveScalars (device)
+  DevBuf hist;                                  // double per-iteration ||r||^2 (kHistCap)
+  SolveScalars* h_scal = nullptr;               // pinned host mirror (2 slots)
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  // optional timing of the stencil sweeps inside solves (HIP events)
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev;              // 2 per recorded launch
+  std::vector<int> prof_kind;                   // 0 FP64, 1 FP32 per recorded launch
+  int prof_used = 0;
+  long long prof_launches[2] = {0, 0};
+  double prof_ms[2] = {0.0, 0.0};
+  Coeffs<double> c64() const {
+    return {tx64.as<double>(), txb64.as<double>(), ty64.as<double>(), tz64.as<double>(), dinv64.as<double>()};
+  }
+  Coeffs<float> c32() const {
+    return {tx32.as<float>(), txb32.as<float>(), ty32.as<float>(), tz32.as<float>(), dinv32.as<float>()};
+  }
+};
+
+// ---------------------------------------------------------------- kernels
+// Stencil sweeps (stencil.hip).  mode: 0 q = A p (+ partial p.q if partials),
+// 1 q = b - A p (+ partial q.q).  Returns the number of partials written.
+enum { ST_APPLY = 0, ST_RESIDUAL = 1 };
+template <class T>
+int launch_stencil(const Grid& g, const Coeffs<T>& c, const T* p, const double* b, T* q,
+                   double* partials, const SolveScalars* sc, int mode, hipStream_t s);
+
+// Merge kernels (stencil.hip): slaves copy their root (primal vectors);
+// roots add their slaves, slaves -> 0 (dual vectors).
+template <class T> void launch_merge_copy(const Grid& g, T* v, hipStream_t s, const SolveScalars* sc);
+template <class T> void launch_merge_gather(const Grid& g, T* v, hipStream_t s, const SolveScalars* sc);
+
+// The learned preconditioner inside flexible CG (unet.hip): z = M(r) on FP32
+// cell arrays, exits at once when the solver state says done.
+nfa_status unet_precond_apply(void* unet, Poisson& op, const float* r, float* z,
+                              const SolveScalars* sc, hipStream_t s);
+
+// Fixed-order sum of `n` partials of `ncomp` components (stride kMaxPartials)
+// into out[0..ncomp) (solver.hip).
+void launch_sum_partials(const double* partials, int n, int ncomp, double* out, hipStream_t s);
+
+}  // namespace nfa
+
+struct nfa_grid_s : nfa::Grid {};
+struct nfa_poisson_s : nfa::Poisson {};

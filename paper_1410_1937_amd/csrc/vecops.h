@@ -1,0 +1,43 @@
+// Launchers of the solver vector kernels (vecops.hip).
+#pragma once
+
+#include "nfa_internal.h"
+
+namespace nfa {
+
+// finalize phases: what a reduction feeds into the solver state
+enum { PH_BB = 0, PH_RR = 1, PH_INIT = 2, PH_PQ = 3, PH_UPD = 4, PH_RRO = 5, PH_ZQ = 6, PH_PR = 7,
+       PH_PQF = 8, PH_UPDF = 9 };
+
+void launch_finalize(const double* partials, int n, int ncomp, int phase, SolveScalars* sc,
+                     double* hist, hipStream_t s);
+template <class T> int launch_dot(const T* a, const T* b, long long n, double* partials,
+                                  const SolveScalars* sc, hipStream_t s);
+template <class T> int launch_masked_sum(const T* a, const unsigned char* mask, long long n,
+                                         double* partials, hipStream_t s);
+void launch_sub_mean(double* b, const unsigned char* mask, long long n, const double* sum,
+                     double count, hipStream_t s);
+template <class T> int launch_jacobi(const T* r, const T* dinv, T* z, long long n, double* partials,
+                                     hipStream_t s);
+template <class T> int launch_update(T* x, const T* p, T* r, const T* q, const T* dinv, T* z,
+                                     long long n, double* partials, const SolveScalars* sc,
+                                     hipStream_t s);
+template <class T> void launch_direction(const T* z, T* p, long long n, const SolveScalars* sc,
+                                         hipStream_t s);
+template <class T> void launch_copy(const T* a, T* b, long long n, hipStream_t s);
+template <class T> void launch_fill(T* a, T v, long long n, hipStream_t s);
+void launch_init_x(double* x, const unsigned char* act, long long n, int warm, hipStream_t s);
+void launch_cast_scaled(const double* r, float* r32, long long n, const SolveScalars* sc, hipStream_t s);
+void launch_refine_update(double* x, const float* d, long long n, const SolveScalars* sc, hipStream_t s);
+void launch_set_scalars(SolveScalars* sc, double t, int tol_mode, int max_iter, int reset_iter,
+                        int window, double ratio, hipStream_t s);
+template <class T> int launch_fdirection(const T* z, T* p, const T* r, long long n, double* partials,
+                                         const SolveScalars* sc, hipStream_t s);
+template <class T> int launch_fupdate(T* x, const T* p, T* r, const T* q, long long n, double* partials,
+                                      const SolveScalars* sc, hipStream_t s);
+template <class T> void launch_scale(const T* r, const T* dinv, T* z, long long n, const SolveScalars* sc,
+                                     hipStream_t s);
+template <class T> void launch_sabotage(const unsigned char* red, T* z, long long n, const SolveScalars* sc,
+                                        hipStream_t s);
+
+}  // namespace nfa

@@ -1,0 +1,455 @@
+// libnfa: vector kernels of the Krylov solvers and fixed-order reductions.
+//
+// Every reduction writes one partial per workgroup (fixed grid, fixed
+// element-to-thread map) and a single workgroup sums the partials in index
+// order, so dot products are bitwise reproducible run to run; there are no
+// floating-point atomics.  FP32 vectors accumulate their products in FP64.
+// Solver scalars (alpha, beta, norms, iteration count, convergence flag) stay
+// on the device (SolveScalars) so that iterations need no host round trip.
+#include <cmath>
+
+#include "device_util.h"
+#include "nfa_internal.h"
+#include "vecops.h"
+
+namespace nfa {
+namespace {
+
+#define GRID_STRIDE(idx, n) \
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < (n); idx += (long long)gridDim.x * blockDim.x)
+
+constexpr int kVecBlocks = 2048;
+
+inline int vec_blocks(long long n) {
+  long long b = (n + kBlock - 1) / kBlock;
+  if (b > kVecBlocks) b = kVecBlocks;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_dot(long long n, const T* __restrict__ a,
+                                                const T* __restrict__ b, double* partials,
+                                                const SolveScalars* sc) {
+  if (solve_done(sc)) return;
+  __shared__ double lds[kBlock / 64];
+  double acc = 0.0;
+  GRID_STRIDE(i, n) acc += (double)a[i] * (double)b[i];
+  const double t = block_sum(acc, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_masked_sum(long long n, const T* __restrict__ a,
+                                                       const unsigned char* __restrict__ m,
+                                                       double* partials) {
+  __shared__ double lds[kBlock / 64];
+  double acc = 0.0;
+  GRID_STRIDE(i, n) acc += m[i] ? (double)a[i] : 0.0;
+  const double t = block_sum(acc, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ void k_sub_mean(long long n, double* b, const unsigned char* __restrict__ m,
+                           const double* sum, double count) {
+  const double mean = *sum / count;
+  GRID_STRIDE(i, n) if (m[i]) b[i] = b[i] - mean;
+}
+
+// out[c] = sum_i partials[c*kMaxPartials + i], fixed order
+__global__ __launch_bounds__(1024) void k_sum_partials(const double* partials, int n, int ncomp,
+                                                        double* out) {
+  __shared__ double lds[1024 / 64];
+  for (int c = 0; c < ncomp; ++c) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) acc += partials[(size_t)c * kMaxPartials + i];
+    const double t = block_sum(acc, lds);
+    if (threadIdx.x == 0) out[c] = t;
+    __syncthreads();
+  }
+}
+
+// Stagnation test on the squared-residual history: mean reduction factor of
+// ||r|| per iteration over the last `window` iterations above `ratio`.
+__device__ __forceinline__ bool stalled_now(const SolveScalars* sc, const double* hist) {
+  const int w = sc->window;
+  if (!hist || w <= 0 || sc->iter < 2 * w || sc->iter > sc->max_iter || sc->iter > kHistCap)
+    return false;
+  const double a = hist[sc->iter], b = hist[sc->iter - w];
+  if (!(b > 0.0)) return false;
+  const double rate = pow(a / b, 0.5 / w);
+  return !(rate <= sc->ratio);
+}
+
+// Finalize a reduction and advance the solver state (single workgroup).
+__global__ __launch_bounds__(1024) void k_finalize(const double* partials, int n, int ncomp, int phase,
+                                                    SolveScalars* sc, double* hist) {
+  if (phase != PH_BB && phase != PH_RR && phase != PH_RRO && phase != PH_INIT && sc->done) return;
+  __shared__ double lds[1024 / 64];
+  __shared__ double val[4];
+  for (int c = 0; c < ncomp; ++c) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) acc += partials[(size_t)c * kMaxPartials + i];
+    const double t = block_sum(acc, lds);
+    if (threadIdx.x == 0) val[c] = t;
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  switch (phase) {
+    case PH_BB:
+      sc->bb = val[0];
+      break;
+    case PH_RR:
+      sc->rr = val[0];
+      break;
+    case PH_RRO:
+      sc->rr_outer = val[0];
+      break;
+    case PH_INIT:
+      // ncomp 2: (r.z, r.r) for PCG; ncomp 1: (r.r) for FCG
+      if (ncomp == 2) { sc->rz = val[0]; sc->rr = val[1]; }
+      else { sc->rr = val[0]; }
+      sc->pq = 0.0;
+      sc->done = 0;
+      sc->breakdown = 0;
+      sc->stalled = 0;
+      if (!isfinite(sc->rr) || (ncomp == 2 && !isfinite(sc->rz))) { sc->breakdown = 2; sc->done = 1; }
+      else if (sc->rr <= sc->tol2) sc->done = 1;
+      if (hist && sc->iter <= sc->max_iter && sc->iter <= kHistCap) hist[sc->iter] = sc->rr;
+      break;
+    case PH_PQ:
+      sc->pq = val[0];
+      if (!(val[0] > 0.0) || !isfinite(val[0])) {
+        sc->breakdown = isfinite(val[0]) ? 1 : 2;
+        sc->done = 1;
+      } else {
+        sc->alpha = sc->rz / val[0];
+      }
+      break;
+    case PH_UPD: {
+      const double rzn = val[0], rr = val[1];
+      sc->beta = rzn / sc->rz;
+      sc->rz = rzn;
+      sc->rr = rr;
+      sc->iter += 1;
+      if (hist && sc->iter <= sc->max_iter && sc->iter <= kHistCap) hist[sc->iter] = rr;
+      if (!isfinite(rr) || !isfinite(rzn)) { sc->breakdown = 2; sc->done = 1; }
+      else if (rr <= sc->tol2) sc->done = 1;
+      else if (sc->iter >= sc->max_iter) sc->done = 1;
+      else if (stalled_now(sc, hist)) { sc->stalled = 1; sc->done = 1; }
+      break;
+    }
+    case PH_ZQ:   // flexible CG: beta = -(z.q_prev)/(p_prev.q_prev), 0 on the first step
+      sc->zq = val[0];
+      sc->beta = (sc->pq > 0.0 && isfinite(val[0])) ? -val[0] / sc->pq : 0.0;
+      break;
+    case PH_PR:
+      sc->pr = val[0];
+      break;
+    case PH_PQF:
+      sc->pq = val[0];
+      if (!(val[0] > 0.0) || !isfinite(val[0])) {
+        sc->breakdown = isfinite(val[0]) ? 1 : 2;
+        sc->done = 1;
+      } else {
+        sc->alpha = sc->pr / val[0];
+      }
+      break;
+    case PH_UPDF: {
+      const double rr = val[0];
+      sc->rr = rr;
+      sc->iter += 1;
+      if (hist && sc->iter <= sc->max_iter && sc->iter <= kHistCap) hist[sc->iter] = rr;
+      if (!isfinite(rr)) { sc->breakdown = 2; sc->done = 1; }
+      else if (rr <= sc->tol2) sc->done = 1;
+      else if (sc->iter >= sc->max_iter) sc->done = 1;
+      else if (stalled_now(sc, hist)) { sc->stalled = 1; sc->done = 1; }
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_jacobi(long long n, const T* __restrict__ r,
+                                                   const T* __restrict__ dinv, T* __restrict__ z,
+                                                   double* partials) {
+  __shared__ double lds[2 * kBlock / 64];
+  double rz = 0.0, rr = 0.0;
+  GRID_STRIDE(i, n) {
+    const T ri = r[i];
+    const T zi = dinv[i] * ri;
+    z[i] = zi;
+    rz += (double)ri * (double)zi;
+    rr += (double)ri * (double)ri;
+  }
+  const double t0 = block_sum(rz, lds);
+  const double t1 = block_sum(rr, lds + kBlock / 64);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = t0;
+    partials[kMaxPartials + blockIdx.x] = t1;
+  }
+}
+
+// x += alpha p; r -= alpha q; z = dinv r; partials r.z, r.r
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_update(long long n, T* __restrict__ x,
+                                                   const T* __restrict__ p, T* __restrict__ r,
+                                                   const T* __restrict__ q,
+                                                   const T* __restrict__ dinv, T* __restrict__ z,
+                                                   double* partials, const SolveScalars* sc) {
+  if (solve_done(sc)) return;
+  __shared__ double lds[2 * kBlock / 64];
+  const T alpha = (T)sc->alpha;
+  double rz = 0.0, rr = 0.0;
+  GRID_STRIDE(i, n) {
+    x[i] = x[i] + alpha * p[i];
+    const T ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    const T zi = dinv[i] * ri;
+    z[i] = zi;
+    rz += (double)ri * (double)zi;
+    rr += (double)ri * (double)ri;
+  }
+  const double t0 = block_sum(rz, lds);
+  const double t1 = block_sum(rr, lds + kBlock / 64);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = t0;
+    partials[kMaxPartials + blockIdx.x] = t1;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_direction(long long n, const T* __restrict__ z,
+                                                      T* __restrict__ p, const SolveScalars* sc) {
+  if (solve_done(sc)) return;
+  const T beta = (T)sc->beta;
+  GRID_STRIDE(i, n) p[i] = z[i] + beta * p[i];
+}
+
+// flexible CG: p = z + beta p (beta = -(z.q)/(p.q) from the device state);
+// partial p.r
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_fdirection(long long n, const T* __restrict__ z,
+                                                       T* __restrict__ p, const T* __restrict__ r,
+                                                       double* partials, const SolveScalars* sc) {
+  if (solve_done(sc)) return;
+  __shared__ double lds[kBlock / 64];
+  const T beta = (T)sc->beta;
+  double pr = 0.0;
+  GRID_STRIDE(i, n) {
+    const T pi = z[i] + beta * p[i];
+    p[i] = pi;
+    pr += (double)pi * (double)r[i];
+  }
+  const double t = block_sum(pr, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// flexible CG: x += alpha p; r -= alpha q; partial r.r
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_fupdate(long long n, T* __restrict__ x,
+                                                    const T* __restrict__ p, T* __restrict__ r,
+                                                    const T* __restrict__ q, double* partials,
+                                                    const SolveScalars* sc) {
+  if (solve_done(sc)) return;
+  __shared__ double lds[kBlock / 64];
+  const T alpha = (T)sc->alpha;
+  double rr = 0.0;
+  GRID_STRIDE(i, n) {
+    x[i] = x[i] + alpha * p[i];
+    const T ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    rr += (double)ri * (double)ri;
+  }
+  const double t = block_sum(rr, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// preconditioner z = dinv r (no reduction), early exit with the solver state
+template <class T>
+__global__ void k_scale(long long n, const T* __restrict__ r, const T* __restrict__ dinv,
+                        T* __restrict__ z, const SolveScalars* sc) {
+  if (solve_done(sc)) return;
+  GRID_STRIDE(i, n) z[i] = dinv[i] * r[i];
+}
+
+// test hook: a fixed field unrelated to r (stands in for a broken preconditioner)
+template <class T>
+__global__ void k_sabotage(long long n, const unsigned char* __restrict__ red, T* __restrict__ z,
+                           const SolveScalars* sc) {
+  if (solve_done(sc)) return;
+  GRID_STRIDE(i, n) {
+    unsigned long long h = (unsigned long long)i * 0x9E3779B97F4A7C15ull + (unsigned long long)sc->iter;
+    h ^= h >> 31;
+    h *= 0xBF58476D1CE4E5B9ull;
+    h ^= h >> 29;
+    const double u = (double)(h >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+    z[i] = red[i] ? (T)(1e-6 * u) : T(0);
+  }
+}
+
+template <class T>
+__global__ void k_copy(long long n, const T* __restrict__ a, T* __restrict__ b) {
+  GRID_STRIDE(i, n) b[i] = a[i];
+}
+
+template <class T>
+__global__ void k_fill(long long n, T* a, T v) {
+  GRID_STRIDE(i, n) a[i] = v;
+}
+
+__global__ void k_init_x(long long n, double* x, const unsigned char* act, int warm) {
+  GRID_STRIDE(i, n) x[i] = (warm && act[i]) ? x[i] : 0.0;
+}
+
+// r32 = float(r64 / ||r||)
+__global__ void k_cast_scaled(long long n, const double* __restrict__ r, float* __restrict__ r32,
+                              const SolveScalars* sc) {
+  const double inv = 1.0 / sqrt(sc->rr_outer);
+  GRID_STRIDE(i, n) r32[i] = (float)(r[i] * inv);
+}
+
+// x += ||r|| * double(d32)
+__global__ void k_refine_update(long long n, double* __restrict__ x, const float* __restrict__ d,
+                                const SolveScalars* sc) {
+  const double s = sqrt(sc->rr_outer);
+  GRID_STRIDE(i, n) x[i] = x[i] + s * (double)d[i];
+}
+
+// tol_mode 0: tol2 = t * bb; 1: tol2 = t (absolute)
+__global__ void k_set_scalars(SolveScalars* sc, double t, int tol_mode, int max_iter, int reset_iter,
+                              int window, double ratio) {
+  sc->tol2 = tol_mode == 0 ? t * sc->bb : t;
+  sc->window = window;
+  sc->ratio = ratio;
+  sc->max_iter = max_iter;
+  sc->done = 0;
+  sc->breakdown = 0;
+  sc->stalled = 0;
+  if (reset_iter) sc->iter = 0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+template <class T> int launch_masked_sum(const T* a, const unsigned char* mask, long long n,
+                                         double* partials, hipStream_t s) {
+  const int nb = vec_blocks(n);
+  k_masked_sum<T><<<nb, kBlock, 0, s>>>(n, a, mask, partials);
+  return nb;
+}
+template int launch_masked_sum<double>(const double*, const unsigned char*, long long, double*, hipStream_t);
+template int launch_masked_sum<float>(const float*, const unsigned char*, long long, double*, hipStream_t);
+
+void launch_sub_mean(double* b, const unsigned char* mask, long long n, const double* sum,
+                     double count, hipStream_t s) {
+  k_sub_mean<<<vec_blocks(n), kBlock, 0, s>>>(n, b, mask, sum, count);
+}
+
+void launch_sum_partials(const double* partials, int n, int ncomp, double* out, hipStream_t s) {
+  k_sum_partials<<<1, 1024, 0, s>>>(partials, n, ncomp, out);
+}
+
+void launch_finalize(const double* partials, int n, int ncomp, int phase, SolveScalars* sc,
+                     double* hist, hipStream_t s) {
+  k_finalize<<<1, 1024, 0, s>>>(partials, n, ncomp, phase, sc, hist);
+}
+
+template <class T> int launch_dot(const T* a, const T* b, long long n, double* partials,
+                                  const SolveScalars* sc, hipStream_t s) {
+  const int nb = vec_blocks(n);
+  k_dot<T><<<nb, kBlock, 0, s>>>(n, a, b, partials, sc);
+  return nb;
+}
+template int launch_dot<double>(const double*, const double*, long long, double*, const SolveScalars*, hipStream_t);
+template int launch_dot<float>(const float*, const float*, long long, double*, const SolveScalars*, hipStream_t);
+
+template <class T> int launch_jacobi(const T* r, const T* dinv, T* z, long long n, double* partials,
+                                     hipStream_t s) {
+  const int nb = vec_blocks(n);
+  k_jacobi<T><<<nb, kBlock, 0, s>>>(n, r, dinv, z, partials);
+  return nb;
+}
+template int launch_jacobi<double>(const double*, const double*, double*, long long, double*, hipStream_t);
+template int launch_jacobi<float>(const float*, const float*, float*, long long, double*, hipStream_t);
+
+template <class T> int launch_update(T* x, const T* p, T* r, const T* q, const T* dinv, T* z,
+                                     long long n, double* partials, const SolveScalars* sc,
+                                     hipStream_t s) {
+  const int nb = vec_blocks(n);
+  k_update<T><<<nb, kBlock, 0, s>>>(n, x, p, r, q, dinv, z, partials, sc);
+  return nb;
+}
+template int launch_update<double>(double*, const double*, double*, const double*, const double*, double*,
+                                   long long, double*, const SolveScalars*, hipStream_t);
+template int launch_update<float>(float*, const float*, float*, const float*, const float*, float*,
+                                  long long, double*, const SolveScalars*, hipStream_t);
+
+template <class T> void launch_direction(const T* z, T* p, long long n, const SolveScalars* sc,
+                                         hipStream_t s) {
+  k_direction<T><<<vec_blocks(n), kBlock, 0, s>>>(n, z, p, sc);
+}
+template void launch_direction<double>(const double*, double*, long long, const SolveScalars*, hipStream_t);
+template void launch_direction<float>(const float*, float*, long long, const SolveScalars*, hipStream_t);
+
+template <class T> int launch_fdirection(const T* z, T* p, const T* r, long long n, double* partials,
+                                         const SolveScalars* sc, hipStream_t s) {
+  const int nb = vec_blocks(n);
+  k_fdirection<T><<<nb, kBlock, 0, s>>>(n, z, p, r, partials, sc);
+  return nb;
+}
+template int launch_fdirection<double>(const double*, double*, const double*, long long, double*, const SolveScalars*, hipStream_t);
+template int launch_fdirection<float>(const float*, float*, const float*, long long, double*, const SolveScalars*, hipStream_t);
+
+template <class T> int launch_fupdate(T* x, const T* p, T* r, const T* q, long long n, double* partials,
+                                      const SolveScalars* sc, hipStream_t s) {
+  const int nb = vec_blocks(n);
+  k_fupdate<T><<<nb, kBlock, 0, s>>>(n, x, p, r, q, partials, sc);
+  return nb;
+}
+template int launch_fupdate<double>(double*, const double*, double*, const double*, long long, double*, const SolveScalars*, hipStream_t);
+template int launch_fupdate<float>(float*, const float*, float*, const float*, long long, double*, const SolveScalars*, hipStream_t);
+
+template <class T> void launch_scale(const T* r, const T* dinv, T* z, long long n, const SolveScalars* sc,
+                                     hipStream_t s) {
+  k_scale<T><<<vec_blocks(n), kBlock, 0, s>>>(n, r, dinv, z, sc);
+}
+template void launch_scale<double>(const double*, const double*, double*, long long, const SolveScalars*, hipStream_t);
+template void launch_scale<float>(const float*, const float*, float*, long long, const SolveScalars*, hipStream_t);
+
+template <class T> void launch_sabotage(const unsigned char* red, T* z, long long n, const SolveScalars* sc,
+                                        hipStream_t s) {
+  k_sabotage<T><<<vec_blocks(n), kBlock, 0, s>>>(n, red, z, sc);
+}
+template void launch_sabotage<double>(const unsigned char*, double*, long long, const SolveScalars*, hipStream_t);
+template void launch_sabotage<float>(const unsigned char*, float*, long long, const SolveScalars*, hipStream_t);
+
+template <class T> void launch_copy(const T* a, T* b, long long n, hipStream_t s) {
+  k_copy<T><<<vec_blocks(n), kBlock, 0, s>>>(n, a, b);
+}
+template void launch_copy<double>(const double*, double*, long long, hipStream_t);
+template void launch_copy<float>(const float*, float*, long long, hipStream_t);
+
+template <class T> void launch_fill(T* a, T v, long long n, hipStream_t s) {
+  k_fill<T><<<vec_blocks(n), kBlock, 0, s>>>(n, a, v);
+}
+template void launch_fill<double>(double*, double, long long, hipStream_t);
+template void launch_fill<float>(float*, float, long long, hipStream_t);
+
+void launch_init_x(double* x, const unsigned char* act, long long n, int warm, hipStream_t s) {
+  k_init_x<<<vec_blocks(n), kBlock, 0, s>>>(n, x, act, warm);
+}
+void launch_cast_scaled(const double* r, float* r32, long long n, const SolveScalars* sc, hipStream_t s) {
+  k_cast_scaled<<<vec_blocks(n), kBlock, 0, s>>>(n, r, r32, sc);
+}
+void launch_refine_update(double* x, const float* d, long long n, const SolveScalars* sc, hipStream_t s) {
+  k_refine_update<<<vec_blocks(n), kBlock, 0, s>>>(n, x, d, sc);
+}
+void launch_set_scalars(SolveScalars* sc, double t, int tol_mode, int max_iter, int reset_iter,
+                        int window, double ratio, hipStream_t s) {
+  k_set_scalars<<<1, 1, 0, s>>>(sc, t, tol_mode, max_iter, reset_iter, window, ratio);
+}
+
+}  // namespace nfa

@@ -1,0 +1,315 @@
+"""Python binding of libnfa (ctypes).
+
+Argument marshalling only: every step of the projection runs in the HIP
+library.  torch supplies device memory (tensors) and the stream (the current
+torch stream).  If the library is not built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnfa.so")
+
+NFA_OK = 0
+NFA_NOT_CONVERGED = 1
+NFA_F64, NFA_F32 = 0, 1
+NFA_PC_JACOBI, NFA_PC_UNET, NFA_PC_TEST_SABOTAGE, NFA_PC_JACOBI_FCG = 1, 2, 3, 4
+NFA_PREC_F64, NFA_PREC_MIXED = 0, 1
+
+EXPORT = {
+    "frac_x": 1, "frac_y": 2, "frac_z": 3, "vfrac": 4, "open_x": 5, "open_y": 6, "open_z": 7,
+    "active": 8, "root": 9, "reduced": 10,
+    "rho": 20, "tx": 21, "ty": 22, "tz": 23, "dinv": 24, "tx32": 25, "ty32": 26, "tz32": 27,
+    "dinv32": 28,
+}
+
+
+class NFAError(RuntimeError):
+    pass
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built (python -m paper_1410_1937_amd.build)")
+    return ctypes.CDLL(LIB_PATH)
+
+
+lib = _load()
+
+c_void_p, c_int, c_double, c_ll = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
+
+
+class GridInfo(ctypes.Structure):
+    _fields_ = [("nx", c_int), ("ny", c_int), ("nz", c_int), ("cells", c_ll), ("active", c_ll),
+                ("reduced", c_ll), ("groups", c_int), ("slaves", c_int), ("all_neumann", c_int)]
+
+
+class AssembleParams(ctypes.Structure):
+    _fields_ = [("rho_liquid", c_double), ("rho_gas", c_double), ("smooth", c_int),
+                ("phi_dtype", c_int)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", c_double), ("max_iters", c_int), ("precond", c_int), ("precision", c_int),
+                ("inner_tol", c_double), ("max_outer", c_int), ("fcg_m", c_int),
+                ("fallback_ratio", c_double), ("fallback_window", c_int), ("warm_start", c_int),
+                ("check_every", c_int), ("unet", c_void_p), ("history", ctypes.POINTER(c_double)),
+                ("history_cap", c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", c_int), ("outer", c_int), ("fallback", c_int),
+                ("history_len", c_int), ("relres", c_double), ("ms", c_double)]
+
+
+class KernelStats(ctypes.Structure):
+    _fields_ = [("launches", c_ll), ("ms", c_double), ("cells", c_ll)]
+
+
+def _sig(name, res, args):
+    f = getattr(lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_sig("nfa_last_error", ctypes.c_char_p, [])
+_sig("nfa_version", c_int, [])
+_sig("nfa_grid_create", c_int, [c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                                ctypes.POINTER(c_void_p)])
+_sig("nfa_grid_set_body", c_int, [c_void_p, c_void_p, c_double, c_int, c_void_p])
+_sig("nfa_grid_get_info", c_int, [c_void_p, ctypes.POINTER(GridInfo)])
+_sig("nfa_grid_export", c_int, [c_void_p, c_int, c_void_p, c_void_p])
+_sig("nfa_grid_destroy", None, [c_void_p])
+_sig("nfa_poisson_create", c_int, [c_void_p, ctypes.POINTER(c_void_p)])
+_sig("nfa_poisson_assemble", c_int, [c_void_p, c_void_p, ctypes.POINTER(AssembleParams), c_void_p])
+_sig("nfa_poisson_apply", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p])
+_sig("nfa_poisson_rhs", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_void_p,
+                                c_void_p, c_void_p])
+_sig("nfa_poisson_project", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double,
+                                    c_void_p, c_void_p, c_void_p, c_void_p])
+_sig("nfa_poisson_divergence", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                       c_void_p])
+_sig("nfa_solve_opts_default", None, [ctypes.POINTER(SolveOpts)])
+_sig("nfa_poisson_solve", c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveOpts),
+                                  c_void_p, ctypes.POINTER(SolveInfo)])
+_sig("nfa_poisson_export", c_int, [c_void_p, c_int, c_void_p, c_void_p])
+_sig("nfa_poisson_destroy", None, [c_void_p])
+_sig("nfa_poisson_profile", c_int, [c_void_p, c_int])
+_sig("nfa_poisson_profile_read", c_int, [c_void_p, c_int, ctypes.POINTER(KernelStats)])
+
+
+def _check(st, what):
+    if st < 0:
+        msg = lib.nfa_last_error().decode()
+        raise NFAError(f"{what} failed ({st}): {msg}")
+    return st
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, shape=None, name="array"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Grid:
+    """Stretched cartesian grid with an optional immersed body."""
+
+    def __init__(self, xf, yf, zf, bc):
+        xf, yf, zf = (np.ascontiguousarray(a, dtype=np.float64) for a in (xf, yf, zf))
+        bc = np.ascontiguousarray(bc, dtype=np.int32)
+        h = c_void_p()
+        _check(lib.nfa_grid_create(len(xf) - 1, len(yf) - 1, len(zf) - 1, xf.ctypes.data,
+                                   yf.ctypes.data, zf.ctypes.data, bc.ctypes.data, ctypes.byref(h)),
+               "nfa_grid_create")
+        self.h = h
+        self.nx, self.ny, self.nz = len(xf) - 1, len(yf) - 1, len(zf) - 1
+        self.shape = (self.nz, self.ny, self.nx)
+
+    def set_body(self, psi, theta=0.25, samples=8):
+        ptr = None if psi is None else _dev(psi, torch.float64,
+                                             (self.nz + 1, self.ny + 1, self.nx + 1), "psi")
+        _check(lib.nfa_grid_set_body(self.h, ptr, theta, samples, _stream()), "nfa_grid_set_body")
+
+    def info(self):
+        gi = GridInfo()
+        _check(lib.nfa_grid_get_info(self.h, ctypes.byref(gi)), "nfa_grid_get_info")
+        return {f: getattr(gi, f) for f, _ in GridInfo._fields_}
+
+    def face_shape(self, axis):
+        nz, ny, nx = self.shape
+        return [(nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx)][axis]
+
+    def export(self, what):
+        code = EXPORT[what]
+        shape = {1: self.face_shape(0), 2: self.face_shape(1), 3: self.face_shape(2),
+                 5: self.face_shape(0), 6: self.face_shape(1), 7: self.face_shape(2)}.get(code, self.shape)
+        dtype = {8: torch.uint8, 9: torch.int32, 10: torch.uint8}.get(code, torch.float64)
+        out = torch.empty(shape, dtype=dtype, device="cuda")
+        _check(lib.nfa_grid_export(self.h, code, c_void_p(out.data_ptr()), _stream()), "nfa_grid_export")
+        return out
+
+    def __del__(self, _destroy=lib.nfa_grid_destroy):
+        if getattr(self, "h", None):
+            _destroy(self.h)
+            self.h = None
+
+
+@dataclasses.dataclass
+class SolveResult:
+    status: int
+    iterations: int
+    outer: int
+    fallback: bool
+    relres: float
+    ms: float
+    history: np.ndarray | None = None
+
+
+class Poisson:
+    """Assembled pressure operator and its solvers on a Grid."""
+
+    def __init__(self, grid: Grid):
+        self.grid = grid
+        h = c_void_p()
+        _check(lib.nfa_poisson_create(grid.h, ctypes.byref(h)), "nfa_poisson_create")
+        self.h = h
+        self.shape = grid.shape
+
+    def assemble(self, phi, rho_l=1000.0, rho_g=1.2, smooth=True):
+        if phi.dtype == torch.float64:
+            dt = NFA_F64
+        elif phi.dtype == torch.float32:
+            dt = NFA_F32
+        else:
+            raise TypeError("phi must be float64 or float32")
+        prm = AssembleParams(rho_l, rho_g, 1 if smooth else 0, dt)
+        _check(lib.nfa_poisson_assemble(self.h, _dev(phi, phi.dtype, self.shape, "phi"),
+                                        ctypes.byref(prm), _stream()), "nfa_poisson_assemble")
+
+    def apply(self, x, out=None):
+        dt = NFA_F64 if x.dtype == torch.float64 else NFA_F32
+        y = torch.empty_like(x) if out is None else out
+        _check(lib.nfa_poisson_apply(self.h, _dev(x, x.dtype, self.shape, "x"),
+                                     _dev(y, x.dtype, self.shape, "y"), dt, _stream()),
+               "nfa_poisson_apply")
+        return y
+
+    def rhs(self, u, v, w, dt=1.0, body_vel=(0.0, 0.0, 0.0), out=None):
+        g = self.grid
+        b = torch.empty(self.shape, dtype=torch.float64, device="cuda") if out is None else out
+        vel = np.ascontiguousarray(body_vel, dtype=np.float64)
+        _check(lib.nfa_poisson_rhs(self.h, _dev(u, torch.float64, g.face_shape(0), "u"),
+                                   _dev(v, torch.float64, g.face_shape(1), "v"),
+                                   _dev(w, torch.float64, g.face_shape(2), "w"), dt, vel.ctypes.data,
+                                   _dev(b, torch.float64, self.shape, "b"), _stream()), "nfa_poisson_rhs")
+        return b
+
+    def project(self, u, v, w, p, dt=1.0):
+        g = self.grid
+        fu, fv, fw = torch.empty_like(u), torch.empty_like(v), torch.empty_like(w)
+        _check(lib.nfa_poisson_project(self.h, _dev(u, torch.float64, g.face_shape(0), "u"),
+                                       _dev(v, torch.float64, g.face_shape(1), "v"),
+                                       _dev(w, torch.float64, g.face_shape(2), "w"),
+                                       _dev(p, torch.float64, self.shape, "p"), dt,
+                                       _dev(fu, torch.float64), _dev(fv, torch.float64),
+                                       _dev(fw, torch.float64), _stream()), "nfa_poisson_project")
+        return fu, fv, fw
+
+    def divergence(self, fu, fv, fw, body_vel=(0.0, 0.0, 0.0)):
+        g = self.grid
+        div = torch.empty(self.shape, dtype=torch.float64, device="cuda")
+        vel = np.ascontiguousarray(body_vel, dtype=np.float64)
+        _check(lib.nfa_poisson_divergence(self.h, _dev(fu, torch.float64, g.face_shape(0), "fu"),
+                                          _dev(fv, torch.float64, g.face_shape(1), "fv"),
+                                          _dev(fw, torch.float64, g.face_shape(2), "fw"),
+                                          vel.ctypes.data, _dev(div, torch.float64), _stream()),
+               "nfa_poisson_divergence")
+        return div
+
+    def solve(self, b, x=None, tol=1e-8, precision="f64", precond="jacobi", max_iters=200000,
+              inner_tol=1e-6, max_outer=8, warm_start=False, check_every=16, unet=None,
+              fallback_ratio=0.99, fallback_window=10, history=0):
+        o = SolveOpts()
+        lib.nfa_solve_opts_default(ctypes.byref(o))
+        o.tol = tol
+        o.max_iters = max_iters
+        o.precision = {"f64": NFA_PREC_F64, "mixed": NFA_PREC_MIXED}[precision]
+        o.precond = {"jacobi": NFA_PC_JACOBI, "unet": NFA_PC_UNET, "jacobi_fcg": NFA_PC_JACOBI_FCG,
+                     "sabotage": NFA_PC_TEST_SABOTAGE}[precond]
+        o.inner_tol = inner_tol
+        o.max_outer = max_outer
+        o.warm_start = 1 if warm_start else 0
+        o.check_every = check_every
+        o.fallback_ratio = fallback_ratio
+        o.fallback_window = fallback_window
+        o.unet = None if unet is None else unet.h
+        hist = None
+        if history:
+            hist = np.zeros(history, dtype=np.float64)
+            o.history = hist.ctypes.data_as(ctypes.POINTER(c_double))
+            o.history_cap = history
+        if x is None:
+            x = torch.zeros(self.shape, dtype=torch.float64, device="cuda")
+        info = SolveInfo()
+        st = _check(lib.nfa_poisson_solve(self.h, _dev(b, torch.float64, self.shape, "b"),
+                                          _dev(x, torch.float64, self.shape, "x"), ctypes.byref(o),
+                                          _stream(), ctypes.byref(info)), "nfa_poisson_solve")
+        res = SolveResult(st, info.iterations, info.outer, bool(info.fallback), info.relres, info.ms,
+                          None if hist is None else hist[:info.history_len].copy())
+        return x, res
+
+    def profile(self, enable=True):
+        _check(lib.nfa_poisson_profile(self.h, 1 if enable else 0), "nfa_poisson_profile")
+
+    def profile_read(self, dtype):
+        ks = KernelStats()
+        _check(lib.nfa_poisson_profile_read(self.h, NFA_F64 if dtype == "f64" else NFA_F32,
+                                            ctypes.byref(ks)), "nfa_poisson_profile_read")
+        return {"launches": ks.launches, "ms": ks.ms, "cells": ks.cells}
+
+    def export(self, what):
+        code = EXPORT[what]
+        g = self.grid
+        shape = {21: g.face_shape(0), 22: g.face_shape(1), 23: g.face_shape(2),
+                 25: g.face_shape(0), 26: g.face_shape(1), 27: g.face_shape(2)}.get(code, self.shape)
+        dtype = torch.float32 if code in (25, 26, 27, 28) else torch.float64
+        out = torch.empty(shape, dtype=dtype, device="cuda")
+        _check(lib.nfa_poisson_export(self.h, code, c_void_p(out.data_ptr()), _stream()),
+               "nfa_poisson_export")
+        return out
+
+    def __del__(self, _destroy=lib.nfa_poisson_destroy):
+        if getattr(self, "h", None):
+            _destroy(self.h)
+            self.h = None
+
+
+def from_workload(wl, device_phi_dtype=torch.float64):
+    """Grid + body + assembled operator + right-hand side for a fixtures.Workload."""
+    g = Grid(wl.xf, wl.yf, wl.zf, wl.bc)
+    if wl.psi is not None:
+        g.set_body(torch.as_tensor(wl.psi, device="cuda"), wl.theta, wl.samples)
+    op = Poisson(g)
+    phi = torch.as_tensor(wl.phi, device="cuda").to(device_phi_dtype).contiguous()
+    op.assemble(phi, wl.rho_l, wl.rho_g, wl.smooth)
+    if wl.b is not None:
+        b = torch.as_tensor(wl.b, device="cuda").contiguous()
+    else:
+        b = op.rhs(torch.as_tensor(wl.u, device="cuda"), torch.as_tensor(wl.v, device="cuda"),
+                   torch.as_tensor(wl.w, device="cuda"), wl.dt, wl.body_vel)
+    return g, op, b

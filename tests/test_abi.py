@@ -1,0 +1,92 @@
+"""The C-ABI library loads and exports every declared symbol; host-side
+argument validation works without a GPU (no compute calls)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1410_1937_amd", "libnfa.so")
+HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+           if f.endswith(".h")]
+
+
+def _declared():
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(nfa_[a-z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libnfa.so is not built (python -m paper_1410_1937_amd.build)")
+    return ctypes.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version_and_error_string(lib):
+    lib.nfa_version.restype = ctypes.c_int
+    assert lib.nfa_version() >= 10000
+    lib.nfa_last_error.restype = ctypes.c_char_p
+    assert isinstance(lib.nfa_last_error(), bytes)
+
+
+def test_grid_create_rejects_bad_arguments_before_touching_the_device(lib):
+    lib.nfa_last_error.restype = ctypes.c_char_p
+    f = lib.nfa_grid_create
+    f.restype = ctypes.c_int
+    h = ctypes.c_void_p()
+    xf = np.array([0.0, 0.5, 0.4, 1.0])        # not increasing
+    yf = np.linspace(0, 1, 3)
+    zf = np.linspace(0, 1, 3)
+    bc = np.zeros(6, dtype=np.int32)
+    st = f(3, 2, 2, xf.ctypes.data_as(ctypes.c_void_p), yf.ctypes.data_as(ctypes.c_void_p),
+           zf.ctypes.data_as(ctypes.c_void_p), bc.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h))
+    assert st == -1 and h.value is None
+    assert b"increasing" in lib.nfa_last_error()
+    bc[2] = 7
+    xf = np.linspace(0, 1, 4)
+    st = f(3, 2, 2, xf.ctypes.data_as(ctypes.c_void_p), yf.ctypes.data_as(ctypes.c_void_p),
+           zf.ctypes.data_as(ctypes.c_void_p), bc.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h))
+    assert st == -1 and b"bc" in lib.nfa_last_error()
+    st = f(0, 2, 2, None, None, None, None, ctypes.byref(h))
+    assert st == -1
+
+
+def test_solve_rejects_null_handle_and_defaults_are_sane(lib):
+    class Opts(ctypes.Structure):
+        _fields_ = [("tol", ctypes.c_double), ("max_iters", ctypes.c_int), ("precond", ctypes.c_int),
+                    ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                    ("max_outer", ctypes.c_int), ("fcg_m", ctypes.c_int),
+                    ("fallback_ratio", ctypes.c_double), ("fallback_window", ctypes.c_int),
+                    ("warm_start", ctypes.c_int), ("check_every", ctypes.c_int),
+                    ("unet", ctypes.c_void_p), ("history", ctypes.c_void_p),
+                    ("history_cap", ctypes.c_int)]
+    o = Opts()
+    lib.nfa_solve_opts_default(ctypes.byref(o))
+    assert o.tol == 1e-8 and o.precond == 1 and o.fallback_ratio == 0.99 and o.fallback_window == 10
+    assert o.fcg_m == 1 and 0 < o.inner_tol < 1e-3
+    lib.nfa_poisson_solve.restype = ctypes.c_int
+    assert lib.nfa_poisson_solve(None, None, None, ctypes.byref(o), None, None) == -1
+
+
+def test_product_path_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1410_1937_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
