@@ -185,7 +185,7 @@ def main():
                               + ("flexible CG with the learned U-Net preconditioner"
                                  if solver["precond"] == "unet" else "Jacobi-PCG")),
                    "step": "assemble + rhs + solve + project + divergence",
-                   "iterations": its_chosen[-1], "outer": r_chosen.outer,
+                   "iterations": its_chosen[-1], "fp64_residuals": r_chosen.outer,
                    "fallback": r_chosen.fallback},
         "plain_fp64": None if ms_fp64 is None else {
             "ms_per_projection": round(ms_fp64, 3), "iterations": its_fp64[-1],

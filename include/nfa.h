@@ -183,16 +183,16 @@ nfa_status nfa_poisson_divergence(nfa_poisson op, const double* fu, const double
 #define NFA_PC_JACOBI_FCG 4    /* flexible CG driver with the Jacobi preconditioner
                                   (reference run of the flexible path) */
 #define NFA_PREC_F64 0   /* FP64 Jacobi-PCG */
-#define NFA_PREC_MIXED 1 /* FP64 refinement around an FP32 inner solve */
+#define NFA_PREC_MIXED 1 /* FP32 CG recurrence, FP64 solution and residual
+                            replacement (the FP64 residual is the judge) */
 
 typedef struct {
   double tol;            /* FP64 true relative residual ||b'-A'x||/||b'|| */
   int max_iters;         /* total (inner) iterations */
   int precond;           /* NFA_PC_* */
   int precision;         /* NFA_PREC_* */
-  double inner_tol;      /* mixed: deepest relative reduction asked of one inner
-                            solve (each asks for what is still needed, x4) */
-  int max_outer;         /* mixed: refinement steps */
+  double replace_drop;   /* mixed: FP64 residual replacement each time the FP32
+                            recursive residual has dropped by this factor (0.1) */
   int fcg_m;             /* flexible CG truncation; 1 (FCG(1)) is supported */
   double fallback_ratio; /* switch to Jacobi-PCG when the mean reduction per
                             iteration over a window exceeds this (0.99) */
@@ -205,15 +205,16 @@ typedef struct {
 } nfa_solve_opts;
 
 typedef struct {
-  int iterations;     /* inner iterations, all phases */
-  int outer;          /* refinement steps (mixed) or restarts (FP64) */
+  int iterations;     /* CG iterations */
+  int outer;          /* FP64 true-residual evaluations (residual replacements) */
   int fallback;       /* 1: switched to Jacobi-PCG */
   int history_len;    /* entries written to opts->history */
   double relres;      /* final FP64 true relative residual */
   double ms;          /* wall time of the solve on the stream */
 } nfa_solve_info;
 
-/* Fills opts with defaults: tol 1e-8, Jacobi, FP64, inner_tol 1e-6, ... */
+/* Fills opts with defaults: tol 1e-8, Jacobi, FP64, replace_drop 0.1,
+ * fallback 0.99 over 10 iterations, check_every 16. */
 void nfa_solve_opts_default(nfa_solve_opts* opts);
 
 /* nfa_poisson_solve -- x = A'^-1 b' by preconditioned CG (Introduction:

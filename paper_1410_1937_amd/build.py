@@ -15,8 +15,8 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libnfa.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["common.hip", "grid.hip", "assemble.hip", "stencil.hip", "vecops.hip", "solver.hip",
-           "unet.hip"]
+SOURCES = ["common.hip", "grid.hip", "assemble.hip", "stencil.hip", "vecops.hip", "cg.hip",
+           "solver.hip", "unet.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -288,12 +288,14 @@ extern "C" nfa_status nfa_poisson_create(nfa_grid g, nfa_poisson* out) {
   ALLOC(r, n * 8);
   ALLOC(z, n * 8);
   ALLOC(p, n * 8);
+  ALLOC(p2, n * 8);
   ALLOC(q, n * 8);
   ALLOC(tmp, n * 8);
   ALLOC(x32, n * 4);
   ALLOC(r32, n * 4);
   ALLOC(z32, n * 4);
   ALLOC(p32, n * 4);
+  ALLOC(p32b, n * 4);
   ALLOC(q32, n * 4);
   ALLOC(partials, (size_t)kMaxPartials * 4 * 8);
   ALLOC(scal, 4 * sizeof(SolveScalars));

@@ -1,0 +1,371 @@
+// libnfa: fused conjugate-gradient sweeps.
+//
+// One CG iteration is two streaming sweeps over the grid:
+//   sweep A:  p  = z + beta p_old            (new search direction)
+//             q  = A p                        (flux-form 7-point operator)
+//             x += alpha_prev p_old           (update deferred from the
+//                                              previous iteration)
+//             partials p.q (and p.r for flexible CG)
+//   sweep B:  r -= alpha q,  z = D^-1 r       partials r.z, r.r
+//             (flexible CG: r -= alpha q, partial r.r; the preconditioner
+//              runs as its own pass)
+// so the direction update and the x update cost no extra pass: 112 B/cell per
+// iteration in FP64 (72 + 40), 56 B/cell in FP32, against 128 / 64 B for the
+// textbook three-pass form.  p is double-buffered (the neighbours of a cell
+// must see the old direction).
+//
+// Launch shape of sweep A: a workgroup is 64 lanes x 4 rows; each lane owns
+// V consecutive x cells (one 16-byte vector: V = 2 doubles or 4 floats) and
+// marches up z-planes keeping the new direction of planes k-1, k, k+1 and
+// the coefficient of face k in registers.  x-neighbours across lanes come
+// from wavefront shuffles; lanes at a wavefront edge read one extra value
+// through the cache; y-neighbours are re-read through L1/L2.  The grid is
+// persistent (one workgroup per resident slot) and the (column tile, plane)
+// work is split into equal contiguous ranges, so no workgroup waits on a
+// partly filled last round; workgroup ids are remapped so that each XCD
+// owns a contiguous block of y-adjacent column tiles (shared L2 halos).
+// The operator sum keeps the order x-, x+, y-, y+, z-, z+ (FP contraction is
+// off), so q is bitwise the value of the plain sweep.
+#include "device_util.h"
+#include "nfa_internal.h"
+#include "vecops.h"
+
+#include <map>
+#include <mutex>
+#include <tuple>
+
+namespace nfa {
+namespace {
+
+template <class T, int V> struct alignas(sizeof(T) * V) Pack {
+  T v[V];
+};
+
+template <class T, int V> __device__ __forceinline__ Pack<T, V> ld(const T* p) {
+  return *reinterpret_cast<const Pack<T, V>*>(p);
+}
+template <class T, int V> __device__ __forceinline__ void st(T* p, const Pack<T, V>& a) {
+  *reinterpret_cast<Pack<T, V>*>(p) = a;
+}
+template <class T, int V> __device__ __forceinline__ Pack<T, V> zero() {
+  Pack<T, V> a;
+#pragma unroll
+  for (int e = 0; e < V; ++e) a.v[e] = T(0);
+  return a;
+}
+// new direction z + beta p_old of V cells
+template <class T, int V>
+__device__ __forceinline__ Pack<T, V> dir(const T* z, const T* po, long long c, T beta) {
+  const Pack<T, V> a = ld<T, V>(z + c), b = ld<T, V>(po + c);
+  Pack<T, V> r;
+#pragma unroll
+  for (int e = 0; e < V; ++e) r.v[e] = a.v[e] + beta * b.v[e];
+  return r;
+}
+
+constexpr int AX = 64, AY = 4;
+
+template <class T, int V, bool FLEX>
+__global__ __launch_bounds__(AX* AY) void k_cg_a(
+    int nx, int ny, int nz, int tiles_x, long long ncol, long long per_block,
+    const T* __restrict__ z, const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ x,
+    const T* __restrict__ r, const T* __restrict__ tx, const T* __restrict__ txb,
+    const T* __restrict__ ty, const T* __restrict__ tz, T* __restrict__ q,
+    double* __restrict__ partials, const SolveScalars* __restrict__ sc) {
+  if (solve_done(sc)) return;
+  __shared__ double lds[2 * AX * AY / 64];
+  const T beta = (T)sc->beta;
+  const T apend = (T)sc->alpha_pend;
+  const int lane = threadIdx.x;
+  const long long plane = (long long)nx * ny;
+  const long long yplane = (long long)(ny + 1) * nx;
+  double acc_pq = 0.0, acc_pr = 0.0;
+  const long long L = xcd_remap(blockIdx.x, gridDim.x);
+  long long u = L * per_block;
+  const long long uend = min(ncol * nz, u + per_block);
+  while (u < uend) {
+    const long long ct = u / nz;
+    const int k0 = (int)(u - ct * nz);
+    const int k1 = (int)min((long long)nz, k0 + (uend - u));
+    u += k1 - k0;
+    const int bx = (int)(ct % tiles_x);
+    const int by = (int)(ct / tiles_x);
+    const int j = by * AY + threadIdx.y;
+    const int i0 = (bx * AX + lane) * V;
+    // every lane of a wavefront shares j, so this branch is uniform per wave
+    if (j >= ny) continue;
+    const bool live = i0 < nx;
+    long long c = (long long)k0 * plane + (long long)j * nx + i0;
+    long long yi = ((long long)k0 * (ny + 1) + j) * nx + i0;
+    const bool lbdy = i0 == 0, rbdy = i0 + V >= nx;
+    const bool lglob = lane == 0 && !lbdy, rglob = lane == AX - 1 && !rbdy;
+    const bool ylo = j > 0, yhi = j < ny - 1;
+    Pack<T, V> pm = zero<T, V>(), pc = zero<T, V>(), poc = zero<T, V>(), tzc = zero<T, V>();
+    if (live) {
+      if (k0 > 0) pm = dir<T, V>(z, pold, c - plane, beta);
+      poc = ld<T, V>(pold + c);
+      const Pack<T, V> zc = ld<T, V>(z + c);
+#pragma unroll
+      for (int e = 0; e < V; ++e) pc.v[e] = zc.v[e] + beta * poc.v[e];
+      tzc = ld<T, V>(tz + c);
+    }
+    for (int k = k0; k < k1; ++k, c += plane, yi += yplane) {
+      Pack<T, V> pp = zero<T, V>(), pop = zero<T, V>(), tzp = zero<T, V>();
+      Pack<T, V> txv = zero<T, V>(), tym = zero<T, V>(), typ = zero<T, V>();
+      Pack<T, V> pym = zero<T, V>(), pyp = zero<T, V>();
+      T left = T(0), right = T(0), txr = T(0);
+      if (live) {
+        if (k + 1 < nz) {
+          pop = ld<T, V>(pold + c + plane);
+          const Pack<T, V> zp = ld<T, V>(z + c + plane);
+#pragma unroll
+          for (int e = 0; e < V; ++e) pp.v[e] = zp.v[e] + beta * pop.v[e];
+        }
+        tzp = ld<T, V>(tz + c + plane);
+        txv = ld<T, V>(tx + c);
+        tym = ld<T, V>(ty + yi);
+        typ = ld<T, V>(ty + yi + nx);
+        if (ylo) pym = dir<T, V>(z, pold, c - nx, beta);
+        if (yhi) pyp = dir<T, V>(z, pold, c + nx, beta);
+        if (lglob) left = z[c - 1] + beta * pold[c - 1];
+        if (rglob) {
+          right = z[c + V] + beta * pold[c + V];
+          txr = tx[c + V];
+        } else if (rbdy) {
+          txr = txb[(long long)k * ny + j];
+        }
+      }
+      // neighbours across lanes (all lanes take part)
+      const T sl = __shfl_up(pc.v[V - 1], 1, AX);
+      const T sr = __shfl_down(pc.v[0], 1, AX);
+      const T st0 = __shfl_down(txv.v[0], 1, AX);
+      if (!lbdy && !lglob) left = sl;
+      if (!rbdy && !rglob) {
+        right = sr;
+        txr = st0;
+      }
+      if (live) {
+        Pack<T, V> qv;
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          const T p0 = pc.v[e];
+          const T pxm = e == 0 ? left : pc.v[e - 1];
+          const T pxp = e == V - 1 ? right : pc.v[e + 1];
+          const T txm = txv.v[e];
+          const T txp = e == V - 1 ? txr : txv.v[e + 1];
+          T s = txm * (p0 - pxm);
+          s = s + txp * (p0 - pxp);
+          s = s + tym.v[e] * (p0 - pym.v[e]);
+          s = s + typ.v[e] * (p0 - pyp.v[e]);
+          s = s + tzc.v[e] * (p0 - pm.v[e]);
+          s = s + tzp.v[e] * (p0 - pp.v[e]);
+          qv.v[e] = s;
+          acc_pq += (double)p0 * (double)s;
+        }
+        st<T, V>(q + c, qv);
+        st<T, V>(pnew + c, pc);
+        Pack<T, V> xv = ld<T, V>(x + c);
+#pragma unroll
+        for (int e = 0; e < V; ++e) xv.v[e] = xv.v[e] + apend * poc.v[e];
+        st<T, V>(x + c, xv);
+        if (FLEX) {
+          const Pack<T, V> rv = ld<T, V>(r + c);
+#pragma unroll
+          for (int e = 0; e < V; ++e) acc_pr += (double)pc.v[e] * (double)rv.v[e];
+        }
+      }
+      pm = pc;
+      pc = pp;
+      poc = pop;
+      tzc = tzp;
+    }
+  }
+  const double t0 = block_sum(acc_pq, lds);
+  if (FLEX) {
+    const double t1 = block_sum(acc_pr, lds + AX * AY / 64);
+    if (threadIdx.x == 0 && threadIdx.y == 0) partials[kMaxPartials + blockIdx.x] = t1;
+  }
+  if (threadIdx.x == 0 && threadIdx.y == 0) partials[blockIdx.x] = t0;
+}
+
+constexpr int kCgbBlocks = 2048;
+
+// r -= alpha q; (PCG) z = dinv r, partials r.z, r.r; (FCG) partial r.r
+template <class T, int V, bool FLEX>
+__global__ __launch_bounds__(kBlock) void k_cg_b(long long nvec, T* __restrict__ r,
+                                                 const T* __restrict__ q,
+                                                 const T* __restrict__ dinv, T* __restrict__ z,
+                                                 double* __restrict__ partials,
+                                                 const SolveScalars* __restrict__ sc) {
+  if (solve_done(sc)) return;
+  __shared__ double lds[2 * kBlock / 64];
+  const T alpha = (T)sc->alpha;
+  double rz = 0.0, rr = 0.0;
+  for (long long iv = blockIdx.x * (long long)blockDim.x + threadIdx.x; iv < nvec;
+       iv += (long long)gridDim.x * blockDim.x) {
+    const long long c = iv * V;
+    Pack<T, V> rv = ld<T, V>(r + c);
+    const Pack<T, V> qv = ld<T, V>(q + c);
+#pragma unroll
+    for (int e = 0; e < V; ++e) rv.v[e] = rv.v[e] - alpha * qv.v[e];
+    st<T, V>(r + c, rv);
+    if (!FLEX) {
+      const Pack<T, V> dv = ld<T, V>(dinv + c);
+      Pack<T, V> zv;
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        zv.v[e] = dv.v[e] * rv.v[e];
+        rz += (double)rv.v[e] * (double)zv.v[e];
+      }
+      st<T, V>(z + c, zv);
+    }
+#pragma unroll
+    for (int e = 0; e < V; ++e) rr += (double)rv.v[e] * (double)rv.v[e];
+  }
+  if (FLEX) {
+    const double t = block_sum(rr, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+  } else {
+    const double t0 = block_sum(rz, lds);
+    const double t1 = block_sum(rr, lds + kBlock / 64);
+    if (threadIdx.x == 0) {
+      partials[blockIdx.x] = t0;
+      partials[kMaxPartials + blockIdx.x] = t1;
+    }
+  }
+}
+
+// x += alpha_pend p (the x update left pending when the iteration stopped)
+template <class T>
+__global__ void k_cg_fixup(long long n, T* __restrict__ x, const T* __restrict__ p,
+                           const SolveScalars* __restrict__ sc) {
+  const T a = (T)sc->alpha_pend;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    x[i] = x[i] + a * p[i];
+}
+
+// x64 += x32 * inv_scale; x32 = 0
+__global__ void k_fold(long long n, double* __restrict__ x, float* __restrict__ d, double inv_scale) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    x[i] = x[i] + (double)d[i] * inv_scale;
+    d[i] = 0.0f;
+  }
+}
+
+// r32 = float(r64 * scale)
+__global__ void k_cast(long long n, const double* __restrict__ r, float* __restrict__ r32, double scale) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    r32[i] = (float)(r[i] * scale);
+}
+
+inline int vblocks(long long n) {
+  long long b = (n + kBlock - 1) / kBlock;
+  return (int)std::max(1LL, std::min(b, (long long)kCgbBlocks));
+}
+
+}  // namespace
+
+template <class T> constexpr int vec_width() { return 16 / (int)sizeof(T); }
+
+template <class T>
+bool cg_vectorizable(const Grid& g, const void* const* ptrs, int nptr) {
+  constexpr int V = vec_width<T>();
+  if (g.nx % V != 0) return false;
+  for (int i = 0; i < nptr; ++i)
+    if (reinterpret_cast<uintptr_t>(ptrs[i]) % 16 != 0) return false;
+  return true;
+}
+
+// resident workgroups per CU of a kernel (cached per kernel)
+int resident_blocks(const void* fn, int threads) {
+  static std::mutex mu;
+  static std::map<const void*, int> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(fn);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+  const int nb = std::min(kMaxPartials, per_cu * cus);
+  cache[fn] = nb;
+  return nb;
+}
+
+// sweep A; returns the number of workgroup partials per component
+template <class T>
+int launch_cg_a(const Grid& g, const Coeffs<T>& C, const T* z, const T* pold, T* pnew, T* x,
+                const T* r, T* q, double* partials, const SolveScalars* sc, bool flex, bool vec,
+                hipStream_t s) {
+  const int V = vec ? vec_width<T>() : 1;
+  const int tiles_x = (g.nx + AX * V - 1) / (AX * V);
+  const long long ncol = (long long)tiles_x * ((g.ny + AY - 1) / AY);
+  dim3 blk(AX, AY);
+  int nb = 0;
+#define CGA(TT, VV, FF)                                                                          \
+  do {                                                                                           \
+    const void* fn = reinterpret_cast<const void*>(&k_cg_a<TT, VV, FF>);                         \
+    nb = resident_blocks(fn, AX * AY);                                                           \
+    const long long per = (ncol * g.nz + nb - 1) / nb;                                           \
+    k_cg_a<TT, VV, FF><<<nb, blk, 0, s>>>(g.nx, g.ny, g.nz, tiles_x, ncol, per, z, pold, pnew, x, \
+                                          r, C.tx, C.txb, C.ty, C.tz, q, partials, sc);          \
+  } while (0)
+  if (vec) {
+    if (flex) CGA(T, vec_width<T>(), true);
+    else CGA(T, vec_width<T>(), false);
+  } else {
+    if (flex) CGA(T, 1, true);
+    else CGA(T, 1, false);
+  }
+#undef CGA
+  return nb;
+}
+
+// sweep B; returns the number of workgroup partials per component
+template <class T>
+int launch_cg_b(const Grid& g, T* r, const T* q, const T* dinv, T* z, double* partials,
+                const SolveScalars* sc, bool flex, bool vec, hipStream_t s) {
+  constexpr int VW = vec_width<T>();
+  const long long nv = vec ? g.n / VW : g.n;
+  const int nb = vblocks(nv);
+#define CGB(VV, FF) k_cg_b<T, VV, FF><<<nb, kBlock, 0, s>>>(nv, r, q, dinv, z, partials, sc)
+  if (vec) {
+    if (flex) CGB(VW, true);
+    else CGB(VW, false);
+  } else {
+    if (flex) CGB(1, true);
+    else CGB(1, false);
+  }
+#undef CGB
+  return nb;
+}
+
+template <class T> void launch_cg_fixup(const Grid& g, T* x, const T* p, const SolveScalars* sc, hipStream_t s) {
+  k_cg_fixup<T><<<vblocks(g.n), kBlock, 0, s>>>(g.n, x, p, sc);
+}
+void launch_fold(const Grid& g, double* x, float* d, double inv_scale, hipStream_t s) {
+  k_fold<<<vblocks(g.n), kBlock, 0, s>>>(g.n, x, d, inv_scale);
+}
+void launch_cast(const Grid& g, const double* r, float* r32, double scale, hipStream_t s) {
+  k_cast<<<vblocks(g.n), kBlock, 0, s>>>(g.n, r, r32, scale);
+}
+
+template bool cg_vectorizable<double>(const Grid&, const void* const*, int);
+template bool cg_vectorizable<float>(const Grid&, const void* const*, int);
+template int launch_cg_a<double>(const Grid&, const Coeffs<double>&, const double*, const double*, double*,
+                                 double*, const double*, double*, double*, const SolveScalars*, bool, bool,
+                                 hipStream_t);
+template int launch_cg_a<float>(const Grid&, const Coeffs<float>&, const float*, const float*, float*, float*,
+                                const float*, float*, double*, const SolveScalars*, bool, bool, hipStream_t);
+template int launch_cg_b<double>(const Grid&, double*, const double*, const double*, double*, double*,
+                                 const SolveScalars*, bool, bool, hipStream_t);
+template int launch_cg_b<float>(const Grid&, float*, const float*, const float*, float*, double*,
+                                const SolveScalars*, bool, bool, hipStream_t);
+template void launch_cg_fixup<double>(const Grid&, double*, const double*, const SolveScalars*, hipStream_t);
+template void launch_cg_fixup<float>(const Grid&, float*, const float*, const SolveScalars*, hipStream_t);
+
+}  // namespace nfa

@@ -92,6 +92,7 @@ struct Grid {
 // Device-side scalars of an iterative solve (one cache line each group).
 struct SolveScalars {
   double rz, pq, rr, bb, alpha, beta, tol2, pr, zq, rr_outer;
+  double alpha_pend; // x += alpha_pend p still owed by the fused sweep
   double ratio;      // stagnation threshold (mean reduction per iteration)
   int iter, done, breakdown, stalled, max_iter, window;
 };
@@ -113,8 +114,8 @@ struct Poisson {
   DevBuf rho, rho_tmp;                          // double cells
   DevBuf tx64, txb64, ty64, tz64, dinv64;       // FP64 coefficients
   DevBuf tx32, txb32, ty32, tz32, dinv32;       // FP32 coefficients
-  DevBuf r, z, p, q, tmp;                       // double work vectors
-  DevBuf x32, r32, z32, p32, q32;               // float work vectors
+  DevBuf r, z, p, p2, q, tmp;                   // double work vectors (p double-buffered)
+  DevBuf x32, r32, z32, p32, p32b, q32;         // float work vectors
   DevBuf partials;                              // double block partials
   DevBuf scal;                                  // SolveScalars (device)
   DevBuf hist;                                  // double per-iteration ||r||^2 (kHistCap)

@@ -3,13 +3,15 @@
 // Introduction: the projection's Poisson equation is solved by a
 // preconditioned conjugate-gradient method; the preconditioner is not named,
 // Jacobi (diag of the merged operator) is used.  Two variants sit on top:
-//  * mixed precision: FP64 iterative refinement (true residual b' - A'x in
-//    FP64, solution update in FP64) around an FP32 inner solve of the
-//    correction equation A'_32 d = r/||r|| to a relative reduction inner_tol;
+//  * mixed precision: the CG recurrence (operator, preconditioner, vector
+//    updates) runs in FP32; the solution is accumulated in FP64 and the true
+//    residual b' - A'x is recomputed in FP64 and replaces the FP32 one each
+//    time the recursive residual has dropped by `replace_drop` (iterative
+//    refinement without restarting the Krylov recurrence);
 //  * flexible CG (Notay FCG(1)) for a nonlinear preconditioner such as the
 //    learned one, with a stagnation monitor that switches to Jacobi-PCG.
 // Every solve ends when the FP64 true relative residual meets tol (the
-// judge); a mixed solve that fails to get there falls back to FP64 PCG.
+// judge).
 //
 // The host only enqueues kernels: alpha, beta, norms, the iteration count
 // and the convergence flag live on the device, every kernel exits at once
@@ -25,19 +27,27 @@
 
 namespace nfa {
 
-template <class T> struct Vecs {
-  T *x, *r, *z, *p, *q;
+template <class T> struct CG {
+  T* x;
+  T* r;
+  T* z;
+  T* q;
+  T* p[2];
+  Coeffs<T> C;
+  bool vec;
 };
 
 namespace {
 
-// Stencil launch wrapped in a timing event pair when profiling is on.
+inline double sq(double a) { return a * a; }
+
+// Sweep A wrapped in a timing event pair when profiling is on.
 template <class T>
-int timed_stencil(Poisson& op, const Coeffs<T>& C, const T* p, T* q, double* parts,
-                  const SolveScalars* sc, hipStream_t st) {
+int timed_cg_a(Poisson& op, CG<T>& B, int j, bool flex, hipStream_t st) {
   const bool rec = op.prof_on && op.prof_used * 2 + 1 < (int)op.prof_ev.size();
   if (rec) (void)hipEventRecord(op.prof_ev[2 * op.prof_used], st);
-  const int np = launch_stencil<T>(*op.g, C, p, nullptr, q, parts, sc, ST_APPLY, st);
+  const int np = launch_cg_a<T>(*op.g, B.C, B.z, B.p[j & 1], B.p[(j + 1) & 1], B.x, B.r, B.q,
+                                op.partials.as<double>(), op.scal.as<SolveScalars>(), flex, B.vec, st);
   if (rec) {
     (void)hipEventRecord(op.prof_ev[2 * op.prof_used + 1], st);
     op.prof_kind[op.prof_used] = sizeof(T) == 8 ? 0 : 1;
@@ -46,14 +56,12 @@ int timed_stencil(Poisson& op, const Coeffs<T>& C, const T* p, T* q, double* par
   return np;
 }
 
-// Accumulate the recorded launches that actually ran (the device state may
-// have ended the solve, making later launches exit at once: those are the
-// ones after the last `done` poll and are excluded by counting only launches
-// up to the iteration count).
-void harvest_profile(Poisson& op, int iterations) {  // iterations run in this phase
+// Accumulate the first `ran` recorded launches (those after the solver state
+// said done exited at once and are not counted).
+void harvest_profile(Poisson& op, int ran) {
   if (!op.prof_on) return;
   (void)hipDeviceSynchronize();
-  const int upto = std::min(op.prof_used, std::max(0, iterations));
+  const int upto = std::min(op.prof_used, std::max(0, ran));
   for (int i = 0; i < upto; ++i) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, op.prof_ev[2 * i], op.prof_ev[2 * i + 1]) == hipSuccess) {
@@ -64,106 +72,13 @@ void harvest_profile(Poisson& op, int iterations) {  // iterations run in this p
   op.prof_used = 0;
 }
 
-nfa_status poll_until_done(Poisson& op, const std::function<void()>& batch, hipStream_t st,
-                           SolveScalars* out) {
-  SolveScalars* sc = op.scal.as<SolveScalars>();
-  int slot = 0;
-  bool have_prev = false;
-  for (;;) {
-    batch();
-    NFA_CHECK_LAUNCH();
-    NFA_HIP(hipMemcpyAsync(&op.h_scal[slot], sc, sizeof(SolveScalars), hipMemcpyDeviceToHost, st));
-    NFA_HIP(hipEventRecord(op.ev[slot], st));
-    if (have_prev) {
-      NFA_HIP(hipEventSynchronize(op.ev[slot ^ 1]));
-      if (op.h_scal[slot ^ 1].done) break;
-    }
-    have_prev = true;
-    slot ^= 1;
-  }
-  NFA_HIP(hipStreamSynchronize(st));
-  NFA_HIP(hipMemcpy(out, sc, sizeof(SolveScalars), hipMemcpyDeviceToHost));
-  return NFA_OK;
-}
-
 nfa_status read_scalars(Poisson& op, hipStream_t st, SolveScalars* out) {
   NFA_HIP(hipStreamSynchronize(st));
   NFA_HIP(hipMemcpy(out, op.scal.p, sizeof(SolveScalars), hipMemcpyDeviceToHost));
   return NFA_OK;
 }
 
-// Jacobi-PCG from the residual in v.r and the iterate in v.x (primal).
-template <class T>
-nfa_status pcg_phase(Poisson& op, const Coeffs<T>& C, Vecs<T> v, int check_every, hipStream_t st,
-                     SolveScalars* out, int iter0) {
-  Grid& g = *op.g;
-  const long long n = g.n;
-  SolveScalars* sc = op.scal.as<SolveScalars>();
-  double* parts = op.partials.as<double>();
-  double* hist = op.hist.as<double>();
-  const int nb = launch_jacobi<T>(v.r, C.dinv, v.z, n, parts, st);
-  launch_merge_copy<T>(g, v.z, st, nullptr);
-  launch_finalize(parts, nb, 2, PH_INIT, sc, hist, st);
-  launch_copy<T>(v.z, v.p, n, st);
-  auto batch = [&]() {
-    for (int it = 0; it < check_every; ++it) {
-      const int np = timed_stencil<T>(op, C, v.p, v.q, parts, sc, st);
-      launch_merge_gather<T>(g, v.q, st, sc);
-      launch_finalize(parts, np, 1, PH_PQ, sc, hist, st);
-      const int nu = launch_update<T>(v.x, v.p, v.r, v.q, C.dinv, v.z, n, parts, sc, st);
-      launch_merge_copy<T>(g, v.z, st, sc);
-      launch_finalize(parts, nu, 2, PH_UPD, sc, hist, st);
-      launch_direction<T>(v.z, v.p, n, sc, st);
-    }
-  };
-  nfa_status e = poll_until_done(op, batch, st, out);
-  harvest_profile(op, out->iter - iter0);
-  return e;
-}
-
-// Flexible CG(1) with preconditioner `pc` from the residual in v.r.
-template <class T>
-nfa_status fcg_phase(Poisson& op, const Coeffs<T>& C, Vecs<T> v, int pc, void* unet,
-                     int check_every, hipStream_t st, SolveScalars* out, int iter0) {
-  Grid& g = *op.g;
-  const long long n = g.n;
-  SolveScalars* sc = op.scal.as<SolveScalars>();
-  double* parts = op.partials.as<double>();
-  double* hist = op.hist.as<double>();
-  launch_fill<T>(v.p, T(0), n, st);
-  launch_fill<T>(v.q, T(0), n, st);
-  const int nb = launch_dot<T>(v.r, v.r, n, parts, nullptr, st);
-  launch_finalize(parts, nb, 1, PH_INIT, sc, hist, st);
-  nfa_status pst = NFA_OK;
-  auto batch = [&]() {
-    for (int it = 0; it < check_every; ++it) {
-      if (pc == NFA_PC_JACOBI || pc == NFA_PC_JACOBI_FCG) {
-        launch_scale<T>(v.r, C.dinv, v.z, n, sc, st);
-      } else if (pc == NFA_PC_TEST_SABOTAGE) {
-        launch_sabotage<T>(g.reduced.as<unsigned char>(), v.z, n, sc, st);
-      } else {
-        nfa_status e = unet_precond_apply(unet, op, (const float*)v.r, (float*)v.z, sc, st);
-        if (e != NFA_OK && pst == NFA_OK) pst = e;
-      }
-      launch_merge_copy<T>(g, v.z, st, sc);
-      const int nz = launch_dot<T>(v.z, v.q, n, parts, sc, st);
-      launch_finalize(parts, nz, 1, PH_ZQ, sc, hist, st);
-      const int nd = launch_fdirection<T>(v.z, v.p, v.r, n, parts, sc, st);
-      launch_finalize(parts, nd, 1, PH_PR, sc, hist, st);
-      const int np = timed_stencil<T>(op, C, v.p, v.q, parts, sc, st);
-      launch_merge_gather<T>(g, v.q, st, sc);
-      launch_finalize(parts, np, 1, PH_PQF, sc, hist, st);
-      const int nu = launch_fupdate<T>(v.x, v.p, v.r, v.q, n, parts, sc, st);
-      launch_finalize(parts, nu, 1, PH_UPDF, sc, hist, st);
-    }
-  };
-  nfa_status e = poll_until_done(op, batch, st, out);
-  harvest_profile(op, out->iter - iter0);
-  if (pst != NFA_OK) return pst;
-  return e;
-}
-
-// r = b' - A' x (x primal), optionally ||r||^2 into the state (phase).
+// r = b' - A' x (x primal), ||r||^2 into the state (phase) when phase >= 0.
 nfa_status residual64(Poisson& op, const double* b, const double* x, double* r, int phase,
                       hipStream_t st) {
   Grid& g = *op.g;
@@ -178,116 +93,183 @@ nfa_status residual64(Poisson& op, const double* b, const double* x, double* r, 
   return NFA_OK;
 }
 
+// One iteration of PCG (pc == Jacobi) or flexible CG (any other pc).
+template <class T>
+void enqueue_iter(Poisson& op, CG<T>& B, int j, int pc, void* unet, nfa_status* pst, hipStream_t st) {
+  Grid& g = *op.g;
+  SolveScalars* sc = op.scal.as<SolveScalars>();
+  double* parts = op.partials.as<double>();
+  double* hist = op.hist.as<double>();
+  const bool flex = pc != NFA_PC_JACOBI;
+  if (flex) {
+    if (pc == NFA_PC_JACOBI_FCG) {
+      launch_scale<T>(B.r, B.C.dinv, B.z, g.n, sc, st);
+    } else if (pc == NFA_PC_TEST_SABOTAGE) {
+      launch_sabotage<T>(g.reduced.as<unsigned char>(), B.z, g.n, sc, st);
+    } else {
+      const nfa_status e = unet_precond_apply(unet, op, (const float*)B.r, (float*)B.z, sc, st);
+      if (e != NFA_OK && *pst == NFA_OK) *pst = e;
+    }
+    launch_merge_copy<T>(g, B.z, st, sc);
+    const int nz = launch_dot<T>(B.z, B.q, g.n, parts, sc, st);
+    launch_finalize(parts, nz, 1, PH_ZQ, sc, hist, st);
+  }
+  const int na = timed_cg_a<T>(op, B, j, flex, st);
+  launch_merge_gather<T>(g, B.q, st, sc);
+  launch_finalize(parts, na, flex ? 2 : 1, flex ? PH_PQF : PH_PQ, sc, hist, st);
+  const int nb = launch_cg_b<T>(g, B.r, B.q, B.C.dinv, B.z, parts, sc, flex, B.vec, st);
+  if (!flex) launch_merge_copy<T>(g, B.z, st, sc);
+  launch_finalize(parts, nb, flex ? 1 : 2, flex ? PH_UPDF : PH_UPD, sc, hist, st);
+}
+
+// Start (fresh) or continue (after a residual replacement) the recurrence
+// from the residual in B.r.
+template <class T>
+void begin_phase(Poisson& op, CG<T>& B, int pc, bool fresh, hipStream_t st) {
+  Grid& g = *op.g;
+  SolveScalars* sc = op.scal.as<SolveScalars>();
+  double* parts = op.partials.as<double>();
+  double* hist = op.hist.as<double>();
+  const bool flex = pc != NFA_PC_JACOBI;
+  if (fresh) {
+    launch_fill<T>(B.p[0], T(0), g.n, st);
+    if (flex) launch_fill<T>(B.q, T(0), g.n, st);
+  }
+  if (flex) {
+    const int nb = launch_dot<T>(B.r, B.r, g.n, parts, nullptr, st);
+    launch_finalize(parts, nb, 1, fresh ? PH_INIT : PH_RELIABLE_F, sc, hist, st);
+  } else {
+    const int nb = launch_jacobi<T>(B.r, B.C.dinv, B.z, g.n, parts, st);
+    launch_merge_copy<T>(g, B.z, st, nullptr);
+    launch_finalize(parts, nb, 2, fresh ? PH_INIT : PH_RELIABLE, sc, hist, st);
+  }
+}
+
 void copy_history(Poisson& op, const nfa_solve_opts* o, nfa_solve_info* info, int upto,
-                  double scale2, hipStream_t st) {
+                  double inv_norm2, hipStream_t st) {
   if (!o->history || o->history_cap <= 0) return;
-  const int have = info->history_len;
-  const int room = o->history_cap - have;
-  if (room <= 0) return;
-  const int cnt = std::min(room, upto + 1);
+  const int cnt = std::min(o->history_cap, std::min(upto, kHistCap) + 1);
   std::vector<double> h(cnt);
   (void)hipStreamSynchronize(st);
   (void)hipMemcpy(h.data(), op.hist.p, cnt * sizeof(double), hipMemcpyDeviceToHost);
-  for (int k = 0; k < cnt; ++k) o->history[have + k] = std::sqrt(std::max(0.0, h[k] * scale2));
-  info->history_len = have + cnt;
+  for (int k = 0; k < cnt; ++k) o->history[k] = std::sqrt(std::max(0.0, h[k] * inv_norm2));
+  info->history_len = cnt;
 }
 
-nfa_status solve_f64(Poisson& op, const double* b, double* x, const nfa_solve_opts* o,
-                     const SolveScalars& s0, hipStream_t st, nfa_solve_info* info, int iters_done) {
+// CG with FP64 residual replacement.  T = double: plain FP64 Jacobi-PCG, the
+// true residual checked when the recursion converges.  T = float: the
+// iteration runs in FP32 on the scaled residual; whenever the recursive
+// residual has dropped by `delta` (or the recursion ends) the FP32 solution
+// increment is folded into the FP64 solution, the FP64 true residual
+// b' - A'x is recomputed (the judge) and replaces the FP32 one, and CG goes
+// on with the same search direction.
+template <class T>
+nfa_status cg_solve(Poisson& op, const double* b, double* x64, const nfa_solve_opts* o,
+                    const SolveScalars& s0, hipStream_t st, nfa_solve_info* info) {
+  constexpr bool mixed = sizeof(T) == 4;
   Grid& g = *op.g;
   SolveScalars* sc = op.scal.as<SolveScalars>();
-  const int budget = std::max(0, o->max_iters - iters_done);
-  launch_set_scalars(sc, o->tol * o->tol, 0, budget, 1, 0, 1.0, st);
-  Vecs<double> v{x, op.r.as<double>(), op.z.as<double>(), op.p.as<double>(), op.q.as<double>()};
-  SolveScalars out{};
-  nfa_status status = NFA_NOT_CONVERGED;
-  for (int restart = 0; restart <= 3; ++restart) {
-    nfa_status e = residual64(op, b, x, v.r, -1, st);
-    if (e != NFA_OK) return e;
-    e = pcg_phase<double>(op, op.c64(), v, std::max(1, o->check_every), st, &out, out.iter);
-    if (e != NFA_OK) return e;
-    if (out.breakdown == 2) return fail(NFA_ERR_NUMERIC, "nfa_poisson_solve: NaN/Inf in the iteration");
-    e = residual64(op, b, x, v.r, PH_RR, st);
-    if (e != NFA_OK) return e;
-    SolveScalars now{};
-    if ((e = read_scalars(op, st, &now)) != NFA_OK) return e;
-    info->relres = std::sqrt(now.rr / s0.bb);
-    info->iterations = iters_done + out.iter;
-    info->outer = restart;
-    if (!std::isfinite(info->relres)) return fail(NFA_ERR_NUMERIC, "nfa_poisson_solve: NaN/Inf residual");
-    if (info->relres <= o->tol) { status = NFA_OK; break; }
-    if (out.iter >= budget) break;
-    launch_set_scalars(sc, o->tol * o->tol, 0, budget, 0, 0, 1.0, st);
+  const double bnorm = std::sqrt(s0.bb);
+  const double scale = mixed ? std::ldexp(1.0, -std::ilogb(bnorm)) : 1.0;   // exact power of two
+  CG<T> B;
+  if constexpr (mixed) {
+    B = CG<T>{op.x32.as<float>(), op.r32.as<float>(), op.z32.as<float>(), op.q32.as<float>(),
+              {op.p32.as<float>(), op.p32b.as<float>()}, op.c32(), false};
+  } else {
+    B = CG<T>{x64, op.r.as<double>(), op.z.as<double>(), op.q.as<double>(),
+              {op.p.as<double>(), op.p2.as<double>()}, op.c64(), false};
   }
-  copy_history(op, o, info, std::min(out.iter, kHistCap), 1.0 / s0.bb, st);
-  return status;
-}
-
-nfa_status solve_mixed(Poisson& op, const double* b, double* x, const nfa_solve_opts* o,
-                       const SolveScalars& s0, hipStream_t st, nfa_solve_info* info) {
-  Grid& g = *op.g;
-  const long long n = g.n;
-  SolveScalars* sc = op.scal.as<SolveScalars>();
-  Vecs<float> v{op.x32.as<float>(), op.r32.as<float>(), op.z32.as<float>(), op.p32.as<float>(),
-                op.q32.as<float>()};
+  const void* ptrs[] = {B.x, B.r, B.z, B.q, B.p[0], B.p[1], B.C.tx, B.C.ty, B.C.tz, B.C.dinv};
+  B.vec = cg_vectorizable<T>(g, ptrs, 10);
+  int pc = o->precond;
+  const double delta = mixed ? o->replace_drop : 0.0;
+  double* r64 = op.r.as<double>();
   const int check = std::max(1, o->check_every);
-  int total = 0;
-  bool converged = false;
-  for (int outer = 0; outer <= o->max_outer; ++outer) {
-    nfa_status e = residual64(op, b, x, op.r.as<double>(), PH_RRO, st);
-    if (e != NFA_OK) return e;
-    SolveScalars now{};
-    if ((e = read_scalars(op, st, &now)) != NFA_OK) return e;
-    const double relres = std::sqrt(now.rr_outer / s0.bb);
-    info->relres = relres;
-    info->outer = outer;
-    info->iterations = total;
-    if (!std::isfinite(relres)) return fail(NFA_ERR_NUMERIC, "nfa_poisson_solve: NaN/Inf residual");
-    if (relres <= o->tol) { converged = true; break; }
-    if (total >= o->max_iters || outer == o->max_outer) break;
-    launch_cast_scaled(op.r.as<double>(), v.r, n, sc, st);
-    launch_fill<float>(v.x, 0.0f, n, st);
-    // inner reduction: what is still needed (with a factor 4 margin), but no
-    // deeper than inner_tol, near where FP32 residuals stop being accurate
-    const double need = 0.25 * o->tol / relres;
-    const double eta = std::min(0.5, std::max(o->inner_tol, need));
-    const double eta2 = eta * eta;
-    const bool flexible = o->precond == NFA_PC_UNET || o->precond == NFA_PC_TEST_SABOTAGE ||
-                          o->precond == NFA_PC_JACOBI_FCG;
-    launch_set_scalars(sc, eta2, 1, o->max_iters - total, 1, flexible ? o->fallback_window : 0,
-                       o->fallback_ratio, st);
-    SolveScalars out{};
-    if (flexible && !info->fallback) {
-      e = fcg_phase<float>(op, op.c32(), v, o->precond, o->unet, check, st, &out, 0);
-      if (e != NFA_OK) return e;
-      if (out.stalled || out.breakdown == 1) {
-        // switch to Jacobi-PCG for the rest of the inner solve, from the current iterate
-        info->fallback = 1;
-        launch_set_scalars(sc, eta2, 1, o->max_iters - total, 0, 0, 1.0, st);
-        e = pcg_phase<float>(op, op.c32(), v, check, st, &out, out.iter);
-        if (e != NFA_OK) return e;
-      }
-    } else {
-      e = pcg_phase<float>(op, op.c32(), v, check, st, &out, 0);
-      if (e != NFA_OK) return e;
-    }
-    copy_history(op, o, info, std::min(out.iter, kHistCap), now.rr_outer / s0.bb, st);
-    if (out.breakdown == 2) return fail(NFA_ERR_NUMERIC, "nfa_poisson_solve: NaN/Inf in the inner iteration");
-    total += out.iter;
-    launch_refine_update(x, v.x, n, sc, st);
+
+  nfa_status e = residual64(op, b, x64, r64, PH_RRO, st);
+  if (e != NFA_OK) return e;
+  SolveScalars S{};
+  if ((e = read_scalars(op, st, &S)) != NFA_OK) return e;
+  double relres = std::sqrt(S.rr_outer / s0.bb);
+  info->relres = relres;
+  if (!std::isfinite(relres)) return fail(NFA_ERR_NUMERIC, "nfa_poisson_solve: NaN/Inf residual");
+  if (relres <= o->tol) return NFA_OK;
+  if (mixed) {
+    launch_cast(g, r64, op.r32.as<float>(), scale, st);
+    launch_fill<float>(op.x32.as<float>(), 0.0f, g.n, st);
+  }
+  // the FP32 recursion aims a little below tol so that its rounding cannot
+  // stop it just above the FP64 tolerance
+  const double tol2 = sq((mixed ? 0.7 : 1.0) * o->tol * bnorm * scale);
+  const bool flex0 = pc != NFA_PC_JACOBI;
+  launch_set_scalars(sc, tol2, 1, o->max_iters, 1,
+                     flex0 ? o->fallback_window : 0, o->fallback_ratio, st);
+  begin_phase<T>(op, B, pc, true, st);
+  int iter_phase = 0, j = 0, last_harvest = 0, last_update_iter = -1, stuck = 0;
+  double rr_ref = sq(relres * bnorm * scale);
+  nfa_status pst = NFA_OK, status = NFA_NOT_CONVERGED;
+  int slot = 0;
+  bool have_prev = false;
+  for (;;) {
+    for (int it = 0; it < check; ++it, ++j) enqueue_iter<T>(op, B, j, pc, o->unet, &pst, st);
     NFA_CHECK_LAUNCH();
+    if (pst != NFA_OK) return pst;
+    NFA_HIP(hipMemcpyAsync(&op.h_scal[slot], sc, sizeof(SolveScalars), hipMemcpyDeviceToHost, st));
+    NFA_HIP(hipEventRecord(op.ev[slot], st));
+    bool act = false;
+    if (have_prev) {
+      NFA_HIP(hipEventSynchronize(op.ev[slot ^ 1]));
+      const SolveScalars& snap = op.h_scal[slot ^ 1];
+      act = snap.done || (delta > 0 && snap.rr <= sq(delta) * rr_ref);
+    }
+    if (!act) {
+      have_prev = true;
+      slot ^= 1;
+      continue;
+    }
+    // ---- residual replacement (the FP64 judge)
+    if ((e = read_scalars(op, st, &S)) != NFA_OK) return e;
+    harvest_profile(op, S.iter - last_harvest);
+    last_harvest = S.iter;
+    const int J = S.iter - iter_phase;
+    launch_cg_fixup<T>(g, B.x, B.p[J & 1], sc, st);
+    if (mixed) launch_fold(g, x64, op.x32.as<float>(), 1.0 / scale, st);
+    if ((e = residual64(op, b, x64, r64, PH_RRO, st)) != NFA_OK) return e;
+    SolveScalars S2{};
+    if ((e = read_scalars(op, st, &S2)) != NFA_OK) return e;
+    relres = std::sqrt(S2.rr_outer / s0.bb);
+    info->relres = relres;
+    info->iterations = S.iter;
+    info->outer += 1;
+    if (S.breakdown == 2 || !std::isfinite(relres))
+      return fail(NFA_ERR_NUMERIC, "nfa_poisson_solve: NaN/Inf in the iteration");
+    if (relres <= o->tol) { status = NFA_OK; break; }
+    if (S.iter >= o->max_iters) break;
+    if (S.iter == last_update_iter && ++stuck >= 3) break;   // no progress possible
+    if (S.iter != last_update_iter) stuck = 0;
+    last_update_iter = S.iter;
+    if (mixed) launch_cast(g, r64, op.r32.as<float>(), scale, st);
+    const bool fresh = S.breakdown == 1 || S.stalled;
+    if (S.stalled && pc != NFA_PC_JACOBI) {
+      // the flexible preconditioner stopped paying: Jacobi-PCG from here on
+      pc = NFA_PC_JACOBI;
+      info->fallback = 1;
+    }
+    launch_set_scalars(sc, tol2, 1, o->max_iters, 0,
+                       pc != NFA_PC_JACOBI ? o->fallback_window : 0, o->fallback_ratio, st);
+    begin_phase<T>(op, B, pc, fresh, st);
+    if (fresh) {
+      iter_phase = S.iter;
+      j = 0;
+    } else {
+      j = J;
+    }
+    rr_ref = sq(relres * bnorm * scale);
+    have_prev = false;
+    slot = 0;
   }
-  info->iterations = total;
-  if (converged) return NFA_OK;
-  if (total < o->max_iters) {
-    // refinement did not reach the tolerance: FP64 Jacobi-PCG from the current x
-    info->fallback = 1;
-    const int outer = info->outer;
-    nfa_status e = solve_f64(op, b, x, o, s0, st, info, total);
-    info->outer += outer;
-    return e;
-  }
-  return NFA_NOT_CONVERGED;
+  copy_history(op, o, info, info->iterations, 1.0 / sq(bnorm * scale), st);
+  return status;
 }
 
 }  // namespace
@@ -301,8 +283,7 @@ extern "C" void nfa_solve_opts_default(nfa_solve_opts* o) {
   o->max_iters = 200000;
   o->precond = NFA_PC_JACOBI;
   o->precision = NFA_PREC_F64;
-  o->inner_tol = 1e-6;
-  o->max_outer = 8;
+  o->replace_drop = 0.1;
   o->fcg_m = 1;
   o->fallback_ratio = 0.99;
   o->fallback_window = 10;
@@ -329,8 +310,8 @@ extern "C" nfa_status nfa_poisson_solve(nfa_poisson op, const double* b, double*
   if (o->precond == NFA_PC_UNET && !o->unet)
     return fail(NFA_ERR_INVALID, "nfa_poisson_solve: NFA_PC_UNET needs opts->unet");
   if (o->fcg_m != 1) return fail(NFA_ERR_INVALID, "nfa_poisson_solve: fcg_m must be 1");
-  if (o->precision == NFA_PREC_MIXED && (!(o->inner_tol > 0 && o->inner_tol < 1) || o->max_outer < 1))
-    return fail(NFA_ERR_INVALID, "nfa_poisson_solve: mixed needs 0 < inner_tol < 1 and max_outer >= 1");
+  if (o->precision == NFA_PREC_MIXED && !(o->replace_drop > 0 && o->replace_drop < 1))
+    return fail(NFA_ERR_INVALID, "nfa_poisson_solve: mixed needs 0 < replace_drop < 1");
   const auto t0 = std::chrono::steady_clock::now();
   Grid& g = *op->g;
   const hipStream_t st = S(s);
@@ -352,8 +333,8 @@ extern "C" nfa_status nfa_poisson_solve(nfa_poisson op, const double* b, double*
     info->relres = 0.0;
     return NFA_OK;
   }
-  nfa_status status = o->precision == NFA_PREC_F64 ? solve_f64(*op, b, x, o, s0, st, info, 0)
-                                                   : solve_mixed(*op, b, x, o, s0, st, info);
+  nfa_status status = o->precision == NFA_PREC_F64 ? cg_solve<double>(*op, b, x, o, s0, st, info)
+                                                   : cg_solve<float>(*op, b, x, o, s0, st, info);
   if (status < 0) return status;
   if (g.all_neumann() && g.n_reduced > 0) {
     const int np = launch_masked_sum<double>(x, g.reduced.as<unsigned char>(), g.n, parts, st);

@@ -11,6 +11,7 @@
 #include "device_util.h"
 #include "nfa_internal.h"
 #include "vecops.h"
+#include "phase.h"
 
 namespace nfa {
 namespace {
@@ -69,22 +70,12 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const double* partials, i
   }
 }
 
-// Stagnation test on the squared-residual history: mean reduction factor of
-// ||r|| per iteration over the last `window` iterations above `ratio`.
-__device__ __forceinline__ bool stalled_now(const SolveScalars* sc, const double* hist) {
-  const int w = sc->window;
-  if (!hist || w <= 0 || sc->iter < 2 * w || sc->iter > sc->max_iter || sc->iter > kHistCap)
-    return false;
-  const double a = hist[sc->iter], b = hist[sc->iter - w];
-  if (!(b > 0.0)) return false;
-  const double rate = pow(a / b, 0.5 / w);
-  return !(rate <= sc->ratio);
-}
-
 // Finalize a reduction and advance the solver state (single workgroup).
 __global__ __launch_bounds__(1024) void k_finalize(const double* partials, int n, int ncomp, int phase,
                                                     SolveScalars* sc, double* hist) {
-  if (phase != PH_BB && phase != PH_RR && phase != PH_RRO && phase != PH_INIT && sc->done) return;
+  if (phase != PH_BB && phase != PH_RR && phase != PH_RRO && phase != PH_INIT && phase != PH_RELIABLE &&
+      phase != PH_RELIABLE_F && sc->done)
+    return;
   __shared__ double lds[1024 / 64];
   __shared__ double val[4];
   for (int c = 0; c < ncomp; ++c) {
@@ -94,81 +85,7 @@ __global__ __launch_bounds__(1024) void k_finalize(const double* partials, int n
     if (threadIdx.x == 0) val[c] = t;
     __syncthreads();
   }
-  if (threadIdx.x != 0) return;
-  switch (phase) {
-    case PH_BB:
-      sc->bb = val[0];
-      break;
-    case PH_RR:
-      sc->rr = val[0];
-      break;
-    case PH_RRO:
-      sc->rr_outer = val[0];
-      break;
-    case PH_INIT:
-      // ncomp 2: (r.z, r.r) for PCG; ncomp 1: (r.r) for FCG
-      if (ncomp == 2) { sc->rz = val[0]; sc->rr = val[1]; }
-      else { sc->rr = val[0]; }
-      sc->pq = 0.0;
-      sc->done = 0;
-      sc->breakdown = 0;
-      sc->stalled = 0;
-      if (!isfinite(sc->rr) || (ncomp == 2 && !isfinite(sc->rz))) { sc->breakdown = 2; sc->done = 1; }
-      else if (sc->rr <= sc->tol2) sc->done = 1;
-      if (hist && sc->iter <= sc->max_iter && sc->iter <= kHistCap) hist[sc->iter] = sc->rr;
-      break;
-    case PH_PQ:
-      sc->pq = val[0];
-      if (!(val[0] > 0.0) || !isfinite(val[0])) {
-        sc->breakdown = isfinite(val[0]) ? 1 : 2;
-        sc->done = 1;
-      } else {
-        sc->alpha = sc->rz / val[0];
-      }
-      break;
-    case PH_UPD: {
-      const double rzn = val[0], rr = val[1];
-      sc->beta = rzn / sc->rz;
-      sc->rz = rzn;
-      sc->rr = rr;
-      sc->iter += 1;
-      if (hist && sc->iter <= sc->max_iter && sc->iter <= kHistCap) hist[sc->iter] = rr;
-      if (!isfinite(rr) || !isfinite(rzn)) { sc->breakdown = 2; sc->done = 1; }
-      else if (rr <= sc->tol2) sc->done = 1;
-      else if (sc->iter >= sc->max_iter) sc->done = 1;
-      else if (stalled_now(sc, hist)) { sc->stalled = 1; sc->done = 1; }
-      break;
-    }
-    case PH_ZQ:   // flexible CG: beta = -(z.q_prev)/(p_prev.q_prev), 0 on the first step
-      sc->zq = val[0];
-      sc->beta = (sc->pq > 0.0 && isfinite(val[0])) ? -val[0] / sc->pq : 0.0;
-      break;
-    case PH_PR:
-      sc->pr = val[0];
-      break;
-    case PH_PQF:
-      sc->pq = val[0];
-      if (!(val[0] > 0.0) || !isfinite(val[0])) {
-        sc->breakdown = isfinite(val[0]) ? 1 : 2;
-        sc->done = 1;
-      } else {
-        sc->alpha = sc->pr / val[0];
-      }
-      break;
-    case PH_UPDF: {
-      const double rr = val[0];
-      sc->rr = rr;
-      sc->iter += 1;
-      if (hist && sc->iter <= sc->max_iter && sc->iter <= kHistCap) hist[sc->iter] = rr;
-      if (!isfinite(rr)) { sc->breakdown = 2; sc->done = 1; }
-      else if (rr <= sc->tol2) sc->done = 1;
-      else if (sc->iter >= sc->max_iter) sc->done = 1;
-      else if (stalled_now(sc, hist)) { sc->stalled = 1; sc->done = 1; }
-      break;
-    }
-    default:
-      break;
-  }
+  if (threadIdx.x == 0) apply_phase(phase, ncomp, val, sc, hist);
 }
 
 template <class T>
@@ -190,81 +107,6 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(long long n, const T* __restr
     partials[blockIdx.x] = t0;
     partials[kMaxPartials + blockIdx.x] = t1;
   }
-}
-
-// x += alpha p; r -= alpha q; z = dinv r; partials r.z, r.r
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_update(long long n, T* __restrict__ x,
-                                                   const T* __restrict__ p, T* __restrict__ r,
-                                                   const T* __restrict__ q,
-                                                   const T* __restrict__ dinv, T* __restrict__ z,
-                                                   double* partials, const SolveScalars* sc) {
-  if (solve_done(sc)) return;
-  __shared__ double lds[2 * kBlock / 64];
-  const T alpha = (T)sc->alpha;
-  double rz = 0.0, rr = 0.0;
-  GRID_STRIDE(i, n) {
-    x[i] = x[i] + alpha * p[i];
-    const T ri = r[i] - alpha * q[i];
-    r[i] = ri;
-    const T zi = dinv[i] * ri;
-    z[i] = zi;
-    rz += (double)ri * (double)zi;
-    rr += (double)ri * (double)ri;
-  }
-  const double t0 = block_sum(rz, lds);
-  const double t1 = block_sum(rr, lds + kBlock / 64);
-  if (threadIdx.x == 0) {
-    partials[blockIdx.x] = t0;
-    partials[kMaxPartials + blockIdx.x] = t1;
-  }
-}
-
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_direction(long long n, const T* __restrict__ z,
-                                                      T* __restrict__ p, const SolveScalars* sc) {
-  if (solve_done(sc)) return;
-  const T beta = (T)sc->beta;
-  GRID_STRIDE(i, n) p[i] = z[i] + beta * p[i];
-}
-
-// flexible CG: p = z + beta p (beta = -(z.q)/(p.q) from the device state);
-// partial p.r
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_fdirection(long long n, const T* __restrict__ z,
-                                                       T* __restrict__ p, const T* __restrict__ r,
-                                                       double* partials, const SolveScalars* sc) {
-  if (solve_done(sc)) return;
-  __shared__ double lds[kBlock / 64];
-  const T beta = (T)sc->beta;
-  double pr = 0.0;
-  GRID_STRIDE(i, n) {
-    const T pi = z[i] + beta * p[i];
-    p[i] = pi;
-    pr += (double)pi * (double)r[i];
-  }
-  const double t = block_sum(pr, lds);
-  if (threadIdx.x == 0) partials[blockIdx.x] = t;
-}
-
-// flexible CG: x += alpha p; r -= alpha q; partial r.r
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_fupdate(long long n, T* __restrict__ x,
-                                                    const T* __restrict__ p, T* __restrict__ r,
-                                                    const T* __restrict__ q, double* partials,
-                                                    const SolveScalars* sc) {
-  if (solve_done(sc)) return;
-  __shared__ double lds[kBlock / 64];
-  const T alpha = (T)sc->alpha;
-  double rr = 0.0;
-  GRID_STRIDE(i, n) {
-    x[i] = x[i] + alpha * p[i];
-    const T ri = r[i] - alpha * q[i];
-    r[i] = ri;
-    rr += (double)ri * (double)ri;
-  }
-  const double t = block_sum(rr, lds);
-  if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
 // preconditioner z = dinv r (no reduction), early exit with the solver state
@@ -302,20 +144,6 @@ __global__ void k_fill(long long n, T* a, T v) {
 
 __global__ void k_init_x(long long n, double* x, const unsigned char* act, int warm) {
   GRID_STRIDE(i, n) x[i] = (warm && act[i]) ? x[i] : 0.0;
-}
-
-// r32 = float(r64 / ||r||)
-__global__ void k_cast_scaled(long long n, const double* __restrict__ r, float* __restrict__ r32,
-                              const SolveScalars* sc) {
-  const double inv = 1.0 / sqrt(sc->rr_outer);
-  GRID_STRIDE(i, n) r32[i] = (float)(r[i] * inv);
-}
-
-// x += ||r|| * double(d32)
-__global__ void k_refine_update(long long n, double* __restrict__ x, const float* __restrict__ d,
-                                const SolveScalars* sc) {
-  const double s = sqrt(sc->rr_outer);
-  GRID_STRIDE(i, n) x[i] = x[i] + s * (double)d[i];
 }
 
 // tol_mode 0: tol2 = t * bb; 1: tol2 = t (absolute)
@@ -375,43 +203,6 @@ template <class T> int launch_jacobi(const T* r, const T* dinv, T* z, long long 
 template int launch_jacobi<double>(const double*, const double*, double*, long long, double*, hipStream_t);
 template int launch_jacobi<float>(const float*, const float*, float*, long long, double*, hipStream_t);
 
-template <class T> int launch_update(T* x, const T* p, T* r, const T* q, const T* dinv, T* z,
-                                     long long n, double* partials, const SolveScalars* sc,
-                                     hipStream_t s) {
-  const int nb = vec_blocks(n);
-  k_update<T><<<nb, kBlock, 0, s>>>(n, x, p, r, q, dinv, z, partials, sc);
-  return nb;
-}
-template int launch_update<double>(double*, const double*, double*, const double*, const double*, double*,
-                                   long long, double*, const SolveScalars*, hipStream_t);
-template int launch_update<float>(float*, const float*, float*, const float*, const float*, float*,
-                                  long long, double*, const SolveScalars*, hipStream_t);
-
-template <class T> void launch_direction(const T* z, T* p, long long n, const SolveScalars* sc,
-                                         hipStream_t s) {
-  k_direction<T><<<vec_blocks(n), kBlock, 0, s>>>(n, z, p, sc);
-}
-template void launch_direction<double>(const double*, double*, long long, const SolveScalars*, hipStream_t);
-template void launch_direction<float>(const float*, float*, long long, const SolveScalars*, hipStream_t);
-
-template <class T> int launch_fdirection(const T* z, T* p, const T* r, long long n, double* partials,
-                                         const SolveScalars* sc, hipStream_t s) {
-  const int nb = vec_blocks(n);
-  k_fdirection<T><<<nb, kBlock, 0, s>>>(n, z, p, r, partials, sc);
-  return nb;
-}
-template int launch_fdirection<double>(const double*, double*, const double*, long long, double*, const SolveScalars*, hipStream_t);
-template int launch_fdirection<float>(const float*, float*, const float*, long long, double*, const SolveScalars*, hipStream_t);
-
-template <class T> int launch_fupdate(T* x, const T* p, T* r, const T* q, long long n, double* partials,
-                                      const SolveScalars* sc, hipStream_t s) {
-  const int nb = vec_blocks(n);
-  k_fupdate<T><<<nb, kBlock, 0, s>>>(n, x, p, r, q, partials, sc);
-  return nb;
-}
-template int launch_fupdate<double>(double*, const double*, double*, const double*, long long, double*, const SolveScalars*, hipStream_t);
-template int launch_fupdate<float>(float*, const float*, float*, const float*, long long, double*, const SolveScalars*, hipStream_t);
-
 template <class T> void launch_scale(const T* r, const T* dinv, T* z, long long n, const SolveScalars* sc,
                                      hipStream_t s) {
   k_scale<T><<<vec_blocks(n), kBlock, 0, s>>>(n, r, dinv, z, sc);
@@ -440,12 +231,6 @@ template void launch_fill<float>(float*, float, long long, hipStream_t);
 
 void launch_init_x(double* x, const unsigned char* act, long long n, int warm, hipStream_t s) {
   k_init_x<<<vec_blocks(n), kBlock, 0, s>>>(n, x, act, warm);
-}
-void launch_cast_scaled(const double* r, float* r32, long long n, const SolveScalars* sc, hipStream_t s) {
-  k_cast_scaled<<<vec_blocks(n), kBlock, 0, s>>>(n, r, r32, sc);
-}
-void launch_refine_update(double* x, const float* d, long long n, const SolveScalars* sc, hipStream_t s) {
-  k_refine_update<<<vec_blocks(n), kBlock, 0, s>>>(n, x, d, sc);
 }
 void launch_set_scalars(SolveScalars* sc, double t, int tol_mode, int max_iter, int reset_iter,
                         int window, double ratio, hipStream_t s) {

@@ -57,7 +57,7 @@ class AssembleParams(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", c_double), ("max_iters", c_int), ("precond", c_int), ("precision", c_int),
-                ("inner_tol", c_double), ("max_outer", c_int), ("fcg_m", c_int),
+                ("replace_drop", c_double), ("fcg_m", c_int),
                 ("fallback_ratio", c_double), ("fallback_window", c_int), ("warm_start", c_int),
                 ("check_every", c_int), ("unet", c_void_p), ("history", ctypes.POINTER(c_double)),
                 ("history_cap", c_int)]
@@ -242,7 +242,7 @@ class Poisson:
         return div
 
     def solve(self, b, x=None, tol=1e-8, precision="f64", precond="jacobi", max_iters=200000,
-              inner_tol=1e-6, max_outer=8, warm_start=False, check_every=16, unet=None,
+              replace_drop=0.1, warm_start=False, check_every=16, unet=None,
               fallback_ratio=0.99, fallback_window=10, history=0):
         o = SolveOpts()
         lib.nfa_solve_opts_default(ctypes.byref(o))
@@ -251,8 +251,7 @@ class Poisson:
         o.precision = {"f64": NFA_PREC_F64, "mixed": NFA_PREC_MIXED}[precision]
         o.precond = {"jacobi": NFA_PC_JACOBI, "unet": NFA_PC_UNET, "jacobi_fcg": NFA_PC_JACOBI_FCG,
                      "sabotage": NFA_PC_TEST_SABOTAGE}[precond]
-        o.inner_tol = inner_tol
-        o.max_outer = max_outer
+        o.replace_drop = replace_drop
         o.warm_start = 1 if warm_start else 0
         o.check_every = check_every
         o.fallback_ratio = fallback_ratio

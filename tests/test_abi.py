@@ -69,8 +69,8 @@ def test_grid_create_rejects_bad_arguments_before_touching_the_device(lib):
 def test_solve_rejects_null_handle_and_defaults_are_sane(lib):
     class Opts(ctypes.Structure):
         _fields_ = [("tol", ctypes.c_double), ("max_iters", ctypes.c_int), ("precond", ctypes.c_int),
-                    ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                    ("max_outer", ctypes.c_int), ("fcg_m", ctypes.c_int),
+                    ("precision", ctypes.c_int), ("replace_drop", ctypes.c_double),
+                    ("fcg_m", ctypes.c_int),
                     ("fallback_ratio", ctypes.c_double), ("fallback_window", ctypes.c_int),
                     ("warm_start", ctypes.c_int), ("check_every", ctypes.c_int),
                     ("unet", ctypes.c_void_p), ("history", ctypes.c_void_p),
@@ -78,7 +78,7 @@ def test_solve_rejects_null_handle_and_defaults_are_sane(lib):
     o = Opts()
     lib.nfa_solve_opts_default(ctypes.byref(o))
     assert o.tol == 1e-8 and o.precond == 1 and o.fallback_ratio == 0.99 and o.fallback_window == 10
-    assert o.fcg_m == 1 and 0 < o.inner_tol < 1e-3
+    assert o.fcg_m == 1 and o.replace_drop == 0.1
     lib.nfa_poisson_solve.restype = ctypes.c_int
     assert lib.nfa_poisson_solve(None, None, None, ctypes.byref(o), None, None) == -1
 
