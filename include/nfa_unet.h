@@ -1,0 +1,87 @@
+/*
+ * libnfa -- learned preconditioner for flexible CG (a small 3-D U-Net).
+ *
+ * Not a method of the paper: the paper's projection uses a preconditioned
+ * conjugate-gradient solver with an unnamed preconditioner (Introduction);
+ * this network is an optional preconditioner of the flexible-CG variant of
+ * that solve (NFA_PC_UNET), judged by the same FP64 true residual and backed
+ * by Jacobi-PCG.
+ *
+ * Network (channels-last BF16 activations, FP32 accumulation, 3x3x3
+ * cross-correlations with zero padding, 2x2x2 average pooling, nearest x2
+ * upsampling, additive skips):
+ *   x0 = [r/s, (log(1/rho) - L0)/L1]     s = RMS of r over the unknowns
+ *   a0 = relu(conv0(x0))            2 -> 16   full resolution
+ *   a1 = relu(conv1(pool(a0)))     16 -> 32   1/2
+ *   a2 = relu(conv2(pool(a1)))     32 -> 64   1/4
+ *   b2 = relu(conv3(a2))           64 -> 32   1/4
+ *   d1 = relu(conv4(up(b2) + a1))  32 -> 16   1/2
+ *   z  = D^-1 (r/s + conv5(up(d1) + a0))      16 -> 1, full resolution
+ * with D^-1 the Jacobi inverse diagonal of the assembled operator, so the
+ * network with conv5 = 0 is the Jacobi step.  Grid sizes must be multiples
+ * of 4 in every direction.
+ *
+ * Parameters: for conv0..conv5 in order, weights [27][cin][cout] (tap
+ * t = 9(dz+1) + 3(dy+1) + (dx+1)) then bias [cout]; FP32 master copies,
+ * BF16 used in the convolutions.
+ *
+ * Training loss for a (residual r, scalar e.A'e with e = A'^-1 r) pair: the
+ * share of the A-norm error left by one optimal step along z,
+ *   L = 1 - (z.r)^2 / ((z.A'z)(e.A'e)).
+ */
+#ifndef NFA_UNET_H
+#define NFA_UNET_H
+
+#include "nfa.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nfa_unet_s* nfa_unet;
+
+/* Network and activation workspace for an nx x ny x nz grid (multiples of 4),
+ * weights He-initialised from `seed`, conv5 zero.  Allocates device memory. */
+nfa_status nfa_unet_create(int nx, int ny, int nz, int seed, nfa_unet* out);
+/* Number of FP32 parameters (weights and biases of the six convolutions). */
+long long nfa_unet_param_count(void);
+/* HOST buffers of nfa_unet_param_count() floats.  Synchronous. */
+nfa_status nfa_unet_get_params(nfa_unet u, float* host);
+nfa_status nfa_unet_set_params(nfa_unet u, const float* host);
+/* Gradients of the last nfa_unet_grad / nfa_unet_train_step.  Synchronous. */
+nfa_status nfa_unet_get_grads(nfa_unet u, float* host);
+
+/* z = network(r) on the operator's grid (same shape as the network).
+ *   op : assembled operator (supplies rho and the Jacobi inverse diagonal).
+ *   r  : DEVICE float cells (a residual: zero on slaves and inactive cells).
+ *   z  : DEVICE float cells (output; zero on slaves and inactive cells).
+ * ASYNC. */
+nfa_status nfa_unet_forward(nfa_unet u, nfa_poisson op, const float* r, float* z, nfa_stream s);
+
+/* Forward, loss and backward for one pair; gradients replace the previous
+ * ones.  eAe = e.A'e > 0.  loss: HOST out.  Synchronous. */
+nfa_status nfa_unet_grad(nfa_unet u, nfa_poisson op, const float* r, double eAe, double* loss,
+                         nfa_stream s);
+
+/* nfa_unet_grad followed by one Adam step (beta1 0.9, beta2 0.999, eps 1e-8)
+ * with learning rate lr at step count t >= 1.  Synchronous. */
+nfa_status nfa_unet_train_step(nfa_unet u, nfa_poisson op, const float* r, double eAe, float lr,
+                               int t, double* loss, nfa_stream s);
+
+/* Activations of the last forward (DEVICE destination): BF16 raw uint16,
+ * channels-last, sizes per level (n0 = cells, n1 = n0/8, n2 = n0/64). */
+#define NFA_UNET_X0 0 /* n0 x 2 */
+#define NFA_UNET_A0 1 /* n0 x 16 */
+#define NFA_UNET_P0 2 /* n1 x 16 */
+#define NFA_UNET_A1 3 /* n1 x 32 */
+#define NFA_UNET_P1 4 /* n2 x 32 */
+#define NFA_UNET_A2 5 /* n2 x 64 */
+#define NFA_UNET_B2 6 /* n2 x 32 */
+#define NFA_UNET_D1 7 /* n1 x 16 */
+nfa_status nfa_unet_export(nfa_unet u, int what, void* dst, nfa_stream s); /* ASYNC */
+void nfa_unet_destroy(nfa_unet u);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NFA_UNET_H */

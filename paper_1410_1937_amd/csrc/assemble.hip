@@ -358,6 +358,7 @@ extern "C" nfa_status nfa_poisson_assemble(nfa_poisson op, const void* phi,
         op->dinv64.as<double>(), op->dinv32.as<float>());
   NFA_CHECK_LAUNCH();
   op->assembled = true;
+  op->version += 1;
   return NFA_OK;
 }
 

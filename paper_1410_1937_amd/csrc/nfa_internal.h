@@ -111,6 +111,7 @@ template <class T> struct Coeffs {
 struct Poisson {
   Grid* g = nullptr;
   bool assembled = false;
+  int version = 0;                              // incremented by every assembly
   DevBuf rho, rho_tmp;                          // double cells
   DevBuf tx64, txb64, ty64, tz64, dinv64;       // FP64 coefficients
   DevBuf tx32, txb32, ty32, tz32, dinv32;       // FP32 coefficients

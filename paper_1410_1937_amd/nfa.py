@@ -102,6 +102,17 @@ _sig("nfa_poisson_solve", c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(S
 _sig("nfa_poisson_export", c_int, [c_void_p, c_int, c_void_p, c_void_p])
 _sig("nfa_poisson_destroy", None, [c_void_p])
 _sig("nfa_poisson_profile", c_int, [c_void_p, c_int])
+_sig("nfa_unet_create", c_int, [c_int, c_int, c_int, c_int, ctypes.POINTER(c_void_p)])
+_sig("nfa_unet_param_count", c_ll, [])
+_sig("nfa_unet_get_params", c_int, [c_void_p, c_void_p])
+_sig("nfa_unet_set_params", c_int, [c_void_p, c_void_p])
+_sig("nfa_unet_get_grads", c_int, [c_void_p, c_void_p])
+_sig("nfa_unet_forward", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p])
+_sig("nfa_unet_grad", c_int, [c_void_p, c_void_p, c_void_p, c_double, ctypes.POINTER(c_double), c_void_p])
+_sig("nfa_unet_train_step", c_int, [c_void_p, c_void_p, c_void_p, c_double, ctypes.c_float, c_int,
+                                    ctypes.POINTER(c_double), c_void_p])
+_sig("nfa_unet_export", c_int, [c_void_p, c_int, c_void_p, c_void_p])
+_sig("nfa_unet_destroy", None, [c_void_p])
 _sig("nfa_poisson_profile_read", c_int, [c_void_p, c_int, ctypes.POINTER(KernelStats)])
 
 
@@ -293,6 +304,88 @@ class Poisson:
         return out
 
     def __del__(self, _destroy=lib.nfa_poisson_destroy):
+        if getattr(self, "h", None):
+            _destroy(self.h)
+            self.h = None
+
+
+UNET_SHAPES = [(2, 16), (16, 32), (32, 64), (64, 32), (32, 16), (16, 1)]
+UNET_EXPORT = {"x0": (0, 0, 2), "a0": (1, 0, 16), "p0": (2, 1, 16), "a1": (3, 1, 32), "p1": (4, 2, 32),
+               "a2": (5, 2, 64), "b2": (6, 2, 32), "d1": (7, 1, 16)}
+
+
+class UNet:
+    """The learned preconditioner (see include/nfa_unet.h)."""
+
+    def __init__(self, nx, ny, nz, seed=0):
+        h = c_void_p()
+        _check(lib.nfa_unet_create(nx, ny, nz, seed, ctypes.byref(h)), "nfa_unet_create")
+        self.h = h
+        self.shape = (nz, ny, nx)
+
+    @staticmethod
+    def param_count():
+        return int(lib.nfa_unet_param_count())
+
+    def _flat(self, fn, what):
+        a = np.empty(self.param_count(), dtype=np.float32)
+        _check(fn(self.h, a.ctypes.data), what)
+        return a
+
+    def get_params(self):
+        return self._flat(lib.nfa_unet_get_params, "nfa_unet_get_params")
+
+    def get_grads(self):
+        return self._flat(lib.nfa_unet_get_grads, "nfa_unet_get_grads")
+
+    def set_params(self, flat):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        if a.size != self.param_count():
+            raise ValueError("wrong parameter count")
+        _check(lib.nfa_unet_set_params(self.h, a.ctypes.data), "nfa_unet_set_params")
+
+    @staticmethod
+    def unflatten(flat):
+        out, o = [], 0
+        for ci, co in UNET_SHAPES:
+            w = flat[o:o + 27 * ci * co].reshape(27, ci, co)
+            o += 27 * ci * co
+            b = flat[o:o + co]
+            o += co
+            out.append((w, b))
+        return out
+
+    @staticmethod
+    def flatten(params):
+        return np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in params]).astype(np.float32)
+
+    def forward(self, op, r, out=None):
+        z = torch.empty_like(r) if out is None else out
+        _check(lib.nfa_unet_forward(self.h, op.h, _dev(r, torch.float32, self.shape, "r"),
+                                    _dev(z, torch.float32, self.shape, "z"), _stream()), "nfa_unet_forward")
+        return z
+
+    def grad(self, op, r, eAe):
+        loss = c_double()
+        _check(lib.nfa_unet_grad(self.h, op.h, _dev(r, torch.float32, self.shape, "r"), float(eAe),
+                                 ctypes.byref(loss), _stream()), "nfa_unet_grad")
+        return loss.value
+
+    def train_step(self, op, r, eAe, lr, t):
+        loss = c_double()
+        _check(lib.nfa_unet_train_step(self.h, op.h, _dev(r, torch.float32, self.shape, "r"), float(eAe),
+                                       float(lr), int(t), ctypes.byref(loss), _stream()), "nfa_unet_train_step")
+        return loss.value
+
+    def export(self, what):
+        code, level, ch = UNET_EXPORT[what]
+        nz, ny, nx = self.shape
+        f = 2 ** level
+        out = torch.empty((nz // f, ny // f, nx // f, ch), dtype=torch.bfloat16, device="cuda")
+        _check(lib.nfa_unet_export(self.h, code, c_void_p(out.data_ptr()), _stream()), "nfa_unet_export")
+        return out
+
+    def __del__(self, _destroy=lib.nfa_unet_destroy):
         if getattr(self, "h", None):
             _destroy(self.h)
             self.h = None

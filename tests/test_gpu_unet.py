@@ -1,0 +1,133 @@
+"""The learned preconditioner on the GPU against the FP64 oracle (needs an
+MI355X).  Layers are checked one at a time, each fed with the GPU's own
+BF16 input, to within one BF16 rounding step of the oracle (FP32 against
+FP64 accumulation can move a value across a rounding boundary); the whole
+forward pass, the loss, the parameter gradients and the Adam update within
+the tolerances stated below."""
+import numpy as np
+import pytest
+
+from oracle import solvers, unet as ou
+from paper_1410_1937_amd import fixtures as fx
+from tests.gpu_helpers import gpu_for, host, oracle_for
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _bf(t):
+    return t.float().cpu().numpy().astype(np.float64)
+
+
+def _ulp_ok(gpu, ref, frac=1e-3):
+    """|gpu - ref| within one BF16 step of |ref| (2^-7 relative) everywhere but
+    a small fraction of entries, which may differ by two steps."""
+    tol = np.maximum(np.abs(ref), 1e-30) * 2.0 ** -7 * 1.0001
+    bad = np.abs(gpu - ref) > tol
+    assert np.mean(bad) <= frac, np.mean(bad)
+    assert np.all(np.abs(gpu - ref)[bad] <= 2 * tol[bad] + 1e-6 * np.max(np.abs(ref)))
+
+
+@pytest.fixture(scope="module")
+def setup():
+    from paper_1410_1937_amd import nfa
+    wl = fx.small(7, 32, 16, 12, body="sphere")
+    og, ob, oop, ob_rhs = oracle_for(wl)
+    gg, gop = gpu_for(wl)
+    net = nfa.UNet(32, 16, 12, seed=3)
+    rng = np.random.default_rng(5)
+    params = ou.init_params(9, zero_last=False)
+    params = [(w.astype(np.float32), (rng.standard_normal(b.shape) * 0.05).astype(np.float32)) for w, b in params]
+    net.set_params(nfa.UNet.flatten(params))
+    r = (ob_rhs * ob.reduced).astype(np.float32)
+    rt = torch.as_tensor(r, device="cuda")
+    z = host(net.forward(gop, rt)).astype(np.float64)
+    return wl, (og, ob, oop, ob_rhs), (gg, gop), net, [(w.astype(np.float64), b.astype(np.float64)) for w, b in params], r, rt, z
+
+
+def test_forward_layers_within_one_bf16_step(setup):
+    wl, (og, ob, oop, _), (gg, gop), net, params, r, rt, z = setup
+    P = [(ou.bf16(w), b) for w, b in params]
+    x0 = _bf(net.export("x0"))
+    x0_ref, s = ou.features(r.astype(np.float64), 1.0 / oop.rho, ob.reduced)
+    _ulp_ok(x0, ou.bf16(x0_ref))
+    a0 = _bf(net.export("a0"))
+    _ulp_ok(a0, ou.bf16(ou.relu(ou.conv3d(x0, *P[0]))))
+    p0 = _bf(net.export("p0"))
+    _ulp_ok(p0, ou.bf16(ou.pool(a0)))
+    a1 = _bf(net.export("a1"))
+    _ulp_ok(a1, ou.bf16(ou.relu(ou.conv3d(p0, *P[1]))))
+    p1 = _bf(net.export("p1"))
+    _ulp_ok(p1, ou.bf16(ou.pool(a1)))
+    a2 = _bf(net.export("a2"))
+    _ulp_ok(a2, ou.bf16(ou.relu(ou.conv3d(p1, *P[2]))))
+    b2 = _bf(net.export("b2"))
+    _ulp_ok(b2, ou.bf16(ou.relu(ou.conv3d(a2, *P[3]))))
+    d1 = _bf(net.export("d1"))
+    _ulp_ok(d1, ou.bf16(ou.relu(ou.conv3d(ou.bf16(ou.up(b2) + a1), *P[4]))))
+    s0 = ou.bf16(ou.up(d1) + a0)
+    y = x0[..., 0] + ou.conv3d(s0, *P[5])[..., 0]
+    zref = oop.dinv * y
+    assert np.max(np.abs(z - zref)) <= 1e-5 * np.max(np.abs(zref))
+
+
+def test_whole_forward_matches_oracle(setup):
+    wl, (og, ob, oop, _), (gg, gop), net, params, r, rt, z = setup
+    x0, s = ou.features(r.astype(np.float64), 1.0 / oop.rho, ob.reduced)
+    y, _ = ou.forward(params, x0, quant=True)
+    zref = oop.dinv * y
+    err = np.linalg.norm(z - zref) / np.linalg.norm(zref)
+    print(f"forward rel L2 vs oracle: {err:.2e}")
+    assert err <= 2e-2
+
+
+def test_untrained_network_is_jacobi_on_the_bf16_residual():
+    from paper_1410_1937_amd import nfa
+    wl = fx.small(8, 16, 16, 8, body="sphere")
+    og, ob, oop, ob_rhs = oracle_for(wl)
+    gg, gop = gpu_for(wl)
+    net = nfa.UNet(16, 16, 8, seed=0)
+    r = (ob_rhs * ob.reduced).astype(np.float32)
+    z = host(net.forward(gop, torch.as_tensor(r, device="cuda")))
+    x0 = _bf(net.export("x0"))
+    assert np.array_equal(z, (gop.export("dinv32").cpu().numpy() * x0[..., 0].astype(np.float32)))
+
+
+def test_gradients_loss_and_adam_match_oracle(setup):
+    from paper_1410_1937_amd import nfa
+    wl, (og, ob, oop, ob_rhs), (gg, gop), net, params, r, rt, z = setup
+    e = solvers.pcg(oop, r.astype(np.float64), tol=1e-12).x
+    eAe = float(np.sum(e * r))
+    loss = net.grad(gop, rt, eAe)
+    x0, s = ou.features(r.astype(np.float64), 1.0 / oop.rho, ob.reduced)
+    y, cache = ou.forward(params, x0, quant=True)
+    zz = oop.dinv * y
+    Lref, dz = ou.step_loss(zz, r.astype(np.float64), oop.apply(zz), eAe)
+    print(f"loss gpu {loss:.6f} oracle {Lref:.6f}")
+    assert abs(loss - Lref) <= 2e-2 * max(abs(Lref), 1e-3)
+    grads = ou.backward(cache, oop.dinv * dz, quant=True)
+    g = nfa.UNet.unflatten(net.get_grads())
+    for layer, ((gw, gb), (rw, rb)) in enumerate(zip(g, grads)):
+        ew = np.linalg.norm(gw - rw) / max(np.linalg.norm(rw), 1e-30)
+        eb = np.linalg.norm(gb - rb) / max(np.linalg.norm(rb), 1e-30)
+        print(f"layer {layer}: weight grad rel err {ew:.2e}, bias {eb:.2e}")
+        assert ew <= 5e-2 and eb <= 5e-2
+    # one Adam step on these gradients
+    p_before = net.get_params().astype(np.float64)
+    g_flat = net.get_grads().astype(np.float64)
+    net.train_step(gop, rt, eAe, 1e-3, 1)
+    g_flat = net.get_grads().astype(np.float64)     # same inputs -> same gradients
+    expect, _, _ = ou.adam(p_before, g_flat, np.zeros_like(p_before), np.zeros_like(p_before), 1, lr=1e-3)
+    assert np.max(np.abs(net.get_params() - expect)) <= 1e-6
+
+
+def test_flexible_cg_with_the_network_meets_the_judge():
+    from paper_1410_1937_amd import nfa
+    wl = fx.small(9, 32, 24, 16, body="sphere")
+    og, ob, oop, ob_rhs = oracle_for(wl)
+    gg, gop = gpu_for(wl)
+    net = nfa.UNet(32, 24, 16, seed=1)
+    b = torch.as_tensor(ob_rhs, device="cuda")
+    x, res = gop.solve(b, tol=1e-8, precision="mixed", precond="unet", unet=net, fallback_ratio=2.0)
+    assert res.status == 0 and res.relres <= 1e-8
+    assert solvers.true_relres(oop, ob_rhs, host(x)) <= 1.01e-8
