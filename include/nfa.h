@@ -244,6 +244,14 @@ nfa_status nfa_poisson_profile(nfa_poisson op, int enable);
 /* dtype NFA_F64 or NFA_F32: the sweep of that precision.  Synchronous. */
 nfa_status nfa_poisson_profile_read(nfa_poisson op, int dtype, nfa_kernel_stats* out);
 
+/* nfa_poisson_residual -- r = b' - A'x in FP64 (the true residual the
+ * solver's judge uses); x is read as P x (slaves take their root's value).
+ *   b, x, r : DEVICE double cells; r may not alias x.
+ *   rr      : HOST out, ||r||^2 over the unknowns (NULL: not computed).
+ * Synchronous when rr is given, else ASYNC. */
+nfa_status nfa_poisson_residual(nfa_poisson op, const double* b, const double* x, double* r, double* rr,
+                                nfa_stream s);
+
 /* what to export from an operator (DEVICE destination, natural layout) */
 #define NFA_EXPORT_RHO 20    /* double cells */
 #define NFA_EXPORT_TX 21     /* double x-faces */

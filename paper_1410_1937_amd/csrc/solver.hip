@@ -373,3 +373,26 @@ extern "C" nfa_status nfa_poisson_profile_read(nfa_poisson op, int dtype, nfa_ke
   out->cells = op->g->n;
   return NFA_OK;
 }
+
+extern "C" nfa_status nfa_poisson_residual(nfa_poisson op, const double* b, const double* x, double* r,
+                                           double* rr, nfa_stream s) {
+  if (!op || !b || !x || !r) return fail(NFA_ERR_INVALID, "nfa_poisson_residual: NULL argument");
+  if (!op->assembled) return fail(NFA_ERR_INVALID, "nfa_poisson_residual: operator not assembled");
+  if (x == r) return fail(NFA_ERR_INVALID, "nfa_poisson_residual: r must not alias x");
+  Grid& g = *op->g;
+  const hipStream_t st = S(s);
+  const double* src = x;
+  if (g.n_slaves > 0) {
+    launch_copy<double>(x, op->tmp.as<double>(), g.n, st);
+    launch_merge_copy<double>(g, op->tmp.as<double>(), st, nullptr);
+    src = op->tmp.as<double>();
+  }
+  nfa_status e = residual64(*op, b, src, r, rr ? PH_RR : -1, st);
+  if (e != NFA_OK) return e;
+  if (rr) {
+    SolveScalars now{};
+    if ((e = read_scalars(*op, st, &now)) != NFA_OK) return e;
+    *rr = now.rr;
+  }
+  return NFA_OK;
+}

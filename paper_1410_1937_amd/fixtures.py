@@ -321,6 +321,42 @@ def c4_step(n: int, nx=256, ny=128, nz=96) -> Workload:
     return wl
 
 
+class C4Sequence:
+    """The 200-step advected free surface on the c2 geometry: the grid, the
+    hull and the surface modes are built once; step n moves the surface by
+    t_n = 0.005 n (unit speed) and draws the face velocity with seed 1000 + n."""
+
+    def __init__(self, nx=256, ny=128, nz=96, seed=0):
+        self.xf, self.yf, self.zf = _grid(nx, ny, nz, [-0.25, 0.25], [0.0], [0.0])
+        self.modes = surface_modes(seed)
+        self.psi = psi_ellipsoid(self.xf, self.yf, self.zf)
+        self.xc, self.yc = centres(self.xf), centres(self.yf)
+        self.bc = ALL_NEUMANN
+        self.theta = 0.1
+        self.shape = (nz, ny, nx)
+
+    def step(self, n: int):
+        e = eta(self.xc, self.yc, self.modes, shift=0.005 * n)
+        phi = vof_from_surface(self.xf, self.yf, self.zf, e)
+        return phi, face_velocity(self.xf, self.yf, self.zf, 1000 + n)
+
+    def smooth_field(self, seed: int, modes: int = 6):
+        """A smooth random cell field (low Fourier modes) used as a synthetic error."""
+        rng = np.random.default_rng(seed)
+        xs = (self.xc - self.xf[0]) / (self.xf[-1] - self.xf[0])
+        ys = (self.yc - self.yf[0]) / (self.yf[-1] - self.yf[0])
+        zc = centres(self.zf)
+        zs = (zc - self.zf[0]) / (self.zf[-1] - self.zf[0])
+        out = np.zeros(self.shape)
+        for _ in range(modes):
+            k = rng.integers(1, 7, size=3)
+            ph = rng.uniform(0, 2 * math.pi, size=3)
+            out += rng.standard_normal() * (np.cos(math.pi * k[2] * zs + ph[2])[:, None, None]
+                                            * np.cos(math.pi * k[1] * ys + ph[1])[None, :, None]
+                                            * np.cos(math.pi * k[0] * xs + ph[0])[None, None, :])
+        return out
+
+
 def c5_step(n: int, nx=768, ny=384, nz=256, seed: int = 1) -> Workload:
     """Projection n of the heaving-sphere sequence, body-fixed frame: the body
     is static; surface and droplets move by -z_h(t) in z and +t in x."""

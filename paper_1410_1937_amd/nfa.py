@@ -102,6 +102,7 @@ _sig("nfa_poisson_solve", c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(S
 _sig("nfa_poisson_export", c_int, [c_void_p, c_int, c_void_p, c_void_p])
 _sig("nfa_poisson_destroy", None, [c_void_p])
 _sig("nfa_poisson_profile", c_int, [c_void_p, c_int])
+_sig("nfa_poisson_residual", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double), c_void_p])
 _sig("nfa_unet_create", c_int, [c_int, c_int, c_int, c_int, ctypes.POINTER(c_void_p)])
 _sig("nfa_unet_param_count", c_ll, [])
 _sig("nfa_unet_get_params", c_int, [c_void_p, c_void_p])
@@ -282,6 +283,16 @@ class Poisson:
         res = SolveResult(st, info.iterations, info.outer, bool(info.fallback), info.relres, info.ms,
                           None if hist is None else hist[:info.history_len].copy())
         return x, res
+
+    def residual(self, b, x, out=None):
+        """(r = b' - A'x in FP64, ||r||^2)."""
+        r = torch.empty_like(b) if out is None else out
+        rr = c_double()
+        _check(lib.nfa_poisson_residual(self.h, _dev(b, torch.float64, self.shape, "b"),
+                                        _dev(x, torch.float64, self.shape, "x"),
+                                        _dev(r, torch.float64, self.shape, "r"), ctypes.byref(rr), _stream()),
+               "nfa_poisson_residual")
+        return r, rr.value
 
     def profile(self, enable=True):
         _check(lib.nfa_poisson_profile(self.h, 1 if enable else 0), "nfa_poisson_profile")
