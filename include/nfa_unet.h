@@ -21,9 +21,9 @@
  * network with conv5 = 0 is the Jacobi step.  Grid sizes must be multiples
  * of 4 in every direction.
  *
- * Parameters: for conv0..conv5 in order, weights [27][cin][cout] (tap
- * t = 9(dz+1) + 3(dy+1) + (dx+1)) then bias [cout]; FP32 master copies,
- * BF16 used in the convolutions.
+ * Parameters: weights [27][cin][cout] (tap t = 9(dz+1) + 3(dy+1) + (dx+1))
+ * then bias [cout] per convolution; FP32 master copies, BF16 used in the
+ * convolutions.
  *
  * Training loss for a (residual r, scalar e.A'e with e = A'^-1 r) pair: the
  * share of the A-norm error left by one optimal step along z,
@@ -40,11 +40,17 @@ extern "C" {
 
 typedef struct nfa_unet_s* nfa_unet;
 
-/* Network and activation workspace for an nx x ny x nz grid (multiples of 4),
- * weights He-initialised from `seed`, conv5 zero.  Allocates device memory. */
-nfa_status nfa_unet_create(int nx, int ny, int nz, int seed, nfa_unet* out);
-/* Number of FP32 parameters (weights and biases of the six convolutions). */
-long long nfa_unet_param_count(void);
+/* Network with `levels` resolution levels (3 = the network above; each
+ * further level adds a 64-channel level with the same encoder / decoder
+ * pattern; 3..6) and its activation workspace for an nx x ny x nz grid
+ * (multiples of 2^(levels-1)); weights He-initialised from `seed`, head
+ * zero.  Allocates device memory.  Errors: NFA_ERR_INVALID, NFA_ERR_HIP. */
+nfa_status nfa_unet_create(int nx, int ny, int nz, int levels, int seed, nfa_unet* out);
+/* Number of FP32 parameters of a network with `levels` levels (-1 if out of
+ * range).  Parameter order: encoder e_0..e_{L-1}, bottleneck, decoder
+ * d_{L-2}..d_1, head; each weights [27][cin][cout] then bias [cout]. */
+long long nfa_unet_param_count(int levels);
+int nfa_unet_levels(nfa_unet u);
 /* HOST buffers of nfa_unet_param_count() floats.  Synchronous. */
 nfa_status nfa_unet_get_params(nfa_unet u, float* host);
 nfa_status nfa_unet_set_params(nfa_unet u, const float* host);
@@ -69,15 +75,12 @@ nfa_status nfa_unet_train_step(nfa_unet u, nfa_poisson op, const float* r, doubl
                                int t, double* loss, nfa_stream s);
 
 /* Activations of the last forward (DEVICE destination): BF16 raw uint16,
- * channels-last, sizes per level (n0 = cells, n1 = n0/8, n2 = n0/64). */
-#define NFA_UNET_X0 0 /* n0 x 2 */
-#define NFA_UNET_A0 1 /* n0 x 16 */
-#define NFA_UNET_P0 2 /* n1 x 16 */
-#define NFA_UNET_A1 3 /* n1 x 32 */
-#define NFA_UNET_P1 4 /* n2 x 32 */
-#define NFA_UNET_A2 5 /* n2 x 64 */
-#define NFA_UNET_B2 6 /* n2 x 32 */
-#define NFA_UNET_D1 7 /* n1 x 16 */
+ * channels-last; level l has n_l = cells / 8^l positions and c_l = 16, 32,
+ * 64, 64, ... channels. */
+#define NFA_UNET_X0 0  /* n_0 x 2 */
+#define NFA_UNET_A 16  /* + l: encoder a_l, n_l x c_l */
+#define NFA_UNET_P 32  /* + l: pool(a_l), n_{l+1} x c_l */
+#define NFA_UNET_D 48  /* + l (l >= 1): decoder d_l (d_{L-1}: bottleneck), n_l x c_{l-1} */
 nfa_status nfa_unet_export(nfa_unet u, int what, void* dst, nfa_stream s); /* ASYNC */
 void nfa_unet_destroy(nfa_unet u);
 

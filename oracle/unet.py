@@ -3,7 +3,8 @@
 The network is a small 3-D U-Net (3 levels, 16/32/64 channels, 3x3x3
 convolutions, 2x2x2 average pooling, nearest-neighbour upsampling, additive
 skip connections) that maps the scaled residual and the log of the inverse
-density to a correction of the Jacobi step:
+density to a correction of the Jacobi step (deeper variants add levels of
+64 channels with the same pattern, see `shapes`):
 
     x0 = [r / s, l]                 s = RMS of r over the unknowns,
                                     l = (log(1/rho) - L0) / L1
@@ -35,10 +36,27 @@ from __future__ import annotations
 
 import numpy as np
 
-CH = (16, 32, 64)
-SHAPES = [(2, 16), (16, 32), (32, 64), (64, 32), (32, 16), (16, 1)]   # conv0..conv5 (Cin, Cout)
-TAPS = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
 L0, L1 = -3.5, 3.4            # log(1/rho) normalisation: [-6.9, -0.18] -> about [-1, 1]
+TAPS = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+
+
+def channels(levels):
+    """Channels per level: 16, 32, 64, then 64 for deeper levels."""
+    return [16, 32, 64][:levels] + [64] * max(0, levels - 3)
+
+
+def shapes(levels=3):
+    """(Cin, Cout) of the convolutions in parameter order: encoder e0..e_{L-1},
+    bottleneck b, decoder d_{L-2}..d_1, head."""
+    c = channels(levels)
+    out = [(2, c[0])] + [(c[l - 1], c[l]) for l in range(1, levels)]
+    out.append((c[levels - 1], c[levels - 2]))
+    out += [(c[l], c[l - 1]) for l in range(levels - 2, 0, -1)]
+    out.append((c[0], 1))
+    return out
+
+
+SHAPES = shapes(3)
 
 
 def bf16(x):
@@ -111,15 +129,16 @@ def relu(x):
 
 
 # --------------------------------------------------------------- network
-def init_params(seed=0, zero_last=True):
-    """He-normal weights (FP32 master copies), zero biases; conv5 zero so that
-    the untrained preconditioner is Jacobi."""
+def init_params(seed=0, zero_last=True, levels=3):
+    """He-normal weights (FP32 master copies), zero biases; the head zero so
+    that the untrained preconditioner is Jacobi."""
     rng = np.random.default_rng(seed)
     params = []
-    for i, (ci, co) in enumerate(SHAPES):
+    sh = shapes(levels)
+    for i, (ci, co) in enumerate(sh):
         std = np.sqrt(2.0 / (27 * ci))
         w = rng.standard_normal((27, ci, co)) * std
-        if zero_last and i == len(SHAPES) - 1:
+        if zero_last and i == len(sh) - 1:
             w[:] = 0.0
         params.append((w.astype(np.float32).astype(np.float64), np.zeros(co)))
     return params
@@ -133,48 +152,55 @@ def features(r, inv_rho, mask):
     return np.stack([r / s, l], axis=-1), s
 
 
+def _levels(params):
+    return len(params) // 2
+
+
 def forward(params, x0, quant=True):
-    """Returns (y, cache); y = x0[..., 0] + conv5(...) on (D, H, W)."""
+    """Returns (y, cache); y = x0[..., 0] + head(up(d1) + a0) on (D, H, W)."""
+    L = _levels(params)
     P = [(_q(w, quant), _q(b, False)) for w, b in params]
+    E, B, Dd, Hd = P[:L], P[L], P[L + 1:2 * L - 1], P[2 * L - 1]
     x0 = _q(x0, quant)
-    a0 = _q(relu(conv3d(x0, *P[0])), quant)
-    p0 = _q(pool(a0), quant)
-    a1 = _q(relu(conv3d(p0, *P[1])), quant)
-    p1 = _q(pool(a1), quant)
-    a2 = _q(relu(conv3d(p1, *P[2])), quant)
-    b2 = _q(relu(conv3d(a2, *P[3])), quant)
-    s1 = _q(up(b2) + a1, quant)
-    d1 = _q(relu(conv3d(s1, *P[4])), quant)
-    s0 = _q(up(d1) + a0, quant)
-    u = conv3d(s0, *P[5])[..., 0]
+    a = [_q(relu(conv3d(x0, *E[0])), quant)]
+    p = []
+    for l in range(1, L):
+        p.append(_q(pool(a[l - 1]), quant))
+        a.append(_q(relu(conv3d(p[l - 1], *E[l])), quant))
+    d = {L - 1: _q(relu(conv3d(a[L - 1], *B)), quant)}
+    s = {}
+    for i, l in enumerate(range(L - 2, 0, -1)):
+        s[l] = _q(up(d[l + 1]) + a[l], quant)
+        d[l] = _q(relu(conv3d(s[l], *Dd[i])), quant)
+    s[0] = _q(up(d[1]) + a[0], quant)
+    u = conv3d(s[0], *Hd)[..., 0]
     y = x0[..., 0] + u
-    cache = dict(P=P, x0=x0, a0=a0, p0=p0, a1=a1, p1=p1, a2=a2, b2=b2, s1=s1, d1=d1, s0=s0)
-    return y, cache
+    return y, dict(P=P, L=L, x0=x0, a=a, p=p, d=d, s=s)
 
 
 def backward(cache, dy, quant=True):
-    """Gradients (dw, db) of every conv for an upstream dL/dy on (D, H, W).
-    Stored gradient tensors are BF16 when quant (as on the GPU)."""
-    P = cache["P"]
-    g = []
+    """Gradients (dw, db) of every conv, in parameter order, for dL/dy on
+    (D, H, W).  Stored gradient tensors are BF16 when quant (as on the GPU)."""
+    L, P, a, p, d, s = cache["L"], cache["P"], cache["a"], cache["p"], cache["d"], cache["s"]
+    E, B, Dd, Hd = P[:L], P[L], P[L + 1:2 * L - 1], P[2 * L - 1]
+    gE, gD = [None] * L, [None] * (L - 2)
     dy4 = dy[..., None]
-    dw5, db5 = conv3d_wgrad(cache["s0"], dy4)
-    ds0 = _q(conv3d_dgrad(dy4, P[5][0]), quant)
-    dd1 = up_T(ds0) * (cache["d1"] > 0)
-    dd1 = _q(dd1, quant)
-    dw4, db4 = conv3d_wgrad(cache["s1"], dd1)
-    ds1 = _q(conv3d_dgrad(dd1, P[4][0]), quant)
-    db2_ = _q(up_T(ds1) * (cache["b2"] > 0), quant)
-    dw3, db3 = conv3d_wgrad(cache["a2"], db2_)
-    da2 = _q(conv3d_dgrad(db2_, P[3][0]) * (cache["a2"] > 0), quant)
-    dw2, db2 = conv3d_wgrad(cache["p1"], da2)
-    dp1 = _q(conv3d_dgrad(da2, P[2][0]), quant)
-    da1 = _q((ds1 + pool_T(dp1)) * (cache["a1"] > 0), quant)
-    dw1, db1 = conv3d_wgrad(cache["p0"], da1)
-    dp0 = _q(conv3d_dgrad(da1, P[1][0]), quant)
-    da0 = _q((ds0 + pool_T(dp0)) * (cache["a0"] > 0), quant)
-    dw0, db0 = conv3d_wgrad(cache["x0"], da0)
-    return [(dw0, db0), (dw1, db1), (dw2, db2), (dw3, db3), (dw4, db4), (dw5, db5)]
+    gH = conv3d_wgrad(s[0], dy4)
+    skip = {0: _q(conv3d_dgrad(dy4, Hd[0]), quant)}
+    for i, l in enumerate(range(1, L - 1)):
+        di = L - 2 - l                      # index of d_l in decoder parameter order
+        dd = _q(up_T(skip[l - 1]) * (d[l] > 0), quant)
+        gD[di] = conv3d_wgrad(s[l], dd)
+        skip[l] = _q(conv3d_dgrad(dd, Dd[di][0]), quant)
+    ddb = _q(up_T(skip[L - 2]) * (d[L - 1] > 0), quant)
+    gB = conv3d_wgrad(a[L - 1], ddb)
+    da = _q(conv3d_dgrad(ddb, B[0]) * (a[L - 1] > 0), quant)
+    for l in range(L - 1, 0, -1):
+        gE[l] = conv3d_wgrad(p[l - 1], da)
+        dp = _q(conv3d_dgrad(da, E[l][0]), quant)
+        da = _q((skip[l - 1] + pool_T(dp)) * (a[l - 1] > 0), quant)
+    gE[0] = conv3d_wgrad(cache["x0"], da)
+    return gE + [gB] + gD + [gH]
 
 
 # --------------------------------------------------------------- loss

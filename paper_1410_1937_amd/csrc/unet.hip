@@ -30,9 +30,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr double kL0 = -3.5, kL1 = 3.4;   // log(1/rho) normalisation
-constexpr int kLayers = 6;
-constexpr int kCin[kLayers] = {2, 16, 32, 64, 32, 16};
-constexpr int kCout[kLayers] = {16, 32, 64, 32, 16, 1};
+constexpr int kMaxLevels = 6;
 constexpr int kWgradBlocks = 64;
 
 __device__ __forceinline__ bf16_t f2bf(float f) {
@@ -538,19 +536,33 @@ __global__ void k_pack_head(const float* __restrict__ w, float* __restrict__ wq)
 }  // namespace
 
 // ============================================================== host side
+// Channels per level 16, 32, 64, 64, ...; convolutions in parameter order:
+// encoder e_0..e_{L-1}, bottleneck b, decoder d_{L-2}..d_1, head (16 -> 1).
+inline int level_channels(int l) { return l == 0 ? 16 : l == 1 ? 32 : 64; }
+
 struct UNet {
-  int nx = 0, ny = 0, nz = 0;
-  long long n0 = 0, n1 = 0, n2 = 0;
-  long long off_w[kLayers], off_b[kLayers], nparam = 0;
-  DevBuf params, grads, adam_m, adam_v;         // FP32, nparam
-  DevBuf frag_f[kLayers], frag_b[kLayers], head_w;
-  DevBuf x0, a0, p0, a1, p1, a2, b2, d1, ell;   // BF16 activations
-  DevBuf ds0, da0, dd1, ds1, da1, dp0, db2, da2, dp1;  // BF16 gradients
-  DevBuf zt, Az, dz;                             // FP32 cells
-  DevBuf wpart, cpart, htmp, dypad;              // FP32 partials, head scratch
-  DevBuf scal;                                   // double: rr, a, c
+  int nx = 0, ny = 0, nz = 0, L = 3;
+  long long npos[kMaxLevels] = {0};
+  int nlayers = 0;
+  std::vector<int> cin, cout;
+  std::vector<long long> off_w, off_b;
+  long long nparam = 0;
+  DevBuf params, grads, adam_m, adam_v;              // FP32, nparam
+  std::vector<DevBuf> frag_f, frag_b;                // packed BF16 weight fragments
+  DevBuf head_w;
+  DevBuf x0, ell;
+  DevBuf a[kMaxLevels], p[kMaxLevels], d[kMaxLevels];            // activations (BF16)
+  DevBuf skip[kMaxLevels], dd[kMaxLevels], da[kMaxLevels], dp[kMaxLevels];  // gradients (BF16)
+  DevBuf zt, Az, dz;                                 // FP32 cells
+  DevBuf wpart, cpart, htmp, dypad;                  // FP32 partials, head scratch
+  DevBuf scal;                                       // double: rr, a, c
   const void* ell_op = nullptr;
   int ell_version = -1;
+  int E(int l) const { return l; }
+  int B() const { return L; }
+  int Dl(int l) const { return L + 1 + (L - 2 - l); }
+  int Hd() const { return 2 * L - 1; }
+  void dims(int l, int& D, int& H, int& W) const { D = nz >> l; H = ny >> l; W = nx >> l; }
 };
 
 }  // namespace nfa
@@ -560,13 +572,28 @@ struct nfa_unet_s : nfa::UNet {};
 namespace nfa {
 namespace {
 
-long long count_params(long long* off_w, long long* off_b) {
+void layer_shapes(int L, std::vector<int>& ci, std::vector<int>& co) {
+  ci.clear();
+  co.clear();
+  ci.push_back(2);
+  co.push_back(16);
+  for (int l = 1; l < L; ++l) { ci.push_back(level_channels(l - 1)); co.push_back(level_channels(l)); }
+  ci.push_back(level_channels(L - 1));
+  co.push_back(level_channels(L - 2));
+  for (int l = L - 2; l >= 1; --l) { ci.push_back(level_channels(l)); co.push_back(level_channels(l - 1)); }
+  ci.push_back(16);
+  co.push_back(1);
+}
+
+long long count_params(int L, std::vector<long long>* off_w, std::vector<long long>* off_b) {
+  std::vector<int> ci, co;
+  layer_shapes(L, ci, co);
   long long o = 0;
-  for (int l = 0; l < kLayers; ++l) {
-    if (off_w) off_w[l] = o;
-    o += 27LL * kCin[l] * kCout[l];
-    if (off_b) off_b[l] = o;
-    o += kCout[l];
+  for (size_t l = 0; l < ci.size(); ++l) {
+    if (off_w) off_w->push_back(o);
+    o += 27LL * ci[l] * co[l];
+    if (off_b) off_b->push_back(o);
+    o += co[l];
   }
   return o;
 }
@@ -575,8 +602,8 @@ inline int eblocks(long long n) { return blocks_for(n, kBlock, 8192); }
 
 nfa_status pack_all(UNet& u, hipStream_t s) {
   const float* P = u.params.as<float>();
-  for (int l = 0; l < kLayers - 1; ++l) {
-    const int cin = kCin[l], cout = kCout[l];
+  for (int l = 0; l < u.nlayers - 1; ++l) {
+    const int cin = u.cin[l], cout = u.cout[l];
     const long long nf = (long long)((27 * cin + 31) / 32) * (cout / 16) * 64 * 8;
     k_pack_fwd<<<eblocks(nf), kBlock, 0, s>>>(P + u.off_w[l], cin, cout, u.frag_f[l].as<bf16_t>());
     if (l > 0) {
@@ -584,31 +611,86 @@ nfa_status pack_all(UNet& u, hipStream_t s) {
       k_pack_bwd<<<eblocks(nb), kBlock, 0, s>>>(P + u.off_w[l], cin, cout, u.frag_b[l].as<bf16_t>());
     }
   }
-  k_pack_head<<<1, 512, 0, s>>>(P + u.off_w[5], u.head_w.as<float>());
+  k_pack_head<<<1, 512, 0, s>>>(P + u.off_w[u.Hd()], u.head_w.as<float>());
   NFA_CHECK_LAUNCH();
   return NFA_OK;
 }
 
 template <int CIN, int COUT, bool UPADD>
-void conv(int D, int H, int W, const bf16_t* in, const bf16_t* in2, const DevBuf& frag, const float* bias,
-          int relu, const bf16_t* mask, bf16_t* out, const SolveScalars* sc, hipStream_t s) {
+void conv_t(int D, int H, int W, const bf16_t* in, const bf16_t* in2, const DevBuf& frag, const float* bias,
+            int relu, const bf16_t* mask, bf16_t* out, const SolveScalars* sc, hipStream_t s) {
   const long long waves = (long long)D * H * ((W + 15) / 16);
   k_conv<CIN, COUT, UPADD><<<(int)((waves + 3) / 4), 256, 0, s>>>(
       D, H, W, in, in2, reinterpret_cast<const uint4*>(frag.p), bias, relu, mask, out, sc);
 }
 
+nfa_status conv(int cin, int cout, bool upadd, int D, int H, int W, const bf16_t* in, const bf16_t* in2,
+                const DevBuf& frag, const float* bias, int relu, const bf16_t* mask, bf16_t* out,
+                const SolveScalars* sc, hipStream_t s) {
+#define C_(A, B, U) \
+  if (cin == A && cout == B && upadd == U) { conv_t<A, B, U>(D, H, W, in, in2, frag, bias, relu, mask, out, sc, s); return NFA_OK; }
+  C_(2, 16, false) C_(16, 32, false) C_(32, 64, false) C_(64, 64, false) C_(64, 32, false)
+  C_(32, 16, false) C_(32, 16, true) C_(64, 32, true) C_(64, 64, true) C_(16, 32, false) C_(32, 64, true)
+#undef C_
+  return fail(NFA_ERR_INVALID, "learned preconditioner: no convolution kernel for this shape");
+}
+
 template <int CIN, int COUT, bool UPADD>
-void wgrad(UNet& u, int l, int D, int H, int W, const bf16_t* in, const bf16_t* in2, const bf16_t* dout,
-           hipStream_t s) {
+void wgrad_t(UNet& u, float* gw, float* gb, int D, int H, int W, const bf16_t* in, const bf16_t* in2,
+             const bf16_t* dout, hipStream_t s) {
   dim3 grid(kWgradBlocks, 27);
   k_wgrad<CIN, COUT, UPADD><<<grid, 256, 0, s>>>(D, H, W, in, in2, dout, u.wpart.as<float>());
-  k_wgrad_reduce<<<eblocks(27LL * CIN * COUT), kBlock, 0, s>>>(u.wpart.as<float>(), kWgradBlocks, CIN * COUT,
-                                                              u.grads.as<float>() + u.off_w[l]);
+  k_wgrad_reduce<<<eblocks(27LL * CIN * COUT), kBlock, 0, s>>>(u.wpart.as<float>(), kWgradBlocks, CIN * COUT, gw);
   const long long n = (long long)D * H * W;
   k_colsum<COUT><<<kWgradBlocks, 256, 0, s>>>(n, dout, u.cpart.as<float>());
-  k_colsum_reduce<<<1, 64, 0, s>>>(u.cpart.as<float>(), kWgradBlocks, COUT, COUT,
-                                   u.grads.as<float>() + u.off_b[l]);
+  k_colsum_reduce<<<1, 64, 0, s>>>(u.cpart.as<float>(), kWgradBlocks, COUT, COUT, gb);
 }
+
+nfa_status wgrad(UNet& u, int layer, bool upadd, int level, const bf16_t* in, const bf16_t* in2,
+                 const bf16_t* dout, hipStream_t s) {
+  int D, H, W;
+  u.dims(level, D, H, W);
+  float* gw = u.grads.as<float>() + u.off_w[layer];
+  float* gb = u.grads.as<float>() + u.off_b[layer];
+  const int cin = u.cin[layer], cout = u.cout[layer];
+#define W_(A, B, U) \
+  if (cin == A && cout == B && upadd == U) { wgrad_t<A, B, U>(u, gw, gb, D, H, W, in, in2, dout, s); return NFA_OK; }
+  W_(2, 16, false) W_(16, 32, false) W_(32, 64, false) W_(64, 64, false) W_(64, 32, false)
+  W_(32, 16, true) W_(64, 32, true) W_(64, 64, true)
+#undef W_
+  return fail(NFA_ERR_INVALID, "learned preconditioner: no weight-gradient kernel for this shape");
+}
+
+void pool(int C, int level_out, const UNet& u, const bf16_t* fine, bf16_t* coarse, hipStream_t s) {
+  int D, H, W;
+  u.dims(level_out, D, H, W);
+  const long long n = (long long)D * H * W * (C / 8);
+  if (C == 16) k_pool<16><<<eblocks(n), kBlock, 0, s>>>(D, H, W, fine, coarse);
+  else if (C == 32) k_pool<32><<<eblocks(n), kBlock, 0, s>>>(D, H, W, fine, coarse);
+  else k_pool<64><<<eblocks(n), kBlock, 0, s>>>(D, H, W, fine, coarse);
+}
+
+void upT_mask(int C, int level_out, const UNet& u, const bf16_t* fine, const bf16_t* mask, bf16_t* coarse,
+              hipStream_t s) {
+  int D, H, W;
+  u.dims(level_out, D, H, W);
+  const long long n = (long long)D * H * W * (C / 8);
+  if (C == 16) k_upT_mask<16><<<eblocks(n), kBlock, 0, s>>>(D, H, W, fine, mask, coarse);
+  else if (C == 32) k_upT_mask<32><<<eblocks(n), kBlock, 0, s>>>(D, H, W, fine, mask, coarse);
+  else k_upT_mask<64><<<eblocks(n), kBlock, 0, s>>>(D, H, W, fine, mask, coarse);
+}
+
+void skip_poolT_mask(int C, int level, const UNet& u, const bf16_t* skip, const bf16_t* coarse,
+                     const bf16_t* mask, bf16_t* fine, hipStream_t s) {
+  int D, H, W;
+  u.dims(level, D, H, W);
+  const long long n = (long long)D * H * W * (C / 8);
+  if (C == 16) k_skip_poolT_mask<16><<<eblocks(n), kBlock, 0, s>>>(D, H, W, skip, coarse, mask, fine);
+  else if (C == 32) k_skip_poolT_mask<32><<<eblocks(n), kBlock, 0, s>>>(D, H, W, skip, coarse, mask, fine);
+  else k_skip_poolT_mask<64><<<eblocks(n), kBlock, 0, s>>>(D, H, W, skip, coarse, mask, fine);
+}
+
+#define B16(buf) (buf).as<bf16_t>()
 
 // forward on the operator's grid; rr / nred give the residual scale
 nfa_status forward(UNet& u, Poisson& op, const float* r, float* z, const double* rr, double nred,
@@ -617,74 +699,98 @@ nfa_status forward(UNet& u, Poisson& op, const float* r, float* z, const double*
   if (g.nx != u.nx || g.ny != u.ny || g.nz != u.nz)
     return fail(NFA_ERR_INVALID, "learned preconditioner: network and operator grids differ");
   if (u.ell_op != (const void*)&op || u.ell_version != op.version) {
-    k_ell<<<eblocks(u.n0), kBlock, 0, s>>>(u.n0, op.rho.as<double>(), u.ell.as<bf16_t>());
+    k_ell<<<eblocks(u.npos[0]), kBlock, 0, s>>>(u.npos[0], op.rho.as<double>(), B16(u.ell));
     u.ell_op = &op;
     u.ell_version = op.version;
   }
-  const int D0 = u.nz, H0 = u.ny, W0 = u.nx;
-  const int D1 = D0 / 2, H1 = H0 / 2, W1 = W0 / 2, D2 = D0 / 4, H2 = H0 / 4, W2 = W0 / 4;
+  const int L = u.L;
   const float* P = u.params.as<float>();
-  k_prep<<<eblocks(u.n0), kBlock, 0, s>>>(u.n0, r, u.ell.as<bf16_t>(), rr, nred, u.x0.as<bf16_t>(), sc);
-  conv<2, 16, false>(D0, H0, W0, u.x0.as<bf16_t>(), nullptr, u.frag_f[0], P + u.off_b[0], 1, nullptr,
-                     u.a0.as<bf16_t>(), sc, s);
-  k_pool<16><<<eblocks(u.n1 * 2), kBlock, 0, s>>>(D1, H1, W1, u.a0.as<bf16_t>(), u.p0.as<bf16_t>());
-  conv<16, 32, false>(D1, H1, W1, u.p0.as<bf16_t>(), nullptr, u.frag_f[1], P + u.off_b[1], 1, nullptr,
-                      u.a1.as<bf16_t>(), sc, s);
-  k_pool<32><<<eblocks(u.n2 * 4), kBlock, 0, s>>>(D2, H2, W2, u.a1.as<bf16_t>(), u.p1.as<bf16_t>());
-  conv<32, 64, false>(D2, H2, W2, u.p1.as<bf16_t>(), nullptr, u.frag_f[2], P + u.off_b[2], 1, nullptr,
-                      u.a2.as<bf16_t>(), sc, s);
-  conv<64, 32, false>(D2, H2, W2, u.a2.as<bf16_t>(), nullptr, u.frag_f[3], P + u.off_b[3], 1, nullptr,
-                      u.b2.as<bf16_t>(), sc, s);
-  conv<32, 16, true>(D1, H1, W1, u.a1.as<bf16_t>(), u.b2.as<bf16_t>(), u.frag_f[4], P + u.off_b[4], 1,
-                     nullptr, u.d1.as<bf16_t>(), sc, s);
-  k_head_fwd<<<eblocks(u.n0), kBlock, 0, s>>>(D0, H0, W0, u.x0.as<bf16_t>(), u.a0.as<bf16_t>(),
-                                              u.d1.as<bf16_t>(), u.head_w.as<float>(), P + u.off_b[5],
-                                              op.dinv32.as<float>(), z, sc);
+  int D, H, W;
+  k_prep<<<eblocks(u.npos[0]), kBlock, 0, s>>>(u.npos[0], r, B16(u.ell), rr, nred, B16(u.x0), sc);
+  u.dims(0, D, H, W);
+  nfa_status e = conv(2, 16, false, D, H, W, B16(u.x0), nullptr, u.frag_f[0], P + u.off_b[0], 1, nullptr,
+                      B16(u.a[0]), sc, s);
+  for (int l = 1; l < L && e == NFA_OK; ++l) {
+    pool(level_channels(l - 1), l, u, B16(u.a[l - 1]), B16(u.p[l - 1]), s);
+    u.dims(l, D, H, W);
+    e = conv(u.cin[u.E(l)], u.cout[u.E(l)], false, D, H, W, B16(u.p[l - 1]), nullptr, u.frag_f[u.E(l)],
+             P + u.off_b[u.E(l)], 1, nullptr, B16(u.a[l]), sc, s);
+  }
+  if (e != NFA_OK) return e;
+  u.dims(L - 1, D, H, W);
+  e = conv(u.cin[u.B()], u.cout[u.B()], false, D, H, W, B16(u.a[L - 1]), nullptr, u.frag_f[u.B()],
+           P + u.off_b[u.B()], 1, nullptr, B16(u.d[L - 1]), sc, s);
+  for (int l = L - 2; l >= 1 && e == NFA_OK; --l) {
+    u.dims(l, D, H, W);
+    e = conv(u.cin[u.Dl(l)], u.cout[u.Dl(l)], true, D, H, W, B16(u.a[l]), B16(u.d[l + 1]), u.frag_f[u.Dl(l)],
+             P + u.off_b[u.Dl(l)], 1, nullptr, B16(u.d[l]), sc, s);
+  }
+  if (e != NFA_OK) return e;
+  u.dims(0, D, H, W);
+  k_head_fwd<<<eblocks(u.npos[0]), kBlock, 0, s>>>(D, H, W, B16(u.x0), B16(u.a[0]), B16(u.d[1]),
+                                                   u.head_w.as<float>(), P + u.off_b[u.Hd()],
+                                                   op.dinv32.as<float>(), z, sc);
   NFA_CHECK_LAUNCH();
   return NFA_OK;
 }
 
 // gradients of all parameters from dL/dz (in u.dz)
 nfa_status backward(UNet& u, Poisson& op, hipStream_t s) {
-  const int D0 = u.nz, H0 = u.ny, W0 = u.nx;
-  const int D1 = D0 / 2, H1 = H0 / 2, W1 = W0 / 2, D2 = D0 / 4, H2 = H0 / 4, W2 = W0 / 4;
+  const int L = u.L;
+  int D, H, W;
+  u.dims(0, D, H, W);
   float* G = u.grads.as<float>();
   const float* dinv = op.dinv32.as<float>();
-  k_head_bwd_data<<<eblocks(u.n0), kBlock, 0, s>>>(D0, H0, W0, u.dz.as<float>(), dinv, u.head_w.as<float>(),
-                                                   u.ds0.as<bf16_t>());
-  // head weights: MFMA weight gradient with dy as channel 0 of a 16-channel tensor
-  k_pad_dy<<<eblocks(u.n0), kBlock, 0, s>>>(u.n0, u.dz.as<float>(), dinv, u.dypad.as<bf16_t>());
+  const long long n0 = u.npos[0];
+  // head: data gradient into skip[0], weights through the MFMA weight gradient
+  // with dy = dinv*dz as channel 0 of a 16-channel tensor
+  k_head_bwd_data<<<eblocks(n0), kBlock, 0, s>>>(D, H, W, u.dz.as<float>(), dinv, u.head_w.as<float>(),
+                                                 B16(u.skip[0]));
+  k_pad_dy<<<eblocks(n0), kBlock, 0, s>>>(n0, u.dz.as<float>(), dinv, B16(u.dypad));
   {
     dim3 grid(kWgradBlocks, 27);
-    k_wgrad<16, 16, true><<<grid, 256, 0, s>>>(D0, H0, W0, u.a0.as<bf16_t>(), u.d1.as<bf16_t>(),
-                                               u.dypad.as<bf16_t>(), u.wpart.as<float>());
+    k_wgrad<16, 16, true><<<grid, 256, 0, s>>>(D, H, W, B16(u.a[0]), B16(u.d[1]), B16(u.dypad),
+                                               u.wpart.as<float>());
     k_wgrad_reduce<<<eblocks(27LL * 256), kBlock, 0, s>>>(u.wpart.as<float>(), kWgradBlocks, 256,
                                                          u.htmp.as<float>());
-    k_head_extract<<<1, 512, 0, s>>>(u.htmp.as<float>(), G + u.off_w[5]);
-    k_colsum<16><<<kWgradBlocks, 256, 0, s>>>(u.n0, u.dypad.as<bf16_t>(), u.cpart.as<float>());
-    k_colsum_reduce<<<1, 64, 0, s>>>(u.cpart.as<float>(), kWgradBlocks, 16, 1, G + u.off_b[5]);
+    k_head_extract<<<1, 512, 0, s>>>(u.htmp.as<float>(), G + u.off_w[u.Hd()]);
+    k_colsum<16><<<kWgradBlocks, 256, 0, s>>>(n0, B16(u.dypad), u.cpart.as<float>());
+    k_colsum_reduce<<<1, 64, 0, s>>>(u.cpart.as<float>(), kWgradBlocks, 16, 1, G + u.off_b[u.Hd()]);
   }
-  k_upT_mask<16><<<eblocks(u.n1 * 2), kBlock, 0, s>>>(D1, H1, W1, u.ds0.as<bf16_t>(), u.d1.as<bf16_t>(),
-                                                      u.dd1.as<bf16_t>());
-  wgrad<32, 16, true>(u, 4, D1, H1, W1, u.a1.as<bf16_t>(), u.b2.as<bf16_t>(), u.dd1.as<bf16_t>(), s);
-  conv<16, 32, false>(D1, H1, W1, u.dd1.as<bf16_t>(), nullptr, u.frag_b[4], nullptr, 0, nullptr,
-                      u.ds1.as<bf16_t>(), nullptr, s);
-  k_upT_mask<32><<<eblocks(u.n2 * 4), kBlock, 0, s>>>(D2, H2, W2, u.ds1.as<bf16_t>(), u.b2.as<bf16_t>(),
-                                                      u.db2.as<bf16_t>());
-  wgrad<64, 32, false>(u, 3, D2, H2, W2, u.a2.as<bf16_t>(), nullptr, u.db2.as<bf16_t>(), s);
-  conv<32, 64, false>(D2, H2, W2, u.db2.as<bf16_t>(), nullptr, u.frag_b[3], nullptr, 0, u.a2.as<bf16_t>(),
-                      u.da2.as<bf16_t>(), nullptr, s);
-  wgrad<32, 64, false>(u, 2, D2, H2, W2, u.p1.as<bf16_t>(), nullptr, u.da2.as<bf16_t>(), s);
-  conv<64, 32, false>(D2, H2, W2, u.da2.as<bf16_t>(), nullptr, u.frag_b[2], nullptr, 0, nullptr,
-                      u.dp1.as<bf16_t>(), nullptr, s);
-  k_skip_poolT_mask<32><<<eblocks(u.n1 * 4), kBlock, 0, s>>>(D1, H1, W1, u.ds1.as<bf16_t>(), u.dp1.as<bf16_t>(),
-                                                             u.a1.as<bf16_t>(), u.da1.as<bf16_t>());
-  wgrad<16, 32, false>(u, 1, D1, H1, W1, u.p0.as<bf16_t>(), nullptr, u.da1.as<bf16_t>(), s);
-  conv<32, 16, false>(D1, H1, W1, u.da1.as<bf16_t>(), nullptr, u.frag_b[1], nullptr, 0, nullptr,
-                      u.dp0.as<bf16_t>(), nullptr, s);
-  k_skip_poolT_mask<16><<<eblocks(u.n0 * 2), kBlock, 0, s>>>(D0, H0, W0, u.ds0.as<bf16_t>(), u.dp0.as<bf16_t>(),
-                                                             u.a0.as<bf16_t>(), u.da0.as<bf16_t>());
-  wgrad<2, 16, false>(u, 0, D0, H0, W0, u.x0.as<bf16_t>(), nullptr, u.da0.as<bf16_t>(), s);
+  nfa_status e = NFA_OK;
+  // decoder, fine to coarse
+  for (int l = 1; l <= L - 2 && e == NFA_OK; ++l) {
+    const int ly = u.Dl(l);
+    upT_mask(level_channels(l - 1), l, u, B16(u.skip[l - 1]), B16(u.d[l]), B16(u.dd[l]), s);
+    e = wgrad(u, ly, true, l, B16(u.a[l]), B16(u.d[l + 1]), B16(u.dd[l]), s);
+    if (e != NFA_OK) break;
+    u.dims(l, D, H, W);
+    e = conv(u.cout[ly], u.cin[ly], false, D, H, W, B16(u.dd[l]), nullptr, u.frag_b[ly], nullptr, 0, nullptr,
+             B16(u.skip[l]), nullptr, s);
+  }
+  if (e != NFA_OK) return e;
+  // bottleneck
+  upT_mask(level_channels(L - 2), L - 1, u, B16(u.skip[L - 2]), B16(u.d[L - 1]), B16(u.dd[L - 1]), s);
+  e = wgrad(u, u.B(), false, L - 1, B16(u.a[L - 1]), nullptr, B16(u.dd[L - 1]), s);
+  if (e != NFA_OK) return e;
+  u.dims(L - 1, D, H, W);
+  e = conv(u.cout[u.B()], u.cin[u.B()], false, D, H, W, B16(u.dd[L - 1]), nullptr, u.frag_b[u.B()], nullptr, 0,
+           B16(u.a[L - 1]), B16(u.da[L - 1]), nullptr, s);
+  // encoder, coarse to fine
+  for (int l = L - 1; l >= 1 && e == NFA_OK; --l) {
+    const int ly = u.E(l);
+    e = wgrad(u, ly, false, l, B16(u.p[l - 1]), nullptr, B16(u.da[l]), s);
+    if (e != NFA_OK) break;
+    u.dims(l, D, H, W);
+    e = conv(u.cout[ly], u.cin[ly], false, D, H, W, B16(u.da[l]), nullptr, u.frag_b[ly], nullptr, 0, nullptr,
+             B16(u.dp[l - 1]), nullptr, s);
+    if (e != NFA_OK) break;
+    skip_poolT_mask(level_channels(l - 1), l - 1, u, B16(u.skip[l - 1]), B16(u.dp[l - 1]), B16(u.a[l - 1]),
+                    B16(u.da[l - 1]), s);
+  }
+  if (e != NFA_OK) return e;
+  e = wgrad(u, u.E(0), false, 0, B16(u.x0), nullptr, B16(u.da[0]), s);
+  if (e != NFA_OK) return e;
   NFA_CHECK_LAUNCH();
   return NFA_OK;
 }
@@ -694,7 +800,7 @@ nfa_status grad_step(UNet& u, Poisson& op, const float* r, double eAe, double* l
   if (!(eAe > 0)) return fail(NFA_ERR_INVALID, "learned preconditioner: eAe must be > 0");
   double* scal = u.scal.as<double>();
   double* parts = op.partials.as<double>();
-  const long long n = u.n0;
+  const long long n = u.npos[0];
   int nb = launch_dot<float>(r, r, n, parts, nullptr, s);
   launch_sum_partials(parts, nb, 1, scal, s);
   nfa_status e = forward(u, op, r, u.zt.as<float>(), scal, (double)op.g->n_reduced, nullptr, s);
@@ -730,21 +836,29 @@ nfa_status unet_precond_apply(void* unet, Poisson& op, const float* r, float* z,
 
 using namespace nfa;
 
-extern "C" long long nfa_unet_param_count(void) { return count_params(nullptr, nullptr); }
+extern "C" long long nfa_unet_param_count(int levels) {
+  if (levels < 3 || levels > kMaxLevels) return -1;
+  return count_params(levels, nullptr, nullptr);
+}
 
-extern "C" nfa_status nfa_unet_create(int nx, int ny, int nz, int seed, nfa_unet* out) {
+extern "C" nfa_status nfa_unet_create(int nx, int ny, int nz, int levels, int seed, nfa_unet* out) {
   if (!out) return fail(NFA_ERR_INVALID, "nfa_unet_create: out is NULL");
   *out = nullptr;
-  if (nx < 4 || ny < 4 || nz < 4 || nx % 4 || ny % 4 || nz % 4)
-    return fail(NFA_ERR_INVALID, "nfa_unet_create: grid sizes must be multiples of 4");
+  if (levels < 3 || levels > kMaxLevels) return fail(NFA_ERR_INVALID, "nfa_unet_create: levels must be in [3, 6]");
+  const int q = 1 << (levels - 1);
+  if (nx < q || ny < q || nz < q || nx % q || ny % q || nz % q)
+    return fail(NFA_ERR_INVALID, "nfa_unet_create: grid sizes must be multiples of 2^(levels-1)");
   auto* u = new nfa_unet_s();
   u->nx = nx;
   u->ny = ny;
   u->nz = nz;
-  u->n0 = (long long)nx * ny * nz;
-  u->n1 = u->n0 / 8;
-  u->n2 = u->n0 / 64;
-  u->nparam = count_params(u->off_w, u->off_b);
+  u->L = levels;
+  for (int l = 0; l < levels; ++l) u->npos[l] = (long long)(nx >> l) * (ny >> l) * (nz >> l);
+  layer_shapes(levels, u->cin, u->cout);
+  u->nlayers = (int)u->cin.size();
+  u->nparam = count_params(levels, &u->off_w, &u->off_b);
+  u->frag_f.resize(u->nlayers);
+  u->frag_b.resize(u->nlayers);
   auto bad = [&](hipError_t e) {
     delete u;
     return fail(NFA_ERR_HIP, std::string("nfa_unet_create: ") + hipGetErrorString(e));
@@ -755,30 +869,29 @@ extern "C" nfa_status nfa_unet_create(int nx, int ny, int nz, int seed, nfa_unet
   UALLOC(grads, u->nparam * 4);
   UALLOC(adam_m, u->nparam * 4);
   UALLOC(adam_v, u->nparam * 4);
-  for (int l = 0; l < kLayers - 1; ++l) {
-    UALLOC(frag_f[l], (size_t)((27 * kCin[l] + 31) / 32) * (kCout[l] / 16) * 64 * 16);
-    if (l > 0) UALLOC(frag_b[l], (size_t)((27 * kCout[l] + 31) / 32) * (kCin[l] / 16) * 64 * 16);
+  for (int l = 0; l < u->nlayers - 1; ++l) {
+    UALLOC(frag_f[l], (size_t)((27 * u->cin[l] + 31) / 32) * (u->cout[l] / 16) * 64 * 16);
+    if (l > 0) UALLOC(frag_b[l], (size_t)((27 * u->cout[l] + 31) / 32) * (u->cin[l] / 16) * 64 * 16);
   }
   UALLOC(head_w, 27 * 16 * 4);
-  const long long n0 = u->n0, n1 = u->n1, n2 = u->n2;
+  const long long n0 = u->npos[0];
   UALLOC(ell, n0 * 2);
   UALLOC(x0, n0 * 2 * 2);
-  UALLOC(a0, n0 * 16 * 2);
-  UALLOC(p0, n1 * 16 * 2);
-  UALLOC(a1, n1 * 32 * 2);
-  UALLOC(p1, n2 * 32 * 2);
-  UALLOC(a2, n2 * 64 * 2);
-  UALLOC(b2, n2 * 32 * 2);
-  UALLOC(d1, n1 * 16 * 2);
-  UALLOC(ds0, n0 * 16 * 2);
-  UALLOC(da0, n0 * 16 * 2);
-  UALLOC(dd1, n1 * 16 * 2);
-  UALLOC(ds1, n1 * 32 * 2);
-  UALLOC(da1, n1 * 32 * 2);
-  UALLOC(dp0, n1 * 16 * 2);
-  UALLOC(db2, n2 * 32 * 2);
-  UALLOC(da2, n2 * 64 * 2);
-  UALLOC(dp1, n2 * 32 * 2);
+  for (int l = 0; l < levels; ++l) {
+    const long long nl = u->npos[l];
+    const int c = level_channels(l);
+    UALLOC(a[l], nl * c * 2);
+    UALLOC(da[l], nl * c * 2);
+    if (l + 1 < levels) {
+      UALLOC(p[l], u->npos[l + 1] * c * 2);
+      UALLOC(dp[l], u->npos[l + 1] * c * 2);
+      UALLOC(skip[l], nl * c * 2);
+    }
+    if (l >= 1) {
+      UALLOC(d[l], nl * level_channels(l - 1) * 2);
+      UALLOC(dd[l], nl * level_channels(l - 1) * 2);
+    }
+  }
   UALLOC(zt, n0 * 4);
   UALLOC(Az, n0 * 4);
   UALLOC(dz, n0 * 4);
@@ -788,13 +901,13 @@ extern "C" nfa_status nfa_unet_create(int nx, int ny, int nz, int seed, nfa_unet
   UALLOC(dypad, n0 * 16 * 2);
   UALLOC(scal, 8 * 8);
 #undef UALLOC
-  // He-normal initial weights, zero biases, conv5 zero (the Jacobi step)
+  // He-normal initial weights, zero biases, head zero (the Jacobi step)
   std::vector<float> h(u->nparam, 0.0f);
   std::mt19937_64 rng((unsigned long long)seed);
   std::normal_distribution<double> nd(0.0, 1.0);
-  for (int l = 0; l < kLayers - 1; ++l) {
-    const double sd = std::sqrt(2.0 / (27.0 * kCin[l]));
-    for (long long i = 0; i < 27LL * kCin[l] * kCout[l]; ++i) h[u->off_w[l] + i] = (float)(nd(rng) * sd);
+  for (int l = 0; l < u->nlayers - 1; ++l) {
+    const double sd = std::sqrt(2.0 / (27.0 * u->cin[l]));
+    for (long long i = 0; i < 27LL * u->cin[l] * u->cout[l]; ++i) h[u->off_w[l] + i] = (float)(nd(rng) * sd);
   }
   nfa_status st = nfa_unet_set_params(u, h.data());
   if (st != NFA_OK) {
@@ -808,6 +921,8 @@ extern "C" nfa_status nfa_unet_create(int nx, int ny, int nz, int seed, nfa_unet
   *out = u;
   return NFA_OK;
 }
+
+extern "C" int nfa_unet_levels(nfa_unet u) { return u ? u->L : -1; }
 
 extern "C" nfa_status nfa_unet_set_params(nfa_unet u, const float* host) {
   if (!u || !host) return fail(NFA_ERR_INVALID, "nfa_unet_set_params: NULL argument");
@@ -837,7 +952,7 @@ extern "C" nfa_status nfa_unet_forward(nfa_unet u, nfa_poisson op, const float* 
   if (!op->assembled) return fail(NFA_ERR_INVALID, "nfa_unet_forward: operator not assembled");
   const hipStream_t st = S(s);
   double* parts = op->partials.as<double>();
-  const int nb = launch_dot<float>(r, r, u->n0, parts, nullptr, st);
+  const int nb = launch_dot<float>(r, r, u->npos[0], parts, nullptr, st);
   launch_sum_partials(parts, nb, 1, u->scal.as<double>(), st);
   return forward(*u, *op, r, z, u->scal.as<double>(), (double)op->g->n_reduced, nullptr, st);
 }
@@ -869,17 +984,11 @@ extern "C" nfa_status nfa_unet_train_step(nfa_unet u, nfa_poisson op, const floa
 extern "C" nfa_status nfa_unet_export(nfa_unet u, int what, void* dst, nfa_stream s) {
   if (!u || !dst) return fail(NFA_ERR_INVALID, "nfa_unet_export: NULL argument");
   const DevBuf* b = nullptr;
-  switch (what) {
-    case NFA_UNET_X0: b = &u->x0; break;
-    case NFA_UNET_A0: b = &u->a0; break;
-    case NFA_UNET_P0: b = &u->p0; break;
-    case NFA_UNET_A1: b = &u->a1; break;
-    case NFA_UNET_P1: b = &u->p1; break;
-    case NFA_UNET_A2: b = &u->a2; break;
-    case NFA_UNET_B2: b = &u->b2; break;
-    case NFA_UNET_D1: b = &u->d1; break;
-    default: return fail(NFA_ERR_INVALID, "nfa_unet_export: unknown item");
-  }
+  if (what == NFA_UNET_X0) b = &u->x0;
+  else if (what >= NFA_UNET_A && what < NFA_UNET_A + u->L) b = &u->a[what - NFA_UNET_A];
+  else if (what >= NFA_UNET_P && what < NFA_UNET_P + u->L - 1) b = &u->p[what - NFA_UNET_P];
+  else if (what > NFA_UNET_D && what < NFA_UNET_D + u->L) b = &u->d[what - NFA_UNET_D];
+  else return fail(NFA_ERR_INVALID, "nfa_unet_export: unknown item");
   NFA_HIP(hipMemcpyAsync(dst, b->p, b->bytes, hipMemcpyDeviceToDevice, S(s)));
   return NFA_OK;
 }

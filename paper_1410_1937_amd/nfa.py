@@ -103,8 +103,9 @@ _sig("nfa_poisson_export", c_int, [c_void_p, c_int, c_void_p, c_void_p])
 _sig("nfa_poisson_destroy", None, [c_void_p])
 _sig("nfa_poisson_profile", c_int, [c_void_p, c_int])
 _sig("nfa_poisson_residual", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double), c_void_p])
-_sig("nfa_unet_create", c_int, [c_int, c_int, c_int, c_int, ctypes.POINTER(c_void_p)])
-_sig("nfa_unet_param_count", c_ll, [])
+_sig("nfa_unet_create", c_int, [c_int, c_int, c_int, c_int, c_int, ctypes.POINTER(c_void_p)])
+_sig("nfa_unet_param_count", c_ll, [c_int])
+_sig("nfa_unet_levels", c_int, [c_void_p])
 _sig("nfa_unet_get_params", c_int, [c_void_p, c_void_p])
 _sig("nfa_unet_set_params", c_int, [c_void_p, c_void_p])
 _sig("nfa_unet_get_grads", c_int, [c_void_p, c_void_p])
@@ -320,23 +321,31 @@ class Poisson:
             self.h = None
 
 
-UNET_SHAPES = [(2, 16), (16, 32), (32, 64), (64, 32), (32, 16), (16, 1)]
-UNET_EXPORT = {"x0": (0, 0, 2), "a0": (1, 0, 16), "p0": (2, 1, 16), "a1": (3, 1, 32), "p1": (4, 2, 32),
-               "a2": (5, 2, 64), "b2": (6, 2, 32), "d1": (7, 1, 16)}
+def unet_channels(levels):
+    return [16, 32, 64][:levels] + [64] * max(0, levels - 3)
+
+
+def unet_shapes(levels=3):
+    c = unet_channels(levels)
+    out = [(2, c[0])] + [(c[l - 1], c[l]) for l in range(1, levels)]
+    out.append((c[levels - 1], c[levels - 2]))
+    out += [(c[l], c[l - 1]) for l in range(levels - 2, 0, -1)]
+    out.append((c[0], 1))
+    return out
 
 
 class UNet:
     """The learned preconditioner (see include/nfa_unet.h)."""
 
-    def __init__(self, nx, ny, nz, seed=0):
+    def __init__(self, nx, ny, nz, seed=0, levels=3):
         h = c_void_p()
-        _check(lib.nfa_unet_create(nx, ny, nz, seed, ctypes.byref(h)), "nfa_unet_create")
+        _check(lib.nfa_unet_create(nx, ny, nz, levels, seed, ctypes.byref(h)), "nfa_unet_create")
         self.h = h
         self.shape = (nz, ny, nx)
+        self.levels = levels
 
-    @staticmethod
-    def param_count():
-        return int(lib.nfa_unet_param_count())
+    def param_count(self):
+        return int(lib.nfa_unet_param_count(self.levels))
 
     def _flat(self, fn, what):
         a = np.empty(self.param_count(), dtype=np.float32)
@@ -355,10 +364,9 @@ class UNet:
             raise ValueError("wrong parameter count")
         _check(lib.nfa_unet_set_params(self.h, a.ctypes.data), "nfa_unet_set_params")
 
-    @staticmethod
-    def unflatten(flat):
+    def unflatten(self, flat):
         out, o = [], 0
-        for ci, co in UNET_SHAPES:
+        for ci, co in unet_shapes(self.levels):
             w = flat[o:o + 27 * ci * co].reshape(27, ci, co)
             o += 27 * ci * co
             b = flat[o:o + co]
@@ -389,7 +397,15 @@ class UNet:
         return loss.value
 
     def export(self, what):
-        code, level, ch = UNET_EXPORT[what]
+        """'x0', 'a<l>', 'p<l>' or 'd<l>' as a channels-last bfloat16 tensor."""
+        c = unet_channels(self.levels)
+        if what == "x0":
+            code, level, ch = 0, 0, 2
+        else:
+            kind, l = what[0], int(what[1:])
+            code = {"a": 16, "p": 32, "d": 48}[kind] + l
+            level = l + 1 if kind == "p" else l
+            ch = c[l - 1] if kind == "d" else c[l]
         nz, ny, nx = self.shape
         f = 2 ** level
         out = torch.empty((nz // f, ny // f, nx // f, ch), dtype=torch.bfloat16, device="cuda")

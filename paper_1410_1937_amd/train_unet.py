@@ -1,16 +1,23 @@
 """Train the learned preconditioner on the GPU with the library's own kernels.
 
-Data: the 200-step advected free surface on the 256 x 128 x 96 hull grid
-(fixtures.C4Sequence).  For every time step the plain FP64 Jacobi-PCG solver
-gives x* (relative residual 1e-10); residual/error pairs (r_k, e_k = x* - x_k)
-are taken along its iteration after k = 0, 4, 16, 64, 256 steps, plus two
-smooth synthetic errors e with r = A'e.  Steps 0-159 train, 160-199 test.
+Data.  Problems on 256 x 128 x 96 grids: the 200-step advected free surface
+around the Wigley-like hull (fixtures.C4Sequence; steps 0-159 train,
+160-199 test) and, so that the weights transfer to the breaking-wave
+workload, snapshots of that workload's geometry (sphere, free surface,
+droplets and bubbles; fixtures.c3 at this size, one seed per snapshot).
+For every problem the plain FP64 Jacobi-PCG solver gives x* (relative
+residual 1e-10); residual/error pairs (r_k, e_k = x* - x_k) are taken along
+its iteration after k = 0, 4, 16, 64, 256 steps, plus two smooth synthetic
+errors e with r = A'e.  After the first phase, each round adds the pairs met
+by flexible CG preconditioned with the current network (after 8, 32 and 96
+iterations), so that the network also learns the residuals it leaves
+behind, then training continues on the union.
 
 Each training step runs nfa_unet_train_step: forward, the A-norm step loss
 1 - (z.r)^2/((z.A'z)(e.A'e)), backward and one Adam step.  The weights are
 written as a raw float32 .npy (no pickling) with a JSON record of the run.
 
-    python -m paper_1410_1937_amd.train_unet --minutes 3 --out paper_1410_1937_amd/weights/unet_c4
+    python -m paper_1410_1937_amd.train_unet --minutes 6 --levels 5 --out paper_1410_1937_amd/weights/unet
 """
 from __future__ import annotations
 
@@ -28,129 +35,176 @@ from paper_1410_1937_amd import fixtures as fx
 from paper_1410_1937_amd import nfa
 
 KS = (0, 4, 16, 64, 256)
+ONPOLICY_KS = (8, 32, 96)
 
 
 def log(*a):
     print(*a, flush=True)
 
 
-def make_operator(seq):
-    g = nfa.Grid(seq.xf, seq.yf, seq.zf, seq.bc)
-    g.set_body(torch.as_tensor(seq.psi, device="cuda"), seq.theta, 8)
+class Problem:
+    """One projection problem on the GPU: operator, rhs, reference solution
+    and its training pairs."""
+
+    def __init__(self, name, op, phi_t, b, xs, red):
+        self.name, self.op, self.phi_t, self.b, self.xs, self.red = name, op, phi_t, b, xs, red
+        self.samples = []
+
+    def activate(self):
+        self.op.assemble(self.phi_t)
+
+    def add_pair(self, x):
+        r, _ = self.op.residual(self.b, x)
+        e = self.xs - x
+        eAe = float(torch.dot(e.ravel(), r.ravel()))
+        if eAe > 0:
+            self.samples.append((r.float().contiguous(), eAe))
+
+
+def operator_for(xf, yf, zf, bc, psi, theta):
+    g = nfa.Grid(xf, yf, zf, bc)
+    g.set_body(torch.as_tensor(psi, device="cuda"), theta, 8)
     return g, nfa.Poisson(g)
 
 
-def generate(seq, op, steps, synth=2):
-    """Per time step: phi (FP32, device) and a list of (r FP32 device, e.A'e)."""
-    data = []
-    nz, ny, nx = seq.shape
-    red = None
-    for n in steps:
-        phi, (u, v, w) = seq.step(n)
-        phi_t = torch.as_tensor(phi, device="cuda").float().contiguous()
-        op.assemble(phi_t)
-        b = op.rhs(*(torch.as_tensor(a, device="cuda") for a in (u, v, w)))
-        xs, res = op.solve(b, tol=1e-10, precision="f64")
-        if red is None:
-            red = op.grid.export("reduced").double()
-        samples = []
-        x = torch.zeros_like(b)
-        done = 0
-        for k in KS:
-            if k > done:
-                x, _ = op.solve(b, x=x, tol=1e-30, precision="f64", max_iters=k - done, warm_start=True)
-                done = k
-            r, _ = op.residual(b, x)
-            e = xs - x
-            eAe = float(torch.dot(e.ravel(), r.ravel()))
-            if eAe > 0:
-                samples.append((r.float().contiguous(), eAe))
+def build_problem(name, op, phi, uvw, smooth_src=None, synth=2, seed=0):
+    phi_t = torch.as_tensor(phi, device="cuda").float().contiguous()
+    op.assemble(phi_t)
+    b = op.rhs(*(torch.as_tensor(a, device="cuda") for a in uvw))
+    xs, res = op.solve(b, tol=1e-10, precision="f64")
+    red = op.grid.export("reduced").double()
+    p = Problem(name, op, phi_t, b, xs, red)
+    x = torch.zeros_like(b)
+    done = 0
+    for k in KS:
+        if k > done:
+            x, _ = op.solve(b, x=x, tol=1e-30, precision="f64", max_iters=k - done, warm_start=True)
+            done = k
+        p.add_pair(x)
+    if smooth_src is not None:
         for q in range(synth):
-            e = torch.as_tensor(seq.smooth_field(7919 * n + q), device="cuda") * red
+            e = torch.as_tensor(smooth_src(seed * 7919 + q), device="cuda") * red
             r = op.apply(e)
             eAe = float(torch.dot(e.ravel(), r.ravel()))
             if eAe > 0:
-                samples.append((r.float().contiguous(), eAe))
-        data.append((n, phi_t, samples))
-        log(f"[train] data step {n}: {res.iterations} its to 1e-10, {len(samples)} pairs")
-    return data
+                p.samples.append((r.float().contiguous(), eAe))
+    log(f"[train] problem {name}: {res.iterations} its to 1e-10, {len(p.samples)} pairs")
+    return p
 
 
-def evaluate(op, net, seq, steps, tol=1e-8):
+def add_onpolicy(problems, net):
+    for p in problems:
+        p.activate()
+        for k in ONPOLICY_KS:
+            x, _ = p.op.solve(p.b, tol=1e-30, precision="mixed", precond="unet", unet=net, max_iters=k,
+                              fallback_ratio=2.0)
+            p.add_pair(x)
+
+
+def train(problems, net, minutes, lr0, step0, rng):
+    budget = minutes * 60.0
+    t1 = time.time()
+    step, hist = step0, []
+    while time.time() - t1 < budget:
+        losses = []
+        for idx in rng.permutation(len(problems)):
+            p = problems[idx]
+            p.activate()
+            for r, eAe in p.samples:
+                step += 1
+                frac = min(1.0, (time.time() - t1) / budget)
+                lr = lr0 * (0.05 + 0.95 * 0.5 * (1 + math.cos(math.pi * frac)))
+                losses.append(net.train_step(p.op, r, eAe, lr, step))
+            if time.time() - t1 >= budget:
+                break
+        hist.append(float(np.mean(losses)))
+        log(f"[train] epoch {len(hist)}: {step} steps, mean loss {hist[-1]:.4f}, "
+            f"{(time.time() - t1) / max(1, step - step0) * 1e3:.1f} ms/step")
+    return step, hist
+
+
+def evaluate(problems, net, tol=1e-8):
     rows = []
-    for n in steps:
-        phi, (u, v, w) = seq.step(n)
-        op.assemble(torch.as_tensor(phi, device="cuda").float().contiguous())
-        b = op.rhs(*(torch.as_tensor(a, device="cuda") for a in (u, v, w)))
-        row = {"step": n}
+    for p in problems:
+        p.activate()
+        row = {"problem": p.name}
         for name, kw in (("fp64_jacobi", dict(precision="f64")),
                          ("mixed_jacobi", dict(precision="mixed")),
-                         ("mixed_unet", dict(precision="mixed", precond="unet", unet=net))):
-            op.solve(b, tol=tol, **kw)   # warm caches
-            _, r = op.solve(b, tol=tol, **kw)
+                         ("mixed_unet", dict(precision="mixed", precond="unet", unet=net)),
+                         ("mixed_unet_no_monitor", dict(precision="mixed", precond="unet", unet=net,
+                                                        fallback_ratio=2.0, max_iters=3000))):
+            p.op.solve(p.b, tol=tol, **kw)
+            _, r = p.op.solve(p.b, tol=tol, **kw)
             row[name] = {"iterations": r.iterations, "ms": r.ms, "relres": r.relres, "fallback": r.fallback}
         rows.append(row)
-        log(f"[train] eval step {n}: " + ", ".join(f"{k} {v['iterations']} its {v['ms']:.1f} ms"
-                                                 for k, v in row.items() if k != "step"))
+        log(f"[train] eval {p.name}: " + ", ".join(
+            f"{k} {v['iterations']} its {v['ms']:.1f} ms{' (fallback)' if v['fallback'] else ''}"
+            for k, v in row.items() if k != "problem"))
     return rows
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--minutes", type=float, default=3.0, help="training time budget")
-    ap.add_argument("--train-steps", type=int, default=160)
-    ap.add_argument("--test-steps", type=int, default=40)
-    ap.add_argument("--stride", type=int, default=1, help="use every stride-th time step")
+    ap.add_argument("--minutes", type=float, default=6.0, help="total training time budget")
+    ap.add_argument("--rounds", type=int, default=3, help="training phases (the first without on-policy pairs)")
+    ap.add_argument("--hull-steps", type=int, default=160)
+    ap.add_argument("--stride", type=int, default=4, help="use every stride-th hull time step")
+    ap.add_argument("--breaking", type=int, default=8, help="breaking-wave geometry snapshots")
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--nx", type=int, default=256)
-    ap.add_argument("--ny", type=int, default=128)
-    ap.add_argument("--nz", type=int, default=96)
-    ap.add_argument("--eval", type=int, default=4, help="test steps to evaluate")
-    ap.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "weights", "unet_c4"))
+    ap.add_argument("--levels", type=int, default=5)
+    ap.add_argument("--eval", type=int, default=2, help="held-out problems of each kind to evaluate")
+    ap.add_argument("--init", default=None, help="start from these weights (.npy)")
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "weights", "unet"))
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
-    seq = fx.C4Sequence(args.nx, args.ny, args.nz)
-    g, op = make_operator(seq)
-    train_ids = list(range(0, args.train_steps, args.stride))
-    test_ids = list(range(args.train_steps, args.train_steps + args.test_steps, args.stride))
+    nx, ny, nz = 256, 128, 96
     t0 = time.time()
-    data = generate(seq, op, train_ids)
+    seq = fx.C4Sequence(nx, ny, nz)
+    _, op_hull = operator_for(seq.xf, seq.yf, seq.zf, seq.bc, seq.psi, seq.theta)
+    problems = []
+    for n in range(0, args.hull_steps, args.stride):
+        phi, uvw = seq.step(n)
+        problems.append(build_problem(f"hull_{n}", op_hull, phi, uvw, seq.smooth_field, seed=n))
+    wl0 = fx.c3(seed=100, nx=nx, ny=ny, nz=nz)
+    _, op_brk = operator_for(wl0.xf, wl0.yf, wl0.zf, wl0.bc, wl0.psi, wl0.theta)
+    for q in range(args.breaking):
+        wl = fx.c3(seed=100 + q, nx=nx, ny=ny, nz=nz)
+        problems.append(build_problem(f"breaking_{100 + q}", op_brk, wl.phi, (wl.u, wl.v, wl.w),
+                                      seq.smooth_field, seed=100 + q))
+    held = []
+    for n in range(160, 160 + 4 * args.eval, 4):
+        phi, uvw = seq.step(n)
+        held.append(build_problem(f"hull_{n}", op_hull, phi, uvw))
+    for q in range(args.eval):
+        wl = fx.c3(seed=200 + q, nx=nx, ny=ny, nz=nz)
+        held.append(build_problem(f"breaking_{200 + q}", op_brk, wl.phi, (wl.u, wl.v, wl.w)))
     t_data = time.time() - t0
-    net = nfa.UNet(args.nx, args.ny, args.nz, seed=args.seed)
+    net = nfa.UNet(nx, ny, nz, seed=args.seed, levels=args.levels)
+    if args.init:
+        net.set_params(np.load(args.init))
     rng = np.random.default_rng(args.seed)
-    budget = args.minutes * 60.0
+    step, hist = 0, []
     t1 = time.time()
-    step, epoch, hist = 0, 0, []
-    total_est = None
-    while time.time() - t1 < budget:
-        order = rng.permutation(len(data))
-        losses = []
-        for idx in order:
-            n, phi_t, samples = data[idx]
-            op.assemble(phi_t)
-            for r, eAe in samples:
-                step += 1
-                frac = min(1.0, (time.time() - t1) / budget)
-                lr = args.lr * (0.05 + 0.95 * 0.5 * (1 + math.cos(math.pi * frac)))
-                losses.append(net.train_step(op, r, eAe, lr, step))
-            if time.time() - t1 >= budget:
-                break
-        epoch += 1
-        hist.append(float(np.mean(losses)))
-        log(f"[train] epoch {epoch}: {step} steps, mean loss {hist[-1]:.4f}, "
-            f"{(time.time() - t1) / step * 1e3:.1f} ms/step")
+    per_round = args.minutes / max(1, args.rounds)
+    for rnd in range(args.rounds):
+        if rnd > 0:
+            add_onpolicy(problems, net)
+            log(f"[train] round {rnd}: {sum(len(p.samples) for p in problems)} pairs")
+        step, h = train(problems, net, per_round, args.lr if rnd == 0 else args.lr * 0.5, step, rng)
+        hist += h
     t_train = time.time() - t1
     params = net.get_params()
-    os.makedirs(os.path.dirname(args.out), exist_ok=True)
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     np.save(args.out + ".npy", params)
-    evals = evaluate(op, net, seq, test_ids[:args.eval]) if args.eval > 0 else []
-    untrained = nfa.UNet(args.nx, args.ny, args.nz, seed=args.seed)
-    ev_un = evaluate(op, untrained, seq, test_ids[:1]) if args.eval > 0 else []
-    rec = {"grid": [args.nx, args.ny, args.nz], "train_steps": train_ids, "test_steps": test_ids[:args.eval],
-           "pairs": sum(len(s) for _, _, s in data), "optimizer_steps": step, "epochs": epoch,
-           "lr": args.lr, "minutes_budget": args.minutes, "data_seconds": t_data, "train_seconds": t_train,
-           "epoch_loss": hist, "eval": evals, "eval_untrained": ev_un, "param_count": int(params.size)}
+    evals = evaluate(held, net) if args.eval > 0 else []
+    untrained = nfa.UNet(nx, ny, nz, seed=args.seed, levels=args.levels)
+    ev_un = evaluate(held[:1], untrained) if args.eval > 0 else []
+    rec = {"levels": args.levels, "grid": [nx, ny, nz], "problems": [p.name for p in problems],
+           "held_out": [p.name for p in held], "pairs": sum(len(p.samples) for p in problems),
+           "optimizer_steps": step, "rounds": args.rounds, "lr": args.lr, "minutes_budget": args.minutes,
+           "data_seconds": t_data, "train_seconds": t_train, "epoch_loss": hist, "eval": evals,
+           "eval_untrained": ev_un, "param_count": int(params.size)}
     with open(args.out + ".json", "w") as f:
         json.dump(rec, f, indent=1)
     log(f"[train] wrote {args.out}.npy and .json")

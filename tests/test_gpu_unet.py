@@ -61,7 +61,7 @@ def test_forward_layers_within_one_bf16_step(setup):
     _ulp_ok(p1, ou.bf16(ou.pool(a1)))
     a2 = _bf(net.export("a2"))
     _ulp_ok(a2, ou.bf16(ou.relu(ou.conv3d(p1, *P[2]))))
-    b2 = _bf(net.export("b2"))
+    b2 = _bf(net.export("d2"))
     _ulp_ok(b2, ou.bf16(ou.relu(ou.conv3d(a2, *P[3]))))
     d1 = _bf(net.export("d1"))
     _ulp_ok(d1, ou.bf16(ou.relu(ou.conv3d(ou.bf16(ou.up(b2) + a1), *P[4]))))
@@ -106,7 +106,7 @@ def test_gradients_loss_and_adam_match_oracle(setup):
     print(f"loss gpu {loss:.6f} oracle {Lref:.6f}")
     assert abs(loss - Lref) <= 2e-2 * max(abs(Lref), 1e-3)
     grads = ou.backward(cache, oop.dinv * dz, quant=True)
-    g = nfa.UNet.unflatten(net.get_grads())
+    g = net.unflatten(net.get_grads())
     for layer, ((gw, gb), (rw, rb)) in enumerate(zip(g, grads)):
         ew = np.linalg.norm(gw - rw) / max(np.linalg.norm(rw), 1e-30)
         eb = np.linalg.norm(gb - rb) / max(np.linalg.norm(rb), 1e-30)
@@ -119,6 +119,35 @@ def test_gradients_loss_and_adam_match_oracle(setup):
     g_flat = net.get_grads().astype(np.float64)     # same inputs -> same gradients
     expect, _, _ = ou.adam(p_before, g_flat, np.zeros_like(p_before), np.zeros_like(p_before), 1, lr=1e-3)
     assert np.max(np.abs(net.get_params() - expect)) <= 1e-6
+
+
+@pytest.mark.parametrize("levels", [4, 5])
+def test_deeper_network_forward_and_gradients(levels):
+    from paper_1410_1937_amd import nfa
+    wl = fx.small(10, 32, 16, 16, body="sphere")
+    og, ob, oop, ob_rhs = oracle_for(wl)
+    gg, gop = gpu_for(wl)
+    net = nfa.UNet(32, 16, 16, seed=2, levels=levels)
+    rng = np.random.default_rng(6)
+    params = ou.init_params(11, zero_last=False, levels=levels)
+    params = [(w.astype(np.float32), (rng.standard_normal(b.shape) * 0.05).astype(np.float32)) for w, b in params]
+    net.set_params(nfa.UNet.flatten(params))
+    params = [(w.astype(np.float64), b.astype(np.float64)) for w, b in params]
+    r = (ob_rhs * ob.reduced).astype(np.float32)
+    rt = torch.as_tensor(r, device="cuda")
+    z = host(net.forward(gop, rt)).astype(np.float64)
+    x0, s = ou.features(r.astype(np.float64), 1.0 / oop.rho, ob.reduced)
+    y, cache = ou.forward(params, x0, quant=True)
+    zref = oop.dinv * y
+    assert np.linalg.norm(z - zref) / np.linalg.norm(zref) <= 2e-2
+    e = solvers.pcg(oop, r.astype(np.float64), tol=1e-12).x
+    eAe = float(np.sum(e * r))
+    net.grad(gop, rt, eAe)
+    Lref, dz = ou.step_loss(zref, r.astype(np.float64), oop.apply(zref), eAe)
+    grads = ou.backward(cache, oop.dinv * dz, quant=True)
+    for layer, ((gw, gb), (rw, rb)) in enumerate(zip(net.unflatten(net.get_grads()), grads)):
+        ew = np.linalg.norm(gw - rw) / max(np.linalg.norm(rw), 1e-30)
+        assert ew <= 5e-2, (layer, ew)
 
 
 def test_flexible_cg_with_the_network_meets_the_judge():

@@ -50,6 +50,12 @@ def test_layer_adjoints():
     assert np.allclose(unet.pool(unet.up(x)), x)
 
 
+def test_layer_shapes_for_three_and_five_levels():
+    assert unet.shapes(3) == [(2, 16), (16, 32), (32, 64), (64, 32), (32, 16), (16, 1)]
+    assert unet.shapes(5) == [(2, 16), (16, 32), (32, 64), (64, 64), (64, 64), (64, 64), (64, 64),
+                              (64, 32), (32, 16), (16, 1)]
+
+
 def test_untrained_network_is_the_jacobi_step():
     rng = np.random.default_rng(2)
     params = unet.init_params(0, zero_last=True)
@@ -58,12 +64,13 @@ def test_untrained_network_is_the_jacobi_step():
     assert np.array_equal(y, x0[..., 0])
 
 
-def test_network_gradient_matches_finite_differences():
+@pytest.mark.parametrize("levels", [3, 4])
+def test_network_gradient_matches_finite_differences(levels):
     rng = np.random.default_rng(3)
-    params = unet.init_params(1, zero_last=False)
+    params = unet.init_params(1, zero_last=False, levels=levels)
     params = [(w, rng.standard_normal(b.shape) * 0.1) for w, b in params]
-    x0 = rng.standard_normal((8, 8, 4, 2))
-    g = rng.standard_normal((8, 8, 4))
+    x0 = rng.standard_normal((16, 8, 8, 2))
+    g = rng.standard_normal((16, 8, 8))
 
     def loss(ps):
         y, _ = unet.forward(ps, x0, quant=False)
@@ -72,7 +79,7 @@ def test_network_gradient_matches_finite_differences():
     _, cache = unet.forward(params, x0, quant=False)
     grads = unet.backward(cache, g, quant=False)
     h = 1e-6
-    for layer in range(6):
+    for layer in range(len(params)):
         w, b = params[layer]
         for _ in range(3):
             idx = tuple(rng.integers(0, s) for s in w.shape)
