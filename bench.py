@@ -11,7 +11,8 @@ body-fixed frame and is set up once, outside the timed region.
 `value` is the chosen form (mixed precision; with the learned preconditioner
 when trained weights are available); the plain FP64 Jacobi-PCG projection is
 timed beside it.  One extra, instrumented step measures the average duration
-of the dominant kernel (the stencil sweep) with HIP events for the roofline.
+of the dominant kernel (sweep A of the fused CG iteration: new direction,
+operator apply and deferred x update) with HIP events for the roofline.
 The CPU baseline is the FP64 oracle on the host cores, timed on a bounded
 sample (a few iterations on the full grid) and scaled to one projection.
 
@@ -39,6 +40,28 @@ WORKLOAD_DESC = ("512x256x192 stretched cartesian grid (25,165,824 cells), tanh 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "cg_sweeps_c3_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1410_1937_amd", "csrc", "cg.hip")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
+    summary, or None when there is none or the kernel source has changed since
+    the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"source sha256 \(paper_1410_1937_amd/csrc/cg.hip\): ([0-9a-f]{64})", text)
+    if not m or m.group(1) != sha:
+        return None
+    m = re.search(r"traffic_bytes_per_launch " + re.escape(kernel) + r": (\d+)", text)
+    return int(m.group(1)) if m else None
 
 
 def cpu_baseline(iters_fp64: int, sample_iters: int = 4) -> dict:
@@ -140,21 +163,25 @@ def main():
         ms_fp64, its_fp64, r_fp64 = timed("fp64", args.steps, args.warmup)
         log(f"[bench] plain FP64: {ms_fp64:.1f} ms/projection")
 
-    # instrumented step: average duration of the stencil sweep (dominant kernel)
+    # instrumented step: average duration of sweep A (dominant kernel)
     op.profile(True)
     step("chosen")
     ks32 = op.profile_read("f32")
     ks64 = op.profile_read("f64")
     op.profile(False)
+    # sweep A moves, per cell: z, p_old, tx, ty, tz, x read; p_new, q, x written
+    # (9 words: 36 B in FP32, 72 B in FP64); neighbour re-reads are cache hits
+    # and not counted.
     if ks32["launches"] > 0:
-        ks, bpc, kname = ks32, 20, "k_stencil<float,true>"
+        ks, bpc, kname = ks32, 36, "k_cg_a<float, 4, 1, false>"
     else:
-        ks, bpc, kname = ks64, 40, "k_stencil<double,true>"
+        wx = next((w for w in (4, 2) if wl.shape[2] % (w * 128) == 0), 1)
+        ks, bpc, kname = ks64, 72, f"k_cg_a<double, 2, {wx}, false>"
     avg_ms = ks["ms"] / max(1, ks["launches"])
     bytes_per_launch = bpc * ks["cells"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname),
                 "kernel": kname, "avg_launch_ms": round(avg_ms, 5), "launches": ks["launches"],
                 "algorithmic_bytes_per_launch": bytes_per_launch}
 
@@ -181,9 +208,10 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_DESC, "cells": n, "tol": 1e-8,
-                   "solver": ("FP64 iterative refinement around FP32 "
-                              + ("flexible CG with the learned U-Net preconditioner"
-                                 if solver["precond"] == "unet" else "Jacobi-PCG")),
+                   "solver": ("FP32 " + ("flexible CG with the learned U-Net preconditioner"
+                                         if solver["precond"] == "unet" else "Jacobi-PCG")
+                              + " with FP64 residual replacement (true residual recomputed "
+                                "in FP64 every 10x reduction)"),
                    "step": "assemble + rhs + solve + project + divergence",
                    "iterations": its_chosen[-1], "fp64_residuals": r_chosen.outer,
                    "fallback": r_chosen.fallback},

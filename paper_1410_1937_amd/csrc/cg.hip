@@ -14,16 +14,20 @@
 // textbook three-pass form.  p is double-buffered (the neighbours of a cell
 // must see the old direction).
 //
-// Launch shape of sweep A: a workgroup is 64 lanes x 4 rows; each lane owns
-// V consecutive x cells (one 16-byte vector: V = 2 doubles or 4 floats) and
-// marches up z-planes keeping the new direction of planes k-1, k, k+1 and
-// the coefficient of face k in registers.  x-neighbours across lanes come
-// from wavefront shuffles; lanes at a wavefront edge read one extra value
-// through the cache; y-neighbours are re-read through L1/L2.  The grid is
-// persistent (one workgroup per resident slot) and the (column tile, plane)
-// work is split into equal contiguous ranges, so no workgroup waits on a
-// partly filled last round; workgroup ids are remapped so that each XCD
-// owns a contiguous block of y-adjacent column tiles (shared L2 halos).
+// Launch shape of sweep A: a workgroup is a tile of WX wavefronts across x
+// by AY rows in y (WX * AY = 16 wavefronts).  Each lane owns V consecutive x
+// cells (one 16-byte vector: V = 2 doubles or 4 floats) and marches up a
+// contiguous range of z-planes keeping the new direction of planes k-1, k,
+// k+1 and the coefficient of face k in registers.  Per plane, the tile's new
+// direction and its lower y-face coefficients are exchanged through LDS
+// (double-buffered, one barrier per plane): y-neighbours inside the tile and
+// x-neighbours across wavefront edges come from LDS, x-neighbours inside a
+// wavefront from shuffles, and only the tile's outer rows and columns read
+// their neighbours through the caches.  The grid is persistent (one
+// workgroup per resident slot) and the (column tile, plane) work is split
+// into equal contiguous ranges, so no workgroup waits on a partly filled
+// last round; workgroup ids are remapped so that each XCD owns a contiguous
+// block of y-adjacent column tiles (shared L2 halos).
 // The operator sum keeps the order x-, x+, y-, y+, z-, z+ (FP contraction is
 // off), so q is bitwise the value of the plain sweep.
 #include "device_util.h"
@@ -63,26 +67,35 @@ __device__ __forceinline__ Pack<T, V> dir(const T* z, const T* po, long long c, 
   return r;
 }
 
-constexpr int AX = 64, AY = 4;
+constexpr int AX = 64;
+constexpr int kTileWaves = 16;
 
-template <class T, int V, bool FLEX>
-__global__ __launch_bounds__(AX* AY) void k_cg_a(
+template <class T, int V, int WX, bool FLEX>
+__global__ __launch_bounds__(AX* kTileWaves) void k_cg_a(
     int nx, int ny, int nz, int tiles_x, long long ncol, long long per_block,
     const T* __restrict__ z, const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ x,
     const T* __restrict__ r, const T* __restrict__ tx, const T* __restrict__ txb,
     const T* __restrict__ ty, const T* __restrict__ tz, T* __restrict__ q,
     double* __restrict__ partials, const SolveScalars* __restrict__ sc) {
+  constexpr int AY = kTileWaves / WX;
+  constexpr int TW = WX * AX;  // vectors per tile row
   if (solve_done(sc)) return;
-  __shared__ double lds[2 * AX * AY / 64];
+  __shared__ Pack<T, V> shp[2][AY][TW];  // new direction of the current plane
+  __shared__ Pack<T, V> sht[2][AY][TW];  // lower y-face coefficient of the current plane
+  __shared__ double lds[2 * kTileWaves];
   const T beta = (T)sc->beta;
   const T apend = (T)sc->alpha_pend;
   const int lane = threadIdx.x;
+  const int wx = threadIdx.y % WX, row = threadIdx.y / WX;
+  const int col = wx * AX + lane;
   const long long plane = (long long)nx * ny;
   const long long yplane = (long long)(ny + 1) * nx;
   double acc_pq = 0.0, acc_pr = 0.0;
   const long long L = xcd_remap(blockIdx.x, gridDim.x);
   long long u = L * per_block;
   const long long uend = min(ncol * nz, u + per_block);
+  // every wavefront of the workgroup walks the same (tile, plane) sequence,
+  // so the barrier below is reached the same number of times by all
   while (u < uend) {
     const long long ct = u / nz;
     const int k0 = (int)(u - ct * nz);
@@ -90,16 +103,16 @@ __global__ __launch_bounds__(AX* AY) void k_cg_a(
     u += k1 - k0;
     const int bx = (int)(ct % tiles_x);
     const int by = (int)(ct / tiles_x);
-    const int j = by * AY + threadIdx.y;
-    const int i0 = (bx * AX + lane) * V;
-    // every lane of a wavefront shares j, so this branch is uniform per wave
-    if (j >= ny) continue;
-    const bool live = i0 < nx;
+    const int j = by * AY + row;
+    const int i0 = (bx * TW + col) * V;
+    const bool live = j < ny && i0 < nx;
     long long c = (long long)k0 * plane + (long long)j * nx + i0;
     long long yi = ((long long)k0 * (ny + 1) + j) * nx + i0;
     const bool lbdy = i0 == 0, rbdy = i0 + V >= nx;
-    const bool lglob = lane == 0 && !lbdy, rglob = lane == AX - 1 && !rbdy;
+    const bool ledge = lane == 0 && !lbdy, redge = lane == AX - 1 && !rbdy;
+    const bool lglob = ledge && wx == 0, rglob = redge && wx == WX - 1;
     const bool ylo = j > 0, yhi = j < ny - 1;
+    const bool yin_lo = ylo && row > 0, yin_hi = yhi && row < AY - 1;
     Pack<T, V> pm = zero<T, V>(), pc = zero<T, V>(), poc = zero<T, V>(), tzc = zero<T, V>();
     if (live) {
       if (k0 > 0) pm = dir<T, V>(z, pold, c - plane, beta);
@@ -124,23 +137,33 @@ __global__ __launch_bounds__(AX* AY) void k_cg_a(
         tzp = ld<T, V>(tz + c + plane);
         txv = ld<T, V>(tx + c);
         tym = ld<T, V>(ty + yi);
-        typ = ld<T, V>(ty + yi + nx);
-        if (ylo) pym = dir<T, V>(z, pold, c - nx, beta);
-        if (yhi) pyp = dir<T, V>(z, pold, c + nx, beta);
+        if (!yin_hi) typ = ld<T, V>(ty + yi + nx);
+        if (ylo && row == 0) pym = dir<T, V>(z, pold, c - nx, beta);
+        if (yhi && row == AY - 1) pyp = dir<T, V>(z, pold, c + nx, beta);
         if (lglob) left = z[c - 1] + beta * pold[c - 1];
-        if (rglob) {
-          right = z[c + V] + beta * pold[c + V];
-          txr = tx[c + V];
-        } else if (rbdy) {
-          txr = txb[(long long)k * ny + j];
-        }
+        if (rglob) right = z[c + V] + beta * pold[c + V];
+        if (redge) txr = tx[c + V];
+        else if (rbdy) txr = txb[(long long)k * ny + j];
       }
-      // neighbours across lanes (all lanes take part)
+      const int b = k & 1;
+      shp[b][row][col] = pc;
+      sht[b][row][col] = tym;
+      __syncthreads();
+      if (live) {
+        if (yin_lo) pym = shp[b][row - 1][col];
+        if (yin_hi) {
+          pyp = shp[b][row + 1][col];
+          typ = sht[b][row + 1][col];
+        }
+        if (ledge && wx > 0) left = shp[b][row][col - 1].v[V - 1];
+        if (redge && wx < WX - 1) right = shp[b][row][col + 1].v[0];
+      }
+      // neighbours inside the wavefront (all lanes take part)
       const T sl = __shfl_up(pc.v[V - 1], 1, AX);
       const T sr = __shfl_down(pc.v[0], 1, AX);
       const T st0 = __shfl_down(txv.v[0], 1, AX);
-      if (!lbdy && !lglob) left = sl;
-      if (!rbdy && !rglob) {
+      if (!lbdy && !ledge) left = sl;
+      if (!rbdy && !redge) {
         right = sr;
         txr = st0;
       }
@@ -182,7 +205,7 @@ __global__ __launch_bounds__(AX* AY) void k_cg_a(
   }
   const double t0 = block_sum(acc_pq, lds);
   if (FLEX) {
-    const double t1 = block_sum(acc_pr, lds + AX * AY / 64);
+    const double t1 = block_sum(acc_pr, lds + kTileWaves);
     if (threadIdx.x == 0 && threadIdx.y == 0) partials[kMaxPartials + blockIdx.x] = t1;
   }
   if (threadIdx.x == 0 && threadIdx.y == 0) partials[blockIdx.x] = t0;
@@ -296,31 +319,51 @@ int resident_blocks(const void* fn, int threads) {
   return nb;
 }
 
+// Tile width in wavefronts for sweep A: the widest of 4, 2, 1 whose tile
+// width divides nx (FP64, where a row of 2-double vectors spans several
+// wavefronts); FP32 uses one wavefront across and 16 rows.
+template <class T> int cg_a_wx(const Grid& g, int V) {
+  if (sizeof(T) != 8 || V == 1) return 1;
+  for (int wx : {4, 2}) {
+    if (g.nx % (wx * AX * V) == 0) return wx;
+  }
+  return 1;
+}
+
 // sweep A; returns the number of workgroup partials per component
 template <class T>
 int launch_cg_a(const Grid& g, const Coeffs<T>& C, const T* z, const T* pold, T* pnew, T* x,
                 const T* r, T* q, double* partials, const SolveScalars* sc, bool flex, bool vec,
                 hipStream_t s) {
   const int V = vec ? vec_width<T>() : 1;
-  const int tiles_x = (g.nx + AX * V - 1) / (AX * V);
-  const long long ncol = (long long)tiles_x * ((g.ny + AY - 1) / AY);
-  dim3 blk(AX, AY);
+  const int wx = cg_a_wx<T>(g, V);
+  const int ay = kTileWaves / wx;
+  const int tiles_x = (g.nx + AX * wx * V - 1) / (AX * wx * V);
+  const long long ncol = (long long)tiles_x * ((g.ny + ay - 1) / ay);
+  dim3 blk(AX, kTileWaves);
   int nb = 0;
-#define CGA(TT, VV, FF)                                                                          \
+#define CGA(VV, WW, FF)                                                                          \
   do {                                                                                           \
-    const void* fn = reinterpret_cast<const void*>(&k_cg_a<TT, VV, FF>);                         \
-    nb = resident_blocks(fn, AX * AY);                                                           \
+    const void* fn = reinterpret_cast<const void*>(&k_cg_a<T, VV, WW, FF>);                      \
+    nb = resident_blocks(fn, AX * kTileWaves);                                                   \
     const long long per = (ncol * g.nz + nb - 1) / nb;                                           \
-    k_cg_a<TT, VV, FF><<<nb, blk, 0, s>>>(g.nx, g.ny, g.nz, tiles_x, ncol, per, z, pold, pnew, x, \
-                                          r, C.tx, C.txb, C.ty, C.tz, q, partials, sc);          \
+    k_cg_a<T, VV, WW, FF><<<nb, blk, 0, s>>>(g.nx, g.ny, g.nz, tiles_x, ncol, per, z, pold, pnew, \
+                                             x, r, C.tx, C.txb, C.ty, C.tz, q, partials, sc);    \
+  } while (0)
+#define CGA_W(VV, FF)              \
+  do {                             \
+    if (wx == 4) CGA(VV, 4, FF);   \
+    else if (wx == 2) CGA(VV, 2, FF); \
+    else CGA(VV, 1, FF);           \
   } while (0)
   if (vec) {
-    if (flex) CGA(T, vec_width<T>(), true);
-    else CGA(T, vec_width<T>(), false);
+    if (flex) CGA_W(vec_width<T>(), true);
+    else CGA_W(vec_width<T>(), false);
   } else {
-    if (flex) CGA(T, 1, true);
-    else CGA(T, 1, false);
+    if (flex) CGA(1, 1, true);
+    else CGA(1, 1, false);
   }
+#undef CGA_W
 #undef CGA
   return nb;
 }

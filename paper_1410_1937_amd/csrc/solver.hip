@@ -115,11 +115,12 @@ void enqueue_iter(Poisson& op, CG<T>& B, int j, int pc, void* unet, nfa_status* 
     launch_finalize(parts, nz, 1, PH_ZQ, sc, hist, st);
   }
   const int na = timed_cg_a<T>(op, B, j, flex, st);
-  launch_merge_gather<T>(g, B.q, st, sc);
-  launch_finalize(parts, na, flex ? 2 : 1, flex ? PH_PQF : PH_PQ, sc, hist, st);
+  launch_finalize_merge<T>(g, true, B.q, parts, na, flex ? 2 : 1, flex ? PH_PQF : PH_PQ, sc, hist, st);
   const int nb = launch_cg_b<T>(g, B.r, B.q, B.C.dinv, B.z, parts, sc, flex, B.vec, st);
-  if (!flex) launch_merge_copy<T>(g, B.z, st, sc);
-  launch_finalize(parts, nb, flex ? 1 : 2, flex ? PH_UPDF : PH_UPD, sc, hist, st);
+  if (flex)
+    launch_finalize(parts, nb, 1, PH_UPDF, sc, hist, st);
+  else
+    launch_finalize_merge<T>(g, false, B.z, parts, nb, 2, PH_UPD, sc, hist, st);
 }
 
 // Start (fresh) or continue (after a residual replacement) the recurrence

@@ -11,6 +11,10 @@ enum { PH_BB = 0, PH_RR = 1, PH_INIT = 2, PH_PQ = 3, PH_UPD = 4, PH_RRO = 5, PH_
 
 void launch_finalize(const double* partials, int n, int ncomp, int phase, SolveScalars* sc,
                      double* hist, hipStream_t s);
+// launch_finalize together with a merge gather (gather) or copy of v
+template <class T>
+void launch_finalize_merge(const Grid& g, bool gather, T* v, const double* partials, int n, int ncomp,
+                           int phase, SolveScalars* sc, double* hist, hipStream_t s);
 template <class T> int launch_dot(const T* a, const T* b, long long n, double* partials,
                                   const SolveScalars* sc, hipStream_t s);
 template <class T> int launch_masked_sum(const T* a, const unsigned char* mask, long long n,

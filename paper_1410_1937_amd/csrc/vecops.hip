@@ -6,6 +6,7 @@
 // floating-point atomics.  FP32 vectors accumulate their products in FP64.
 // Solver scalars (alpha, beta, norms, iteration count, convergence flag) stay
 // on the device (SolveScalars) so that iterations need no host round trip.
+#include <algorithm>
 #include <cmath>
 
 #include "device_util.h"
@@ -70,9 +71,10 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const double* partials, i
   }
 }
 
-// Finalize a reduction and advance the solver state (single workgroup).
-__global__ __launch_bounds__(1024) void k_finalize(const double* partials, int n, int ncomp, int phase,
-                                                    SolveScalars* sc, double* hist) {
+// Finalize a reduction and advance the solver state; run by one workgroup of
+// 1024 threads (every thread of that workgroup must call it).
+__device__ __forceinline__ void finalize_block(const double* partials, int n, int ncomp, int phase,
+                                               SolveScalars* sc, double* hist) {
   if (phase != PH_BB && phase != PH_RR && phase != PH_RRO && phase != PH_INIT && phase != PH_RELIABLE &&
       phase != PH_RELIABLE_F && sc->done)
     return;
@@ -86,6 +88,45 @@ __global__ __launch_bounds__(1024) void k_finalize(const double* partials, int n
     __syncthreads();
   }
   if (threadIdx.x == 0) apply_phase(phase, ncomp, val, sc, hist);
+}
+
+__global__ __launch_bounds__(1024) void k_finalize(const double* partials, int n, int ncomp, int phase,
+                                                    SolveScalars* sc, double* hist) {
+  finalize_block(partials, n, ncomp, phase, sc, hist);
+}
+
+// Workgroup 0 finalizes a reduction; the others apply a merge operation the
+// reduction does not depend on (the dots of the merged system need neither
+// the gathered q nor the copied z: slaves carry r = 0 and p equal to their
+// root's).  GATHER: v[root] += v[slaves] in ascending member order, slaves
+// set to 0.  Otherwise: v[slave] = v[root].  Both are idempotent, so the
+// merge part runs whatever the solver state says (no read of the flag the
+// finalizing workgroup may be writing).
+template <class T, bool GATHER>
+__global__ __launch_bounds__(1024) void k_finalize_merge(const double* partials, int n, int ncomp,
+                                                          int phase, SolveScalars* sc, double* hist,
+                                                          int cnt, const int* __restrict__ ia,
+                                                          const int* __restrict__ ib,
+                                                          const int* __restrict__ ic, T* v) {
+  if (blockIdx.x == 0) {
+    finalize_block(partials, n, ncomp, phase, sc, hist);
+    return;
+  }
+  const int stride = (gridDim.x - 1) * blockDim.x;
+  for (int t = (blockIdx.x - 1) * blockDim.x + threadIdx.x; t < cnt; t += stride) {
+    if (GATHER) {
+      const int r = ia[t];
+      T acc = v[r];
+      for (int m = ib[t]; m < ib[t + 1]; ++m) {
+        const int cm = ic[m];
+        acc = acc + v[cm];
+        v[cm] = T(0);
+      }
+      v[r] = acc;
+    } else {
+      v[ia[t]] = v[ib[t]];
+    }
+  }
 }
 
 template <class T>
@@ -184,6 +225,28 @@ void launch_finalize(const double* partials, int n, int ncomp, int phase, SolveS
                      double* hist, hipStream_t s) {
   k_finalize<<<1, 1024, 0, s>>>(partials, n, ncomp, phase, sc, hist);
 }
+
+template <class T>
+void launch_finalize_merge(const Grid& g, bool gather, T* v, const double* partials, int n, int ncomp,
+                           int phase, SolveScalars* sc, double* hist, hipStream_t s) {
+  const int cnt = gather ? g.n_groups : g.n_slaves;
+  if (cnt == 0) {
+    k_finalize<<<1, 1024, 0, s>>>(partials, n, ncomp, phase, sc, hist);
+    return;
+  }
+  const int mb = std::min(64, (cnt + 1023) / 1024);
+  if (gather)
+    k_finalize_merge<T, true><<<1 + mb, 1024, 0, s>>>(partials, n, ncomp, phase, sc, hist, cnt,
+                                                      g.g_root.as<int>(), g.g_off.as<int>(),
+                                                      g.g_mem.as<int>(), v);
+  else
+    k_finalize_merge<T, false><<<1 + mb, 1024, 0, s>>>(partials, n, ncomp, phase, sc, hist, cnt,
+                                                       g.s_cell.as<int>(), g.s_root.as<int>(), nullptr, v);
+}
+template void launch_finalize_merge<double>(const Grid&, bool, double*, const double*, int, int, int,
+                                            SolveScalars*, double*, hipStream_t);
+template void launch_finalize_merge<float>(const Grid&, bool, float*, const double*, int, int, int,
+                                           SolveScalars*, double*, hipStream_t);
 
 template <class T> int launch_dot(const T* a, const T* b, long long n, double* partials,
                                   const SolveScalars* sc, hipStream_t s) {

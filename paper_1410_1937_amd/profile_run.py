@@ -1,0 +1,52 @@
+"""A short, fixed workload for hardware-counter runs of the CG sweeps.
+
+Sets up the 512 x 256 x 192 breaking-wave projection problem
+(fixtures.c3), then runs a fixed number of mixed-precision and FP64
+Jacobi-PCG iterations (tolerance unreachable, so every iteration runs both
+sweeps), and finally a plain device-to-device copy of known size whose
+counter readings calibrate the FETCH_SIZE / WRITE_SIZE counters to bytes.
+Each phase prints a line when it ends.
+
+    rocprofv3 --pmc FETCH_SIZE -d OUT -- python3 -m paper_1410_1937_amd.profile_run --iters 8
+"""
+from __future__ import annotations
+
+import argparse
+import sys
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--iters", type=int, default=8, help="iterations per precision")
+    ap.add_argument("--copy-mib", type=int, default=256, help="size of the calibration copy")
+    args = ap.parse_args(argv)
+    import torch
+    from paper_1410_1937_amd import fixtures as fx
+    from paper_1410_1937_amd import nfa
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    wl = fx.c3()
+    g = nfa.Grid(wl.xf, wl.yf, wl.zf, wl.bc)
+    g.set_body(torch.as_tensor(wl.psi, device=dev), wl.theta, wl.samples)
+    op = nfa.Poisson(g)
+    op.assemble(torch.as_tensor(wl.phi, device=dev).float().contiguous(), wl.rho_l, wl.rho_g, wl.smooth)
+    b = op.rhs(*(torch.as_tensor(a, device=dev) for a in (wl.u, wl.v, wl.w)), wl.dt, wl.body_vel)
+    torch.cuda.synchronize()
+    print(f"[profile_run] set up {g.nx * g.ny * g.nz} cells", flush=True)
+    for prec in ("mixed", "f64"):
+        _, res = op.solve(b, tol=1e-30, precision=prec, max_iters=args.iters)
+        torch.cuda.synchronize()
+        print(f"[profile_run] {prec}: {res.iterations} iterations", flush=True)
+    n = args.copy_mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"[profile_run] copy: 3 x {args.copy_mib} MiB read + written", flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

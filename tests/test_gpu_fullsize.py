@@ -42,3 +42,36 @@ def test_full_size_projection(name):
         assert res.status == 0 and res.relres <= 1e-8
         tr = solvers.true_relres(oop, ob_rhs, host(p))
         assert tr <= 1.01e-8, tr
+
+
+def test_heaving_sphere_sequence_warm_started():
+    """Three consecutive projections of the 768x384x256 heaving-sphere sequence
+    (75.5M cells) in the chosen form: mixed precision, the first one with the
+    learned preconditioner behind the stagnation monitor (it runs at any grid
+    size divisible by 16), each later one warm-started from the previous
+    pressure and each judged by the oracle's own FP64 apply."""
+    import os
+    from oracle.operator import Operator
+    from paper_1410_1937_amd import nfa
+    wl = fx.c5_step(0)
+    print("[c5] building oracle geometry", flush=True)
+    og, ob, oop, ob_rhs = oracle_for(wl)
+    gg, gop = gpu_for(wl, phi_dtype=torch.float32)
+    net = nfa.UNet(*gop.shape[::-1], levels=5)
+    wpath = os.path.join(os.path.dirname(nfa.__file__), "weights", "unet_l5_hull.npy")
+    net.set_params(np.load(wpath))
+    x = torch.zeros(gop.shape, dtype=torch.float64, device="cuda")
+    for n in range(3):
+        if n > 0:
+            wl = fx.c5_step(n)
+            oop = Operator(og, ob, wl.phi, wl.rho_l, wl.rho_g, wl.smooth)
+            ob_rhs = oop.rhs(wl.u, wl.v, wl.w, wl.dt, wl.body_vel)
+            gop.assemble(torch.as_tensor(wl.phi, device="cuda").float().contiguous(), wl.rho_l, wl.rho_g, wl.smooth)
+        u, v, w = (torch.as_tensor(a, device="cuda") for a in (wl.u, wl.v, wl.w))
+        b = gop.rhs(u, v, w, wl.dt, wl.body_vel)
+        kw = dict(precond="unet", unet=net) if n == 0 else {}
+        x, res = gop.solve(b, x=x, tol=1e-8, precision="mixed", warm_start=n > 0, **kw)
+        print(f"[c5] projection {n}: {res.iterations} its, outer {res.outer}, fallback {res.fallback}, "
+              f"relres {res.relres:.3e}, {res.ms:.0f} ms", flush=True)
+        assert res.status == 0 and res.relres <= 1e-8
+        assert solvers.true_relres(oop, ob_rhs, host(x)) <= 1.01e-8

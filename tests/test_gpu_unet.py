@@ -160,3 +160,33 @@ def test_flexible_cg_with_the_network_meets_the_judge():
     x, res = gop.solve(b, tol=1e-8, precision="mixed", precond="unet", unet=net, fallback_ratio=2.0)
     assert res.status == 0 and res.relres <= 1e-8
     assert solvers.true_relres(oop, ob_rhs, host(x)) <= 1.01e-8
+
+
+def test_trained_network_gains_over_the_untrained_one_on_a_held_out_step():
+    """What the trained weights gain: on held-out step 160 of the advected-
+    surface sequence (256x128x96), the relative residual after 100 flexible-CG
+    iterations with the trained network against the untrained one (which is the
+    Jacobi step), stagnation monitor off; then the full solve with the monitor
+    on meets the FP64 judge (the trained network does not carry the solve to
+    1e-8 by itself: the monitor hands it to Jacobi-PCG)."""
+    import os
+    from paper_1410_1937_amd import nfa
+    wl = fx.c4_step(160)
+    og, ob, oop, ob_rhs = oracle_for(wl)
+    gg, gop = gpu_for(wl, phi_dtype=torch.float32)
+    b = torch.as_tensor(ob_rhs, device="cuda")
+    wpath = os.path.join(os.path.dirname(nfa.__file__), "weights", "unet_l5_hull.npy")
+    after = {}
+    for tag in ("untrained", "trained"):
+        net = nfa.UNet(256, 128, 96, levels=5)
+        if tag == "trained":
+            net.set_params(np.load(wpath))
+        _, res = gop.solve(b, tol=1e-30, precision="mixed", precond="unet", unet=net, fallback_ratio=2.0,
+                           max_iters=100, history=256)
+        after[tag] = float(res.history[-1])
+        print(f"[learned] {tag}: relres after {len(res.history) - 1} FCG iterations {after[tag]:.3e}", flush=True)
+    assert after["trained"] <= 0.2 * after["untrained"], after
+    x, res = gop.solve(b, tol=1e-8, precision="mixed", precond="unet", unet=net)
+    print(f"[learned] full solve: {res.iterations} its, fallback {res.fallback}, relres {res.relres:.3e}", flush=True)
+    assert res.status == 0 and res.relres <= 1e-8
+    assert solvers.true_relres(oop, ob_rhs, host(x)) <= 1.01e-8
