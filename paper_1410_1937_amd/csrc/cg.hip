@@ -51,6 +51,43 @@ template <class T, int V> __device__ __forceinline__ Pack<T, V> ld(const T* p) {
 template <class T, int V> __device__ __forceinline__ void st(T* p, const Pack<T, V>& a) {
   *reinterpret_cast<Pack<T, V>*>(p) = a;
 }
+// Streaming accesses of the sweeps (each element touched once per sweep) may
+// carry the non-temporal hint.  Where it pays was measured per sweep and
+// precision on the 512 x 256 x 192 grid (sweep A: loads and stores in FP32,
+// stores only in FP64; sweep B: loads in FP32, loads and stores in FP64);
+// neighbour and halo reads always use ordinary loads.
+template <bool NT, class T, int V> __device__ __forceinline__ Pack<T, V> ld_stream(const T* p) {
+  Pack<T, V> r;
+  if constexpr (!NT) {
+    r = ld<T, V>(p);
+  } else if constexpr (V == 1) {
+    r.v[0] = __builtin_nontemporal_load(p);
+  } else {
+    typedef T vt __attribute__((ext_vector_type(V)));
+    const vt a = __builtin_nontemporal_load(reinterpret_cast<const vt*>(p));
+#pragma unroll
+    for (int e = 0; e < V; ++e) r.v[e] = a[e];
+  }
+  return r;
+}
+template <bool NT, class T, int V> __device__ __forceinline__ void st_stream(T* p, const Pack<T, V>& a) {
+  if constexpr (!NT) {
+    st<T, V>(p, a);
+  } else if constexpr (V == 1) {
+    __builtin_nontemporal_store(a.v[0], p);
+  } else {
+    typedef T vt __attribute__((ext_vector_type(V)));
+    vt b;
+#pragma unroll
+    for (int e = 0; e < V; ++e) b[e] = a.v[e];
+    __builtin_nontemporal_store(b, reinterpret_cast<vt*>(p));
+  }
+}
+template <class T> struct StreamHints {
+  static constexpr bool a_load = sizeof(T) == 4, a_store = true;
+  static constexpr bool b_load = true, b_store = sizeof(T) == 8;
+};
+
 template <class T, int V> __device__ __forceinline__ Pack<T, V> zero() {
   Pack<T, V> a;
 #pragma unroll
@@ -129,14 +166,14 @@ __global__ __launch_bounds__(AX* kTileWaves) void k_cg_a(
       T left = T(0), right = T(0), txr = T(0);
       if (live) {
         if (k + 1 < nz) {
-          pop = ld<T, V>(pold + c + plane);
-          const Pack<T, V> zp = ld<T, V>(z + c + plane);
+          pop = ld_stream<StreamHints<T>::a_load, T, V>(pold + c + plane);
+          const Pack<T, V> zp = ld_stream<StreamHints<T>::a_load, T, V>(z + c + plane);
 #pragma unroll
           for (int e = 0; e < V; ++e) pp.v[e] = zp.v[e] + beta * pop.v[e];
         }
-        tzp = ld<T, V>(tz + c + plane);
-        txv = ld<T, V>(tx + c);
-        tym = ld<T, V>(ty + yi);
+        tzp = ld_stream<StreamHints<T>::a_load, T, V>(tz + c + plane);
+        txv = ld_stream<StreamHints<T>::a_load, T, V>(tx + c);
+        tym = ld_stream<StreamHints<T>::a_load, T, V>(ty + yi);
         if (!yin_hi) typ = ld<T, V>(ty + yi + nx);
         if (ylo && row == 0) pym = dir<T, V>(z, pold, c - nx, beta);
         if (yhi && row == AY - 1) pyp = dir<T, V>(z, pold, c + nx, beta);
@@ -185,14 +222,14 @@ __global__ __launch_bounds__(AX* kTileWaves) void k_cg_a(
           qv.v[e] = s;
           acc_pq += (double)p0 * (double)s;
         }
-        st<T, V>(q + c, qv);
-        st<T, V>(pnew + c, pc);
-        Pack<T, V> xv = ld<T, V>(x + c);
+        st_stream<StreamHints<T>::a_store, T, V>(q + c, qv);
+        st_stream<StreamHints<T>::a_store, T, V>(pnew + c, pc);
+        Pack<T, V> xv = ld_stream<StreamHints<T>::a_load, T, V>(x + c);
 #pragma unroll
         for (int e = 0; e < V; ++e) xv.v[e] = xv.v[e] + apend * poc.v[e];
-        st<T, V>(x + c, xv);
+        st_stream<StreamHints<T>::a_store, T, V>(x + c, xv);
         if (FLEX) {
-          const Pack<T, V> rv = ld<T, V>(r + c);
+          const Pack<T, V> rv = ld_stream<StreamHints<T>::a_load, T, V>(r + c);
 #pragma unroll
           for (int e = 0; e < V; ++e) acc_pr += (double)pc.v[e] * (double)rv.v[e];
         }
@@ -227,20 +264,20 @@ __global__ __launch_bounds__(kBlock) void k_cg_b(long long nvec, T* __restrict__
   for (long long iv = blockIdx.x * (long long)blockDim.x + threadIdx.x; iv < nvec;
        iv += (long long)gridDim.x * blockDim.x) {
     const long long c = iv * V;
-    Pack<T, V> rv = ld<T, V>(r + c);
-    const Pack<T, V> qv = ld<T, V>(q + c);
+    Pack<T, V> rv = ld_stream<StreamHints<T>::b_load, T, V>(r + c);
+    const Pack<T, V> qv = ld_stream<StreamHints<T>::b_load, T, V>(q + c);
 #pragma unroll
     for (int e = 0; e < V; ++e) rv.v[e] = rv.v[e] - alpha * qv.v[e];
-    st<T, V>(r + c, rv);
+    st_stream<StreamHints<T>::b_store, T, V>(r + c, rv);
     if (!FLEX) {
-      const Pack<T, V> dv = ld<T, V>(dinv + c);
+      const Pack<T, V> dv = ld_stream<StreamHints<T>::b_load, T, V>(dinv + c);
       Pack<T, V> zv;
 #pragma unroll
       for (int e = 0; e < V; ++e) {
         zv.v[e] = dv.v[e] * rv.v[e];
         rz += (double)rv.v[e] * (double)zv.v[e];
       }
-      st<T, V>(z + c, zv);
+      st_stream<StreamHints<T>::b_store, T, V>(z + c, zv);
     }
 #pragma unroll
     for (int e = 0; e < V; ++e) rr += (double)rv.v[e] * (double)rv.v[e];

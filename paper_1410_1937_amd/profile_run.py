@@ -5,9 +5,12 @@ Sets up the 512 x 256 x 192 breaking-wave projection problem
 Jacobi-PCG iterations (tolerance unreachable, so every iteration runs both
 sweeps), and finally a plain device-to-device copy of known size whose
 counter readings calibrate the FETCH_SIZE / WRITE_SIZE counters to bytes.
-Each phase prints a line when it ends.
+With --unet L it also runs --unet-reps forward passes of an L-level learned
+preconditioner on the same grid (the committed weights for L = 5).  Each
+phase prints a line when it ends.
 
     rocprofv3 --pmc FETCH_SIZE -d OUT -- python3 -m paper_1410_1937_amd.profile_run --iters 8
+    rocprofv3 --kernel-trace --stats -d OUT -- python3 -m paper_1410_1937_amd.profile_run --iters 0 --unet 5
 """
 from __future__ import annotations
 
@@ -19,6 +22,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--iters", type=int, default=8, help="iterations per precision")
     ap.add_argument("--copy-mib", type=int, default=256, help="size of the calibration copy")
+    ap.add_argument("--unet", type=int, default=0, help="levels of the learned preconditioner to run (0: none)")
+    ap.add_argument("--unet-reps", type=int, default=5)
     args = ap.parse_args(argv)
     import torch
     from paper_1410_1937_amd import fixtures as fx
@@ -34,10 +39,22 @@ def main(argv=None):
     b = op.rhs(*(torch.as_tensor(a, device=dev) for a in (wl.u, wl.v, wl.w)), wl.dt, wl.body_vel)
     torch.cuda.synchronize()
     print(f"[profile_run] set up {g.nx * g.ny * g.nz} cells", flush=True)
-    for prec in ("mixed", "f64"):
+    for prec in ("mixed", "f64") if args.iters > 0 else ():
         _, res = op.solve(b, tol=1e-30, precision=prec, max_iters=args.iters)
         torch.cuda.synchronize()
         print(f"[profile_run] {prec}: {res.iterations} iterations", flush=True)
+    if args.unet:
+        import os
+        import numpy as np
+        net = nfa.UNet(g.nx, g.ny, g.nz, levels=args.unet)
+        wpath = os.path.join(os.path.dirname(nfa.__file__), "weights", f"unet_l{args.unet}_hull.npy")
+        if os.path.exists(wpath):
+            net.set_params(np.load(wpath))
+        r = (b / torch.linalg.vector_norm(b)).float().contiguous()
+        for _ in range(args.unet_reps):
+            net.forward(op, r)
+        torch.cuda.synchronize()
+        print(f"[profile_run] unet L{args.unet}: {args.unet_reps} forward passes", flush=True)
     n = args.copy_mib * (1 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)

@@ -13,6 +13,12 @@ by flexible CG preconditioned with the current network (after 8, 32 and 96
 iterations), so that the network also learns the residuals it leaves
 behind, then training continues on the union.
 
+Training longer than a few epochs lowers the one-step loss but costs the
+network its use inside flexible CG (it stalls after a few iterations on
+held-out steps), so the committed weights come from a short run:
+
+    python -m paper_1410_1937_amd.train_unet --max-steps 13000 --rounds 1 --breaking 0 --stride 4 --levels 5
+
 Each training step runs nfa_unet_train_step: forward, the A-norm step loss
 1 - (z.r)^2/((z.A'z)(e.A'e)), backward and one Adam step.  The weights are
 written as a raw float32 .npy (no pickling) with a JSON record of the run.
@@ -101,22 +107,34 @@ def add_onpolicy(problems, net):
             p.add_pair(x)
 
 
-def train(problems, net, minutes, lr0, step0, rng):
+def train(problems, net, minutes, lr0, step0, rng, max_steps=0):
+    """Adam over shuffled problems for `minutes` or, when max_steps > 0, for
+    that many optimizer steps; cosine learning-rate decay over the budget."""
     budget = minutes * 60.0
     t1 = time.time()
     step, hist = step0, []
-    while time.time() - t1 < budget:
+
+    def progress():
+        if max_steps > 0:
+            return (step - step0) / max_steps
+        return (time.time() - t1) / budget
+
+    while progress() < 1.0:
         losses = []
         for idx in rng.permutation(len(problems)):
             p = problems[idx]
             p.activate()
             for r, eAe in p.samples:
+                if progress() >= 1.0:
+                    break
                 step += 1
-                frac = min(1.0, (time.time() - t1) / budget)
+                frac = min(1.0, progress())
                 lr = lr0 * (0.05 + 0.95 * 0.5 * (1 + math.cos(math.pi * frac)))
                 losses.append(net.train_step(p.op, r, eAe, lr, step))
-            if time.time() - t1 >= budget:
+            if progress() >= 1.0:
                 break
+        if not losses:
+            break
         hist.append(float(np.mean(losses)))
         log(f"[train] epoch {len(hist)}: {step} steps, mean loss {hist[-1]:.4f}, "
             f"{(time.time() - t1) / max(1, step - step0) * 1e3:.1f} ms/step")
@@ -146,6 +164,8 @@ def evaluate(problems, net, tol=1e-8):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--minutes", type=float, default=6.0, help="total training time budget")
+    ap.add_argument("--max-steps", type=int, default=0,
+                    help="total optimizer steps (replaces the time budget when > 0)")
     ap.add_argument("--rounds", type=int, default=3, help="training phases (the first without on-policy pairs)")
     ap.add_argument("--hull-steps", type=int, default=160)
     ap.add_argument("--stride", type=int, default=4, help="use every stride-th hull time step")
@@ -191,7 +211,8 @@ def main(argv=None):
         if rnd > 0:
             add_onpolicy(problems, net)
             log(f"[train] round {rnd}: {sum(len(p.samples) for p in problems)} pairs")
-        step, h = train(problems, net, per_round, args.lr if rnd == 0 else args.lr * 0.5, step, rng)
+        step, h = train(problems, net, per_round, args.lr if rnd == 0 else args.lr * 0.5, step, rng,
+                        args.max_steps // max(1, args.rounds))
         hist += h
     t_train = time.time() - t1
     params = net.get_params()
@@ -203,6 +224,8 @@ def main(argv=None):
     rec = {"levels": args.levels, "grid": [nx, ny, nz], "problems": [p.name for p in problems],
            "held_out": [p.name for p in held], "pairs": sum(len(p.samples) for p in problems),
            "optimizer_steps": step, "rounds": args.rounds, "lr": args.lr, "minutes_budget": args.minutes,
+           "max_steps": args.max_steps, "stride": args.stride, "hull_steps": args.hull_steps,
+           "breaking": args.breaking,
            "data_seconds": t_data, "train_seconds": t_train, "epoch_loss": hist, "eval": evals,
            "eval_untrained": ev_un, "param_count": int(params.size)}
     with open(args.out + ".json", "w") as f:
