@@ -13,13 +13,17 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.mark.parametrize("name", ["c2", "c3"])
-def test_full_size_projection(name):
+@pytest.mark.parametrize("name,phi_dtype", [("c2", "float64"), ("c3", "float32")])
+def test_full_size_projection(name, phi_dtype):
+    """The 25M-cell case holds phi in FP32, as the benchmark does; the oracle
+    gets the same FP32-representable values."""
     wl = getattr(fx, name)()
+    if phi_dtype == "float32":
+        wl.phi = wl.phi.astype(np.float32).astype(np.float64)
     print(f"[{name}] building oracle", flush=True)
     og, ob, oop, ob_rhs = oracle_for(wl)
     print(f"[{name}] building GPU operator", flush=True)
-    gg, gop = gpu_for(wl, phi_dtype=torch.float64)
+    gg, gop = gpu_for(wl, phi_dtype=getattr(torch, phi_dtype))
     for item, ref in (("frac_x", ob.frac_x), ("vfrac", ob.vfrac), ("open_y", ob.open_y),
                       ("open_z", ob.open_z)):
         assert np.array_equal(host(gg.export(item)), ref), item

@@ -26,6 +26,9 @@ def _cases():
         "nobody_uniform_all_dirichlet": fx.small(2, 33, 7, 5, body=None, bc=(1,) * 6, stretch=False,
                                                  smooth=False),
         "c1": fx.c1(),
+        # three FP32 column tiles across x (the last 8 cells wide), five FP64
+        # ones, and a partial 16-row tile in y
+        "wide_ragged": fx.small(6, 520, 18, 9, body="sphere"),
     }
 
 
@@ -215,3 +218,40 @@ def test_float32_phi_input():
     og, ob, oop, _ = oracle_for(wl)
     gg, gop = gpu_for(wl, phi_dtype=torch.float32)
     assert np.array_equal(host(gop.export("tz")), oop.tz)
+
+
+def test_zero_rhs_and_a_single_column():
+    """Degenerate inputs: a zero right-hand side returns x = 0 at once; a
+    1 x 1 x 64 column (one lane live in every sweep) with the 1000 : 1.2 jump,
+    Neumann bottom and Dirichlet top, solved against a banded direct solve of
+    the oracle's own matrix."""
+    from scipy.linalg import solve_banded
+    from oracle.geometry import Body
+    from oracle.grid import Grid
+    from oracle.operator import Operator
+    from paper_1410_1937_amd import nfa
+    nz = 64
+    xf = yf = np.array([0.0, 1.0])
+    zf = fx.stretched_faces(0.0, 1.0, nz, [0.5])
+    phi = (fx.centres(zf) < 0.5).astype(np.float64).reshape(nz, 1, 1)
+    bc = (0, 0, 0, 0, 0, 1)
+    g = nfa.Grid(xf, yf, zf, bc)
+    g.set_body(None)
+    op = nfa.Poisson(g)
+    op.assemble(torch.as_tensor(phi, device="cuda"), 1000.0, 1.2, False)
+    for precision in ("f64", "mixed"):
+        x, res = op.solve(torch.zeros((nz, 1, 1), dtype=torch.float64, device="cuda"), precision=precision)
+        assert res.status == 0 and res.iterations == 0 and res.relres == 0.0
+        assert not torch.any(x)
+    og = Grid(xf, yf, zf, bc)
+    oop = Operator(og, Body(og, None, 0.25, 8), phi, 1000.0, 1.2, False)
+    A = oop.csr().toarray()
+    ab = np.zeros((3, nz))
+    ab[0, 1:] = np.diag(A, 1)
+    ab[1] = np.diag(A)
+    ab[2, :-1] = np.diag(A, -1)
+    b = np.random.default_rng(8).standard_normal(nz)
+    ref = solve_banded((1, 1), ab, b)
+    x, res = op.solve(torch.as_tensor(b.reshape(nz, 1, 1), device="cuda"), tol=1e-12, precision="f64")
+    assert res.status == 0 and res.relres <= 1e-12
+    assert rel_l2(host(x).ravel(), ref) <= 1e-9
