@@ -265,6 +265,63 @@ nfa_status nfa_poisson_residual(nfa_poisson op, const double* b, const double* x
 nfa_status nfa_poisson_export(nfa_poisson op, int what, void* dst, nfa_stream s); /* ASYNC */
 void nfa_poisson_destroy(nfa_poisson op);
 
+/* ------------------------------------------------------------------------
+ * The Runge-Kutta projection cycle around the solve (Numerical Time
+ * Integration, eqs. poisson1, runge1, poisson2, runge2).  Velocities live on
+ * faces: x-faces [nz][ny][nx+1], y-faces [nz][ny+1][nx], z-faces
+ * [nz+1][ny][nx], DEVICE doubles.
+ * ------------------------------------------------------------------------ */
+
+/* nfa_poisson_velocity -- velocity form of eqs. runge1 / runge2 on every face:
+ *   u = scale * (u~ - dt * (g * (p+ - p-))),   g = beta_f / h_f,
+ * beta_f = 2/(rho_L + rho_R) inside and 1/rho_c with the half width on a
+ * Dirichlet boundary face (p = 0 beyond it), with rho of the last assembly;
+ * g = 0 on Neumann boundary faces and on closed faces (zero open area), which
+ * keep scale * u~.
+ *   ut_x, ut_y, ut_z : DEVICE provisional velocity (may alias the outputs).
+ *   p                : DEVICE double cells; read as P p (slaves take their
+ *                      root's value).
+ *   dt > 0; scale finite (1 for stage 1, 1/2 for stage 2).
+ *   u_x, u_y, u_z    : DEVICE outputs.   ASYNC.
+ * Errors: NFA_ERR_INVALID (NULL, not assembled, dt <= 0). */
+nfa_status nfa_poisson_velocity(nfa_poisson op, const double* ut_x, const double* ut_y,
+                                const double* ut_z, const double* p, double dt, double scale,
+                                double* u_x, double* u_y, double* u_z, nfa_stream s);
+
+/* nfa_faces_combine -- out = (a + b) + s * c on n DEVICE doubles, or a + s * c
+ * when b is NULL: the provisional fields u~1 = u^k + dt R and
+ * u~2 = (u* + u^k) + dt R.  out may alias a or b.  ASYNC. */
+nfa_status nfa_faces_combine(long long n, const double* a, const double* b, double s,
+                             const double* c, double* out, nfa_stream st);
+
+typedef struct {
+  double dt;                 /* time step > 0 */
+  double body_vel[3];        /* body velocity (body-fixed frame): stage 1 uses v,
+                                stage 2 the flux of 2v (u~2 sums two fields) */
+  nfa_assemble_params rho;   /* densities, smoothing, dtype of phi_k and phi_star */
+} nfa_rk2_params;
+
+/* nfa_rk2_cycle -- one cycle: assemble with phi_k; u~1 = u^k + dt R; solve
+ * for P*; u* = u~1 - dt beta grad P*; assemble with phi_star (the advected
+ * volume fraction, an input); u~2 = (u* + u^k) + dt R; solve for P;
+ * u^{k+1} = (u~2 - dt beta grad P) / 2.
+ *   phi_k, phi_star : DEVICE cells of rho->phi_dtype.
+ *   uk, R           : three DEVICE face arrays each (x, y, z faces).
+ *   ut              : three DEVICE face arrays of workspace (caller-owned).
+ *   ustar, unext    : three DEVICE face arrays each, outputs u* and u^{k+1}.
+ *   pstar, p        : DEVICE double cells, outputs P* and P (also the warm
+ *                     starts when opts->warm_start).
+ *   opts            : solve options of both stages.
+ *   info            : HOST, two entries (stage 1, stage 2).
+ * Leaves the operator assembled with phi_star.  Synchronous.  Returns the
+ * worse of the two solves' statuses (NFA_NOT_CONVERGED is a warning) or the
+ * first error. */
+nfa_status nfa_rk2_cycle(nfa_poisson op, const void* phi_k, const void* phi_star,
+                         const nfa_rk2_params* prm, const double* const* uk, const double* const* R,
+                         double* const* ut, double* const* ustar, double* pstar, double* p,
+                         double* const* unext, const nfa_solve_opts* opts, nfa_stream s,
+                         nfa_solve_info* info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -302,13 +302,15 @@ def c2(seed: int = 0, nx=256, ny=128, nz=96, t: float = 0.0, rhs_seed=None) -> W
     return Workload("c2", xf, yf, zf, ALL_NEUMANN, phi, psi, 0.1, True, u=u, v=v, w=w)
 
 
-def c3(seed: int = 1, nx=512, ny=256, nz=192) -> Workload:
+def c3(seed: int = 1, nx=512, ny=256, nz=192, t: float = 0.0) -> Workload:
+    """Breaking-wave workload; t > 0 moves the surface and the droplets by t in
+    x (the advected volume fraction of a later time)."""
     xf, yf, zf = _grid(nx, ny, nz, [-0.1, 0.1], [0.0], [0.0, -0.15])
     modes = surface_modes(seed)
-    e = eta(centres(xf), centres(yf), modes)
+    e = eta(centres(xf), centres(yf), modes, shift=t)
     phi = vof_from_surface(xf, yf, zf, e)
     phi = add_droplets(phi, xf, yf, zf, lambda x, y: eta(x, y, modes), seed,
-                       body=((0.0, 0.0, -0.15), 0.1))
+                       body=((0.0, 0.0, -0.15), 0.1), shift=(t, 0.0, 0.0))
     psi = psi_sphere(xf, yf, zf)
     u, v, w = face_velocity(xf, yf, zf, seed)
     return Workload("c3", xf, yf, zf, ALL_NEUMANN, phi, psi, 0.25, True, u=u, v=v, w=w)

@@ -68,6 +68,10 @@ class SolveInfo(ctypes.Structure):
                 ("history_len", c_int), ("relres", c_double), ("ms", c_double)]
 
 
+class RK2Params(ctypes.Structure):
+    _fields_ = [("dt", c_double), ("body_vel", c_double * 3), ("rho", AssembleParams)]
+
+
 class KernelStats(ctypes.Structure):
     _fields_ = [("launches", c_ll), ("ms", c_double), ("cells", c_ll)]
 
@@ -116,6 +120,25 @@ _sig("nfa_unet_train_step", c_int, [c_void_p, c_void_p, c_void_p, c_double, ctyp
 _sig("nfa_unet_export", c_int, [c_void_p, c_int, c_void_p, c_void_p])
 _sig("nfa_unet_destroy", None, [c_void_p])
 _sig("nfa_poisson_profile_read", c_int, [c_void_p, c_int, ctypes.POINTER(KernelStats)])
+_sig("nfa_poisson_velocity", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_double,
+                                     c_void_p, c_void_p, c_void_p, c_void_p])
+_sig("nfa_faces_combine", c_int, [c_ll, c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p])
+_sig("nfa_rk2_cycle", c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(RK2Params),
+                              ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
+                              ctypes.POINTER(c_void_p), c_void_p, c_void_p, ctypes.POINTER(c_void_p),
+                              ctypes.POINTER(SolveOpts), c_void_p, ctypes.POINTER(SolveInfo)])
+
+
+def faces_combine(a, b, s, c, out=None):
+    """out = (a + b) + s c, or a + s c when b is None (nfa_faces_combine)."""
+    out = torch.empty_like(a) if out is None else out
+    n = a.numel()
+    for name, t in (("a", a), ("c", c), ("out", out)) + ((("b", b),) if b is not None else ()):
+        _dev(t, torch.float64, a.shape, name)
+    _check(lib.nfa_faces_combine(n, c_void_p(a.data_ptr()), None if b is None else c_void_p(b.data_ptr()),
+                                 s, c_void_p(c.data_ptr()), c_void_p(out.data_ptr()), _stream()),
+           "nfa_faces_combine")
+    return out
 
 
 def _check(st, what):
@@ -294,6 +317,56 @@ class Poisson:
                                         _dev(r, torch.float64, self.shape, "r"), ctypes.byref(rr), _stream()),
                "nfa_poisson_residual")
         return r, rr.value
+
+    def velocity(self, ut, p, dt=1.0, scale=1.0):
+        """Velocity form of the projection on the three face sets:
+        scale * (u~ - dt beta grad p), closed and Neumann faces keep scale * u~."""
+        g = self.grid
+        shapes = [g.face_shape(a) for a in range(3)]
+        ins = [_dev(t, torch.float64, sh, f"ut[{a}]") for a, (t, sh) in enumerate(zip(ut, shapes))]
+        out = [torch.empty(sh, dtype=torch.float64, device="cuda") for sh in shapes]
+        _check(lib.nfa_poisson_velocity(self.h, *ins, _dev(p, torch.float64, self.shape, "p"), dt, scale,
+                                        *[_dev(o, torch.float64) for o in out], _stream()),
+               "nfa_poisson_velocity")
+        return tuple(out)
+
+    def rk2_cycle(self, phi_k, phi_star, uk, R, dt, body_vel=(0.0, 0.0, 0.0), rho_l=1000.0, rho_g=1.2,
+                  smooth=True, tol=1e-8, precision="f64", precond="jacobi", max_iters=200000,
+                  pstar=None, p=None, warm_start=False, unet=None):
+        """One Runge-Kutta projection cycle (nfa_rk2_cycle).  Returns a dict with
+        u* ('ustar'), u^{k+1} ('unext'), the pressures 'pstar' and 'p', and the
+        two stages' SolveResult.  Leaves the operator assembled with phi_star."""
+        g = self.grid
+        if phi_k.dtype != phi_star.dtype or phi_k.dtype not in (torch.float64, torch.float32):
+            raise TypeError("phi_k and phi_star must share a float64 or float32 dtype")
+        dtp = NFA_F64 if phi_k.dtype == torch.float64 else NFA_F32
+        shapes = [g.face_shape(a) for a in range(3)]
+        trip = lambda ts, name: (c_void_p * 3)(*[_dev(t, torch.float64, sh, f"{name}[{a}]")
+                                                 for a, (t, sh) in enumerate(zip(ts, shapes))])
+        ut = [torch.empty(sh, dtype=torch.float64, device="cuda") for sh in shapes]
+        ustar = [torch.empty(sh, dtype=torch.float64, device="cuda") for sh in shapes]
+        unext = [torch.empty(sh, dtype=torch.float64, device="cuda") for sh in shapes]
+        pstar = torch.zeros(self.shape, dtype=torch.float64, device="cuda") if pstar is None else pstar
+        p = torch.zeros(self.shape, dtype=torch.float64, device="cuda") if p is None else p
+        prm = RK2Params(dt, (c_double * 3)(*body_vel), AssembleParams(rho_l, rho_g, 1 if smooth else 0, dtp))
+        o = SolveOpts()
+        lib.nfa_solve_opts_default(ctypes.byref(o))
+        o.tol = tol
+        o.max_iters = max_iters
+        o.precision = {"f64": NFA_PREC_F64, "mixed": NFA_PREC_MIXED}[precision]
+        o.precond = {"jacobi": NFA_PC_JACOBI, "unet": NFA_PC_UNET, "jacobi_fcg": NFA_PC_JACOBI_FCG}[precond]
+        o.warm_start = 1 if warm_start else 0
+        o.unet = None if unet is None else unet.h
+        info = (SolveInfo * 2)()
+        st = _check(lib.nfa_rk2_cycle(self.h, _dev(phi_k, phi_k.dtype, self.shape, "phi_k"),
+                                      _dev(phi_star, phi_star.dtype, self.shape, "phi_star"), ctypes.byref(prm),
+                                      trip(uk, "uk"), trip(R, "R"), trip(ut, "ut"), trip(ustar, "ustar"),
+                                      _dev(pstar, torch.float64, self.shape, "pstar"),
+                                      _dev(p, torch.float64, self.shape, "p"), trip(unext, "unext"),
+                                      ctypes.byref(o), _stream(), info), "nfa_rk2_cycle")
+        res = [SolveResult(st, i.iterations, i.outer, bool(i.fallback), i.relres, i.ms) for i in info]
+        return {"ustar": tuple(ustar), "unext": tuple(unext), "pstar": pstar, "p": p, "ut2": tuple(ut),
+                "stage1": res[0], "stage2": res[1], "status": st}
 
     def profile(self, enable=True):
         _check(lib.nfa_poisson_profile(self.h, 1 if enable else 0), "nfa_poisson_profile")
