@@ -184,7 +184,7 @@ nfa_status nfa_poisson_divergence(nfa_poisson op, const double* fu, const double
                                   (reference run of the flexible path) */
 #define NFA_PREC_F64 0   /* FP64 Jacobi-PCG */
 #define NFA_PREC_MIXED 1 /* FP32 CG recurrence, FP64 solution and residual
-                            replacement (the FP64 residual is the judge) */
+                            replacement (the FP64 residual decides) */
 
 typedef struct {
   double tol;            /* FP64 true relative residual ||b'-A'x||/||b'|| */
@@ -244,8 +244,8 @@ nfa_status nfa_poisson_profile(nfa_poisson op, int enable);
 /* dtype NFA_F64 or NFA_F32: the sweep of that precision.  Synchronous. */
 nfa_status nfa_poisson_profile_read(nfa_poisson op, int dtype, nfa_kernel_stats* out);
 
-/* nfa_poisson_residual -- r = b' - A'x in FP64 (the true residual the
- * solver's judge uses); x is read as P x (slaves take their root's value).
+/* nfa_poisson_residual -- r = b' - A'x in FP64 (the true residual that
+ * decides convergence); x is read as P x (slaves take their root's value).
  *   b, x, r : DEVICE double cells; r may not alias x.
  *   rr      : HOST out, ||r||^2 over the unknowns (NULL: not computed).
  * Synchronous when rr is given, else ASYNC. */

@@ -4,7 +4,7 @@
  * Not a method of the paper: the paper's projection uses a preconditioned
  * conjugate-gradient solver with an unnamed preconditioner (Introduction);
  * this network is an optional preconditioner of the flexible-CG variant of
- * that solve (NFA_PC_UNET), judged by the same FP64 true residual and backed
+ * that solve (NFA_PC_UNET), held to the same FP64 true residual and backed
  * by Jacobi-PCG.
  *
  * Network (channels-last BF16 activations, FP32 accumulation, 3x3x3

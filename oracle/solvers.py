@@ -102,7 +102,7 @@ def fcg(op, b, precond, x0=None, tol=1e-8, maxit=100000, m=1, ratio=0.99, window
         fallback=True):
     """Flexible CG (Notay FCG(m)) with an arbitrary preconditioner callable
     z = precond(r) (cell arrays), a stagnation fallback to Jacobi-PCG, and a
-    true-residual judge."""
+    true-residual check."""
     b = np.asarray(b, dtype=np.float64)
     bnorm = norm(b)
     x = np.zeros_like(b) if x0 is None else op.expand(np.array(x0, dtype=np.float64))

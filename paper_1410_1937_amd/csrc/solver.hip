@@ -10,8 +10,7 @@
 //    refinement without restarting the Krylov recurrence);
 //  * flexible CG (Notay FCG(1)) for a nonlinear preconditioner such as the
 //    learned one, with a stagnation monitor that switches to Jacobi-PCG.
-// Every solve ends when the FP64 true relative residual meets tol (the
-// judge).
+// Every solve ends when the FP64 true relative residual meets tol.
 //
 // The host only enqueues kernels: alpha, beta, norms, the iteration count
 // and the convergence flag live on the device, every kernel exits at once
@@ -162,7 +161,7 @@ void copy_history(Poisson& op, const nfa_solve_opts* o, nfa_solve_info* info, in
 // iteration runs in FP32 on the scaled residual; whenever the recursive
 // residual has dropped by `delta` (or the recursion ends) the FP32 solution
 // increment is folded into the FP64 solution, the FP64 true residual
-// b' - A'x is recomputed (the judge) and replaces the FP32 one, and CG goes
+// b' - A'x is recomputed and replaces the FP32 one, and CG goes
 // on with the same search direction.
 template <class T>
 nfa_status cg_solve(Poisson& op, const double* b, double* x64, const nfa_solve_opts* o,
@@ -228,7 +227,7 @@ nfa_status cg_solve(Poisson& op, const double* b, double* x64, const nfa_solve_o
       slot ^= 1;
       continue;
     }
-    // ---- residual replacement (the FP64 judge)
+    // ---- residual replacement (FP64 true residual)
     if ((e = read_scalars(op, st, &S)) != NFA_OK) return e;
     harvest_profile(op, S.iter - last_harvest);
     last_harvest = S.iter;

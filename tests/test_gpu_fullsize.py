@@ -53,7 +53,7 @@ def test_heaving_sphere_sequence_warm_started():
     (75.5M cells) in the chosen form: mixed precision, the first one with the
     learned preconditioner behind the stagnation monitor (it runs at any grid
     size divisible by 16), each later one warm-started from the previous
-    pressure and each judged by the oracle's own FP64 apply."""
+    pressure and each checked by the oracle's own FP64 apply."""
     import os
     from oracle.operator import Operator
     from paper_1410_1937_amd import nfa

@@ -112,7 +112,7 @@ def _gpu_b(wl, gop):
 
 
 def test_fp64_solve_matches_oracle_at_relres_1e10(case):
-    """Spec bar: rel L2 <= 1e-9 against the oracle solved tightly."""
+    """rel L2 <= 1e-9 against the oracle solved tightly (to 1e-13)."""
     name, wl, (og, ob, oop, ob_rhs), (gg, gop) = case
     ref = solvers.pcg(oop, ob_rhs, tol=1e-13)
     xr = oop.gauge(ref.x)
@@ -128,7 +128,7 @@ def test_fp64_solve_matches_oracle_at_relres_1e10(case):
     assert abs(res.iterations - it_or) <= max(3, 0.05 * it_or)
 
 
-def test_mixed_solve_meets_fp64_judge(case):
+def test_mixed_solve_meets_fp64_tolerance(case):
     name, wl, (og, ob, oop, ob_rhs), (gg, gop) = case
     b = _gpu_b(wl, gop)
     x, res = gop.solve(b, tol=1e-8, precision="mixed")

@@ -1,6 +1,6 @@
 """The Runge-Kutta projection cycle on the GPU against the oracle (needs an
 MI355X): the face-array combination and the velocity update bitwise, the
-whole cycle to the solve tolerances, and a full-size cycle judged by the
+whole cycle to the solve tolerances, and a full-size cycle checked by the
 oracle's own operators."""
 import numpy as np
 import pytest
@@ -78,8 +78,8 @@ def test_cycle_matches_oracle():
 def test_full_size_cycle_on_the_hull_sequence():
     """Steps 40 -> 41 of the advected-surface sequence (256 x 128 x 96), mixed
     precision, checked step by step from the seeded inputs: stage 1 meets the
-    FP64 judge of the oracle's operator; u* is the velocity update of that P*;
-    u~2 is (u* + u^k) + dt R; P meets the judge for that u~2 and u^{k+1} is its
+    FP64 tolerance under the oracle's operator; u* is the velocity update of that P*;
+    u~2 is (u* + u^k) + dt R; P meets it for that u~2 and u^{k+1} is its
     halved update, discretely solenoidal."""
     seq = fx.C4Sequence()
     wl = fx.c4_step(40)

@@ -150,7 +150,7 @@ def test_deeper_network_forward_and_gradients(levels):
         assert ew <= 5e-2, (layer, ew)
 
 
-def test_flexible_cg_with_the_network_meets_the_judge():
+def test_flexible_cg_with_the_network_meets_the_fp64_tolerance():
     from paper_1410_1937_amd import nfa
     wl = fx.small(9, 32, 24, 16, body="sphere")
     og, ob, oop, ob_rhs = oracle_for(wl)
@@ -167,7 +167,7 @@ def test_trained_network_gains_over_the_untrained_one_on_a_held_out_step():
     surface sequence (256x128x96), the relative residual after 100 flexible-CG
     iterations with the trained network against the untrained one (which is the
     Jacobi step), stagnation monitor off; then the full solve with the monitor
-    on meets the FP64 judge (the trained network does not carry the solve to
+    on meets the FP64 tolerance (the trained network does not carry the solve to
     1e-8 by itself: the monitor hands it to Jacobi-PCG).  The gain belongs to
     these weights: rerunning their training recipe does not reliably give a
     network that keeps it inside flexible CG."""
