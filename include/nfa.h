@@ -288,6 +288,29 @@ nfa_status nfa_poisson_velocity(nfa_poisson op, const double* ut_x, const double
                                 const double* ut_z, const double* p, double dt, double scale,
                                 double* u_x, double* u_y, double* u_z, nfa_stream s);
 
+/* nfa_poisson_rhs_cells -- nfa_poisson_rhs with a body velocity that varies
+ * from cell to cell (the integral of v* . n over the body surface in eq.
+ * integral2, for rotating or deforming bodies): B_c = v_c . S_c.
+ *   vbx, vby, vbz : DEVICE double cells, body velocity per cell (read only on
+ *                   cells the body cuts).  Other arguments as nfa_poisson_rhs.
+ * ASYNC. */
+nfa_status nfa_poisson_rhs_cells(nfa_poisson op, const double* u, const double* v,
+                                 const double* w, double dt, const double* vbx, const double* vby,
+                                 const double* vbz, double* b, nfa_stream s);
+
+/* nfa_exit_velocity -- the exit condition of the Radiation Conditions section
+ * (eqs. orlanski, exit): on the outflow plane (the +x boundary x-faces),
+ *   ut_x = u_e - ((uc dt) / dx) (u_e - u_i)
+ * with u_e, u_i the x-velocities of uk_x on the exit face and one cell inward
+ * and dx the width of the last cell: the upwind step of du/dt + uc du/dx = 0.
+ * The result is the exit face's provisional velocity; its flux enters the
+ * right-hand side through nfa_poisson_rhs like any face flux, the face being a
+ * Neumann face of the pressure.  Only the exit plane of ut_x is written.
+ *   uk_x, ut_x : DEVICE double x-faces [nz][ny][nx+1] (may alias).
+ *   0 <= uc dt <= dx (Courant number at most 1), dt > 0, nx >= 2.   ASYNC. */
+nfa_status nfa_exit_velocity(nfa_grid g, const double* uk_x, double uc, double dt, double* ut_x,
+                             nfa_stream s);
+
 /* nfa_faces_combine -- out = (a + b) + s * c on n DEVICE doubles, or a + s * c
  * when b is NULL: the provisional fields u~1 = u^k + dt R and
  * u~2 = (u* + u^k) + dt R.  out may alias a or b.  ASYNC. */

@@ -152,9 +152,11 @@ __global__ void k_dinv_groups(int nx, int ny, int nz, int ng, const int* g_root,
 }
 
 // b = -((D F~) + B)/dt on active cells, 0 elsewhere
+// (vbx, vby, vbz: per-cell body velocity, or NULL for the uniform (vx, vy, vz))
 __global__ void k_rhs(int nx, int ny, int nz, const double* ox, const double* oy, const double* oz,
                       const double* u, const double* v, const double* w, double dt, double vx,
-                      double vy, double vz, const unsigned char* act, double* b) {
+                      double vy, double vz, const double* vbx, const double* vby, const double* vbz,
+                      const unsigned char* act, double* b) {
   const long long n = (long long)nx * ny * nz;
   const long long plane = (long long)nx * ny;
   GRID_STRIDE(c, n) {
@@ -171,7 +173,7 @@ __global__ void k_rhs(int nx, int ny, int nz, const double* ox, const double* oy
     const double sx = -(ox[fx + 1] - ox[fx]);
     const double sy = -(oy[fy + nx] - oy[fy]);
     const double sz = -(oz[fz + plane] - oz[fz]);
-    const double B = (vx * sx + vy * sy) + vz * sz;
+    const double B = vbx ? (vbx[c] * sx + vby[c] * sy) + vbz[c] * sz : (vx * sx + vy * sy) + vz * sz;
     b[c] = act[c] ? -(div + B) / dt : 0.0;
   }
 }
@@ -394,17 +396,18 @@ extern "C" nfa_status nfa_poisson_apply(nfa_poisson op, const void* x, void* y, 
   return NFA_OK;
 }
 
-extern "C" nfa_status nfa_poisson_rhs(nfa_poisson op, const double* u, const double* v,
-                                      const double* w, double dt, const double* vel, double* b,
-                                      nfa_stream s) {
-  if (!op || !u || !v || !w || !b) return fail(NFA_ERR_INVALID, "nfa_poisson_rhs: NULL argument");
-  if (!(dt > 0)) return fail(NFA_ERR_INVALID, "nfa_poisson_rhs: dt must be > 0");
+namespace {
+nfa_status rhs_impl(nfa_poisson op, const double* u, const double* v, const double* w, double dt,
+                    const double* vel, const double* vbx, const double* vby, const double* vbz,
+                    double* b, nfa_stream s, const char* who) {
+  if (!op || !u || !v || !w || !b) return fail(NFA_ERR_INVALID, std::string(who) + ": NULL argument");
+  if (!(dt > 0)) return fail(NFA_ERR_INVALID, std::string(who) + ": dt must be > 0");
   Grid& g = *op->g;
   const hipStream_t st = S(s);
   const double vx = vel ? vel[0] : 0.0, vy = vel ? vel[1] : 0.0, vz = vel ? vel[2] : 0.0;
   k_rhs<<<blocks_for(g.n), kBlock, 0, st>>>(g.nx, g.ny, g.nz, g.open_x.as<double>(),
                                             g.open_y.as<double>(), g.open_z.as<double>(), u, v, w, dt,
-                                            vx, vy, vz, g.active.as<unsigned char>(), b);
+                                            vx, vy, vz, vbx, vby, vbz, g.active.as<unsigned char>(), b);
   launch_merge_gather<double>(g, b, st, nullptr);
   if (g.all_neumann() && g.n_reduced > 0) {
     double* parts = op->partials.as<double>();
@@ -415,6 +418,21 @@ extern "C" nfa_status nfa_poisson_rhs(nfa_poisson op, const double* u, const dou
   }
   NFA_CHECK_LAUNCH();
   return NFA_OK;
+}
+}  // namespace
+
+extern "C" nfa_status nfa_poisson_rhs(nfa_poisson op, const double* u, const double* v,
+                                      const double* w, double dt, const double* vel, double* b,
+                                      nfa_stream s) {
+  return rhs_impl(op, u, v, w, dt, vel, nullptr, nullptr, nullptr, b, s, "nfa_poisson_rhs");
+}
+
+extern "C" nfa_status nfa_poisson_rhs_cells(nfa_poisson op, const double* u, const double* v,
+                                            const double* w, double dt, const double* vbx,
+                                            const double* vby, const double* vbz, double* b,
+                                            nfa_stream s) {
+  if (!vbx || !vby || !vbz) return fail(NFA_ERR_INVALID, "nfa_poisson_rhs_cells: NULL body velocity");
+  return rhs_impl(op, u, v, w, dt, nullptr, vbx, vby, vbz, b, s, "nfa_poisson_rhs_cells");
 }
 
 extern "C" nfa_status nfa_poisson_project(nfa_poisson op, const double* u, const double* v,

@@ -102,6 +102,15 @@ __global__ void k_combine(long long n, const double* a, const double* b, double 
   }
 }
 
+// exit plane (x-face nx) of ut: the upwind update of uk there, u_e - c (u_e - u_i)
+__global__ void k_exit(int nx, long long nrow, const double* __restrict__ uk, double c, double* ut) {
+  GRID_STRIDE(r, nrow) {
+    const long long f = r * (nx + 1) + nx;
+    const double ue = uk[f], ui = uk[f - 1];
+    ut[f] = ue - c * (ue - ui);
+  }
+}
+
 bool three(const void* const* v) { return v && v[0] && v[1] && v[2]; }
 
 }  // namespace
@@ -132,6 +141,19 @@ extern "C" nfa_status nfa_poisson_velocity(nfa_poisson op, const double* ut_x, c
       g.nx, g.ny, g.nz, bc, op->rho.as<double>(), g.open_x.as<double>(), g.open_y.as<double>(),
       g.open_z.as<double>(), g.d_hx.as<double>(), g.d_hy.as<double>(), g.d_hz.as<double>(), ut_x,
       ut_y, ut_z, src, dt, scale, u_x, u_y, u_z);
+  NFA_CHECK_LAUNCH();
+  return NFA_OK;
+}
+
+extern "C" nfa_status nfa_exit_velocity(nfa_grid g, const double* uk_x, double uc, double dt,
+                                        double* ut_x, nfa_stream s) {
+  if (!g || !uk_x || !ut_x) return fail(NFA_ERR_INVALID, "nfa_exit_velocity: NULL argument");
+  if (g->nx < 2) return fail(NFA_ERR_INVALID, "nfa_exit_velocity: needs nx >= 2");
+  const double dxl = g->dx[g->nx - 1];
+  if (!(dt > 0) || !(uc >= 0) || !(uc * dt <= dxl))
+    return fail(NFA_ERR_INVALID, "nfa_exit_velocity: needs dt > 0 and 0 <= uc dt <= width of the last cell");
+  const long long nrow = (long long)g->ny * g->nz;
+  k_exit<<<blocks_for(nrow), kBlock, 0, S(s)>>>(g->nx, nrow, uk_x, (uc * dt) / dxl, ut_x);
   NFA_CHECK_LAUNCH();
   return NFA_OK;
 }

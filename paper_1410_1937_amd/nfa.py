@@ -123,6 +123,9 @@ _sig("nfa_poisson_profile_read", c_int, [c_void_p, c_int, ctypes.POINTER(KernelS
 _sig("nfa_poisson_velocity", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_double,
                                      c_void_p, c_void_p, c_void_p, c_void_p])
 _sig("nfa_faces_combine", c_int, [c_ll, c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p])
+_sig("nfa_poisson_rhs_cells", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p,
+                                      c_void_p, c_void_p, c_void_p])
+_sig("nfa_exit_velocity", c_int, [c_void_p, c_void_p, c_double, c_double, c_void_p, c_void_p])
 _sig("nfa_rk2_cycle", c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(RK2Params),
                               ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
                               ctypes.POINTER(c_void_p), c_void_p, c_void_p, ctypes.POINTER(c_void_p),
@@ -180,6 +183,15 @@ class Grid:
         ptr = None if psi is None else _dev(psi, torch.float64,
                                              (self.nz + 1, self.ny + 1, self.nx + 1), "psi")
         _check(lib.nfa_grid_set_body(self.h, ptr, theta, samples, _stream()), "nfa_grid_set_body")
+
+    def exit_velocity(self, uk_x, uc, dt, ut_x=None):
+        """Exit-plane x-velocity of the radiation condition (nfa_exit_velocity);
+        writes the +x boundary plane of ut_x (a copy of uk_x when not given)."""
+        sh = self.face_shape(0)
+        ut = uk_x.clone() if ut_x is None else ut_x
+        _check(lib.nfa_exit_velocity(self.h, _dev(uk_x, torch.float64, sh, "uk_x"), uc, dt,
+                                     _dev(ut, torch.float64, sh, "ut_x"), _stream()), "nfa_exit_velocity")
+        return ut
 
     def info(self):
         gi = GridInfo()
@@ -253,6 +265,17 @@ class Poisson:
                                    _dev(v, torch.float64, g.face_shape(1), "v"),
                                    _dev(w, torch.float64, g.face_shape(2), "w"), dt, vel.ctypes.data,
                                    _dev(b, torch.float64, self.shape, "b"), _stream()), "nfa_poisson_rhs")
+        return b
+
+    def rhs_cells(self, u, v, w, dt, vb, out=None):
+        """nfa_poisson_rhs with a per-cell body velocity vb = (vx, vy, vz) cells."""
+        g = self.grid
+        b = torch.empty(self.shape, dtype=torch.float64, device="cuda") if out is None else out
+        _check(lib.nfa_poisson_rhs_cells(self.h, _dev(u, torch.float64, g.face_shape(0), "u"),
+                                         _dev(v, torch.float64, g.face_shape(1), "v"),
+                                         _dev(w, torch.float64, g.face_shape(2), "w"), dt,
+                                         *[_dev(a, torch.float64, self.shape, "vb") for a in vb],
+                                         _dev(b, torch.float64, self.shape, "b"), _stream()), "nfa_poisson_rhs_cells")
         return b
 
     def project(self, u, v, w, p, dt=1.0):
