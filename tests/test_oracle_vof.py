@@ -1,0 +1,207 @@
+"""Pins of the oracle's VOF advection (no GPU): the cube volume function
+against an independent integral and its closed forms, the plane constant's
+inversion, the normal stencil on a single wet cell, the flux correction's
+per-cell balance, hand-computed sweeps of a compressing row (explicit and
+implicit dilation, the alternating order), exact transport of a horizontal
+interface, a uniform fraction kept under any flow, and boundedness and
+near-conservation in a rotating flow."""
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+
+from oracle import vof
+from oracle.geometry import Body
+from oracle.grid import Grid
+from paper_1410_1937_amd import fixtures as fx
+
+
+def _integral(n, a, N=1500):
+    """Fraction of the unit cube below n . x = a by integrating the column
+    height over a fine midpoint grid in (x, y) (n3 > 0)."""
+    g = (np.arange(N) + 0.5) / N
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    return float(np.mean(np.clip((a - n[0] * X - n[1] * Y) / n[2], 0.0, 1.0)))
+
+
+def test_unit_fraction_closed_forms_and_symmetry():
+    assert vof.unit_fraction(0.0, 0.0, 1.0, 0.3) == pytest.approx(0.3, abs=1e-15)      # a slab
+    assert vof.unit_fraction(0.0, 0.5, 0.5, 0.2) == pytest.approx(2 * 0.2 ** 2, abs=1e-15)  # a prism
+    assert vof.unit_fraction(1 / 3, 1 / 3, 1 / 3, 1 / 3) == pytest.approx(1 / 6, abs=1e-15)  # a corner tetrahedron
+    rng = np.random.default_rng(0)
+    n = np.sort(rng.dirichlet([1, 1, 1], size=200), axis=1)
+    a = rng.uniform(0, 1, 200)
+    f = vof.unit_fraction(n[:, 0], n[:, 1], n[:, 2], a)
+    g = vof.unit_fraction(n[:, 0], n[:, 1], n[:, 2], 1.0 - a)
+    assert np.max(np.abs(f + g - 1.0)) <= 1e-14
+    assert np.all(np.diff(vof.unit_fraction(0.2, 0.3, 0.5, np.linspace(0, 1, 101))) >= 0)
+
+
+def test_unit_fraction_matches_an_independent_integral():
+    rng = np.random.default_rng(1)
+    for _ in range(12):
+        n = np.sort(rng.dirichlet([1, 1, 1]))
+        a = rng.uniform(0, 1)
+        assert abs(vof.unit_fraction(*n, a) - _integral(n, a)) <= 2e-6, (n, a)
+
+
+def test_plane_constant_inverts_the_volume_function():
+    rng = np.random.default_rng(2)
+    m = rng.standard_normal((500, 3))
+    m[::7, 0] = 0.0
+    dims = rng.uniform(0.5, 2.0, (500, 3))
+    phi = rng.uniform(0, 1, 500)
+    s, n, t = vof.plane(m, dims, phi)
+    ns = np.sort(n, axis=1)
+    back = vof.unit_fraction(ns[:, 0], ns[:, 1], ns[:, 2], t)
+    assert np.max(np.abs(back - phi)) <= 1e-14
+
+
+def test_flux_correction_balances_every_cell():
+    wl = fx.small(0, 20, 12, 10, body="sphere")
+    g = Grid(wl.xf, wl.yf, wl.zf, wl.bc)
+    body = Body(g, wl.psi, wl.theta, wl.samples)
+    uh = vof.corrected_velocities(g, body, wl.u, wl.v, wl.w)
+    V = g.volumes()
+    dx = g.ax.d[None, None, :]
+    dy = g.ay.d[None, :, None]
+    dz = g.az.d[:, None, None]
+    bal = ((uh["x", 1] - uh["x", 0]) * V / dx + (uh["y", 1] - uh["y", 0]) * V / dy) + \
+        (uh["z", 1] - uh["z", 0]) * V / dz
+    cut = (body.open_z[:-1] + body.open_z[1:]) > 0
+    scale = np.max(np.abs(uh["x", 1] * V / dx))
+    assert np.max(np.abs(bal[cut])) <= 1e-13 * scale
+    assert np.all(uh["x", 0][body.active == 0] == 0)
+
+
+def _column(nz=24, nxy=6):
+    xf = yf = fx.uniform_faces(0.0, 1.0, nxy)
+    zf = fx.stretched_faces(0.0, 1.0, nz, [0.5])
+    g = Grid(xf, yf, zf, (0,) * 6)
+    return g, Body(g, None, 0.25, 8)
+
+
+def _plane_fractions(g, z0):
+    return np.broadcast_to(np.clip((z0 - g.az.f[:-1]) / g.az.d, 0.0, 1.0)[:, None, None], g.shape).copy()
+
+
+@pytest.mark.parametrize("W", [0.7, -0.7])
+def test_a_horizontal_interface_is_transported_exactly(W):
+    g, body = _column()
+    z0, dt = 0.5137, 0.004
+    phi = _plane_fractions(g, z0)
+    u = np.zeros((g.nz, g.ny, g.nx + 1))
+    v = np.zeros((g.nz, g.ny + 1, g.nx))
+    w = np.full((g.nz + 1, g.ny, g.nx), W)
+    for step in range(2):
+        phi = vof.advect(g, body, phi, u, v, w, dt, step)
+    exact = _plane_fractions(g, z0 + 2 * W * dt)
+    assert np.max(np.abs(phi - exact)) <= 1e-12
+
+
+def test_rotating_flow_stays_bounded_and_nearly_conserves_water():
+    n = 24
+    f = fx.uniform_faces(0.0, 1.0, n)
+    g = Grid(f, f, f, (0,) * 6)
+    body = Body(g, None, 0.25, 8)
+    c = fx.centres(f)
+    # a sphere of water in a rotation about the z-axis through the centre
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    phi = np.clip(0.5 - (np.sqrt((X - 0.62) ** 2 + (Y - 0.5) ** 2 + (Z - 0.5) ** 2) - 0.18) / (1.5 / n), 0, 1)
+    # face velocities of the rotation (exactly solenoidal on the grid)
+    u = -(c[None, :, None] - 0.5) * np.ones((n, n, n + 1))
+    v = (c[None, None, :] - 0.5) * np.ones((n, n + 1, n))
+    u[:, :, [0, -1]] = 0.0
+    v[:, [0, -1], :] = 0.0
+    w = np.zeros((n + 1, n, n))
+    dt = 0.5 / n / 0.5                      # Courant number 0.5 at the corners
+    m0 = np.sum(phi * g.volumes())
+    for step in range(6):
+        phi = vof.advect(g, body, phi, u, v, w, dt, step)
+        assert np.min(phi) >= -1e-12 and np.max(phi) <= 1 + 1e-12
+    assert abs(np.sum(phi * g.volumes()) - m0) <= 2e-3 * m0
+
+
+def _uniform(nx, ny, nz):
+    return Grid(fx.uniform_faces(0.0, nx, nx), fx.uniform_faces(0.0, ny, ny), fx.uniform_faces(0.0, nz, nz), (0,) * 6)
+
+
+def test_normal_of_a_single_wet_cell_follows_the_weighted_stencil():
+    """m = -grad phi by central differences averaged across the difference
+    direction with weights 1/4, 1/2, 1/4: one wet neighbour at (+1, +1, 0) of
+    a unit cell contributes -(1/4)(1/2)/2 to m_x (x offset 2 between the
+    centres, weight 1/4 for the y offset, 1/2 for no z offset) and likewise
+    to m_y; a neighbour at (0, -1, -1) contributes to m_y and m_z."""
+    g = _uniform(5, 5, 5)
+    act = np.ones(g.shape)
+    phi = np.zeros(g.shape)
+    phi[2, 3, 3] = 1.0                       # (z, y, x) = centre + (0, +1, +1)
+    m = vof.normals(g, phi, act)[2, 2, 2]
+    assert np.allclose(m, [-(0.25 * 0.5) / 2, -(0.25 * 0.5) / 2, 0.0], rtol=0, atol=1e-15)
+    phi[:] = 0.0
+    phi[1, 1, 2] = 1.0                       # centre + (x 0, y -1, z -1)
+    m = vof.normals(g, phi, act)[2, 2, 2]
+    assert np.allclose(m, [0.0, (0.5 * 0.25) / 2, (0.5 * 0.25) / 2], rtol=0, atol=1e-15)
+
+
+def _row_case(d):
+    """Four unit cells along direction d (0 = x, 1 = y) with the faces of the
+    other directions closed (so no flux correction); face velocities
+    0, .2, .3, .1, 0 compress the water of (1, 1, 0, 0) into the third cell."""
+    shape_cells = [1, 1, 1]                  # (nz, ny, nx)
+    shape_cells[2 - d] = 4
+    nz, ny, nx = shape_cells
+    g = _uniform(nx, ny, nz)
+    vel = np.array([0.0, 0.2, 0.3, 0.1, 0.0])
+    u = np.zeros((nz, ny, nx + 1))
+    v = np.zeros((nz, ny + 1, nx))
+    w = np.zeros((nz + 1, ny, nx))
+    (u if d == 0 else v)[...] = vel.reshape((1, 1, 5) if d == 0 else (1, 5, 1))
+    body = SimpleNamespace(open_x=np.ones(u.shape) * (d == 0), open_y=np.ones(v.shape) * (d == 1),
+                           open_z=np.zeros(w.shape), active=np.ones(g.shape))
+    phi = np.array([1.0, 1.0, 0.0, 0.0]).reshape(shape_cells)
+    return g, body, phi, u, v, w
+
+
+# By hand: the face fluxes are .2 and .3 (full donors) and 0 (an empty
+# donor), so the cells keep 1 - .2 = .8, 1 - .1 = .9, .3 and 0 before the
+# dilation term dt phi (u+ - u-) = (.2, .1, -.2, -.1) phi.  With the sweep's
+# input fraction (explicit): (1, 1, .3, 0); with its output (implicit,
+# phi (1 - dt D) = rest): (.8/.8, .9/.9, .3/1.2, 0) = (1, 1, .25, 0).
+EXPLICIT = np.array([1.0, 1.0, 0.3, 0.0])
+IMPLICIT = np.array([1.0, 1.0, 0.25, 0.0])
+
+
+def test_the_x_sweep_is_explicit_first_and_implicit_last():
+    g, body, phi, u, v, w = _row_case(0)
+    first = vof.advect(g, body, phi, u, v, w, 1.0, step=0)      # order x, y, z
+    last = vof.advect(g, body, phi, u, v, w, 1.0, step=1)       # order z, y, x
+    assert np.allclose(first.ravel(), EXPLICIT, rtol=0, atol=1e-15)
+    assert np.allclose(last.ravel(), IMPLICIT, rtol=0, atol=1e-15)
+
+
+def test_the_middle_y_sweep_is_explicit_on_both_orders():
+    g, body, phi, u, v, w = _row_case(1)
+    for step in (0, 1):
+        out = vof.advect(g, body, phi, u, v, w, 1.0, step=step)
+        assert np.allclose(out.ravel(), EXPLICIT, rtol=0, atol=1e-15)
+
+
+def test_a_uniform_fraction_stays_uniform_through_every_sweep():
+    """Without an interface (a uniform field has no normal) every face passes
+    phi times its slab, which the dilation term returns exactly, explicit or
+    implicit, in any of the three directions.  (Over a whole step the
+    rounding of the first sweep leaves a field whose normals point anywhere,
+    so the check is per sweep.)"""
+    wl = fx.small(3, 16, 12, 10, body="sphere")
+    g = Grid(wl.xf, wl.yf, wl.zf, wl.bc)
+    body = Body(g, wl.psi, wl.theta, wl.samples)
+    phi = np.full(g.shape, 0.37)
+    uh = vof.corrected_velocities(g, body, wl.u, wl.v, wl.w)
+    width = {"x": g.ax.d[None, None, :], "y": g.ay.d[None, :, None], "z": g.az.d[:, None, None]}
+    courant = max(np.max(np.abs(uh[k]) / width[k[0]]) for k in uh)
+    dt = 0.45 / courant                      # Courant number 0.45 after the correction
+    for d in range(3):
+        for implicit in (False, True):
+            out = vof.sweep(g, body, phi, uh, d, dt, implicit)
+            assert np.max(np.abs(out - 0.37)) <= 1e-15, (d, implicit)
