@@ -13,12 +13,13 @@ is cut by the body:
    A3- > 0).  Each cell then gets its own face velocities on uncut areas,
    uhat_i = dx_i F_i / V (continuous across x- and y-faces, per cell on
    z-faces).
-2. Interface reconstruction (piecewise linear).  In each cell the interface
-   is the plane m . x = alpha with m = -grad phi from weighted central
-   differences over the 3x3x3 neighbourhood (weights 1/4, 1/2, 1/4 across the
-   difference direction; neighbours inside the body or beyond the domain take
-   the cell's own fraction), and alpha such that the water below the plane
-   fills phi of the cell.
+2. Interface reconstruction (piecewise linear).  In each cell with
+   EPS < phi < 1 - EPS the interface is the plane m . x = alpha with
+   m = -grad phi from weighted central differences over the 3x3x3
+   neighbourhood (weights 1/4, 1/2, 1/4 across the difference direction; a
+   neighbour beyond the domain repeats the edge cell, one inside the body
+   takes the cell's own fraction), and alpha such that the water below the
+   plane fills phi of the cell.
 3. Three one-directional sweeps, in the order x, y, z on even steps and z, y,
    x on odd ones.  In direction d each cell loses the water volume its faces
    pass in dt, F_d[uhat, phi, dt]: the water in the slab of thickness |uhat|
@@ -30,11 +31,14 @@ is cut by the body:
 
 Readings where the paper is silent or garbled (each taken identically by the
 GPU path): the normal stencil and its boundary and body treatment; the plane
-constant by 64 bisection steps on the cell's volume function; the first two
-sweeps explicit and the last implicit (the text; the printed equations place
-the new value in the first and the old one in the last, and name an undefined
-phi-hat in the last); a face on the domain boundary draws from the cell
-inside it; cells inside the body keep their fraction.
+constant by 64 bisection steps on the cell's volume function; a fraction
+within EPS = 1e-12 of 0 or 1 is an empty or full cell without a plane (the
+rounding of the dilation term leaves full cells at 1 - 1e-16, whose planes
+would be arbitrary); the first two sweeps explicit and the last implicit (the
+text; the printed equations place the new value in the first and the old one
+in the last, and name an undefined phi-hat in the last); a face on the domain
+boundary draws from the cell inside it; cells inside the body keep their
+fraction.
 """
 from __future__ import annotations
 
@@ -42,6 +46,7 @@ import numpy as np
 
 W = (0.25, 0.5, 0.25)
 BISECT = 64
+EPS = 1e-12        # fractions within EPS of 0 or 1 count as empty or full (no plane)
 
 
 # --------------------------------------------------------------- geometry
@@ -79,8 +84,9 @@ def box_fraction(n, lo, hi, t):
     cube, (..., 3)) under sum_d n_d xi_d <= t, n >= 0."""
     ext = hi - lo
     nn = n * ext
-    S = np.sum(nn, axis=-1)
-    tt = t - np.sum(n * lo, axis=-1)
+    S = (nn[..., 0] + nn[..., 1]) + nn[..., 2]
+    nl = n * lo
+    tt = t - ((nl[..., 0] + nl[..., 1]) + nl[..., 2])
     with np.errstate(divide="ignore", invalid="ignore"):
         ns = _sorted3(nn / S[..., None])
         f = unit_fraction(ns[..., 0], ns[..., 1], ns[..., 2], tt / S)
@@ -95,7 +101,7 @@ def plane(m, dims, phi):
     sum 1, and t in [0, 1] such that the fraction of {n . xi <= t} is phi."""
     s = np.where(m < 0, -1.0, 1.0)
     nm = np.abs(m) * dims
-    S = np.sum(nm, axis=-1)
+    S = (nm[..., 0] + nm[..., 1]) + nm[..., 2]
     with np.errstate(divide="ignore", invalid="ignore"):
         n = nm / S[..., None]
     ns = _sorted3(n)
@@ -243,7 +249,7 @@ def sweep(grid, body, phi, uhat, d, dt, implicit):
                                             grid.az.d[:, None, None]), axis=-1)
     V = grid.volumes()
     m = normals(grid, phi, body.active)
-    interface = (phi > 0.0) & (phi < 1.0) & (np.sum(np.abs(m), axis=-1) > 0)
+    interface = (phi > EPS) & (phi < 1.0 - EPS) & (np.sum(np.abs(m), axis=-1) > 0)
     s, n, t = plane(m, dims_all, np.clip(phi, 0.0, 1.0))
     width = dims_all[..., d]
 

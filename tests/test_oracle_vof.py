@@ -205,3 +205,14 @@ def test_a_uniform_fraction_stays_uniform_through_every_sweep():
         for implicit in (False, True):
             out = vof.sweep(g, body, phi, uh, d, dt, implicit)
             assert np.max(np.abs(out - 0.37)) <= 1e-15, (d, implicit)
+
+
+def test_a_nearly_full_cell_passes_its_fraction_without_a_plane():
+    """A fraction within 1e-12 of 1 (what the rounding of the dilation term
+    leaves in full cells) has no interface plane: the face passes the slab
+    times the fraction, here 0.3 (1 - 1e-14) into the empty third cell."""
+    g, body, phi, u, v, w = _row_case(0)
+    phi = phi.copy()
+    phi[0, 0, 1] = 1.0 - 1e-14
+    out = vof.advect(g, body, phi, u, v, w, 1.0, step=0)
+    assert out[0, 0, 2] == 0.3 * (1.0 - 1e-14)
