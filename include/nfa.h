@@ -345,6 +345,57 @@ nfa_status nfa_rk2_cycle(nfa_poisson op, const void* phi_k, const void* phi_star
                          double* const* unext, const nfa_solve_opts* opts, nfa_stream s,
                          nfa_solve_info* info);
 
+/* ------------------------------------------------------------------------
+ * Split VOF advection of the water fraction (Interface reconstruction and
+ * advection section: eq. vof advanced by three one-directional sweeps, the
+ * flux correction that restores eq. diverge cell by cell, piecewise-planar
+ * interfaces).  Fractions are DEVICE double cells; u, v, w are DEVICE double
+ * face velocities relative to the body on x-, y- and z-faces.  The fluxes
+ * are F = A u with A the grid's open face areas (zero on faces of inactive
+ * cells).  Inactive cells keep their fraction.
+ * ------------------------------------------------------------------------ */
+
+/* nfa_vof_create -- work memory of the advection on grid g (which must
+ * outlive it; its body is read at every call, so it may be set or changed
+ * later): a plane table (32 bytes per cell), two cell lists (4 bytes per cell
+ * each) and one fraction buffer (8 bytes per cell).  Errors: NFA_ERR_HIP. */
+typedef struct nfa_vof_s* nfa_vof;
+nfa_status nfa_vof_create(nfa_grid g, nfa_vof* out);
+void nfa_vof_destroy(nfa_vof v);
+
+/* nfa_vof_sweep -- one sweep along dir (0 x, 1 y, 2 z):
+ *   phi_out = phi - (F_d[uhat+] - F_d[uhat-]) / V + dilation,
+ * uhat = dx_d F~ / V with the z-faces of each cell corrected by its share of
+ * the cell's flux imbalance E (in proportion to the two z areas) so that
+ * its six fluxes balance.  F_d moves across a face the water in the slab of
+ * thickness |uhat| dt of the upwind cell next to it (below that cell's
+ * interface plane, or times its fraction when it has none; a face on the
+ * domain boundary draws from the cell inside).  The dilation is
+ * dt phi (uhat+ - uhat-) / dx_d with the input phi (implicit = 0) or
+ * phi_out (1 - dt (uhat+ - uhat-) / dx_d) = the rest (implicit = 1).
+ * Interface planes: in each cell with 1e-12 < phi < 1 - 1e-12 and a non-zero
+ * normal; normal -grad phi by weighted (1/4, 1/2, 1/4) central differences
+ * over the 3x3x3 neighbourhood (the edge cell repeats beyond the domain, a
+ * neighbour inside the body takes the cell's own fraction), constant by 64
+ * bisection steps on the cube's volume function.
+ *   dt > 0; the slab is capped at the full cell (|uhat| dt <= dx_d is the
+ *   caller's Courant condition).  phi_out must not overlap phi.  Calls on
+ *   one handle are ordered by their streams; calls that may overlap need
+ *   handles of their own.   ASYNC.
+ * Errors: NFA_ERR_INVALID (NULL, dt, dir, overlap). */
+nfa_status nfa_vof_sweep(nfa_vof vof, const double* phi, const double* u, const double* v,
+                         const double* w, double dt, int dir, int implicit, double* phi_out,
+                         nfa_stream s);
+
+/* nfa_vof_advect -- one time step: sweeps x, y, z on even `step`, z, y, x on
+ * odd ones (the order alternates from step to step), the first two explicit
+ * and the last implicit.  The face velocities are those of the step (u^k in
+ * stage 1, (u* + u^k)/2 in stage 2 of the Runge-Kutta cycle).
+ *   phi     : DEVICE double cells, input (not written).
+ *   phi_out : DEVICE double cells, output; must not overlap phi.   ASYNC. */
+nfa_status nfa_vof_advect(nfa_vof vof, const double* phi, const double* u, const double* v,
+                          const double* w, double dt, int step, double* phi_out, nfa_stream s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -294,6 +294,19 @@ void axis_metrics(const double* f, int n, std::vector<double>& fv, std::vector<d
   h[n] = 0.5 * d[n - 1];
 }
 
+// Denominators of the central differences of the interface normals: the
+// distance between the centres either side of each cell, with a ghost centre
+// mirrored across each boundary face.
+std::vector<double> normal_den(const std::vector<double>& f) {
+  const int n = (int)f.size() - 1;
+  std::vector<double> cg(n + 2), den(n);
+  for (int i = 0; i < n; ++i) cg[i + 1] = 0.5 * (f[i] + f[i + 1]);
+  cg[0] = 2.0 * f[0] - cg[1];
+  cg[n + 1] = 2.0 * f[n] - cg[n];
+  for (int i = 0; i < n; ++i) den[i] = cg[i + 2] - cg[i];
+  return den;
+}
+
 hipError_t upload(DevBuf& b, const std::vector<double>& v) {
   hipError_t e = b.alloc(v.size() * sizeof(double));
   if (e != hipSuccess) return e;
@@ -461,6 +474,9 @@ extern "C" nfa_status nfa_grid_create(int nx, int ny, int nz, const double* xf, 
   if ((e = upload(g->d_hx, g->hx)) != hipSuccess) return bad(e);
   if ((e = upload(g->d_hy, g->hy)) != hipSuccess) return bad(e);
   if ((e = upload(g->d_hz, g->hz)) != hipSuccess) return bad(e);
+  if ((e = upload(g->d_gx, normal_den(g->xf))) != hipSuccess) return bad(e);
+  if ((e = upload(g->d_gy, normal_den(g->yf))) != hipSuccess) return bad(e);
+  if ((e = upload(g->d_gz, normal_den(g->zf))) != hipSuccess) return bad(e);
   const long long n = g->n;
   if ((e = g->frac_x.alloc(g->nfx() * 8)) != hipSuccess) return bad(e);
   if ((e = g->frac_y.alloc(g->nfy() * 8)) != hipSuccess) return bad(e);

@@ -70,6 +70,7 @@ struct Grid {
   std::vector<double> hx, hy, hz;     // host face distances (n+1 each)
   // device 1-D metrics
   DevBuf d_dx, d_dy, d_dz, d_hx, d_hy, d_hz;
+  DevBuf d_gx, d_gy, d_gz;            // centre-to-centre spans of the normal stencil (n each)
   // body (always present: "no body" = all open)
   bool has_body = false;
   DevBuf frac_x, frac_y, frac_z;      // face fractions (double)

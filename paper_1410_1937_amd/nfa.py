@@ -126,6 +126,12 @@ _sig("nfa_faces_combine", c_int, [c_ll, c_void_p, c_void_p, c_double, c_void_p, 
 _sig("nfa_poisson_rhs_cells", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p,
                                       c_void_p, c_void_p, c_void_p])
 _sig("nfa_exit_velocity", c_int, [c_void_p, c_void_p, c_double, c_double, c_void_p, c_void_p])
+_sig("nfa_vof_create", c_int, [c_void_p, ctypes.POINTER(c_void_p)])
+_sig("nfa_vof_destroy", None, [c_void_p])
+_sig("nfa_vof_sweep", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int, c_int,
+                              c_void_p, c_void_p])
+_sig("nfa_vof_advect", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int, c_void_p,
+                               c_void_p])
 _sig("nfa_rk2_cycle", c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(RK2Params),
                               ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
                               ctypes.POINTER(c_void_p), c_void_p, c_void_p, ctypes.POINTER(c_void_p),
@@ -212,6 +218,42 @@ class Grid:
         return out
 
     def __del__(self, _destroy=lib.nfa_grid_destroy):
+        if getattr(self, "h", None):
+            _destroy(self.h)
+            self.h = None
+
+
+class Vof:
+    """Split VOF advection on a grid (nfa_vof_*); the handle owns the plane
+    table, the cell lists and a fraction buffer."""
+
+    def __init__(self, grid: Grid):
+        self.grid = grid
+        h = c_void_p()
+        _check(lib.nfa_vof_create(grid.h, ctypes.byref(h)), "nfa_vof_create")
+        self.h = h
+
+    def _args(self, phi, u, v, w):
+        g = self.grid
+        return (_dev(phi, torch.float64, g.shape, "phi"), _dev(u, torch.float64, g.face_shape(0), "u"),
+                _dev(v, torch.float64, g.face_shape(1), "v"), _dev(w, torch.float64, g.face_shape(2), "w"))
+
+    def sweep(self, phi, u, v, w, dt, direction, implicit, out=None):
+        """One directional sweep (nfa_vof_sweep)."""
+        out = torch.empty_like(phi) if out is None else out
+        _check(lib.nfa_vof_sweep(self.h, *self._args(phi, u, v, w), dt, direction, int(bool(implicit)),
+                                 _dev(out, torch.float64, self.grid.shape, "out"), _stream()), "nfa_vof_sweep")
+        return out
+
+    def advect(self, phi, u, v, w, dt, step=0, out=None):
+        """One time step (nfa_vof_advect): face velocities u, v, w relative to
+        the body, the order of the sweeps set by the parity of step."""
+        out = torch.empty_like(phi) if out is None else out
+        _check(lib.nfa_vof_advect(self.h, *self._args(phi, u, v, w), dt, step,
+                                  _dev(out, torch.float64, self.grid.shape, "out"), _stream()), "nfa_vof_advect")
+        return out
+
+    def __del__(self, _destroy=lib.nfa_vof_destroy):
         if getattr(self, "h", None):
             _destroy(self.h)
             self.h = None
