@@ -28,16 +28,15 @@
 // Work layout.  Interface cells are about 1 % of the grid, so a plane per
 // thread of the sweep would leave most lanes of a wavefront idle through
 // the bisection.  Each sweep therefore runs in two launches:
-//   k_planes  one thread per cell of a compact list of the active cells with
-//             1e-12 < phi < 1 - 1e-12: normal, bisection, the plane stored
-//             in a per-cell table (signed normal, constant);
+//   k_planes  each block scans its rows for active cells with
+//             1e-12 < phi < 1 - 1e-12, stages them in LDS and solves them a
+//             block at a time (normal, bisection), storing the plane in a
+//             per-cell table (signed normal, constant);
 //   k_sweep   one thread per cell, x fastest: face speeds, the two face
 //             fluxes (reading the upwind cell's plane from the table), the
-//             update; it appends the cells it leaves inside (1e-12, 1 - 1e-12)
-//             to the list of the next sweep.
-// The first list comes from k_scan.  Appends are staged in LDS and flushed
-// with one global atomic per block and flush.  Blocks take grid rows
-// (x-lines) round robin.
+//             update.  All loads a cell may need are issued before any is
+//             used, so a wavefront waits for memory about once per cell.
+// Both take grid rows (x-lines) round robin.
 //
 // Built with -ffp-contract=off: every expression is rounded as written.
 #include <cmath>
@@ -50,9 +49,7 @@ namespace {
 
 constexpr int kBisect = 64;
 constexpr double kEps = 1e-12;   // fractions within kEps of 0 or 1 have no plane
-constexpr int kPlaneBlocks = 2048;
 constexpr int kRowBlocks = 4096;   // blocks of the row kernels
-constexpr int kStage = 2048;       // LDS list entries per block
 
 struct Sweep {
   int nx, ny, nz;
@@ -186,18 +183,13 @@ __device__ double4 make_plane(const Sweep& A, int i, int j, int k, double phi) {
 }
 
 // Water volume in the slab of thickness speed dt next to the upper (or
-// lower) d-face of cell (i, j, k).
-__device__ double slab_water(const Sweep& A, const double4* __restrict__ planes, int d, int i, int j, int k,
-                             bool upper, double speed) {
-  const double dims[3] = {A.dx[i], A.dy[j], A.dz[k]};
-  const double dw = dims[d];
-  const double frac = fmin(speed * A.dt, dw) / dw;
-  const double vol = (A.dz[k] * A.dy[j]) * A.dx[i];
+// lower) d-face of donor cell cd: width dw along d, volume vol, fraction phi.
+__device__ __forceinline__ double water(const double4* __restrict__ planes, long long cd, double phi, double dw,
+                                        double vol, int d, bool upper, double speed, double dt) {
+  const double frac = fmin(speed * dt, dw) / dw;
   const double slab = frac * vol;
-  const long long c = cell(A, i, j, k);
-  const double phi = A.phi[c];
   if (!in_band(phi)) return slab * clip01(phi);
-  const double4 P = planes[c];
+  const double4 P = planes[cd];
   if (!(P.w >= 0.0)) return slab * clip01(phi);
   const double pn[3] = {fabs(P.x), fabs(P.y), fabs(P.z)};
   double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {1.0, 1.0, 1.0};
@@ -228,187 +220,239 @@ __device__ double slab_water(const Sweep& A, const double4* __restrict__ planes,
   return slab * f;
 }
 
-// Face velocities uhat of cell (i, j, k) on its lower and upper d-faces.
-__device__ void face_speeds(const Sweep& A, int d, int i, int j, int k, double& lo, double& up) {
-  const int nx = A.nx, ny = A.ny;
-  const long long fxm = ((long long)k * ny + j) * (nx + 1) + i;
-  const long long fym = ((long long)k * (ny + 1) + j) * nx + i;
-  const long long fzm = ((long long)k * ny + j) * nx + i;
-  const long long plane = (long long)nx * ny;
-  const double V = (A.dz[k] * A.dy[j]) * A.dx[i];
-  if (d == 0) {
-    lo = (A.dx[i] * (A.ox[fxm] * A.u[fxm])) / V;
-    up = (A.dx[i] * (A.ox[fxm + 1] * A.u[fxm + 1])) / V;
-  } else if (d == 1) {
-    lo = (A.dy[j] * (A.oy[fym] * A.v[fym])) / V;
-    up = (A.dy[j] * (A.oy[fym + nx] * A.v[fym + nx])) / V;
-  } else {
-    const double Fxm = A.ox[fxm] * A.u[fxm], Fxp = A.ox[fxm + 1] * A.u[fxm + 1];
-    const double Fym = A.oy[fym] * A.v[fym], Fyp = A.oy[fym + nx] * A.v[fym + nx];
-    const double Azm = A.oz[fzm], Azp = A.oz[fzm + plane];
-    double Fzm = Azm * A.w[fzm], Fzp = Azp * A.w[fzm + plane];
-    const double E = ((Fxp - Fxm) + (Fyp - Fym)) + (Fzp - Fzm);
-    const double den = Azp + Azm;
-    if (den > 0.0) {
-      Fzp = Fzp - (E * Azp) / den;
-      Fzm = Fzm + (E * Azm) / den;
-    }
-    lo = (A.dz[k] * Fzm) / V;
-    up = (A.dz[k] * Fzp) / V;
-  }
-}
-
-// A list staged in LDS (s_list, kStage entries): appended by wavefronts
-// (one LDS atomic each), flushed to the global list with one global atomic
-// per flush.  Every lane of the block must call these.
-struct Stage {
-  int cnt;
-  int base;
-};
-
-__device__ __forceinline__ void stage_append(int* s_list, Stage& S, bool flag, int c) {
-  const unsigned long long mask = __ballot(flag);
-  if (mask == 0) return;
-  const int lane = threadIdx.x & 63;
-  const int leader = __ffsll((long long)mask) - 1;
-  int b = 0;
-  if (lane == leader) b = atomicAdd(&S.cnt, __popcll(mask));
-  b = __shfl(b, leader, 64);
-  if (flag) s_list[b + __popcll(mask & ((1ull << lane) - 1ull))] = c;
-}
-
-// Flushes when forced or when the next chunk of blockDim appends might not fit.
-__device__ __forceinline__ void stage_flush(const int* s_list, Stage& S, int* __restrict__ list, int* counter,
-                                            bool force) {
-  __syncthreads();
-  const int m = S.cnt;
-  __syncthreads();   // every thread has read S.cnt before the next append changes it
-  if (m == 0 || (!force && m <= kStage - (int)blockDim.x)) return;
-  if (threadIdx.x == 0) S.base = atomicAdd(counter, m);
-  __syncthreads();
-  const int base = S.base;
-  for (int e = threadIdx.x; e < m; e += blockDim.x) list[base + e] = s_list[e];
-  __syncthreads();
-  if (threadIdx.x == 0) S.cnt = 0;
-  __syncthreads();
-}
-
 // Rows (x-lines, row r = k ny + j) are dealt to blocks round robin, so the
 // free surface's band of rows spreads over every block and XCD; the logical
 // block order is remapped so that the blocks of one XCD take neighbouring
 // rows.
 __device__ __forceinline__ int first_row() { return xcd_remap(blockIdx.x, gridDim.x); }
 
-__global__ __launch_bounds__(64) void k_reset(int* counters) {
-  if (threadIdx.x < 2) counters[threadIdx.x] = 0;
+// The cells of a block, in chunks of blockDim: chunk q is part q % cpr of
+// the block's row q / cpr (rows first_row(), first_row() + gridDim, ...).
+struct Chunks {
+  int r0, cpr, nq;
+};
+
+__device__ __forceinline__ Chunks block_chunks(int nx, int nrows) {
+  Chunks C;
+  C.r0 = first_row();
+  C.cpr = (nx + blockDim.x - 1) / blockDim.x;
+  const int nr = C.r0 < nrows ? (nrows - C.r0 + gridDim.x - 1) / gridDim.x : 0;
+  C.nq = nr * C.cpr;
+  return C;
 }
 
-// The in-band active cells of phi.
-__global__ __launch_bounds__(kBlock) void k_scan(int nx, int nrows, const double* __restrict__ phi,
-                                                 const unsigned char* __restrict__ act, int* __restrict__ list,
-                                                 int* counter) {
-  __shared__ int s_list[kStage];
-  __shared__ Stage S;
-  if (threadIdx.x == 0) S.cnt = 0;
+// Row and x-index of this thread's cell in chunk q; valid = inside the grid.
+__device__ __forceinline__ bool chunk_cell(const Chunks& C, int q, int nx, int nrows, int& r, int& i) {
+  r = C.r0 + (q / C.cpr) * gridDim.x;
+  i = (q % C.cpr) * blockDim.x + threadIdx.x;
+  return q < C.nq && r < nrows && i < nx;
+}
+
+constexpr int kScanUnroll = 4;             // chunks loaded per barrier in the plane scan
+
+// Planes of every active in-band cell.  Each block scans its rows (loading
+// kScanUnroll chunks before it waits), stages the in-band cells in LDS and
+// solves them a full block at a time (one cell per thread), so the bisection
+// runs on dense wavefronts.
+__global__ __launch_bounds__(kBlock) void k_planes(Sweep A, double4* __restrict__ planes) {
+  __shared__ int s_list[(kScanUnroll + 1) * kBlock];
+  __shared__ int s_cnt;
+  if (threadIdx.x == 0) s_cnt = 0;
   __syncthreads();
-  for (int r = first_row(); r < nrows; r += gridDim.x) {
-    const long long row = (long long)r * nx;
-    for (int i0 = 0; i0 < nx; i0 += blockDim.x) {
-      const int i = i0 + threadIdx.x;
-      const long long c = row + i;
-      const bool f = i < nx && act[c] && in_band(phi[c]);
-      stage_append(s_list, S, f, (int)c);
-      stage_flush(s_list, S, list, counter, false);
-    }
-  }
-  stage_flush(s_list, S, list, counter, true);
-}
-
-// Planes of the listed cells; also clears the counter of the next list.
-__global__ __launch_bounds__(kBlock) void k_planes(Sweep A, const int* __restrict__ list, const int* count,
-                                                   double4* __restrict__ planes, int* next_counter) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) *next_counter = 0;
-  const int m = *count;
-  const unsigned nx = A.nx, ny = A.ny;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
-    const unsigned c = list[e];
-    const unsigned r = c / nx;
-    const int i = (int)(c - r * nx);
-    const int k = (int)(r / ny);
-    const int j = (int)(r - (unsigned)k * ny);
+  const int nx = A.nx, nrows = A.ny * A.nz;
+  const unsigned unx = nx, uny = A.ny;
+  auto solve = [&](int e) {
+    const unsigned c = s_list[e];
+    const unsigned r = c / unx;
+    const int i = (int)(c - r * unx);
+    const int k = (int)(r / uny);
+    const int j = (int)(r - (unsigned)k * uny);
     planes[c] = make_plane(A, i, j, k, A.phi[c]);
-  }
-}
-
-template <int D, bool IMPLICIT, bool APPEND>
-__global__ __launch_bounds__(kBlock) void k_sweep(Sweep A, const double4* __restrict__ planes,
-                                                  int* __restrict__ list, int* counter) {
-  __shared__ int s_list[APPEND ? kStage : 1];
-  __shared__ Stage S;
-  if (APPEND) {
-    if (threadIdx.x == 0) S.cnt = 0;
+  };
+  const Chunks C = block_chunks(nx, nrows);
+  for (int q0 = 0; q0 < C.nq; q0 += kScanUnroll) {
+    bool f[kScanUnroll];
+    long long cc[kScanUnroll];
+    double ph[kScanUnroll];
+    unsigned char ac[kScanUnroll];
+#pragma unroll
+    for (int u = 0; u < kScanUnroll; ++u) {
+      int r, i;
+      f[u] = chunk_cell(C, q0 + u, nx, nrows, r, i);
+      cc[u] = f[u] ? (long long)r * nx + i : 0;
+      ph[u] = A.phi[cc[u]];
+      ac[u] = A.act[cc[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < kScanUnroll; ++u) {
+      const bool g = f[u] && ac[u] && in_band(ph[u]);
+      const unsigned long long mask = __ballot(g);
+      if (mask != 0) {
+        const int lane = threadIdx.x & 63;
+        const int leader = __ffsll((long long)mask) - 1;
+        int b = 0;
+        if (lane == leader) b = atomicAdd(&s_cnt, __popcll(mask));
+        b = __shfl(b, leader, 64);
+        if (g) s_list[b + __popcll(mask & ((1ull << lane) - 1ull))] = (int)cc[u];
+      }
+    }
+    __syncthreads();
+    const int m = s_cnt;
+    const int full = m / (int)blockDim.x;
+    if (full > 0) {                 // dense rounds; the remainder moves to the front
+      for (int t = 0; t < full; ++t) solve(t * blockDim.x + threadIdx.x);
+      const int rest = m - full * (int)blockDim.x;
+      const int keep = (int)threadIdx.x < rest ? s_list[full * blockDim.x + threadIdx.x] : 0;
+      __syncthreads();
+      if ((int)threadIdx.x < rest) s_list[threadIdx.x] = keep;
+      if (threadIdx.x == 0) s_cnt = rest;
+    }
     __syncthreads();
   }
-  const int nx = A.nx, ny = A.ny, nz = A.nz;
-  for (int r = first_row(); r < ny * nz; r += gridDim.x) {
-    const int k = r / ny, j = r - k * ny;
-    const long long row = (long long)r * nx;
-    for (int i0 = 0; i0 < nx; i0 += blockDim.x) {
-      const int i = i0 + threadIdx.x;
-      const long long c = row + i;
-      bool listed = false;
-      if (i < nx) {
-        const double phi = A.phi[c];
-        if (!A.act[c]) {
-          A.out[c] = phi;
-        } else {
-          double lo, up;
-          face_speeds(A, D, i, j, k, lo, up);
-          // the neighbours along D (a face on the domain boundary draws from the cell itself)
-          const int nD = D == 0 ? nx : (D == 1 ? ny : nz);
-          const int pos = D == 0 ? i : (D == 1 ? j : k);
-          const int pm = pos > 0 ? pos - 1 : pos, pp = pos < nD - 1 ? pos + 1 : pos;
-          const int im = D == 0 ? pm : i, jm = D == 1 ? pm : j, km = D == 2 ? pm : k;
-          const int ip = D == 0 ? pp : i, jp = D == 1 ? pp : j, kp = D == 2 ? pp : k;
-          double f_up, f_lo;
-          if (up > 0.0) f_up = slab_water(A, planes, D, i, j, k, true, up);
-          else if (up < 0.0) f_up = -slab_water(A, planes, D, ip, jp, kp, false, -up);
-          else f_up = 0.0;
-          if (lo > 0.0) f_lo = slab_water(A, planes, D, im, jm, km, true, lo);
-          else if (lo < 0.0) f_lo = -slab_water(A, planes, D, i, j, k, false, -lo);
-          else f_lo = 0.0;
-          const double width = D == 0 ? A.dx[i] : (D == 1 ? A.dy[j] : A.dz[k]);
-          const double V = (A.dz[k] * A.dy[j]) * A.dx[i];
-          const double div = (up - lo) / width;
-          const double rest = phi - (f_up - f_lo) / V;
-          const double nw = IMPLICIT ? rest / (1.0 - A.dt * div) : rest + (A.dt * phi) * div;
-          A.out[c] = nw;
-          listed = in_band(nw);
-        }
-      }
-      if (APPEND) {
-        stage_append(s_list, S, listed, (int)c);
-        stage_flush(s_list, S, list, counter, false);
-      }
-    }
-  }
-  if (APPEND) stage_flush(s_list, S, list, counter, true);
+  const int m = s_cnt;
+  if ((int)threadIdx.x < m) solve(threadIdx.x);
 }
 
-void launch_sweep(const Sweep& A, int d, bool implicit, bool append_next, const double4* planes, int* list,
-                  int* counter, hipStream_t s) {
-  const int nb = std::min(kRowBlocks, A.ny * A.nz);
-#define NFA_SWEEP(D, I, P) k_sweep<D, I, P><<<nb, kBlock, 0, s>>>(A, planes, list, counter)
-  if (append_next) {
-    if (d == 0) { if (implicit) NFA_SWEEP(0, true, true); else NFA_SWEEP(0, false, true); }
-    else if (d == 1) { if (implicit) NFA_SWEEP(1, true, true); else NFA_SWEEP(1, false, true); }
-    else { if (implicit) NFA_SWEEP(2, true, true); else NFA_SWEEP(2, false, true); }
-  } else {
-    if (d == 0) { if (implicit) NFA_SWEEP(0, true, false); else NFA_SWEEP(0, false, false); }
-    else if (d == 1) { if (implicit) NFA_SWEEP(1, true, false); else NFA_SWEEP(1, false, false); }
-    else { if (implicit) NFA_SWEEP(2, true, false); else NFA_SWEEP(2, false, false); }
+// What a sweep along D reads for one cell.
+struct CellIn {
+  long long c, cm, cp;        // the cell and its neighbours along D (itself beyond the domain)
+  int i, j, k;
+  bool valid, act;
+  double phi, phim, phip;
+  double dxc, dyc, dzc, wm, wp, vm, vp_;   // widths, neighbour widths along D, neighbour volumes' factors
+  double a[12];               // face data
+};
+
+template <int D>
+__device__ __forceinline__ void load_cell(const Sweep& A, const Chunks& C, int q, CellIn& X) {
+  const int nx = A.nx, ny = A.ny, nz = A.nz;
+  int r, i;
+  X.valid = chunk_cell(C, q, nx, ny * nz, r, i);
+  if (!X.valid) {
+    r = 0;
+    i = 0;
   }
-#undef NFA_SWEEP
+  const int k = r / ny, j = r - k * ny;
+  X.i = i;
+  X.j = j;
+  X.k = k;
+  const long long plane = (long long)nx * ny;
+  const long long c = ((long long)k * ny + j) * nx + i;
+  const int pos = D == 0 ? i : (D == 1 ? j : k);
+  const int nD = D == 0 ? nx : (D == 1 ? ny : nz);
+  const long long sD = D == 0 ? 1 : (D == 1 ? nx : plane);
+  const bool hasm = pos > 0, hasp = pos < nD - 1;
+  X.c = c;
+  X.cm = hasm ? c - sD : c;
+  X.cp = hasp ? c + sD : c;
+  X.phi = A.phi[c];
+  X.act = A.act[c] != 0;
+  X.phim = A.phi[X.cm];
+  X.phip = A.phi[X.cp];
+  X.dxc = A.dx[i];
+  X.dyc = A.dy[j];
+  X.dzc = A.dz[k];
+  // the donor volumes (dz dy) dx of the two neighbours along D
+  const int im = D == 0 && hasm ? i - 1 : i, ip = D == 0 && hasp ? i + 1 : i;
+  const int jm = D == 1 && hasm ? j - 1 : j, jp = D == 1 && hasp ? j + 1 : j;
+  const int km = D == 2 && hasm ? k - 1 : k, kp = D == 2 && hasp ? k + 1 : k;
+  const double dxm = A.dx[im], dxp = A.dx[ip], dym = A.dy[jm], dyp = A.dy[jp], dzm = A.dz[km], dzp = A.dz[kp];
+  X.wm = D == 0 ? dxm : (D == 1 ? dym : dzm);
+  X.wp = D == 0 ? dxp : (D == 1 ? dyp : dzp);
+  X.vm = (dzm * dym) * dxm;
+  X.vp_ = (dzp * dyp) * dxp;
+  const long long fxm = ((long long)k * ny + j) * (nx + 1) + i;
+  const long long fym = ((long long)k * (ny + 1) + j) * nx + i;
+  if (D == 0 || D == 2) {
+    X.a[0] = A.ox[fxm];
+    X.a[1] = A.u[fxm];
+    X.a[2] = A.ox[fxm + 1];
+    X.a[3] = A.u[fxm + 1];
+  }
+  if (D == 1 || D == 2) {
+    X.a[4] = A.oy[fym];
+    X.a[5] = A.v[fym];
+    X.a[6] = A.oy[fym + nx];
+    X.a[7] = A.v[fym + nx];
+  }
+  if (D == 2) {
+    X.a[8] = A.oz[c];
+    X.a[9] = A.w[c];
+    X.a[10] = A.oz[c + plane];
+    X.a[11] = A.w[c + plane];
+  }
+}
+
+template <int D, bool IMPLICIT>
+__device__ __forceinline__ void update_cell(const Sweep& A, const double4* __restrict__ planes, const CellIn& X) {
+  if (!X.valid) return;
+  if (!X.act) {
+    A.out[X.c] = X.phi;
+    return;
+  }
+  const double dt = A.dt;
+  const double V = (X.dzc * X.dyc) * X.dxc;
+  double lo, up;
+  if (D == 0) {
+    lo = (X.dxc * (X.a[0] * X.a[1])) / V;
+    up = (X.dxc * (X.a[2] * X.a[3])) / V;
+  } else if (D == 1) {
+    lo = (X.dyc * (X.a[4] * X.a[5])) / V;
+    up = (X.dyc * (X.a[6] * X.a[7])) / V;
+  } else {
+    const double Fxm = X.a[0] * X.a[1], Fxp = X.a[2] * X.a[3];
+    const double Fym = X.a[4] * X.a[5], Fyp = X.a[6] * X.a[7];
+    const double Azm = X.a[8], Azp = X.a[10];
+    double Fzm = Azm * X.a[9], Fzp = Azp * X.a[11];
+    const double E = ((Fxp - Fxm) + (Fyp - Fym)) + (Fzp - Fzm);
+    const double den = Azp + Azm;
+    if (den > 0.0) {
+      Fzp = Fzp - (E * Azp) / den;
+      Fzm = Fzm + (E * Azm) / den;
+    }
+    lo = (X.dzc * Fzm) / V;
+    up = (X.dzc * Fzp) / V;
+  }
+  const double wc = D == 0 ? X.dxc : (D == 1 ? X.dyc : X.dzc);
+  double f_up, f_lo;
+  if (up > 0.0) f_up = water(planes, X.c, X.phi, wc, V, D, true, up, dt);
+  else if (up < 0.0) f_up = -water(planes, X.cp, X.phip, X.wp, X.vp_, D, false, -up, dt);
+  else f_up = 0.0;
+  if (lo > 0.0) f_lo = water(planes, X.cm, X.phim, X.wm, X.vm, D, true, lo, dt);
+  else if (lo < 0.0) f_lo = -water(planes, X.c, X.phi, wc, V, D, false, -lo, dt);
+  else f_lo = 0.0;
+  const double div = (up - lo) / wc;
+  const double rest = X.phi - (f_up - f_lo) / V;
+  A.out[X.c] = IMPLICIT ? rest / (1.0 - dt * div) : rest + (dt * X.phi) * div;
+}
+
+// Two chunks per iteration: both cells' loads are in flight before either
+// is used.
+template <int D, bool IMPLICIT>
+__global__ __launch_bounds__(kBlock) void k_sweep(Sweep A, const double4* __restrict__ planes) {
+  const Chunks C = block_chunks(A.nx, A.ny * A.nz);
+  for (int q = 0; q < C.nq; q += 2) {
+    CellIn X0, X1;
+    load_cell<D>(A, C, q, X0);
+    load_cell<D>(A, C, q + 1, X1);
+    update_cell<D, IMPLICIT>(A, planes, X0);
+    update_cell<D, IMPLICIT>(A, planes, X1);
+  }
+}
+
+void launch_sweep(const Sweep& A, int d, bool implicit, const double4* planes, hipStream_t s) {
+  const int nb = std::min(kRowBlocks, A.ny * A.nz);
+  k_planes<<<nb, kBlock, 0, s>>>(A, const_cast<double4*>(planes));
+  if (d == 0) {
+    if (implicit) k_sweep<0, true><<<nb, kBlock, 0, s>>>(A, planes);
+    else k_sweep<0, false><<<nb, kBlock, 0, s>>>(A, planes);
+  } else if (d == 1) {
+    if (implicit) k_sweep<1, true><<<nb, kBlock, 0, s>>>(A, planes);
+    else k_sweep<1, false><<<nb, kBlock, 0, s>>>(A, planes);
+  } else {
+    if (implicit) k_sweep<2, true><<<nb, kBlock, 0, s>>>(A, planes);
+    else k_sweep<2, false><<<nb, kBlock, 0, s>>>(A, planes);
+  }
 }
 
 Sweep make_sweep(const Grid& g, const double* u, const double* v, const double* w, double dt) {
@@ -446,13 +490,10 @@ bool overlap(const void* a, const void* b, size_t bytes) {
 
 using namespace nfa;
 
-// Work memory of the advection: the plane table, two cell lists, their
-// counters and one fraction buffer.
+// Work memory of the advection: the plane table and one fraction buffer.
 struct nfa_vof_s {
   nfa::Grid* g = nullptr;
   nfa::DevBuf planes;    // double4 per cell
-  nfa::DevBuf lists;     // 2 x int32 per cell
-  nfa::DevBuf counters;  // 2 x int32
   nfa::DevBuf work;      // double per cell
 };
 
@@ -464,8 +505,7 @@ extern "C" nfa_status nfa_vof_create(nfa_grid g, nfa_vof* out) {
   v->g = g;
   const size_t n = (size_t)g->n;
   hipError_t e;
-  if ((e = v->planes.alloc(n * sizeof(double4))) != hipSuccess || (e = v->lists.alloc(2 * n * 4)) != hipSuccess ||
-      (e = v->counters.alloc(256)) != hipSuccess || (e = v->work.alloc(n * 8)) != hipSuccess) {
+  if ((e = v->planes.alloc(n * sizeof(double4))) != hipSuccess || (e = v->work.alloc(n * 8)) != hipSuccess) {
     delete v;
     return fail(NFA_ERR_HIP, std::string("nfa_vof_create: ") + hipGetErrorString(e));
   }
@@ -486,24 +526,6 @@ nfa_status check(const char* who, nfa_vof vf, const double* phi, const double* u
   return NFA_OK;
 }
 
-// Lists and planes of the sweeps: list 0 and counter 0 hold the cells of
-// phi, the sweep appends those of its output to list 1 and counter 1.
-struct Work {
-  double4* planes;
-  int* list[2];
-  int* count[2];
-};
-
-Work work_of(nfa_vof v) {
-  Work W;
-  W.planes = v->planes.as<double4>();
-  W.list[0] = v->lists.as<int>();
-  W.list[1] = v->lists.as<int>() + v->g->n;
-  W.count[0] = v->counters.as<int>();
-  W.count[1] = v->counters.as<int>() + 1;
-  return W;
-}
-
 }  // namespace
 
 extern "C" nfa_status nfa_vof_sweep(nfa_vof vf, const double* phi, const double* u, const double* v,
@@ -512,17 +534,10 @@ extern "C" nfa_status nfa_vof_sweep(nfa_vof vf, const double* phi, const double*
   nfa_status e = check("nfa_vof_sweep", vf, phi, u, v, w, dt, phi_out);
   if (e != NFA_OK) return e;
   if (dir < 0 || dir > 2) return fail(NFA_ERR_INVALID, "nfa_vof_sweep: dir must be 0, 1 or 2");
-  const Grid& g = *vf->g;
-  const hipStream_t st = S(s);
-  Work W = work_of(vf);
-  Sweep A = make_sweep(g, u, v, w, dt);
+  Sweep A = make_sweep(*vf->g, u, v, w, dt);
   A.phi = phi;
   A.out = phi_out;
-  k_reset<<<1, 64, 0, st>>>(W.count[0]);
-  k_scan<<<std::min(kRowBlocks, g.ny * g.nz), kBlock, 0, st>>>(g.nx, g.ny * g.nz, phi, g.active.as<unsigned char>(),
-                                                               W.list[0], W.count[0]);
-  k_planes<<<kPlaneBlocks, kBlock, 0, st>>>(A, W.list[0], W.count[0], W.planes, W.count[1]);
-  launch_sweep(A, dir, implicit != 0, false, W.planes, nullptr, nullptr, st);
+  launch_sweep(A, dir, implicit != 0, vf->planes.as<double4>(), S(s));
   NFA_CHECK_LAUNCH();
   return NFA_OK;
 }
@@ -531,25 +546,18 @@ extern "C" nfa_status nfa_vof_advect(nfa_vof vf, const double* phi, const double
                                      const double* w, double dt, int step, double* phi_out, nfa_stream s) {
   nfa_status e = check("nfa_vof_advect", vf, phi, u, v, w, dt, phi_out);
   if (e != NFA_OK) return e;
-  const Grid& g = *vf->g;
   const hipStream_t st = S(s);
-  Work W = work_of(vf);
   double* work = vf->work.as<double>();
   const int order[2][3] = {{0, 1, 2}, {2, 1, 0}};
   const int* o = order[step % 2 == 0 ? 0 : 1];
-  // phi -> phi_out -> work -> phi_out; the lists alternate 0, 1, 0
+  // phi -> phi_out -> work -> phi_out
   const double* src[3] = {phi, phi_out, work};
   double* dst[3] = {phi_out, work, phi_out};
-  Sweep A = make_sweep(g, u, v, w, dt);
-  k_reset<<<1, 64, 0, st>>>(W.count[0]);
-  k_scan<<<std::min(kRowBlocks, g.ny * g.nz), kBlock, 0, st>>>(g.nx, g.ny * g.nz, phi, g.active.as<unsigned char>(),
-                                                               W.list[0], W.count[0]);
+  Sweep A = make_sweep(*vf->g, u, v, w, dt);
   for (int p = 0; p < 3; ++p) {
-    const int cur = p & 1, nxt = cur ^ 1;
     A.phi = src[p];
     A.out = dst[p];
-    k_planes<<<kPlaneBlocks, kBlock, 0, st>>>(A, W.list[cur], W.count[cur], W.planes, W.count[nxt]);
-    launch_sweep(A, o[p], p == 2, p < 2, W.planes, W.list[nxt], W.count[nxt], st);
+    launch_sweep(A, o[p], p == 2, vf->planes.as<double4>(), st);
     NFA_CHECK_LAUNCH();
   }
   return NFA_OK;

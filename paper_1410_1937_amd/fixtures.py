@@ -376,6 +376,16 @@ def c5_step(n: int, nx=768, ny=384, nz=256, seed: int = 1) -> Workload:
                     u=u, v=v, w=w, body_vel=(0.0, 0.0, v3))
 
 
+def vof_time_step(wl: Workload, courant: float = 0.45) -> float:
+    """A VOF time step for the workload's face velocities: the velocity a
+    face can carry after the flux correction is bounded by twice the sum of
+    the three components' maxima, each over the smallest width along its
+    axis, so this step keeps every Courant number below `courant`."""
+    rate = 2.0 * (np.max(np.abs(wl.u)) / np.min(np.diff(wl.xf)) + np.max(np.abs(wl.v)) / np.min(np.diff(wl.yf))
+                  + np.max(np.abs(wl.w)) / np.min(np.diff(wl.zf)))
+    return courant / rate
+
+
 def small(seed: int, nx: int, ny: int, nz: int, body: str = "sphere", bc=ALL_NEUMANN,
           stretch: bool = True, theta: float = 0.25, smooth: bool = True) -> Workload:
     """Reduced-size ship-wave-shaped workload for parity tests."""

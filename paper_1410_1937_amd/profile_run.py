@@ -6,11 +6,14 @@ Jacobi-PCG iterations (tolerance unreachable, so every iteration runs both
 sweeps), and finally a plain device-to-device copy of known size whose
 counter readings calibrate the FETCH_SIZE / WRITE_SIZE counters to bytes.
 With --unet L it also runs --unet-reps forward passes of an L-level learned
-preconditioner on the same grid (the committed weights for L = 5).  Each
-phase prints a line when it ends.
+preconditioner on the same grid (the committed weights for L = 5).  With
+--vof N it runs N split VOF advection steps (alternating sweep order) of the
+FP64 volume fraction through the workload's face velocities.  Each phase
+prints a line when it ends.
 
     rocprofv3 --pmc FETCH_SIZE -d OUT -- python3 -m paper_1410_1937_amd.profile_run --iters 8
     rocprofv3 --kernel-trace --stats -d OUT -- python3 -m paper_1410_1937_amd.profile_run --iters 0 --unet 5
+    rocprofv3 --kernel-trace --stats -d OUT -- python3 -m paper_1410_1937_amd.profile_run --iters 0 --vof 6
 """
 from __future__ import annotations
 
@@ -24,6 +27,7 @@ def main(argv=None):
     ap.add_argument("--copy-mib", type=int, default=256, help="size of the calibration copy")
     ap.add_argument("--unet", type=int, default=0, help="levels of the learned preconditioner to run (0: none)")
     ap.add_argument("--unet-reps", type=int, default=5)
+    ap.add_argument("--vof", type=int, default=0, help="VOF advection steps to run")
     args = ap.parse_args(argv)
     import torch
     from paper_1410_1937_amd import fixtures as fx
@@ -55,6 +59,16 @@ def main(argv=None):
             net.forward(op, r)
         torch.cuda.synchronize()
         print(f"[profile_run] unet L{args.unet}: {args.unet_reps} forward passes", flush=True)
+    if args.vof:
+        vf = nfa.Vof(g)
+        phi = torch.as_tensor(wl.phi, device=dev)
+        out = torch.empty_like(phi)
+        vel = tuple(torch.as_tensor(a, device=dev) for a in (wl.u, wl.v, wl.w))
+        dt = fx.vof_time_step(wl)
+        for step in range(args.vof):
+            vf.advect(phi, *vel, dt, step, out=out)
+        torch.cuda.synchronize()
+        print(f"[profile_run] vof: {args.vof} steps", flush=True)
     n = args.copy_mib * (1 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
