@@ -15,6 +15,8 @@ of the dominant kernel (sweep A of the fused CG iteration: new direction,
 operator apply and deferred x update) with HIP events for the roofline.
 The CPU baseline is the FP64 oracle on the host cores, timed on a bounded
 sample (a few iterations on the full grid) and scaled to one projection.
+Beside the metric it times one Runge-Kutta cycle (two projections) and one
+split VOF advection step of the volume fraction on the same grid.
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu-baseline]
 """
@@ -107,6 +109,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true", help="do not time the plain FP64 projection")
     ap.add_argument("--skip-rk2", action="store_true", help="do not time the Runge-Kutta cycle")
+    ap.add_argument("--skip-vof", action="store_true", help="do not time the VOF advection step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the projection runs on a single MI355X with no "
@@ -207,6 +210,35 @@ def main():
                         "solve + velocity"}
         log(f"[bench] Runge-Kutta cycle: {rk2['ms']:.1f} ms, iterations {rk2['iterations']}")
 
+    # one split VOF advection step of the FP64 volume fraction on the same
+    # grid (3 plane launches + 3 directional sweeps); algorithmic bytes per
+    # cell: each plane launch reads phi and the active flag (9 B), the x- and
+    # y-sweeps read phi, the flag and one face array pair and write phi
+    # (33 B each), the z-sweep reads all six face arrays (65 B): 158 B
+    vof = None
+    if not args.skip_vof:
+        vf = nfa.Vof(g)
+        phi64 = torch.as_tensor(wl.phi, device=dev)
+        out = torch.empty_like(phi64)
+        dt_vof = fx.vof_time_step(wl)
+        for i in range(2):
+            vf.advect(phi64, u, v, w, dt_vof, i, out=out)
+        torch.cuda.synchronize()
+        reps = 10
+        t0 = time.perf_counter()
+        for i in range(reps):
+            vf.advect(phi64, u, v, w, dt_vof, i, out=out)
+        torch.cuda.synchronize()
+        ms_vof = (time.perf_counter() - t0) * 1e3 / reps
+        gbs = 158 * wl.ncells / (ms_vof * 1e-3) / 1e9
+        vof = {"ms_per_step": round(ms_vof, 4), "steps_timed": reps, "dtype": "f64",
+               "cells_per_s": round(wl.ncells / (ms_vof * 1e-3), 1),
+               "algorithmic_bytes_per_cell": 158, "achieved_GBs": round(gbs, 1),
+               "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+               "courant": 0.45, "step": "planes + sweep x3, order alternating"}
+        log(f"[bench] VOF step: {ms_vof:.3f} ms ({gbs:.0f} GB/s algorithmic)")
+        del vf, phi64, out
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle)")
@@ -242,6 +274,7 @@ def main():
             "speedup_of_value": round(ms_fp64 / ms_chosen, 3)},
         "cell_updates_per_s": round(n * its_chosen[-1] / (ms_chosen * 1e-3), 1),
         "rk2_cycle": rk2,
+        "vof_step": vof,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -440,6 +440,111 @@ __global__ __launch_bounds__(kBlock) void k_sweep(Sweep A, const double4* __rest
   }
 }
 
+// What the z sweep loads for plane k of its column: the fraction above,
+// the upper z-face, the flag and the x- and y-faces of the cell.
+struct ZIn {
+  double phip, Azp, wzp, ox0, u0, ox1, u1, oy0, v0, oy1, v1;
+  unsigned char act;
+};
+
+__device__ __forceinline__ void load_z(const Sweep& A, long long c, int k, long long fxm, long long fym, ZIn& Z) {
+  const long long plane = (long long)A.nx * A.ny;
+  Z.phip = A.phi[k < A.nz - 1 ? c + plane : c];
+  Z.Azp = A.oz[c + plane];
+  Z.wzp = A.w[c + plane];
+  Z.act = A.act[c];
+  Z.ox0 = A.ox[fxm];
+  Z.u0 = A.u[fxm];
+  Z.ox1 = A.ox[fxm + 1];
+  Z.u1 = A.u[fxm + 1];
+  Z.oy0 = A.oy[fym];
+  Z.v0 = A.v[fym];
+  Z.oy1 = A.oy[fym + A.nx];
+  Z.v1 = A.v[fym + A.nx];
+}
+
+// The z sweep marches up columns: a block takes one chunk of an x-line (j)
+// over a segment of planes; the fraction below, the cell's own fraction and
+// the lower z-face come from the previous plane in registers, so each is
+// read from memory once, and the next plane's inputs are loaded before the
+// current one is computed.  Neighbouring logical blocks take neighbouring j,
+// so the y-faces a block shares with the next line are read on one XCD.
+template <bool IMPLICIT>
+__global__ __launch_bounds__(kBlock) void k_sweep_z(Sweep A, const double4* __restrict__ planes, int nseg) {
+  const int nx = A.nx, ny = A.ny, nz = A.nz;
+  const int cpr = (nx + blockDim.x - 1) / blockDim.x;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int chunk = lb % cpr, j = (lb / cpr) % ny, seg = lb / (cpr * ny);
+  const int per = (nz + nseg - 1) / nseg;
+  const int k0 = seg * per, k1 = min(nz, k0 + per);
+  if (seg >= nseg || k0 >= k1) return;
+  const int i = chunk * (int)blockDim.x + threadIdx.x;
+  const bool valid = i < nx;
+  const int ic = valid ? i : 0;
+  const long long plane = (long long)nx * ny;
+  const double dxc = A.dx[ic], dyc = A.dy[j];
+  long long c = ((long long)k0 * ny + j) * nx + ic;
+  long long fxm = ((long long)k0 * ny + j) * (nx + 1) + ic;
+  long long fym = ((long long)k0 * (ny + 1) + j) * nx + ic;
+  const long long sfx = (long long)ny * (nx + 1), sfy = (long long)(ny + 1) * nx;
+  double phim = A.phi[k0 > 0 ? c - plane : c];
+  double phi = A.phi[c];
+  double Azm = A.oz[c], wzm = A.w[c];
+  ZIn cur, nxt;
+  load_z(A, c, k0, fxm, fym, cur);
+  for (int k = k0; k < k1; ++k) {
+    if (k + 1 < k1) load_z(A, c + plane, k + 1, fxm + sfx, fym + sfy, nxt);
+    const int km = k > 0 ? k - 1 : k, kp = k < nz - 1 ? k + 1 : k;
+    CellIn X;
+    X.valid = valid;
+    X.i = ic;
+    X.j = j;
+    X.k = k;
+    X.c = c;
+    X.cm = k > 0 ? c - plane : c;
+    X.cp = k < nz - 1 ? c + plane : c;
+    X.act = cur.act != 0;
+    X.phi = phi;
+    X.phim = phim;
+    X.phip = cur.phip;
+    X.dxc = dxc;
+    X.dyc = dyc;
+    X.dzc = A.dz[k];
+    const double dzm = A.dz[km], dzp = A.dz[kp];
+    X.wm = dzm;
+    X.wp = dzp;
+    X.vm = (dzm * dyc) * dxc;
+    X.vp_ = (dzp * dyc) * dxc;
+    X.a[0] = cur.ox0;
+    X.a[1] = cur.u0;
+    X.a[2] = cur.ox1;
+    X.a[3] = cur.u1;
+    X.a[4] = cur.oy0;
+    X.a[5] = cur.v0;
+    X.a[6] = cur.oy1;
+    X.a[7] = cur.v1;
+    X.a[8] = Azm;
+    X.a[9] = wzm;
+    X.a[10] = cur.Azp;
+    X.a[11] = cur.wzp;
+    update_cell<2, IMPLICIT>(A, planes, X);
+    phim = phi;
+    phi = cur.phip;
+    Azm = cur.Azp;
+    wzm = cur.wzp;
+    cur = nxt;
+    c += plane;
+    fxm += sfx;
+    fym += sfy;
+  }
+}
+
+// Segments of the z columns: enough blocks to fill the chip.
+int z_segments(const Sweep& A) {
+  const int cols = ((A.nx + kBlock - 1) / kBlock) * A.ny;
+  return std::max(1, std::min(A.nz, (kRowBlocks + cols - 1) / cols));
+}
+
 void launch_sweep(const Sweep& A, int d, bool implicit, const double4* planes, hipStream_t s) {
   const int nb = std::min(kRowBlocks, A.ny * A.nz);
   k_planes<<<nb, kBlock, 0, s>>>(A, const_cast<double4*>(planes));
@@ -450,8 +555,10 @@ void launch_sweep(const Sweep& A, int d, bool implicit, const double4* planes, h
     if (implicit) k_sweep<1, true><<<nb, kBlock, 0, s>>>(A, planes);
     else k_sweep<1, false><<<nb, kBlock, 0, s>>>(A, planes);
   } else {
-    if (implicit) k_sweep<2, true><<<nb, kBlock, 0, s>>>(A, planes);
-    else k_sweep<2, false><<<nb, kBlock, 0, s>>>(A, planes);
+    const int nseg = z_segments(A);
+    const int nbz = ((A.nx + kBlock - 1) / kBlock) * A.ny * nseg;
+    if (implicit) k_sweep_z<true><<<nbz, kBlock, 0, s>>>(A, planes, nseg);
+    else k_sweep_z<false><<<nbz, kBlock, 0, s>>>(A, planes, nseg);
   }
 }
 
