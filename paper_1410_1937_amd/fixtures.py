@@ -376,6 +376,74 @@ def c5_step(n: int, nx=768, ny=384, nz=256, seed: int = 1) -> Workload:
                     u=u, v=v, w=w, body_vel=(0.0, 0.0, v3))
 
 
+# --------------------------------------------------------------------------
+# triangulated body surfaces (panels (m, 3, 3), outward-oriented)
+# --------------------------------------------------------------------------
+def box_panels(lo, hi) -> np.ndarray:
+    """The 12 triangles of an axis-aligned box, outward normals."""
+    lo, hi = np.asarray(lo, dtype=np.float64), np.asarray(hi, dtype=np.float64)
+    corner = lambda i, j, k: np.array([(lo, hi)[i][0], (lo, hi)[j][1], (lo, hi)[k][2]])
+    quads = [((0, 0, 0), (0, 1, 0), (1, 1, 0), (1, 0, 0)),    # z = lo (normal -z)
+             ((0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)),    # z = hi
+             ((0, 0, 0), (1, 0, 0), (1, 0, 1), (0, 0, 1)),    # y = lo
+             ((0, 1, 0), (0, 1, 1), (1, 1, 1), (1, 1, 0)),    # y = hi
+             ((0, 0, 0), (0, 0, 1), (0, 1, 1), (0, 1, 0)),    # x = lo
+             ((1, 0, 0), (1, 1, 0), (1, 1, 1), (1, 0, 1))]    # x = hi
+    tris = []
+    for q in quads:
+        v = [corner(*c) for c in q]
+        tris += [(v[0], v[1], v[2]), (v[0], v[2], v[3])]
+    return np.array(tris)
+
+
+def icosphere_panels(radius=0.1, centre=(0.0, 0.0, -0.15), levels=3) -> np.ndarray:
+    """A sphere triangulated by `levels` midpoint subdivisions of an
+    icosahedron (20 * 4**levels triangles), vertices on the sphere."""
+    t = (1.0 + 5 ** 0.5) / 2.0
+    v = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    f = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2), (10, 7, 6),
+         (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5), (2, 4, 11), (6, 2, 10),
+         (8, 6, 7), (9, 8, 1)]
+    tris = np.array([[v[a], v[b], v[c]] for a, b, c in f], dtype=np.float64)
+    tris /= np.linalg.norm(tris, axis=-1, keepdims=True)
+    for _ in range(levels):
+        a, b, c = tris[:, 0], tris[:, 1], tris[:, 2]
+        ab, bc, ca = ((x + y) for x, y in ((a, b), (b, c), (c, a)))
+        ab, bc, ca = (m / np.linalg.norm(m, axis=-1, keepdims=True) for m in (ab, bc, ca))
+        tris = np.concatenate([np.stack(q, axis=1) for q in ((a, ab, ca), (ab, b, bc), (ca, bc, c), (ab, bc, ca))])
+    if np.mean(np.sum(np.cross(tris[:, 1] - tris[:, 0], tris[:, 2] - tris[:, 0]) * tris[:, 0], axis=-1)) < 0:
+        tris = tris[:, ::-1]
+    return tris * radius + np.asarray(centre, dtype=np.float64)
+
+
+def wigley_panels(length=0.5, beam=0.05, draft=0.03125, freeboard=0.02, nx=40, nz=10) -> np.ndarray:
+    """A closed Wigley-type hull: half-breadth y = (B/2)(1 - (2x/L)^2)(1 - (z/T)^2)
+    below the waterline z = 0, vertical sides up to a flat deck at z = freeboard;
+    the two sides meet on the keel and at bow and stern.  Outward normals."""
+    xs = np.linspace(-length / 2, length / 2, nx + 1)
+    zs = np.concatenate([np.linspace(-draft, 0.0, nz + 1), [freeboard]])
+    def half(x, z):
+        return 0.5 * beam * (1 - (2 * x / length) ** 2) * (1 - (min(z, 0.0) / draft) ** 2)
+    tris = []
+    for side in (1.0, -1.0):
+        P = [[np.array([x, side * half(x, z), z]) for z in zs] for x in xs]
+        for i in range(nx):
+            for k in range(len(zs) - 1):
+                a, b, c, d = P[i][k], P[i + 1][k], P[i + 1][k + 1], P[i][k + 1]
+                tris += [(a, b, c), (a, c, d)] if side < 0 else [(a, c, b), (a, d, c)]
+    top = freeboard
+    for i in range(nx):
+        x0, x1 = xs[i], xs[i + 1]
+        a, b = np.array([x0, -half(x0, top), top]), np.array([x1, -half(x1, top), top])
+        c, d = np.array([x1, half(x1, top), top]), np.array([x0, half(x0, top), top])
+        tris += [(a, b, c), (a, c, d)]
+    tris = np.array(tris)
+    area = np.cross(tris[:, 1] - tris[:, 0], tris[:, 2] - tris[:, 0])
+    keep = np.linalg.norm(area, axis=-1) > 1e-14 * length ** 2      # drop the degenerate panels at bow and stern
+    return tris[keep]
+
+
 def vof_time_step(wl: Workload, courant: float = 0.45) -> float:
     """A VOF time step for the workload's face velocities: the velocity a
     face can carry after the flux correction is bounded by twice the sum of
