@@ -98,6 +98,44 @@ nfa_status nfa_grid_create(int nx, int ny, int nz, const double* xf, const doubl
  * inactive (no unknown).  Synchronous (merge groups are resolved on the
  * host).  Errors: NFA_ERR_INVALID, NFA_ERR_HIP.
  */
+/* nfa_stretch_axis -- face coordinates of one stretched axis (Gridding
+ * section, eq. grid): the n + 1 nodes x_0 = a < ... < x_n = b that solve
+ * (w x_xi)_xi = 0 in its conservative discrete form
+ *   w(m_{i+1/2}) (x_{i+1} - x_i) = w(m_{i-1/2}) (x_i - x_{i-1}),
+ * m the midpoints, by Picard iteration from uniform nodes (weights frozen at
+ * the current midpoints, the tridiagonal system solved exactly) until no
+ * node moves by more than tol (b - a).  The weight is levels[0] before the
+ * first transition zone, the section's cosine transition
+ *   w = (w0 - w1)/2 (1 + cos(pi (x - x0)/(x1 - x0))) + w1
+ * from levels[k] to levels[k+1] across zone k = [zones[2k], zones[2k+1]],
+ * and levels[k+1] after it; a large weight clusters nodes (the spacing is
+ * inversely proportional to w).
+ *   levels : HOST, nzones + 1 finite weights > 0.
+ *   zones  : HOST, 2 nzones coordinates, increasing, not overlapping.
+ *   nodes  : HOST out, n + 1 doubles (pass them to nfa_grid_create).
+ *   iterations : HOST out, sweeps taken.
+ * Runs on the host (no device work).  Returns NFA_OK, NFA_NOT_CONVERGED
+ * after max_iter sweeps (nodes filled with the last iterate), or
+ * NFA_ERR_INVALID. */
+nfa_status nfa_stretch_axis(double a, double b, int n, int nzones, const double* levels,
+                            const double* zones, double tol, int max_iter, double* nodes,
+                            int* iterations);
+
+/* nfa_panels_psi -- signed distance psi of a triangulated body at the grid
+ * nodes (Enforcement of Body Boundary Conditions section): the least
+ * distance to the panels (closest point inside a panel, on an edge or at a
+ * vertex), negative inside the body and positive outside, inside told by
+ * Gauss's theorem on the solid angle the panels subtend (4 pi inside, 0
+ * outside a closed surface; a node outside the panels' bounding box is
+ * outside).  FP64.
+ *   panels : DEVICE double, m panels of 9 values: vertices a, b, c as
+ *            (x, y, z); a closed surface, consistently oriented.
+ *   psi    : DEVICE double, node array [nz+1][ny+1][nx+1] (output; feed it
+ *            to nfa_grid_set_body).
+ * Allocates and frees 48 bytes of device memory; synchronous.  Errors:
+ * NFA_ERR_INVALID (NULL, m < 1 or m > 2^30), NFA_ERR_HIP. */
+nfa_status nfa_panels_psi(nfa_grid g, const double* panels, long long m, double* psi, nfa_stream s);
+
 nfa_status nfa_grid_set_body(nfa_grid g, const double* psi_nodes, double theta, int samples,
                              nfa_stream s);
 

@@ -477,6 +477,9 @@ extern "C" nfa_status nfa_grid_create(int nx, int ny, int nz, const double* xf, 
   if ((e = upload(g->d_gx, normal_den(g->xf))) != hipSuccess) return bad(e);
   if ((e = upload(g->d_gy, normal_den(g->yf))) != hipSuccess) return bad(e);
   if ((e = upload(g->d_gz, normal_den(g->zf))) != hipSuccess) return bad(e);
+  if ((e = upload(g->d_xf, g->xf)) != hipSuccess) return bad(e);
+  if ((e = upload(g->d_yf, g->yf)) != hipSuccess) return bad(e);
+  if ((e = upload(g->d_zf, g->zf)) != hipSuccess) return bad(e);
   const long long n = g->n;
   if ((e = g->frac_x.alloc(g->nfx() * 8)) != hipSuccess) return bad(e);
   if ((e = g->frac_y.alloc(g->nfy() * 8)) != hipSuccess) return bad(e);

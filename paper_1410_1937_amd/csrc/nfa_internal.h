@@ -71,6 +71,7 @@ struct Grid {
   // device 1-D metrics
   DevBuf d_dx, d_dy, d_dz, d_hx, d_hy, d_hz;
   DevBuf d_gx, d_gy, d_gz;            // centre-to-centre spans of the normal stencil (n each)
+  DevBuf d_xf, d_yf, d_zf;            // face coordinates (n+1 each)
   // body (always present: "no body" = all open)
   bool has_body = false;
   DevBuf frac_x, frac_y, frac_z;      // face fractions (double)

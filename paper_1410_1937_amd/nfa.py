@@ -126,6 +126,9 @@ _sig("nfa_faces_combine", c_int, [c_ll, c_void_p, c_void_p, c_double, c_void_p, 
 _sig("nfa_poisson_rhs_cells", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p,
                                       c_void_p, c_void_p, c_void_p])
 _sig("nfa_exit_velocity", c_int, [c_void_p, c_void_p, c_double, c_double, c_void_p, c_void_p])
+_sig("nfa_stretch_axis", c_int, [c_double, c_double, c_int, c_int, c_void_p, c_void_p, c_double, c_int, c_void_p,
+                                 ctypes.POINTER(c_int)])
+_sig("nfa_panels_psi", c_int, [c_void_p, c_void_p, c_ll, c_void_p, c_void_p])
 _sig("nfa_vof_create", c_int, [c_void_p, ctypes.POINTER(c_void_p)])
 _sig("nfa_vof_destroy", None, [c_void_p])
 _sig("nfa_vof_sweep", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int, c_int,
@@ -148,6 +151,24 @@ def faces_combine(a, b, s, c, out=None):
                                  s, c_void_p(c.data_ptr()), c_void_p(out.data_ptr()), _stream()),
            "nfa_faces_combine")
     return out
+
+
+def stretch_axis(a, b, n, levels, zones=(), tol=1e-13, max_iter=500):
+    """Nodes of one stretched axis and the sweeps taken (nfa_stretch_axis);
+    zones is a sequence of (x0, x1) transitions between consecutive levels.
+    Raises if the iteration did not converge."""
+    lv = np.ascontiguousarray(levels, dtype=np.float64)
+    zn = np.ascontiguousarray(np.asarray(zones, dtype=np.float64).reshape(-1))
+    if len(lv) != len(zn) // 2 + 1:
+        raise ValueError("need one more level than transition zones")
+    out = np.empty(n + 1)
+    it = c_int()
+    st = lib.nfa_stretch_axis(a, b, n, len(zn) // 2, lv.ctypes.data, zn.ctypes.data if len(zn) else None, tol,
+                              max_iter, out.ctypes.data, ctypes.byref(it))
+    _check(st, "nfa_stretch_axis")
+    if st != 0:
+        raise NFAError(f"nfa_stretch_axis did not converge in {it.value} sweeps")
+    return out, it.value
 
 
 def _check(st, what):
@@ -189,6 +210,17 @@ class Grid:
         ptr = None if psi is None else _dev(psi, torch.float64,
                                              (self.nz + 1, self.ny + 1, self.nx + 1), "psi")
         _check(lib.nfa_grid_set_body(self.h, ptr, theta, samples, _stream()), "nfa_grid_set_body")
+
+    def panels_psi(self, panels, out=None):
+        """Signed distance of a triangulated body at the nodes (nfa_panels_psi);
+        panels: (m, 3, 3) FP64 device tensor."""
+        if panels.ndim != 3 or tuple(panels.shape[1:]) != (3, 3):
+            raise ValueError("panels must have shape (m, 3, 3)")
+        shape = (self.nz + 1, self.ny + 1, self.nx + 1)
+        out = torch.empty(shape, dtype=torch.float64, device=panels.device) if out is None else out
+        _check(lib.nfa_panels_psi(self.h, _dev(panels, torch.float64, None, "panels"), panels.shape[0],
+                                  _dev(out, torch.float64, shape, "psi"), _stream()), "nfa_panels_psi")
+        return out
 
     def exit_velocity(self, uk_x, uc, dt, ut_x=None):
         """Exit-plane x-velocity of the radiation condition (nfa_exit_velocity);

@@ -8,8 +8,10 @@ counter readings calibrate the FETCH_SIZE / WRITE_SIZE counters to bytes.
 With --unet L it also runs --unet-reps forward passes of an L-level learned
 preconditioner on the same grid (the committed weights for L = 5).  With
 --vof N it runs N split VOF advection steps (alternating sweep order) of the
-FP64 volume fraction through the workload's face velocities.  Each phase
-prints a line when it ends.
+FP64 volume fraction through the workload's face velocities.  With --psi L
+it computes the signed distance of an L-times subdivided icosphere (the
+workload's sphere) at the grid nodes three times.  Each phase prints a line
+when it ends.
 
     rocprofv3 --pmc FETCH_SIZE -d OUT -- python3 -m paper_1410_1937_amd.profile_run --iters 8
     rocprofv3 --kernel-trace --stats -d OUT -- python3 -m paper_1410_1937_amd.profile_run --iters 0 --unet 5
@@ -28,6 +30,7 @@ def main(argv=None):
     ap.add_argument("--unet", type=int, default=0, help="levels of the learned preconditioner to run (0: none)")
     ap.add_argument("--unet-reps", type=int, default=5)
     ap.add_argument("--vof", type=int, default=0, help="VOF advection steps to run")
+    ap.add_argument("--psi", type=int, default=-1, help="icosphere subdivision levels for the signed distance")
     args = ap.parse_args(argv)
     import torch
     from paper_1410_1937_amd import fixtures as fx
@@ -69,6 +72,13 @@ def main(argv=None):
             vf.advect(phi, *vel, dt, step, out=out)
         torch.cuda.synchronize()
         print(f"[profile_run] vof: {args.vof} steps", flush=True)
+    if args.psi >= 0:
+        tri = torch.as_tensor(fx.icosphere_panels(0.1, (0.0, 0.0, -0.15), levels=args.psi), device=dev)
+        psi = g.panels_psi(tri)
+        for _ in range(2):
+            g.panels_psi(tri, out=psi)
+        torch.cuda.synchronize()
+        print(f"[profile_run] psi: 3 x {tri.shape[0]} panels", flush=True)
     n = args.copy_mib * (1 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
