@@ -15,8 +15,10 @@ of the dominant kernel (sweep A of the fused CG iteration: new direction,
 operator apply and deferred x update) with HIP events for the roofline.
 The CPU baseline is the FP64 oracle on the host cores, timed on a bounded
 sample (a few iterations on the full grid) and scaled to one projection.
-Beside the metric it times one Runge-Kutta cycle (two projections) and one
-split VOF advection step of the volume fraction on the same grid.
+Beside the metric it times one Runge-Kutta cycle (two projections), one
+split VOF advection step of the volume fraction on the same grid, and the
+set-up geometry (signed distance of a panelled sphere at the grid nodes, one
+stretched axis).
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu-baseline]
 """
@@ -110,6 +112,7 @@ def main():
     ap.add_argument("--skip-fp64", action="store_true", help="do not time the plain FP64 projection")
     ap.add_argument("--skip-rk2", action="store_true", help="do not time the Runge-Kutta cycle")
     ap.add_argument("--skip-vof", action="store_true", help="do not time the VOF advection step")
+    ap.add_argument("--skip-setup", action="store_true", help="do not time the set-up geometry")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the projection runs on a single MI355X with no "
@@ -239,6 +242,27 @@ def main():
         log(f"[bench] VOF step: {ms_vof:.3f} ms ({gbs:.0f} GB/s algorithmic)")
         del vf, phi64, out
 
+    # set-up geometry: the signed distance of a 5120-panel sphere (the
+    # workload's body) at the 25.4M grid nodes, and one stretched axis
+    setup = None
+    if not args.skip_setup:
+        tri = torch.as_tensor(fx.icosphere_panels(0.1, (0.0, 0.0, -0.15), levels=4), device=dev)
+        psi = g.panels_psi(tri)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            g.panels_psi(tri, out=psi)
+        torch.cuda.synchronize()
+        ms_psi = (time.perf_counter() - t0) * 1e3 / 3
+        t0 = time.perf_counter()
+        nodes, sweeps = nfa.stretch_axis(-0.75, 0.75, 512, (1.0, 8.0, 1.0, 8.0, 1.0),
+                                         ((-0.2, -0.12), (-0.08, 0.0), (0.0, 0.08), (0.12, 0.2)))
+        ms_axis = (time.perf_counter() - t0) * 1e3
+        setup = {"panels_psi_ms": round(ms_psi, 3), "panels": int(tri.shape[0]), "nodes": int(psi.numel()),
+                 "stretch_axis_ms": round(ms_axis, 3), "stretch_axis_nodes": 513, "stretch_axis_sweeps": sweeps}
+        log(f"[bench] signed distance: {ms_psi:.1f} ms; stretched axis: {ms_axis:.2f} ms ({sweeps} sweeps)")
+        del tri, psi
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle)")
@@ -275,6 +299,7 @@ def main():
         "cell_updates_per_s": round(n * its_chosen[-1] / (ms_chosen * 1e-3), 1),
         "rk2_cycle": rk2,
         "vof_step": vof,
+        "setup_geometry": setup,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

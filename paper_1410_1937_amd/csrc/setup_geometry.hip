@@ -14,8 +14,10 @@
 // and streamed through LDS in tiles of 128 (each block derives a tile's edge
 // vectors and normal once).  A brick skips a whole tile when the tile's box
 // is farther from the brick's box than an upper bound of every node's
-// distance (the nearest tile vertex), unless the brick meets the panels'
-// bounding box, where every node needs every tile's solid angle.  Per node:
+// distance (the nearest sub-tile vertex), unless the brick meets the panels'
+// bounding box, where every node needs every tile's solid angle; a node
+// skips each 32-panel sub-tile whose box is farther than its best distance
+// so far, which starts at its own bound.  Per node:
 //   - the least squared distance to the panels: to the foot of the
 //     perpendicular when it falls inside the triangle, else to the nearest
 //     of its three edges; a tile whose bounding box is farther than the best
@@ -26,7 +28,8 @@
 //     mesh's bounding box is outside and skips the sum.
 // psi = -sqrt(d2) inside, +sqrt(d2) outside, in FP64.
 //
-// Built with -ffp-contract=off.
+// Built with -ffp-contract=off; the signed-distance kernel alone allows FMA
+// contraction.
 #include <algorithm>
 #include <cmath>
 #include <utility>
@@ -56,6 +59,7 @@ double stretch_weight(double x, int nz, const double* lv, const double* zn) {
 // ------------------------------------------------------- signed distance
 constexpr int kPsiBlock = 256;
 constexpr int kTile = 128;
+constexpr int kSub = 32;        // panels per culling sub-tile (kTile / kSub per tile)
 
 struct Box {
   double lo[3], hi[3];
@@ -98,9 +102,9 @@ __device__ __forceinline__ double seg_d2(double qx, double qy, double qz, double
   return (dx * dx + dy * dy) + dz * dz;
 }
 
-// Bounding box of each tile of kTile consecutive (sorted) panels.
+// Bounding box of each sub-tile of kSub consecutive (sorted) panels.
 __global__ __launch_bounds__(kPsiBlock) void k_tile_boxes(const double* __restrict__ tri, int m, Box* __restrict__ out) {
-  const int ntiles = (m + kTile - 1) / kTile;
+  const int ntiles = (m + kSub - 1) / kSub;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += gridDim.x * blockDim.x) {
     Box B;
 #pragma unroll
@@ -108,8 +112,8 @@ __global__ __launch_bounds__(kPsiBlock) void k_tile_boxes(const double* __restri
       B.lo[d] = INFINITY;
       B.hi[d] = -INFINITY;
     }
-    const int p1 = min(m, (t + 1) * kTile);
-    for (int p = t * kTile; p < p1; ++p)
+    const int p1 = min(m, (t + 1) * kSub);
+    for (int p = t * kSub; p < p1; ++p)
       for (int v = 0; v < 3; ++v)
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -127,8 +131,11 @@ constexpr int kBx = 8, kBy = 8, kBz = 4;
 __global__ __launch_bounds__(kPsiBlock) void k_psi(int nx1, int ny1, int nz1, const double* __restrict__ xf,
                                                    const double* __restrict__ yf, const double* __restrict__ zf,
                                                    const double* __restrict__ tri, int m,
-                                                   const Box* __restrict__ tiles, const Box* __restrict__ box,
+                                                   const Box* __restrict__ subs, const Box* __restrict__ box,
                                                    double* __restrict__ psi) {
+  // psi is held to the oracle by tolerance, not bitwise, so products and
+  // sums may fuse into FMAs here (the library is otherwise built without)
+#pragma clang fp contract(fast)
   // tile of panels: vertices, edge vectors, scaled in-plane coordinate
   // vectors u1 = (e1 x n)/|n|^2, u2 = (n x e0)/|n|^2, normal, 1/|n|^2 and
   // the inverse squared edge lengths
@@ -150,12 +157,12 @@ __global__ __launch_bounds__(kPsiBlock) void k_psi(int nx1, int ny1, int nz1, co
   bool brick_meets_box = true;
 #pragma unroll
   for (int d = 0; d < 3; ++d) brick_meets_box = brick_meets_box && bhi[d] >= box->lo[d] && blo[d] <= box->hi[d];
-  const int ntiles = (m + kTile - 1) / kTile;
-  // an upper bound of each node's distance: the nearest of the tiles' first
-  // vertices (all on the surface); the brick takes the largest
+  const int ntiles = (m + kTile - 1) / kTile, nsubs = (m + kSub - 1) / kSub;
+  // an upper bound of each node's distance: the nearest of the sub-tiles'
+  // first vertices (all on the surface); the brick takes the largest
   double ub = INFINITY;
-  for (int t = 0; t < ntiles; ++t) {
-    const double* v = tri + 9LL * t * kTile;
+  for (int t = 0; t < nsubs; ++t) {
+    const double* v = tri + 9LL * t * kSub;
     const double dx = px - v[0], dy = py - v[1], dz = pz - v[2];
     ub = fmin(ub, (dx * dx + dy * dy) + dz * dz);
   }
@@ -166,9 +173,20 @@ __global__ __launch_bounds__(kPsiBlock) void k_psi(int nx1, int ny1, int nz1, co
     __syncthreads();
   }
   const double brick_ub = s_red[0];
-  double best = INFINITY, omega = 0.0;
+  // the node's own bound starts its running minimum: the tile holding the
+  // true minimum is never culled (its box is no farther than that minimum)
+  double best = ub, omega = 0.0;
   for (int tile = 0; tile < ntiles; ++tile) {
-    const Box T = tiles[tile];
+    const int s0 = tile * (kTile / kSub), s1 = min(nsubs, s0 + kTile / kSub);
+    Box T = subs[s0];
+    for (int u = s0 + 1; u < s1; ++u) {
+      const Box U = subs[u];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        T.lo[d] = fmin(T.lo[d], U.lo[d]);
+        T.hi[d] = fmax(T.hi[d], U.hi[d]);
+      }
+    }
     double g2 = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -224,13 +242,16 @@ __global__ __launch_bounds__(kPsiBlock) void k_psi(int nx1, int ny1, int nz1, co
     }
     __syncthreads();
     if (!valid) continue;
-    // distance: skip the tile when its box is farther than this node's best
-    const double gx = fmax(fmax(T.lo[0] - px, 0.0), px - T.hi[0]);
-    const double gy = fmax(fmax(T.lo[1] - py, 0.0), py - T.hi[1]);
-    const double gz = fmax(fmax(T.lo[2] - pz, 0.0), pz - T.hi[2]);
-    const double box_d2 = (gx * gx + gy * gy) + gz * gz;
-    if (!(box_d2 > best)) {
-      for (int t = 0; t < nt; ++t) {
+    // distance: skip a sub-tile when its box is farther than this node's best
+    for (int u = s0; u < s1; ++u) {
+      const Box U = subs[u];
+      const double gx = fmax(fmax(U.lo[0] - px, 0.0), px - U.hi[0]);
+      const double gy = fmax(fmax(U.lo[1] - py, 0.0), py - U.hi[1]);
+      const double gz = fmax(fmax(U.lo[2] - pz, 0.0), pz - U.hi[2]);
+      const double box_d2 = (gx * gx + gy * gy) + gz * gz;
+      if (box_d2 > best) continue;
+      const int ta = (u - s0) * kSub, tb = min(nt, ta + kSub);
+      for (int t = ta; t < tb; ++t) {
         const double ax = px - s_a[0][t], ay = py - s_a[1][t], az = pz - s_a[2][t];
         const double inn = s_inn[t];
         double d2;
@@ -379,9 +400,9 @@ extern "C" nfa_status nfa_panels_psi(nfa_grid g, const double* panels, long long
   panels = tri.as<double>();
   k_panel_box<<<1, kPsiBlock, 0, st>>>(panels, m, box.as<Box>());
   NFA_CHECK_LAUNCH();
-  const int ntiles = (int)((m + kTile - 1) / kTile);
-  NFA_HIP(tiles.alloc((size_t)ntiles * sizeof(Box)));
-  k_tile_boxes<<<(ntiles + kPsiBlock - 1) / kPsiBlock, kPsiBlock, 0, st>>>(panels, (int)m, tiles.as<Box>());
+  const int nsubs = (int)((m + kSub - 1) / kSub);
+  NFA_HIP(tiles.alloc((size_t)nsubs * sizeof(Box)));
+  k_tile_boxes<<<(nsubs + kPsiBlock - 1) / kPsiBlock, kPsiBlock, 0, st>>>(panels, (int)m, tiles.as<Box>());
   NFA_CHECK_LAUNCH();
   const int nx1 = g->nx + 1, ny1 = g->ny + 1, nz1 = g->nz + 1;
   const long long nb = (long long)((nx1 + kBx - 1) / kBx) * ((ny1 + kBy - 1) / kBy) * ((nz1 + kBz - 1) / kBz);
