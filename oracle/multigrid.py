@@ -1,0 +1,115 @@
+"""Aggregation multigrid preconditioner (oracle, FP64).
+
+Test infrastructure: a plain CPU statement of the multigrid V-cycle the
+library offers as a preconditioner of the projection's conjugate-gradient
+solve (Introduction: preconditioned conjugate gradients; the preconditioner
+is not named -- Jacobi is the default, this is the stronger option).
+
+Hierarchy.  Level 0 is the merged operator A' over the reduced unknowns (the
+cells that carry an unknown).  A level's cells are aggregated in blocks of
+2 x 2 x 2 (the last block along an odd axis holds one layer); an unknown of
+level 0 belongs to the block of its own cell.  With P_l the 0/1 matrix that
+maps a block to its unknowns, the next operator is the Galerkin product
+A_{l+1} = P_l^T A_l P_l, kept on the full block grid (blocks without an
+unknown have empty rows).  Couplings of A_1 between blocks that are not
+neighbours (|offset| > 1 along an axis, possible only through long merge
+chains) are dropped, the diagonal kept -- each such face then adds a
+positive semidefinite term, so A_1 stays symmetric positive semidefinite;
+coarser levels are exact Galerkin products (their couplings never reach
+further).  Coarsening stops at `min_coarse` cells or fewer.
+
+V-cycle (symmetric, so it preconditions CG): on level l with right-hand
+side r,
+    z = omega D^-1 r;  r_c = P^T (r - A z);  z += P V(r_c);
+    z += omega D^-1 (r - A z)
+with D the diagonal (rows without an unknown get z = 0).  The coarsest level
+is solved exactly: empty rows become identity rows and, when every boundary
+is Neumann, c v v^T is added (v the indicator of the non-empty rows, c their
+mean diagonal), which leaves A x = b for every compatible b.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+OMEGA = 0.7
+MIN_COARSE = 600
+
+
+def _blocks(shape):
+    nz, ny, nx = shape
+    cz, cy, cx = (nz + 1) // 2, (ny + 1) // 2, (nx + 1) // 2
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    blk = ((k // 2) * cy + j // 2) * cx + i // 2
+    return blk.reshape(-1), (cz, cy, cx)
+
+
+def _drop_far(A, shape):
+    """Remove the off-diagonal entries between blocks more than one apart
+    along an axis (the diagonal is kept)."""
+    nz, ny, nx = shape
+    A = A.tocoo()
+    rk, rem = np.divmod(A.row, nx * ny)
+    rj, ri = np.divmod(rem, nx)
+    ck, rem = np.divmod(A.col, nx * ny)
+    cj, ci = np.divmod(rem, nx)
+    near = (np.abs(rk - ck) <= 1) & (np.abs(rj - cj) <= 1) & (np.abs(ri - ci) <= 1)
+    return sp.csr_matrix((A.data[near], (A.row[near], A.col[near])), shape=A.shape), int(np.count_nonzero(~near))
+
+
+class Hierarchy:
+    """Operators, shapes and aggregation maps of every level."""
+
+    def __init__(self, op, min_coarse=MIN_COARSE, omega=OMEGA):
+        self.op = op
+        self.omega = omega
+        g = op.grid
+        shape = g.shape
+        A = op.csr()
+        red = op.reduced_mask().reshape(-1) > 0
+        self.A, self.shapes, self.maps = [A], [shape], []
+        self.dropped = 0
+        rows_mask = red
+        while A.shape[0] > min_coarse and max(shape) > 1:
+            blk, cshape = _blocks(shape)
+            nc = int(np.prod(cshape))
+            rows = np.nonzero(rows_mask)[0]
+            P = sp.csr_matrix((np.ones(len(rows)), (rows, blk[rows])), shape=(A.shape[0], nc))
+            Ac = (P.T @ A @ P).tocsr()
+            Ac, nd = _drop_far(Ac, cshape)
+            self.dropped += nd
+            self.maps.append(P)
+            self.A.append(Ac)
+            self.shapes.append(cshape)
+            A, shape = Ac, cshape
+            rows_mask = np.ones(nc, dtype=bool)
+        self.diag = [a.diagonal() for a in self.A]
+        self.dinv = [np.where(d > 0, 1.0 / np.where(d > 0, d, 1.0), 0.0) for d in self.diag]
+        self.coarse_inv = self._coarsest(g.all_neumann)
+
+    def _coarsest(self, singular):
+        A = self.A[-1].toarray()
+        d = np.diag(A).copy()
+        empty = ~(d > 0)
+        M = A.copy()
+        if singular and np.any(~empty):
+            v = (~empty).astype(np.float64)
+            M = M + np.mean(d[~empty]) * np.outer(v, v)
+        M[empty, :] = 0.0
+        M[:, empty] = 0.0
+        M[empty, empty] = 1.0
+        return np.linalg.inv(M)
+
+    def vcycle(self, r, level=0):
+        if level == len(self.A) - 1:
+            return self.coarse_inv @ r
+        A, P, dinv, w = self.A[level], self.maps[level], self.dinv[level], self.omega
+        z = w * (dinv * r)
+        rc = P.T @ (r - A @ z)
+        z = z + P @ self.vcycle(rc, level + 1)
+        return z + w * (dinv * (r - A @ z))
+
+    def precond(self, r):
+        """z = V(r) on cell arrays (zeros off the reduced unknowns)."""
+        shape = np.shape(r)
+        return self.vcycle(np.asarray(r, dtype=np.float64).reshape(-1)).reshape(shape)

@@ -1,0 +1,82 @@
+"""Pins of the oracle's aggregation multigrid (no GPU): the level-1 operator
+of a uniform problem is the 7-point operator with four fine faces per coarse
+face; Galerkin levels keep the constants in the null space when every
+boundary is Neumann; the V-cycle is a symmetric positive definite operator
+(dense check, with a body and merges); a hierarchy of one level solves
+exactly; and multigrid-preconditioned CG converges in a small fraction of
+the Jacobi iterations to the dense solution."""
+import numpy as np
+import pytest
+
+from oracle import multigrid, solvers
+from oracle.geometry import Body
+from oracle.grid import Grid
+from oracle.operator import Operator
+from paper_1410_1937_amd import fixtures as fx
+from tests.gpu_helpers import oracle_for
+
+
+def _uniform_op(n, bc=(0,) * 6):
+    f = fx.uniform_faces(0.0, 1.0, n)
+    g = Grid(f, f, f, bc)
+    return Operator(g, Body(g, None, 0.25, 8), np.ones(g.shape), 1.0, 1.0, smooth=False)
+
+
+def test_level_one_of_a_uniform_problem_is_the_coarse_seven_point_operator():
+    op = _uniform_op(8)
+    H = multigrid.Hierarchy(op, min_coarse=1)
+    T = op.tx[0, 0, 1]
+    A1 = H.A[1].toarray()
+    assert H.shapes[1] == (4, 4, 4)
+    c = (1 * 4 + 2) * 4 + 1                    # an interior block
+    nbrs = {c - 1, c + 1, c - 4, c + 4, c - 16, c + 16}
+    assert A1[c, c] == pytest.approx(24 * T, rel=1e-14)
+    for m in nbrs:
+        assert A1[c, m] == pytest.approx(-4 * T, rel=1e-14)
+    assert np.count_nonzero(A1[c]) == 7
+
+
+def test_constants_stay_in_the_null_space_of_every_level():
+    wl = fx.small(1, 24, 16, 12, body="sphere")
+    og, ob, op, b = oracle_for(wl)
+    H = multigrid.Hierarchy(op, min_coarse=10)
+    assert len(H.A) >= 3
+    for l, A in enumerate(H.A[1:], start=1):
+        rows = np.abs(A @ np.ones(A.shape[0]))
+        assert np.max(rows) <= 1e-12 * np.max(np.abs(A.diagonal())), l
+
+
+@pytest.mark.parametrize("bc", [(0,) * 6, (0, 0, 0, 0, 0, 1)])
+def test_vcycle_is_symmetric_positive_definite(bc):
+    wl = fx.small(2, 12, 10, 8, body="sphere", bc=bc)
+    og, ob, op, b = oracle_for(wl)
+    H = multigrid.Hierarchy(op, min_coarse=20)
+    red = np.nonzero(op.reduced_mask().reshape(-1))[0]
+    n = op.grid.n
+    M = np.zeros((len(red), len(red)))
+    for col, c in enumerate(red):
+        e = np.zeros(n)
+        e[c] = 1.0
+        M[:, col] = H.vcycle(e)[red]
+    assert np.max(np.abs(M - M.T)) <= 1e-12 * np.max(np.abs(M))
+    assert np.min(np.linalg.eigvalsh(0.5 * (M + M.T))) > 0
+
+
+def test_one_level_hierarchy_solves_exactly():
+    wl = fx.small(3, 8, 6, 6, body="sphere")
+    og, ob, op, b = oracle_for(wl)
+    H = multigrid.Hierarchy(op, min_coarse=10 ** 6)
+    assert len(H.A) == 1
+    x = H.precond(b)
+    assert np.linalg.norm(op.apply(x) - b) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_multigrid_cg_converges_fast_to_the_dense_solution():
+    wl = fx.c1()
+    og, ob, op, b = oracle_for(wl)
+    H = multigrid.Hierarchy(op)
+    res = solvers.fcg(op, b, H.precond, tol=1e-10, fallback=False)
+    jac = solvers.pcg(op, b, tol=1e-10)
+    assert res.relres <= 1e-10
+    assert res.iterations * 5 <= jac.iterations, (res.iterations, jac.iterations)
+    assert np.linalg.norm(res.x - jac.x) <= 1e-8 * np.linalg.norm(jac.x)
