@@ -220,6 +220,7 @@ nfa_status nfa_poisson_divergence(nfa_poisson op, const double* fu, const double
                                   unrelated field, to exercise the fallback */
 #define NFA_PC_JACOBI_FCG 4    /* flexible CG driver with the Jacobi preconditioner
                                   (reference run of the flexible path) */
+#define NFA_PC_MG 5            /* aggregation multigrid V-cycle (opts->mg) */
 #define NFA_PREC_F64 0   /* FP64 Jacobi-PCG */
 #define NFA_PREC_MIXED 1 /* FP32 CG recurrence, FP64 solution and residual
                             replacement (the FP64 residual decides) */
@@ -236,10 +237,12 @@ typedef struct {
                             iteration over a window exceeds this (0.99) */
   int fallback_window;   /* window length in iterations (10) */
   int warm_start;        /* 1: x holds the initial guess */
-  int check_every;       /* iterations between host polls of ||r|| */
+  int check_every;       /* iterations between host polls of ||r|| (at most 2
+                            with NFA_PC_MG) */
   void* unet;            /* nfa_unet handle when precond == NFA_PC_UNET */
   double* history;       /* optional HOST buffer of ||r_k||/||b'|| (inner) */
   int history_cap;
+  void* mg;              /* nfa_mg handle when precond == NFA_PC_MG */
 } nfa_solve_opts;
 
 typedef struct {
@@ -254,6 +257,43 @@ typedef struct {
 /* Fills opts with defaults: tol 1e-8, Jacobi, FP64, replace_drop 0.1,
  * fallback 0.99 over 10 iterations, check_every 16. */
 void nfa_solve_opts_default(nfa_solve_opts* opts);
+
+/* ------------------------------------------------------------------------
+ * Aggregation multigrid preconditioner (the paper names PCG and no
+ * preconditioner; Jacobi is the default, this the stronger option).
+ * Levels: 0 = A' over the reduced unknowns; l+1 = the Galerkin product
+ * P^T A_l P with P the piecewise-constant prolongation from blocks of
+ * 2 x 2 x 2 cells (an unknown of level 0 belongs to the block of its cell;
+ * level 1 is assembled from the faces, merge groups included, and drops
+ * couplings to blocks more than one apart while keeping their diagonal
+ * terms); at least one coarsening; the coarsest level (at most 600 cells)
+ * solved with a dense inverse (empty rows identity; c v v^T added when
+ * every boundary is Neumann).  V-cycle in FP32: damped Jacobi (0.7), one
+ * sweep before and one after the coarse correction -- symmetric.
+ * ------------------------------------------------------------------------ */
+typedef struct nfa_mg_s* nfa_mg;
+/* nfa_mg_create -- allocates the hierarchy of op's grid (op must outlive it):
+ * per coarse cell 27 FP64 + 27 FP32 stencil entries and four FP32 vectors,
+ * about 2.3 GB per 10^7 cells of level 1.  Errors: NFA_ERR_INVALID (a
+ * single-cell grid), NFA_ERR_HIP. */
+nfa_status nfa_mg_create(nfa_poisson op, nfa_mg* out);
+void nfa_mg_destroy(nfa_mg mg);
+/* nfa_mg_setup -- builds every level from op's current FP64 coefficients
+ * (call after each nfa_poisson_assemble; nfa_poisson_solve with NFA_PC_MG
+ * calls it when the operator has changed).  Synchronous (the coarsest
+ * inverse is formed on the host).  Errors: NFA_ERR_INVALID (not
+ * assembled), NFA_ERR_NUMERIC (coarsest matrix not positive definite). */
+nfa_status nfa_mg_setup(nfa_mg mg, nfa_stream s);
+/* nfa_mg_apply -- z = V(r), one V-cycle; r, z: DEVICE float cells (r zero
+ * off the reduced unknowns; z's slaves take their root's value).  ASYNC. */
+nfa_status nfa_mg_apply(nfa_mg mg, const float* r, float* z, nfa_stream s);
+/* nfa_mg_info -- number of levels and, if dims is not NULL, (nz, ny, nx) of
+ * each level (HOST, 3 * levels ints, at most 48). */
+nfa_status nfa_mg_info(nfa_mg mg, int* levels, int* dims);
+/* nfa_mg_export -- level >= 1's FP64 stencil, 27 x n doubles (entry
+ * o = (dz+1) 9 + (dy+1) 3 + (dx+1) of cell c at [o n + c]) into DEVICE dst.
+ * ASYNC. */
+nfa_status nfa_mg_export(nfa_mg mg, int level, double* dst, nfa_stream s);
 
 /* nfa_poisson_solve -- x = A'^-1 b' by preconditioned CG (Introduction:
  * "preconditioned conjugate-gradient"; Jacobi by default).

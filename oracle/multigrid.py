@@ -11,7 +11,7 @@ cells that carry an unknown).  A level's cells are aggregated in blocks of
 level 0 belongs to the block of its own cell.  With P_l the 0/1 matrix that
 maps a block to its unknowns, the next operator is the Galerkin product
 A_{l+1} = P_l^T A_l P_l, kept on the full block grid (blocks without an
-unknown have empty rows).  Couplings of A_1 between blocks that are not
+unknown have empty rows).  There is always at least one coarse level.  Couplings of A_1 between blocks that are not
 neighbours (|offset| > 1 along an axis, possible only through long merge
 chains) are dropped, the diagonal kept -- each such face then adds a
 positive semidefinite term, so A_1 stays symmetric positive semidefinite;
@@ -70,7 +70,7 @@ class Hierarchy:
         self.A, self.shapes, self.maps = [A], [shape], []
         self.dropped = 0
         rows_mask = red
-        while A.shape[0] > min_coarse and max(shape) > 1:
+        while (len(self.A) == 1 or A.shape[0] > min_coarse) and max(shape) > 1:
             blk, cshape = _blocks(shape)
             nc = int(np.prod(cshape))
             rows = np.nonzero(rows_mask)[0]

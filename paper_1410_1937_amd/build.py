@@ -16,7 +16,8 @@ LIB = os.path.join(HERE, "libnfa.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["common.hip", "grid.hip", "assemble.hip", "stencil.hip", "vecops.hip", "cg.hip",
-           "solver.hip", "unet.hip", "rk2.hip", "vof.hip", "setup_geometry.hip"]
+           "solver.hip", "unet.hip", "rk2.hip", "vof.hip", "setup_geometry.hip",
+           "multigrid.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

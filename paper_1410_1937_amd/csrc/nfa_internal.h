@@ -164,4 +164,12 @@ void launch_sum_partials(const double* partials, int n, int ncomp, double* out, 
 }  // namespace nfa
 
 struct nfa_grid_s : nfa::Grid {};
+
+namespace nfa {
+// Multigrid preconditioner (multigrid.hip): one V-cycle z = M r in FP32, and
+// a (re)build of the hierarchy when the operator has been reassembled.
+nfa_status mg_precond_apply(void* mg, Poisson& op, const float* r, float* z, const SolveScalars* sc,
+                            hipStream_t s);
+nfa_status mg_ensure(void* mg, Poisson& op, hipStream_t s);
+}  // namespace nfa
 struct nfa_poisson_s : nfa::Poisson {};

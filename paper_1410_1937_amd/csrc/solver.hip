@@ -105,6 +105,9 @@ void enqueue_iter(Poisson& op, CG<T>& B, int j, int pc, void* unet, nfa_status* 
       launch_scale<T>(B.r, B.C.dinv, B.z, g.n, sc, st);
     } else if (pc == NFA_PC_TEST_SABOTAGE) {
       launch_sabotage<T>(g.reduced.as<unsigned char>(), B.z, g.n, sc, st);
+    } else if (pc == NFA_PC_MG) {
+      const nfa_status e = mg_precond_apply(unet, op, (const float*)B.r, (float*)B.z, sc, st);
+      if (e != NFA_OK && *pst == NFA_OK) *pst = e;
     } else {
       const nfa_status e = unet_precond_apply(unet, op, (const float*)B.r, (float*)B.z, sc, st);
       if (e != NFA_OK && *pst == NFA_OK) *pst = e;
@@ -184,7 +187,10 @@ nfa_status cg_solve(Poisson& op, const double* b, double* x64, const nfa_solve_o
   int pc = o->precond;
   const double delta = mixed ? o->replace_drop : 0.0;
   double* r64 = op.r.as<double>();
-  const int check = std::max(1, o->check_every);
+  // the multigrid-preconditioned recursion falls by ~10x every two or three
+  // iterations: polled less often, an FP32 phase would run far past the
+  // replacement point and below its own accuracy
+  const int check = pc == NFA_PC_MG ? std::min(std::max(1, o->check_every), 2) : std::max(1, o->check_every);
 
   nfa_status e = residual64(op, b, x64, r64, PH_RRO, st);
   if (e != NFA_OK) return e;
@@ -211,7 +217,8 @@ nfa_status cg_solve(Poisson& op, const double* b, double* x64, const nfa_solve_o
   int slot = 0;
   bool have_prev = false;
   for (;;) {
-    for (int it = 0; it < check; ++it, ++j) enqueue_iter<T>(op, B, j, pc, o->unet, &pst, st);
+    void* handle = pc == NFA_PC_MG ? o->mg : o->unet;
+    for (int it = 0; it < check; ++it, ++j) enqueue_iter<T>(op, B, j, pc, handle, &pst, st);
     NFA_CHECK_LAUNCH();
     if (pst != NFA_OK) return pst;
     NFA_HIP(hipMemcpyAsync(&op.h_scal[slot], sc, sizeof(SolveScalars), hipMemcpyDeviceToHost, st));
@@ -292,6 +299,7 @@ extern "C" void nfa_solve_opts_default(nfa_solve_opts* o) {
   o->unet = nullptr;
   o->history = nullptr;
   o->history_cap = 0;
+  o->mg = nullptr;
 }
 
 extern "C" nfa_status nfa_poisson_solve(nfa_poisson op, const double* b, double* x,
@@ -303,18 +311,24 @@ extern "C" nfa_status nfa_poisson_solve(nfa_poisson op, const double* b, double*
   if (o->precision != NFA_PREC_F64 && o->precision != NFA_PREC_MIXED)
     return fail(NFA_ERR_INVALID, "nfa_poisson_solve: unknown precision");
   if (o->precond != NFA_PC_JACOBI && o->precond != NFA_PC_UNET && o->precond != NFA_PC_TEST_SABOTAGE &&
-      o->precond != NFA_PC_JACOBI_FCG)
+      o->precond != NFA_PC_JACOBI_FCG && o->precond != NFA_PC_MG)
     return fail(NFA_ERR_INVALID, "nfa_poisson_solve: unknown preconditioner");
   if (o->precond != NFA_PC_JACOBI && o->precision != NFA_PREC_MIXED)
     return fail(NFA_ERR_INVALID, "nfa_poisson_solve: flexible CG runs as the FP32 inner solve (NFA_PREC_MIXED)");
   if (o->precond == NFA_PC_UNET && !o->unet)
     return fail(NFA_ERR_INVALID, "nfa_poisson_solve: NFA_PC_UNET needs opts->unet");
+  if (o->precond == NFA_PC_MG && !o->mg)
+    return fail(NFA_ERR_INVALID, "nfa_poisson_solve: NFA_PC_MG needs opts->mg");
   if (o->fcg_m != 1) return fail(NFA_ERR_INVALID, "nfa_poisson_solve: fcg_m must be 1");
   if (o->precision == NFA_PREC_MIXED && !(o->replace_drop > 0 && o->replace_drop < 1))
     return fail(NFA_ERR_INVALID, "nfa_poisson_solve: mixed needs 0 < replace_drop < 1");
   const auto t0 = std::chrono::steady_clock::now();
   Grid& g = *op->g;
   const hipStream_t st = S(s);
+  if (o->precond == NFA_PC_MG) {
+    const nfa_status me = mg_ensure(o->mg, *op, st);   // rebuild after a new assembly
+    if (me != NFA_OK) return me;
+  }
   *info = nfa_solve_info{};
   SolveScalars* sc = op->scal.as<SolveScalars>();
   double* parts = op->partials.as<double>();

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libnfa.so")
 NFA_OK = 0
 NFA_NOT_CONVERGED = 1
 NFA_F64, NFA_F32 = 0, 1
-NFA_PC_JACOBI, NFA_PC_UNET, NFA_PC_TEST_SABOTAGE, NFA_PC_JACOBI_FCG = 1, 2, 3, 4
+NFA_PC_JACOBI, NFA_PC_UNET, NFA_PC_TEST_SABOTAGE, NFA_PC_JACOBI_FCG, NFA_PC_MG = 1, 2, 3, 4, 5
 NFA_PREC_F64, NFA_PREC_MIXED = 0, 1
 
 EXPORT = {
@@ -60,7 +60,7 @@ class SolveOpts(ctypes.Structure):
                 ("replace_drop", c_double), ("fcg_m", c_int),
                 ("fallback_ratio", c_double), ("fallback_window", c_int), ("warm_start", c_int),
                 ("check_every", c_int), ("unet", c_void_p), ("history", ctypes.POINTER(c_double)),
-                ("history_cap", c_int)]
+                ("history_cap", c_int), ("mg", c_void_p)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -126,6 +126,12 @@ _sig("nfa_faces_combine", c_int, [c_ll, c_void_p, c_void_p, c_double, c_void_p, 
 _sig("nfa_poisson_rhs_cells", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p,
                                       c_void_p, c_void_p, c_void_p])
 _sig("nfa_exit_velocity", c_int, [c_void_p, c_void_p, c_double, c_double, c_void_p, c_void_p])
+_sig("nfa_mg_create", c_int, [c_void_p, ctypes.POINTER(c_void_p)])
+_sig("nfa_mg_destroy", None, [c_void_p])
+_sig("nfa_mg_setup", c_int, [c_void_p, c_void_p])
+_sig("nfa_mg_apply", c_int, [c_void_p, c_void_p, c_void_p, c_void_p])
+_sig("nfa_mg_info", c_int, [c_void_p, ctypes.POINTER(c_int), c_void_p])
+_sig("nfa_mg_export", c_int, [c_void_p, c_int, c_void_p, c_void_p])
 _sig("nfa_stretch_axis", c_int, [c_double, c_double, c_int, c_int, c_void_p, c_void_p, c_double, c_int, c_void_p,
                                  ctypes.POINTER(c_int)])
 _sig("nfa_panels_psi", c_int, [c_void_p, c_void_p, c_ll, c_void_p, c_void_p])
@@ -255,6 +261,44 @@ class Grid:
             self.h = None
 
 
+class Multigrid:
+    """Aggregation multigrid preconditioner of an operator (nfa_mg_*)."""
+
+    def __init__(self, op):
+        self.op = op
+        h = c_void_p()
+        _check(lib.nfa_mg_create(op.h, ctypes.byref(h)), "nfa_mg_create")
+        self.h = h
+
+    def setup(self):
+        _check(lib.nfa_mg_setup(self.h, _stream()), "nfa_mg_setup")
+
+    def apply(self, r, out=None):
+        """z = V(r), one V-cycle (FP32 cell arrays)."""
+        z = torch.empty_like(r) if out is None else out
+        _check(lib.nfa_mg_apply(self.h, _dev(r, torch.float32, self.op.shape, "r"),
+                                _dev(z, torch.float32, self.op.shape, "z"), _stream()), "nfa_mg_apply")
+        return z
+
+    def levels(self):
+        L = c_int()
+        dims = (c_int * 48)()
+        _check(lib.nfa_mg_info(self.h, ctypes.byref(L), dims), "nfa_mg_info")
+        return [tuple(dims[3 * l:3 * l + 3]) for l in range(L.value)]
+
+    def export(self, level):
+        """Level >= 1's FP64 stencil as (27, nz, ny, nx)."""
+        shape = self.levels()[level]
+        out = torch.empty((27,) + shape, dtype=torch.float64, device="cuda")
+        _check(lib.nfa_mg_export(self.h, level, c_void_p(out.data_ptr()), _stream()), "nfa_mg_export")
+        return out
+
+    def __del__(self, _destroy=lib.nfa_mg_destroy):
+        if getattr(self, "h", None):
+            _destroy(self.h)
+            self.h = None
+
+
 class Vof:
     """Split VOF advection on a grid (nfa_vof_*); the handle owns the plane
     table, the cell lists and a fraction buffer."""
@@ -374,16 +418,24 @@ class Poisson:
                "nfa_poisson_divergence")
         return div
 
+    def multigrid(self):
+        """The operator's multigrid preconditioner (created on first use)."""
+        if getattr(self, "_mg", None) is None:
+            self._mg = Multigrid(self)
+        return self._mg
+
     def solve(self, b, x=None, tol=1e-8, precision="f64", precond="jacobi", max_iters=200000,
               replace_drop=0.1, warm_start=False, check_every=16, unet=None,
-              fallback_ratio=0.99, fallback_window=10, history=0):
+              fallback_ratio=0.99, fallback_window=10, history=0, mg=None):
         o = SolveOpts()
         lib.nfa_solve_opts_default(ctypes.byref(o))
         o.tol = tol
         o.max_iters = max_iters
         o.precision = {"f64": NFA_PREC_F64, "mixed": NFA_PREC_MIXED}[precision]
         o.precond = {"jacobi": NFA_PC_JACOBI, "unet": NFA_PC_UNET, "jacobi_fcg": NFA_PC_JACOBI_FCG,
-                     "sabotage": NFA_PC_TEST_SABOTAGE}[precond]
+                     "sabotage": NFA_PC_TEST_SABOTAGE, "mg": NFA_PC_MG}[precond]
+        if precond == "mg":
+            o.mg = (mg if mg is not None else self.multigrid()).h
         o.replace_drop = replace_drop
         o.warm_start = 1 if warm_start else 0
         o.check_every = check_every
