@@ -8,11 +8,14 @@ solve to FP64 true relative residual 1e-8, project the face fluxes and
 compute the post-projection divergence.  The body geometry is static in the
 body-fixed frame and is set up once, outside the timed region.
 
-`value` is the chosen form (mixed precision; with the learned preconditioner
-when trained weights are available); the plain FP64 Jacobi-PCG projection is
-timed beside it.  One extra, instrumented step measures the average duration
-of the dominant kernel (sweep A of the fused CG iteration: new direction,
-operator apply and deferred x update) with HIP events for the roofline.
+`value` is the chosen form: mixed precision (FP32 recurrence, FP64 solution
+and true residual) with the aggregation-multigrid V-cycle as the flexible CG
+preconditioner, its hierarchy rebuilt from each assembly inside the step;
+the plain FP64 Jacobi-PCG projection is timed beside it.  One extra,
+instrumented step measures, with HIP events, the average durations of sweep
+A of the fused CG iteration (new direction, operator apply, deferred x
+update) and of the V-cycle's level-0 operator apply; the roofline is that of
+the one with the larger summed time.
 The CPU baseline is the FP64 oracle on the host cores, timed on a bounded
 sample (a few iterations on the full grid) and scaled to one projection.
 Beside the metric it times one Runge-Kutta cycle (two projections), one
@@ -133,14 +136,13 @@ def main():
     phi = torch.as_tensor(wl.phi, device=dev).to(torch.float32).contiguous()
     u, v, w = (torch.as_tensor(a, device=dev) for a in (wl.u, wl.v, wl.w))
     x = torch.zeros(op.shape, dtype=torch.float64, device=dev)
-    unet = None
-    solver = dict(precision="mixed", precond="jacobi")
+    solver = dict(precision="mixed", precond="mg")
 
     def step(kind):
         op.assemble(phi, wl.rho_l, wl.rho_g, wl.smooth)
         b = op.rhs(u, v, w, wl.dt, wl.body_vel)
         if kind == "chosen":
-            p, res = op.solve(b, x=x, tol=1e-8, unet=unet, **solver)
+            p, res = op.solve(b, x=x, tol=1e-8, **solver)
         else:
             p, res = op.solve(b, x=x, tol=1e-8, precision="f64")
         F = op.project(u, v, w, p, wl.dt)
@@ -170,27 +172,38 @@ def main():
         ms_fp64, its_fp64, r_fp64 = timed("fp64", args.steps, args.warmup)
         log(f"[bench] plain FP64: {ms_fp64:.1f} ms/projection")
 
-    # instrumented step: average duration of sweep A (dominant kernel)
+    # instrumented step: HIP events around sweep A of every iteration and
+    # the two level-0 operator applies of every V-cycle; the roofline is
+    # that of the one with the larger summed time (the dominant kernel)
     op.profile(True)
     step("chosen")
-    ks32 = op.profile_read("f32")
-    ks64 = op.profile_read("f64")
+    kinds = {k: op.profile_read(k) for k in ("f32", "f64", "mg_apply")}
     op.profile(False)
-    # sweep A moves, per cell: z, p_old, tx, ty, tz, x read; p_new, q, x written
-    # (9 words: 36 B in FP32, 72 B in FP64); neighbour re-reads are cache hits
-    # and not counted.
-    if ks32["launches"] > 0:
-        ks, bpc, kname = ks32, 36, "k_cg_a<float, 4, 1, false>"
-    else:
-        wx = next((w for w in (4, 2) if wl.shape[2] % (w * 128) == 0), 1)
-        ks, bpc, kname = ks64, 72, f"k_cg_a<double, 2, {wx}, false>"
-    avg_ms = ks["ms"] / max(1, ks["launches"])
-    bytes_per_launch = bpc * ks["cells"]
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname),
-                "kernel": kname, "avg_launch_ms": round(avg_ms, 5), "launches": ks["launches"],
-                "algorithmic_bytes_per_launch": bytes_per_launch}
+    # sweep A moves, per cell: z, p_old, tx, ty, tz, x read; p_new, q, x
+    # written (9 words: 36 B in FP32, 72 B in FP64).  The level-0 apply
+    # reads z, tx, ty, tz and writes q (5 words, 20 B in FP32).  Neighbour
+    # re-reads are cache hits and not counted.
+    wx = next((w for w in (4, 2) if wl.shape[2] % (w * 128) == 0), 1)
+    meta = {"f32": (36, "k_cg_a<float, 4, 1, true>"), "f64": (72, f"k_cg_a<double, 2, {wx}, false>"),
+            "mg_apply": (20, "k_stencil<float, false>")}
+    entries = {}
+    for k, ks in kinds.items():
+        if ks["launches"] == 0:
+            continue
+        bpc, kname = meta[k]
+        avg_ms = ks["ms"] / ks["launches"]
+        bpl = bpc * ks["cells"]
+        gbs = bpl / (avg_ms * 1e-3) / 1e9
+        entries[k] = {"kernel": kname, "avg_launch_ms": round(avg_ms, 5), "launches": ks["launches"],
+                      "ms_per_step": round(ks["ms"], 3), "algorithmic_bytes_per_launch": bpl,
+                      "achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    dom = max(entries, key=lambda k: entries[k]["ms_per_step"])
+    e = entries[dom]
+    roofline = {"bound": "hbm", "achieved": e["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": e["frac"], "traffic": measured_traffic(e["kernel"]), "kernel": e["kernel"],
+                "avg_launch_ms": e["avg_launch_ms"], "launches": e["launches"],
+                "algorithmic_bytes_per_launch": e["algorithmic_bytes_per_launch"],
+                "other_timed_kernels": [entries[k] for k in entries if k != dom]}
 
     # one Runge-Kutta projection cycle (two projections around the advected
     # volume fraction) on the same grid, mixed precision; reported beside the
@@ -201,13 +214,14 @@ def main():
         phi_s = torch.as_tensor(fx.c3(t=0.005).phi, device=dev).to(torch.float32).contiguous()
         R = tuple(torch.as_tensor(0.1 * a, device=dev) for a in fx.face_velocity(wl.xf, wl.yf, wl.zf, 11))
         cyc = lambda: op.rk2_cycle(phi, phi_s, (u, v, w), R, 0.005, wl.body_vel, wl.rho_l, wl.rho_g,
-                                   wl.smooth, tol=1e-8, precision="mixed")
+                                   wl.smooth, tol=1e-8, **solver)
         cyc()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         out = cyc()
         torch.cuda.synchronize()
-        rk2 = {"ms": round((time.perf_counter() - t0) * 1e3, 3), "precision": "mixed", "tol": 1e-8,
+        rk2 = {"ms": round((time.perf_counter() - t0) * 1e3, 3), "precision": "mixed", "precond": "mg",
+               "tol": 1e-8,
                "iterations": [out["stage1"].iterations, out["stage2"].iterations],
                "steps": "assemble(phi^k) + u~1 + rhs + solve + velocity + assemble(phi*) + u~2 + rhs + "
                         "solve + velocity"}
@@ -286,10 +300,10 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_DESC, "cells": n, "tol": 1e-8,
-                   "solver": ("FP32 " + ("flexible CG with the learned U-Net preconditioner"
-                                         if solver["precond"] == "unet" else "Jacobi-PCG")
-                              + " with FP64 residual replacement (true residual recomputed "
-                                "in FP64 every 10x reduction)"),
+                   "solver": ("FP32 flexible CG preconditioned by one symmetric aggregation-multigrid "
+                              "V-cycle (2x2x2 Galerkin levels, damped Jacobi, FP64 dense coarsest "
+                              "solve; hierarchy rebuilt every step) with FP64 residual replacement "
+                              "(true residual recomputed in FP64 every 10x reduction)"),
                    "step": "assemble + rhs + solve + project + divergence",
                    "iterations": its_chosen[-1], "fp64_residuals": r_chosen.outer,
                    "fallback": r_chosen.fallback},

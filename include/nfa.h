@@ -269,27 +269,42 @@ void nfa_solve_opts_default(nfa_solve_opts* opts);
  * terms); at least one coarsening; the coarsest level (at most 600 cells)
  * solved with a dense inverse (empty rows identity; c v v^T added when
  * every boundary is Neumann).  V-cycle in FP32: damped Jacobi (0.7), one
- * sweep before and one after the coarse correction -- symmetric.
+ * sweep before and one after the coarse correction -- symmetric.  Levels
+ * >= 1 are held in FP32 as (D^-1, +x, +y, +z couplings) per cell plus a
+ * side list of the rows that merges couple beyond the 7 points; the levels
+ * from the first with at most the "tail" cell count (nfa_mg_set_tail) down
+ * to the coarsest run in a single workgroup.
  * ------------------------------------------------------------------------ */
 typedef struct nfa_mg_s* nfa_mg;
 /* nfa_mg_create -- allocates the hierarchy of op's grid (op must outlive it):
- * per coarse cell 27 FP64 + 27 FP32 stencil entries and four FP32 vectors,
- * about 2.3 GB per 10^7 cells of level 1.  Errors: NFA_ERR_INVALID (a
- * single-cell grid), NFA_ERR_HIP. */
+ * per coarse cell 27 FP64 stencil entries, a float4 and two FP32 vectors
+ * (about 2.5 GB per 10^7 cells of level 1), plus side lists sized for the
+ * grid's current merge set.  Errors: NFA_ERR_INVALID (a single-cell grid),
+ * NFA_ERR_HIP. */
 nfa_status nfa_mg_create(nfa_poisson op, nfa_mg* out);
 void nfa_mg_destroy(nfa_mg mg);
 /* nfa_mg_setup -- builds every level from op's current FP64 coefficients
  * (call after each nfa_poisson_assemble; nfa_poisson_solve with NFA_PC_MG
- * calls it when the operator has changed).  Synchronous (the coarsest
- * inverse is formed on the host).  Errors: NFA_ERR_INVALID (not
- * assembled), NFA_ERR_NUMERIC (coarsest matrix not positive definite). */
+ * calls it when the operator has changed).  Synchronous (the side lists
+ * are scanned and the coarsest inverse formed on the host).  Allocates only
+ * when a side list outgrows what creation reserved (merge set grown since).
+ * Errors: NFA_ERR_INVALID (not assembled), NFA_ERR_NUMERIC (coarsest matrix
+ * not positive definite), NFA_ERR_HIP. */
 nfa_status nfa_mg_setup(nfa_mg mg, nfa_stream s);
+/* nfa_mg_set_tail -- the single-workgroup part of the cycle starts at the
+ * first level with at most max_cells cells whose vectors (with those of
+ * every coarser level) fit in 64 KiB of LDS; 0: only the coarsest level;
+ * < 0: the default, 8192.  Changes no result beyond FP32 rounding order. */
+nfa_status nfa_mg_set_tail(nfa_mg mg, int max_cells);
 /* nfa_mg_apply -- z = V(r), one V-cycle; r, z: DEVICE float cells (r zero
  * off the reduced unknowns; z's slaves take their root's value).  ASYNC. */
 nfa_status nfa_mg_apply(nfa_mg mg, const float* r, float* z, nfa_stream s);
 /* nfa_mg_info -- number of levels and, if dims is not NULL, (nz, ny, nx) of
  * each level (HOST, 3 * levels ints, at most 48). */
 nfa_status nfa_mg_info(nfa_mg mg, int* levels, int* dims);
+/* nfa_mg_side_rows -- rows of level >= 1 (below the coarsest) held in the
+ * side list by the last set-up (couplings beyond the 7 points). */
+nfa_status nfa_mg_side_rows(nfa_mg mg, int level, int* rows);
 /* nfa_mg_export -- level >= 1's FP64 stencil, 27 x n doubles (entry
  * o = (dz+1) 9 + (dy+1) 3 + (dx+1) of cell c at [o n + c]) into DEVICE dst.
  * ASYNC. */
@@ -308,18 +323,22 @@ nfa_status nfa_mg_export(nfa_mg mg, int level, double* dst, nfa_stream s);
 nfa_status nfa_poisson_solve(nfa_poisson op, const double* b, double* x, const nfa_solve_opts* opts,
                              nfa_stream s, nfa_solve_info* info);
 
-/* Timing of the operator sweep inside solves.  nfa_poisson_profile(op, 1)
- * brackets the first 4096 stencil launches of each later solve with HIP
- * events on the solve's stream (creating the events here, not in the solve)
- * and resets the counters; nfa_poisson_profile(op, 0) stops.  Only launches
- * of iterations that ran are counted. */
+/* Timing of the operator sweeps inside solves.  nfa_poisson_profile(op, 1)
+ * brackets the first 4096 timed launches of each later solve (sweep A of
+ * every iteration; with NFA_PC_MG also the two level-0 operator applies of
+ * each V-cycle) with HIP events on the solve's stream (creating the events
+ * here, not in the solve) and resets the counters;
+ * nfa_poisson_profile(op, 0) stops.  Only launches of iterations that ran
+ * are counted. */
+#define NFA_PROF_MG_APPLY 2
 typedef struct {
   long long launches; /* stencil launches timed */
   double ms;          /* their summed duration */
   long long cells;    /* cells swept per launch */
 } nfa_kernel_stats;
 nfa_status nfa_poisson_profile(nfa_poisson op, int enable);
-/* dtype NFA_F64 or NFA_F32: the sweep of that precision.  Synchronous. */
+/* dtype NFA_F64 or NFA_F32: sweep A of that precision; NFA_PROF_MG_APPLY:
+ * the V-cycle's level-0 operator apply (FP32).  Synchronous. */
 nfa_status nfa_poisson_profile_read(nfa_poisson op, int dtype, nfa_kernel_stats* out);
 
 /* nfa_poisson_residual -- r = b' - A'x in FP64 (the true residual that

@@ -20,12 +20,28 @@
 // Each thread assembles one coarse row, summing in a fixed order in FP64:
 // the hierarchy is bitwise reproducible.  Stencils are stored structure of
 // arrays, entry o = (dz+1) 9 + (dy+1) 3 + (dx+1) of cell c at [o n + c], in
-// FP64 (for building the next level) and FP32 (for the cycle).
+// FP64 (for building the next level and for export).
+//
+// Cycle storage of a level l >= 1 (FP32): a Galerkin product of a 7-point
+// operator over 2 x 2 x 2 blocks is again 7-point; couplings outside the
+// 7 points come only from merge groups, so each cell keeps one float4
+// (D^-1, a(+x), a(+y), a(+z)) -- the coupling to a lower neighbour is that
+// neighbour's upper one (the operator is symmetric) -- and the rare rows with
+// other couplings are flagged by a negative D^-1 and hold their 20 remaining
+// entries in a side list sorted by cell (found by binary search).
 //
 // V-cycle in FP32, symmetric (damped Jacobi, omega = 0.7, one sweep before
 // and one after the coarse correction; restriction = transpose of the
 // piecewise-constant prolongation), so the solve may use it in (flexible)
-// CG.  Every kernel returns at once when the solve has converged.
+// CG.  On levels >= 1 the pre-smoothed z = omega D^-1 r is never stored:
+//   down   r_{l+1} = P^T (r - A z) = P^T ((1 - omega) r - omega N (D^-1 r)),
+//   up     z' = z + P z_{l+1};  zt = (1 - omega) z' + omega D^-1 (r - N z'),
+// N the off-diagonal part (the diagonal terms cancel against D^-1 exactly in
+// exact arithmetic), z' formed on the fly at each neighbour.  Rows without
+// an unknown keep z' (zero coupling).  The levels from the first one with at
+// most `tail` cells down run in one workgroup with their vectors in LDS,
+// ending in the dense FP64 coarsest solve.  Every kernel returns at once
+// when the solve has converged.
 //
 // Built with -ffp-contract=off.
 #include <cmath>
@@ -61,14 +77,24 @@ __global__ void k_group_of(int ng, const int* __restrict__ groot, int* __restric
     group_of[groot[gi]] = gi;
 }
 
-__device__ __forceinline__ void store_row(long long n, long long B, const double* acc, double* A64, float* A32,
-                                          float* dinv) {
+// The 20 stencil entries outside the 7 points (o != 4, 10, 12, 13, 14, 16, 22).
+constexpr int kXSlots = 20;
+__host__ __device__ constexpr int xoff(int t) {
+  return t < 4 ? t : t < 9 ? t + 1 : t == 9 ? 11 : t == 10 ? 15 : t < 16 ? t + 6 : t + 7;
+}
+__host__ __device__ constexpr bool in7(int o) {
+  return o == 4 || o == 10 || o == 12 || o == 13 || o == 14 || o == 16 || o == 22;
+}
+
+__device__ __forceinline__ void store_row(long long n, long long B, const double* acc, double* A64, float4* S) {
+  bool extra = false;
 #pragma unroll
   for (int o = 0; o < 27; ++o) {
     A64[o * n + B] = acc[o];
-    A32[o * n + B] = (float)acc[o];
+    if (!in7(o) && acc[o] != 0.0) extra = true;
   }
-  dinv[B] = acc[13] > 0.0 ? (float)(1.0 / acc[13]) : 0.0f;
+  const float dv = acc[13] > 0.0 ? (float)(1.0 / acc[13]) : 0.0f;
+  S[B] = make_float4(extra ? -dv : dv, (float)acc[14], (float)acc[16], (float)acc[22]);
 }
 
 // Level 1 from the faces of level 0 (see the file head).
@@ -76,7 +102,7 @@ __global__ void k_level1(Dims f, Dims c, const double* __restrict__ tx, const do
                          const double* __restrict__ ty, const double* __restrict__ tz,
                          const unsigned char* __restrict__ reduced, const int* __restrict__ root,
                          const int* __restrict__ group_of, const int* __restrict__ g_off,
-                         const int* __restrict__ g_mem, double* A64, float* A32, float* dinv) {
+                         const int* __restrict__ g_mem, double* A64, float4* S) {
   const long long fplane = (long long)f.nx * f.ny;
   MG_STRIDE(B, c.n) {
     const int I = (int)(B % c.nx);
@@ -139,12 +165,12 @@ __global__ void k_level1(Dims f, Dims c, const double* __restrict__ tx, const do
             }
           }
         }
-    store_row(c.n, B, acc, A64, A32, dinv);
+    store_row(c.n, B, acc, A64, S);
   }
 }
 
 // Level l+1 as the Galerkin sum of level l's 27-point stencil.
-__global__ void k_coarsen(Dims f, Dims c, const double* __restrict__ Af, double* A64, float* A32, float* dinv) {
+__global__ void k_coarsen(Dims f, Dims c, const double* __restrict__ Af, double* A64, float4* S) {
   MG_STRIDE(B, c.n) {
     const int I = (int)(B % c.nx);
     const long long rr = B / c.nx;
@@ -166,97 +192,197 @@ __global__ void k_coarsen(Dims f, Dims c, const double* __restrict__ Af, double*
             acc[((kn >> 1) - K + 1) * 9 + ((jn >> 1) - J + 1) * 3 + ((in >> 1) - I + 1)] += a;
           }
         }
-    store_row(c.n, B, acc, A64, A32, dinv);
+    store_row(c.n, B, acc, A64, S);
+  }
+}
+
+// ---------------------------------------------------- side list of rows
+// Flagged rows per block of kBlock cells.
+__global__ void k_xcount(long long n, const float4* __restrict__ S, int* cnt) {
+  const long long c = blockIdx.x * (long long)kBlock + threadIdx.x;
+  const int f = c < n && S[c].x < 0.0f;
+  const int total = __syncthreads_count(f);
+  if (threadIdx.x == 0) cnt[blockIdx.x] = total;
+}
+
+// Flagged rows in cell order: xcell[e] = c, xval[e * 20 + t] = A(c, xoff(t)).
+__global__ void k_xscatter(long long n, const float4* __restrict__ S, const double* __restrict__ A64,
+                           const int* __restrict__ off, int* xcell, float* xval) {
+  __shared__ int wcount[kBlock / 64];
+  const long long c = blockIdx.x * (long long)kBlock + threadIdx.x;
+  const bool f = c < n && S[c].x < 0.0f;
+  const unsigned long long ballot = __ballot(f);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) wcount[w] = __popcll(ballot);
+  __syncthreads();
+  int e = off[blockIdx.x] + __popcll(ballot & ((1ull << lane) - 1ull));
+  for (int q = 0; q < w; ++q) e += wcount[q];
+  if (f) {
+    xcell[e] = (int)c;
+#pragma unroll
+    for (int t = 0; t < kXSlots; ++t) xval[(long long)e * kXSlots + t] = (float)A64[xoff(t) * n + c];
   }
 }
 
 // ------------------------------------------------------------------ cycle
-__global__ void k_pre(long long n, const float* __restrict__ r, const float* __restrict__ dinv, float* z,
-                      const SolveScalars* sc) {
-  if (solve_done(sc)) return;
-  MG_STRIDE(i, n) z[i] = kOmega * (dinv[i] * r[i]);
-}
+// One level of the cycle as the kernels see it (levels >= 1).
+struct LevelView {
+  int nx, ny, nz, m;            // m flagged rows
+  const float4* S;
+  const int* xcell;
+  const float* xval;
+};
 
-// 27-point product at cell (k, j, i) of a level.
-__device__ __forceinline__ float apply27(const Dims& d, const float* __restrict__ A, const float* __restrict__ z,
-                                         long long c, int k, int j, int i) {
+// sum over the couplings of row c outside the 7 points of a * w(nb, kn, jn, in)
+template <class W>
+__device__ __forceinline__ float extras_sum(const LevelView& L, int c, int k, int j, int i, W w) {
+  int lo = 0, hi = L.m - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (L.xcell[mid] < c)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  const float* v = L.xval + (long long)lo * kXSlots;
   float s = 0.0f;
 #pragma unroll
-  for (int o = 0; o < 27; ++o) {
-    const int kn = k + o / 9 - 1, jn = j + (o / 3) % 3 - 1, in = i + o % 3 - 1;
-    if (kn < 0 || kn >= d.nz || jn < 0 || jn >= d.ny || in < 0 || in >= d.nx) continue;
-    const long long nb = c + ((long long)(o / 9 - 1) * d.ny + ((o / 3) % 3 - 1)) * d.nx + (o % 3 - 1);
-    s += A[o * d.n + c] * z[nb];
+  for (int t = 0; t < kXSlots; ++t) {
+    const int o = xoff(t);
+    const int dz = o / 9 - 1, dy = (o / 3) % 3 - 1, dx = o % 3 - 1;
+    const float a = v[t];
+    const int kn = k + dz, jn = j + dy, in = i + dx;
+    if (a == 0.0f || kn < 0 || kn >= L.nz || jn < 0 || jn >= L.ny || in < 0 || in >= L.nx) continue;
+    s += a * w(c + (dz * L.ny + dy) * L.nx + dx, kn, jn, in);
   }
   return s;
 }
 
-// r_c = P^T (r - q) on level 0 (q = A' z; only reduced unknowns).
-__global__ void k_restrict0(Dims f, Dims c, const float* __restrict__ r, const float* __restrict__ q,
-                            const unsigned char* __restrict__ reduced, float* rc, const SolveScalars* sc) {
-  if (solve_done(sc)) return;
-  MG_STRIDE(B, c.n) {
-    const int I = (int)(B % c.nx);
-    const long long rr = B / c.nx;
-    const int J = (int)(rr % c.ny), K = (int)(rr / c.ny);
-    float s = 0.0f;
-    for (int kk = 0; kk < 2; ++kk)
-      for (int jj = 0; jj < 2; ++jj)
-        for (int ii = 0; ii < 2; ++ii) {
-          const int k = 2 * K + kk, j = 2 * J + jj, i = 2 * I + ii;
-          if (k >= f.nz || j >= f.ny || i >= f.nx) continue;
-          const long long cidx = ((long long)k * f.ny + j) * f.nx + i;
-          if (reduced[cidx]) s += r[cidx] - q[cidx];
-        }
-    rc[B] = s;
+// (N w)_c: the off-diagonal part of row c applied to the cell function w
+// (x-, x+, y-, y+, z-, z+, then the side list), s4 = S[c].
+template <class W>
+__device__ __forceinline__ float offdiag(const LevelView& L, const float4& s4, int c, int k, int j, int i, W w) {
+  const int nx = L.nx, plane = L.nx * L.ny;
+  float s = 0.0f;
+  if (i > 0) s += L.S[c - 1].y * w(c - 1, k, j, i - 1);
+  if (i + 1 < nx) s += s4.y * w(c + 1, k, j, i + 1);
+  if (j > 0) s += L.S[c - nx].z * w(c - nx, k, j - 1, i);
+  if (j + 1 < L.ny) s += s4.z * w(c + nx, k, j + 1, i);
+  if (k > 0) s += L.S[c - plane].w * w(c - plane, k - 1, j, i);
+  if (k + 1 < L.nz) s += s4.w * w(c + plane, k + 1, j, i);
+  if (s4.x < 0.0f) s += extras_sum(L, c, k, j, i, w);
+  return s;
+}
+
+// Fine-cell term of the restriction: r - A z with z = omega D^-1 r.
+__device__ __forceinline__ float down_value(const LevelView& L, const float* r, int c, int k, int j, int i) {
+  const float4 s4 = L.S[c];
+  const float rc = r[c];
+  if (s4.x == 0.0f) return rc;
+  const float n = offdiag(L, s4, c, k, j, i, [&](int nb, int, int, int) { return fabsf(L.S[nb].x) * r[nb]; });
+  return (1.0f - kOmega) * rc - kOmega * n;
+}
+
+// Post-smoothed z of a fine cell, z' = omega D^-1 r + z_{l+1}(parent).
+__device__ __forceinline__ float up_value(const LevelView& L, const float* r, const float* zc, int cnx, int cny,
+                                          int c, int k, int j, int i) {
+  auto zp = [&](int nb, int kn, int jn, int in) {
+    return kOmega * (fabsf(L.S[nb].x) * r[nb]) + zc[((kn >> 1) * cny + (jn >> 1)) * cnx + (in >> 1)];
+  };
+  const float4 s4 = L.S[c];
+  const float z0 = zp(c, k, j, i);
+  if (s4.x == 0.0f) return z0;
+  const float n = offdiag(L, s4, c, k, j, i, zp);
+  return (1.0f - kOmega) * z0 + kOmega * (fabsf(s4.x) * (r[c] - n));
+}
+
+// Launch geometry shared by the grid-wide level kernels: a workgroup of
+// 64 x 2 x 2 fine cells (x fastest), i.e. 32 coarse cells of one coarse
+// row; the 8 children of a coarse cell are lanes 2I, 2I+1 of 4 wavefronts.
+struct Tile {
+  int i, j, k, I, J, K, lane, w;
+};
+__device__ __forceinline__ Tile tile_of(int tiles_x, int cny) {
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  Tile t;
+  const int bx = blk % tiles_x, rest = blk / tiles_x;
+  t.J = rest % cny;
+  t.K = rest / cny;
+  t.lane = threadIdx.x & 63;
+  t.w = threadIdx.x >> 6;
+  t.i = bx * 64 + t.lane;
+  t.j = 2 * t.J + (t.w & 1);
+  t.k = 2 * t.K + (t.w >> 1);
+  t.I = bx * 32 + (t.lane >> 1);
+  return t;
+}
+
+// rc[coarse] = sum of v over its (up to) 8 children; v in every thread.
+__device__ __forceinline__ void restrict_store(const Tile& t, float v, int cnx, int cny, float* rc) {
+  __shared__ float red[4][32];
+  v += __shfl_xor(v, 1, 64);
+  if ((t.lane & 1) == 0) red[t.w][t.lane >> 1] = v;
+  __syncthreads();
+  if (threadIdx.x < 32) {
+    const int I = t.I - (t.lane >> 1) + threadIdx.x;   // wave 0: lane == threadIdx.x
+    if (I < cnx) rc[((long long)t.K * cny + t.J) * cnx + I] = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                                                            (red[2][threadIdx.x] + red[3][threadIdx.x]);
   }
 }
 
-// r_c = P^T (r - A z) on a coarse level.
-__global__ void k_resid_restrict(Dims f, Dims c, const float* __restrict__ A, const float* __restrict__ r,
-                                 const float* __restrict__ z, float* rc, const SolveScalars* sc) {
+// level l -> l+1 (l >= 1): r_{l+1} = P^T (r - A omega D^-1 r)
+__global__ __launch_bounds__(256) void k_down(LevelView L, int tiles_x, int cnx, int cny, const float* __restrict__ r,
+                                              float* rc, const SolveScalars* sc) {
   if (solve_done(sc)) return;
-  MG_STRIDE(B, c.n) {
-    const int I = (int)(B % c.nx);
-    const long long rr = B / c.nx;
-    const int J = (int)(rr % c.ny), K = (int)(rr / c.ny);
-    float s = 0.0f;
-    for (int kk = 0; kk < 2; ++kk)
-      for (int jj = 0; jj < 2; ++jj)
-        for (int ii = 0; ii < 2; ++ii) {
-          const int k = 2 * K + kk, j = 2 * J + jj, i = 2 * I + ii;
-          if (k >= f.nz || j >= f.ny || i >= f.nx) continue;
-          const long long cidx = ((long long)k * f.ny + j) * f.nx + i;
-          s += r[cidx] - apply27(f, A, z, cidx, k, j, i);
-        }
-    rc[B] = s;
+  const Tile t = tile_of(tiles_x, cny);
+  float v = 0.0f;
+  if (t.i < L.nx && t.j < L.ny && t.k < L.nz)
+    v = down_value(L, r, (t.k * L.ny + t.j) * L.nx + t.i, t.k, t.j, t.i);
+  restrict_store(t, v, cnx, cny, rc);
+}
+
+// level l+1 -> l (l >= 1): zt = post-smoothed (omega D^-1 r + P z_{l+1})
+__global__ __launch_bounds__(256) void k_up(LevelView L, int tiles_x, int cnx, int cny, const float* __restrict__ r,
+                                            const float* __restrict__ zc, float* zt, const SolveScalars* sc) {
+  if (solve_done(sc)) return;
+  const Tile t = tile_of(tiles_x, cny);
+  if (t.i < L.nx && t.j < L.ny && t.k < L.nz) {
+    const int c = (t.k * L.ny + t.j) * L.nx + t.i;
+    zt[c] = up_value(L, r, zc, cnx, cny, c, t.k, t.j, t.i);
   }
 }
 
-// z += P z_c (on level 0 only where mask, the reduced unknowns).
-__global__ void k_prolong(Dims f, Dims c, const float* __restrict__ zc, float* z,
-                          const unsigned char* __restrict__ mask, const SolveScalars* sc) {
+// level 0 -> 1: r_1 = P^T (r - q) over the reduced unknowns (q = A' z).
+__global__ __launch_bounds__(256) void k_restrict0(int nx, int ny, int nz, int tiles_x, int cnx, int cny,
+                                                   const float* __restrict__ r, const float* __restrict__ q,
+                                                   const unsigned char* __restrict__ reduced, float* rc,
+                                                   const SolveScalars* sc) {
   if (solve_done(sc)) return;
-  MG_STRIDE(idx, f.n) {
-    if (mask && !mask[idx]) continue;
-    const int i = (int)(idx % f.nx);
-    const long long rr = idx / f.nx;
-    const int j = (int)(rr % f.ny), k = (int)(rr / f.ny);
-    z[idx] += zc[((long long)(k >> 1) * c.ny + (j >> 1)) * c.nx + (i >> 1)];
+  const Tile t = tile_of(tiles_x, cny);
+  float v = 0.0f;
+  if (t.i < nx && t.j < ny && t.k < nz) {
+    const long long c = ((long long)t.k * ny + t.j) * nx + t.i;
+    if (reduced[c]) v = r[c] - q[c];
+  }
+  restrict_store(t, v, cnx, cny, rc);
+}
+
+// level 1 -> 0: z += P z_1 on the reduced unknowns.
+__global__ __launch_bounds__(256) void k_prolong0(int nx, int ny, int nz, int tiles_x, int cnx, int cny,
+                                                  const float* __restrict__ zc, float* z,
+                                                  const unsigned char* __restrict__ reduced, const SolveScalars* sc) {
+  if (solve_done(sc)) return;
+  const Tile t = tile_of(tiles_x, cny);
+  if (t.i < nx && t.j < ny && t.k < nz) {
+    const long long c = ((long long)t.k * ny + t.j) * nx + t.i;
+    if (reduced[c]) z[c] += zc[((long long)t.K * cny + t.J) * cnx + t.I];
   }
 }
 
-// zout = z + omega D^-1 (r - A z) on a coarse level.
-__global__ void k_post(Dims d, const float* __restrict__ A, const float* __restrict__ dinv,
-                       const float* __restrict__ r, const float* __restrict__ z, float* zout,
-                       const SolveScalars* sc) {
+__global__ void k_pre(long long n, const float* __restrict__ r, const float* __restrict__ dinv, float* z,
+                      const SolveScalars* sc) {
   if (solve_done(sc)) return;
-  MG_STRIDE(idx, d.n) {
-    const int i = (int)(idx % d.nx);
-    const long long rr = idx / d.nx;
-    const int j = (int)(rr % d.ny), k = (int)(rr / d.ny);
-    zout[idx] = z[idx] + kOmega * (dinv[idx] * (r[idx] - apply27(d, A, z, idx, k, j, i)));
-  }
+  MG_STRIDE(i, n) z[i] = kOmega * (dinv[i] * r[i]);
 }
 
 // z += omega D^-1 (r - q) on level 0 (q = A' z).
@@ -266,23 +392,67 @@ __global__ void k_post0(long long n, const float* __restrict__ dinv, const float
   MG_STRIDE(i, n) z[i] += kOmega * (dinv[i] * (r[i] - q[i]));
 }
 
-// z = M r with the dense coarsest inverse (column-major), in FP64: the
-// coarsest matrix of a 1000:1 two-fluid problem is too ill-conditioned for
-// an FP32 inverse.
-__global__ void k_dense(int N, const double* __restrict__ minv, const float* __restrict__ r, float* z,
-                        const SolveScalars* sc) {
-  if (solve_done(sc)) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  double s = 0.0;
-  for (int jcol = 0; jcol < N; ++jcol) s += minv[(long long)jcol * N + i] * (double)r[jcol];
-  z[i] = (float)s;
-}
-
-struct Level {
-  Dims d;
-  DevBuf A64, A32, dinv, r, z, zt;
+// The levels from `first` down, in one workgroup: vectors of level l in LDS
+// at [off[l], off[l] + n_l) (r) and [off[l] + n_l, off[l] + 2 n_l) (z).
+struct TailArgs {
+  int first, last;                 // last = the coarsest level
+  int off[kMaxLevels];
+  LevelView lv[kMaxLevels];
+  const float* rin;                // r of level `first`
+  float* zout;                     // z of level `first`
+  const double* minv;              // coarsest dense inverse (column-major)
 };
+
+__global__ __launch_bounds__(1024) void k_tail(TailArgs A, const SolveScalars* sc) {
+  if (solve_done(sc)) return;
+  extern __shared__ float lds[];
+  const int t = threadIdx.x, nt = blockDim.x;
+  auto cells = [&](int l) { return A.lv[l].nx * A.lv[l].ny * A.lv[l].nz; };
+  for (int c = t; c < cells(A.first); c += nt) lds[A.off[A.first] + c] = A.rin[c];
+  __syncthreads();
+  for (int l = A.first; l < A.last; ++l) {
+    const LevelView& F = A.lv[l];
+    const LevelView& C = A.lv[l + 1];
+    const float* r = lds + A.off[l];
+    float* rc = lds + A.off[l + 1];
+    for (int B = t; B < cells(l + 1); B += nt) {
+      const int I = B % C.nx, rr = B / C.nx, J = rr % C.ny, K = rr / C.ny;
+      float v = 0.0f;
+      for (int kk = 0; kk < 2; ++kk)
+        for (int jj = 0; jj < 2; ++jj)
+          for (int ii = 0; ii < 2; ++ii) {
+            const int k = 2 * K + kk, j = 2 * J + jj, i = 2 * I + ii;
+            if (k < F.nz && j < F.ny && i < F.nx) v += down_value(F, r, (k * F.ny + j) * F.nx + i, k, j, i);
+          }
+      rc[B] = v;
+    }
+    __syncthreads();
+  }
+  {
+    const int N = cells(A.last);
+    const float* r = lds + A.off[A.last];
+    float* z = lds + A.off[A.last] + N;
+    for (int i = t; i < N; i += nt) {
+      double s = 0.0;
+      for (int jc = 0; jc < N; ++jc) s += A.minv[(long long)jc * N + i] * (double)r[jc];
+      z[i] = (float)s;
+    }
+  }
+  __syncthreads();
+  for (int l = A.last - 1; l >= A.first; --l) {
+    const LevelView& F = A.lv[l];
+    const LevelView& C = A.lv[l + 1];
+    const float* r = lds + A.off[l];
+    float* z = lds + A.off[l] + cells(l);
+    const float* zc = lds + A.off[l + 1] + cells(l + 1);
+    for (int c = t; c < cells(l); c += nt) {
+      const int i = c % F.nx, rr = c / F.nx, j = rr % F.ny, k = rr / F.ny;
+      z[c] = up_value(F, r, zc, C.nx, C.ny, c, k, j, i);
+    }
+    __syncthreads();
+  }
+  for (int c = t; c < cells(A.first); c += nt) A.zout[c] = lds[A.off[A.first] + cells(A.first) + c];
+}
 
 // Inverse of a dense symmetric positive definite matrix (Cholesky).
 bool spd_inverse(std::vector<double>& a, int n) {
@@ -317,6 +487,23 @@ bool spd_inverse(std::vector<double>& a, int n) {
   return true;
 }
 
+struct Level {
+  Dims d;
+  DevBuf A64;                   // 27 x n FP64 stencil
+  DevBuf S;                     // float4 per cell: cycle storage
+  DevBuf xcell, xval;           // side list of rows with couplings outside the 7 points
+  int m = 0;                    // its length
+  long long xcap = 0;           // its capacity (rows)
+  DevBuf r, zt;                 // cycle vectors: right-hand side, corrected z
+  LevelView view() const {
+    return {d.nx, d.ny, d.nz, m, S.as<float4>(), xcell.as<int>(), xval.as<float>()};
+  }
+};
+
+constexpr int kTailThreads = 1024;
+constexpr int kTailLdsBytes = 64 * 1024;
+constexpr int kDefaultTailCells = 8192;
+
 }  // namespace
 }  // namespace nfa
 
@@ -326,12 +513,66 @@ struct nfa_mg_s {
   Poisson* op = nullptr;
   int L = 0;                    // levels including level 0
   Level lv[kMaxLevels];         // lv[0]: dims only
-  DevBuf q0, group_of, minv;
+  DevBuf q0, group_of, minv, xcnt;
   int ncoarse = 0;
+  int tail_cells = kDefaultTailCells;
+  int first_tail = 1;           // first level run by the one-workgroup tail kernel
   int built_version = -1;       // op->version the coarse operators belong to
 };
 
 namespace nfa {
+namespace {
+
+// The first level of the tail: the coarsest, or further up while each level
+// has at most tail_cells cells and the tail's vectors fit in LDS.
+void plan_tail(nfa_mg_s& mg) {
+  int first = mg.L - 1;
+  long long floats = 2 * mg.lv[first].d.n;
+  while (first > 1) {
+    const long long n = mg.lv[first - 1].d.n;
+    if (n > mg.tail_cells || (floats + 2 * n) * 4 > kTailLdsBytes) break;
+    floats += 2 * n;
+    --first;
+  }
+  mg.first_tail = first;
+}
+
+// Side list of level l: count per block, scan on the host, scatter in cell
+// order.  Grows the list's storage when the merge set needs more rows.
+nfa_status build_side_list(nfa_mg_s& mg, Level& C, hipStream_t st) {
+  const long long nb = (C.d.n + kBlock - 1) / kBlock;
+  int* cnt = mg.xcnt.as<int>();
+  k_xcount<<<(int)nb, kBlock, 0, st>>>(C.d.n, C.S.as<float4>(), cnt);
+  NFA_CHECK_LAUNCH();
+  std::vector<int> h(nb);
+  NFA_HIP(hipMemcpyAsync(h.data(), cnt, nb * sizeof(int), hipMemcpyDeviceToHost, st));
+  NFA_HIP(hipStreamSynchronize(st));
+  long long m = 0;
+  for (long long b = 0; b < nb; ++b) {
+    const int c = h[b];
+    h[b] = (int)m;
+    m += c;
+  }
+  C.m = (int)m;
+  if (m == 0) return NFA_OK;
+  if (m > C.xcap) {
+    const long long cap = std::min<long long>(C.d.n, m + m / 2 + 256);
+    if (C.xcell.alloc(cap * sizeof(int)) != hipSuccess || C.xval.alloc(cap * kXSlots * sizeof(float)) != hipSuccess) {
+      C.xcap = 0;
+      C.m = 0;
+      return fail(NFA_ERR_HIP, "multigrid: out of device memory for the side list");
+    }
+    C.xcap = cap;
+  }
+  NFA_HIP(hipMemcpyAsync(cnt + nb, h.data(), nb * sizeof(int), hipMemcpyHostToDevice, st));
+  k_xscatter<<<(int)nb, kBlock, 0, st>>>(C.d.n, C.S.as<float4>(), C.A64.as<double>(), cnt + nb, C.xcell.as<int>(),
+                                         C.xval.as<float>());
+  NFA_CHECK_LAUNCH();
+  NFA_HIP(hipStreamSynchronize(st));   // h must outlive the copy
+  return NFA_OK;
+}
+
+}  // namespace
 
 nfa_status mg_setup(nfa_mg_s& mg, hipStream_t st) {
   Poisson& op = *mg.op;
@@ -347,11 +588,15 @@ nfa_status mg_setup(nfa_mg_s& mg, hipStream_t st) {
       k_level1<<<blocks_for(C.d.n), kBlock, 0, st>>>(mg.lv[0].d, C.d, c.tx, c.txb, c.ty, c.tz,
                                                      g.reduced.as<unsigned char>(), g.root.as<int>(),
                                                      mg.group_of.as<int>(), g.g_off.as<int>(), g.g_mem.as<int>(),
-                                                     C.A64.as<double>(), C.A32.as<float>(), C.dinv.as<float>());
+                                                     C.A64.as<double>(), C.S.as<float4>());
     else
       k_coarsen<<<blocks_for(C.d.n), kBlock, 0, st>>>(mg.lv[l - 1].d, C.d, mg.lv[l - 1].A64.as<double>(),
-                                                      C.A64.as<double>(), C.A32.as<float>(), C.dinv.as<float>());
+                                                      C.A64.as<double>(), C.S.as<float4>());
     NFA_CHECK_LAUNCH();
+  }
+  for (int l = 1; l < mg.L - 1; ++l) {
+    const nfa_status e = build_side_list(mg, mg.lv[l], st);
+    if (e != NFA_OK) return e;
   }
   // the coarsest level: dense, regularized, inverted on the host
   const Level& Z = mg.lv[mg.L - 1];
@@ -407,32 +652,61 @@ nfa_status mg_vcycle(nfa_mg_s& mg, const float* r0, float* z0, const SolveScalar
   const Dims d0 = mg.lv[0].d;
   auto apply0 = [&](float* z) {   // q0 = A' z (z's slaves take their root's value)
     launch_merge_copy<float>(g, z, st, sc);
+    const bool rec = prof_begin(op, st);
     launch_stencil<float>(g, c32, z, nullptr, q0, nullptr, sc, ST_APPLY, st);
+    prof_end(op, rec, kProfMgApply, st);
     launch_merge_gather<float>(g, q0, st, sc);
   };
-  // downward
+  // the grid of a fine level l in 64 x 2 x 2 tiles
+  auto tiles = [&](int l, int* tx) {
+    *tx = (mg.lv[l].d.nx + 63) / 64;
+    return (int)((long long)*tx * mg.lv[l + 1].d.ny * mg.lv[l + 1].d.nz);
+  };
+  int tx;
+  // level 0, down
   k_pre<<<blocks_for(d0.n), kBlock, 0, st>>>(d0.n, r0, c32.dinv, z0, sc);
   apply0(z0);
-  k_restrict0<<<blocks_for(mg.lv[1].d.n), kBlock, 0, st>>>(d0, mg.lv[1].d, r0, q0, red, mg.lv[1].r.as<float>(), sc);
-  for (int l = 1; l < mg.L - 1; ++l) {
-    Level& F = mg.lv[l];
-    Level& C = mg.lv[l + 1];
-    k_pre<<<blocks_for(F.d.n), kBlock, 0, st>>>(F.d.n, F.r.as<float>(), F.dinv.as<float>(), F.z.as<float>(), sc);
-    k_resid_restrict<<<blocks_for(C.d.n), kBlock, 0, st>>>(F.d, C.d, F.A32.as<float>(), F.r.as<float>(),
-                                                            F.z.as<float>(), C.r.as<float>(), sc);
+  {
+    const int nb = tiles(0, &tx);
+    const Dims& C = mg.lv[1].d;
+    k_restrict0<<<nb, 256, 0, st>>>(d0.nx, d0.ny, d0.nz, tx, C.nx, C.ny, r0, q0, red, mg.lv[1].r.as<float>(), sc);
   }
-  Level& Z = mg.lv[mg.L - 1];
-  k_dense<<<(int)((Z.d.n + 255) / 256), 256, 0, st>>>((int)Z.d.n, mg.minv.as<double>(), Z.r.as<float>(),
-                                                      Z.zt.as<float>(), sc);
-  // upward: each level's corrected z ends in zt
-  for (int l = mg.L - 2; l >= 1; --l) {
-    Level& F = mg.lv[l];
-    Level& C = mg.lv[l + 1];
-    k_prolong<<<blocks_for(F.d.n), kBlock, 0, st>>>(F.d, C.d, C.zt.as<float>(), F.z.as<float>(), nullptr, sc);
-    k_post<<<blocks_for(F.d.n), kBlock, 0, st>>>(F.d, F.A32.as<float>(), F.dinv.as<float>(), F.r.as<float>(),
-                                                 F.z.as<float>(), F.zt.as<float>(), sc);
+  // grid-wide levels, down
+  const int T = mg.first_tail;
+  for (int l = 1; l < T; ++l) {
+    const int nb = tiles(l, &tx);
+    const Dims& C = mg.lv[l + 1].d;
+    k_down<<<nb, 256, 0, st>>>(mg.lv[l].view(), tx, C.nx, C.ny, mg.lv[l].r.as<float>(), mg.lv[l + 1].r.as<float>(), sc);
   }
-  k_prolong<<<blocks_for(d0.n), kBlock, 0, st>>>(d0, mg.lv[1].d, mg.lv[1].zt.as<float>(), z0, red, sc);
+  // the tail: levels T.. in one workgroup
+  {
+    TailArgs A{};
+    A.first = T;
+    A.last = mg.L - 1;
+    int off = 0;
+    for (int l = T; l < mg.L; ++l) {
+      A.off[l] = off;
+      A.lv[l] = mg.lv[l].view();
+      off += 2 * (int)mg.lv[l].d.n;
+    }
+    A.rin = mg.lv[T].r.as<float>();
+    A.zout = mg.lv[T].zt.as<float>();
+    A.minv = mg.minv.as<double>();
+    k_tail<<<1, kTailThreads, off * sizeof(float), st>>>(A, sc);
+  }
+  // grid-wide levels, up
+  for (int l = T - 1; l >= 1; --l) {
+    const int nb = tiles(l, &tx);
+    const Dims& C = mg.lv[l + 1].d;
+    k_up<<<nb, 256, 0, st>>>(mg.lv[l].view(), tx, C.nx, C.ny, mg.lv[l].r.as<float>(), mg.lv[l + 1].zt.as<float>(),
+                             mg.lv[l].zt.as<float>(), sc);
+  }
+  // level 0, up
+  {
+    const int nb = tiles(0, &tx);
+    const Dims& C = mg.lv[1].d;
+    k_prolong0<<<nb, 256, 0, st>>>(d0.nx, d0.ny, d0.nz, tx, C.nx, C.ny, mg.lv[1].zt.as<float>(), z0, red, sc);
+  }
   apply0(z0);
   k_post0<<<blocks_for(d0.n), kBlock, 0, st>>>(d0.n, c32.dinv, r0, q0, z0, sc);
   NFA_CHECK_LAUNCH();
@@ -480,17 +754,27 @@ extern "C" nfa_status nfa_mg_create(nfa_poisson op, nfa_mg* out) {
     return fail(NFA_ERR_INVALID, "nfa_mg_create: the grid has a single cell");
   }
   hipError_t e;
-  if ((e = mg->q0.alloc(g.n * 4)) != hipSuccess || (e = mg->group_of.alloc(g.n * 4)) != hipSuccess) return bad(e);
+  if ((e = mg->q0.alloc(g.n * 4)) != hipSuccess || (e = mg->group_of.alloc(g.n * 4)) != hipSuccess ||
+      (e = mg->xcnt.alloc(2 * ((mg->lv[1].d.n + kBlock - 1) / kBlock) * sizeof(int))) != hipSuccess)
+    return bad(e);
   for (int l = 1; l < mg->L; ++l) {
     Level& C = mg->lv[l];
     const size_t n = (size_t)C.d.n;
-    if ((e = C.A64.alloc(27 * n * 8)) != hipSuccess || (e = C.A32.alloc(27 * n * 4)) != hipSuccess ||
-        (e = C.dinv.alloc(n * 4)) != hipSuccess || (e = C.r.alloc(n * 4)) != hipSuccess ||
-        (e = C.z.alloc(n * 4)) != hipSuccess || (e = C.zt.alloc(n * 4)) != hipSuccess)
+    if ((e = C.A64.alloc(27 * n * 8)) != hipSuccess || (e = C.S.alloc(n * sizeof(float4))) != hipSuccess ||
+        (e = C.r.alloc(n * 4)) != hipSuccess || (e = C.zt.alloc(n * 4)) != hipSuccess)
       return bad(e);
+    // side-list rows reserved for the merge set at creation (grown by set-up)
+    const long long cap = std::min<long long>((long long)n, 12LL * g.n_slaves + 256);
+    if (l < mg->L - 1) {
+      if ((e = C.xcell.alloc(cap * sizeof(int))) != hipSuccess ||
+          (e = C.xval.alloc(cap * kXSlots * sizeof(float))) != hipSuccess)
+        return bad(e);
+      C.xcap = cap;
+    }
   }
   mg->ncoarse = (int)mg->lv[mg->L - 1].d.n;
   if ((e = mg->minv.alloc((size_t)mg->ncoarse * mg->ncoarse * 8)) != hipSuccess) return bad(e);
+  plan_tail(*mg);
   *out = mg;
   return NFA_OK;
 }
@@ -511,6 +795,20 @@ extern "C" nfa_status nfa_mg_apply(nfa_mg mg, const float* r, float* z, nfa_stre
   if (e != NFA_OK) return e;
   launch_merge_copy<float>(*mg->op->g, z, S(s), nullptr);
   NFA_CHECK_LAUNCH();
+  return NFA_OK;
+}
+
+extern "C" nfa_status nfa_mg_set_tail(nfa_mg mg, int max_cells) {
+  if (!mg) return fail(NFA_ERR_INVALID, "nfa_mg_set_tail: NULL handle");
+  mg->tail_cells = max_cells < 0 ? kDefaultTailCells : max_cells;
+  plan_tail(*mg);
+  return NFA_OK;
+}
+
+extern "C" nfa_status nfa_mg_side_rows(nfa_mg mg, int level, int* rows) {
+  if (!mg || !rows) return fail(NFA_ERR_INVALID, "nfa_mg_side_rows: NULL argument");
+  if (level < 1 || level >= mg->L) return fail(NFA_ERR_INVALID, "nfa_mg_side_rows: level out of range");
+  *rows = mg->lv[level].m;
   return NFA_OK;
 }
 

@@ -124,13 +124,17 @@ struct Poisson {
   DevBuf hist;                                  // double per-iteration ||r||^2 (kHistCap)
   SolveScalars* h_scal = nullptr;               // pinned host mirror (2 slots)
   hipEvent_t ev[2] = {nullptr, nullptr};
-  // optional timing of the stencil sweeps inside solves (HIP events)
+  // optional timing of selected launches inside solves (HIP events), by
+  // kind: 0 / 1 sweep A in FP64 / FP32, 2 the multigrid cycle's level-0
+  // operator apply (FP32)
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;              // 2 per recorded launch
-  std::vector<int> prof_kind;                   // 0 FP64, 1 FP32 per recorded launch
+  std::vector<int> prof_kind;                   // kind per recorded launch
+  std::vector<int> prof_seq;                    // iteration (since the last harvest) per recorded launch
   int prof_used = 0;
-  long long prof_launches[2] = {0, 0};
-  double prof_ms[2] = {0.0, 0.0};
+  int prof_iter = 0;                            // iterations enqueued since the last harvest
+  long long prof_launches[3] = {0, 0, 0};
+  double prof_ms[3] = {0.0, 0.0, 0.0};
   Coeffs<double> c64() const {
     return {tx64.as<double>(), txb64.as<double>(), ty64.as<double>(), tz64.as<double>(), dinv64.as<double>()};
   }
@@ -138,6 +142,22 @@ struct Poisson {
     return {tx32.as<float>(), txb32.as<float>(), ty32.as<float>(), tz32.as<float>(), dinv32.as<float>()};
   }
 };
+
+constexpr int kProfMgApply = 2;
+
+// Open / close the timing of one launch on st when profiling is on.
+inline bool prof_begin(Poisson& op, hipStream_t st) {
+  const bool rec = op.prof_on && op.prof_used * 2 + 1 < (int)op.prof_ev.size();
+  if (rec) (void)hipEventRecord(op.prof_ev[2 * op.prof_used], st);
+  return rec;
+}
+inline void prof_end(Poisson& op, bool rec, int kind, hipStream_t st) {
+  if (!rec) return;
+  (void)hipEventRecord(op.prof_ev[2 * op.prof_used + 1], st);
+  op.prof_kind[op.prof_used] = kind;
+  op.prof_seq[op.prof_used] = op.prof_iter;
+  ++op.prof_used;
+}
 
 // ---------------------------------------------------------------- kernels
 // Stencil sweeps (stencil.hip).  mode: 0 q = A p (+ partial p.q if partials),

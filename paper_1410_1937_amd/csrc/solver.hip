@@ -43,25 +43,21 @@ inline double sq(double a) { return a * a; }
 // Sweep A wrapped in a timing event pair when profiling is on.
 template <class T>
 int timed_cg_a(Poisson& op, CG<T>& B, int j, bool flex, hipStream_t st) {
-  const bool rec = op.prof_on && op.prof_used * 2 + 1 < (int)op.prof_ev.size();
-  if (rec) (void)hipEventRecord(op.prof_ev[2 * op.prof_used], st);
+  const bool rec = prof_begin(op, st);
   const int np = launch_cg_a<T>(*op.g, B.C, B.z, B.p[j & 1], B.p[(j + 1) & 1], B.x, B.r, B.q,
                                 op.partials.as<double>(), op.scal.as<SolveScalars>(), flex, B.vec, st);
-  if (rec) {
-    (void)hipEventRecord(op.prof_ev[2 * op.prof_used + 1], st);
-    op.prof_kind[op.prof_used] = sizeof(T) == 8 ? 0 : 1;
-    ++op.prof_used;
-  }
+  prof_end(op, rec, sizeof(T) == 8 ? 0 : 1, st);
   return np;
 }
 
-// Accumulate the first `ran` recorded launches (those after the solver state
-// said done exited at once and are not counted).
+// Accumulate the recorded launches of the first `ran` iterations enqueued
+// since the last harvest (later ones saw the solver state say done and
+// exited at once).
 void harvest_profile(Poisson& op, int ran) {
   if (!op.prof_on) return;
   (void)hipDeviceSynchronize();
-  const int upto = std::min(op.prof_used, std::max(0, ran));
-  for (int i = 0; i < upto; ++i) {
+  for (int i = 0; i < op.prof_used; ++i) {
+    if (op.prof_seq[i] >= ran) continue;
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, op.prof_ev[2 * i], op.prof_ev[2 * i + 1]) == hipSuccess) {
       op.prof_ms[op.prof_kind[i]] += ms;
@@ -69,6 +65,7 @@ void harvest_profile(Poisson& op, int ran) {
     }
   }
   op.prof_used = 0;
+  op.prof_iter = 0;
 }
 
 nfa_status read_scalars(Poisson& op, hipStream_t st, SolveScalars* out) {
@@ -123,6 +120,7 @@ void enqueue_iter(Poisson& op, CG<T>& B, int j, int pc, void* unet, nfa_status* 
     launch_finalize(parts, nb, 1, PH_UPDF, sc, hist, st);
   else
     launch_finalize_merge<T>(g, false, B.z, parts, nb, 2, PH_UPD, sc, hist, st);
+  ++op.prof_iter;
 }
 
 // Start (fresh) or continue (after a residual replacement) the recurrence
@@ -192,6 +190,8 @@ nfa_status cg_solve(Poisson& op, const double* b, double* x64, const nfa_solve_o
   // replacement point and below its own accuracy
   const int check = pc == NFA_PC_MG ? std::min(std::max(1, o->check_every), 2) : std::max(1, o->check_every);
 
+  op.prof_used = 0;
+  op.prof_iter = 0;
   nfa_status e = residual64(op, b, x64, r64, PH_RRO, st);
   if (e != NFA_OK) return e;
   SolveScalars S{};
@@ -370,17 +370,21 @@ extern "C" nfa_status nfa_poisson_profile(nfa_poisson op, int enable) {
     const int pairs = 4096;
     op->prof_ev.resize(2 * pairs, nullptr);
     op->prof_kind.resize(pairs, 0);
+    op->prof_seq.resize(pairs, 0);
     for (auto& e : op->prof_ev) NFA_HIP(hipEventCreate(&e));
   }
   op->prof_on = enable != 0;
   op->prof_used = 0;
-  op->prof_launches[0] = op->prof_launches[1] = 0;
-  op->prof_ms[0] = op->prof_ms[1] = 0.0;
+  op->prof_iter = 0;
+  for (int k = 0; k < 3; ++k) {
+    op->prof_launches[k] = 0;
+    op->prof_ms[k] = 0.0;
+  }
   return NFA_OK;
 }
 
 extern "C" nfa_status nfa_poisson_profile_read(nfa_poisson op, int dtype, nfa_kernel_stats* out) {
-  if (!op || !out || (dtype != NFA_F64 && dtype != NFA_F32))
+  if (!op || !out || (dtype != NFA_F64 && dtype != NFA_F32 && dtype != NFA_PROF_MG_APPLY))
     return fail(NFA_ERR_INVALID, "nfa_poisson_profile_read: bad argument");
   out->launches = op->prof_launches[dtype];
   out->ms = op->prof_ms[dtype];

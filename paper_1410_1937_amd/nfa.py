@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libnfa.so")
 NFA_OK = 0
 NFA_NOT_CONVERGED = 1
 NFA_F64, NFA_F32 = 0, 1
+NFA_PROF_MG_APPLY = 2
 NFA_PC_JACOBI, NFA_PC_UNET, NFA_PC_TEST_SABOTAGE, NFA_PC_JACOBI_FCG, NFA_PC_MG = 1, 2, 3, 4, 5
 NFA_PREC_F64, NFA_PREC_MIXED = 0, 1
 
@@ -131,6 +132,8 @@ _sig("nfa_mg_destroy", None, [c_void_p])
 _sig("nfa_mg_setup", c_int, [c_void_p, c_void_p])
 _sig("nfa_mg_apply", c_int, [c_void_p, c_void_p, c_void_p, c_void_p])
 _sig("nfa_mg_info", c_int, [c_void_p, ctypes.POINTER(c_int), c_void_p])
+_sig("nfa_mg_set_tail", c_int, [c_void_p, c_int])
+_sig("nfa_mg_side_rows", c_int, [c_void_p, c_int, ctypes.POINTER(c_int)])
 _sig("nfa_mg_export", c_int, [c_void_p, c_int, c_void_p, c_void_p])
 _sig("nfa_stretch_axis", c_int, [c_double, c_double, c_int, c_int, c_void_p, c_void_p, c_double, c_int, c_void_p,
                                  ctypes.POINTER(c_int)])
@@ -273,6 +276,11 @@ class Multigrid:
     def setup(self):
         _check(lib.nfa_mg_setup(self.h, _stream()), "nfa_mg_setup")
 
+    def set_tail(self, max_cells):
+        """First level of the single-workgroup tail: at most max_cells cells
+        (0: the coarsest only; negative: the default)."""
+        _check(lib.nfa_mg_set_tail(self.h, int(max_cells)), "nfa_mg_set_tail")
+
     def apply(self, r, out=None):
         """z = V(r), one V-cycle (FP32 cell arrays)."""
         z = torch.empty_like(r) if out is None else out
@@ -285,6 +293,12 @@ class Multigrid:
         dims = (c_int * 48)()
         _check(lib.nfa_mg_info(self.h, ctypes.byref(L), dims), "nfa_mg_info")
         return [tuple(dims[3 * l:3 * l + 3]) for l in range(L.value)]
+
+    def side_rows(self, level):
+        """Rows of a level held in the side list (couplings beyond 7 points)."""
+        m = c_int()
+        _check(lib.nfa_mg_side_rows(self.h, level, ctypes.byref(m)), "nfa_mg_side_rows")
+        return m.value
 
     def export(self, level):
         """Level >= 1's FP64 stencil as (27, nz, ny, nx)."""
@@ -503,7 +517,10 @@ class Poisson:
         o.tol = tol
         o.max_iters = max_iters
         o.precision = {"f64": NFA_PREC_F64, "mixed": NFA_PREC_MIXED}[precision]
-        o.precond = {"jacobi": NFA_PC_JACOBI, "unet": NFA_PC_UNET, "jacobi_fcg": NFA_PC_JACOBI_FCG}[precond]
+        o.precond = {"jacobi": NFA_PC_JACOBI, "unet": NFA_PC_UNET, "jacobi_fcg": NFA_PC_JACOBI_FCG,
+                     "mg": NFA_PC_MG}[precond]
+        if precond == "mg":
+            o.mg = self.multigrid().h
         o.warm_start = 1 if warm_start else 0
         o.unet = None if unet is None else unet.h
         info = (SolveInfo * 2)()
@@ -522,8 +539,8 @@ class Poisson:
 
     def profile_read(self, dtype):
         ks = KernelStats()
-        _check(lib.nfa_poisson_profile_read(self.h, NFA_F64 if dtype == "f64" else NFA_F32,
-                                            ctypes.byref(ks)), "nfa_poisson_profile_read")
+        code = {"f64": NFA_F64, "f32": NFA_F32, "mg_apply": NFA_PROF_MG_APPLY}[dtype]
+        _check(lib.nfa_poisson_profile_read(self.h, code, ctypes.byref(ks)), "nfa_poisson_profile_read")
         return {"launches": ks.launches, "ms": ks.ms, "cells": ks.cells}
 
     def export(self, what):

@@ -5,7 +5,8 @@ Sets up the 512 x 256 x 192 breaking-wave projection problem
 Jacobi-PCG iterations (tolerance unreachable, so every iteration runs both
 sweeps), and finally a plain device-to-device copy of known size whose
 counter readings calibrate the FETCH_SIZE / WRITE_SIZE counters to bytes.
-With --unet L it also runs --unet-reps forward passes of an L-level learned
+With --mg N it runs N mixed-precision iterations preconditioned by the
+multigrid V-cycle (hierarchy set-up included).  With --unet L it also runs --unet-reps forward passes of an L-level learned
 preconditioner on the same grid (the committed weights for L = 5).  With
 --vof N it runs N split VOF advection steps (alternating sweep order) of the
 FP64 volume fraction through the workload's face velocities.  With --psi L
@@ -27,6 +28,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--iters", type=int, default=8, help="iterations per precision")
     ap.add_argument("--copy-mib", type=int, default=256, help="size of the calibration copy")
+    ap.add_argument("--mg", type=int, default=0, help="mixed-precision multigrid-preconditioned iterations")
     ap.add_argument("--unet", type=int, default=0, help="levels of the learned preconditioner to run (0: none)")
     ap.add_argument("--unet-reps", type=int, default=5)
     ap.add_argument("--vof", type=int, default=0, help="VOF advection steps to run")
@@ -50,6 +52,10 @@ def main(argv=None):
         _, res = op.solve(b, tol=1e-30, precision=prec, max_iters=args.iters)
         torch.cuda.synchronize()
         print(f"[profile_run] {prec}: {res.iterations} iterations", flush=True)
+    if args.mg:
+        _, res = op.solve(b, tol=1e-30, precision="mixed", precond="mg", max_iters=args.mg)
+        torch.cuda.synchronize()
+        print(f"[profile_run] mixed+mg: {res.iterations} iterations", flush=True)
     if args.unet:
         import os
         import numpy as np

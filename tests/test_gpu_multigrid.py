@@ -55,19 +55,30 @@ def test_every_level_matches_the_oracle_and_rebuilds_bitwise(body, bc, shape):
         ref = H.A[l]
         scale = np.max(np.abs(ref.diagonal()))
         assert abs(A - ref).max() <= 1e-12 * scale, l
+        if l < len(levels) - 1:
+            # rows coupled beyond the 7 points, as the cycle's side list holds them
+            far = np.zeros(st.shape[1:], dtype=bool)
+            for o in set(range(27)) - {4, 10, 12, 13, 14, 16, 22}:
+                far |= st[o] != 0
+            assert mg.side_rows(l) == int(far.sum()), l
     mg.setup()
     for l in range(1, len(levels)):
         assert np.array_equal(host(mg.export(l)), first[l - 1])
 
 
-@pytest.mark.parametrize("body,bc,shape", CASES[:2])
-def test_one_vcycle_matches_the_oracle(body, bc, shape):
+@pytest.mark.parametrize("tail", [-1, 0])
+@pytest.mark.parametrize("body,bc,shape", CASES + [("sphere", (0,) * 6, (64, 48, 40))])
+def test_one_vcycle_matches_the_oracle(body, bc, shape, tail):
+    """tail -1: every coarse level in the one-workgroup kernel; 0: the
+    grid-wide level kernels down to the coarsest."""
     wl = fx.small(6, *shape, body=body, bc=bc)
     og, ob, oop, b = oracle_for(wl)
     H = multigrid.Hierarchy(oop)
     g, op = gpu_for(wl)
     mg = op.multigrid()
+    mg.set_tail(tail)
     mg.setup()
+    assert mg.side_rows(1) > 0   # merges couple level 1 beyond the 7 points
     red = oop.reduced_mask() > 0
     r = np.where(red, np.random.default_rng(0).standard_normal(og.shape), 0.0).astype(np.float32)
     z = host(mg.apply(torch.as_tensor(r, device="cuda")))
@@ -75,14 +86,15 @@ def test_one_vcycle_matches_the_oracle(body, bc, shape):
     assert rel_l2(z[red | (ob.root.reshape(og.shape) >= 0)], ref[red | (ob.root.reshape(og.shape) >= 0)]) <= 1e-4
 
 
-@pytest.mark.parametrize("name", ["c1", "sphere"])
-def test_mg_solve_meets_tolerance_and_the_oracle(name):
+@pytest.mark.parametrize("name,tail", [("c1", -1), ("sphere", -1), ("sphere", 0)])
+def test_mg_solve_meets_tolerance_and_the_oracle(name, tail):
     wl = fx.c1() if name == "c1" else fx.small(7, 37, 21, 17, body="sphere")
     og, ob, oop, b = oracle_for(wl)
     ref = solvers.pcg(oop, b, tol=1e-11)
     H = multigrid.Hierarchy(oop)
     ref_mg = solvers.fcg(oop, b, H.precond, tol=1e-10, fallback=False)
     g, op = gpu_for(wl)
+    op.multigrid().set_tail(tail)
     bt = torch.as_tensor(b, device="cuda")
     x, res = op.solve(bt, tol=1e-10, precision="mixed", precond="mg")
     assert res.status == 0 and res.relres <= 1e-10 and not res.fallback
