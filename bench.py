@@ -14,8 +14,8 @@ preconditioner, its hierarchy rebuilt from each assembly inside the step;
 the plain FP64 Jacobi-PCG projection is timed beside it.  One extra,
 instrumented step measures, with HIP events, the average durations of sweep
 A of the fused CG iteration (new direction, operator apply, deferred x
-update) and of the V-cycle's level-0 operator apply; the roofline is that of
-the one with the larger summed time.
+update) and of the V-cycle's fused level-0 down and up sweeps; the roofline
+is that of the one with the largest summed time.
 The CPU baseline is the FP64 oracle on the host cores, timed on a bounded
 sample (a few iterations on the full grid) and scaled to one projection.
 Beside the metric it times one Runge-Kutta cycle (two projections), one
@@ -177,22 +177,24 @@ def main():
     # that of the one with the larger summed time (the dominant kernel)
     op.profile(True)
     step("chosen")
-    kinds = {k: op.profile_read(k) for k in ("f32", "f64", "mg_apply")}
+    kinds = {k: op.profile_read(k) for k in ("f32", "f64", "mg_down", "mg_up")}
     op.profile(False)
     # sweep A moves, per cell: z, p_old, tx, ty, tz, x read; p_new, q, x
-    # written (9 words: 36 B in FP32, 72 B in FP64).  The level-0 apply
-    # reads z, tx, ty, tz and writes q (5 words, 20 B in FP32).  Neighbour
-    # re-reads are cache hits and not counted.
+    # written (9 words: 36 B in FP32, 72 B in FP64).  The fused level-0
+    # down sweep reads r, D^-1, tx, ty, tz (4 B each) and the unknown flag
+    # (1 B) and writes one level-1 value per 8 cells (0.5 B): 21.5 B; the up
+    # sweep reads the same plus one level-1 value per 8 cells and writes z:
+    # 25.5 B.  Neighbour re-reads are cache hits and not counted.
     wx = next((w for w in (4, 2) if wl.shape[2] % (w * 128) == 0), 1)
     meta = {"f32": (36, "k_cg_a<float, 4, 1, true>"), "f64": (72, f"k_cg_a<double, 2, {wx}, false>"),
-            "mg_apply": (20, "k_stencil<float, false>")}
+            "mg_down": (21.5, "k_l0<false>"), "mg_up": (25.5, "k_l0<true>")}
     entries = {}
     for k, ks in kinds.items():
         if ks["launches"] == 0:
             continue
         bpc, kname = meta[k]
         avg_ms = ks["ms"] / ks["launches"]
-        bpl = bpc * ks["cells"]
+        bpl = int(bpc * ks["cells"])
         gbs = bpl / (avg_ms * 1e-3) / 1e9
         entries[k] = {"kernel": kname, "avg_launch_ms": round(avg_ms, 5), "launches": ks["launches"],
                       "ms_per_step": round(ks["ms"], 3), "algorithmic_bytes_per_launch": bpl,

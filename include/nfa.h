@@ -268,7 +268,7 @@ void nfa_solve_opts_default(nfa_solve_opts* opts);
  * couplings to blocks more than one apart while keeping their diagonal
  * terms); at least one coarsening; the coarsest level (at most 600 cells)
  * solved with a dense inverse (empty rows identity; c v v^T added when
- * every boundary is Neumann).  V-cycle in FP32: damped Jacobi (0.7), one
+ * every boundary is Neumann).  V-cycle in FP32: damped Jacobi (0.9), one
  * sweep before and one after the coarse correction -- symmetric.  Levels
  * >= 1 are held in FP32 as (D^-1, +x, +y, +z couplings) per cell plus a
  * side list of the rows that merges couple beyond the 7 points; the levels
@@ -294,7 +294,7 @@ nfa_status nfa_mg_setup(nfa_mg mg, nfa_stream s);
 /* nfa_mg_set_tail -- the single-workgroup part of the cycle starts at the
  * first level with at most max_cells cells whose vectors (with those of
  * every coarser level) fit in 64 KiB of LDS; 0: only the coarsest level;
- * < 0: the default, 8192.  Changes no result beyond FP32 rounding order. */
+ * < 0: the default, 1024.  Changes no result beyond FP32 rounding order. */
 nfa_status nfa_mg_set_tail(nfa_mg mg, int max_cells);
 /* nfa_mg_apply -- z = V(r), one V-cycle; r, z: DEVICE float cells (r zero
  * off the reduced unknowns; z's slaves take their root's value).  ASYNC. */
@@ -302,6 +302,11 @@ nfa_status nfa_mg_apply(nfa_mg mg, const float* r, float* z, nfa_stream s);
 /* nfa_mg_info -- number of levels and, if dims is not NULL, (nz, ny, nx) of
  * each level (HOST, 3 * levels ints, at most 48). */
 nfa_status nfa_mg_info(nfa_mg mg, int* levels, int* dims);
+/* nfa_mg_set_params -- omega: damping of the Jacobi sweeps (0 < omega < 1,
+ * default 0.9); alpha: scale of every coarse-grid correction, z += alpha P z_c
+ * (0 < alpha < 2, default 1; any such alpha keeps the cycle symmetric
+ * positive definite).  Errors: NFA_ERR_INVALID. */
+nfa_status nfa_mg_set_params(nfa_mg mg, double omega, double alpha);
 /* nfa_mg_side_rows -- rows of level >= 1 (below the coarsest) held in the
  * side list by the last set-up (couplings beyond the 7 points). */
 nfa_status nfa_mg_side_rows(nfa_mg mg, int level, int* rows);
@@ -325,20 +330,21 @@ nfa_status nfa_poisson_solve(nfa_poisson op, const double* b, double* x, const n
 
 /* Timing of the operator sweeps inside solves.  nfa_poisson_profile(op, 1)
  * brackets the first 4096 timed launches of each later solve (sweep A of
- * every iteration; with NFA_PC_MG also the two level-0 operator applies of
- * each V-cycle) with HIP events on the solve's stream (creating the events
- * here, not in the solve) and resets the counters;
+ * every iteration; with NFA_PC_MG also the fused level-0 down and up sweeps
+ * of each V-cycle) with HIP events on the solve's stream (creating the
+ * events here, not in the solve) and resets the counters;
  * nfa_poisson_profile(op, 0) stops.  Only launches of iterations that ran
  * are counted. */
-#define NFA_PROF_MG_APPLY 2
+#define NFA_PROF_MG_DOWN 2
+#define NFA_PROF_MG_UP 3
 typedef struct {
   long long launches; /* stencil launches timed */
   double ms;          /* their summed duration */
   long long cells;    /* cells swept per launch */
 } nfa_kernel_stats;
 nfa_status nfa_poisson_profile(nfa_poisson op, int enable);
-/* dtype NFA_F64 or NFA_F32: sweep A of that precision; NFA_PROF_MG_APPLY:
- * the V-cycle's level-0 operator apply (FP32).  Synchronous. */
+/* dtype NFA_F64 or NFA_F32: sweep A of that precision; NFA_PROF_MG_DOWN /
+ * NFA_PROF_MG_UP: the V-cycle's fused level-0 sweeps (FP32).  Synchronous. */
 nfa_status nfa_poisson_profile_read(nfa_poisson op, int dtype, nfa_kernel_stats* out);
 
 /* nfa_poisson_residual -- r = b' - A'x in FP64 (the true residual that

@@ -20,9 +20,12 @@ further).  Coarsening stops at `min_coarse` cells or fewer.
 
 V-cycle (symmetric, so it preconditions CG): on level l with right-hand
 side r,
-    z = omega D^-1 r;  r_c = P^T (r - A z);  z += P V(r_c);
+    z = omega D^-1 r;  r_c = P^T (r - A z);  z += alpha P V(r_c);
     z += omega D^-1 (r - A z)
-with D the diagonal (rows without an unknown get z = 0).  The coarsest level
+with D the diagonal (rows without an unknown get z = 0) and alpha the scale
+of the coarse correction (1: the plain cycle; 0 < alpha < 2 keeps the cycle
+symmetric positive definite, since the coarse step then contracts in the
+energy norm).  The coarsest level
 is solved exactly: empty rows become identity rows and, when every boundary
 is Neumann, c v v^T is added (v the indicator of the non-empty rows, c their
 mean diagonal), which leaves A x = b for every compatible b.
@@ -32,7 +35,8 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-OMEGA = 0.7
+OMEGA = 0.9
+ALPHA = 1.0
 MIN_COARSE = 600
 
 
@@ -60,9 +64,10 @@ def _drop_far(A, shape):
 class Hierarchy:
     """Operators, shapes and aggregation maps of every level."""
 
-    def __init__(self, op, min_coarse=MIN_COARSE, omega=OMEGA):
+    def __init__(self, op, min_coarse=MIN_COARSE, omega=OMEGA, alpha=ALPHA):
         self.op = op
         self.omega = omega
+        self.alpha = alpha
         g = op.grid
         shape = g.shape
         A = op.csr()
@@ -106,7 +111,7 @@ class Hierarchy:
         A, P, dinv, w = self.A[level], self.maps[level], self.dinv[level], self.omega
         z = w * (dinv * r)
         rc = P.T @ (r - A @ z)
-        z = z + P @ self.vcycle(rc, level + 1)
+        z = z + self.alpha * (P @ self.vcycle(rc, level + 1))
         return z + w * (dinv * (r - A @ z))
 
     def precond(self, r):

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <map>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "device_util.h"
@@ -415,6 +416,29 @@ nfa_status compute_body(Grid& g, const double* psi, double theta, int S, hipStre
   }
   g.n_groups = (int)groot.size();
   g.n_slaves = (int)scell.size();
+  // rows whose merged-operator row differs from the plain 7-point row of a
+  // cell-wise vector: the roots (they carry their slaves' rows) and the
+  // unknowns next to a slave (its value is its root's)
+  {
+    std::unordered_set<long long> slave(scell.begin(), scell.end());
+    std::vector<int> fix(groot.begin(), groot.end());
+    const long long plane = (long long)nx * ny;
+    for (int sc : scell) {
+      const long long c = sc;
+      const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / plane);
+      const long long nbs[6] = {i > 0 ? c - 1 : -1, i < nx - 1 ? c + 1 : -1, j > 0 ? c - nx : -1,
+                                j < ny - 1 ? c + nx : -1, k > 0 ? c - plane : -1, k < nz - 1 ? c + plane : -1};
+      for (long long nb : nbs)
+        if (nb >= 0 && act[nb] && !slave.count(nb)) fix.push_back((int)nb);
+    }
+    std::sort(fix.begin(), fix.end());
+    fix.erase(std::unique(fix.begin(), fix.end()), fix.end());
+    g.h_fix = fix;
+    g.h_scell = scell;
+    g.h_sroot = sroot;
+    NFA_HIP(upload_vec(g.fix_rows, fix));
+  }
+  ++g.body_version;
   g.n_reduced = nact - g.n_slaves;
   NFA_HIP(upload_vec(g.g_root, groot));
   NFA_HIP(upload_vec(g.g_off, goff));

@@ -30,7 +30,7 @@
 // other couplings are flagged by a negative D^-1 and hold their 20 remaining
 // entries in a side list sorted by cell (found by binary search).
 //
-// V-cycle in FP32, symmetric (damped Jacobi, omega = 0.7, one sweep before
+// V-cycle in FP32, symmetric (damped Jacobi, omega = 0.9, one sweep before
 // and one after the coarse correction; restriction = transpose of the
 // piecewise-constant prolongation), so the solve may use it in (flexible)
 // CG.  On levels >= 1 the pre-smoothed z = omega D^-1 r is never stored:
@@ -55,7 +55,13 @@ namespace {
 
 constexpr int kMaxLevels = 16;
 constexpr long long kMinCoarse = 600;
-constexpr float kOmega = 0.7f;
+constexpr double kDefaultOmega = 0.9;    // damping of the Jacobi sweeps
+constexpr double kDefaultAlpha = 1.0;    // scale of the coarse correction
+
+// Cycle parameters as the kernels take them.
+struct Cyc {
+  float w, a;   // omega, alpha
+};
 
 struct Dims {
   int nx, ny, nz;
@@ -275,25 +281,25 @@ __device__ __forceinline__ float offdiag(const LevelView& L, const float4& s4, i
 }
 
 // Fine-cell term of the restriction: r - A z with z = omega D^-1 r.
-__device__ __forceinline__ float down_value(const LevelView& L, const float* r, int c, int k, int j, int i) {
+__device__ __forceinline__ float down_value(const LevelView& L, Cyc p, const float* r, int c, int k, int j, int i) {
   const float4 s4 = L.S[c];
   const float rc = r[c];
   if (s4.x == 0.0f) return rc;
   const float n = offdiag(L, s4, c, k, j, i, [&](int nb, int, int, int) { return fabsf(L.S[nb].x) * r[nb]; });
-  return (1.0f - kOmega) * rc - kOmega * n;
+  return (1.0f - p.w) * rc - p.w * n;
 }
 
-// Post-smoothed z of a fine cell, z' = omega D^-1 r + z_{l+1}(parent).
-__device__ __forceinline__ float up_value(const LevelView& L, const float* r, const float* zc, int cnx, int cny,
-                                          int c, int k, int j, int i) {
+// Post-smoothed z of a fine cell, z' = omega D^-1 r + alpha z_{l+1}(parent).
+__device__ __forceinline__ float up_value(const LevelView& L, Cyc p, const float* r, const float* zc, int cnx,
+                                          int cny, int c, int k, int j, int i) {
   auto zp = [&](int nb, int kn, int jn, int in) {
-    return kOmega * (fabsf(L.S[nb].x) * r[nb]) + zc[((kn >> 1) * cny + (jn >> 1)) * cnx + (in >> 1)];
+    return p.w * (fabsf(L.S[nb].x) * r[nb]) + p.a * zc[((kn >> 1) * cny + (jn >> 1)) * cnx + (in >> 1)];
   };
   const float4 s4 = L.S[c];
   const float z0 = zp(c, k, j, i);
   if (s4.x == 0.0f) return z0;
   const float n = offdiag(L, s4, c, k, j, i, zp);
-  return (1.0f - kOmega) * z0 + kOmega * (fabsf(s4.x) * (r[c] - n));
+  return (1.0f - p.w) * z0 + p.w * (fabsf(s4.x) * (r[c] - n));
 }
 
 // Launch geometry shared by the grid-wide level kernels: a workgroup of
@@ -330,66 +336,371 @@ __device__ __forceinline__ void restrict_store(const Tile& t, float v, int cnx, 
   }
 }
 
+// The seven cells of a fine cell's 7-point neighbourhood (x-, x+, y-, y+,
+// z-, z+ and the cell), loaded up front: S and r, plus (up) the parents'
+// corrections; zero beyond the domain.
+template <bool UP>
+struct Hood {
+  float4 s[7];
+  float r[7], z[7];
+};
+template <bool UP>
+__device__ __forceinline__ void load_hood(const LevelView& L, const float* __restrict__ r, const float* __restrict__ zc,
+                                          int cnx, int cny, int c, int k, int j, int i, Hood<UP>& h) {
+  const int nx = L.nx, plane = L.nx * L.ny;
+  const bool ok[6] = {i > 0, i + 1 < nx, j > 0, j + 1 < L.ny, k > 0, k + 1 < L.nz};
+  const int off[6] = {-1, 1, -nx, nx, -plane, plane};
+  const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
+#pragma unroll
+  for (int f = 0; f < 7; ++f) {
+    const bool v = f == 6 || ok[f];
+    const int nb = f == 6 ? c : c + off[f];
+    h.s[f] = v ? L.S[nb] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    h.r[f] = v ? r[nb] : 0.0f;
+    if (UP) {
+      const int kn = f == 6 ? k : k + dk[f], jn = f == 6 ? j : j + dj[f], in = f == 6 ? i : i + di[f];
+      h.z[f] = v ? zc[((kn >> 1) * cny + (jn >> 1)) * cnx + (in >> 1)] : 0.0f;
+    }
+  }
+}
+// (N w)_c from a loaded neighbourhood: couplings x-: S[x-].y, x+: S[c].y,
+// y-: S[y-].z, y+: S[c].z, z-: S[z-].w, z+: S[c].w.
+__device__ __forceinline__ float hood_offdiag(const float4* s, const float* w) {
+  float n = s[0].y * w[0];
+  n += s[6].y * w[1];
+  n += s[2].z * w[2];
+  n += s[6].z * w[3];
+  n += s[4].w * w[4];
+  n += s[6].w * w[5];
+  return n;
+}
+
 // level l -> l+1 (l >= 1): r_{l+1} = P^T (r - A omega D^-1 r)
-__global__ __launch_bounds__(256) void k_down(LevelView L, int tiles_x, int cnx, int cny, const float* __restrict__ r,
-                                              float* rc, const SolveScalars* sc) {
+__global__ __launch_bounds__(256) void k_down(LevelView L, Cyc p, int tiles_x, int cnx, int cny,
+                                              const float* __restrict__ r, float* rc, const SolveScalars* sc) {
   if (solve_done(sc)) return;
   const Tile t = tile_of(tiles_x, cny);
   float v = 0.0f;
-  if (t.i < L.nx && t.j < L.ny && t.k < L.nz)
-    v = down_value(L, r, (t.k * L.ny + t.j) * L.nx + t.i, t.k, t.j, t.i);
+  if (t.i < L.nx && t.j < L.ny && t.k < L.nz) {
+    const int c = (t.k * L.ny + t.j) * L.nx + t.i;
+    Hood<false> h;
+    load_hood<false>(L, r, nullptr, cnx, cny, c, t.k, t.j, t.i, h);
+    float w[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) w[f] = fabsf(h.s[f].x) * h.r[f];
+    if (h.s[6].x == 0.0f) {
+      v = h.r[6];
+    } else {
+      float n = hood_offdiag(h.s, w);
+      if (h.s[6].x < 0.0f)
+        n += extras_sum(L, c, t.k, t.j, t.i, [&](int nb, int, int, int) { return fabsf(L.S[nb].x) * r[nb]; });
+      v = (1.0f - p.w) * h.r[6] - p.w * n;
+    }
+  }
   restrict_store(t, v, cnx, cny, rc);
 }
 
-// level l+1 -> l (l >= 1): zt = post-smoothed (omega D^-1 r + P z_{l+1})
-__global__ __launch_bounds__(256) void k_up(LevelView L, int tiles_x, int cnx, int cny, const float* __restrict__ r,
-                                            const float* __restrict__ zc, float* zt, const SolveScalars* sc) {
+// level l+1 -> l (l >= 1): zt = post-smoothed (omega D^-1 r + alpha P z_{l+1})
+__global__ __launch_bounds__(256) void k_up(LevelView L, Cyc p, int tiles_x, int cnx, int cny,
+                                            const float* __restrict__ r, const float* __restrict__ zc, float* zt,
+                                            const SolveScalars* sc) {
   if (solve_done(sc)) return;
   const Tile t = tile_of(tiles_x, cny);
   if (t.i < L.nx && t.j < L.ny && t.k < L.nz) {
     const int c = (t.k * L.ny + t.j) * L.nx + t.i;
-    zt[c] = up_value(L, r, zc, cnx, cny, c, t.k, t.j, t.i);
+    Hood<true> h;
+    load_hood<true>(L, r, zc, cnx, cny, c, t.k, t.j, t.i, h);
+    float w[7];
+#pragma unroll
+    for (int f = 0; f < 7; ++f) w[f] = p.w * (fabsf(h.s[f].x) * h.r[f]) + p.a * h.z[f];
+    float out = w[6];
+    if (h.s[6].x != 0.0f) {
+      float n = hood_offdiag(h.s, w);
+      if (h.s[6].x < 0.0f)
+        n += extras_sum(L, c, t.k, t.j, t.i, [&](int nb, int kn, int jn, int in) {
+          return p.w * (fabsf(L.S[nb].x) * r[nb]) + p.a * zc[((kn >> 1) * cny + (jn >> 1)) * cnx + (in >> 1)];
+        });
+      out = (1.0f - p.w) * w[6] + p.w * (fabsf(h.s[6].x) * (h.r[6] - n));
+    }
+    zt[c] = out;
   }
 }
 
-// level 0 -> 1: r_1 = P^T (r - q) over the reduced unknowns (q = A' z).
-__global__ __launch_bounds__(256) void k_restrict0(int nx, int ny, int nz, int tiles_x, int cnx, int cny,
-                                                   const float* __restrict__ r, const float* __restrict__ q,
-                                                   const unsigned char* __restrict__ reduced, float* rc,
-                                                   const SolveScalars* sc) {
+// ------------------------------------------------------------- level 0
+// Level 0 in two fused sweeps, each marching a 64 x 4 tile of (i, j)
+// columns up a chunk of z-planes (an even number) with the plane's values in
+// LDS (halo included, double-buffered) and the column's z-neighbours in
+// registers:
+//   down  zt = omega D^-1 r formed per cell, q = A zt, and
+//         r_1 = P^T (r - q) over the unknowns (pairs of planes summed in
+//         registers, pairs of columns by a shuffle, pairs of rows in LDS);
+//   up    zp = omega D^-1 r + alpha P z_1 formed per cell, q = A zp, and
+//         z = zp + omega D^-1 (r - q) on the unknowns (0 elsewhere).
+// Both treat every cell on its own: a slave's value is taken as 0 and its
+// row is not moved to its root.  The rows this changes (roots, and unknowns
+// next to a slave) are redone afterwards by the fix-up kernels with the
+// merged operator: slaves take their root's value, roots add their slaves'
+// rows.
+struct L0 {
+  int nx, ny, nz, kchunk, tiles_x, tiles_y;
+  const float *tx, *txb, *ty, *tz, *dinv, *r;
+  const unsigned char* red;
+  Cyc p;
+  int cnx, cny;            // level 1
+  const float* zc;         // level-1 correction (up)
+};
+
+constexpr int L0X = 64, L0Y = 4;
+
+// What a cell's value is formed from: r, D^-1, the unknown flag and (up)
+// the level-1 correction of its parent; loaded unconditionally so that the
+// loads of one plane are independent.
+struct Raw {
+  float r, d, z;
+  int m;
+};
+
+template <bool UP>
+__device__ __forceinline__ Raw l0_raw(const L0& a, long long c, int i, int j, int k) {
+  Raw w;
+  w.r = a.r[c];
+  w.d = a.dinv[c];
+  w.m = a.red[c];
+  w.z = UP ? a.zc[((long long)(k >> 1) * a.cny + (j >> 1)) * a.cnx + (i >> 1)] : 0.0f;
+  return w;
+}
+
+template <bool UP>
+__device__ __forceinline__ float l0_val(const L0& a, const Raw& w) {
+  const float v = a.p.w * (w.d * w.r);
+  return UP && w.m ? v + a.p.a * w.z : v;
+}
+
+template <bool UP>
+__device__ __forceinline__ float l0_value(const L0& a, long long c, int i, int j, int k) {
+  return l0_val<UP>(a, l0_raw<UP>(a, c, i, j, k));
+}
+
+// The five face coefficients of a cell other than its lower z-face.
+struct Faces {
+  float txm, txp, tym, typ, tzp;
+};
+__device__ __forceinline__ Faces l0_faces(const L0& a, long long c, long long yi, int i, int j, int k) {
+  const long long plane = (long long)a.nx * a.ny;
+  Faces f;
+  f.txm = a.tx[c];
+  f.txp = i < a.nx - 1 ? a.tx[c + 1] : a.txb[(long long)k * a.ny + j];
+  f.tym = a.ty[yi];
+  f.typ = a.ty[yi + a.nx];
+  f.tzp = a.tz[c + plane];
+  return f;
+}
+
+template <bool UP>
+__global__ __launch_bounds__(L0X* L0Y) void k_l0(L0 a, float* out, const SolveScalars* sc) {
   if (solve_done(sc)) return;
-  const Tile t = tile_of(tiles_x, cny);
-  float v = 0.0f;
-  if (t.i < nx && t.j < ny && t.k < nz) {
-    const long long c = ((long long)t.k * ny + t.j) * nx + t.i;
-    if (reduced[c]) v = r[c] - q[c];
+  __shared__ float pl[2][L0Y + 2][L0X + 2];
+  __shared__ float rb[2][L0Y][L0X / 2];
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int bx = blk % a.tiles_x, rest = blk / a.tiles_x;
+  const int by = rest % a.tiles_y, bz = rest / a.tiles_y;
+  const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+  const int i = bx * L0X + lx, j = by * L0Y + ly;
+  const int k0 = bz * a.kchunk, k1 = min(a.nz, k0 + a.kchunk);
+  const bool in = i < a.nx && j < a.ny;
+  const long long plane = (long long)a.nx * a.ny;
+  // halo cell of this thread (if any): rows below / above the tile from
+  // waves 0 / 3, the columns left / right from lanes 0-3 / 4-7 of wave 1
+  int hi = 0, hj = 0, hy = 0, hx = 0;
+  bool has_halo = true;
+  if (ly == 0) {
+    hi = i; hj = by * L0Y - 1; hy = 0; hx = lx + 1;
+  } else if (ly == L0Y - 1) {
+    hi = i; hj = by * L0Y + L0Y; hy = L0Y + 1; hx = lx + 1;
+  } else if (ly == 1 && lx < 2 * L0Y) {
+    hi = lx < L0Y ? bx * L0X - 1 : bx * L0X + L0X;
+    hj = by * L0Y + (lx & (L0Y - 1));
+    hy = (lx & (L0Y - 1)) + 1;
+    hx = lx < L0Y ? 0 : L0X + 1;
+  } else {
+    has_halo = false;
   }
-  restrict_store(t, v, cnx, cny, rc);
-}
-
-// level 1 -> 0: z += P z_1 on the reduced unknowns.
-__global__ __launch_bounds__(256) void k_prolong0(int nx, int ny, int nz, int tiles_x, int cnx, int cny,
-                                                  const float* __restrict__ zc, float* z,
-                                                  const unsigned char* __restrict__ reduced, const SolveScalars* sc) {
-  if (solve_done(sc)) return;
-  const Tile t = tile_of(tiles_x, cny);
-  if (t.i < nx && t.j < ny && t.k < nz) {
-    const long long c = ((long long)t.k * ny + t.j) * nx + t.i;
-    if (reduced[c]) z[c] += zc[((long long)t.K * cny + t.J) * cnx + t.I];
+  const bool halo_in = has_halo && hi >= 0 && hi < a.nx && hj >= 0 && hj < a.ny;
+  const long long hc0 = (long long)hj * a.nx + hi;
+  const Raw zero{0.0f, 0.0f, 0.0f, 0};
+  long long c = (long long)k0 * plane + (long long)j * a.nx + i;
+  long long yi = ((long long)k0 * (a.ny + 1) + j) * a.nx + i;
+  const long long yplane = (long long)(a.ny + 1) * a.nx;
+  // software pipeline: the cell's own values at k and k+1, its faces at k,
+  // the halo's values at k
+  float vm = 0.0f, tzm = 0.0f;
+  Raw cur = zero, nxt = zero, hcur = zero;
+  Faces f{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  if (k0 < a.nz) {
+    if (in) {
+      if (k0 > 0) vm = l0_value<UP>(a, c - plane, i, j, k0 - 1);
+      cur = l0_raw<UP>(a, c, i, j, k0);
+      if (k0 + 1 < a.nz) nxt = l0_raw<UP>(a, c + plane, i, j, k0 + 1);
+      tzm = a.tz[c];
+      f = l0_faces(a, c, yi, i, j, k0);
+    }
+    if (halo_in) hcur = l0_raw<UP>(a, (long long)k0 * plane + hc0, hi, hj, k0);
+  }
+  float acc = 0.0f;
+  for (int k = k0; k < k1; ++k, c += plane, yi += yplane) {
+    const int b = (k - k0) & 1;
+    const float vc = in ? l0_val<UP>(a, cur) : 0.0f;
+    pl[b][ly + 1][lx + 1] = vc;
+    if (has_halo) pl[b][hy][hx] = halo_in ? l0_val<UP>(a, hcur) : 0.0f;
+    // prefetch the next plane before waiting
+    Raw nn = zero, hnext = zero;
+    Faces fn = f;
+    if (in && k + 1 < k1) {
+      if (k + 2 < a.nz) nn = l0_raw<UP>(a, c + 2 * plane, i, j, k + 2);
+      fn = l0_faces(a, c + plane, yi + yplane, i, j, k + 1);
+    }
+    if (halo_in && k + 1 < k1) hnext = l0_raw<UP>(a, (long long)(k + 1) * plane + hc0, hi, hj, k + 1);
+    __syncthreads();
+    const float vp = (in && k + 1 < a.nz) ? l0_val<UP>(a, nxt) : 0.0f;
+    float w = 0.0f;
+    if (in) {
+      float q = f.txm * (vc - pl[b][ly + 1][lx]);
+      q = q + f.txp * (vc - pl[b][ly + 1][lx + 2]);
+      q = q + f.tym * (vc - pl[b][ly][lx + 1]);
+      q = q + f.typ * (vc - pl[b][ly + 2][lx + 1]);
+      q = q + tzm * (vc - vm);
+      q = q + f.tzp * (vc - vp);
+      if (UP)
+        out[c] = cur.m ? vc + a.p.w * (cur.d * (cur.r - q)) : 0.0f;
+      else if (cur.m)
+        w = cur.r - q;
+    }
+    if (!UP) {
+      acc += w;
+      if (((k - k0) & 1) == 1 || k == a.nz - 1) {   // a pair of planes (or the last, odd one) done
+        const int pb = ((k - k0) >> 1) & 1;
+        const float v2 = acc + __shfl_xor(acc, 1, 64);
+        if ((lx & 1) == 0) rb[pb][ly][lx >> 1] = v2;
+        acc = 0.0f;
+        __syncthreads();
+        if (lx < 32 && ly < 2) {
+          const int I = bx * (L0X / 2) + lx, J = by * (L0Y / 2) + ly, K = k >> 1;
+          if (I < a.cnx && J < a.cny)
+            out[((long long)K * a.cny + J) * a.cnx + I] = rb[pb][2 * ly][lx] + rb[pb][2 * ly + 1][lx];
+        }
+      }
+    }
+    vm = vc;
+    tzm = f.tzp;
+    cur = nxt;
+    nxt = nn;
+    hcur = hnext;
+    f = fn;
   }
 }
 
-__global__ void k_pre(long long n, const float* __restrict__ r, const float* __restrict__ dinv, float* z,
-                      const SolveScalars* sc) {
-  if (solve_done(sc)) return;
-  MG_STRIDE(i, n) z[i] = kOmega * (dinv[i] * r[i]);
+// Row c of the 7-point operator applied to a cell function f (0 beyond the
+// domain), in the sweep's face order.
+template <class F>
+__device__ __forceinline__ float l0_row(const L0& a, long long c, F f) {
+  const long long plane = (long long)a.nx * a.ny;
+  const int i = (int)(c % a.nx), j = (int)((c / a.nx) % a.ny), k = (int)(c / plane);
+  const long long yi = ((long long)k * (a.ny + 1) + j) * a.nx + i;
+  const float fc = f(c);
+  float q = a.tx[c] * (fc - (i > 0 ? f(c - 1) : 0.0f));
+  q = q + (i < a.nx - 1 ? a.tx[c + 1] : a.txb[(long long)k * a.ny + j]) * (fc - (i < a.nx - 1 ? f(c + 1) : 0.0f));
+  q = q + a.ty[yi] * (fc - (j > 0 ? f(c - a.nx) : 0.0f));
+  q = q + a.ty[yi + a.nx] * (fc - (j < a.ny - 1 ? f(c + a.nx) : 0.0f));
+  q = q + a.tz[c] * (fc - (k > 0 ? f(c - plane) : 0.0f));
+  q = q + a.tz[c + plane] * (fc - (k < a.nz - 1 ? f(c + plane) : 0.0f));
+  return q;
 }
 
-// z += omega D^-1 (r - q) on level 0 (q = A' z).
-__global__ void k_post0(long long n, const float* __restrict__ dinv, const float* __restrict__ r,
-                        const float* __restrict__ q, float* z, const SolveScalars* sc) {
+// Down fix-up, step 1: one thread per entry.  An entry c >= 0 (an unknown
+// next to a slave, or a root) owes q~_c - q_c: only its faces to slaves
+// differ, each by T_f z(root of the slave); an entry -(s+1) (a slave whose
+// root lies in the entry's level-1 cell) owes -q_s, the slave's row with
+// merged values.
+__global__ void k_l0_fix_terms(L0 a, int nent, const int* __restrict__ ent, const int* __restrict__ root,
+                               float* term, const SolveScalars* sc) {
   if (solve_done(sc)) return;
-  MG_STRIDE(i, n) z[i] += kOmega * (dinv[i] * (r[i] - q[i]));
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nent) return;
+  const int code = ent[e];
+  const long long c = code >= 0 ? code : -(long long)code - 1;
+  const long long plane = (long long)a.nx * a.ny;
+  const int i = (int)(c % a.nx), j = (int)((c / a.nx) % a.ny), k = (int)(c / plane);
+  const long long yi = ((long long)k * (a.ny + 1) + j) * a.nx + i;
+  const long long nb[6] = {i > 0 ? c - 1 : -1, i < a.nx - 1 ? c + 1 : -1, j > 0 ? c - a.nx : -1,
+                           j < a.ny - 1 ? c + a.nx : -1, k > 0 ? c - plane : -1, k < a.nz - 1 ? c + plane : -1};
+  const float T[6] = {a.tx[c], i < a.nx - 1 ? a.tx[c + 1] : a.txb[(long long)k * a.ny + j], a.ty[yi], a.ty[yi + a.nx],
+                      a.tz[c], a.tz[c + plane]};
+  int rt[6];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) rt[f] = nb[f] >= 0 ? root[nb[f]] : -1;
+  auto zr = [&](int x) { return x < 0 ? 0.0f : a.p.w * (a.dinv[x] * a.r[x]); };
+  float t = 0.0f;
+  if (code >= 0) {
+#pragma unroll
+    for (int f = 0; f < 6; ++f)
+      if (rt[f] >= 0 && rt[f] != nb[f]) t += T[f] * zr(rt[f]);
+  } else {
+    const float zs = zr(root[c]);
+    float q = 0.0f;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) q = q + T[f] * (zs - zr(rt[f]));
+    t = -q;
+  }
+  term[e] = t;
+}
+
+// Down fix-up, step 2: one thread per level-1 cell adds its terms in order.
+__global__ void k_l0_fix_sum(int nblk, const int* __restrict__ blk, const int* __restrict__ off,
+                             const float* __restrict__ term, float* rc, const SolveScalars* sc) {
+  if (solve_done(sc)) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nblk) return;
+  float d = 0.0f;
+  for (int e = off[t]; e < off[t + 1]; ++e) d += term[e];
+  rc[blk[t]] += d;
+}
+
+// Up fix-up, step 1: each slave's z slot takes its root's zp (the value the
+// merged operator gives it; the up sweep left 0 there).
+__global__ void k_l0_slave_zp(L0 a, int ns, const int* __restrict__ s_cell, const int* __restrict__ s_root, float* z,
+                              const SolveScalars* sc) {
+  if (solve_done(sc)) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ns) return;
+  const long long rt = s_root[t];
+  const long long plane = (long long)a.nx * a.ny;
+  z[s_cell[t]] = l0_value<true>(a, rt, (int)(rt % a.nx), (int)((rt / a.nx) % a.ny), (int)(rt / plane));
+}
+
+// Up fix-up, step 2: one thread per row of the list, redone with the merged
+// operator (a slave's value read from its z slot, a root adding its slaves'
+// rows).
+__global__ void k_l0_up_fix(L0 a, int nrow, const int* __restrict__ rows, const int* __restrict__ root,
+                            const int* __restrict__ group_of, const int* __restrict__ g_off,
+                            const int* __restrict__ g_mem, float* z, const SolveScalars* sc) {
+  if (solve_done(sc)) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrow) return;
+  const long long plane = (long long)a.nx * a.ny;
+  auto zp = [&](long long x) {
+    const int i = (int)(x % a.nx), j = (int)((x / a.nx) % a.ny), k = (int)(x / plane);
+    const Raw w = l0_raw<true>(a, x, i, j, k);
+    const int rt = root[x];
+    const float zs = z[x];
+    return w.m ? l0_val<true>(a, w) : rt >= 0 ? zs : 0.0f;
+  };
+  const long long c = rows[t];
+  const float zc = zp(c);
+  float q = l0_row(a, c, zp);
+  const int gi = group_of[c];
+  if (gi >= 0)
+    for (int m = g_off[gi]; m < g_off[gi + 1]; ++m) q = q + l0_row(a, g_mem[m], zp);
+  z[c] = zc + a.p.w * (a.dinv[c] * (a.r[c] - q));
 }
 
 // The levels from `first` down, in one workgroup: vectors of level l in LDS
@@ -398,6 +709,7 @@ struct TailArgs {
   int first, last;                 // last = the coarsest level
   int off[kMaxLevels];
   LevelView lv[kMaxLevels];
+  Cyc p;
   const float* rin;                // r of level `first`
   float* zout;                     // z of level `first`
   const double* minv;              // coarsest dense inverse (column-major)
@@ -410,33 +722,45 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs A, const SolveScalars* s
   auto cells = [&](int l) { return A.lv[l].nx * A.lv[l].ny * A.lv[l].nz; };
   for (int c = t; c < cells(A.first); c += nt) lds[A.off[A.first] + c] = A.rin[c];
   __syncthreads();
+  // down: a thread per fine cell (its term parked in the level's z slot,
+  // unused until the way up), then a thread per coarse cell sums 8 terms
   for (int l = A.first; l < A.last; ++l) {
     const LevelView& F = A.lv[l];
     const LevelView& C = A.lv[l + 1];
     const float* r = lds + A.off[l];
+    float* v = lds + A.off[l] + cells(l);
     float* rc = lds + A.off[l + 1];
+    for (int c = t; c < cells(l); c += nt) {
+      const int i = c % F.nx, rr = c / F.nx, j = rr % F.ny, k = rr / F.ny;
+      v[c] = down_value(F, A.p, r, c, k, j, i);
+    }
+    __syncthreads();
     for (int B = t; B < cells(l + 1); B += nt) {
       const int I = B % C.nx, rr = B / C.nx, J = rr % C.ny, K = rr / C.ny;
-      float v = 0.0f;
+      float s = 0.0f;
       for (int kk = 0; kk < 2; ++kk)
         for (int jj = 0; jj < 2; ++jj)
           for (int ii = 0; ii < 2; ++ii) {
             const int k = 2 * K + kk, j = 2 * J + jj, i = 2 * I + ii;
-            if (k < F.nz && j < F.ny && i < F.nx) v += down_value(F, r, (k * F.ny + j) * F.nx + i, k, j, i);
+            if (k < F.nz && j < F.ny && i < F.nx) s += v[(k * F.ny + j) * F.nx + i];
           }
-      rc[B] = v;
+      rc[B] = s;
     }
     __syncthreads();
   }
+  // coarsest: z = M r in FP64, G lanes per row (G a power of two dividing 64)
   {
     const int N = cells(A.last);
     const float* r = lds + A.off[A.last];
     float* z = lds + A.off[A.last] + N;
-    for (int i = t; i < N; i += nt) {
-      double s = 0.0;
-      for (int jc = 0; jc < N; ++jc) s += A.minv[(long long)jc * N + i] * (double)r[jc];
-      z[i] = (float)s;
-    }
+    int G = 1;
+    while (G < 64 && 2 * G * N <= nt) G *= 2;
+    const int i = t / G, q = t % G;
+    double s = 0.0;
+    if (i < N)
+      for (int jc = q; jc < N; jc += G) s += A.minv[(long long)jc * N + i] * (double)r[jc];
+    for (int m = 1; m < G; m <<= 1) s += __shfl_xor(s, m, 64);
+    if (i < N && q == 0) z[i] = (float)s;
   }
   __syncthreads();
   for (int l = A.last - 1; l >= A.first; --l) {
@@ -447,7 +771,7 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs A, const SolveScalars* s
     const float* zc = lds + A.off[l + 1] + cells(l + 1);
     for (int c = t; c < cells(l); c += nt) {
       const int i = c % F.nx, rr = c / F.nx, j = rr % F.ny, k = rr / F.ny;
-      z[c] = up_value(F, r, zc, C.nx, C.ny, c, k, j, i);
+      z[c] = up_value(F, A.p, r, zc, C.nx, C.ny, c, k, j, i);
     }
     __syncthreads();
   }
@@ -502,7 +826,7 @@ struct Level {
 
 constexpr int kTailThreads = 1024;
 constexpr int kTailLdsBytes = 64 * 1024;
-constexpr int kDefaultTailCells = 8192;
+constexpr int kDefaultTailCells = 1024;
 
 }  // namespace
 }  // namespace nfa
@@ -513,9 +837,13 @@ struct nfa_mg_s {
   Poisson* op = nullptr;
   int L = 0;                    // levels including level 0
   Level lv[kMaxLevels];         // lv[0]: dims only
-  DevBuf q0, group_of, minv, xcnt;
+  DevBuf group_of, minv, xcnt;
+  DevBuf fblk, foff, fent, fterm;   // level-0 down fix-up: level-1 cells, CSR offsets, entries, terms
+  int nfblk = 0, nfent = 0;
+  int body_version = -1;        // grid body the fix-up lists belong to
   int ncoarse = 0;
   int tail_cells = kDefaultTailCells;
+  double omega = kDefaultOmega, alpha = kDefaultAlpha;
   int first_tail = 1;           // first level run by the one-workgroup tail kernel
   int built_version = -1;       // op->version the coarse operators belong to
 };
@@ -598,6 +926,40 @@ nfa_status mg_setup(nfa_mg_s& mg, hipStream_t st) {
     const nfa_status e = build_side_list(mg, mg.lv[l], st);
     if (e != NFA_OK) return e;
   }
+  if (mg.body_version != g.body_version) {
+    // level-0 down fix-up entries grouped by level-1 cell, in a fixed order:
+    // the listed rows ascending, then the slaves by their root's cell
+    const Dims& C = mg.lv[1].d;
+    auto blk0 = [&](long long c) {
+      const long long i = c % g.nx, j = (c / g.nx) % g.ny, k = c / ((long long)g.nx * g.ny);
+      return (int)(((k >> 1) * C.ny + (j >> 1)) * C.nx + (i >> 1));
+    };
+    std::vector<std::pair<int, int>> ent;
+    for (int c : g.h_fix) ent.push_back({blk0(c), c});
+    for (size_t t = 0; t < g.h_scell.size(); ++t) ent.push_back({blk0(g.h_sroot[t]), -(g.h_scell[t] + 1)});
+    std::stable_sort(ent.begin(), ent.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+    std::vector<int> fb, fo, fe;
+    for (size_t e = 0; e < ent.size(); ++e) {
+      if (e == 0 || ent[e].first != ent[e - 1].first) {
+        fb.push_back(ent[e].first);
+        fo.push_back((int)e);
+      }
+      fe.push_back(ent[e].second);
+    }
+    fo.push_back((int)ent.size());
+    auto up = [&](DevBuf& b, const std::vector<int>& v) -> hipError_t {
+      hipError_t e2 = b.alloc(std::max<size_t>(1, v.size()) * sizeof(int));
+      if (e2 != hipSuccess || v.empty()) return e2;
+      return hipMemcpy(b.p, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice);
+    };
+    NFA_HIP(up(mg.fblk, fb));
+    NFA_HIP(up(mg.foff, fo));
+    NFA_HIP(up(mg.fent, fe));
+    NFA_HIP(mg.fterm.alloc(std::max<size_t>(1, fe.size()) * sizeof(float)));
+    mg.nfblk = (int)fb.size();
+    mg.nfent = (int)fe.size();
+    mg.body_version = g.body_version;
+  }
   // the coarsest level: dense, regularized, inverted on the host
   const Level& Z = mg.lv[mg.L - 1];
   const int N = (int)Z.d.n;
@@ -647,36 +1009,38 @@ nfa_status mg_vcycle(nfa_mg_s& mg, const float* r0, float* z0, const SolveScalar
   Poisson& op = *mg.op;
   Grid& g = *op.g;
   const Coeffs<float> c32 = op.c32();
-  float* q0 = mg.q0.as<float>();
   const unsigned char* red = g.reduced.as<unsigned char>();
   const Dims d0 = mg.lv[0].d;
-  auto apply0 = [&](float* z) {   // q0 = A' z (z's slaves take their root's value)
-    launch_merge_copy<float>(g, z, st, sc);
-    const bool rec = prof_begin(op, st);
-    launch_stencil<float>(g, c32, z, nullptr, q0, nullptr, sc, ST_APPLY, st);
-    prof_end(op, rec, kProfMgApply, st);
-    launch_merge_gather<float>(g, q0, st, sc);
-  };
   // the grid of a fine level l in 64 x 2 x 2 tiles
   auto tiles = [&](int l, int* tx) {
     *tx = (mg.lv[l].d.nx + 63) / 64;
     return (int)((long long)*tx * mg.lv[l + 1].d.ny * mg.lv[l + 1].d.nz);
   };
   int tx;
+  const Cyc p{(float)mg.omega, (float)mg.alpha};
+  const Dims& C1 = mg.lv[1].d;
+  L0 a{d0.nx, d0.ny, d0.nz, 16, (d0.nx + L0X - 1) / L0X, (d0.ny + L0Y - 1) / L0Y, c32.tx, c32.txb, c32.ty, c32.tz,
+       c32.dinv, r0, red, p, C1.nx, C1.ny, nullptr};
+  const int nb0 = a.tiles_x * a.tiles_y * ((d0.nz + a.kchunk - 1) / a.kchunk);
   // level 0, down
-  k_pre<<<blocks_for(d0.n), kBlock, 0, st>>>(d0.n, r0, c32.dinv, z0, sc);
-  apply0(z0);
   {
-    const int nb = tiles(0, &tx);
-    const Dims& C = mg.lv[1].d;
-    k_restrict0<<<nb, 256, 0, st>>>(d0.nx, d0.ny, d0.nz, tx, C.nx, C.ny, r0, q0, red, mg.lv[1].r.as<float>(), sc);
+    const bool rec = prof_begin(op, st);
+    k_l0<false><<<nb0, L0X * L0Y, 0, st>>>(a, mg.lv[1].r.as<float>(), sc);
+    prof_end(op, rec, kProfMgDown, st);
+    if (mg.nfblk > 0) {
+      k_l0_fix_terms<<<(mg.nfent + 255) / 256, 256, 0, st>>>(a, mg.nfent, mg.fent.as<int>(), g.root.as<int>(),
+                                                             mg.fterm.as<float>(), sc);
+      k_l0_fix_sum<<<(mg.nfblk + 255) / 256, 256, 0, st>>>(mg.nfblk, mg.fblk.as<int>(), mg.foff.as<int>(),
+                                                           mg.fterm.as<float>(), mg.lv[1].r.as<float>(), sc);
+    }
   }
   // grid-wide levels, down
   const int T = mg.first_tail;
   for (int l = 1; l < T; ++l) {
     const int nb = tiles(l, &tx);
     const Dims& C = mg.lv[l + 1].d;
-    k_down<<<nb, 256, 0, st>>>(mg.lv[l].view(), tx, C.nx, C.ny, mg.lv[l].r.as<float>(), mg.lv[l + 1].r.as<float>(), sc);
+    k_down<<<nb, 256, 0, st>>>(mg.lv[l].view(), p, tx, C.nx, C.ny, mg.lv[l].r.as<float>(),
+                               mg.lv[l + 1].r.as<float>(), sc);
   }
   // the tail: levels T.. in one workgroup
   {
@@ -689,6 +1053,7 @@ nfa_status mg_vcycle(nfa_mg_s& mg, const float* r0, float* z0, const SolveScalar
       A.lv[l] = mg.lv[l].view();
       off += 2 * (int)mg.lv[l].d.n;
     }
+    A.p = p;
     A.rin = mg.lv[T].r.as<float>();
     A.zout = mg.lv[T].zt.as<float>();
     A.minv = mg.minv.as<double>();
@@ -698,17 +1063,24 @@ nfa_status mg_vcycle(nfa_mg_s& mg, const float* r0, float* z0, const SolveScalar
   for (int l = T - 1; l >= 1; --l) {
     const int nb = tiles(l, &tx);
     const Dims& C = mg.lv[l + 1].d;
-    k_up<<<nb, 256, 0, st>>>(mg.lv[l].view(), tx, C.nx, C.ny, mg.lv[l].r.as<float>(), mg.lv[l + 1].zt.as<float>(),
-                             mg.lv[l].zt.as<float>(), sc);
+    k_up<<<nb, 256, 0, st>>>(mg.lv[l].view(), p, tx, C.nx, C.ny, mg.lv[l].r.as<float>(),
+                             mg.lv[l + 1].zt.as<float>(), mg.lv[l].zt.as<float>(), sc);
   }
   // level 0, up
   {
-    const int nb = tiles(0, &tx);
-    const Dims& C = mg.lv[1].d;
-    k_prolong0<<<nb, 256, 0, st>>>(d0.nx, d0.ny, d0.nz, tx, C.nx, C.ny, mg.lv[1].zt.as<float>(), z0, red, sc);
+    a.zc = mg.lv[1].zt.as<float>();
+    const bool rec = prof_begin(op, st);
+    k_l0<true><<<nb0, L0X * L0Y, 0, st>>>(a, z0, sc);
+    prof_end(op, rec, kProfMgUp, st);
+    const int nfix = (int)g.h_fix.size();
+    if (g.n_slaves > 0)
+      k_l0_slave_zp<<<(g.n_slaves + 255) / 256, 256, 0, st>>>(a, g.n_slaves, g.s_cell.as<int>(), g.s_root.as<int>(),
+                                                              z0, sc);
+    if (nfix > 0)
+      k_l0_up_fix<<<(nfix + 255) / 256, 256, 0, st>>>(a, nfix, g.fix_rows.as<int>(), g.root.as<int>(),
+                                                      mg.group_of.as<int>(), g.g_off.as<int>(), g.g_mem.as<int>(),
+                                                      z0, sc);
   }
-  apply0(z0);
-  k_post0<<<blocks_for(d0.n), kBlock, 0, st>>>(d0.n, c32.dinv, r0, q0, z0, sc);
   NFA_CHECK_LAUNCH();
   return NFA_OK;
 }
@@ -754,7 +1126,7 @@ extern "C" nfa_status nfa_mg_create(nfa_poisson op, nfa_mg* out) {
     return fail(NFA_ERR_INVALID, "nfa_mg_create: the grid has a single cell");
   }
   hipError_t e;
-  if ((e = mg->q0.alloc(g.n * 4)) != hipSuccess || (e = mg->group_of.alloc(g.n * 4)) != hipSuccess ||
+  if ((e = mg->group_of.alloc(g.n * 4)) != hipSuccess ||
       (e = mg->xcnt.alloc(2 * ((mg->lv[1].d.n + kBlock - 1) / kBlock) * sizeof(int))) != hipSuccess)
     return bad(e);
   for (int l = 1; l < mg->L; ++l) {
@@ -802,6 +1174,15 @@ extern "C" nfa_status nfa_mg_set_tail(nfa_mg mg, int max_cells) {
   if (!mg) return fail(NFA_ERR_INVALID, "nfa_mg_set_tail: NULL handle");
   mg->tail_cells = max_cells < 0 ? kDefaultTailCells : max_cells;
   plan_tail(*mg);
+  return NFA_OK;
+}
+
+extern "C" nfa_status nfa_mg_set_params(nfa_mg mg, double omega, double alpha) {
+  if (!mg) return fail(NFA_ERR_INVALID, "nfa_mg_set_params: NULL handle");
+  if (!(omega > 0.0 && omega < 1.0) || !(alpha > 0.0 && alpha < 2.0))
+    return fail(NFA_ERR_INVALID, "nfa_mg_set_params: need 0 < omega < 1 and 0 < alpha < 2");
+  mg->omega = omega;
+  mg->alpha = alpha;
   return NFA_OK;
 }
 

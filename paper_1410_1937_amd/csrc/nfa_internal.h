@@ -85,6 +85,11 @@ struct Grid {
   long long n_active = 0, n_reduced = 0;
   DevBuf g_root, g_off, g_mem;        // int32
   DevBuf s_cell, s_root;              // int32: slave list and its root
+  // rows whose merged row differs from the cell-wise 7-point row (roots and
+  // unknowns next to a slave), ascending; host copies of the slave list
+  DevBuf fix_rows;                    // int32
+  std::vector<int> h_fix, h_scell, h_sroot;
+  int body_version = 0;               // incremented by every body set-up
   bool all_neumann() const { return !(bc[0] | bc[1] | bc[2] | bc[3] | bc[4] | bc[5]); }
   long long nfx() const { return (long long)nz * ny * (nx + 1); }
   long long nfy() const { return (long long)nz * (ny + 1) * nx; }
@@ -125,16 +130,16 @@ struct Poisson {
   SolveScalars* h_scal = nullptr;               // pinned host mirror (2 slots)
   hipEvent_t ev[2] = {nullptr, nullptr};
   // optional timing of selected launches inside solves (HIP events), by
-  // kind: 0 / 1 sweep A in FP64 / FP32, 2 the multigrid cycle's level-0
-  // operator apply (FP32)
+  // kind: 0 / 1 sweep A in FP64 / FP32, 2 / 3 the multigrid cycle's fused
+  // level-0 down / up sweep (FP32)
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;              // 2 per recorded launch
   std::vector<int> prof_kind;                   // kind per recorded launch
   std::vector<int> prof_seq;                    // iteration (since the last harvest) per recorded launch
   int prof_used = 0;
   int prof_iter = 0;                            // iterations enqueued since the last harvest
-  long long prof_launches[3] = {0, 0, 0};
-  double prof_ms[3] = {0.0, 0.0, 0.0};
+  long long prof_launches[4] = {0, 0, 0, 0};
+  double prof_ms[4] = {0.0, 0.0, 0.0, 0.0};
   Coeffs<double> c64() const {
     return {tx64.as<double>(), txb64.as<double>(), ty64.as<double>(), tz64.as<double>(), dinv64.as<double>()};
   }
@@ -143,7 +148,7 @@ struct Poisson {
   }
 };
 
-constexpr int kProfMgApply = 2;
+constexpr int kProfMgDown = 2, kProfMgUp = 3, kProfKinds = 4;
 
 // Open / close the timing of one launch on st when profiling is on.
 inline bool prof_begin(Poisson& op, hipStream_t st) {

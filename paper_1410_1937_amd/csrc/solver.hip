@@ -376,7 +376,7 @@ extern "C" nfa_status nfa_poisson_profile(nfa_poisson op, int enable) {
   op->prof_on = enable != 0;
   op->prof_used = 0;
   op->prof_iter = 0;
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < kProfKinds; ++k) {
     op->prof_launches[k] = 0;
     op->prof_ms[k] = 0.0;
   }
@@ -384,7 +384,7 @@ extern "C" nfa_status nfa_poisson_profile(nfa_poisson op, int enable) {
 }
 
 extern "C" nfa_status nfa_poisson_profile_read(nfa_poisson op, int dtype, nfa_kernel_stats* out) {
-  if (!op || !out || (dtype != NFA_F64 && dtype != NFA_F32 && dtype != NFA_PROF_MG_APPLY))
+  if (!op || !out || dtype < 0 || dtype >= kProfKinds)
     return fail(NFA_ERR_INVALID, "nfa_poisson_profile_read: bad argument");
   out->launches = op->prof_launches[dtype];
   out->ms = op->prof_ms[dtype];

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libnfa.so")
 NFA_OK = 0
 NFA_NOT_CONVERGED = 1
 NFA_F64, NFA_F32 = 0, 1
-NFA_PROF_MG_APPLY = 2
+NFA_PROF_MG_DOWN, NFA_PROF_MG_UP = 2, 3
 NFA_PC_JACOBI, NFA_PC_UNET, NFA_PC_TEST_SABOTAGE, NFA_PC_JACOBI_FCG, NFA_PC_MG = 1, 2, 3, 4, 5
 NFA_PREC_F64, NFA_PREC_MIXED = 0, 1
 
@@ -133,6 +133,7 @@ _sig("nfa_mg_setup", c_int, [c_void_p, c_void_p])
 _sig("nfa_mg_apply", c_int, [c_void_p, c_void_p, c_void_p, c_void_p])
 _sig("nfa_mg_info", c_int, [c_void_p, ctypes.POINTER(c_int), c_void_p])
 _sig("nfa_mg_set_tail", c_int, [c_void_p, c_int])
+_sig("nfa_mg_set_params", c_int, [c_void_p, c_double, c_double])
 _sig("nfa_mg_side_rows", c_int, [c_void_p, c_int, ctypes.POINTER(c_int)])
 _sig("nfa_mg_export", c_int, [c_void_p, c_int, c_void_p, c_void_p])
 _sig("nfa_stretch_axis", c_int, [c_double, c_double, c_int, c_int, c_void_p, c_void_p, c_double, c_int, c_void_p,
@@ -293,6 +294,10 @@ class Multigrid:
         dims = (c_int * 48)()
         _check(lib.nfa_mg_info(self.h, ctypes.byref(L), dims), "nfa_mg_info")
         return [tuple(dims[3 * l:3 * l + 3]) for l in range(L.value)]
+
+    def set_params(self, omega=0.9, alpha=1.0):
+        """Jacobi damping and coarse-correction scale of the V-cycle."""
+        _check(lib.nfa_mg_set_params(self.h, float(omega), float(alpha)), "nfa_mg_set_params")
 
     def side_rows(self, level):
         """Rows of a level held in the side list (couplings beyond 7 points)."""
@@ -539,7 +544,7 @@ class Poisson:
 
     def profile_read(self, dtype):
         ks = KernelStats()
-        code = {"f64": NFA_F64, "f32": NFA_F32, "mg_apply": NFA_PROF_MG_APPLY}[dtype]
+        code = {"f64": NFA_F64, "f32": NFA_F32, "mg_down": NFA_PROF_MG_DOWN, "mg_up": NFA_PROF_MG_UP}[dtype]
         _check(lib.nfa_poisson_profile_read(self.h, code, ctypes.byref(ks)), "nfa_poisson_profile_read")
         return {"launches": ks.launches, "ms": ks.ms, "cells": ks.cells}
 

@@ -86,6 +86,28 @@ def test_one_vcycle_matches_the_oracle(body, bc, shape, tail):
     assert rel_l2(z[red | (ob.root.reshape(og.shape) >= 0)], ref[red | (ob.root.reshape(og.shape) >= 0)]) <= 1e-4
 
 
+@pytest.mark.parametrize("tail", [-1, 0])
+def test_vcycle_with_other_damping_and_coarse_scale(tail):
+    wl = fx.small(8, 64, 48, 40, body="sphere")
+    og, ob, oop, b = oracle_for(wl)
+    H = multigrid.Hierarchy(oop, omega=0.85, alpha=1.6)
+    g, op = gpu_for(wl)
+    mg = op.multigrid()
+    mg.set_tail(tail)
+    mg.set_params(0.85, 1.6)
+    mg.setup()
+    red = oop.reduced_mask() > 0
+    r = np.where(red, np.random.default_rng(1).standard_normal(og.shape), 0.0).astype(np.float32)
+    z = host(mg.apply(torch.as_tensor(r, device="cuda")))
+    ref = oop.expand(H.precond(r.astype(np.float64)))
+    keep = red | (ob.root.reshape(og.shape) >= 0)
+    assert rel_l2(z[keep], ref[keep]) <= 1e-4
+    with pytest.raises(Exception):
+        mg.set_params(1.0, 1.0)
+    with pytest.raises(Exception):
+        mg.set_params(0.7, 2.0)
+
+
 @pytest.mark.parametrize("name,tail", [("c1", -1), ("sphere", -1), ("sphere", 0)])
 def test_mg_solve_meets_tolerance_and_the_oracle(name, tail):
     wl = fx.c1() if name == "c1" else fx.small(7, 37, 21, 17, body="sphere")

@@ -46,11 +46,12 @@ def test_constants_stay_in_the_null_space_of_every_level():
         assert np.max(rows) <= 1e-12 * np.max(np.abs(A.diagonal())), l
 
 
+@pytest.mark.parametrize("alpha", [1.0, 0.5, 1.9])
 @pytest.mark.parametrize("bc", [(0,) * 6, (0, 0, 0, 0, 0, 1)])
-def test_vcycle_is_symmetric_positive_definite(bc):
+def test_vcycle_is_symmetric_positive_definite(bc, alpha):
     wl = fx.small(2, 12, 10, 8, body="sphere", bc=bc)
     og, ob, op, b = oracle_for(wl)
-    H = multigrid.Hierarchy(op, min_coarse=20)
+    H = multigrid.Hierarchy(op, min_coarse=20, alpha=alpha)
     red = np.nonzero(op.reduced_mask().reshape(-1))[0]
     n = op.grid.n
     M = np.zeros((len(red), len(red)))
@@ -82,3 +83,30 @@ def test_multigrid_cg_converges_fast_to_the_dense_solution():
     assert res.relres <= 1e-10
     assert res.iterations * 5 <= jac.iterations, (res.iterations, jac.iterations)
     assert np.linalg.norm(res.x - jac.x) <= 1e-8 * np.linalg.norm(jac.x)
+
+
+@pytest.mark.parametrize("alpha", [0.6, 1.0, 1.7])
+def test_two_level_cycle_follows_its_error_propagation(alpha):
+    """With an exact coarse solve, e -> S (I - alpha P A_c^-1 P^T A) S e for
+    the error e = x - V(A x), S = I - omega D^-1 A: the pre-smoothing, the
+    scaled coarse correction and the post-smoothing in that order, built
+    here from dense matrices."""
+    wl = fx.small(3, 10, 8, 8, body="sphere", bc=(0, 0, 0, 0, 0, 1))
+    og, ob, op, b = oracle_for(wl)
+    omega = 0.8
+    H = multigrid.Hierarchy(op, min_coarse=10 ** 6, omega=omega, alpha=alpha)
+    assert len(H.A) == 2
+    red = np.nonzero(op.reduced_mask().reshape(-1))[0]
+    A = H.A[0][red][:, red].toarray()
+    P = H.maps[0][red].toarray()
+    ne = np.nonzero(P.sum(axis=0) > 0)[0]
+    P = P[:, ne]
+    Ac = H.A[1][ne][:, ne].toarray()
+    I = np.eye(len(red))
+    S = I - omega * (A / np.diag(A)[:, None])
+    E = S @ (I - alpha * P @ np.linalg.solve(Ac, P.T @ A)) @ S
+    x = np.random.default_rng(0).standard_normal(len(red))
+    r = np.zeros(op.grid.n)
+    r[red] = A @ x
+    got = H.vcycle(r)[red]
+    assert np.linalg.norm(got - (x - E @ x)) <= 1e-10 * np.linalg.norm(x)
