@@ -351,15 +351,21 @@ __device__ __forceinline__ void load_hood(const LevelView& L, const float* __res
   const bool ok[6] = {i > 0, i + 1 < nx, j > 0, j + 1 < L.ny, k > 0, k + 1 < L.nz};
   const int off[6] = {-1, 1, -nx, nx, -plane, plane};
   const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
+  // every load unconditional, so that all of them are in flight at once: a
+  // neighbour beyond the domain reads the cell itself and is multiplied by 0
+  // (a product the compiler may not fold, unlike a select, which it would
+  // turn back into a branch around the load)
 #pragma unroll
   for (int f = 0; f < 7; ++f) {
     const bool v = f == 6 || ok[f];
-    const int nb = f == 6 ? c : c + off[f];
-    h.s[f] = v ? L.S[nb] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    h.r[f] = v ? r[nb] : 0.0f;
+    const float m = v ? 1.0f : 0.0f;
+    const int nb = v && f < 6 ? c + off[f] : c;
+    const float4 sv = L.S[nb];
+    h.s[f] = make_float4(sv.x * m, sv.y * m, sv.z * m, sv.w * m);
+    h.r[f] = r[nb] * m;
     if (UP) {
-      const int kn = f == 6 ? k : k + dk[f], jn = f == 6 ? j : j + dj[f], in = f == 6 ? i : i + di[f];
-      h.z[f] = v ? zc[((kn >> 1) * cny + (jn >> 1)) * cnx + (in >> 1)] : 0.0f;
+      const int kn = v && f < 6 ? k + dk[f] : k, jn = v && f < 6 ? j + dj[f] : j, in = v && f < 6 ? i + di[f] : i;
+      h.z[f] = zc[((kn >> 1) * cny + (jn >> 1)) * cnx + (in >> 1)] * m;
     }
   }
 }
@@ -388,14 +394,13 @@ __global__ __launch_bounds__(256) void k_down(LevelView L, Cyc p, int tiles_x, i
     float w[6];
 #pragma unroll
     for (int f = 0; f < 6; ++f) w[f] = fabsf(h.s[f].x) * h.r[f];
-    if (h.s[6].x == 0.0f) {
-      v = h.r[6];
-    } else {
-      float n = hood_offdiag(h.s, w);
-      if (h.s[6].x < 0.0f)
-        n += extras_sum(L, c, t.k, t.j, t.i, [&](int nb, int, int, int) { return fabsf(L.S[nb].x) * r[nb]; });
-      v = (1.0f - p.w) * h.r[6] - p.w * n;
-    }
+    // computed for every row and selected (a branch would let the compiler
+    // sink the neighbour loads behind the load of the row's own entry)
+    float n = hood_offdiag(h.s, w);
+    if (h.s[6].x < 0.0f)
+      n += extras_sum(L, c, t.k, t.j, t.i, [&](int nb, int, int, int) { return fabsf(L.S[nb].x) * r[nb]; });
+    const float full = (1.0f - p.w) * h.r[6] - p.w * n;
+    v = h.s[6].x == 0.0f ? h.r[6] : full;
   }
   restrict_store(t, v, cnx, cny, rc);
 }
@@ -413,16 +418,13 @@ __global__ __launch_bounds__(256) void k_up(LevelView L, Cyc p, int tiles_x, int
     float w[7];
 #pragma unroll
     for (int f = 0; f < 7; ++f) w[f] = p.w * (fabsf(h.s[f].x) * h.r[f]) + p.a * h.z[f];
-    float out = w[6];
-    if (h.s[6].x != 0.0f) {
-      float n = hood_offdiag(h.s, w);
-      if (h.s[6].x < 0.0f)
-        n += extras_sum(L, c, t.k, t.j, t.i, [&](int nb, int kn, int jn, int in) {
-          return p.w * (fabsf(L.S[nb].x) * r[nb]) + p.a * zc[((kn >> 1) * cny + (jn >> 1)) * cnx + (in >> 1)];
-        });
-      out = (1.0f - p.w) * w[6] + p.w * (fabsf(h.s[6].x) * (h.r[6] - n));
-    }
-    zt[c] = out;
+    float n = hood_offdiag(h.s, w);
+    if (h.s[6].x < 0.0f)
+      n += extras_sum(L, c, t.k, t.j, t.i, [&](int nb, int kn, int jn, int in) {
+        return p.w * (fabsf(L.S[nb].x) * r[nb]) + p.a * zc[((kn >> 1) * cny + (jn >> 1)) * cnx + (in >> 1)];
+      });
+    const float full = (1.0f - p.w) * w[6] + p.w * (fabsf(h.s[6].x) * (h.r[6] - n));
+    zt[c] = h.s[6].x == 0.0f ? w[6] : full;
   }
 }
 
@@ -599,6 +601,202 @@ __global__ __launch_bounds__(L0X* L0Y) void k_l0(L0 a, float* out, const SolveSc
   }
 }
 
+// The same two sweeps with 4 consecutive cells per lane (nx a multiple of
+// 4, arrays 16-byte aligned): a workgroup marches a 256 x 4 tile, every
+// per-cell array is read with one 16-byte load per lane, so that a plane
+// costs about 3 vector memory instructions per cell instead of 12.
+struct Raw4 {
+  float4 r, d, z;   // z: parents' corrections of cells 0-1 and 2-3 in z.x, z.y
+  uchar4 m;
+};
+
+template <bool UP>
+__device__ __forceinline__ Raw4 l0_raw4(const L0& a, long long c, int i0, int j, int k) {
+  Raw4 w;
+  w.r = *reinterpret_cast<const float4*>(a.r + c);
+  w.d = *reinterpret_cast<const float4*>(a.dinv + c);
+  w.m = *reinterpret_cast<const uchar4*>(a.red + c);
+  if (UP) {
+    const float2 zz =
+        *reinterpret_cast<const float2*>(a.zc + ((long long)(k >> 1) * a.cny + (j >> 1)) * a.cnx + (i0 >> 1));
+    w.z = make_float4(zz.x, zz.y, 0.0f, 0.0f);
+  } else {
+    w.z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
+  return w;
+}
+
+template <bool UP>
+__device__ __forceinline__ float4 l0_val4(const L0& a, const Raw4& w) {
+  float4 v = make_float4(a.p.w * (w.d.x * w.r.x), a.p.w * (w.d.y * w.r.y), a.p.w * (w.d.z * w.r.z),
+                         a.p.w * (w.d.w * w.r.w));
+  if (UP) {
+    v.x = w.m.x ? v.x + a.p.a * w.z.x : v.x;
+    v.y = w.m.y ? v.y + a.p.a * w.z.x : v.y;
+    v.z = w.m.z ? v.z + a.p.a * w.z.y : v.z;
+    v.w = w.m.w ? v.w + a.p.a * w.z.y : v.w;
+  }
+  return v;
+}
+
+struct Faces4 {
+  float4 txm, tym, typ, tzp;
+  float tx4;   // the +x face of the last cell
+};
+__device__ __forceinline__ Faces4 l0_faces4(const L0& a, long long c, long long yi, int i0, int j, int k) {
+  const long long plane = (long long)a.nx * a.ny;
+  Faces4 f;
+  f.txm = *reinterpret_cast<const float4*>(a.tx + c);
+  const bool last = i0 + 4 >= a.nx;
+  const float t4 = a.tx[last ? c : c + 4];
+  const float tb = a.txb[(long long)k * a.ny + j];
+  const float ml = last ? 1.0f : 0.0f;
+  f.tx4 = t4 * (1.0f - ml) + tb * ml;
+  f.tym = *reinterpret_cast<const float4*>(a.ty + yi);
+  f.typ = *reinterpret_cast<const float4*>(a.ty + yi + a.nx);
+  f.tzp = *reinterpret_cast<const float4*>(a.tz + c + plane);
+  return f;
+}
+
+__device__ __forceinline__ float4 f4(float v) { return make_float4(v, v, v, v); }
+__device__ __forceinline__ float comp(const float4& v, int e) { return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w; }
+
+template <bool UP>
+__global__ __launch_bounds__(256) void k_l0_x4(L0 a, float* out, const SolveScalars* sc) {
+  if (solve_done(sc)) return;
+  constexpr int W = 4 * L0X;   // cells of a tile row
+  __shared__ float pl[2][L0Y + 2][W + 2];
+  __shared__ float rb[2][L0Y][W / 2];
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int bx = blk % a.tiles_x, rest = blk / a.tiles_x;
+  const int by = rest % a.tiles_y, bz = rest / a.tiles_y;
+  const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+  const int i0 = bx * W + 4 * lx, j = by * L0Y + ly;
+  const int k0 = bz * a.kchunk, k1 = min(a.nz, k0 + a.kchunk);
+  const bool in = i0 < a.nx && j < a.ny;
+  const long long plane = (long long)a.nx * a.ny;
+  // halo: rows below / above from waves 0 / 3 (4 cells per lane), the
+  // columns left / right from lanes 0-3 / 4-7 of wave 1 (one cell each)
+  int hj = 0, hi = 0, hy = 0, hx = 0, hkind = 0;   // 1: 4-cell row segment, 2: single cell
+  if (ly == 0 || ly == L0Y - 1) {
+    hkind = 1;
+    hi = i0;
+    hj = ly == 0 ? by * L0Y - 1 : by * L0Y + L0Y;
+    hy = ly == 0 ? 0 : L0Y + 1;
+    hx = 4 * lx + 1;
+  } else if (ly == 1 && lx < 2 * L0Y) {
+    hkind = 2;
+    hi = lx < L0Y ? bx * W - 1 : bx * W + W;
+    hj = by * L0Y + (lx & (L0Y - 1));
+    hy = (lx & (L0Y - 1)) + 1;
+    hx = lx < L0Y ? 0 : W + 1;
+  }
+  const bool halo_in = hkind != 0 && hi >= 0 && hi < a.nx && hj >= 0 && hj < a.ny;
+  const long long hc0 = (long long)hj * a.nx + hi;
+  Raw4 zero4;
+  zero4.r = zero4.d = zero4.z = f4(0.0f);
+  zero4.m = make_uchar4(0, 0, 0, 0);
+  const Raw zero1{0.0f, 0.0f, 0.0f, 0};
+  long long c = (long long)k0 * plane + (long long)j * a.nx + i0;
+  long long yi = ((long long)k0 * (a.ny + 1) + j) * a.nx + i0;
+  const long long yplane = (long long)(a.ny + 1) * a.nx;
+  float4 vm = f4(0.0f), tzm = f4(0.0f);
+  Raw4 cur = zero4, nxt = zero4, hc4 = zero4;
+  Raw hc1 = zero1;
+  Faces4 f{f4(0.0f), f4(0.0f), f4(0.0f), f4(0.0f), 0.0f};
+  if (k0 < a.nz) {
+    if (in) {
+      if (k0 > 0) vm = l0_val4<UP>(a, l0_raw4<UP>(a, c - plane, i0, j, k0 - 1));
+      cur = l0_raw4<UP>(a, c, i0, j, k0);
+      if (k0 + 1 < a.nz) nxt = l0_raw4<UP>(a, c + plane, i0, j, k0 + 1);
+      tzm = *reinterpret_cast<const float4*>(a.tz + c);
+      f = l0_faces4(a, c, yi, i0, j, k0);
+    }
+    if (halo_in) {
+      if (hkind == 1) hc4 = l0_raw4<UP>(a, (long long)k0 * plane + hc0, hi, hj, k0);
+      else hc1 = l0_raw<UP>(a, (long long)k0 * plane + hc0, hi, hj, k0);
+    }
+  }
+  float acc0 = 0.0f, acc1 = 0.0f;
+  for (int k = k0; k < k1; ++k, c += plane, yi += yplane) {
+    const int b = (k - k0) & 1;
+    const float4 vc = in ? l0_val4<UP>(a, cur) : f4(0.0f);
+    float* row = &pl[b][ly + 1][4 * lx + 1];
+    row[0] = vc.x; row[1] = vc.y; row[2] = vc.z; row[3] = vc.w;
+    if (hkind == 1) {
+      const float4 hv = halo_in ? l0_val4<UP>(a, hc4) : f4(0.0f);
+      float* hr = &pl[b][hy][hx];
+      hr[0] = hv.x; hr[1] = hv.y; hr[2] = hv.z; hr[3] = hv.w;
+    } else if (hkind == 2) {
+      pl[b][hy][hx] = halo_in ? l0_val<UP>(a, hc1) : 0.0f;
+    }
+    // prefetch the next plane before waiting
+    Raw4 nn = zero4, hn4 = zero4;
+    Raw hn1 = zero1;
+    Faces4 fn = f;
+    if (in && k + 1 < k1) {
+      if (k + 2 < a.nz) nn = l0_raw4<UP>(a, c + 2 * plane, i0, j, k + 2);
+      fn = l0_faces4(a, c + plane, yi + yplane, i0, j, k + 1);
+    }
+    if (halo_in && k + 1 < k1) {
+      if (hkind == 1) hn4 = l0_raw4<UP>(a, (long long)(k + 1) * plane + hc0, hi, hj, k + 1);
+      else hn1 = l0_raw<UP>(a, (long long)(k + 1) * plane + hc0, hi, hj, k + 1);
+    }
+    __syncthreads();
+    const float4 vp = (in && k + 1 < a.nz) ? l0_val4<UP>(a, nxt) : f4(0.0f);
+    float w[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (in) {
+      const float xl = pl[b][ly + 1][4 * lx], xr = pl[b][ly + 1][4 * lx + 5];
+      float o[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float ve = comp(vc, e);
+        const float vxm = e == 0 ? xl : comp(vc, e - 1);
+        const float vxp = e == 3 ? xr : comp(vc, e + 1);
+        const float txp = e == 3 ? f.tx4 : comp(f.txm, e + 1);
+        float q = comp(f.txm, e) * (ve - vxm);
+        q = q + txp * (ve - vxp);
+        q = q + comp(f.tym, e) * (ve - pl[b][ly][4 * lx + 1 + e]);
+        q = q + comp(f.typ, e) * (ve - pl[b][ly + 2][4 * lx + 1 + e]);
+        q = q + comp(tzm, e) * (ve - comp(vm, e));
+        q = q + comp(f.tzp, e) * (ve - comp(vp, e));
+        const int me = e == 0 ? cur.m.x : e == 1 ? cur.m.y : e == 2 ? cur.m.z : cur.m.w;
+        if (UP)
+          o[e] = me ? ve + a.p.w * (comp(cur.d, e) * (comp(cur.r, e) - q)) : 0.0f;
+        else
+          w[e] = me ? comp(cur.r, e) - q : 0.0f;
+      }
+      if (UP) *reinterpret_cast<float4*>(out + c) = make_float4(o[0], o[1], o[2], o[3]);
+    }
+    if (!UP) {
+      acc0 += w[0] + w[1];
+      acc1 += w[2] + w[3];
+      if (((k - k0) & 1) == 1 || k == a.nz - 1) {   // a pair of planes (or the last, odd one) done
+        const int pb = ((k - k0) >> 1) & 1;
+        rb[pb][ly][2 * lx] = acc0;
+        rb[pb][ly][2 * lx + 1] = acc1;
+        acc0 = acc1 = 0.0f;
+        __syncthreads();
+        if (ly < 2) {
+          const int I = bx * (W / 2) + 2 * lx, J = by * (L0Y / 2) + ly, K = k >> 1;
+          if (I < a.cnx && J < a.cny) {
+            const long long o = ((long long)K * a.cny + J) * a.cnx + I;
+            out[o] = rb[pb][2 * ly][2 * lx] + rb[pb][2 * ly + 1][2 * lx];
+            if (I + 1 < a.cnx) out[o + 1] = rb[pb][2 * ly][2 * lx + 1] + rb[pb][2 * ly + 1][2 * lx + 1];
+          }
+        }
+      }
+    }
+    vm = vc;
+    tzm = f.tzp;
+    cur = nxt;
+    nxt = nn;
+    hc4 = hn4;
+    hc1 = hn1;
+    f = fn;
+  }
+}
+
 // Row c of the 7-point operator applied to a cell function f (0 beyond the
 // domain), in the sweep's face order.
 template <class F>
@@ -606,13 +804,21 @@ __device__ __forceinline__ float l0_row(const L0& a, long long c, F f) {
   const long long plane = (long long)a.nx * a.ny;
   const int i = (int)(c % a.nx), j = (int)((c / a.nx) % a.ny), k = (int)(c / plane);
   const long long yi = ((long long)k * (a.ny + 1) + j) * a.nx + i;
+  const bool ok[6] = {i > 0, i < a.nx - 1, j > 0, j < a.ny - 1, k > 0, k < a.nz - 1};
+  const long long off[6] = {-1, 1, -a.nx, a.nx, -plane, plane};
+  // unconditional loads: a neighbour beyond the domain reads the cell itself
+  // and is multiplied by 0
+  float fv[6];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) fv[d] = f(ok[d] ? c + off[d] : c) * (ok[d] ? 1.0f : 0.0f);
+  const float m1 = ok[1] ? 1.0f : 0.0f;
+  const float tb = a.txb[(long long)k * a.ny + j];
+  const float txp = a.tx[ok[1] ? c + 1 : c];
+  const float T[6] = {a.tx[c], txp * m1 + tb * (1.0f - m1), a.ty[yi], a.ty[yi + a.nx], a.tz[c], a.tz[c + plane]};
   const float fc = f(c);
-  float q = a.tx[c] * (fc - (i > 0 ? f(c - 1) : 0.0f));
-  q = q + (i < a.nx - 1 ? a.tx[c + 1] : a.txb[(long long)k * a.ny + j]) * (fc - (i < a.nx - 1 ? f(c + 1) : 0.0f));
-  q = q + a.ty[yi] * (fc - (j > 0 ? f(c - a.nx) : 0.0f));
-  q = q + a.ty[yi + a.nx] * (fc - (j < a.ny - 1 ? f(c + a.nx) : 0.0f));
-  q = q + a.tz[c] * (fc - (k > 0 ? f(c - plane) : 0.0f));
-  q = q + a.tz[c + plane] * (fc - (k < a.nz - 1 ? f(c + plane) : 0.0f));
+  float q = T[0] * (fc - fv[0]);
+#pragma unroll
+  for (int d = 1; d < 6; ++d) q = q + T[d] * (fc - fv[d]);
   return q;
 }
 
@@ -631,24 +837,42 @@ __global__ void k_l0_fix_terms(L0 a, int nent, const int* __restrict__ ent, cons
   const long long plane = (long long)a.nx * a.ny;
   const int i = (int)(c % a.nx), j = (int)((c / a.nx) % a.ny), k = (int)(c / plane);
   const long long yi = ((long long)k * (a.ny + 1) + j) * a.nx + i;
-  const long long nb[6] = {i > 0 ? c - 1 : -1, i < a.nx - 1 ? c + 1 : -1, j > 0 ? c - a.nx : -1,
-                           j < a.ny - 1 ? c + a.nx : -1, k > 0 ? c - plane : -1, k < a.nz - 1 ? c + plane : -1};
-  const float T[6] = {a.tx[c], i < a.nx - 1 ? a.tx[c + 1] : a.txb[(long long)k * a.ny + j], a.ty[yi], a.ty[yi + a.nx],
-                      a.tz[c], a.tz[c + plane]};
+  const bool ok[6] = {i > 0, i < a.nx - 1, j > 0, j < a.ny - 1, k > 0, k < a.nz - 1};
+  const long long off[6] = {-1, 1, -a.nx, a.nx, -plane, plane};
+  const float m1 = ok[1] ? 1.0f : 0.0f;
+  const float tb = a.txb[(long long)k * a.ny + j];
+  const float txp = a.tx[ok[1] ? c + 1 : c];
+  const float T[6] = {a.tx[c], txp * m1 + tb * (1.0f - m1), a.ty[yi], a.ty[yi + a.nx], a.tz[c], a.tz[c + plane]};
+  // roots of the neighbours, then the smoothed values of the roots, each
+  // batch loaded unconditionally; a neighbour beyond the domain reads the
+  // cell itself, an inactive one (root -1) reads cell 0, and both are
+  // multiplied by 0
+  long long nb[6];
   int rt[6];
 #pragma unroll
-  for (int f = 0; f < 6; ++f) rt[f] = nb[f] >= 0 ? root[nb[f]] : -1;
-  auto zr = [&](int x) { return x < 0 ? 0.0f : a.p.w * (a.dinv[x] * a.r[x]); };
+  for (int f = 0; f < 6; ++f) {
+    nb[f] = ok[f] ? c + off[f] : c;
+    rt[f] = root[nb[f]];
+  }
+  const int rs = root[c];
+  float zr[6], slave[6];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const float m = ok[f] && rt[f] >= 0 ? 1.0f : 0.0f;
+    const int x = rt[f] < 0 ? 0 : rt[f];
+    zr[f] = a.p.w * (a.dinv[x] * a.r[x]) * m;
+    slave[f] = ok[f] && rt[f] >= 0 && rt[f] != nb[f] ? 1.0f : 0.0f;
+  }
   float t = 0.0f;
   if (code >= 0) {
 #pragma unroll
-    for (int f = 0; f < 6; ++f)
-      if (rt[f] >= 0 && rt[f] != nb[f]) t += T[f] * zr(rt[f]);
+    for (int f = 0; f < 6; ++f) t += T[f] * zr[f] * slave[f];
   } else {
-    const float zs = zr(root[c]);
-    float q = 0.0f;
+    const int x = rs < 0 ? 0 : rs;
+    const float zs = a.p.w * (a.dinv[x] * a.r[x]) * (rs < 0 ? 0.0f : 1.0f);
+    float q = T[0] * (zs - zr[0]);
 #pragma unroll
-    for (int f = 0; f < 6; ++f) q = q + T[f] * (zs - zr(rt[f]));
+    for (int f = 1; f < 6; ++f) q = q + T[f] * (zs - zr[f]);
     t = -q;
   }
   term[e] = t;
@@ -692,7 +916,9 @@ __global__ void k_l0_up_fix(L0 a, int nrow, const int* __restrict__ rows, const 
     const Raw w = l0_raw<true>(a, x, i, j, k);
     const int rt = root[x];
     const float zs = z[x];
-    return w.m ? l0_val<true>(a, w) : rt >= 0 ? zs : 0.0f;
+    // an unknown: its own zp; a slave: its slot; inactive: 0
+    const float mu = w.m ? 1.0f : 0.0f, ms = !w.m && rt >= 0 ? 1.0f : 0.0f;
+    return (a.p.w * (w.d * w.r) + a.p.a * w.z) * mu + zs * ms;
   };
   const long long c = rows[t];
   const float zc = zp(c);
@@ -1019,13 +1245,19 @@ nfa_status mg_vcycle(nfa_mg_s& mg, const float* r0, float* z0, const SolveScalar
   int tx;
   const Cyc p{(float)mg.omega, (float)mg.alpha};
   const Dims& C1 = mg.lv[1].d;
-  L0 a{d0.nx, d0.ny, d0.nz, 16, (d0.nx + L0X - 1) / L0X, (d0.ny + L0Y - 1) / L0Y, c32.tx, c32.txb, c32.ty, c32.tz,
+  // 4 cells per lane when rows and every per-cell array allow 16-byte loads
+  const bool x4 = d0.nx % 4 == 0 && ((uintptr_t)r0 % 16) == 0 && ((uintptr_t)z0 % 16) == 0;
+  const int tw = x4 ? 4 * L0X : L0X;
+  L0 a{d0.nx, d0.ny, d0.nz, 16, (d0.nx + tw - 1) / tw, (d0.ny + L0Y - 1) / L0Y, c32.tx, c32.txb, c32.ty, c32.tz,
        c32.dinv, r0, red, p, C1.nx, C1.ny, nullptr};
   const int nb0 = a.tiles_x * a.tiles_y * ((d0.nz + a.kchunk - 1) / a.kchunk);
   // level 0, down
   {
     const bool rec = prof_begin(op, st);
-    k_l0<false><<<nb0, L0X * L0Y, 0, st>>>(a, mg.lv[1].r.as<float>(), sc);
+    if (x4)
+      k_l0_x4<false><<<nb0, L0X * L0Y, 0, st>>>(a, mg.lv[1].r.as<float>(), sc);
+    else
+      k_l0<false><<<nb0, L0X * L0Y, 0, st>>>(a, mg.lv[1].r.as<float>(), sc);
     prof_end(op, rec, kProfMgDown, st);
     if (mg.nfblk > 0) {
       k_l0_fix_terms<<<(mg.nfent + 255) / 256, 256, 0, st>>>(a, mg.nfent, mg.fent.as<int>(), g.root.as<int>(),
@@ -1070,7 +1302,10 @@ nfa_status mg_vcycle(nfa_mg_s& mg, const float* r0, float* z0, const SolveScalar
   {
     a.zc = mg.lv[1].zt.as<float>();
     const bool rec = prof_begin(op, st);
-    k_l0<true><<<nb0, L0X * L0Y, 0, st>>>(a, z0, sc);
+    if (x4)
+      k_l0_x4<true><<<nb0, L0X * L0Y, 0, st>>>(a, z0, sc);
+    else
+      k_l0<true><<<nb0, L0X * L0Y, 0, st>>>(a, z0, sc);
     prof_end(op, rec, kProfMgUp, st);
     const int nfix = (int)g.h_fix.size();
     if (g.n_slaves > 0)
