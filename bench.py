@@ -49,26 +49,29 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "cg_sweeps_c3_traffic.md")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1410_1937_amd", "csrc", "cg.hip")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
-    summary, or None when there is none or the kernel source has changed since
-    the counters were taken."""
+    """HBM bytes per launch of `kernel` from a committed FETCH_SIZE/WRITE_SIZE
+    summary (profiles/*_traffic.md) whose listed sources are unchanged since
+    the counters were taken, else None."""
+    import glob
     import hashlib
     import re
-    try:
-        text = open(TRAFFIC_SUMMARY).read()
-        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    except OSError:
-        return None
-    m = re.search(r"source sha256 \(paper_1410_1937_amd/csrc/cg.hip\): ([0-9a-f]{64})", text)
-    if not m or m.group(1) != sha:
-        return None
-    m = re.search(r"traffic_bytes_per_launch " + re.escape(kernel) + r": (\d+)", text)
-    return int(m.group(1)) if m else None
+    for path in sorted(glob.glob(os.path.join(PROFILES, "*_traffic.md"))):
+        text = open(path).read()
+        m = re.search(r"traffic_bytes_per_launch " + re.escape(kernel) + r": (\d+)", text)
+        srcs = re.findall(r"source sha256 \(([^)]+)\): ([0-9a-f]{64})", text)
+        if not m or not srcs:
+            continue
+        try:
+            fresh = all(hashlib.sha256(open(os.path.join(ROOT, p), "rb").read()).hexdigest() == h for p, h in srcs)
+        except OSError:
+            fresh = False
+        if fresh:
+            return int(m.group(1))
+    return None
 
 
 def cpu_baseline(iters_fp64: int, sample_iters: int = 4) -> dict:
@@ -186,8 +189,9 @@ def main():
     # sweep reads the same plus one level-1 value per 8 cells and writes z:
     # 25.5 B.  Neighbour re-reads are cache hits and not counted.
     wx = next((w for w in (4, 2) if wl.shape[2] % (w * 128) == 0), 1)
+    l0 = "k_l0_x4" if wl.shape[2] % 4 == 0 else "k_l0"
     meta = {"f32": (36, "k_cg_a<float, 4, 1, true>"), "f64": (72, f"k_cg_a<double, 2, {wx}, false>"),
-            "mg_down": (21.5, "k_l0<false>"), "mg_up": (25.5, "k_l0<true>")}
+            "mg_down": (21.5, f"{l0}<false>"), "mg_up": (25.5, f"{l0}<true>")}
     entries = {}
     for k, ks in kinds.items():
         if ks["launches"] == 0:
