@@ -499,7 +499,8 @@ __device__ __forceinline__ Faces l0_faces(const L0& a, long long c, long long yi
 }
 
 template <bool UP>
-__global__ __launch_bounds__(L0X* L0Y) void k_l0(L0 a, float* out, const SolveScalars* sc) {
+__global__ __launch_bounds__(L0X* L0Y) void k_l0(L0 a, float* out, const float* __restrict__ q,
+                                                double* __restrict__ part, const SolveScalars* sc) {
   if (solve_done(sc)) return;
   __shared__ float pl[2][L0Y + 2][L0X + 2];
   __shared__ float rb[2][L0Y][L0X / 2];
@@ -549,6 +550,7 @@ __global__ __launch_bounds__(L0X* L0Y) void k_l0(L0 a, float* out, const SolveSc
     if (halo_in) hcur = l0_raw<UP>(a, (long long)k0 * plane + hc0, hi, hj, k0);
   }
   float acc = 0.0f;
+  double dot = 0.0;
   for (int k = k0; k < k1; ++k, c += plane, yi += yplane) {
     const int b = (k - k0) & 1;
     const float vc = in ? l0_val<UP>(a, cur) : 0.0f;
@@ -566,16 +568,19 @@ __global__ __launch_bounds__(L0X* L0Y) void k_l0(L0 a, float* out, const SolveSc
     const float vp = (in && k + 1 < a.nz) ? l0_val<UP>(a, nxt) : 0.0f;
     float w = 0.0f;
     if (in) {
-      float q = f.txm * (vc - pl[b][ly + 1][lx]);
-      q = q + f.txp * (vc - pl[b][ly + 1][lx + 2]);
-      q = q + f.tym * (vc - pl[b][ly][lx + 1]);
-      q = q + f.typ * (vc - pl[b][ly + 2][lx + 1]);
-      q = q + tzm * (vc - vm);
-      q = q + f.tzp * (vc - vp);
-      if (UP)
-        out[c] = cur.m ? vc + a.p.w * (cur.d * (cur.r - q)) : 0.0f;
-      else if (cur.m)
-        w = cur.r - q;
+      float aq = f.txm * (vc - pl[b][ly + 1][lx]);
+      aq = aq + f.txp * (vc - pl[b][ly + 1][lx + 2]);
+      aq = aq + f.tym * (vc - pl[b][ly][lx + 1]);
+      aq = aq + f.typ * (vc - pl[b][ly + 2][lx + 1]);
+      aq = aq + tzm * (vc - vm);
+      aq = aq + f.tzp * (vc - vp);
+      if (UP) {
+        const float zo = cur.m ? vc + a.p.w * (cur.d * (cur.r - aq)) : 0.0f;
+        out[c] = zo;
+        if (part) dot += (double)zo * (double)q[c];
+      } else if (cur.m) {
+        w = cur.r - aq;
+      }
     }
     if (!UP) {
       acc += w;
@@ -598,6 +603,11 @@ __global__ __launch_bounds__(L0X* L0Y) void k_l0(L0 a, float* out, const SolveSc
     nxt = nn;
     hcur = hnext;
     f = fn;
+  }
+  if (UP && part) {
+    __shared__ double red[L0X * L0Y / 64];
+    const double t = block_sum(dot, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
   }
 }
 
@@ -662,7 +672,8 @@ __device__ __forceinline__ float4 f4(float v) { return make_float4(v, v, v, v); 
 __device__ __forceinline__ float comp(const float4& v, int e) { return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w; }
 
 template <bool UP>
-__global__ __launch_bounds__(256) void k_l0_x4(L0 a, float* out, const SolveScalars* sc) {
+__global__ __launch_bounds__(256) void k_l0_x4(L0 a, float* out, const float* __restrict__ q,
+                                               double* __restrict__ part, const SolveScalars* sc) {
   if (solve_done(sc)) return;
   constexpr int W = 4 * L0X;   // cells of a tile row
   __shared__ float pl[2][L0Y + 2][W + 2];
@@ -718,6 +729,7 @@ __global__ __launch_bounds__(256) void k_l0_x4(L0 a, float* out, const SolveScal
     }
   }
   float acc0 = 0.0f, acc1 = 0.0f;
+  double dot = 0.0;
   for (int k = k0; k < k1; ++k, c += plane, yi += yplane) {
     const int b = (k - k0) & 1;
     const float4 vc = in ? l0_val4<UP>(a, cur) : f4(0.0f);
@@ -766,7 +778,14 @@ __global__ __launch_bounds__(256) void k_l0_x4(L0 a, float* out, const SolveScal
         else
           w[e] = me ? comp(cur.r, e) - q : 0.0f;
       }
-      if (UP) *reinterpret_cast<float4*>(out + c) = make_float4(o[0], o[1], o[2], o[3]);
+      if (UP) {
+        *reinterpret_cast<float4*>(out + c) = make_float4(o[0], o[1], o[2], o[3]);
+        if (part) {
+          const float4 q4 = *reinterpret_cast<const float4*>(q + c);
+          dot += (double)o[0] * (double)q4.x + (double)o[1] * (double)q4.y + (double)o[2] * (double)q4.z +
+                 (double)o[3] * (double)q4.w;
+        }
+      }
     }
     if (!UP) {
       acc0 += w[0] + w[1];
@@ -794,6 +813,11 @@ __global__ __launch_bounds__(256) void k_l0_x4(L0 a, float* out, const SolveScal
     hc4 = hn4;
     hc1 = hn1;
     f = fn;
+  }
+  if (UP && part) {
+    __shared__ double red[256 / 64];
+    const double t = block_sum(dot, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
   }
 }
 
@@ -901,32 +925,64 @@ __global__ void k_l0_slave_zp(L0 a, int ns, const int* __restrict__ s_cell, cons
   z[s_cell[t]] = l0_value<true>(a, rt, (int)(rt % a.nx), (int)((rt / a.nx) % a.ny), (int)(rt / plane));
 }
 
-// Up fix-up, step 2: one thread per row of the list, redone with the merged
-// operator (a slave's value read from its z slot, a root adding its slaves'
-// rows).
-__global__ void k_l0_up_fix(L0 a, int nrow, const int* __restrict__ rows, const int* __restrict__ root,
-                            const int* __restrict__ group_of, const int* __restrict__ g_off,
-                            const int* __restrict__ g_mem, float* z, const SolveScalars* sc) {
+// Up fix-up, step 2: one thread per row of the list.  The up sweep formed
+// z = z' + omega D^-1 (r - q^) with a slave's value taken as 0 and a root
+// without its slaves' rows; with the merged operator q' = q^ - sum over the
+// row's faces to slaves of T_f z(slave) (+ the slaves' rows for a root), so
+// z -= omega D^-1 (q' - q^).  Slaves' values are their z slots (step 1).
+__global__ __launch_bounds__(256) void k_l0_up_fix(L0 a, int nrow, const int* __restrict__ rows,
+                                                   const int* __restrict__ root, const int* __restrict__ group_of,
+                                                   const int* __restrict__ g_off, const int* __restrict__ g_mem, float* z,
+                                                   const float* __restrict__ qv, double* __restrict__ part,
+                                                   const SolveScalars* sc) {
   if (solve_done(sc)) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nrow) return;
   const long long plane = (long long)a.nx * a.ny;
+  // a neighbour's merged value: its own z' (an unknown), its slot (a slave), 0 (inactive)
   auto zp = [&](long long x) {
     const int i = (int)(x % a.nx), j = (int)((x / a.nx) % a.ny), k = (int)(x / plane);
     const Raw w = l0_raw<true>(a, x, i, j, k);
     const int rt = root[x];
     const float zs = z[x];
-    // an unknown: its own zp; a slave: its slot; inactive: 0
     const float mu = w.m ? 1.0f : 0.0f, ms = !w.m && rt >= 0 ? 1.0f : 0.0f;
     return (a.p.w * (w.d * w.r) + a.p.a * w.z) * mu + zs * ms;
   };
-  const long long c = rows[t];
-  const float zc = zp(c);
-  float q = l0_row(a, c, zp);
-  const int gi = group_of[c];
-  if (gi >= 0)
-    for (int m = g_off[gi]; m < g_off[gi + 1]; ++m) q = q + l0_row(a, g_mem[m], zp);
-  z[c] = zc + a.p.w * (a.dinv[c] * (a.r[c] - q));
+  double dd = 0.0;
+  if (t < nrow) {
+    const long long c = rows[t];
+    const int i = (int)(c % a.nx), j = (int)((c / a.nx) % a.ny), k = (int)(c / plane);
+    const long long yi = ((long long)k * (a.ny + 1) + j) * a.nx + i;
+    const bool ok[6] = {i > 0, i < a.nx - 1, j > 0, j < a.ny - 1, k > 0, k < a.nz - 1};
+    const long long off[6] = {-1, 1, -a.nx, a.nx, -plane, plane};
+    const float m1 = ok[1] ? 1.0f : 0.0f;
+    const float tb = a.txb[(long long)k * a.ny + j];
+    const float txp = a.tx[ok[1] ? c + 1 : c];
+    const float T[6] = {a.tx[c], txp * m1 + tb * (1.0f - m1), a.ty[yi], a.ty[yi + a.nx], a.tz[c], a.tz[c + plane]};
+    // faces to slaves: all loads issued together, a face masked by a product
+    float dq = 0.0f;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      const long long nb = ok[f] ? c + off[f] : c;
+      const int rt = root[nb];
+      const int red = a.red[nb];
+      const float zs = z[nb];
+      const float slave = ok[f] && !red && rt >= 0 ? 1.0f : 0.0f;
+      dq -= T[f] * (zs * slave);
+    }
+    const int gi = group_of[c];
+    if (gi >= 0)
+      for (int m = g_off[gi]; m < g_off[gi + 1]; ++m) dq = dq + l0_row(a, g_mem[m], zp);
+    const float zold = z[c];
+    const float znew = zold - a.p.w * (a.dinv[c] * dq);
+    z[c] = znew;
+    // the up sweep summed zold . q for this row; the z.q partial takes the difference
+    if (part) dd = ((double)znew - (double)zold) * (double)qv[c];
+  }
+  if (part) {
+    __shared__ double red2[256 / 64];
+    const double s2 = block_sum(dd, red2);
+    if (threadIdx.x == 0) part[blockIdx.x] = s2;
+  }
 }
 
 // The levels from `first` down, in one workgroup: vectors of level l in LDS
@@ -1231,7 +1287,8 @@ nfa_status mg_setup(nfa_mg_s& mg, hipStream_t st) {
 }
 
 // One V-cycle: z = M r on the reduced unknowns of level 0 (FP32).
-nfa_status mg_vcycle(nfa_mg_s& mg, const float* r0, float* z0, const SolveScalars* sc, hipStream_t st) {
+nfa_status mg_vcycle(nfa_mg_s& mg, const float* r0, float* z0, const float* qdot, double* parts, int* np,
+                     const SolveScalars* sc, hipStream_t st) {
   Poisson& op = *mg.op;
   Grid& g = *op.g;
   const Coeffs<float> c32 = op.c32();
@@ -1251,13 +1308,17 @@ nfa_status mg_vcycle(nfa_mg_s& mg, const float* r0, float* z0, const SolveScalar
   L0 a{d0.nx, d0.ny, d0.nz, 16, (d0.nx + tw - 1) / tw, (d0.ny + L0Y - 1) / L0Y, c32.tx, c32.txb, c32.ty, c32.tz,
        c32.dinv, r0, red, p, C1.nx, C1.ny, nullptr};
   const int nb0 = a.tiles_x * a.tiles_y * ((d0.nz + a.kchunk - 1) / a.kchunk);
+  // z.q of the flexible direction summed by the up sweep and the up fix-up
+  const int nfix_blocks = ((int)g.h_fix.size() + 255) / 256;
+  const bool dot = qdot && parts && nb0 + nfix_blocks <= kMaxPartials;
+  if (np) *np = 0;
   // level 0, down
   {
     const bool rec = prof_begin(op, st);
     if (x4)
-      k_l0_x4<false><<<nb0, L0X * L0Y, 0, st>>>(a, mg.lv[1].r.as<float>(), sc);
+      k_l0_x4<false><<<nb0, L0X * L0Y, 0, st>>>(a, mg.lv[1].r.as<float>(), nullptr, nullptr, sc);
     else
-      k_l0<false><<<nb0, L0X * L0Y, 0, st>>>(a, mg.lv[1].r.as<float>(), sc);
+      k_l0<false><<<nb0, L0X * L0Y, 0, st>>>(a, mg.lv[1].r.as<float>(), nullptr, nullptr, sc);
     prof_end(op, rec, kProfMgDown, st);
     if (mg.nfblk > 0) {
       k_l0_fix_terms<<<(mg.nfent + 255) / 256, 256, 0, st>>>(a, mg.nfent, mg.fent.as<int>(), g.root.as<int>(),
@@ -1303,30 +1364,31 @@ nfa_status mg_vcycle(nfa_mg_s& mg, const float* r0, float* z0, const SolveScalar
     a.zc = mg.lv[1].zt.as<float>();
     const bool rec = prof_begin(op, st);
     if (x4)
-      k_l0_x4<true><<<nb0, L0X * L0Y, 0, st>>>(a, z0, sc);
+      k_l0_x4<true><<<nb0, L0X * L0Y, 0, st>>>(a, z0, qdot, dot ? parts : nullptr, sc);
     else
-      k_l0<true><<<nb0, L0X * L0Y, 0, st>>>(a, z0, sc);
+      k_l0<true><<<nb0, L0X * L0Y, 0, st>>>(a, z0, qdot, dot ? parts : nullptr, sc);
     prof_end(op, rec, kProfMgUp, st);
     const int nfix = (int)g.h_fix.size();
     if (g.n_slaves > 0)
       k_l0_slave_zp<<<(g.n_slaves + 255) / 256, 256, 0, st>>>(a, g.n_slaves, g.s_cell.as<int>(), g.s_root.as<int>(),
                                                               z0, sc);
+    const int nfb = (nfix + 255) / 256;
     if (nfix > 0)
-      k_l0_up_fix<<<(nfix + 255) / 256, 256, 0, st>>>(a, nfix, g.fix_rows.as<int>(), g.root.as<int>(),
-                                                      mg.group_of.as<int>(), g.g_off.as<int>(), g.g_mem.as<int>(),
-                                                      z0, sc);
+      k_l0_up_fix<<<nfb, 256, 0, st>>>(a, nfix, g.fix_rows.as<int>(), g.root.as<int>(), mg.group_of.as<int>(),
+                                       g.g_off.as<int>(), g.g_mem.as<int>(), z0, qdot, dot ? parts + nb0 : nullptr, sc);
+    if (np) *np = dot ? nb0 + (nfix > 0 ? nfb : 0) : 0;
   }
   NFA_CHECK_LAUNCH();
   return NFA_OK;
 }
 
-nfa_status mg_precond_apply(void* mgh, Poisson& op, const float* r, float* z, const SolveScalars* sc,
-                            hipStream_t st) {
+nfa_status mg_precond_apply(void* mgh, Poisson& op, const float* r, float* z, const float* q, double* parts, int* np,
+                            const SolveScalars* sc, hipStream_t st) {
   if (!mgh) return fail(NFA_ERR_INVALID, "multigrid preconditioner: no handle");
   nfa_mg_s& mg = *static_cast<nfa_mg_s*>(mgh);
   if (mg.op != &op) return fail(NFA_ERR_INVALID, "multigrid preconditioner: built for another operator");
   if (mg.built_version != op.version) return fail(NFA_ERR_INVALID, "multigrid preconditioner: not set up");
-  return mg_vcycle(mg, r, z, sc, st);
+  return mg_vcycle(mg, r, z, q, parts, np, sc, st);
 }
 
 nfa_status mg_ensure(void* mgh, Poisson& op, hipStream_t st) {
@@ -1398,7 +1460,7 @@ extern "C" nfa_status nfa_mg_apply(nfa_mg mg, const float* r, float* z, nfa_stre
   if (r == z) return fail(NFA_ERR_INVALID, "nfa_mg_apply: r and z must differ");
   if (mg->built_version != mg->op->version)
     return fail(NFA_ERR_INVALID, "nfa_mg_apply: call nfa_mg_setup after the last assembly");
-  const nfa_status e = mg_vcycle(*mg, r, z, nullptr, S(s));
+  const nfa_status e = mg_vcycle(*mg, r, z, nullptr, nullptr, nullptr, nullptr, S(s));
   if (e != NFA_OK) return e;
   launch_merge_copy<float>(*mg->op->g, z, S(s), nullptr);
   NFA_CHECK_LAUNCH();

@@ -192,9 +192,12 @@ struct nfa_grid_s : nfa::Grid {};
 
 namespace nfa {
 // Multigrid preconditioner (multigrid.hip): one V-cycle z = M r in FP32, and
-// a (re)build of the hierarchy when the operator has been reassembled.
-nfa_status mg_precond_apply(void* mg, Poisson& op, const float* r, float* z, const SolveScalars* sc,
-                            hipStream_t s);
+// a (re)build of the hierarchy when the operator has been reassembled.  With
+// q and partials given, the cycle also writes the block partial sums of
+// z.q (z before the slaves copy their roots) and returns their count in *np
+// (0: not summed, the caller sums them).
+nfa_status mg_precond_apply(void* mg, Poisson& op, const float* r, float* z, const float* q, double* partials,
+                            int* np, const SolveScalars* sc, hipStream_t s);
 nfa_status mg_ensure(void* mg, Poisson& op, hipStream_t s);
 }  // namespace nfa
 struct nfa_poisson_s : nfa::Poisson {};

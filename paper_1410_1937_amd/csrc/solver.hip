@@ -98,20 +98,23 @@ void enqueue_iter(Poisson& op, CG<T>& B, int j, int pc, void* unet, nfa_status* 
   double* hist = op.hist.as<double>();
   const bool flex = pc != NFA_PC_JACOBI;
   if (flex) {
+    int nzq = 0;   // partials of z.q written by the preconditioner itself
     if (pc == NFA_PC_JACOBI_FCG) {
       launch_scale<T>(B.r, B.C.dinv, B.z, g.n, sc, st);
     } else if (pc == NFA_PC_TEST_SABOTAGE) {
       launch_sabotage<T>(g.reduced.as<unsigned char>(), B.z, g.n, sc, st);
     } else if (pc == NFA_PC_MG) {
-      const nfa_status e = mg_precond_apply(unet, op, (const float*)B.r, (float*)B.z, sc, st);
+      const nfa_status e = mg_precond_apply(unet, op, (const float*)B.r, (float*)B.z, (const float*)B.q, parts, &nzq,
+                                            sc, st);
       if (e != NFA_OK && *pst == NFA_OK) *pst = e;
     } else {
       const nfa_status e = unet_precond_apply(unet, op, (const float*)B.r, (float*)B.z, sc, st);
       if (e != NFA_OK && *pst == NFA_OK) *pst = e;
     }
     launch_merge_copy<T>(g, B.z, st, sc);
-    const int nz = launch_dot<T>(B.z, B.q, g.n, parts, sc, st);
-    launch_finalize(parts, nz, 1, PH_ZQ, sc, hist, st);
+    // slaves' q is 0 (gathered), so their z does not enter z.q
+    if (nzq == 0) nzq = launch_dot<T>(B.z, B.q, g.n, parts, sc, st);
+    launch_finalize(parts, nzq, 1, PH_ZQ, sc, hist, st);
   }
   const int na = timed_cg_a<T>(op, B, j, flex, st);
   launch_finalize_merge<T>(g, true, B.q, parts, na, flex ? 2 : 1, flex ? PH_PQF : PH_PQ, sc, hist, st);

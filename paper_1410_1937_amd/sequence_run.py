@@ -5,10 +5,11 @@ sphere static in the body-fixed frame while the surface and droplets heave and
 drift; each projection's right-hand side carries the body flux of the heave
 velocity, and each solve starts from the previous pressure.  Every projection
 (assemble, right-hand side, solve, projection, divergence) is timed on the
-device; the inputs of step n+1 are generated on host worker processes while
-step n runs.  Prints one line per projection and a JSON summary.
+device (with the multigrid preconditioner its hierarchy is rebuilt from each
+assembly inside the timed projection); the inputs of step n+1 are generated on
+host worker processes while step n runs.  Prints one line per projection and a JSON summary.
 
-    python -m paper_1410_1937_amd.sequence_run --steps 50 --precond unet
+    python -m paper_1410_1937_amd.sequence_run --steps 50 --precond mg
 """
 from __future__ import annotations
 
@@ -32,7 +33,7 @@ def _inputs(n):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--precond", default="unet", choices=("unet", "jacobi"))
+    ap.add_argument("--precond", default="mg", choices=("mg", "unet", "jacobi"))
     ap.add_argument("--precision", default="mixed", choices=("mixed", "f64"))
     ap.add_argument("--workers", type=int, default=6)
     ap.add_argument("--out", default=None, help="write the summary JSON here")
