@@ -183,15 +183,19 @@ def main():
     kinds = {k: op.profile_read(k) for k in ("f32", "f64", "mg_down", "mg_up")}
     op.profile(False)
     # sweep A moves, per cell: z, p_old, tx, ty, tz, x read; p_new, q, x
-    # written (9 words: 36 B in FP32, 72 B in FP64).  The fused level-0
+    # written (9 words: 36 B in FP32, 72 B in FP64); its flexible form also
+    # reads r for p.r (10 words, 40 B in FP32).  The fused level-0
     # down sweep reads r, D^-1, tx, ty, tz (4 B each) and the unknown flag
     # (1 B) and writes one level-1 value per 8 cells (0.5 B): 21.5 B; the up
-    # sweep reads the same plus one level-1 value per 8 cells and writes z:
-    # 25.5 B.  Neighbour re-reads are cache hits and not counted.
+    # sweep reads the same plus one level-1 value per 8 cells and the CG's q
+    # (for z.q) and writes z: 29.5 B.  Neighbour re-reads are cache hits and
+    # not counted.
     wx = next((w for w in (4, 2) if wl.shape[2] % (w * 128) == 0), 1)
     l0 = "k_l0_x4" if wl.shape[2] % 4 == 0 else "k_l0"
-    meta = {"f32": (36, "k_cg_a<float, 4, 1, true>"), "f64": (72, f"k_cg_a<double, 2, {wx}, false>"),
-            "mg_down": (21.5, f"{l0}<false>"), "mg_up": (25.5, f"{l0}<true>")}
+    flex = solver["precond"] != "jacobi"
+    meta = {"f32": (40, "k_cg_a<float, 4, 1, true>") if flex else (36, "k_cg_a<float, 4, 1, false>"),
+            "f64": (72, f"k_cg_a<double, 2, {wx}, false>"),
+            "mg_down": (21.5, f"{l0}<false>"), "mg_up": (29.5, f"{l0}<true>")}
     entries = {}
     for k, ks in kinds.items():
         if ks["launches"] == 0:

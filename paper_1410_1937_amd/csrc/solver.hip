@@ -111,10 +111,15 @@ void enqueue_iter(Poisson& op, CG<T>& B, int j, int pc, void* unet, nfa_status* 
       const nfa_status e = unet_precond_apply(unet, op, (const float*)B.r, (float*)B.z, sc, st);
       if (e != NFA_OK && *pst == NFA_OK) *pst = e;
     }
-    launch_merge_copy<T>(g, B.z, st, sc);
-    // slaves' q is 0 (gathered), so their z does not enter z.q
-    if (nzq == 0) nzq = launch_dot<T>(B.z, B.q, g.n, parts, sc, st);
-    launch_finalize(parts, nzq, 1, PH_ZQ, sc, hist, st);
+    if (nzq > 0) {
+      // z.q summed by the cycle (slaves' q is 0, so their z does not enter
+      // it): its finalize and the slaves' copy of z share a launch
+      launch_finalize_merge<T>(g, false, B.z, parts, nzq, 1, PH_ZQ, sc, hist, st);
+    } else {
+      launch_merge_copy<T>(g, B.z, st, sc);
+      nzq = launch_dot<T>(B.z, B.q, g.n, parts, sc, st);
+      launch_finalize(parts, nzq, 1, PH_ZQ, sc, hist, st);
+    }
   }
   const int na = timed_cg_a<T>(op, B, j, flex, st);
   launch_finalize_merge<T>(g, true, B.q, parts, na, flex ? 2 : 1, flex ? PH_PQF : PH_PQ, sc, hist, st);
