@@ -92,6 +92,14 @@ __host__ __device__ constexpr bool in7(int o) {
   return o == 4 || o == 10 || o == 12 || o == 13 || o == 14 || o == 16 || o == 22;
 }
 
+// acc[o] += v for a run-time o, written so that acc stays in registers (a
+// dynamic index would put the 27 doubles in scratch memory).
+__device__ __forceinline__ void add27(double (&acc)[27], int o, double v) {
+#pragma unroll
+  for (int t = 0; t < 27; ++t)
+    if (t == o) acc[t] += v;
+}
+
 __device__ __forceinline__ void store_row(long long n, long long B, const double* acc, double* A64, float4* S) {
   bool extra = false;
 #pragma unroll
@@ -114,63 +122,113 @@ __global__ void k_level1(Dims f, Dims c, const double* __restrict__ tx, const do
     const int I = (int)(B % c.nx);
     const long long rr = B / c.nx;
     const int J = (int)(rr % c.ny), K = (int)(rr / c.ny);
-    double acc[27];
+    // acc takes the couplings whose target block is fixed by the face (a
+    // neighbour that is its own root), dyn the ones through merge groups;
+    // only dyn is indexed at run time, so acc stays in registers
+    double acc[27], dyn[27];
+    bool has_dyn = false;   // dyn is zeroed and read only when a merge touches the block
 #pragma unroll
     for (int o = 0; o < 27; ++o) acc[o] = 0.0;
+    // a face of member m (cell indices im, jm, km) to a cell whose root is rn
+    auto merged_face = [&](double T, int rn) {
+      if (rn < 0) return;
+      const int in = rn % f.nx;
+      const int rrn = rn / f.nx;
+      const int jn = rrn % f.ny, kn = rrn / f.ny;
+      const int dK = (kn >> 1) - K, dJ = (jn >> 1) - J, dI = (in >> 1) - I;
+      if (dK == 0 && dJ == 0 && dI == 0) return;
+      acc[13] += T;
+      if (dK >= -1 && dK <= 1 && dJ >= -1 && dJ <= 1 && dI >= -1 && dI <= 1) {
+        if (!has_dyn) {
+          for (int o = 0; o < 27; ++o) dyn[o] = 0.0;
+          has_dyn = true;
+        }
+        dyn[(dK + 1) * 9 + (dJ + 1) * 3 + (dI + 1)] -= T;
+      }
+    };
+    auto face_of = [&](long long m, int im, int jm, int km, long long rm, int face, double& T) -> long long {
+      long long nb = -1;
+      if (face == 0) {
+        T = tx[m];
+        if (im > 0) nb = m - 1;
+      } else if (face == 1) {
+        T = im < f.nx - 1 ? tx[m + 1] : txb[rm];
+        if (im < f.nx - 1) nb = m + 1;
+      } else if (face == 2) {
+        T = ty[((long long)km * (f.ny + 1) + jm) * f.nx + im];
+        if (jm > 0) nb = m - f.nx;
+      } else if (face == 3) {
+        T = ty[((long long)km * (f.ny + 1) + jm + 1) * f.nx + im];
+        if (jm < f.ny - 1) nb = m + f.nx;
+      } else if (face == 4) {
+        T = tz[m];
+        if (km > 0) nb = m - fplane;
+      } else {
+        T = tz[m + fplane];
+        if (km < f.nz - 1) nb = m + fplane;
+      }
+      return nb;
+    };
+#pragma unroll
     for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
       for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
         for (int ii = 0; ii < 2; ++ii) {
           const int k = 2 * K + kk, j = 2 * J + jj, i = 2 * I + ii;
           if (k >= f.nz || j >= f.ny || i >= f.nx) continue;
           const long long cidx = ((long long)k * f.ny + j) * f.nx + i;
           if (!reduced[cidx]) continue;
-          const int gi = group_of[cidx];
-          const int nmem = 1 + (gi >= 0 ? g_off[gi + 1] - g_off[gi] : 0);
-          for (int mi = 0; mi < nmem; ++mi) {
-            const long long m = mi == 0 ? cidx : (long long)g_mem[g_off[gi] + mi - 1];
-            const int im = (int)(m % f.nx);
-            const long long rm = m / f.nx;
-            const int jm = (int)(rm % f.ny), km = (int)(rm / f.ny);
-            for (int face = 0; face < 6; ++face) {
-              double T;
-              long long nb = -1;
-              if (face == 0) {
-                T = tx[m];
-                if (im > 0) nb = m - 1;
-              } else if (face == 1) {
-                T = im < f.nx - 1 ? tx[m + 1] : txb[rm];
-                if (im < f.nx - 1) nb = m + 1;
-              } else if (face == 2) {
-                T = ty[((long long)km * (f.ny + 1) + jm) * f.nx + im];
-                if (jm > 0) nb = m - f.nx;
-              } else if (face == 3) {
-                T = ty[((long long)km * (f.ny + 1) + jm + 1) * f.nx + im];
-                if (jm < f.ny - 1) nb = m + f.nx;
-              } else if (face == 4) {
-                T = tz[m];
-                if (km > 0) nb = m - fplane;
-              } else {
-                T = tz[m + fplane];
-                if (km < f.nz - 1) nb = m + fplane;
-              }
-              if (!(T > 0.0)) continue;
-              if (nb < 0) {          // a Dirichlet boundary face
-                acc[13] += T;
-                continue;
-              }
-              const int rn = root[nb];
-              if (rn < 0 || (long long)rn == cidx) continue;
-              const int in = rn % f.nx;
-              const int rrn = rn / f.nx;
-              const int jn = rrn % f.ny, kn = rrn / f.ny;
-              const int dK = (kn >> 1) - K, dJ = (jn >> 1) - J, dI = (in >> 1) - I;
+          const long long rm0 = cidx / f.nx;
+#pragma unroll
+          for (int face = 0; face < 6; ++face) {
+            double T;
+            const long long nb = face_of(cidx, i, j, k, rm0, face, T);
+            if (!(T > 0.0)) continue;
+            if (nb < 0) {          // a Dirichlet boundary face
+              acc[13] += T;
+              continue;
+            }
+            const int rn = root[nb];
+            if (rn < 0 || (long long)rn == cidx) continue;
+            if ((long long)rn == nb) {
+              // the neighbour carries its own unknown: its block follows from the face
+              const int dI = face == 0 ? (ii - 1) >> 1 : face == 1 ? (ii + 1) >> 1 : 0;
+              const int dJ = face == 2 ? (jj - 1) >> 1 : face == 3 ? (jj + 1) >> 1 : 0;
+              const int dK = face == 4 ? (kk - 1) >> 1 : face == 5 ? (kk + 1) >> 1 : 0;
               if (dK == 0 && dJ == 0 && dI == 0) continue;
               acc[13] += T;
-              if (dK >= -1 && dK <= 1 && dJ >= -1 && dJ <= 1 && dI >= -1 && dI <= 1)
-                acc[(dK + 1) * 9 + (dJ + 1) * 3 + (dI + 1)] -= T;
+              acc[(dK + 1) * 9 + (dJ + 1) * 3 + (dI + 1)] -= T;
+            } else {
+              merged_face(T, rn);
             }
           }
+          // the faces of the cell's slaves, through their roots
+          const int gi = group_of[cidx];
+          if (gi >= 0)
+            for (int e = g_off[gi]; e < g_off[gi + 1]; ++e) {
+              const long long m = g_mem[e];
+              const int im = (int)(m % f.nx);
+              const long long rm = m / f.nx;
+              const int jm = (int)(rm % f.ny), km = (int)(rm / f.ny);
+              for (int face = 0; face < 6; ++face) {
+                double T;
+                const long long nb = face_of(m, im, jm, km, rm, face, T);
+                if (!(T > 0.0)) continue;
+                if (nb < 0) {
+                  acc[13] += T;
+                  continue;
+                }
+                const int rn = root[nb];
+                if (rn < 0 || (long long)rn == cidx) continue;
+                merged_face(T, rn);
+              }
+            }
         }
+    if (has_dyn) {
+#pragma unroll
+      for (int o = 0; o < 27; ++o) acc[o] += dyn[o];
+    }
     store_row(c.n, B, acc, A64, S);
   }
 }
@@ -184,18 +242,24 @@ __global__ void k_coarsen(Dims f, Dims c, const double* __restrict__ Af, double*
     double acc[27];
 #pragma unroll
     for (int o = 0; o < 27; ++o) acc[o] = 0.0;
+    // child (kk, jj, ii) and fine offset o fix the coarse offset, so every
+    // index into acc is a constant once the loops are unrolled
+#pragma unroll
     for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
       for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
         for (int ii = 0; ii < 2; ++ii) {
           const int k = 2 * K + kk, j = 2 * J + jj, i = 2 * I + ii;
           if (k >= f.nz || j >= f.ny || i >= f.nx) continue;
           const long long cidx = ((long long)k * f.ny + j) * f.nx + i;
+#pragma unroll
           for (int o = 0; o < 27; ++o) {
-            const double a = Af[o * f.n + cidx];
-            if (a == 0.0) continue;
-            const int kn = k + o / 9 - 1, jn = j + (o / 3) % 3 - 1, in = i + o % 3 - 1;
+            const int dz = o / 9 - 1, dy = (o / 3) % 3 - 1, dx = o % 3 - 1;
+            const int kn = k + dz, jn = j + dy, in = i + dx;
             if (kn < 0 || kn >= f.nz || jn < 0 || jn >= f.ny || in < 0 || in >= f.nx) continue;
-            acc[((kn >> 1) - K + 1) * 9 + ((jn >> 1) - J + 1) * 3 + ((in >> 1) - I + 1)] += a;
+            const double a = Af[o * f.n + cidx];
+            if (a != 0.0) acc[(((kk + dz) >> 1) + 1) * 9 + (((jj + dy) >> 1) + 1) * 3 + (((ii + dx) >> 1) + 1)] += a;
           }
         }
     store_row(c.n, B, acc, A64, S);
