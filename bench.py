@@ -54,19 +54,23 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from a committed FETCH_SIZE/WRITE_SIZE
-    summary (profiles/*_traffic.md) whose listed sources are unchanged since
-    the counters were taken, else None."""
+    summary (profiles/*_traffic.md), provided the kernel's source file (its
+    `kernel_source` line, else every listed source) is unchanged since the
+    counters were taken; else None."""
     import glob
     import hashlib
     import re
     for path in sorted(glob.glob(os.path.join(PROFILES, "*_traffic.md"))):
         text = open(path).read()
         m = re.search(r"traffic_bytes_per_launch " + re.escape(kernel) + r": (\d+)", text)
-        srcs = re.findall(r"source sha256 \(([^)]+)\): ([0-9a-f]{64})", text)
-        if not m or not srcs:
+        shas = dict(re.findall(r"source sha256 \(([^)]+)\): ([0-9a-f]{64})", text))
+        if not m or not shas:
             continue
+        own = re.search(r"kernel_source " + re.escape(kernel) + r": (\S+)", text)
+        need = [own.group(1)] if own else list(shas)
         try:
-            fresh = all(hashlib.sha256(open(os.path.join(ROOT, p), "rb").read()).hexdigest() == h for p, h in srcs)
+            fresh = all(p in shas and hashlib.sha256(open(os.path.join(ROOT, p), "rb").read()).hexdigest() == shas[p]
+                        for p in need)
         except OSError:
             fresh = False
         if fresh:
