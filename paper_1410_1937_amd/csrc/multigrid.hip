@@ -35,13 +35,21 @@
 // piecewise-constant prolongation), so the solve may use it in (flexible)
 // CG.  On levels >= 1 the pre-smoothed z = omega D^-1 r is never stored:
 //   down   r_{l+1} = P^T (r - A z) = P^T ((1 - omega) r - omega N (D^-1 r)),
-//   up     z' = z + P z_{l+1};  zt = (1 - omega) z' + omega D^-1 (r - N z'),
+//   up     z' = z + alpha P z_{l+1};  zt = (1 - omega) z' + omega D^-1 (r - N z'),
 // N the off-diagonal part (the diagonal terms cancel against D^-1 exactly in
 // exact arithmetic), z' formed on the fly at each neighbour.  Rows without
 // an unknown keep z' (zero coupling).  The levels from the first one with at
 // most `tail` cells down run in one workgroup with their vectors in LDS,
-// ending in the dense FP64 coarsest solve.  Every kernel returns at once
-// when the solve has converged.
+// ending in the dense FP64 coarsest solve.
+//
+// Level 0 (the merged operator, read from the operator's FP32 face
+// coefficients) runs as two fused sweeps that march z-columns: down forms
+// omega D^-1 r, applies the operator and restricts; up prolongs, applies the
+// operator, post-smooths and sums z.q for the flexible CG.  Both treat every
+// cell on its own; the rows this gets wrong (roots, which carry their
+// slaves' rows, and unknowns next to a slave) are corrected afterwards from
+// lists built when the body is set.  Every kernel returns at once when the
+// solve has converged.
 //
 // Built with -ffp-contract=off.
 #include <cmath>
@@ -654,7 +662,7 @@ __global__ __launch_bounds__(L0X* L0Y) void k_l0(L0 a, float* out, const float* 
         if ((lx & 1) == 0) rb[pb][ly][lx >> 1] = v2;
         acc = 0.0f;
         __syncthreads();
-        if (lx < 32 && ly < 2) {
+        if (lx < 32 && ly < L0Y / 2) {
           const int I = bx * (L0X / 2) + lx, J = by * (L0Y / 2) + ly, K = k >> 1;
           if (I < a.cnx && J < a.cny)
             out[((long long)K * a.cny + J) * a.cnx + I] = rb[pb][2 * ly][lx] + rb[pb][2 * ly + 1][lx];
@@ -736,7 +744,7 @@ __device__ __forceinline__ float4 f4(float v) { return make_float4(v, v, v, v); 
 __device__ __forceinline__ float comp(const float4& v, int e) { return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w; }
 
 template <bool UP>
-__global__ __launch_bounds__(256) void k_l0_x4(L0 a, float* out, const float* __restrict__ q,
+__global__ __launch_bounds__(L0X* L0Y) void k_l0_x4(L0 a, float* out, const float* __restrict__ q,
                                                double* __restrict__ part, const SolveScalars* sc) {
   if (solve_done(sc)) return;
   constexpr int W = 4 * L0X;   // cells of a tile row
@@ -860,7 +868,7 @@ __global__ __launch_bounds__(256) void k_l0_x4(L0 a, float* out, const float* __
         rb[pb][ly][2 * lx + 1] = acc1;
         acc0 = acc1 = 0.0f;
         __syncthreads();
-        if (ly < 2) {
+        if (ly < L0Y / 2) {
           const int I = bx * (W / 2) + 2 * lx, J = by * (L0Y / 2) + ly, K = k >> 1;
           if (I < a.cnx && J < a.cny) {
             const long long o = ((long long)K * a.cny + J) * a.cnx + I;
@@ -879,7 +887,7 @@ __global__ __launch_bounds__(256) void k_l0_x4(L0 a, float* out, const float* __
     f = fn;
   }
   if (UP && part) {
-    __shared__ double red[256 / 64];
+    __shared__ double red[L0X * L0Y / 64];
     const double t = block_sum(dot, red);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
   }

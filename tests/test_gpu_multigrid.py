@@ -148,3 +148,24 @@ def test_full_size_breaking_wave_projection_with_multigrid():
     assert res.status == 0 and res.relres <= 1e-8 and not res.fallback
     assert res.iterations < 400, res.iterations
     assert solvers.true_relres(oop, ob_rhs, host(x)) <= 1.01e-8
+
+
+@pytest.mark.parametrize("shape,body,bc", [((3, 2, 2), "none", (0, 0, 0, 0, 0, 1)), ((5, 4, 3), "none", (0,) * 6),
+                                           ((9, 7, 6), "sphere", (0,) * 6), ((12, 8, 8), "sphere", (0, 0, 0, 0, 0, 1))])
+def test_tiny_grids_solve_with_one_coarsening(shape, body, bc):
+    """Grids small enough that level 1 is already the coarsest (dense) level,
+    odd sizes and the one-cell-per-lane level-0 sweeps: the multigrid solve
+    meets its tolerance and the oracle's solution."""
+    wl = fx.small(9, *shape, body=body, bc=bc)
+    og, ob, oop, b = oracle_for(wl)
+    H = multigrid.Hierarchy(oop)
+    g, op = gpu_for(wl)
+    mg = op.multigrid()
+    assert [tuple(s) for s in mg.levels()] == [tuple(s) for s in H.shapes]
+    x, res = op.solve(torch.as_tensor(b, device="cuda"), tol=1e-10, precision="mixed", precond="mg")
+    assert res.status == 0 and res.relres <= 1e-10
+    ref = solvers.pcg(oop, b, tol=1e-12)
+    xs, xr = host(x), ref.x
+    if og.all_neumann:
+        xs, xr = oop.gauge(xs), oop.gauge(xr)
+    assert rel_l2(xs, xr) <= 1e-7
