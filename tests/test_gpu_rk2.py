@@ -50,7 +50,8 @@ def test_velocity_update_bitwise(bc):
             assert np.array_equal(host(g), r)
 
 
-def test_cycle_matches_oracle():
+@pytest.mark.parametrize("precision,precond", [("f64", "jacobi"), ("mixed", "mg")])
+def test_cycle_matches_oracle(precision, precond):
     wl = fx.small(3, 36, 20, 16, body="sphere")       # all-Neumann, moving sphere
     og, ob, _, _ = oracle_for(wl)
     phi_s = np.roll(wl.phi, 1, axis=2)
@@ -60,8 +61,9 @@ def test_cycle_matches_oracle():
     ref = rk2.cycle(og, ob, wl.phi, phi_s, uk, R, dt, wl.body_vel, tol=1e-12)
     gg, gop = gpu_for(wl)
     out = gop.rk2_cycle(_t(wl.phi), _t(phi_s), tuple(_t(a) for a in uk), tuple(_t(a) for a in R), dt,
-                        wl.body_vel, tol=1e-10, precision="f64")
+                        wl.body_vel, tol=1e-10, precision=precision, precond=precond)
     assert out["status"] == 0 and out["stage1"].relres <= 1e-10 and out["stage2"].relres <= 1e-10
+    assert not out["stage1"].fallback and not out["stage2"].fallback
     assert rel_l2(host(out["pstar"]), ref["p1"]) <= 1e-8
     assert rel_l2(host(out["p"]), ref["p2"]) <= 1e-8
     for name, rname in (("ustar", "us"), ("unext", "un")):
