@@ -65,6 +65,7 @@ typedef void* nfa_stream; /* hipStream_t */
 /* element types */
 #define NFA_F64 0
 #define NFA_F32 1
+#define NFA_BF16 2
 
 /* Thread-local message of the last failing call (empty if none). */
 const char* nfa_last_error(void);
@@ -307,6 +308,12 @@ nfa_status nfa_mg_info(nfa_mg mg, int* levels, int* dims);
  * (0 < alpha < 2, default 1; any such alpha keeps the cycle symmetric
  * positive definite).  Errors: NFA_ERR_INVALID. */
 nfa_status nfa_mg_set_params(nfa_mg mg, double omega, double alpha);
+/* nfa_mg_set_coef -- the precision in which the cycle's level-0 sweeps read
+ * the face coefficients and D^-1: NFA_F32 (the operator's FP32 copies) or
+ * NFA_BF16 (those rounded to BF16, nearest even; made at set-up, half the
+ * bytes).  The operator of the CG itself is unaffected.  Takes effect at the
+ * next set-up.  Errors: NFA_ERR_INVALID. */
+nfa_status nfa_mg_set_coef(nfa_mg mg, int dtype);
 /* nfa_mg_side_rows -- rows of level >= 1 (below the coarsest) held in the
  * side list by the last set-up (couplings beyond the 7 points). */
 nfa_status nfa_mg_side_rows(nfa_mg mg, int level, int* rows);

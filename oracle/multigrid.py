@@ -25,7 +25,13 @@ side r,
 with D the diagonal (rows without an unknown get z = 0) and alpha the scale
 of the coarse correction (1: the plain cycle; 0 < alpha < 2 keeps the cycle
 symmetric positive definite, since the coarse step then contracts in the
-energy norm).  The coarsest level
+energy norm).
+
+With coef="bf16" the cycle's level 0 applies the operator assembled from
+the face coefficients rounded to FP32 and then to BF16 (nearest even), and
+smooths with D^-1 rounded the same way; level 1 is still the Galerkin
+product of the exact operator.  The cycle stays symmetric (each face keeps
+one coefficient).  The coarsest level
 is solved exactly: empty rows become identity rows and, when every boundary
 is Neumann, c v v^T is added (v the indicator of the non-empty rows, c their
 mean diagonal), which leaves A x = b for every compatible b.
@@ -61,10 +67,18 @@ def _drop_far(A, shape):
     return sp.csr_matrix((A.data[near], (A.row[near], A.col[near])), shape=A.shape), int(np.count_nonzero(~near))
 
 
+def bf16(x):
+    """Round to FP32, then to the nearest BF16 (ties to even); float64 values."""
+    x32 = np.asarray(x, dtype=np.float32)
+    u = x32.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
 class Hierarchy:
     """Operators, shapes and aggregation maps of every level."""
 
-    def __init__(self, op, min_coarse=MIN_COARSE, omega=OMEGA, alpha=ALPHA):
+    def __init__(self, op, min_coarse=MIN_COARSE, omega=OMEGA, alpha=ALPHA, coef="f64"):
         self.op = op
         self.omega = omega
         self.alpha = alpha
@@ -91,6 +105,12 @@ class Hierarchy:
         self.diag = [a.diagonal() for a in self.A]
         self.dinv = [np.where(d > 0, 1.0 / np.where(d > 0, d, 1.0), 0.0) for d in self.diag]
         self.coarse_inv = self._coarsest(g.all_neumann)
+        if coef == "bf16":
+            # the cycle's level 0 (the coarse levels above were built exactly)
+            self.A[0] = op.csr(coeffs=(bf16(op.tx), bf16(op.ty), bf16(op.tz)))
+            self.dinv[0] = bf16(op.dinv).reshape(-1)
+        elif coef != "f64":
+            raise ValueError("coef must be 'f64' or 'bf16'")
 
     def _coarsest(self, singular):
         A = self.A[-1].toarray()

@@ -177,12 +177,14 @@ class Operator:
         return dinv
 
     # --------------------------------------------------------------- sparse
-    def csr(self):
+    def csr(self, coeffs=None):
         """A' as a scipy CSR matrix over the cell index (rows/cols of slaves and
-        inactive cells are empty), assembled from the face list."""
+        inactive cells are empty), assembled from the face list; `coeffs`
+        (tx, ty, tz) replaces the operator's face coefficients."""
         g = self.grid
         nz, ny, nx = g.shape
         idx = np.arange(g.n).reshape(g.shape)
+        tx, ty, tz = (self.tx, self.ty, self.tz) if coeffs is None else coeffs
         rows, cols, vals = [], [], []
 
         def couple(t, a, b):
@@ -192,12 +194,12 @@ class Operator:
             cols.extend([a, b, b, a])
             vals.extend([t, t, -t, -t])
 
-        couple(self.tx[:, :, 1:-1].ravel(), idx[:, :, :-1].ravel(), idx[:, :, 1:].ravel())
-        couple(self.ty[:, 1:-1, :].ravel(), idx[:, :-1, :].ravel(), idx[:, 1:, :].ravel())
-        couple(self.tz[1:-1].ravel(), idx[:-1].ravel(), idx[1:].ravel())
-        for t, cells in ((self.tx[:, :, 0], idx[:, :, 0]), (self.tx[:, :, -1], idx[:, :, -1]),
-                         (self.ty[:, 0, :], idx[:, 0, :]), (self.ty[:, -1, :], idx[:, -1, :]),
-                         (self.tz[0], idx[0]), (self.tz[-1], idx[-1])):
+        couple(tx[:, :, 1:-1].ravel(), idx[:, :, :-1].ravel(), idx[:, :, 1:].ravel())
+        couple(ty[:, 1:-1, :].ravel(), idx[:, :-1, :].ravel(), idx[:, 1:, :].ravel())
+        couple(tz[1:-1].ravel(), idx[:-1].ravel(), idx[1:].ravel())
+        for t, cells in ((tx[:, :, 0], idx[:, :, 0]), (tx[:, :, -1], idx[:, :, -1]),
+                         (ty[:, 0, :], idx[:, 0, :]), (ty[:, -1, :], idx[:, -1, :]),
+                         (tz[0], idx[0]), (tz[-1], idx[-1])):
             t, cells = t.ravel(), cells.ravel()
             m = t != 0
             rows.append(cells[m])

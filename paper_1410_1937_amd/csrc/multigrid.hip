@@ -82,6 +82,14 @@ Dims coarser(const Dims& d) { return make_dims((d.nx + 1) / 2, (d.ny + 1) / 2, (
 #define MG_STRIDE(idx, n) \
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < (n); idx += (long long)gridDim.x * blockDim.x)
 
+// FP32 -> BF16, round to nearest even (the upper 16 bits of the rounded value).
+__global__ void k_to_bf16(long long n, const float* __restrict__ src, unsigned short* __restrict__ dst) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const unsigned u = __float_as_uint(src[i]);
+    dst[i] = (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+  }
+}
+
 __global__ void k_fill_int(long long n, int v, int* a) {
   MG_STRIDE(i, n) a[i] = v;
 }
@@ -515,14 +523,27 @@ __global__ __launch_bounds__(256) void k_up(LevelView L, Cyc p, int tiles_x, int
 // next to a slave) are redone afterwards by the fix-up kernels with the
 // merged operator: slaves take their root's value, roots add their slaves'
 // rows.
+template <class C>
 struct L0 {
   int nx, ny, nz, kchunk, tiles_x, tiles_y;
-  const float *tx, *txb, *ty, *tz, *dinv, *r;
+  const C *tx, *txb, *ty, *tz, *dinv;   // coefficients: FP32, or their BF16 roundings
+  const float* r;
   const unsigned char* red;
   Cyc p;
   int cnx, cny;            // level 1
   const float* zc;         // level-1 correction (up)
 };
+
+// A coefficient as FP32: itself, or a BF16 (stored as its upper 16 bits).
+__device__ __forceinline__ float cf(float v) { return v; }
+__device__ __forceinline__ float cf(unsigned short h) { return __uint_as_float(((unsigned)h) << 16); }
+// Four consecutive coefficients (16- or 8-byte aligned).
+__device__ __forceinline__ float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+__device__ __forceinline__ float4 ld4(const unsigned short* p) {
+  const uint2 u = *reinterpret_cast<const uint2*>(p);
+  return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u), __uint_as_float(u.y << 16),
+                     __uint_as_float(u.y & 0xffff0000u));
+}
 
 constexpr int L0X = 64, L0Y = 4;
 
@@ -534,24 +555,24 @@ struct Raw {
   int m;
 };
 
-template <bool UP>
-__device__ __forceinline__ Raw l0_raw(const L0& a, long long c, int i, int j, int k) {
+template <bool UP, class C>
+__device__ __forceinline__ Raw l0_raw(const L0<C>& a, long long c, int i, int j, int k) {
   Raw w;
   w.r = a.r[c];
-  w.d = a.dinv[c];
+  w.d = cf(a.dinv[c]);
   w.m = a.red[c];
   w.z = UP ? a.zc[((long long)(k >> 1) * a.cny + (j >> 1)) * a.cnx + (i >> 1)] : 0.0f;
   return w;
 }
 
-template <bool UP>
-__device__ __forceinline__ float l0_val(const L0& a, const Raw& w) {
+template <bool UP, class C>
+__device__ __forceinline__ float l0_val(const L0<C>& a, const Raw& w) {
   const float v = a.p.w * (w.d * w.r);
   return UP && w.m ? v + a.p.a * w.z : v;
 }
 
-template <bool UP>
-__device__ __forceinline__ float l0_value(const L0& a, long long c, int i, int j, int k) {
+template <bool UP, class C>
+__device__ __forceinline__ float l0_value(const L0<C>& a, long long c, int i, int j, int k) {
   return l0_val<UP>(a, l0_raw<UP>(a, c, i, j, k));
 }
 
@@ -559,19 +580,20 @@ __device__ __forceinline__ float l0_value(const L0& a, long long c, int i, int j
 struct Faces {
   float txm, txp, tym, typ, tzp;
 };
-__device__ __forceinline__ Faces l0_faces(const L0& a, long long c, long long yi, int i, int j, int k) {
+template <class C>
+__device__ __forceinline__ Faces l0_faces(const L0<C>& a, long long c, long long yi, int i, int j, int k) {
   const long long plane = (long long)a.nx * a.ny;
   Faces f;
-  f.txm = a.tx[c];
-  f.txp = i < a.nx - 1 ? a.tx[c + 1] : a.txb[(long long)k * a.ny + j];
-  f.tym = a.ty[yi];
-  f.typ = a.ty[yi + a.nx];
-  f.tzp = a.tz[c + plane];
+  f.txm = cf(a.tx[c]);
+  f.txp = i < a.nx - 1 ? cf(a.tx[c + 1]) : cf(a.txb[(long long)k * a.ny + j]);
+  f.tym = cf(a.ty[yi]);
+  f.typ = cf(a.ty[yi + a.nx]);
+  f.tzp = cf(a.tz[c + plane]);
   return f;
 }
 
-template <bool UP>
-__global__ __launch_bounds__(L0X* L0Y) void k_l0(L0 a, float* out, const float* __restrict__ q,
+template <bool UP, class C>
+__global__ __launch_bounds__(L0X* L0Y) void k_l0(L0<C> a, float* out, const float* __restrict__ q,
                                                 double* __restrict__ part, const SolveScalars* sc) {
   if (solve_done(sc)) return;
   __shared__ float pl[2][L0Y + 2][L0X + 2];
@@ -616,7 +638,7 @@ __global__ __launch_bounds__(L0X* L0Y) void k_l0(L0 a, float* out, const float* 
       if (k0 > 0) vm = l0_value<UP>(a, c - plane, i, j, k0 - 1);
       cur = l0_raw<UP>(a, c, i, j, k0);
       if (k0 + 1 < a.nz) nxt = l0_raw<UP>(a, c + plane, i, j, k0 + 1);
-      tzm = a.tz[c];
+      tzm = cf(a.tz[c]);
       f = l0_faces(a, c, yi, i, j, k0);
     }
     if (halo_in) hcur = l0_raw<UP>(a, (long long)k0 * plane + hc0, hi, hj, k0);
@@ -692,11 +714,11 @@ struct Raw4 {
   uchar4 m;
 };
 
-template <bool UP>
-__device__ __forceinline__ Raw4 l0_raw4(const L0& a, long long c, int i0, int j, int k) {
+template <bool UP, class C>
+__device__ __forceinline__ Raw4 l0_raw4(const L0<C>& a, long long c, int i0, int j, int k) {
   Raw4 w;
   w.r = *reinterpret_cast<const float4*>(a.r + c);
-  w.d = *reinterpret_cast<const float4*>(a.dinv + c);
+  w.d = ld4(a.dinv + c);
   w.m = *reinterpret_cast<const uchar4*>(a.red + c);
   if (UP) {
     const float2 zz =
@@ -708,8 +730,8 @@ __device__ __forceinline__ Raw4 l0_raw4(const L0& a, long long c, int i0, int j,
   return w;
 }
 
-template <bool UP>
-__device__ __forceinline__ float4 l0_val4(const L0& a, const Raw4& w) {
+template <bool UP, class C>
+__device__ __forceinline__ float4 l0_val4(const L0<C>& a, const Raw4& w) {
   float4 v = make_float4(a.p.w * (w.d.x * w.r.x), a.p.w * (w.d.y * w.r.y), a.p.w * (w.d.z * w.r.z),
                          a.p.w * (w.d.w * w.r.w));
   if (UP) {
@@ -725,26 +747,27 @@ struct Faces4 {
   float4 txm, tym, typ, tzp;
   float tx4;   // the +x face of the last cell
 };
-__device__ __forceinline__ Faces4 l0_faces4(const L0& a, long long c, long long yi, int i0, int j, int k) {
+template <class C>
+__device__ __forceinline__ Faces4 l0_faces4(const L0<C>& a, long long c, long long yi, int i0, int j, int k) {
   const long long plane = (long long)a.nx * a.ny;
   Faces4 f;
-  f.txm = *reinterpret_cast<const float4*>(a.tx + c);
+  f.txm = ld4(a.tx + c);
   const bool last = i0 + 4 >= a.nx;
-  const float t4 = a.tx[last ? c : c + 4];
-  const float tb = a.txb[(long long)k * a.ny + j];
+  const float t4 = cf(a.tx[last ? c : c + 4]);
+  const float tb = cf(a.txb[(long long)k * a.ny + j]);
   const float ml = last ? 1.0f : 0.0f;
   f.tx4 = t4 * (1.0f - ml) + tb * ml;
-  f.tym = *reinterpret_cast<const float4*>(a.ty + yi);
-  f.typ = *reinterpret_cast<const float4*>(a.ty + yi + a.nx);
-  f.tzp = *reinterpret_cast<const float4*>(a.tz + c + plane);
+  f.tym = ld4(a.ty + yi);
+  f.typ = ld4(a.ty + yi + a.nx);
+  f.tzp = ld4(a.tz + c + plane);
   return f;
 }
 
 __device__ __forceinline__ float4 f4(float v) { return make_float4(v, v, v, v); }
 __device__ __forceinline__ float comp(const float4& v, int e) { return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w; }
 
-template <bool UP>
-__global__ __launch_bounds__(L0X* L0Y) void k_l0_x4(L0 a, float* out, const float* __restrict__ q,
+template <bool UP, class C>
+__global__ __launch_bounds__(L0X* L0Y) void k_l0_x4(L0<C> a, float* out, const float* __restrict__ q,
                                                double* __restrict__ part, const SolveScalars* sc) {
   if (solve_done(sc)) return;
   constexpr int W = 4 * L0X;   // cells of a tile row
@@ -792,7 +815,7 @@ __global__ __launch_bounds__(L0X* L0Y) void k_l0_x4(L0 a, float* out, const floa
       if (k0 > 0) vm = l0_val4<UP>(a, l0_raw4<UP>(a, c - plane, i0, j, k0 - 1));
       cur = l0_raw4<UP>(a, c, i0, j, k0);
       if (k0 + 1 < a.nz) nxt = l0_raw4<UP>(a, c + plane, i0, j, k0 + 1);
-      tzm = *reinterpret_cast<const float4*>(a.tz + c);
+      tzm = ld4(a.tz + c);
       f = l0_faces4(a, c, yi, i0, j, k0);
     }
     if (halo_in) {
@@ -895,8 +918,8 @@ __global__ __launch_bounds__(L0X* L0Y) void k_l0_x4(L0 a, float* out, const floa
 
 // Row c of the 7-point operator applied to a cell function f (0 beyond the
 // domain), in the sweep's face order.
-template <class F>
-__device__ __forceinline__ float l0_row(const L0& a, long long c, F f) {
+template <class C, class F>
+__device__ __forceinline__ float l0_row(const L0<C>& a, long long c, F f) {
   const long long plane = (long long)a.nx * a.ny;
   const int i = (int)(c % a.nx), j = (int)((c / a.nx) % a.ny), k = (int)(c / plane);
   const long long yi = ((long long)k * (a.ny + 1) + j) * a.nx + i;
@@ -908,9 +931,10 @@ __device__ __forceinline__ float l0_row(const L0& a, long long c, F f) {
 #pragma unroll
   for (int d = 0; d < 6; ++d) fv[d] = f(ok[d] ? c + off[d] : c) * (ok[d] ? 1.0f : 0.0f);
   const float m1 = ok[1] ? 1.0f : 0.0f;
-  const float tb = a.txb[(long long)k * a.ny + j];
-  const float txp = a.tx[ok[1] ? c + 1 : c];
-  const float T[6] = {a.tx[c], txp * m1 + tb * (1.0f - m1), a.ty[yi], a.ty[yi + a.nx], a.tz[c], a.tz[c + plane]};
+  const float tb = cf(a.txb[(long long)k * a.ny + j]);
+  const float txp = cf(a.tx[ok[1] ? c + 1 : c]);
+  const float T[6] = {cf(a.tx[c]), txp * m1 + tb * (1.0f - m1), cf(a.ty[yi]), cf(a.ty[yi + a.nx]), cf(a.tz[c]),
+                      cf(a.tz[c + plane])};
   const float fc = f(c);
   float q = T[0] * (fc - fv[0]);
 #pragma unroll
@@ -923,7 +947,8 @@ __device__ __forceinline__ float l0_row(const L0& a, long long c, F f) {
 // differ, each by T_f z(root of the slave); an entry -(s+1) (a slave whose
 // root lies in the entry's level-1 cell) owes -q_s, the slave's row with
 // merged values.
-__global__ void k_l0_fix_terms(L0 a, int nent, const int* __restrict__ ent, const int* __restrict__ root,
+template <class C>
+__global__ void k_l0_fix_terms(L0<C> a, int nent, const int* __restrict__ ent, const int* __restrict__ root,
                                float* term, const SolveScalars* sc) {
   if (solve_done(sc)) return;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -936,9 +961,10 @@ __global__ void k_l0_fix_terms(L0 a, int nent, const int* __restrict__ ent, cons
   const bool ok[6] = {i > 0, i < a.nx - 1, j > 0, j < a.ny - 1, k > 0, k < a.nz - 1};
   const long long off[6] = {-1, 1, -a.nx, a.nx, -plane, plane};
   const float m1 = ok[1] ? 1.0f : 0.0f;
-  const float tb = a.txb[(long long)k * a.ny + j];
-  const float txp = a.tx[ok[1] ? c + 1 : c];
-  const float T[6] = {a.tx[c], txp * m1 + tb * (1.0f - m1), a.ty[yi], a.ty[yi + a.nx], a.tz[c], a.tz[c + plane]};
+  const float tb = cf(a.txb[(long long)k * a.ny + j]);
+  const float txp = cf(a.tx[ok[1] ? c + 1 : c]);
+  const float T[6] = {cf(a.tx[c]), txp * m1 + tb * (1.0f - m1), cf(a.ty[yi]), cf(a.ty[yi + a.nx]), cf(a.tz[c]),
+                      cf(a.tz[c + plane])};
   // roots of the neighbours, then the smoothed values of the roots, each
   // batch loaded unconditionally; a neighbour beyond the domain reads the
   // cell itself, an inactive one (root -1) reads cell 0, and both are
@@ -956,7 +982,7 @@ __global__ void k_l0_fix_terms(L0 a, int nent, const int* __restrict__ ent, cons
   for (int f = 0; f < 6; ++f) {
     const float m = ok[f] && rt[f] >= 0 ? 1.0f : 0.0f;
     const int x = rt[f] < 0 ? 0 : rt[f];
-    zr[f] = a.p.w * (a.dinv[x] * a.r[x]) * m;
+    zr[f] = a.p.w * (cf(a.dinv[x]) * a.r[x]) * m;
     slave[f] = ok[f] && rt[f] >= 0 && rt[f] != nb[f] ? 1.0f : 0.0f;
   }
   float t = 0.0f;
@@ -965,7 +991,7 @@ __global__ void k_l0_fix_terms(L0 a, int nent, const int* __restrict__ ent, cons
     for (int f = 0; f < 6; ++f) t += T[f] * zr[f] * slave[f];
   } else {
     const int x = rs < 0 ? 0 : rs;
-    const float zs = a.p.w * (a.dinv[x] * a.r[x]) * (rs < 0 ? 0.0f : 1.0f);
+    const float zs = a.p.w * (cf(a.dinv[x]) * a.r[x]) * (rs < 0 ? 0.0f : 1.0f);
     float q = T[0] * (zs - zr[0]);
 #pragma unroll
     for (int f = 1; f < 6; ++f) q = q + T[f] * (zs - zr[f]);
@@ -987,7 +1013,8 @@ __global__ void k_l0_fix_sum(int nblk, const int* __restrict__ blk, const int* _
 
 // Up fix-up, step 1: each slave's z slot takes its root's zp (the value the
 // merged operator gives it; the up sweep left 0 there).
-__global__ void k_l0_slave_zp(L0 a, int ns, const int* __restrict__ s_cell, const int* __restrict__ s_root, float* z,
+template <class C>
+__global__ void k_l0_slave_zp(L0<C> a, int ns, const int* __restrict__ s_cell, const int* __restrict__ s_root, float* z,
                               const SolveScalars* sc) {
   if (solve_done(sc)) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1002,7 +1029,8 @@ __global__ void k_l0_slave_zp(L0 a, int ns, const int* __restrict__ s_cell, cons
 // without its slaves' rows; with the merged operator q' = q^ - sum over the
 // row's faces to slaves of T_f z(slave) (+ the slaves' rows for a root), so
 // z -= omega D^-1 (q' - q^).  Slaves' values are their z slots (step 1).
-__global__ __launch_bounds__(256) void k_l0_up_fix(L0 a, int nrow, const int* __restrict__ rows,
+template <class C>
+__global__ __launch_bounds__(256) void k_l0_up_fix(L0<C> a, int nrow, const int* __restrict__ rows,
                                                    const int* __restrict__ root, const int* __restrict__ group_of,
                                                    const int* __restrict__ g_off, const int* __restrict__ g_mem, float* z,
                                                    const float* __restrict__ qv, double* __restrict__ part,
@@ -1027,9 +1055,10 @@ __global__ __launch_bounds__(256) void k_l0_up_fix(L0 a, int nrow, const int* __
     const bool ok[6] = {i > 0, i < a.nx - 1, j > 0, j < a.ny - 1, k > 0, k < a.nz - 1};
     const long long off[6] = {-1, 1, -a.nx, a.nx, -plane, plane};
     const float m1 = ok[1] ? 1.0f : 0.0f;
-    const float tb = a.txb[(long long)k * a.ny + j];
-    const float txp = a.tx[ok[1] ? c + 1 : c];
-    const float T[6] = {a.tx[c], txp * m1 + tb * (1.0f - m1), a.ty[yi], a.ty[yi + a.nx], a.tz[c], a.tz[c + plane]};
+    const float tb = cf(a.txb[(long long)k * a.ny + j]);
+    const float txp = cf(a.tx[ok[1] ? c + 1 : c]);
+    const float T[6] = {cf(a.tx[c]), txp * m1 + tb * (1.0f - m1), cf(a.ty[yi]), cf(a.ty[yi + a.nx]), cf(a.tz[c]),
+                        cf(a.tz[c + plane])};
     // faces to slaves: all loads issued together, a face masked by a product
     float dq = 0.0f;
 #pragma unroll
@@ -1045,7 +1074,7 @@ __global__ __launch_bounds__(256) void k_l0_up_fix(L0 a, int nrow, const int* __
     if (gi >= 0)
       for (int m = g_off[gi]; m < g_off[gi + 1]; ++m) dq = dq + l0_row(a, g_mem[m], zp);
     const float zold = z[c];
-    const float znew = zold - a.p.w * (a.dinv[c] * dq);
+    const float znew = zold - a.p.w * (cf(a.dinv[c]) * dq);
     z[c] = znew;
     // the up sweep summed zold . q for this row; the z.q partial takes the difference
     if (part) dd = ((double)znew - (double)zold) * (double)qv[c];
@@ -1192,6 +1221,8 @@ struct nfa_mg_s {
   int L = 0;                    // levels including level 0
   Level lv[kMaxLevels];         // lv[0]: dims only
   DevBuf group_of, minv, xcnt;
+  DevBuf tx16, txb16, ty16, tz16, d16;   // level-0 coefficients and D^-1 rounded to BF16
+  bool coef16 = false;          // the cycle's level 0 reads the BF16 copies
   DevBuf fblk, foff, fent, fterm;   // level-0 down fix-up: level-1 cells, CSR offsets, entries, terms
   int nfblk = 0, nfent = 0;
   int body_version = -1;        // grid body the fix-up lists belong to
@@ -1280,6 +1311,15 @@ nfa_status mg_setup(nfa_mg_s& mg, hipStream_t st) {
     const nfa_status e = build_side_list(mg, mg.lv[l], st);
     if (e != NFA_OK) return e;
   }
+  if (mg.coef16) {
+    const Coeffs<float> c32 = op.c32();
+    const float* src[5] = {c32.tx, c32.txb, c32.ty, c32.tz, c32.dinv};
+    DevBuf* dst[5] = {&mg.tx16, &mg.txb16, &mg.ty16, &mg.tz16, &mg.d16};
+    const long long cnt[5] = {g.n, (long long)g.nz * g.ny, g.nfy(), g.nfz(), g.n};
+    for (int t = 0; t < 5; ++t)
+      k_to_bf16<<<blocks_for(cnt[t]), kBlock, 0, st>>>(cnt[t], src[t], dst[t]->as<unsigned short>());
+    NFA_CHECK_LAUNCH();
+  }
   if (mg.body_version != g.body_version) {
     // level-0 down fix-up entries grouped by level-1 cell, in a fixed order:
     // the listed rows ascending, then the slaves by their root's cell
@@ -1358,6 +1398,48 @@ nfa_status mg_setup(nfa_mg_s& mg, hipStream_t st) {
   return NFA_OK;
 }
 
+// Level 0 of the cycle, down: the fused sweep and the merged rows' fix-up.
+template <class C>
+void l0_down(nfa_mg_s& mg, const L0<C>& a, bool x4, int nb0, const SolveScalars* sc, hipStream_t st) {
+  Poisson& op = *mg.op;
+  Grid& g = *op.g;
+  const bool rec = prof_begin(op, st);
+  if (x4)
+    k_l0_x4<false, C><<<nb0, L0X * L0Y, 0, st>>>(a, mg.lv[1].r.as<float>(), nullptr, nullptr, sc);
+  else
+    k_l0<false, C><<<nb0, L0X * L0Y, 0, st>>>(a, mg.lv[1].r.as<float>(), nullptr, nullptr, sc);
+  prof_end(op, rec, kProfMgDown, st);
+  if (mg.nfblk > 0) {
+    k_l0_fix_terms<C><<<(mg.nfent + 255) / 256, 256, 0, st>>>(a, mg.nfent, mg.fent.as<int>(), g.root.as<int>(),
+                                                              mg.fterm.as<float>(), sc);
+    k_l0_fix_sum<<<(mg.nfblk + 255) / 256, 256, 0, st>>>(mg.nfblk, mg.fblk.as<int>(), mg.foff.as<int>(),
+                                                         mg.fterm.as<float>(), mg.lv[1].r.as<float>(), sc);
+  }
+}
+
+// Level 0 of the cycle, up: the fused sweep (with the z.q partials when
+// parts is given, nb0 of them, the fix-up's after them) and the fix-ups.
+template <class C>
+void l0_up(nfa_mg_s& mg, const L0<C>& a, bool x4, int nb0, float* z0, const float* qdot, double* parts,
+           const SolveScalars* sc, hipStream_t st) {
+  Poisson& op = *mg.op;
+  Grid& g = *op.g;
+  const bool rec = prof_begin(op, st);
+  if (x4)
+    k_l0_x4<true, C><<<nb0, L0X * L0Y, 0, st>>>(a, z0, qdot, parts, sc);
+  else
+    k_l0<true, C><<<nb0, L0X * L0Y, 0, st>>>(a, z0, qdot, parts, sc);
+  prof_end(op, rec, kProfMgUp, st);
+  const int nfix = (int)g.h_fix.size();
+  if (g.n_slaves > 0)
+    k_l0_slave_zp<C><<<(g.n_slaves + 255) / 256, 256, 0, st>>>(a, g.n_slaves, g.s_cell.as<int>(),
+                                                               g.s_root.as<int>(), z0, sc);
+  if (nfix > 0)
+    k_l0_up_fix<C><<<(nfix + 255) / 256, 256, 0, st>>>(a, nfix, g.fix_rows.as<int>(), g.root.as<int>(),
+                                                        mg.group_of.as<int>(), g.g_off.as<int>(), g.g_mem.as<int>(),
+                                                        z0, qdot, parts ? parts + nb0 : nullptr, sc);
+}
+
 // One V-cycle: z = M r on the reduced unknowns of level 0 (FP32).
 nfa_status mg_vcycle(nfa_mg_s& mg, const float* r0, float* z0, const float* qdot, double* parts, int* np,
                      const SolveScalars* sc, hipStream_t st) {
@@ -1377,28 +1459,20 @@ nfa_status mg_vcycle(nfa_mg_s& mg, const float* r0, float* z0, const float* qdot
   // 4 cells per lane when rows and every per-cell array allow 16-byte loads
   const bool x4 = d0.nx % 4 == 0 && ((uintptr_t)r0 % 16) == 0 && ((uintptr_t)z0 % 16) == 0;
   const int tw = x4 ? 4 * L0X : L0X;
-  L0 a{d0.nx, d0.ny, d0.nz, 16, (d0.nx + tw - 1) / tw, (d0.ny + L0Y - 1) / L0Y, c32.tx, c32.txb, c32.ty, c32.tz,
-       c32.dinv, r0, red, p, C1.nx, C1.ny, nullptr};
-  const int nb0 = a.tiles_x * a.tiles_y * ((d0.nz + a.kchunk - 1) / a.kchunk);
+  L0<float> a32{d0.nx, d0.ny, d0.nz, 16, (d0.nx + tw - 1) / tw, (d0.ny + L0Y - 1) / L0Y, c32.tx, c32.txb, c32.ty,
+                c32.tz, c32.dinv, r0, red, p, C1.nx, C1.ny, nullptr};
+  L0<unsigned short> a16{d0.nx, d0.ny, d0.nz, 16, a32.tiles_x, a32.tiles_y, mg.tx16.as<unsigned short>(),
+                         mg.txb16.as<unsigned short>(), mg.ty16.as<unsigned short>(), mg.tz16.as<unsigned short>(),
+                         mg.d16.as<unsigned short>(), r0, red, p, C1.nx, C1.ny, nullptr};
+  const int nb0 = a32.tiles_x * a32.tiles_y * ((d0.nz + a32.kchunk - 1) / a32.kchunk);
   // z.q of the flexible direction summed by the up sweep and the up fix-up
   const int nfix_blocks = ((int)g.h_fix.size() + 255) / 256;
   const bool dot = qdot && parts && nb0 + nfix_blocks <= kMaxPartials;
   if (np) *np = 0;
-  // level 0, down
-  {
-    const bool rec = prof_begin(op, st);
-    if (x4)
-      k_l0_x4<false><<<nb0, L0X * L0Y, 0, st>>>(a, mg.lv[1].r.as<float>(), nullptr, nullptr, sc);
-    else
-      k_l0<false><<<nb0, L0X * L0Y, 0, st>>>(a, mg.lv[1].r.as<float>(), nullptr, nullptr, sc);
-    prof_end(op, rec, kProfMgDown, st);
-    if (mg.nfblk > 0) {
-      k_l0_fix_terms<<<(mg.nfent + 255) / 256, 256, 0, st>>>(a, mg.nfent, mg.fent.as<int>(), g.root.as<int>(),
-                                                             mg.fterm.as<float>(), sc);
-      k_l0_fix_sum<<<(mg.nfblk + 255) / 256, 256, 0, st>>>(mg.nfblk, mg.fblk.as<int>(), mg.foff.as<int>(),
-                                                           mg.fterm.as<float>(), mg.lv[1].r.as<float>(), sc);
-    }
-  }
+  if (mg.coef16)
+    l0_down(mg, a16, x4, nb0, sc, st);
+  else
+    l0_down(mg, a32, x4, nb0, sc, st);
   // grid-wide levels, down
   const int T = mg.first_tail;
   for (int l = 1; l < T; ++l) {
@@ -1432,24 +1506,13 @@ nfa_status mg_vcycle(nfa_mg_s& mg, const float* r0, float* z0, const float* qdot
                              mg.lv[l + 1].zt.as<float>(), mg.lv[l].zt.as<float>(), sc);
   }
   // level 0, up
-  {
-    a.zc = mg.lv[1].zt.as<float>();
-    const bool rec = prof_begin(op, st);
-    if (x4)
-      k_l0_x4<true><<<nb0, L0X * L0Y, 0, st>>>(a, z0, qdot, dot ? parts : nullptr, sc);
-    else
-      k_l0<true><<<nb0, L0X * L0Y, 0, st>>>(a, z0, qdot, dot ? parts : nullptr, sc);
-    prof_end(op, rec, kProfMgUp, st);
-    const int nfix = (int)g.h_fix.size();
-    if (g.n_slaves > 0)
-      k_l0_slave_zp<<<(g.n_slaves + 255) / 256, 256, 0, st>>>(a, g.n_slaves, g.s_cell.as<int>(), g.s_root.as<int>(),
-                                                              z0, sc);
-    const int nfb = (nfix + 255) / 256;
-    if (nfix > 0)
-      k_l0_up_fix<<<nfb, 256, 0, st>>>(a, nfix, g.fix_rows.as<int>(), g.root.as<int>(), mg.group_of.as<int>(),
-                                       g.g_off.as<int>(), g.g_mem.as<int>(), z0, qdot, dot ? parts + nb0 : nullptr, sc);
-    if (np) *np = dot ? nb0 + (nfix > 0 ? nfb : 0) : 0;
-  }
+  a32.zc = a16.zc = mg.lv[1].zt.as<float>();
+  const int nfix = (int)g.h_fix.size();
+  if (mg.coef16)
+    l0_up(mg, a16, x4, nb0, z0, qdot, dot ? parts : nullptr, sc, st);
+  else
+    l0_up(mg, a32, x4, nb0, z0, qdot, dot ? parts : nullptr, sc, st);
+  if (np) *np = dot ? nb0 + (nfix > 0 ? (nfix + 255) / 256 : 0) : 0;
   NFA_CHECK_LAUNCH();
   return NFA_OK;
 }
@@ -1495,6 +1558,10 @@ extern "C" nfa_status nfa_mg_create(nfa_poisson op, nfa_mg* out) {
     return fail(NFA_ERR_INVALID, "nfa_mg_create: the grid has a single cell");
   }
   hipError_t e;
+  if ((e = mg->tx16.alloc(g.n * 2)) != hipSuccess || (e = mg->txb16.alloc((size_t)g.nz * g.ny * 2)) != hipSuccess ||
+      (e = mg->ty16.alloc(g.nfy() * 2)) != hipSuccess || (e = mg->tz16.alloc(g.nfz() * 2)) != hipSuccess ||
+      (e = mg->d16.alloc(g.n * 2)) != hipSuccess)
+    return bad(e);
   if ((e = mg->group_of.alloc(g.n * 4)) != hipSuccess ||
       (e = mg->xcnt.alloc(2 * ((mg->lv[1].d.n + kBlock - 1) / kBlock) * sizeof(int))) != hipSuccess)
     return bad(e);
@@ -1552,6 +1619,17 @@ extern "C" nfa_status nfa_mg_set_params(nfa_mg mg, double omega, double alpha) {
     return fail(NFA_ERR_INVALID, "nfa_mg_set_params: need 0 < omega < 1 and 0 < alpha < 2");
   mg->omega = omega;
   mg->alpha = alpha;
+  return NFA_OK;
+}
+
+extern "C" nfa_status nfa_mg_set_coef(nfa_mg mg, int dtype) {
+  if (!mg) return fail(NFA_ERR_INVALID, "nfa_mg_set_coef: NULL handle");
+  if (dtype != NFA_F32 && dtype != NFA_BF16) return fail(NFA_ERR_INVALID, "nfa_mg_set_coef: NFA_F32 or NFA_BF16");
+  const bool c16 = dtype == NFA_BF16;
+  if (c16 != mg->coef16) {
+    mg->coef16 = c16;
+    mg->built_version = -1;   // the BF16 copies are made by the next set-up
+  }
   return NFA_OK;
 }
 

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libnfa.so")
 
 NFA_OK = 0
 NFA_NOT_CONVERGED = 1
-NFA_F64, NFA_F32 = 0, 1
+NFA_F64, NFA_F32, NFA_BF16 = 0, 1, 2
 NFA_PROF_MG_DOWN, NFA_PROF_MG_UP = 2, 3
 NFA_PC_JACOBI, NFA_PC_UNET, NFA_PC_TEST_SABOTAGE, NFA_PC_JACOBI_FCG, NFA_PC_MG = 1, 2, 3, 4, 5
 NFA_PREC_F64, NFA_PREC_MIXED = 0, 1
@@ -134,6 +134,7 @@ _sig("nfa_mg_apply", c_int, [c_void_p, c_void_p, c_void_p, c_void_p])
 _sig("nfa_mg_info", c_int, [c_void_p, ctypes.POINTER(c_int), c_void_p])
 _sig("nfa_mg_set_tail", c_int, [c_void_p, c_int])
 _sig("nfa_mg_set_params", c_int, [c_void_p, c_double, c_double])
+_sig("nfa_mg_set_coef", c_int, [c_void_p, c_int])
 _sig("nfa_mg_side_rows", c_int, [c_void_p, c_int, ctypes.POINTER(c_int)])
 _sig("nfa_mg_export", c_int, [c_void_p, c_int, c_void_p, c_void_p])
 _sig("nfa_stretch_axis", c_int, [c_double, c_double, c_int, c_int, c_void_p, c_void_p, c_double, c_int, c_void_p,
@@ -298,6 +299,10 @@ class Multigrid:
     def set_params(self, omega=0.9, alpha=1.0):
         """Jacobi damping and coarse-correction scale of the V-cycle."""
         _check(lib.nfa_mg_set_params(self.h, float(omega), float(alpha)), "nfa_mg_set_params")
+
+    def set_coef(self, dtype):
+        """Precision of the level-0 coefficients the cycle reads: "f32" or "bf16"."""
+        _check(lib.nfa_mg_set_coef(self.h, {"f32": NFA_F32, "bf16": NFA_BF16}[dtype]), "nfa_mg_set_coef")
 
     def side_rows(self, level):
         """Rows of a level held in the side list (couplings beyond 7 points)."""

@@ -169,3 +169,36 @@ def test_tiny_grids_solve_with_one_coarsening(shape, body, bc):
     if og.all_neumann:
         xs, xr = oop.gauge(xs), oop.gauge(xr)
     assert rel_l2(xs, xr) <= 1e-7
+
+
+@pytest.mark.parametrize("tail", [-1, 0])
+@pytest.mark.parametrize("body,bc,shape", [CASES[0], CASES[1], ("sphere", (0,) * 6, (64, 48, 40))])
+def test_vcycle_with_bf16_coefficients_matches_the_oracle(body, bc, shape, tail):
+    """Level 0 of the cycle reading its coefficients and D^-1 in BF16: equal
+    to the oracle's cycle with the same roundings."""
+    wl = fx.small(6, *shape, body=body, bc=bc)
+    og, ob, oop, b = oracle_for(wl)
+    H = multigrid.Hierarchy(oop, coef="bf16")
+    g, op = gpu_for(wl)
+    mg = op.multigrid()
+    mg.set_tail(tail)
+    mg.set_coef("bf16")
+    mg.setup()
+    red = oop.reduced_mask() > 0
+    r = np.where(red, np.random.default_rng(2).standard_normal(og.shape), 0.0).astype(np.float32)
+    z = host(mg.apply(torch.as_tensor(r, device="cuda")))
+    ref = oop.expand(H.precond(r.astype(np.float64)))
+    keep = red | (ob.root.reshape(og.shape) >= 0)
+    assert rel_l2(z[keep], ref[keep]) <= 1e-4
+
+
+@pytest.mark.parametrize("coef", ["f32", "bf16"])
+def test_mg_solve_with_either_coefficient_precision(coef):
+    wl = fx.small(7, 64, 48, 40, body="sphere")
+    og, ob, oop, b = oracle_for(wl)
+    ref = solvers.pcg(oop, b, tol=1e-11)
+    g, op = gpu_for(wl)
+    op.multigrid().set_coef(coef)
+    x, res = op.solve(torch.as_tensor(b, device="cuda"), tol=1e-10, precision="mixed", precond="mg")
+    assert res.status == 0 and res.relres <= 1e-10 and not res.fallback
+    assert rel_l2(oop.gauge(host(x)), oop.gauge(ref.x)) <= 1e-7

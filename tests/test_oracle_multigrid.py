@@ -46,12 +46,12 @@ def test_constants_stay_in_the_null_space_of_every_level():
         assert np.max(rows) <= 1e-12 * np.max(np.abs(A.diagonal())), l
 
 
-@pytest.mark.parametrize("alpha", [1.0, 0.5, 1.9])
+@pytest.mark.parametrize("alpha,coef", [(1.0, "f64"), (0.5, "f64"), (1.9, "f64"), (1.0, "bf16")])
 @pytest.mark.parametrize("bc", [(0,) * 6, (0, 0, 0, 0, 0, 1)])
-def test_vcycle_is_symmetric_positive_definite(bc, alpha):
+def test_vcycle_is_symmetric_positive_definite(bc, alpha, coef):
     wl = fx.small(2, 12, 10, 8, body="sphere", bc=bc)
     og, ob, op, b = oracle_for(wl)
-    H = multigrid.Hierarchy(op, min_coarse=20, alpha=alpha)
+    H = multigrid.Hierarchy(op, min_coarse=20, alpha=alpha, coef=coef)
     red = np.nonzero(op.reduced_mask().reshape(-1))[0]
     n = op.grid.n
     M = np.zeros((len(red), len(red)))
@@ -110,3 +110,33 @@ def test_two_level_cycle_follows_its_error_propagation(alpha):
     r[red] = A @ x
     got = H.vcycle(r)[red]
     assert np.linalg.norm(got - (x - E @ x)) <= 1e-10 * np.linalg.norm(x)
+
+
+def test_bf16_rounding_is_nearest_even_after_fp32():
+    """Worked values: ties go to the even mantissa, magnitudes below a half
+    unit round down, signs and zero pass through, and an FP64 value takes
+    its FP32 rounding first."""
+    one = 1.0
+    u = 2.0 ** -7                      # BF16 spacing at 1
+    vals = np.array([one + u / 2, one + 3 * u / 2, one + u / 2 + 2.0 ** -20, one + u / 4, -(one + 3 * u / 2), 0.0,
+                     3.0e-30])
+    got = multigrid.bf16(vals)
+    want = [one, one + 2 * u, one + u, one, -(one + 2 * u), 0.0]
+    assert np.array_equal(got[:6], want)
+    # the last value: FP32 first, then 8 significant bits
+    x32 = np.float32(3.0e-30)
+    m, e = np.frexp(np.float64(x32))
+    assert abs(got[6] - np.ldexp(np.round(m * 256) / 256, e)) <= np.ldexp(1.0, e - 9)
+
+
+def test_bf16_cycle_stays_close_to_the_exact_one():
+    """Rounding the level-0 coefficients to BF16 (relative error <= 2^-9)
+    moves one V-cycle's output by a comparable relative amount."""
+    wl = fx.small(5, 20, 14, 12, body="sphere")
+    og, ob, op, b = oracle_for(wl)
+    Hf = multigrid.Hierarchy(op)
+    Hb = multigrid.Hierarchy(op, coef="bf16")
+    r = np.where(op.reduced_mask() > 0, np.random.default_rng(3).standard_normal(og.shape), 0.0)
+    zf, zb = Hf.precond(r), Hb.precond(r)
+    d = np.linalg.norm(zb - zf) / np.linalg.norm(zf)
+    assert 1e-6 < d < 3e-2
