@@ -311,8 +311,9 @@ nfa_status nfa_mg_set_params(nfa_mg mg, double omega, double alpha);
 /* nfa_mg_set_coef -- the precision in which the cycle's level-0 sweeps read
  * the face coefficients and D^-1: NFA_F32 (the operator's FP32 copies) or
  * NFA_BF16 (those rounded to BF16, nearest even; made at set-up, half the
- * bytes).  The operator of the CG itself is unaffected.  Takes effect at the
- * next set-up.  Errors: NFA_ERR_INVALID. */
+ * bytes; the first such set-up allocates 8 bytes per cell for them).  The
+ * operator of the CG itself is unaffected.  Takes effect at the next
+ * set-up.  Errors: NFA_ERR_INVALID. */
 nfa_status nfa_mg_set_coef(nfa_mg mg, int dtype);
 /* nfa_mg_side_rows -- rows of level >= 1 (below the coarsest) held in the
  * side list by the last set-up (couplings beyond the 7 points). */

@@ -1312,6 +1312,14 @@ nfa_status mg_setup(nfa_mg_s& mg, hipStream_t st) {
     if (e != NFA_OK) return e;
   }
   if (mg.coef16) {
+    if (!mg.d16.p) {   // the BF16 copies are allocated by the first set-up that needs them
+      if (mg.tx16.alloc(g.n * 2) != hipSuccess || mg.txb16.alloc((size_t)g.nz * g.ny * 2) != hipSuccess ||
+          mg.ty16.alloc(g.nfy() * 2) != hipSuccess || mg.tz16.alloc(g.nfz() * 2) != hipSuccess ||
+          mg.d16.alloc(g.n * 2) != hipSuccess) {
+        mg.d16.release();
+        return fail(NFA_ERR_HIP, "multigrid: out of device memory for the BF16 coefficients");
+      }
+    }
     const Coeffs<float> c32 = op.c32();
     const float* src[5] = {c32.tx, c32.txb, c32.ty, c32.tz, c32.dinv};
     DevBuf* dst[5] = {&mg.tx16, &mg.txb16, &mg.ty16, &mg.tz16, &mg.d16};
@@ -1558,10 +1566,6 @@ extern "C" nfa_status nfa_mg_create(nfa_poisson op, nfa_mg* out) {
     return fail(NFA_ERR_INVALID, "nfa_mg_create: the grid has a single cell");
   }
   hipError_t e;
-  if ((e = mg->tx16.alloc(g.n * 2)) != hipSuccess || (e = mg->txb16.alloc((size_t)g.nz * g.ny * 2)) != hipSuccess ||
-      (e = mg->ty16.alloc(g.nfy() * 2)) != hipSuccess || (e = mg->tz16.alloc(g.nfz() * 2)) != hipSuccess ||
-      (e = mg->d16.alloc(g.n * 2)) != hipSuccess)
-    return bad(e);
   if ((e = mg->group_of.alloc(g.n * 4)) != hipSuccess ||
       (e = mg->xcnt.alloc(2 * ((mg->lv[1].d.n + kBlock - 1) / kBlock) * sizeof(int))) != hipSuccess)
     return bad(e);
