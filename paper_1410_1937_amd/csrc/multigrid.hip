@@ -916,22 +916,46 @@ __global__ __launch_bounds__(L0X* L0Y) void k_l0_x4(L0<C> a, float* out, const f
   }
 }
 
+// Coordinates of a cell from its linear index.  The fix-up kernels below
+// index in 32 bits: a grid has fewer than 2^31 nodes, so every cell and face
+// index fits.
+struct Ijk {
+  int i, j, k;
+};
+template <class C> __device__ __forceinline__ Ijk ijk_of(const L0<C>& a, unsigned c) {
+  const unsigned nx = a.nx, ny = a.ny;
+  const unsigned row = c / nx, k = row / ny;
+  return {(int)(c - row * nx), (int)(row - k * ny), (int)k};
+}
+
+// The value before post-smoothing that the merged operator sees at cell x:
+// that of its root (an unknown is its own root, a slave takes its root's),
+// 0 when x is inactive.
+template <class C>
+__device__ __forceinline__ float merged_zp(const L0<C>& a, const int* __restrict__ root, unsigned x) {
+  const int rt = root[x];
+  const unsigned y = rt < 0 ? 0u : (unsigned)rt;
+  const Ijk p = ijk_of(a, y);
+  return l0_value<true>(a, (long long)y, p.i, p.j, p.k) * (rt < 0 ? 0.0f : 1.0f);
+}
+
 // Row c of the 7-point operator applied to a cell function f (0 beyond the
 // domain), in the sweep's face order.
 template <class C, class F>
-__device__ __forceinline__ float l0_row(const L0<C>& a, long long c, F f) {
-  const long long plane = (long long)a.nx * a.ny;
-  const int i = (int)(c % a.nx), j = (int)((c / a.nx) % a.ny), k = (int)(c / plane);
-  const long long yi = ((long long)k * (a.ny + 1) + j) * a.nx + i;
+__device__ __forceinline__ float l0_row(const L0<C>& a, unsigned c, F f) {
+  const unsigned plane = (unsigned)a.nx * a.ny;
+  const Ijk p = ijk_of(a, c);
+  const int i = p.i, j = p.j, k = p.k;
+  const unsigned yi = ((unsigned)k * (a.ny + 1) + j) * a.nx + i;
   const bool ok[6] = {i > 0, i < a.nx - 1, j > 0, j < a.ny - 1, k > 0, k < a.nz - 1};
-  const long long off[6] = {-1, 1, -a.nx, a.nx, -plane, plane};
+  const unsigned off[6] = {~0u, 1u, 0u - (unsigned)a.nx, (unsigned)a.nx, 0u - plane, plane};
   // unconditional loads: a neighbour beyond the domain reads the cell itself
   // and is multiplied by 0
   float fv[6];
 #pragma unroll
   for (int d = 0; d < 6; ++d) fv[d] = f(ok[d] ? c + off[d] : c) * (ok[d] ? 1.0f : 0.0f);
   const float m1 = ok[1] ? 1.0f : 0.0f;
-  const float tb = cf(a.txb[(long long)k * a.ny + j]);
+  const float tb = cf(a.txb[(unsigned)k * a.ny + j]);
   const float txp = cf(a.tx[ok[1] ? c + 1 : c]);
   const float T[6] = {cf(a.tx[c]), txp * m1 + tb * (1.0f - m1), cf(a.ty[yi]), cf(a.ty[yi + a.nx]), cf(a.tz[c]),
                       cf(a.tz[c + plane])};
@@ -954,14 +978,15 @@ __global__ void k_l0_fix_terms(L0<C> a, int nent, const int* __restrict__ ent, c
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nent) return;
   const int code = ent[e];
-  const long long c = code >= 0 ? code : -(long long)code - 1;
-  const long long plane = (long long)a.nx * a.ny;
-  const int i = (int)(c % a.nx), j = (int)((c / a.nx) % a.ny), k = (int)(c / plane);
-  const long long yi = ((long long)k * (a.ny + 1) + j) * a.nx + i;
+  const unsigned c = code >= 0 ? (unsigned)code : (unsigned)(-(code + 1));
+  const unsigned plane = (unsigned)a.nx * a.ny;
+  const Ijk p = ijk_of(a, c);
+  const int i = p.i, j = p.j, k = p.k;
+  const unsigned yi = ((unsigned)k * (a.ny + 1) + j) * a.nx + i;
   const bool ok[6] = {i > 0, i < a.nx - 1, j > 0, j < a.ny - 1, k > 0, k < a.nz - 1};
-  const long long off[6] = {-1, 1, -a.nx, a.nx, -plane, plane};
+  const unsigned off[6] = {~0u, 1u, 0u - (unsigned)a.nx, (unsigned)a.nx, 0u - plane, plane};
   const float m1 = ok[1] ? 1.0f : 0.0f;
-  const float tb = cf(a.txb[(long long)k * a.ny + j]);
+  const float tb = cf(a.txb[(unsigned)k * a.ny + j]);
   const float txp = cf(a.tx[ok[1] ? c + 1 : c]);
   const float T[6] = {cf(a.tx[c]), txp * m1 + tb * (1.0f - m1), cf(a.ty[yi]), cf(a.ty[yi + a.nx]), cf(a.tz[c]),
                       cf(a.tz[c + plane])};
@@ -969,7 +994,7 @@ __global__ void k_l0_fix_terms(L0<C> a, int nent, const int* __restrict__ ent, c
   // batch loaded unconditionally; a neighbour beyond the domain reads the
   // cell itself, an inactive one (root -1) reads cell 0, and both are
   // multiplied by 0
-  long long nb[6];
+  unsigned nb[6];
   int rt[6];
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
@@ -983,7 +1008,7 @@ __global__ void k_l0_fix_terms(L0<C> a, int nent, const int* __restrict__ ent, c
     const float m = ok[f] && rt[f] >= 0 ? 1.0f : 0.0f;
     const int x = rt[f] < 0 ? 0 : rt[f];
     zr[f] = a.p.w * (cf(a.dinv[x]) * a.r[x]) * m;
-    slave[f] = ok[f] && rt[f] >= 0 && rt[f] != nb[f] ? 1.0f : 0.0f;
+    slave[f] = ok[f] && rt[f] >= 0 && (unsigned)rt[f] != nb[f] ? 1.0f : 0.0f;
   }
   float t = 0.0f;
   if (code >= 0) {
@@ -1011,24 +1036,13 @@ __global__ void k_l0_fix_sum(int nblk, const int* __restrict__ blk, const int* _
   rc[blk[t]] += d;
 }
 
-// Up fix-up, step 1: each slave's z slot takes its root's zp (the value the
-// merged operator gives it; the up sweep left 0 there).
-template <class C>
-__global__ void k_l0_slave_zp(L0<C> a, int ns, const int* __restrict__ s_cell, const int* __restrict__ s_root, float* z,
-                              const SolveScalars* sc) {
-  if (solve_done(sc)) return;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ns) return;
-  const long long rt = s_root[t];
-  const long long plane = (long long)a.nx * a.ny;
-  z[s_cell[t]] = l0_value<true>(a, rt, (int)(rt % a.nx), (int)((rt / a.nx) % a.ny), (int)(rt / plane));
-}
-
-// Up fix-up, step 2: one thread per row of the list.  The up sweep formed
+// Up fix-up: one thread per row of the list.  The up sweep formed
 // z = z' + omega D^-1 (r - q^) with a slave's value taken as 0 and a root
 // without its slaves' rows; with the merged operator q' = q^ - sum over the
-// row's faces to slaves of T_f z(slave) (+ the slaves' rows for a root), so
-// z -= omega D^-1 (q' - q^).  Slaves' values are their z slots (step 1).
+// row's faces to slaves of T_f z'(slave) (+ the slaves' rows for a root), so
+// z -= omega D^-1 (q' - q^).  A slave's z' is its root's, formed again from
+// the root's r, D^-1 and level-1 value (the z slots of slaves are left as
+// the up sweep wrote them: the merge copy that follows the cycle sets them).
 template <class C>
 __global__ __launch_bounds__(256) void k_l0_up_fix(L0<C> a, int nrow, const int* __restrict__ rows,
                                                    const int* __restrict__ root, const int* __restrict__ group_of,
@@ -1037,25 +1051,18 @@ __global__ __launch_bounds__(256) void k_l0_up_fix(L0<C> a, int nrow, const int*
                                                    const SolveScalars* sc) {
   if (solve_done(sc)) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const long long plane = (long long)a.nx * a.ny;
-  // a neighbour's merged value: its own z' (an unknown), its slot (a slave), 0 (inactive)
-  auto zp = [&](long long x) {
-    const int i = (int)(x % a.nx), j = (int)((x / a.nx) % a.ny), k = (int)(x / plane);
-    const Raw w = l0_raw<true>(a, x, i, j, k);
-    const int rt = root[x];
-    const float zs = z[x];
-    const float mu = w.m ? 1.0f : 0.0f, ms = !w.m && rt >= 0 ? 1.0f : 0.0f;
-    return (a.p.w * (w.d * w.r) + a.p.a * w.z) * mu + zs * ms;
-  };
+  auto zp = [&](unsigned x) { return merged_zp(a, root, x); };
   double dd = 0.0;
   if (t < nrow) {
-    const long long c = rows[t];
-    const int i = (int)(c % a.nx), j = (int)((c / a.nx) % a.ny), k = (int)(c / plane);
-    const long long yi = ((long long)k * (a.ny + 1) + j) * a.nx + i;
+    const unsigned c = (unsigned)rows[t];
+    const unsigned plane = (unsigned)a.nx * a.ny;
+    const Ijk p = ijk_of(a, c);
+    const int i = p.i, j = p.j, k = p.k;
+    const unsigned yi = ((unsigned)k * (a.ny + 1) + j) * a.nx + i;
     const bool ok[6] = {i > 0, i < a.nx - 1, j > 0, j < a.ny - 1, k > 0, k < a.nz - 1};
-    const long long off[6] = {-1, 1, -a.nx, a.nx, -plane, plane};
+    const unsigned off[6] = {~0u, 1u, 0u - (unsigned)a.nx, (unsigned)a.nx, 0u - plane, plane};
     const float m1 = ok[1] ? 1.0f : 0.0f;
-    const float tb = cf(a.txb[(long long)k * a.ny + j]);
+    const float tb = cf(a.txb[(unsigned)k * a.ny + j]);
     const float txp = cf(a.tx[ok[1] ? c + 1 : c]);
     const float T[6] = {cf(a.tx[c]), txp * m1 + tb * (1.0f - m1), cf(a.ty[yi]), cf(a.ty[yi + a.nx]), cf(a.tz[c]),
                         cf(a.tz[c + plane])};
@@ -1063,16 +1070,16 @@ __global__ __launch_bounds__(256) void k_l0_up_fix(L0<C> a, int nrow, const int*
     float dq = 0.0f;
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
-      const long long nb = ok[f] ? c + off[f] : c;
+      const unsigned nb = ok[f] ? c + off[f] : c;
       const int rt = root[nb];
       const int red = a.red[nb];
-      const float zs = z[nb];
+      const float zs = zp(nb);
       const float slave = ok[f] && !red && rt >= 0 ? 1.0f : 0.0f;
       dq -= T[f] * (zs * slave);
     }
     const int gi = group_of[c];
     if (gi >= 0)
-      for (int m = g_off[gi]; m < g_off[gi + 1]; ++m) dq = dq + l0_row(a, g_mem[m], zp);
+      for (int m = g_off[gi]; m < g_off[gi + 1]; ++m) dq = dq + l0_row(a, (unsigned)g_mem[m], zp);
     const float zold = z[c];
     const float znew = zold - a.p.w * (cf(a.dinv[c]) * dq);
     z[c] = znew;
@@ -1439,9 +1446,6 @@ void l0_up(nfa_mg_s& mg, const L0<C>& a, bool x4, int nb0, float* z0, const floa
     k_l0<true, C><<<nb0, L0X * L0Y, 0, st>>>(a, z0, qdot, parts, sc);
   prof_end(op, rec, kProfMgUp, st);
   const int nfix = (int)g.h_fix.size();
-  if (g.n_slaves > 0)
-    k_l0_slave_zp<C><<<(g.n_slaves + 255) / 256, 256, 0, st>>>(a, g.n_slaves, g.s_cell.as<int>(),
-                                                               g.s_root.as<int>(), z0, sc);
   if (nfix > 0)
     k_l0_up_fix<C><<<(nfix + 255) / 256, 256, 0, st>>>(a, nfix, g.fix_rows.as<int>(), g.root.as<int>(),
                                                         mg.group_of.as<int>(), g.g_off.as<int>(), g.g_mem.as<int>(),
