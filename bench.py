@@ -219,6 +219,27 @@ def main():
                 "algorithmic_bytes_per_launch": e["algorithmic_bytes_per_launch"],
                 "other_timed_kernels": [entries[k] for k in entries if k != dom]}
 
+    # attainable HBM bandwidth beside the peak: the library's plain streaming
+    # copy over 1 GiB (4x the Infinity Cache), bytes read + written per second
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev).uniform_()
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        nfa.stream_copy(dst, src)
+    if not torch.equal(dst, src):
+        raise RuntimeError("stream copy mismatch")
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    c0.record()
+    for _ in range(reps):
+        nfa.stream_copy(dst, src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 4 * reps / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    roofline["attainable_copy"] = {"GBs": round(copy_gbs, 1), "bytes_per_copy": 2 * src.numel() * 4,
+                                   "kernel": "k_stream_copy", "frac_of_copy": round(roofline["achieved"] / copy_gbs, 4)}
+    log(f"[bench] plain copy: {copy_gbs:.0f} GB/s")
+    del src, dst
+
     # one Runge-Kutta projection cycle (two projections around the advected
     # volume fraction) on the same grid, mixed precision; reported beside the
     # metric, which is per projection

@@ -72,6 +72,16 @@ const char* nfa_last_error(void);
 /* Library version, major*10000 + minor*100 + patch. */
 int nfa_version(void);
 
+/* nfa_stream_copy -- dst = src over `bytes` bytes with a plain streaming
+ * kernel (16-byte non-temporal loads and stores, four in flight per lane).
+ * Not a step of the method: the attainable HBM bandwidth that the rates of
+ * the sweeps are set against.
+ *   dst, src : DEVICE, 16-byte aligned, not overlapping; owned by the caller.
+ *   bytes    : a multiple of 16 (0: nothing to do).
+ * NFA_ERR_INVALID for a misaligned pointer or size, or a null pointer with
+ * bytes > 0.  ASYNC on s. */
+nfa_status nfa_stream_copy(void* dst, const void* src, size_t bytes, nfa_stream s);
+
 /* ------------------------------------------------------------------ grid
  * nfa_grid_create -- stretched cartesian grid (Gridding section).
  *   nx, ny, nz : cells per axis, each >= 1.

@@ -592,13 +592,30 @@ __device__ __forceinline__ Faces l0_faces(const L0<C>& a, long long c, long long
   return f;
 }
 
+// The down fix-up's terms, formed by the workgroups of the down sweep's
+// launch that follow the sweep's own (ids from nsweep on): they read only the
+// inputs of the cycle's level 0 (r, D^-1, the coefficients and the roots),
+// never what the sweep writes, so they need no launch of their own.
+struct Fix {
+  int nsweep = 0;                  // workgroups of the sweep itself
+  int n = 0;                       // fix-up entries (0: none)
+  const int* ent = nullptr;        // entry codes
+  const int* root = nullptr;
+  float* term = nullptr;           // one term per entry
+};
+template <class C> __device__ void l0_fix_block(const L0<C>& a, const Fix& F, int b);
+
 template <bool UP, class C>
 __global__ __launch_bounds__(L0X* L0Y) void k_l0(L0<C> a, float* out, const float* __restrict__ q,
-                                                double* __restrict__ part, const SolveScalars* sc) {
+                                                double* __restrict__ part, Fix fx, const SolveScalars* sc) {
   if (solve_done(sc)) return;
+  if (!UP && (int)blockIdx.x >= fx.nsweep) {
+    l0_fix_block(a, fx, (int)blockIdx.x - fx.nsweep);
+    return;
+  }
   __shared__ float pl[2][L0Y + 2][L0X + 2];
   __shared__ float rb[2][L0Y][L0X / 2];
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int blk = xcd_remap(blockIdx.x, fx.nsweep);
   const int bx = blk % a.tiles_x, rest = blk / a.tiles_x;
   const int by = rest % a.tiles_y, bz = rest / a.tiles_y;
   const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
@@ -768,12 +785,16 @@ __device__ __forceinline__ float comp(const float4& v, int e) { return e == 0 ? 
 
 template <bool UP, class C>
 __global__ __launch_bounds__(L0X* L0Y) void k_l0_x4(L0<C> a, float* out, const float* __restrict__ q,
-                                               double* __restrict__ part, const SolveScalars* sc) {
+                                               double* __restrict__ part, Fix fx, const SolveScalars* sc) {
   if (solve_done(sc)) return;
+  if (!UP && (int)blockIdx.x >= fx.nsweep) {
+    l0_fix_block(a, fx, (int)blockIdx.x - fx.nsweep);
+    return;
+  }
   constexpr int W = 4 * L0X;   // cells of a tile row
   __shared__ float pl[2][L0Y + 2][W + 2];
   __shared__ float rb[2][L0Y][W / 2];
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int blk = xcd_remap(blockIdx.x, fx.nsweep);
   const int bx = blk % a.tiles_x, rest = blk / a.tiles_x;
   const int by = rest % a.tiles_y, bz = rest / a.tiles_y;
   const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
@@ -966,18 +987,13 @@ __device__ __forceinline__ float l0_row(const L0<C>& a, unsigned c, F f) {
   return q;
 }
 
-// Down fix-up, step 1: one thread per entry.  An entry c >= 0 (an unknown
+// Down fix-up, step 1: the term of one entry.  An entry c >= 0 (an unknown
 // next to a slave, or a root) owes q~_c - q_c: only its faces to slaves
 // differ, each by T_f z(root of the slave); an entry -(s+1) (a slave whose
 // root lies in the entry's level-1 cell) owes -q_s, the slave's row with
 // merged values.
 template <class C>
-__global__ void k_l0_fix_terms(L0<C> a, int nent, const int* __restrict__ ent, const int* __restrict__ root,
-                               float* term, const SolveScalars* sc) {
-  if (solve_done(sc)) return;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nent) return;
-  const int code = ent[e];
+__device__ __forceinline__ float down_term(const L0<C>& a, const int* __restrict__ root, int code) {
   const unsigned c = code >= 0 ? (unsigned)code : (unsigned)(-(code + 1));
   const unsigned plane = (unsigned)a.nx * a.ny;
   const Ijk p = ijk_of(a, c);
@@ -1022,10 +1038,11 @@ __global__ void k_l0_fix_terms(L0<C> a, int nent, const int* __restrict__ ent, c
     for (int f = 1; f < 6; ++f) q = q + T[f] * (zs - zr[f]);
     t = -q;
   }
-  term[e] = t;
+  return t;
 }
 
-// Down fix-up, step 2: one thread per level-1 cell adds its terms in order.
+// Down fix-up, step 2 (after the sweep and its trailing workgroups): one thread
+// per level-1 cell adds its terms in order.
 __global__ void k_l0_fix_sum(int nblk, const int* __restrict__ blk, const int* __restrict__ off,
                              const float* __restrict__ term, float* rc, const SolveScalars* sc) {
   if (solve_done(sc)) return;
@@ -1036,13 +1053,55 @@ __global__ void k_l0_fix_sum(int nblk, const int* __restrict__ blk, const int* _
   rc[blk[t]] += d;
 }
 
-// Up fix-up: one thread per row of the list.  The up sweep formed
+// Up fix-up: the correction of one listed row.  The up sweep formed
 // z = z' + omega D^-1 (r - q^) with a slave's value taken as 0 and a root
 // without its slaves' rows; with the merged operator q' = q^ - sum over the
 // row's faces to slaves of T_f z'(slave) (+ the slaves' rows for a root), so
-// z -= omega D^-1 (q' - q^).  A slave's z' is its root's, formed again from
-// the root's r, D^-1 and level-1 value (the z slots of slaves are left as
-// the up sweep wrote them: the merge copy that follows the cycle sets them).
+// z -= omega D^-1 dq with dq = q' - q^.  A slave's z' is its root's, formed
+// again from the root's r, D^-1 and level-1 value (the z slots of slaves are
+// left as the up sweep wrote them: the merge copy that follows the cycle
+// sets them).
+template <class C>
+__device__ __forceinline__ float up_dq(const L0<C>& a, const int* __restrict__ root, const int* __restrict__ group_of,
+                                      const int* __restrict__ g_off, const int* __restrict__ g_mem, unsigned c) {
+  auto zp = [&](unsigned x) { return merged_zp(a, root, x); };
+  const unsigned plane = (unsigned)a.nx * a.ny;
+  const Ijk p = ijk_of(a, c);
+  const int i = p.i, j = p.j, k = p.k;
+  const unsigned yi = ((unsigned)k * (a.ny + 1) + j) * a.nx + i;
+  const bool ok[6] = {i > 0, i < a.nx - 1, j > 0, j < a.ny - 1, k > 0, k < a.nz - 1};
+  const unsigned off[6] = {~0u, 1u, 0u - (unsigned)a.nx, (unsigned)a.nx, 0u - plane, plane};
+  const float m1 = ok[1] ? 1.0f : 0.0f;
+  const float tb = cf(a.txb[(unsigned)k * a.ny + j]);
+  const float txp = cf(a.tx[ok[1] ? c + 1 : c]);
+  const float T[6] = {cf(a.tx[c]), txp * m1 + tb * (1.0f - m1), cf(a.ty[yi]), cf(a.ty[yi + a.nx]), cf(a.tz[c]),
+                      cf(a.tz[c + plane])};
+  // faces to slaves: all loads issued together, a face masked by a product
+  float dq = 0.0f;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const unsigned nb = ok[f] ? c + off[f] : c;
+    const int rt = root[nb];
+    const int red = a.red[nb];
+    const float zs = zp(nb);
+    const float slave = ok[f] && !red && rt >= 0 ? 1.0f : 0.0f;
+    dq -= T[f] * (zs * slave);
+  }
+  const int gi = group_of[c];
+  if (gi >= 0)
+    for (int m = g_off[gi]; m < g_off[gi + 1]; ++m) dq = dq + l0_row(a, (unsigned)g_mem[m], zp);
+  return dq;
+}
+
+// The fix-up workgroups of the down sweep: one thread per entry.
+template <class C> __device__ void l0_fix_block(const L0<C>& a, const Fix& F, int b) {
+  const int t = b * (L0X * L0Y) + (int)threadIdx.x;
+  if (t < F.n) F.term[t] = down_term(a, F.root, F.ent[t]);
+}
+
+// Up fix-up, after the up sweep: one thread per listed row forms dq and
+// applies z -= omega D^-1 dq.  The up sweep summed z_old . q for the row; the
+// z.q partial takes the difference.
 template <class C>
 __global__ __launch_bounds__(256) void k_l0_up_fix(L0<C> a, int nrow, const int* __restrict__ rows,
                                                    const int* __restrict__ root, const int* __restrict__ group_of,
@@ -1051,39 +1110,13 @@ __global__ __launch_bounds__(256) void k_l0_up_fix(L0<C> a, int nrow, const int*
                                                    const SolveScalars* sc) {
   if (solve_done(sc)) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  auto zp = [&](unsigned x) { return merged_zp(a, root, x); };
   double dd = 0.0;
   if (t < nrow) {
     const unsigned c = (unsigned)rows[t];
-    const unsigned plane = (unsigned)a.nx * a.ny;
-    const Ijk p = ijk_of(a, c);
-    const int i = p.i, j = p.j, k = p.k;
-    const unsigned yi = ((unsigned)k * (a.ny + 1) + j) * a.nx + i;
-    const bool ok[6] = {i > 0, i < a.nx - 1, j > 0, j < a.ny - 1, k > 0, k < a.nz - 1};
-    const unsigned off[6] = {~0u, 1u, 0u - (unsigned)a.nx, (unsigned)a.nx, 0u - plane, plane};
-    const float m1 = ok[1] ? 1.0f : 0.0f;
-    const float tb = cf(a.txb[(unsigned)k * a.ny + j]);
-    const float txp = cf(a.tx[ok[1] ? c + 1 : c]);
-    const float T[6] = {cf(a.tx[c]), txp * m1 + tb * (1.0f - m1), cf(a.ty[yi]), cf(a.ty[yi + a.nx]), cf(a.tz[c]),
-                        cf(a.tz[c + plane])};
-    // faces to slaves: all loads issued together, a face masked by a product
-    float dq = 0.0f;
-#pragma unroll
-    for (int f = 0; f < 6; ++f) {
-      const unsigned nb = ok[f] ? c + off[f] : c;
-      const int rt = root[nb];
-      const int red = a.red[nb];
-      const float zs = zp(nb);
-      const float slave = ok[f] && !red && rt >= 0 ? 1.0f : 0.0f;
-      dq -= T[f] * (zs * slave);
-    }
-    const int gi = group_of[c];
-    if (gi >= 0)
-      for (int m = g_off[gi]; m < g_off[gi + 1]; ++m) dq = dq + l0_row(a, (unsigned)g_mem[m], zp);
+    const float dq = up_dq(a, root, group_of, g_off, g_mem, c);
     const float zold = z[c];
     const float znew = zold - a.p.w * (cf(a.dinv[c]) * dq);
     z[c] = znew;
-    // the up sweep summed zold . q for this row; the z.q partial takes the difference
     if (part) dd = ((double)znew - (double)zold) * (double)qv[c];
   }
   if (part) {
@@ -1413,37 +1446,46 @@ nfa_status mg_setup(nfa_mg_s& mg, hipStream_t st) {
   return NFA_OK;
 }
 
-// Level 0 of the cycle, down: the fused sweep and the merged rows' fix-up.
+// Level 0 of the cycle, down: the fused sweep, whose trailing workgroups
+// form the merged rows' fix-up terms, then the terms' sums into level 1.
 template <class C>
 void l0_down(nfa_mg_s& mg, const L0<C>& a, bool x4, int nb0, const SolveScalars* sc, hipStream_t st) {
   Poisson& op = *mg.op;
   Grid& g = *op.g;
+  Fix fx;
+  fx.nsweep = nb0;
+  if (mg.nfblk > 0) {
+    fx.n = mg.nfent;
+    fx.ent = mg.fent.as<int>();
+    fx.root = g.root.as<int>();
+    fx.term = mg.fterm.as<float>();
+  }
+  const int nb = nb0 + (fx.n + L0X * L0Y - 1) / (L0X * L0Y);
   const bool rec = prof_begin(op, st);
   if (x4)
-    k_l0_x4<false, C><<<nb0, L0X * L0Y, 0, st>>>(a, mg.lv[1].r.as<float>(), nullptr, nullptr, sc);
+    k_l0_x4<false, C><<<nb, L0X * L0Y, 0, st>>>(a, mg.lv[1].r.as<float>(), nullptr, nullptr, fx, sc);
   else
-    k_l0<false, C><<<nb0, L0X * L0Y, 0, st>>>(a, mg.lv[1].r.as<float>(), nullptr, nullptr, sc);
+    k_l0<false, C><<<nb, L0X * L0Y, 0, st>>>(a, mg.lv[1].r.as<float>(), nullptr, nullptr, fx, sc);
   prof_end(op, rec, kProfMgDown, st);
-  if (mg.nfblk > 0) {
-    k_l0_fix_terms<C><<<(mg.nfent + 255) / 256, 256, 0, st>>>(a, mg.nfent, mg.fent.as<int>(), g.root.as<int>(),
-                                                              mg.fterm.as<float>(), sc);
+  if (mg.nfblk > 0)
     k_l0_fix_sum<<<(mg.nfblk + 255) / 256, 256, 0, st>>>(mg.nfblk, mg.fblk.as<int>(), mg.foff.as<int>(),
                                                          mg.fterm.as<float>(), mg.lv[1].r.as<float>(), sc);
-  }
 }
 
 // Level 0 of the cycle, up: the fused sweep (with the z.q partials when
-// parts is given, nb0 of them, the fix-up's after them) and the fix-ups.
+// parts is given, nb0 of them, the fix-up's after them) and the fix-up.
 template <class C>
 void l0_up(nfa_mg_s& mg, const L0<C>& a, bool x4, int nb0, float* z0, const float* qdot, double* parts,
            const SolveScalars* sc, hipStream_t st) {
   Poisson& op = *mg.op;
   Grid& g = *op.g;
+  Fix fx;
+  fx.nsweep = nb0;
   const bool rec = prof_begin(op, st);
   if (x4)
-    k_l0_x4<true, C><<<nb0, L0X * L0Y, 0, st>>>(a, z0, qdot, parts, sc);
+    k_l0_x4<true, C><<<nb0, L0X * L0Y, 0, st>>>(a, z0, qdot, parts, fx, sc);
   else
-    k_l0<true, C><<<nb0, L0X * L0Y, 0, st>>>(a, z0, qdot, parts, sc);
+    k_l0<true, C><<<nb0, L0X * L0Y, 0, st>>>(a, z0, qdot, parts, fx, sc);
   prof_end(op, rec, kProfMgUp, st);
   const int nfix = (int)g.h_fix.size();
   if (nfix > 0)

@@ -301,3 +301,37 @@ void launch_set_scalars(SolveScalars* sc, double t, int tol_mode, int max_iter, 
 }
 
 }  // namespace nfa
+
+namespace {
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kCopyUnroll = 4;
+
+// dst = src in 16-byte words: every lane keeps kCopyUnroll non-temporal loads
+// in flight, a grid-stride loop over the rest
+__global__ __launch_bounds__(256) void k_stream_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
+                                                     long long n) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  for (; i + (kCopyUnroll - 1) * stride < n; i += kCopyUnroll * stride) {
+    u32x4 v[kCopyUnroll];
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) __builtin_nontemporal_store(v[u], dst + i + u * stride);
+  }
+  for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+}  // namespace
+
+extern "C" nfa_status nfa_stream_copy(void* dst, const void* src, size_t bytes, nfa_stream s) {
+  using namespace nfa;
+  if (bytes % 16 != 0 || reinterpret_cast<uintptr_t>(dst) % 16 != 0 || reinterpret_cast<uintptr_t>(src) % 16 != 0)
+    return fail(NFA_ERR_INVALID, "nfa_stream_copy: pointers and size must be multiples of 16 bytes");
+  if (bytes == 0) return NFA_OK;
+  if (dst == nullptr || src == nullptr) return fail(NFA_ERR_INVALID, "nfa_stream_copy: null pointer");
+  const long long n = (long long)(bytes / 16);
+  const int nb = blocks_for(n, 256 * kCopyUnroll, 8192);
+  k_stream_copy<<<nb, 256, 0, S(s)>>>(reinterpret_cast<const u32x4*>(src), reinterpret_cast<u32x4*>(dst), n);
+  NFA_CHECK_LAUNCH();
+  return NFA_OK;
+}

@@ -86,6 +86,7 @@ def _sig(name, res, args):
 
 _sig("nfa_last_error", ctypes.c_char_p, [])
 _sig("nfa_version", c_int, [])
+_sig("nfa_stream_copy", c_int, [c_void_p, c_void_p, ctypes.c_size_t, c_void_p])
 _sig("nfa_grid_create", c_int, [c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
                                 ctypes.POINTER(c_void_p)])
 _sig("nfa_grid_set_body", c_int, [c_void_p, c_void_p, c_double, c_int, c_void_p])
@@ -162,6 +163,22 @@ def faces_combine(a, b, s, c, out=None):
                                  s, c_void_p(c.data_ptr()), c_void_p(out.data_ptr()), _stream()),
            "nfa_faces_combine")
     return out
+
+
+def stream_copy(dst, src):
+    """dst = src (same-size contiguous device tensors, 16-byte aligned) with
+    the library's plain streaming copy (nfa_stream_copy); on the current
+    stream."""
+    if not (isinstance(dst, torch.Tensor) and isinstance(src, torch.Tensor) and dst.is_cuda and src.is_cuda):
+        raise TypeError("dst and src must be CUDA (HIP) tensors")
+    if not (dst.is_contiguous() and src.is_contiguous()):
+        raise TypeError("dst and src must be contiguous")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("dst and src differ in size")
+    _check(lib.nfa_stream_copy(c_void_p(dst.data_ptr()), c_void_p(src.data_ptr()), nbytes, _stream()),
+           "nfa_stream_copy")
+    return dst
 
 
 def stretch_axis(a, b, n, levels, zones=(), tol=1e-13, max_iter=500):

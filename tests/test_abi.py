@@ -90,3 +90,16 @@ def test_product_path_does_not_import_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
+
+
+def test_stream_copy_rejects_misaligned_arguments_before_any_device_work(lib):
+    f = lib.nfa_stream_copy
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.nfa_last_error.restype = ctypes.c_char_p
+    assert f(ctypes.c_void_p(16), ctypes.c_void_p(32), 24, None) < 0          # size not a multiple of 16
+    assert b"multiples of 16" in lib.nfa_last_error()
+    assert f(ctypes.c_void_p(8), ctypes.c_void_p(32), 16, None) < 0           # misaligned destination
+    assert f(ctypes.c_void_p(16), ctypes.c_void_p(40), 16, None) < 0          # misaligned source
+    assert f(None, None, 16, None) < 0                                         # null with bytes > 0
+    assert f(None, None, 0, None) == 0                                         # nothing to do
