@@ -52,7 +52,9 @@
 // solve has converged.
 //
 // Built with -ffp-contract=off.
+#include <algorithm>
 #include <cmath>
+#include <map>
 #include <vector>
 
 #include "device_util.h"
@@ -949,44 +951,6 @@ template <class C> __device__ __forceinline__ Ijk ijk_of(const L0<C>& a, unsigne
   return {(int)(c - row * nx), (int)(row - k * ny), (int)k};
 }
 
-// The value before post-smoothing that the merged operator sees at cell x:
-// that of its root (an unknown is its own root, a slave takes its root's),
-// 0 when x is inactive.
-template <class C>
-__device__ __forceinline__ float merged_zp(const L0<C>& a, const int* __restrict__ root, unsigned x) {
-  const int rt = root[x];
-  const unsigned y = rt < 0 ? 0u : (unsigned)rt;
-  const Ijk p = ijk_of(a, y);
-  return l0_value<true>(a, (long long)y, p.i, p.j, p.k) * (rt < 0 ? 0.0f : 1.0f);
-}
-
-// Row c of the 7-point operator applied to a cell function f (0 beyond the
-// domain), in the sweep's face order.
-template <class C, class F>
-__device__ __forceinline__ float l0_row(const L0<C>& a, unsigned c, F f) {
-  const unsigned plane = (unsigned)a.nx * a.ny;
-  const Ijk p = ijk_of(a, c);
-  const int i = p.i, j = p.j, k = p.k;
-  const unsigned yi = ((unsigned)k * (a.ny + 1) + j) * a.nx + i;
-  const bool ok[6] = {i > 0, i < a.nx - 1, j > 0, j < a.ny - 1, k > 0, k < a.nz - 1};
-  const unsigned off[6] = {~0u, 1u, 0u - (unsigned)a.nx, (unsigned)a.nx, 0u - plane, plane};
-  // unconditional loads: a neighbour beyond the domain reads the cell itself
-  // and is multiplied by 0
-  float fv[6];
-#pragma unroll
-  for (int d = 0; d < 6; ++d) fv[d] = f(ok[d] ? c + off[d] : c) * (ok[d] ? 1.0f : 0.0f);
-  const float m1 = ok[1] ? 1.0f : 0.0f;
-  const float tb = cf(a.txb[(unsigned)k * a.ny + j]);
-  const float txp = cf(a.tx[ok[1] ? c + 1 : c]);
-  const float T[6] = {cf(a.tx[c]), txp * m1 + tb * (1.0f - m1), cf(a.ty[yi]), cf(a.ty[yi + a.nx]), cf(a.tz[c]),
-                      cf(a.tz[c + plane])};
-  const float fc = f(c);
-  float q = T[0] * (fc - fv[0]);
-#pragma unroll
-  for (int d = 1; d < 6; ++d) q = q + T[d] * (fc - fv[d]);
-  return q;
-}
-
 // Down fix-up, step 1: the term of one entry.  An entry c >= 0 (an unknown
 // next to a slave, or a root) owes q~_c - q_c: only its faces to slaves
 // differ, each by T_f z(root of the slave); an entry -(s+1) (a slave whose
@@ -1053,59 +1017,55 @@ __global__ void k_l0_fix_sum(int nblk, const int* __restrict__ blk, const int* _
   rc[blk[t]] += d;
 }
 
-// Up fix-up: the correction of one listed row.  The up sweep formed
-// z = z' + omega D^-1 (r - q^) with a slave's value taken as 0 and a root
-// without its slaves' rows; with the merged operator q' = q^ - sum over the
-// row's faces to slaves of T_f z'(slave) (+ the slaves' rows for a root), so
-// z -= omega D^-1 dq with dq = q' - q^.  A slave's z' is its root's, formed
-// again from the root's r, D^-1 and level-1 value (the z slots of slaves are
-// left as the up sweep wrote them: the merge copy that follows the cycle
-// sets them).
-template <class C>
-__device__ __forceinline__ float up_dq(const L0<C>& a, const int* __restrict__ root, const int* __restrict__ group_of,
-                                      const int* __restrict__ g_off, const int* __restrict__ g_mem, unsigned c) {
-  auto zp = [&](unsigned x) { return merged_zp(a, root, x); };
-  const unsigned plane = (unsigned)a.nx * a.ny;
-  const Ijk p = ijk_of(a, c);
-  const int i = p.i, j = p.j, k = p.k;
-  const unsigned yi = ((unsigned)k * (a.ny + 1) + j) * a.nx + i;
-  const bool ok[6] = {i > 0, i < a.nx - 1, j > 0, j < a.ny - 1, k > 0, k < a.nz - 1};
-  const unsigned off[6] = {~0u, 1u, 0u - (unsigned)a.nx, (unsigned)a.nx, 0u - plane, plane};
-  const float m1 = ok[1] ? 1.0f : 0.0f;
-  const float tb = cf(a.txb[(unsigned)k * a.ny + j]);
-  const float txp = cf(a.tx[ok[1] ? c + 1 : c]);
-  const float T[6] = {cf(a.tx[c]), txp * m1 + tb * (1.0f - m1), cf(a.ty[yi]), cf(a.ty[yi + a.nx]), cf(a.tz[c]),
-                      cf(a.tz[c + plane])};
-  // faces to slaves: all loads issued together, a face masked by a product
-  float dq = 0.0f;
-#pragma unroll
-  for (int f = 0; f < 6; ++f) {
-    const unsigned nb = ok[f] ? c + off[f] : c;
-    const int rt = root[nb];
-    const int red = a.red[nb];
-    const float zs = zp(nb);
-    const float slave = ok[f] && !red && rt >= 0 ? 1.0f : 0.0f;
-    dq -= T[f] * (zs * slave);
-  }
-  const int gi = group_of[c];
-  if (gi >= 0)
-    for (int m = g_off[gi]; m < g_off[gi + 1]; ++m) dq = dq + l0_row(a, (unsigned)g_mem[m], zp);
-  return dq;
-}
-
 // The fix-up workgroups of the down sweep: one thread per entry.
 template <class C> __device__ void l0_fix_block(const L0<C>& a, const Fix& F, int b) {
   const int t = b * (L0X * L0Y) + (int)threadIdx.x;
   if (t < F.n) F.term[t] = down_term(a, F.root, F.ent[t]);
 }
 
-// Up fix-up, after the up sweep: one thread per listed row forms dq and
-// applies z -= omega D^-1 dq.  The up sweep summed z_old . q for the row; the
-// z.q partial takes the difference.
+// Up fix-up.  The up sweep formed z = z' + omega D^-1 (r - q^) with a
+// slave's value taken as 0 and a root without its slaves' rows.  With the
+// merged operator q' = q^ + dq, where dq takes -T_f z'(root of the slave) for
+// each face of the row to a slave and, on a root, adds its slaves' rows
+// sum_f T_f (z'(root) - z'(neighbour's root)); so z -= omega D^-1 dq.  Every
+// term is s T (z'(y1) - z'(y2)) with a stored face, sign and unknown cells
+// (y2 < 0: 0), listed per row when the body is set; z'(y) = omega D^-1 r +
+// alpha z1(parent) is the value before post-smoothing of the unknown y.
+struct UpTerm {
+  int face;   // coefficient array (0 tx, 1 txb, 2 ty, 3 tz) + 4 for a negative sign
+  int idx;    // index in that array
+  int y1, y2;
+};
+
+template <class C> __device__ __forceinline__ float zprime(const L0<C>& a, unsigned y) {
+  const Ijk p = ijk_of(a, y);
+  const unsigned par = ((unsigned)(p.k >> 1) * a.cny + (unsigned)(p.j >> 1)) * a.cnx + (unsigned)(p.i >> 1);
+  return a.p.w * (cf(a.dinv[y]) * a.r[y]) + a.p.a * a.zc[par];
+}
+
+// step 1: one thread per term
+template <class C>
+__global__ __launch_bounds__(256) void k_l0_up_terms(L0<C> a, int nterm, const int4* __restrict__ terms,
+                                                     float* __restrict__ val, const SolveScalars* sc) {
+  if (solve_done(sc)) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nterm) return;
+  const int4 t = terms[e];
+  const int arr = t.x & 3;
+  const C* base = arr == 0 ? a.tx : arr == 1 ? a.txb : arr == 2 ? a.ty : a.tz;
+  const float T = cf(base[(unsigned)t.y]);
+  const float z1 = zprime(a, (unsigned)t.z);
+  const float z2 = zprime(a, t.w < 0 ? 0u : (unsigned)t.w) * (t.w < 0 ? 0.0f : 1.0f);
+  const float v = T * (z1 - z2);
+  val[e] = (t.x & 4) ? -v : v;
+}
+
+// step 2: one thread per listed row adds its terms in order and applies
+// z -= omega D^-1 dq.  The up sweep summed z_old . q for the row; the z.q
+// partial takes the difference.
 template <class C>
 __global__ __launch_bounds__(256) void k_l0_up_fix(L0<C> a, int nrow, const int* __restrict__ rows,
-                                                   const int* __restrict__ root, const int* __restrict__ group_of,
-                                                   const int* __restrict__ g_off, const int* __restrict__ g_mem, float* z,
+                                                   const int* __restrict__ off, const float* __restrict__ val, float* z,
                                                    const float* __restrict__ qv, double* __restrict__ part,
                                                    const SolveScalars* sc) {
   if (solve_done(sc)) return;
@@ -1113,7 +1073,8 @@ __global__ __launch_bounds__(256) void k_l0_up_fix(L0<C> a, int nrow, const int*
   double dd = 0.0;
   if (t < nrow) {
     const unsigned c = (unsigned)rows[t];
-    const float dq = up_dq(a, root, group_of, g_off, g_mem, c);
+    float dq = 0.0f;
+    for (int e = off[t]; e < off[t + 1]; ++e) dq += val[e];
     const float zold = z[c];
     const float znew = zold - a.p.w * (cf(a.dinv[c]) * dq);
     z[c] = znew;
@@ -1265,6 +1226,8 @@ struct nfa_mg_s {
   bool coef16 = false;          // the cycle's level 0 reads the BF16 copies
   DevBuf fblk, foff, fent, fterm;   // level-0 down fix-up: level-1 cells, CSR offsets, entries, terms
   int nfblk = 0, nfent = 0;
+  DevBuf uoff, uterm, uval;         // level-0 up fix-up: CSR offsets per listed row, terms (UpTerm), their values
+  int nuterm = 0;
   int body_version = -1;        // grid body the fix-up lists belong to
   int ncoarse = 0;
   int tail_cells = kDefaultTailCells;
@@ -1400,6 +1363,64 @@ nfa_status mg_setup(nfa_mg_s& mg, hipStream_t st) {
     NFA_HIP(mg.fterm.alloc(std::max<size_t>(1, fe.size()) * sizeof(float)));
     mg.nfblk = (int)fb.size();
     mg.nfent = (int)fe.size();
+    // level-0 up fix-up terms of every listed row, in a fixed order: the
+    // row's faces to slaves, then (a root) its slaves' rows face by face
+    std::vector<int> uo(1, 0);
+    std::vector<UpTerm> ut;
+    if (!g.h_fix.empty()) {
+      std::vector<int> root(g.n);
+      NFA_HIP(hipMemcpy(root.data(), g.root.p, g.n * sizeof(int), hipMemcpyDeviceToHost));
+      std::vector<std::vector<int>> members;
+      std::vector<int> gidx;   // per fix row: index into members, -1 when it has no slaves
+      std::map<int, int> slot;
+      for (size_t t = 0; t < g.h_scell.size(); ++t) {
+        auto it = slot.find(g.h_sroot[t]);
+        if (it == slot.end()) it = slot.emplace(g.h_sroot[t], (int)members.size()).first, members.emplace_back();
+        members[it->second].push_back(g.h_scell[t]);
+      }
+      for (auto& m : members) std::sort(m.begin(), m.end());
+      const long long plane = (long long)g.nx * g.ny;
+      // face f of cell c: coefficient array and index, whether it lies inside the domain, the neighbour
+      auto face = [&](long long c, int f, int* arr, long long* idx, bool* in, long long* nb) {
+        const int i = (int)(c % g.nx), j = (int)((c / g.nx) % g.ny), k = (int)(c / plane);
+        const long long yi = ((long long)k * (g.ny + 1) + j) * g.nx + i;
+        switch (f) {
+          case 0: *arr = 0; *idx = c; *in = i > 0; *nb = c - 1; break;
+          case 1:
+            if (i < g.nx - 1) { *arr = 0; *idx = c + 1; } else { *arr = 1; *idx = (long long)k * g.ny + j; }
+            *in = i < g.nx - 1; *nb = c + 1; break;
+          case 2: *arr = 2; *idx = yi; *in = j > 0; *nb = c - g.nx; break;
+          case 3: *arr = 2; *idx = yi + g.nx; *in = j < g.ny - 1; *nb = c + g.nx; break;
+          case 4: *arr = 3; *idx = c; *in = k > 0; *nb = c - plane; break;
+          default: *arr = 3; *idx = c + plane; *in = k < g.nz - 1; *nb = c + plane; break;
+        }
+      };
+      for (int c : g.h_fix) {
+        for (int f = 0; f < 6; ++f) {
+          int arr; long long idx, nb; bool in;
+          face(c, f, &arr, &idx, &in, &nb);
+          if (!in) continue;
+          const int rt = root[nb];
+          if (rt >= 0 && rt != nb) ut.push_back({arr | 4, (int)idx, rt, -1});
+        }
+        auto it = slot.find(c);
+        if (it != slot.end())
+          for (int m : members[it->second])
+            for (int f = 0; f < 6; ++f) {
+              int arr; long long idx, nb; bool in;
+              face(m, f, &arr, &idx, &in, &nb);
+              const int rt = in ? root[nb] : -1;
+              if (rt == c) continue;   // T (z'(c) - z'(c)) = 0
+              ut.push_back({arr, (int)idx, c, rt});
+            }
+        uo.push_back((int)ut.size());
+      }
+    }
+    NFA_HIP(up(mg.uoff, uo));
+    NFA_HIP(mg.uterm.alloc(std::max<size_t>(1, ut.size()) * sizeof(UpTerm)));
+    if (!ut.empty()) NFA_HIP(hipMemcpy(mg.uterm.p, ut.data(), ut.size() * sizeof(UpTerm), hipMemcpyHostToDevice));
+    NFA_HIP(mg.uval.alloc(std::max<size_t>(1, ut.size()) * sizeof(float)));
+    mg.nuterm = (int)ut.size();
     mg.body_version = g.body_version;
   }
   // the coarsest level: dense, regularized, inverted on the host
@@ -1488,10 +1509,13 @@ void l0_up(nfa_mg_s& mg, const L0<C>& a, bool x4, int nb0, float* z0, const floa
     k_l0<true, C><<<nb0, L0X * L0Y, 0, st>>>(a, z0, qdot, parts, fx, sc);
   prof_end(op, rec, kProfMgUp, st);
   const int nfix = (int)g.h_fix.size();
-  if (nfix > 0)
-    k_l0_up_fix<C><<<(nfix + 255) / 256, 256, 0, st>>>(a, nfix, g.fix_rows.as<int>(), g.root.as<int>(),
-                                                        mg.group_of.as<int>(), g.g_off.as<int>(), g.g_mem.as<int>(),
-                                                        z0, qdot, parts ? parts + nb0 : nullptr, sc);
+  if (nfix > 0) {
+    if (mg.nuterm > 0)
+      k_l0_up_terms<C><<<(mg.nuterm + 255) / 256, 256, 0, st>>>(a, mg.nuterm, mg.uterm.as<int4>(),
+                                                                mg.uval.as<float>(), sc);
+    k_l0_up_fix<C><<<(nfix + 255) / 256, 256, 0, st>>>(a, nfix, g.fix_rows.as<int>(), mg.uoff.as<int>(),
+                                                        mg.uval.as<float>(), z0, qdot, parts ? parts + nb0 : nullptr, sc);
+  }
 }
 
 // One V-cycle: z = M r on the reduced unknowns of level 0 (FP32).
