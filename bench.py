@@ -199,7 +199,7 @@ def main():
     flex = solver["precond"] != "jacobi"
     meta = {"f32": (40, "k_cg_a<float, 4, 1, true>") if flex else (36, "k_cg_a<float, 4, 1, false>"),
             "f64": (72, f"k_cg_a<double, 2, {wx}, false>"),
-            "mg_down": (21.5, f"{l0}<false>"), "mg_up": (29.5, f"{l0}<true>")}
+            "mg_down": (21.5, f"{l0}<false, float>"), "mg_up": (29.5, f"{l0}<true, float>")}
     entries = {}
     for k, ks in kinds.items():
         if ks["launches"] == 0:
