@@ -67,10 +67,11 @@ def test_every_level_matches_the_oracle_and_rebuilds_bitwise(body, bc, shape):
 
 
 @pytest.mark.parametrize("tail", [-1, 0])
-@pytest.mark.parametrize("body,bc,shape", CASES + [("sphere", (0,) * 6, (64, 48, 40))])
+@pytest.mark.parametrize("body,bc,shape", CASES + [("sphere", (0,) * 6, (64, 48, 40)), ("sphere", (0,) * 6, (300, 20, 10))])
 def test_one_vcycle_matches_the_oracle(body, bc, shape, tail):
     """tail -1: every coarse level in the one-workgroup kernel; 0: the
-    grid-wide level kernels down to the coarsest."""
+    grid-wide level kernels down to the coarsest.  The 300 x 20 x 10 grid
+    spans several level-0 tiles in x and y, each with a ragged last one."""
     wl = fx.small(6, *shape, body=body, bc=bc)
     og, ob, oop, b = oracle_for(wl)
     H = multigrid.Hierarchy(oop)
