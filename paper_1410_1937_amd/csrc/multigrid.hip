@@ -96,6 +96,12 @@ __global__ void k_fill_int(long long n, int v, int* a) {
   MG_STRIDE(i, n) a[i] = v;
 }
 
+// dst[t] = src[idx[t]]
+__global__ void k_gather_int(int n, const int* __restrict__ idx, const int* __restrict__ src, int* __restrict__ dst) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) dst[t] = src[idx[t]];
+}
+
 __global__ void k_group_of(int ng, const int* __restrict__ groot, int* __restrict__ group_of) {
   for (int gi = blockIdx.x * blockDim.x + threadIdx.x; gi < ng; gi += gridDim.x * blockDim.x)
     group_of[groot[gi]] = gi;
@@ -1368,8 +1374,6 @@ nfa_status mg_setup(nfa_mg_s& mg, hipStream_t st) {
     std::vector<int> uo(1, 0);
     std::vector<UpTerm> ut;
     if (!g.h_fix.empty()) {
-      std::vector<int> root(g.n);
-      NFA_HIP(hipMemcpy(root.data(), g.root.p, g.n * sizeof(int), hipMemcpyDeviceToHost));
       std::vector<std::vector<int>> members;
       std::vector<int> gidx;   // per fix row: index into members, -1 when it has no slaves
       std::map<int, int> slot;
@@ -1395,12 +1399,38 @@ nfa_status mg_setup(nfa_mg_s& mg, hipStream_t st) {
           default: *arr = 3; *idx = c + plane; *in = k < g.nz - 1; *nb = c + plane; break;
         }
       };
+      // the roots the terms need (of the neighbours of the listed rows and of
+      // the slaves), gathered on the device
+      std::vector<int> need;
+      for (const std::vector<int>* list : {&g.h_fix, &g.h_scell})
+        for (int c : *list)
+          for (int f = 0; f < 6; ++f) {
+            int arr; long long idx, nb; bool in;
+            face(c, f, &arr, &idx, &in, &nb);
+            if (in) need.push_back((int)nb);
+          }
+      std::sort(need.begin(), need.end());
+      need.erase(std::unique(need.begin(), need.end()), need.end());
+      std::vector<int> need_root(need.size());
+      {
+        DevBuf d_need, d_out;
+        NFA_HIP(up(d_need, need));
+        NFA_HIP(d_out.alloc(std::max<size_t>(1, need.size()) * sizeof(int)));
+        k_gather_int<<<blocks_for((long long)need.size()), kBlock, 0, st>>>((int)need.size(), d_need.as<int>(),
+                                                                            g.root.as<int>(), d_out.as<int>());
+        NFA_CHECK_LAUNCH();
+        NFA_HIP(hipMemcpyAsync(need_root.data(), d_out.p, need.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+        NFA_HIP(hipStreamSynchronize(st));
+      }
+      auto root_of = [&](long long x) {
+        return need_root[std::lower_bound(need.begin(), need.end(), (int)x) - need.begin()];
+      };
       for (int c : g.h_fix) {
         for (int f = 0; f < 6; ++f) {
           int arr; long long idx, nb; bool in;
           face(c, f, &arr, &idx, &in, &nb);
           if (!in) continue;
-          const int rt = root[nb];
+          const int rt = root_of(nb);
           if (rt >= 0 && rt != nb) ut.push_back({arr | 4, (int)idx, rt, -1});
         }
         auto it = slot.find(c);
@@ -1409,7 +1439,7 @@ nfa_status mg_setup(nfa_mg_s& mg, hipStream_t st) {
             for (int f = 0; f < 6; ++f) {
               int arr; long long idx, nb; bool in;
               face(m, f, &arr, &idx, &in, &nb);
-              const int rt = in ? root[nb] : -1;
+              const int rt = in ? root_of(nb) : -1;
               if (rt == c) continue;   // T (z'(c) - z'(c)) = 0
               ut.push_back({arr, (int)idx, c, rt});
             }
