@@ -116,14 +116,6 @@ __host__ __device__ constexpr bool in7(int o) {
   return o == 4 || o == 10 || o == 12 || o == 13 || o == 14 || o == 16 || o == 22;
 }
 
-// acc[o] += v for a run-time o, written so that acc stays in registers (a
-// dynamic index would put the 27 doubles in scratch memory).
-__device__ __forceinline__ void add27(double (&acc)[27], int o, double v) {
-#pragma unroll
-  for (int t = 0; t < 27; ++t)
-    if (t == o) acc[t] += v;
-}
-
 __device__ __forceinline__ void store_row(long long n, long long B, const double* acc, double* A64, float4* S) {
   bool extra = false;
 #pragma unroll

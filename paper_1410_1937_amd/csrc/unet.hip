@@ -372,10 +372,6 @@ __global__ void k_skip_poolT_mask(int D, int H, int W, const bf16_t* __restrict_
 }
 
 // ------------------------------------------------------------ head (16 -> 1)
-__device__ __forceinline__ float s0_at(const bf16_t* a0, const bf16_t* d1, long long p, long long q, int ci) {
-  return bf2f(f2bf(bf2f(a0[p * 16 + ci]) + bf2f(d1[q * 16 + ci])));
-}
-
 // z = dinv * (x0[.,0] + b5 + sum_{t,ci} w5[t][ci] s0[p + off_t][ci]),  s0 = bf16(a0 + up(d1))
 __global__ __launch_bounds__(256) void k_head_fwd(int D, int H, int W, const bf16_t* __restrict__ x0,
                                                   const bf16_t* __restrict__ a0,
