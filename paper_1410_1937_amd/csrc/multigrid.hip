@@ -592,25 +592,27 @@ __device__ __forceinline__ Faces l0_faces(const L0<C>& a, long long c, long long
   return f;
 }
 
-// The down fix-up's terms, formed by the workgroups of the down sweep's
-// launch that follow the sweep's own (ids from nsweep on): they read only the
-// inputs of the cycle's level 0 (r, D^-1, the coefficients and the roots),
-// never what the sweep writes, so they need no launch of their own.
+// The fix-ups' terms, formed by the workgroups of a level-0 sweep's launch
+// that follow the sweep's own (ids from nsweep on): they read only the
+// inputs of the cycle's level 0 (r, D^-1, the coefficients, the roots and,
+// up, the level-1 correction), never what the sweep writes, so they need no
+// launch of their own.
 struct Fix {
   int nsweep = 0;                  // workgroups of the sweep itself
-  int n = 0;                       // fix-up entries (0: none)
-  const int* ent = nullptr;        // entry codes
-  const int* root = nullptr;
-  float* term = nullptr;           // one term per entry
+  int n = 0;                       // terms (0: none)
+  const int* ent = nullptr;        // down: entry codes
+  const int* root = nullptr;       // down: roots
+  const int4* uterm = nullptr;     // up: the listed terms
+  float* term = nullptr;           // one value per term
 };
-template <class C> __device__ void l0_fix_block(const L0<C>& a, const Fix& F, int b);
+template <bool UP, class C> __device__ void l0_fix_block(const L0<C>& a, const Fix& F, int b);
 
 template <bool UP, class C>
 __global__ __launch_bounds__(L0X* L0Y) void k_l0(L0<C> a, float* out, const float* __restrict__ q,
                                                 double* __restrict__ part, Fix fx, const SolveScalars* sc) {
   if (solve_done(sc)) return;
-  if (!UP && (int)blockIdx.x >= fx.nsweep) {
-    l0_fix_block(a, fx, (int)blockIdx.x - fx.nsweep);
+  if ((int)blockIdx.x >= fx.nsweep) {
+    l0_fix_block<UP>(a, fx, (int)blockIdx.x - fx.nsweep);
     return;
   }
   __shared__ float pl[2][L0Y + 2][L0X + 2];
@@ -787,8 +789,8 @@ template <bool UP, class C>
 __global__ __launch_bounds__(L0X* L0Y) void k_l0_x4(L0<C> a, float* out, const float* __restrict__ q,
                                                double* __restrict__ part, Fix fx, const SolveScalars* sc) {
   if (solve_done(sc)) return;
-  if (!UP && (int)blockIdx.x >= fx.nsweep) {
-    l0_fix_block(a, fx, (int)blockIdx.x - fx.nsweep);
+  if ((int)blockIdx.x >= fx.nsweep) {
+    l0_fix_block<UP>(a, fx, (int)blockIdx.x - fx.nsweep);
     return;
   }
   constexpr int W = 4 * L0X;   // cells of a tile row
@@ -1015,11 +1017,6 @@ __global__ void k_l0_fix_sum(int nblk, const int* __restrict__ blk, const int* _
   rc[blk[t]] += d;
 }
 
-// The fix-up workgroups of the down sweep: one thread per entry.
-template <class C> __device__ void l0_fix_block(const L0<C>& a, const Fix& F, int b) {
-  const int t = b * (L0X * L0Y) + (int)threadIdx.x;
-  if (t < F.n) F.term[t] = down_term(a, F.root, F.ent[t]);
-}
 
 // Up fix-up.  The up sweep formed z = z' + omega D^-1 (r - q^) with a
 // slave's value taken as 0 and a root without its slaves' rows.  With the
@@ -1041,24 +1038,29 @@ template <class C> __device__ __forceinline__ float zprime(const L0<C>& a, unsig
   return a.p.w * (cf(a.dinv[y]) * a.r[y]) + a.p.a * a.zc[par];
 }
 
-// step 1: one thread per term
-template <class C>
-__global__ __launch_bounds__(256) void k_l0_up_terms(L0<C> a, int nterm, const int4* __restrict__ terms,
-                                                     float* __restrict__ val, const SolveScalars* sc) {
-  if (solve_done(sc)) return;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nterm) return;
-  const int4 t = terms[e];
+// step 1: the value of one term
+template <class C> __device__ __forceinline__ float up_term(const L0<C>& a, const int4 t) {
   const int arr = t.x & 3;
   const C* base = arr == 0 ? a.tx : arr == 1 ? a.txb : arr == 2 ? a.ty : a.tz;
   const float T = cf(base[(unsigned)t.y]);
   const float z1 = zprime(a, (unsigned)t.z);
   const float z2 = zprime(a, t.w < 0 ? 0u : (unsigned)t.w) * (t.w < 0 ? 0.0f : 1.0f);
   const float v = T * (z1 - z2);
-  val[e] = (t.x & 4) ? -v : v;
+  return (t.x & 4) ? -v : v;
 }
 
-// step 2: one thread per listed row adds its terms in order and applies
+// The fix-up workgroups of a level-0 sweep: one thread per term.
+template <bool UP, class C> __device__ void l0_fix_block(const L0<C>& a, const Fix& F, int b) {
+  const int t = b * (L0X * L0Y) + (int)threadIdx.x;
+  if (t >= F.n) return;
+  if constexpr (UP)
+    F.term[t] = up_term(a, F.uterm[t]);
+  else
+    F.term[t] = down_term(a, F.root, F.ent[t]);
+}
+
+// step 2 (after the up sweep and its trailing workgroups): one thread per
+// listed row adds its terms in order and applies
 // z -= omega D^-1 dq.  The up sweep summed z_old . q for the row; the z.q
 // partial takes the difference.
 template <class C>
@@ -1516,25 +1518,29 @@ void l0_down(nfa_mg_s& mg, const L0<C>& a, bool x4, int nb0, const SolveScalars*
 }
 
 // Level 0 of the cycle, up: the fused sweep (with the z.q partials when
-// parts is given, nb0 of them, the fix-up's after them) and the fix-up.
+// parts is given, nb0 of them, the fix-up's after them), whose trailing
+// workgroups form the fix-up's terms, then the fix-up.
 template <class C>
 void l0_up(nfa_mg_s& mg, const L0<C>& a, bool x4, int nb0, float* z0, const float* qdot, double* parts,
            const SolveScalars* sc, hipStream_t st) {
   Poisson& op = *mg.op;
   Grid& g = *op.g;
+  const int nfix = (int)g.h_fix.size();
   Fix fx;
   fx.nsweep = nb0;
+  if (nfix > 0) {
+    fx.n = mg.nuterm;
+    fx.uterm = mg.uterm.as<int4>();
+    fx.term = mg.uval.as<float>();
+  }
+  const int nb = nb0 + (fx.n + L0X * L0Y - 1) / (L0X * L0Y);
   const bool rec = prof_begin(op, st);
   if (x4)
-    k_l0_x4<true, C><<<nb0, L0X * L0Y, 0, st>>>(a, z0, qdot, parts, fx, sc);
+    k_l0_x4<true, C><<<nb, L0X * L0Y, 0, st>>>(a, z0, qdot, parts, fx, sc);
   else
-    k_l0<true, C><<<nb0, L0X * L0Y, 0, st>>>(a, z0, qdot, parts, fx, sc);
+    k_l0<true, C><<<nb, L0X * L0Y, 0, st>>>(a, z0, qdot, parts, fx, sc);
   prof_end(op, rec, kProfMgUp, st);
-  const int nfix = (int)g.h_fix.size();
   if (nfix > 0) {
-    if (mg.nuterm > 0)
-      k_l0_up_terms<C><<<(mg.nuterm + 255) / 256, 256, 0, st>>>(a, mg.nuterm, mg.uterm.as<int4>(),
-                                                                mg.uval.as<float>(), sc);
     k_l0_up_fix<C><<<(nfix + 255) / 256, 256, 0, st>>>(a, nfix, g.fix_rows.as<int>(), mg.uoff.as<int>(),
                                                         mg.uval.as<float>(), z0, qdot, parts ? parts + nb0 : nullptr, sc);
   }
