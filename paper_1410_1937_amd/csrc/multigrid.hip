@@ -600,10 +600,8 @@ __device__ __forceinline__ Faces l0_faces(const L0<C>& a, long long c, long long
 struct Fix {
   int nsweep = 0;                  // workgroups of the sweep itself
   int n = 0;                       // terms (0: none)
-  const int* ent = nullptr;        // down: entry codes
-  const int* root = nullptr;       // down: roots
-  const int4* uterm = nullptr;     // up: the listed terms
-  float* term = nullptr;           // one value per term
+  const int4* terms = nullptr;     // the listed terms (FixTerm)
+  float* val = nullptr;            // one value per term
 };
 template <bool UP, class C> __device__ void l0_fix_block(const L0<C>& a, const Fix& F, int b);
 
@@ -951,70 +949,33 @@ template <class C> __device__ __forceinline__ Ijk ijk_of(const L0<C>& a, unsigne
   return {(int)(c - row * nx), (int)(row - k * ny), (int)k};
 }
 
-// Down fix-up, step 1: the term of one entry.  An entry c >= 0 (an unknown
-// next to a slave, or a root) owes q~_c - q_c: only its faces to slaves
-// differ, each by T_f z(root of the slave); an entry -(s+1) (a slave whose
-// root lies in the entry's level-1 cell) owes -q_s, the slave's row with
-// merged values.
-template <class C>
-__device__ __forceinline__ float down_term(const L0<C>& a, const int* __restrict__ root, int code) {
-  const unsigned c = code >= 0 ? (unsigned)code : (unsigned)(-(code + 1));
-  const unsigned plane = (unsigned)a.nx * a.ny;
-  const Ijk p = ijk_of(a, c);
-  const int i = p.i, j = p.j, k = p.k;
-  const unsigned yi = ((unsigned)k * (a.ny + 1) + j) * a.nx + i;
-  const bool ok[6] = {i > 0, i < a.nx - 1, j > 0, j < a.ny - 1, k > 0, k < a.nz - 1};
-  const unsigned off[6] = {~0u, 1u, 0u - (unsigned)a.nx, (unsigned)a.nx, 0u - plane, plane};
-  const float m1 = ok[1] ? 1.0f : 0.0f;
-  const float tb = cf(a.txb[(unsigned)k * a.ny + j]);
-  const float txp = cf(a.tx[ok[1] ? c + 1 : c]);
-  const float T[6] = {cf(a.tx[c]), txp * m1 + tb * (1.0f - m1), cf(a.ty[yi]), cf(a.ty[yi + a.nx]), cf(a.tz[c]),
-                      cf(a.tz[c + plane])};
-  // roots of the neighbours, then the smoothed values of the roots, each
-  // batch loaded unconditionally; a neighbour beyond the domain reads the
-  // cell itself, an inactive one (root -1) reads cell 0, and both are
-  // multiplied by 0
-  unsigned nb[6];
-  int rt[6];
-#pragma unroll
-  for (int f = 0; f < 6; ++f) {
-    nb[f] = ok[f] ? c + off[f] : c;
-    rt[f] = root[nb[f]];
+// v[e0] + ... + v[e1 - 1], added left to right, four loads issued at a time
+__device__ __forceinline__ float sum_in_order(const float* __restrict__ v, int e0, int e1) {
+  float d = 0.0f;
+  int e = e0;
+  for (; e + 4 <= e1; e += 4) {
+    const float a = v[e], b = v[e + 1], c = v[e + 2], w = v[e + 3];
+    d = d + a;
+    d = d + b;
+    d = d + c;
+    d = d + w;
   }
-  const int rs = root[c];
-  float zr[6], slave[6];
-#pragma unroll
-  for (int f = 0; f < 6; ++f) {
-    const float m = ok[f] && rt[f] >= 0 ? 1.0f : 0.0f;
-    const int x = rt[f] < 0 ? 0 : rt[f];
-    zr[f] = a.p.w * (cf(a.dinv[x]) * a.r[x]) * m;
-    slave[f] = ok[f] && rt[f] >= 0 && (unsigned)rt[f] != nb[f] ? 1.0f : 0.0f;
-  }
-  float t = 0.0f;
-  if (code >= 0) {
-#pragma unroll
-    for (int f = 0; f < 6; ++f) t += T[f] * zr[f] * slave[f];
-  } else {
-    const int x = rs < 0 ? 0 : rs;
-    const float zs = a.p.w * (cf(a.dinv[x]) * a.r[x]) * (rs < 0 ? 0.0f : 1.0f);
-    float q = T[0] * (zs - zr[0]);
-#pragma unroll
-    for (int f = 1; f < 6; ++f) q = q + T[f] * (zs - zr[f]);
-    t = -q;
-  }
-  return t;
+  for (; e < e1; ++e) d = d + v[e];
+  return d;
 }
 
-// Down fix-up, step 2 (after the sweep and its trailing workgroups): one thread
-// per level-1 cell adds its terms in order.
+// Down fix-up.  Per entry the merged operator owes q~_c - q_c: an unknown c
+// next to a slave, or a root, sum over its faces to slaves of T_f z(root of
+// the slave); a slave s (listed with its root's level-1 cell) minus its row
+// with merged values, sum_f T_f (z(root) - z(neighbour's root)).  The terms
+// are formed by trailing workgroups of the down sweep; then one thread per
+// level-1 cell adds its entries' terms in order.
 __global__ void k_l0_fix_sum(int nblk, const int* __restrict__ blk, const int* __restrict__ off,
                              const float* __restrict__ term, float* rc, const SolveScalars* sc) {
   if (solve_done(sc)) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nblk) return;
-  float d = 0.0f;
-  for (int e = off[t]; e < off[t + 1]; ++e) d += term[e];
-  rc[blk[t]] += d;
+  rc[blk[t]] += sum_in_order(term, off[t], off[t + 1]);
 }
 
 
@@ -1022,29 +983,32 @@ __global__ void k_l0_fix_sum(int nblk, const int* __restrict__ blk, const int* _
 // slave's value taken as 0 and a root without its slaves' rows.  With the
 // merged operator q' = q^ + dq, where dq takes -T_f z'(root of the slave) for
 // each face of the row to a slave and, on a root, adds its slaves' rows
-// sum_f T_f (z'(root) - z'(neighbour's root)); so z -= omega D^-1 dq.  Every
-// term is s T (z'(y1) - z'(y2)) with a stored face, sign and unknown cells
-// (y2 < 0: 0), listed per row when the body is set; z'(y) = omega D^-1 r +
-// alpha z1(parent) is the value before post-smoothing of the unknown y.
-struct UpTerm {
+// sum_f T_f (z'(root) - z'(neighbour's root)); so z -= omega D^-1 dq.
+
+// A term of either fix-up: s T (z(y1) - z(y2)), listed when the body is set.
+struct FixTerm {
   int face;   // coefficient array (0 tx, 1 txb, 2 ty, 3 tz) + 4 for a negative sign
   int idx;    // index in that array
-  int y1, y2;
+  int y1, y2;  // unknowns (y2 < 0: none)
 };
 
-template <class C> __device__ __forceinline__ float zprime(const L0<C>& a, unsigned y) {
+// z of an unknown y: omega D^-1 r after pre-smoothing (down); plus alpha
+// times its parent's level-1 correction before post-smoothing (up)
+template <bool UP, class C> __device__ __forceinline__ float zfix(const L0<C>& a, unsigned y) {
+  const float v = a.p.w * (cf(a.dinv[y]) * a.r[y]);
+  if constexpr (!UP) return v;
   const Ijk p = ijk_of(a, y);
   const unsigned par = ((unsigned)(p.k >> 1) * a.cny + (unsigned)(p.j >> 1)) * a.cnx + (unsigned)(p.i >> 1);
-  return a.p.w * (cf(a.dinv[y]) * a.r[y]) + a.p.a * a.zc[par];
+  return v + a.p.a * a.zc[par];
 }
 
-// step 1: the value of one term
-template <class C> __device__ __forceinline__ float up_term(const L0<C>& a, const int4 t) {
+// the value of one term
+template <bool UP, class C> __device__ __forceinline__ float fix_term(const L0<C>& a, const int4 t) {
   const int arr = t.x & 3;
   const C* base = arr == 0 ? a.tx : arr == 1 ? a.txb : arr == 2 ? a.ty : a.tz;
   const float T = cf(base[(unsigned)t.y]);
-  const float z1 = zprime(a, (unsigned)t.z);
-  const float z2 = zprime(a, t.w < 0 ? 0u : (unsigned)t.w) * (t.w < 0 ? 0.0f : 1.0f);
+  const float z1 = zfix<UP>(a, (unsigned)t.z);
+  const float z2 = zfix<UP>(a, t.w < 0 ? 0u : (unsigned)t.w) * (t.w < 0 ? 0.0f : 1.0f);
   const float v = T * (z1 - z2);
   return (t.x & 4) ? -v : v;
 }
@@ -1052,11 +1016,7 @@ template <class C> __device__ __forceinline__ float up_term(const L0<C>& a, cons
 // The fix-up workgroups of a level-0 sweep: one thread per term.
 template <bool UP, class C> __device__ void l0_fix_block(const L0<C>& a, const Fix& F, int b) {
   const int t = b * (L0X * L0Y) + (int)threadIdx.x;
-  if (t >= F.n) return;
-  if constexpr (UP)
-    F.term[t] = up_term(a, F.uterm[t]);
-  else
-    F.term[t] = down_term(a, F.root, F.ent[t]);
+  if (t < F.n) F.val[t] = fix_term<UP>(a, F.terms[t]);
 }
 
 // step 2 (after the up sweep and its trailing workgroups): one thread per
@@ -1073,8 +1033,7 @@ __global__ __launch_bounds__(256) void k_l0_up_fix(L0<C> a, int nrow, const int*
   double dd = 0.0;
   if (t < nrow) {
     const unsigned c = (unsigned)rows[t];
-    float dq = 0.0f;
-    for (int e = off[t]; e < off[t + 1]; ++e) dq += val[e];
+    const float dq = sum_in_order(val, off[t], off[t + 1]);
     const float zold = z[c];
     const float znew = zold - a.p.w * (cf(a.dinv[c]) * dq);
     z[c] = znew;
@@ -1224,9 +1183,9 @@ struct nfa_mg_s {
   DevBuf group_of, minv, xcnt;
   DevBuf tx16, txb16, ty16, tz16, d16;   // level-0 coefficients and D^-1 rounded to BF16
   bool coef16 = false;          // the cycle's level 0 reads the BF16 copies
-  DevBuf fblk, foff, fent, fterm;   // level-0 down fix-up: level-1 cells, CSR offsets, entries, terms
-  int nfblk = 0, nfent = 0;
-  DevBuf uoff, uterm, uval;         // level-0 up fix-up: CSR offsets per listed row, terms (UpTerm), their values
+  DevBuf fblk, foff, fterm, fval;   // level-0 down fix-up: level-1 cells, CSR offsets, terms (FixTerm), values
+  int nfblk = 0, nfterm = 0;
+  DevBuf uoff, uterm, uval;         // level-0 up fix-up: CSR offsets per listed row, terms (FixTerm), values
   int nuterm = 0;
   int body_version = -1;        // grid body the fix-up lists belong to
   int ncoarse = 0;
@@ -1332,117 +1291,127 @@ nfa_status mg_setup(nfa_mg_s& mg, hipStream_t st) {
     NFA_CHECK_LAUNCH();
   }
   if (mg.body_version != g.body_version) {
-    // level-0 down fix-up entries grouped by level-1 cell, in a fixed order:
-    // the listed rows ascending, then the slaves by their root's cell
-    const Dims& C = mg.lv[1].d;
-    auto blk0 = [&](long long c) {
-      const long long i = c % g.nx, j = (c / g.nx) % g.ny, k = c / ((long long)g.nx * g.ny);
-      return (int)(((k >> 1) * C.ny + (j >> 1)) * C.nx + (i >> 1));
-    };
-    std::vector<std::pair<int, int>> ent;
-    for (int c : g.h_fix) ent.push_back({blk0(c), c});
-    for (size_t t = 0; t < g.h_scell.size(); ++t) ent.push_back({blk0(g.h_sroot[t]), -(g.h_scell[t] + 1)});
-    std::stable_sort(ent.begin(), ent.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
-    std::vector<int> fb, fo, fe;
-    for (size_t e = 0; e < ent.size(); ++e) {
-      if (e == 0 || ent[e].first != ent[e - 1].first) {
-        fb.push_back(ent[e].first);
-        fo.push_back((int)e);
+    // The merge fix-ups' terms, listed once per body.  Every term is
+    // s T_f (z(y1) - z(y2)) with a face coefficient, a sign and one or two
+    // unknowns (y2 < 0: none); z is an unknown's value after pre-smoothing
+    // (down) or before post-smoothing (up).
+    const long long plane = (long long)g.nx * g.ny;
+    // face f of cell c: coefficient array and index, whether it lies inside the domain, the neighbour
+    auto face = [&](long long c, int f, int* arr, long long* idx, bool* in, long long* nb) {
+      const int i = (int)(c % g.nx), j = (int)((c / g.nx) % g.ny), k = (int)(c / plane);
+      const long long yi = ((long long)k * (g.ny + 1) + j) * g.nx + i;
+      switch (f) {
+        case 0: *arr = 0; *idx = c; *in = i > 0; *nb = c - 1; break;
+        case 1:
+          if (i < g.nx - 1) { *arr = 0; *idx = c + 1; } else { *arr = 1; *idx = (long long)k * g.ny + j; }
+          *in = i < g.nx - 1; *nb = c + 1; break;
+        case 2: *arr = 2; *idx = yi; *in = j > 0; *nb = c - g.nx; break;
+        case 3: *arr = 2; *idx = yi + g.nx; *in = j < g.ny - 1; *nb = c + g.nx; break;
+        case 4: *arr = 3; *idx = c; *in = k > 0; *nb = c - plane; break;
+        default: *arr = 3; *idx = c + plane; *in = k < g.nz - 1; *nb = c + plane; break;
       }
-      fe.push_back(ent[e].second);
-    }
-    fo.push_back((int)ent.size());
+    };
+    // each root's slaves, ascending
+    std::map<int, std::vector<int>> members;
+    for (size_t t = 0; t < g.h_scell.size(); ++t) members[g.h_sroot[t]].push_back(g.h_scell[t]);
+    for (auto& m : members) std::sort(m.second.begin(), m.second.end());
     auto up = [&](DevBuf& b, const std::vector<int>& v) -> hipError_t {
       hipError_t e2 = b.alloc(std::max<size_t>(1, v.size()) * sizeof(int));
       if (e2 != hipSuccess || v.empty()) return e2;
       return hipMemcpy(b.p, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice);
     };
-    NFA_HIP(up(mg.fblk, fb));
-    NFA_HIP(up(mg.foff, fo));
-    NFA_HIP(up(mg.fent, fe));
-    NFA_HIP(mg.fterm.alloc(std::max<size_t>(1, fe.size()) * sizeof(float)));
-    mg.nfblk = (int)fb.size();
-    mg.nfent = (int)fe.size();
-    // level-0 up fix-up terms of every listed row, in a fixed order: the
-    // row's faces to slaves, then (a root) its slaves' rows face by face
-    std::vector<int> uo(1, 0);
-    std::vector<UpTerm> ut;
-    if (!g.h_fix.empty()) {
-      std::vector<std::vector<int>> members;
-      std::vector<int> gidx;   // per fix row: index into members, -1 when it has no slaves
-      std::map<int, int> slot;
-      for (size_t t = 0; t < g.h_scell.size(); ++t) {
-        auto it = slot.find(g.h_sroot[t]);
-        if (it == slot.end()) it = slot.emplace(g.h_sroot[t], (int)members.size()).first, members.emplace_back();
-        members[it->second].push_back(g.h_scell[t]);
-      }
-      for (auto& m : members) std::sort(m.begin(), m.end());
-      const long long plane = (long long)g.nx * g.ny;
-      // face f of cell c: coefficient array and index, whether it lies inside the domain, the neighbour
-      auto face = [&](long long c, int f, int* arr, long long* idx, bool* in, long long* nb) {
-        const int i = (int)(c % g.nx), j = (int)((c / g.nx) % g.ny), k = (int)(c / plane);
-        const long long yi = ((long long)k * (g.ny + 1) + j) * g.nx + i;
-        switch (f) {
-          case 0: *arr = 0; *idx = c; *in = i > 0; *nb = c - 1; break;
-          case 1:
-            if (i < g.nx - 1) { *arr = 0; *idx = c + 1; } else { *arr = 1; *idx = (long long)k * g.ny + j; }
-            *in = i < g.nx - 1; *nb = c + 1; break;
-          case 2: *arr = 2; *idx = yi; *in = j > 0; *nb = c - g.nx; break;
-          case 3: *arr = 2; *idx = yi + g.nx; *in = j < g.ny - 1; *nb = c + g.nx; break;
-          case 4: *arr = 3; *idx = c; *in = k > 0; *nb = c - plane; break;
-          default: *arr = 3; *idx = c + plane; *in = k < g.nz - 1; *nb = c + plane; break;
-        }
-      };
-      // the roots the terms need (of the neighbours of the listed rows and of
-      // the slaves), gathered on the device
-      std::vector<int> need;
-      for (const std::vector<int>* list : {&g.h_fix, &g.h_scell})
-        for (int c : *list)
-          for (int f = 0; f < 6; ++f) {
-            int arr; long long idx, nb; bool in;
-            face(c, f, &arr, &idx, &in, &nb);
-            if (in) need.push_back((int)nb);
-          }
-      std::sort(need.begin(), need.end());
-      need.erase(std::unique(need.begin(), need.end()), need.end());
-      std::vector<int> need_root(need.size());
-      {
-        DevBuf d_need, d_out;
-        NFA_HIP(up(d_need, need));
-        NFA_HIP(d_out.alloc(std::max<size_t>(1, need.size()) * sizeof(int)));
-        k_gather_int<<<blocks_for((long long)need.size()), kBlock, 0, st>>>((int)need.size(), d_need.as<int>(),
-                                                                            g.root.as<int>(), d_out.as<int>());
-        NFA_CHECK_LAUNCH();
-        NFA_HIP(hipMemcpyAsync(need_root.data(), d_out.p, need.size() * sizeof(int), hipMemcpyDeviceToHost, st));
-        NFA_HIP(hipStreamSynchronize(st));
-      }
-      auto root_of = [&](long long x) {
-        return need_root[std::lower_bound(need.begin(), need.end(), (int)x) - need.begin()];
-      };
-      for (int c : g.h_fix) {
+    // the roots the terms need (of the neighbours of the listed rows and of
+    // the slaves), gathered on the device
+    std::vector<int> need;
+    for (const std::vector<int>* list : {&g.h_fix, &g.h_scell})
+      for (int c : *list)
         for (int f = 0; f < 6; ++f) {
           int arr; long long idx, nb; bool in;
           face(c, f, &arr, &idx, &in, &nb);
-          if (!in) continue;
-          const int rt = root_of(nb);
-          if (rt >= 0 && rt != nb) ut.push_back({arr | 4, (int)idx, rt, -1});
+          if (in) need.push_back((int)nb);
         }
-        auto it = slot.find(c);
-        if (it != slot.end())
-          for (int m : members[it->second])
-            for (int f = 0; f < 6; ++f) {
-              int arr; long long idx, nb; bool in;
-              face(m, f, &arr, &idx, &in, &nb);
-              const int rt = in ? root_of(nb) : -1;
-              if (rt == c) continue;   // T (z'(c) - z'(c)) = 0
-              ut.push_back({arr, (int)idx, c, rt});
-            }
-        uo.push_back((int)ut.size());
-      }
+    std::sort(need.begin(), need.end());
+    need.erase(std::unique(need.begin(), need.end()), need.end());
+    std::vector<int> need_root(need.size());
+    if (!need.empty()) {
+      DevBuf d_need, d_out;
+      NFA_HIP(up(d_need, need));
+      NFA_HIP(d_out.alloc(need.size() * sizeof(int)));
+      k_gather_int<<<blocks_for((long long)need.size()), kBlock, 0, st>>>((int)need.size(), d_need.as<int>(),
+                                                                          g.root.as<int>(), d_out.as<int>());
+      NFA_CHECK_LAUNCH();
+      NFA_HIP(hipMemcpyAsync(need_root.data(), d_out.p, need.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+      NFA_HIP(hipStreamSynchronize(st));
     }
+    auto root_of = [&](long long x) {
+      return need_root[std::lower_bound(need.begin(), need.end(), (int)x) - need.begin()];
+    };
+    // terms of a row's faces to slaves: s T_f z(root of the slave)
+    auto slave_faces = [&](int c, int sign, std::vector<FixTerm>& out) {
+      for (int f = 0; f < 6; ++f) {
+        int arr; long long idx, nb; bool in;
+        face(c, f, &arr, &idx, &in, &nb);
+        if (!in) continue;
+        const int rt = root_of(nb);
+        if (rt >= 0 && rt != nb) out.push_back({arr | sign, (int)idx, rt, -1});
+      }
+    };
+    // terms of slave m's row with merged values: s T_f (z(root) - z(root of the neighbour))
+    auto slave_row = [&](int m, int rm, int sign, std::vector<FixTerm>& out) {
+      for (int f = 0; f < 6; ++f) {
+        int arr; long long idx, nb; bool in;
+        face(m, f, &arr, &idx, &in, &nb);
+        const int rt = in ? root_of(nb) : -1;
+        if (rt == rm) continue;   // T (z(r) - z(r)) = 0
+        out.push_back({arr | sign, (int)idx, rm, rt});
+      }
+    };
+    // down: q~ - q per entry, entries grouped by level-1 cell in a fixed
+    // order (the listed rows ascending, then the slaves by their root's cell)
+    const Dims& C = mg.lv[1].d;
+    auto blk0 = [&](long long c) {
+      const long long i = c % g.nx, j = (c / g.nx) % g.ny, k = c / plane;
+      return (int)(((k >> 1) * C.ny + (j >> 1)) * C.nx + (i >> 1));
+    };
+    std::vector<std::pair<int, int>> ent;
+    for (int c : g.h_fix) ent.push_back({blk0(c), c});
+    for (size_t t = 0; t < g.h_scell.size(); ++t) ent.push_back({blk0(g.h_sroot[t]), -(int)t - 1});
+    std::stable_sort(ent.begin(), ent.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+    std::vector<int> fb, fo;
+    std::vector<FixTerm> dt;
+    for (size_t e = 0; e < ent.size(); ++e) {
+      if (e == 0 || ent[e].first != ent[e - 1].first) {
+        fb.push_back(ent[e].first);
+        fo.push_back((int)dt.size());
+      }
+      const int code = ent[e].second;
+      if (code >= 0) slave_faces(code, 0, dt);   // an unknown's faces to slaves
+      else slave_row(g.h_scell[-code - 1], g.h_sroot[-code - 1], 4, dt);   // minus a slave's row
+    }
+    fo.push_back((int)dt.size());
+    // up: dq per listed row, its faces to slaves, then (a root) its slaves' rows
+    std::vector<int> uo(1, 0);
+    std::vector<FixTerm> ut;
+    for (int c : g.h_fix) {
+      slave_faces(c, 4, ut);
+      auto it = members.find(c);
+      if (it != members.end())
+        for (int m : it->second) slave_row(m, c, 0, ut);
+      uo.push_back((int)ut.size());
+    }
+    auto up_terms = [&](DevBuf& b, const std::vector<FixTerm>& v) -> hipError_t {
+      hipError_t e2 = b.alloc(std::max<size_t>(1, v.size()) * sizeof(FixTerm));
+      if (e2 != hipSuccess || v.empty()) return e2;
+      return hipMemcpy(b.p, v.data(), v.size() * sizeof(FixTerm), hipMemcpyHostToDevice);
+    };
+    NFA_HIP(up(mg.fblk, fb));
+    NFA_HIP(up(mg.foff, fo));
+    NFA_HIP(up_terms(mg.fterm, dt));
+    NFA_HIP(mg.fval.alloc(std::max<size_t>(1, dt.size()) * sizeof(float)));
+    mg.nfblk = (int)fb.size();
+    mg.nfterm = (int)dt.size();
     NFA_HIP(up(mg.uoff, uo));
-    NFA_HIP(mg.uterm.alloc(std::max<size_t>(1, ut.size()) * sizeof(UpTerm)));
-    if (!ut.empty()) NFA_HIP(hipMemcpy(mg.uterm.p, ut.data(), ut.size() * sizeof(UpTerm), hipMemcpyHostToDevice));
+    NFA_HIP(up_terms(mg.uterm, ut));
     NFA_HIP(mg.uval.alloc(std::max<size_t>(1, ut.size()) * sizeof(float)));
     mg.nuterm = (int)ut.size();
     mg.body_version = g.body_version;
@@ -1496,14 +1465,12 @@ nfa_status mg_setup(nfa_mg_s& mg, hipStream_t st) {
 template <class C>
 void l0_down(nfa_mg_s& mg, const L0<C>& a, bool x4, int nb0, const SolveScalars* sc, hipStream_t st) {
   Poisson& op = *mg.op;
-  Grid& g = *op.g;
   Fix fx;
   fx.nsweep = nb0;
   if (mg.nfblk > 0) {
-    fx.n = mg.nfent;
-    fx.ent = mg.fent.as<int>();
-    fx.root = g.root.as<int>();
-    fx.term = mg.fterm.as<float>();
+    fx.n = mg.nfterm;
+    fx.terms = mg.fterm.as<int4>();
+    fx.val = mg.fval.as<float>();
   }
   const int nb = nb0 + (fx.n + L0X * L0Y - 1) / (L0X * L0Y);
   const bool rec = prof_begin(op, st);
@@ -1514,7 +1481,7 @@ void l0_down(nfa_mg_s& mg, const L0<C>& a, bool x4, int nb0, const SolveScalars*
   prof_end(op, rec, kProfMgDown, st);
   if (mg.nfblk > 0)
     k_l0_fix_sum<<<(mg.nfblk + 255) / 256, 256, 0, st>>>(mg.nfblk, mg.fblk.as<int>(), mg.foff.as<int>(),
-                                                         mg.fterm.as<float>(), mg.lv[1].r.as<float>(), sc);
+                                                         mg.fval.as<float>(), mg.lv[1].r.as<float>(), sc);
 }
 
 // Level 0 of the cycle, up: the fused sweep (with the z.q partials when
@@ -1530,8 +1497,8 @@ void l0_up(nfa_mg_s& mg, const L0<C>& a, bool x4, int nb0, float* z0, const floa
   fx.nsweep = nb0;
   if (nfix > 0) {
     fx.n = mg.nuterm;
-    fx.uterm = mg.uterm.as<int4>();
-    fx.term = mg.uval.as<float>();
+    fx.terms = mg.uterm.as<int4>();
+    fx.val = mg.uval.as<float>();
   }
   const int nb = nb0 + (fx.n + L0X * L0Y - 1) / (L0X * L0Y);
   const bool rec = prof_begin(op, st);
