@@ -1051,11 +1051,12 @@ __global__ __launch_bounds__(256) void k_l0_up_fix(L0<C> a, int nrow, const int*
 struct TailArgs {
   int first, last;                 // last = the coarsest level
   int off[kMaxLevels];
+  int soff[kMaxLevels];            // LDS copy of S of level l < last at [soff[l], soff[l] + 4 n_l) (16-byte aligned)
   LevelView lv[kMaxLevels];
   Cyc p;
   const float* rin;                // r of level `first`
   float* zout;                     // z of level `first`
-  const double* minv;              // coarsest dense inverse (column-major)
+  const double* minv;              // coarsest dense inverse (row-major)
 };
 
 __global__ __launch_bounds__(1024) void k_tail(TailArgs A, const SolveScalars* sc) {
@@ -1063,12 +1064,24 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs A, const SolveScalars* s
   extern __shared__ float lds[];
   const int t = threadIdx.x, nt = blockDim.x;
   auto cells = [&](int l) { return A.lv[l].nx * A.lv[l].ny * A.lv[l].nz; };
+  // r of the first level and the cycle storage of every level but the
+  // coarsest, into LDS in one round of loads; the levels' views then read S
+  // there (their side lists stay in global memory)
   for (int c = t; c < cells(A.first); c += nt) lds[A.off[A.first] + c] = A.rin[c];
+  for (int l = A.first; l < A.last; ++l) {
+    float4* s = reinterpret_cast<float4*>(lds + A.soff[l]);
+    for (int c = t; c < cells(l); c += nt) s[c] = A.lv[l].S[c];
+  }
   __syncthreads();
+  auto view = [&](int l) {
+    LevelView v = A.lv[l];
+    if (l < A.last) v.S = reinterpret_cast<const float4*>(lds + A.soff[l]);
+    return v;
+  };
   // down: a thread per fine cell (its term parked in the level's z slot,
   // unused until the way up), then a thread per coarse cell sums 8 terms
   for (int l = A.first; l < A.last; ++l) {
-    const LevelView& F = A.lv[l];
+    const LevelView F = view(l);
     const LevelView& C = A.lv[l + 1];
     const float* r = lds + A.off[l];
     float* v = lds + A.off[l] + cells(l);
@@ -1101,13 +1114,13 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs A, const SolveScalars* s
     const int i = t / G, q = t % G;
     double s = 0.0;
     if (i < N)
-      for (int jc = q; jc < N; jc += G) s += A.minv[(long long)jc * N + i] * (double)r[jc];
+      for (int jc = q; jc < N; jc += G) s += A.minv[(long long)i * N + jc] * (double)r[jc];
     for (int m = 1; m < G; m <<= 1) s += __shfl_xor(s, m, 64);
     if (i < N && q == 0) z[i] = (float)s;
   }
   __syncthreads();
   for (int l = A.last - 1; l >= A.first; --l) {
-    const LevelView& F = A.lv[l];
+    const LevelView F = view(l);
     const LevelView& C = A.lv[l + 1];
     const float* r = lds + A.off[l];
     float* z = lds + A.off[l] + cells(l);
@@ -1202,11 +1215,13 @@ namespace {
 // has at most tail_cells cells and the tail's vectors fit in LDS.
 void plan_tail(nfa_mg_s& mg) {
   int first = mg.L - 1;
-  long long floats = 2 * mg.lv[first].d.n;
+  // LDS floats: r and z of every tail level, a float4 copy of S of each
+  // but the coarsest, and 3 floats of alignment padding
+  long long floats = 2 * mg.lv[first].d.n + 3;
   while (first > 1) {
     const long long n = mg.lv[first - 1].d.n;
-    if (n > mg.tail_cells || (floats + 2 * n) * 4 > kTailLdsBytes) break;
-    floats += 2 * n;
+    if (n > mg.tail_cells || (floats + 6 * n) * 4 > kTailLdsBytes) break;
+    floats += 6 * n;
     --first;
   }
   mg.first_tail = first;
@@ -1453,8 +1468,12 @@ nfa_status mg_setup(nfa_mg_s& mg, hipStream_t st) {
     if (empty[a])
       for (int b = 0; b < N; ++b) M[(size_t)a * N + b] = M[(size_t)b * N + a] = (a == b) ? 1.0 : 0.0;
   if (!spd_inverse(M, N)) return fail(NFA_ERR_NUMERIC, "multigrid: coarsest matrix is not positive definite");
-  // M is symmetric: its column-major and row-major layouts agree
-  NFA_HIP(hipMemcpyAsync(mg.minv.p, M.data(), M.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  // the inverse comes column by column; the tail kernel reads it by rows
+  // (consecutive lanes, consecutive columns)
+  std::vector<double> Mt((size_t)N * N);
+  for (int a = 0; a < N; ++a)
+    for (int b = 0; b < N; ++b) Mt[(size_t)a * N + b] = M[(size_t)b * N + a];
+  NFA_HIP(hipMemcpyAsync(mg.minv.p, Mt.data(), Mt.size() * sizeof(double), hipMemcpyHostToDevice, st));
   NFA_HIP(hipStreamSynchronize(st));
   mg.built_version = op.version;
   return NFA_OK;
@@ -1564,6 +1583,11 @@ nfa_status mg_vcycle(nfa_mg_s& mg, const float* r0, float* z0, const float* qdot
       A.off[l] = off;
       A.lv[l] = mg.lv[l].view();
       off += 2 * (int)mg.lv[l].d.n;
+    }
+    off = (off + 3) & ~3;   // 16-byte alignment of the S copies
+    for (int l = T; l < mg.L - 1; ++l) {
+      A.soff[l] = off;
+      off += 4 * (int)mg.lv[l].d.n;
     }
     A.p = p;
     A.rin = mg.lv[T].r.as<float>();
