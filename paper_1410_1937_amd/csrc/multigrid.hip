@@ -520,9 +520,10 @@ __global__ __launch_bounds__(256) void k_up(LevelView L, Cyc p, int tiles_x, int
 //         z = zp + omega D^-1 (r - q) on the unknowns (0 elsewhere).
 // Both treat every cell on its own: a slave's value is taken as 0 and its
 // row is not moved to its root.  The rows this changes (roots, and unknowns
-// next to a slave) are redone afterwards by the fix-up kernels with the
-// merged operator: slaves take their root's value, roots add their slaves'
-// rows.
+// next to a slave) are corrected to the merged operator (slaves take their
+// root's value, roots add their slaves' rows) from term lists built when the
+// body is set: trailing workgroups of each sweep's launch form the terms, a
+// small kernel after it adds them in.
 template <class C>
 struct L0 {
   int nx, ny, nz, kchunk, tiles_x, tiles_y;
@@ -991,6 +992,7 @@ struct FixTerm {
   int idx;    // index in that array
   int y1, y2;  // unknowns (y2 < 0: none)
 };
+static_assert(sizeof(FixTerm) == sizeof(int4), "a FixTerm is read on the device as one int4");
 
 // z of an unknown y: omega D^-1 r after pre-smoothing (down); plus alpha
 // times its parent's level-1 correction before post-smoothing (up)
