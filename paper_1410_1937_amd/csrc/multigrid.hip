@@ -1332,7 +1332,7 @@ nfa_status mg_setup(nfa_mg_s& mg, hipStream_t st) {
     std::map<int, std::vector<int>> members;
     for (size_t t = 0; t < g.h_scell.size(); ++t) members[g.h_sroot[t]].push_back(g.h_scell[t]);
     for (auto& m : members) std::sort(m.second.begin(), m.second.end());
-    auto up = [&](DevBuf& b, const std::vector<int>& v) -> hipError_t {
+    auto upload = [&](DevBuf& b, const std::vector<int>& v) -> hipError_t {
       hipError_t e2 = b.alloc(std::max<size_t>(1, v.size()) * sizeof(int));
       if (e2 != hipSuccess || v.empty()) return e2;
       return hipMemcpy(b.p, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice);
@@ -1352,7 +1352,7 @@ nfa_status mg_setup(nfa_mg_s& mg, hipStream_t st) {
     std::vector<int> need_root(need.size());
     if (!need.empty()) {
       DevBuf d_need, d_out;
-      NFA_HIP(up(d_need, need));
+      NFA_HIP(upload(d_need, need));
       NFA_HIP(d_out.alloc(need.size() * sizeof(int)));
       k_gather_int<<<blocks_for((long long)need.size()), kBlock, 0, st>>>((int)need.size(), d_need.as<int>(),
                                                                           g.root.as<int>(), d_out.as<int>());
@@ -1416,19 +1416,19 @@ nfa_status mg_setup(nfa_mg_s& mg, hipStream_t st) {
         for (int m : it->second) slave_row(m, c, 0, ut);
       uo.push_back((int)ut.size());
     }
-    auto up_terms = [&](DevBuf& b, const std::vector<FixTerm>& v) -> hipError_t {
+    auto upload_terms = [&](DevBuf& b, const std::vector<FixTerm>& v) -> hipError_t {
       hipError_t e2 = b.alloc(std::max<size_t>(1, v.size()) * sizeof(FixTerm));
       if (e2 != hipSuccess || v.empty()) return e2;
       return hipMemcpy(b.p, v.data(), v.size() * sizeof(FixTerm), hipMemcpyHostToDevice);
     };
-    NFA_HIP(up(mg.fblk, fb));
-    NFA_HIP(up(mg.foff, fo));
-    NFA_HIP(up_terms(mg.fterm, dt));
+    NFA_HIP(upload(mg.fblk, fb));
+    NFA_HIP(upload(mg.foff, fo));
+    NFA_HIP(upload_terms(mg.fterm, dt));
     NFA_HIP(mg.fval.alloc(std::max<size_t>(1, dt.size()) * sizeof(float)));
     mg.nfblk = (int)fb.size();
     mg.nfterm = (int)dt.size();
-    NFA_HIP(up(mg.uoff, uo));
-    NFA_HIP(up_terms(mg.uterm, ut));
+    NFA_HIP(upload(mg.uoff, uo));
+    NFA_HIP(upload_terms(mg.uterm, ut));
     NFA_HIP(mg.uval.alloc(std::max<size_t>(1, ut.size()) * sizeof(float)));
     mg.nuterm = (int)ut.size();
     mg.body_version = g.body_version;
