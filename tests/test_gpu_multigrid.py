@@ -88,6 +88,31 @@ def test_one_vcycle_matches_the_oracle(body, bc, shape, tail):
 
 
 @pytest.mark.parametrize("tail", [-1, 0])
+def test_vcycle_with_merges_at_a_dirichlet_wall(tail):
+    """A sphere cut by the bottom wall, which holds p = 0: slaves and roots
+    lie on the wall, so the merged rows' corrections meet boundary faces with
+    nonzero coefficients."""
+    import dataclasses
+    wl = fx.small(11, 60, 28, 24, body="sphere", bc=(0, 0, 0, 0, 1, 0))
+    wl = dataclasses.replace(wl, psi=fx.psi_sphere(wl.xf, wl.yf, wl.zf, radius=0.15, centre=(0.02, 0.01, -0.47)))
+    og, ob, oop, b = oracle_for(wl)
+    root = ob.root.reshape(og.shape)
+    slave = (root >= 0) & (root != np.arange(root.size).reshape(og.shape))
+    assert slave[0].sum() > 0   # slaves on the wall layer
+    H = multigrid.Hierarchy(oop)
+    g, op = gpu_for(wl)
+    mg = op.multigrid()
+    mg.set_tail(tail)
+    mg.setup()
+    red = oop.reduced_mask() > 0
+    r = np.where(red, np.random.default_rng(3).standard_normal(og.shape), 0.0).astype(np.float32)
+    z = host(mg.apply(torch.as_tensor(r, device="cuda")))
+    ref = oop.expand(H.precond(r.astype(np.float64)))
+    act = red | (root >= 0)
+    assert rel_l2(z[act], ref[act]) <= 1e-4
+
+
+@pytest.mark.parametrize("tail", [-1, 0])
 def test_vcycle_with_other_damping_and_coarse_scale(tail):
     wl = fx.small(8, 64, 48, 40, body="sphere")
     og, ob, oop, b = oracle_for(wl)
