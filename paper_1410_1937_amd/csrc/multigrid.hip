@@ -1204,6 +1204,7 @@ struct nfa_mg_s {
   int nuterm = 0;
   int body_version = -1;        // grid body the fix-up lists belong to
   int ncoarse = 0;
+  int cus = 1;                  // compute units of the device the handle was made on
   int tail_cells = kDefaultTailCells;
   double omega = kDefaultOmega, alpha = kDefaultAlpha;
   int first_tail = 1;           // first level run by the one-workgroup tail kernel
@@ -1553,9 +1554,13 @@ nfa_status mg_vcycle(nfa_mg_s& mg, const float* r0, float* z0, const float* qdot
   // 4 cells per lane when rows and every per-cell array allow 16-byte loads
   const bool x4 = d0.nx % 4 == 0 && ((uintptr_t)r0 % 16) == 0 && ((uintptr_t)z0 % 16) == 0;
   const int tw = x4 ? 4 * L0X : L0X;
-  L0<float> a32{d0.nx, d0.ny, d0.nz, 16, (d0.nx + tw - 1) / tw, (d0.ny + L0Y - 1) / L0Y, c32.tx, c32.txb, c32.ty,
+  // planes per workgroup: 32 (fewer re-read chunk-boundary planes) when the
+  // sweep still has a workgroup for each of the 3 resident slots per CU, else 16
+  const long long cols = (long long)((d0.nx + tw - 1) / tw) * ((d0.ny + L0Y - 1) / L0Y);
+  const int kchunk = cols * ((d0.nz + 31) / 32) >= 3LL * mg.cus ? 32 : 16;
+  L0<float> a32{d0.nx, d0.ny, d0.nz, kchunk, (d0.nx + tw - 1) / tw, (d0.ny + L0Y - 1) / L0Y, c32.tx, c32.txb, c32.ty,
                 c32.tz, c32.dinv, r0, red, p, C1.nx, C1.ny, nullptr};
-  L0<unsigned short> a16{d0.nx, d0.ny, d0.nz, 16, a32.tiles_x, a32.tiles_y, mg.tx16.as<unsigned short>(),
+  L0<unsigned short> a16{d0.nx, d0.ny, d0.nz, kchunk, a32.tiles_x, a32.tiles_y, mg.tx16.as<unsigned short>(),
                          mg.txb16.as<unsigned short>(), mg.ty16.as<unsigned short>(), mg.tz16.as<unsigned short>(),
                          mg.d16.as<unsigned short>(), r0, red, p, C1.nx, C1.ny, nullptr};
   const int nb0 = a32.tiles_x * a32.tiles_y * ((d0.nz + a32.kchunk - 1) / a32.kchunk);
@@ -1640,6 +1645,12 @@ extern "C" nfa_status nfa_mg_create(nfa_poisson op, nfa_mg* out) {
   if (!op) return fail(NFA_ERR_INVALID, "nfa_mg_create: NULL operator");
   auto* mg = new nfa_mg_s();
   mg->op = op;
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      mg->cus = cus;
+  }
   Grid& g = *op->g;
   mg->lv[0].d = make_dims(g.nx, g.ny, g.nz);
   mg->L = 1;
