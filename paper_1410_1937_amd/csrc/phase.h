@@ -1,6 +1,5 @@
-// Solver-state transitions applied after each reduction (device code shared
-// by the standalone finalize kernel and the last workgroup of the fused CG
-// sweeps).  Header-only: device functions do not link across files here.
+// Solver-state transitions applied after each reduction by the finalize
+// kernels.  Header-only: device functions do not link across files here.
 #pragma once
 
 #include <hip/hip_runtime.h>
