@@ -298,13 +298,17 @@ void nfa_mg_destroy(nfa_mg mg);
  * (call after each nfa_poisson_assemble; nfa_poisson_solve with NFA_PC_MG
  * calls it when the operator has changed).  Synchronous (the side lists
  * are scanned and the coarsest inverse formed on the host).  Allocates only
- * when a side list outgrows what creation reserved (merge set grown since).
+ * when a side list outgrows what creation reserved (merge set grown since)
+ * and, on the first set-up after the grid's body was set, for the merged
+ * rows' correction terms (16 bytes a term, a few per merged cell; the roots
+ * they need are gathered on the device and read back).
  * Errors: NFA_ERR_INVALID (not assembled), NFA_ERR_NUMERIC (coarsest matrix
  * not positive definite), NFA_ERR_HIP. */
 nfa_status nfa_mg_setup(nfa_mg mg, nfa_stream s);
 /* nfa_mg_set_tail -- the single-workgroup part of the cycle starts at the
- * first level with at most max_cells cells whose vectors (with those of
- * every coarser level) fit in 64 KiB of LDS; 0: only the coarsest level;
+ * first level with at most max_cells cells whose two vectors and float4
+ * cycle storage (with those of every coarser level) fit in 64 KiB of LDS;
+ * 0: only the coarsest level;
  * < 0: the default, 1024.  Changes no result beyond FP32 rounding order. */
 nfa_status nfa_mg_set_tail(nfa_mg mg, int max_cells);
 /* nfa_mg_apply -- z = V(r), one V-cycle; r, z: DEVICE float cells (r zero
