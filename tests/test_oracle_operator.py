@@ -213,3 +213,43 @@ def test_rhs_is_compatible_before_mean_removal():
     raw = (op.divergence(Fx, Fy, Fz) + op.body_flux((0.3, -0.2, 0.5))) * body.active
     scale = np.sum(np.abs(raw))
     assert abs(raw.sum()) <= 1e-13 * scale
+
+
+def _wall_sphere_case(theta):
+    """A sphere cut by the bottom wall, which holds p = 0 (Dirichlet): merge
+    groups lie on the wall, so their diagonals take boundary faces."""
+    import dataclasses
+    wl = fx.small(11, 20, 12, 10, body="sphere", bc=(0, 0, 0, 0, 1, 0), theta=theta)
+    wl = dataclasses.replace(wl, psi=fx.psi_sphere(wl.xf, wl.yf, wl.zf, radius=0.15, centre=(0.02, 0.01, -0.47)))
+    g = Grid(wl.xf, wl.yf, wl.zf, wl.bc)
+    body = Body(g, wl.psi, wl.theta)
+    return g, body, Operator(g, body, wl.phi, smooth=True)
+
+
+@pytest.mark.parametrize("case", ["neumann", "dirichlet_top", "dirichlet_sides", "dirichlet_wall"])
+def test_jacobi_diagonal_is_the_diagonal_of_the_merged_matrix(case):
+    """The group Jacobi inverse (Introduction: the PCG preconditioner; merged
+    rows from Enforcement of Body Boundary Conditions) is 1/diag(P^T A P),
+    with the merged matrix formed by sparse products from the face list, and
+    zero on slaves and on inactive cells.  A group's diagonal is the sum of
+    its members' faces that lead out of the group: counting the faces between
+    two members as well (or leaving out a boundary face) moves it by at least
+    one face coefficient.  A merge threshold of 0.95 chains cut cells into
+    groups of three members."""
+    if case == "dirichlet_wall":
+        g, body, op = _wall_sphere_case(0.95)
+        nxy = g.shape[1] * g.shape[2]
+        assert any(len(m) >= 3 and any(c // nxy == 0 for c in m) for m in body.groups.values())
+    else:
+        bc = {"neumann": (0,) * 6, "dirichlet_top": (0, 0, 0, 0, 0, 1),
+              "dirichlet_sides": (1, 0, 0, 1, 0, 0)}[case]
+        wl, g, body, op = _body_case(bc=bc, theta=0.95)
+    assert sum(len(m) >= 3 for m in body.groups.values()) >= 3
+    diag = op.csr().diagonal().reshape(g.shape)
+    red = body.reduced
+    assert np.all(diag[red] > 0)
+    rel = np.abs(op.dinv[red] * diag[red] - 1.0)
+    assert np.max(rel) <= 1e-14
+    assert np.all(op.dinv[~red] == 0.0)
+    # rows of the cells that carry no unknown are empty in the merged matrix
+    assert np.all(diag[~red] == 0.0)
