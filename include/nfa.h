@@ -107,7 +107,10 @@ nfa_status nfa_grid_create(int nx, int ny, int nz, const double* xf, const doubl
  * interpolant that are > 0; cell fractions likewise with S^3 trilinear
  * samples.  Cells with fraction 0 or without an open coupling become
  * inactive (no unknown).  Synchronous (merge groups are resolved on the
- * host).  Errors: NFA_ERR_INVALID, NFA_ERR_HIP.
+ * host).  A new body leaves every operator of the grid stale: until it is
+ * assembled again, nfa_poisson_apply, _solve, _residual, _project,
+ * nfa_poisson_velocity, the learned and multigrid preconditioners return
+ * NFA_ERR_INVALID.  Errors: NFA_ERR_INVALID, NFA_ERR_HIP.
  */
 /* nfa_stretch_axis -- face coordinates of one stretched axis (Gridding
  * section, eq. grid): the n + 1 nodes x_0 = a < ... < x_n = b that solve

@@ -361,13 +361,14 @@ extern "C" nfa_status nfa_poisson_assemble(nfa_poisson op, const void* phi,
   NFA_CHECK_LAUNCH();
   op->assembled = true;
   op->version += 1;
+  op->body_version = g.body_version;
   return NFA_OK;
 }
 
 extern "C" nfa_status nfa_poisson_apply(nfa_poisson op, const void* x, void* y, int dtype,
                                         nfa_stream s) {
   if (!op || !x || !y) return fail(NFA_ERR_INVALID, "nfa_poisson_apply: NULL argument");
-  if (!op->assembled) return fail(NFA_ERR_INVALID, "nfa_poisson_apply: operator not assembled");
+  if (const nfa_status e = require_assembled(*op, "nfa_poisson_apply")) return e;
   if (x == y) return fail(NFA_ERR_INVALID, "nfa_poisson_apply: x and y must not overlap");
   Grid& g = *op->g;
   const hipStream_t st = S(s);
@@ -440,7 +441,7 @@ extern "C" nfa_status nfa_poisson_project(nfa_poisson op, const double* u, const
                                           double* fv, double* fw, nfa_stream s) {
   if (!op || !u || !v || !w || !p || !fu || !fv || !fw)
     return fail(NFA_ERR_INVALID, "nfa_poisson_project: NULL argument");
-  if (!op->assembled) return fail(NFA_ERR_INVALID, "nfa_poisson_project: operator not assembled");
+  if (const nfa_status e = require_assembled(*op, "nfa_poisson_project")) return e;
   Grid& g = *op->g;
   const hipStream_t st = S(s);
   const double* src = p;

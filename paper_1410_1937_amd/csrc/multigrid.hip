@@ -1270,7 +1270,7 @@ nfa_status build_side_list(nfa_mg_s& mg, Level& C, hipStream_t st) {
 nfa_status mg_setup(nfa_mg_s& mg, hipStream_t st) {
   Poisson& op = *mg.op;
   Grid& g = *op.g;
-  if (!op.assembled) return fail(NFA_ERR_INVALID, "multigrid: operator not assembled");
+  if (const nfa_status e = require_assembled(op, "multigrid")) return e;
   k_fill_int<<<blocks_for(g.n), kBlock, 0, st>>>(g.n, -1, mg.group_of.as<int>());
   if (g.n_groups > 0)
     k_group_of<<<blocks_for(g.n_groups), kBlock, 0, st>>>(g.n_groups, g.g_root.as<int>(), mg.group_of.as<int>());
@@ -1634,7 +1634,7 @@ nfa_status mg_ensure(void* mgh, Poisson& op, hipStream_t st) {
   if (!mgh) return fail(NFA_ERR_INVALID, "multigrid preconditioner: no handle");
   nfa_mg_s& mg = *static_cast<nfa_mg_s*>(mgh);
   if (mg.op != &op) return fail(NFA_ERR_INVALID, "multigrid preconditioner: built for another operator");
-  return mg.built_version == op.version ? NFA_OK : mg_setup(mg, st);
+  return mg.built_version == op.version && mg.body_version == op.g->body_version ? NFA_OK : mg_setup(mg, st);
 }
 
 }  // namespace nfa
@@ -1703,8 +1703,8 @@ extern "C" nfa_status nfa_mg_setup(nfa_mg mg, nfa_stream s) {
 extern "C" nfa_status nfa_mg_apply(nfa_mg mg, const float* r, float* z, nfa_stream s) {
   if (!mg || !r || !z) return fail(NFA_ERR_INVALID, "nfa_mg_apply: NULL argument");
   if (r == z) return fail(NFA_ERR_INVALID, "nfa_mg_apply: r and z must differ");
-  if (mg->built_version != mg->op->version)
-    return fail(NFA_ERR_INVALID, "nfa_mg_apply: call nfa_mg_setup after the last assembly");
+  if (mg->built_version != mg->op->version || mg->body_version != mg->op->g->body_version)
+    return fail(NFA_ERR_INVALID, "nfa_mg_apply: call nfa_mg_setup after the last assembly (and after a new body)");
   const nfa_status e = mg_vcycle(*mg, r, z, nullptr, nullptr, nullptr, nullptr, S(s));
   if (e != NFA_OK) return e;
   launch_merge_copy<float>(*mg->op->g, z, S(s), nullptr);

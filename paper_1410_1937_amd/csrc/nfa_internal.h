@@ -119,6 +119,7 @@ struct Poisson {
   Grid* g = nullptr;
   bool assembled = false;
   int version = 0;                              // incremented by every assembly
+  int body_version = -1;                        // the grid's body version at the last assembly
   DevBuf rho, rho_tmp;                          // double cells
   DevBuf tx64, txb64, ty64, tz64, dinv64;       // FP64 coefficients
   DevBuf tx32, txb32, ty32, tz32, dinv32;       // FP32 coefficients
@@ -149,6 +150,16 @@ struct Poisson {
 };
 
 constexpr int kProfMgDown = 2, kProfMgUp = 3, kProfKinds = 4;
+
+// The operator holds coefficients of its grid's current body: assembled, and
+// no nfa_grid_set_body since (a new body changes the apertures, the active
+// set and the merge groups that the coefficients and D^-1 were formed from).
+inline nfa_status require_assembled(const Poisson& op, const char* who) {
+  if (!op.assembled) return fail(NFA_ERR_INVALID, std::string(who) + ": operator not assembled");
+  if (op.body_version != op.g->body_version)
+    return fail(NFA_ERR_INVALID, std::string(who) + ": the grid's body was set after the last assembly; assemble again");
+  return NFA_OK;
+}
 
 // Open / close the timing of one launch on st when profiling is on.
 inline bool prof_begin(Poisson& op, hipStream_t st) {

@@ -124,7 +124,7 @@ extern "C" nfa_status nfa_poisson_velocity(nfa_poisson op, const double* ut_x, c
                                            nfa_stream s) {
   if (!op || !ut_x || !ut_y || !ut_z || !p || !u_x || !u_y || !u_z)
     return fail(NFA_ERR_INVALID, "nfa_poisson_velocity: NULL argument");
-  if (!op->assembled) return fail(NFA_ERR_INVALID, "nfa_poisson_velocity: operator not assembled");
+  if (const nfa_status e = require_assembled(*op, "nfa_poisson_velocity")) return e;
   if (!(dt > 0) || !std::isfinite(scale))
     return fail(NFA_ERR_INVALID, "nfa_poisson_velocity: dt must be > 0 and scale finite");
   Grid& g = *op->g;

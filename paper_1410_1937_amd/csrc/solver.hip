@@ -313,7 +313,7 @@ extern "C" void nfa_solve_opts_default(nfa_solve_opts* o) {
 extern "C" nfa_status nfa_poisson_solve(nfa_poisson op, const double* b, double* x,
                                         const nfa_solve_opts* o, nfa_stream s, nfa_solve_info* info) {
   if (!op || !b || !x || !o || !info) return fail(NFA_ERR_INVALID, "nfa_poisson_solve: NULL argument");
-  if (!op->assembled) return fail(NFA_ERR_INVALID, "nfa_poisson_solve: operator not assembled");
+  if (const nfa_status e = require_assembled(*op, "nfa_poisson_solve")) return e;
   if (!(o->tol > 0) || o->max_iters < 1 || o->check_every < 1)
     return fail(NFA_ERR_INVALID, "nfa_poisson_solve: tol > 0, max_iters >= 1, check_every >= 1 required");
   if (o->precision != NFA_PREC_F64 && o->precision != NFA_PREC_MIXED)
@@ -403,7 +403,7 @@ extern "C" nfa_status nfa_poisson_profile_read(nfa_poisson op, int dtype, nfa_ke
 extern "C" nfa_status nfa_poisson_residual(nfa_poisson op, const double* b, const double* x, double* r,
                                            double* rr, nfa_stream s) {
   if (!op || !b || !x || !r) return fail(NFA_ERR_INVALID, "nfa_poisson_residual: NULL argument");
-  if (!op->assembled) return fail(NFA_ERR_INVALID, "nfa_poisson_residual: operator not assembled");
+  if (const nfa_status e = require_assembled(*op, "nfa_poisson_residual")) return e;
   if (x == r) return fail(NFA_ERR_INVALID, "nfa_poisson_residual: r must not alias x");
   Grid& g = *op->g;
   const hipStream_t st = S(s);

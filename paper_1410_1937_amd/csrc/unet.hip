@@ -792,7 +792,7 @@ nfa_status backward(UNet& u, Poisson& op, hipStream_t s) {
 }
 
 nfa_status grad_step(UNet& u, Poisson& op, const float* r, double eAe, double* loss, hipStream_t s) {
-  if (!op.assembled) return fail(NFA_ERR_INVALID, "learned preconditioner: operator not assembled");
+  if (const nfa_status e = require_assembled(op, "learned preconditioner")) return e;
   if (!(eAe > 0)) return fail(NFA_ERR_INVALID, "learned preconditioner: eAe must be > 0");
   double* scal = u.scal.as<double>();
   double* parts = op.partials.as<double>();
@@ -945,7 +945,7 @@ extern "C" nfa_status nfa_unet_get_grads(nfa_unet u, float* host) {
 
 extern "C" nfa_status nfa_unet_forward(nfa_unet u, nfa_poisson op, const float* r, float* z, nfa_stream s) {
   if (!u || !op || !r || !z) return fail(NFA_ERR_INVALID, "nfa_unet_forward: NULL argument");
-  if (!op->assembled) return fail(NFA_ERR_INVALID, "nfa_unet_forward: operator not assembled");
+  if (const nfa_status e = require_assembled(*op, "nfa_unet_forward")) return e;
   const hipStream_t st = S(s);
   double* parts = op->partials.as<double>();
   const int nb = launch_dot<float>(r, r, u->npos[0], parts, nullptr, st);

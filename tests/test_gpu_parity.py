@@ -29,6 +29,12 @@ def _cases():
         # three FP32 column tiles across x (the last 8 cells wide), five FP64
         # ones, and a partial 16-row tile in y
         "wide_ragged": fx.small(6, 520, 18, 9, body="sphere"),
+        # the FP64 sweep-A tile widths of the full-size grids: rows of 512
+        # cells (4 wavefronts across, 4 rows per tile; 10 rows leave a 2-row
+        # tile) and of 256 cells (2 across, 8 rows; 13 rows leave 5), both with
+        # merged cells
+        "wx4_sphere_neumann": fx.small(3, 512, 10, 6, body="sphere", theta=0.5),
+        "wx2_sphere_dirichlet_top": fx.small(4, 256, 13, 7, body="sphere", bc=(0, 0, 0, 0, 0, 1), theta=0.5),
     }
 
 
@@ -255,3 +261,27 @@ def test_zero_rhs_and_a_single_column():
     x, res = op.solve(torch.as_tensor(b.reshape(nz, 1, 1), device="cuda"), tol=1e-12, precision="f64")
     assert res.status == 0 and res.relres <= 1e-12
     assert rel_l2(host(x).ravel(), ref) <= 1e-9
+
+
+def test_a_new_body_leaves_the_operator_stale_until_it_is_assembled_again():
+    """nfa_grid_set_body after an assembly changes the apertures, the active
+    set and the merge groups the coefficients were formed from: the
+    operator's calls refuse until it is assembled again, then match the
+    oracle of the new body."""
+    import dataclasses
+    from paper_1410_1937_amd import nfa
+    wl = fx.small(5, 40, 14, 12, body="sphere", theta=0.5)
+    gg, gop = gpu_for(wl)
+    x = torch.as_tensor(np.random.default_rng(2).standard_normal(gg.shape), device="cuda")
+    gop.apply(x)
+    b = _gpu_b(wl, gop)
+    wl2 = dataclasses.replace(wl, psi=fx.psi_sphere(wl.xf, wl.yf, wl.zf, radius=0.09, centre=(0.05, 0.02, -0.2)))
+    gg.set_body(torch.as_tensor(wl2.psi, device="cuda").contiguous(), wl2.theta, wl2.samples)
+    for call in (lambda: gop.apply(x), lambda: gop.solve(b, tol=1e-8), lambda: gop.residual(b, x),
+                 lambda: gop.project(*(torch.as_tensor(a, device="cuda") for a in (wl.u, wl.v, wl.w)), x)):
+        with pytest.raises(nfa.NFAError, match="assemble again"):
+            call()
+    gop.assemble(torch.as_tensor(wl2.phi, device="cuda").contiguous(), wl2.rho_l, wl2.rho_g, wl2.smooth)
+    og, ob, oop, _ = oracle_for(wl2)
+    assert np.array_equal(host(gop.apply(x)), oop.apply(host(x)))
+    assert np.array_equal(host(gop.export("dinv")), oop.dinv)
