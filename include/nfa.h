@@ -146,9 +146,23 @@ nfa_status nfa_stretch_axis(double a, double b, int n, int nzones, const double*
  *            (x, y, z); a closed surface, consistently oriented.
  *   psi    : DEVICE double, node array [nz+1][ny+1][nx+1] (output; feed it
  *            to nfa_grid_set_body).
- * Allocates and frees 48 bytes of device memory; synchronous.  Errors:
- * NFA_ERR_INVALID (NULL, m < 1 or m > 2^30), NFA_ERR_HIP. */
+ * Allocates and frees its work memory (the Morton-sorted panels, 72 bytes a
+ * panel, and their bounding boxes); synchronous.  Errors: NFA_ERR_INVALID
+ * (NULL, m < 1 or m > 2^30), NFA_ERR_HIP. */
 nfa_status nfa_panels_psi(nfa_grid g, const double* panels, long long m, double* psi, nfa_stream s);
+
+/* nfa_panels_psi_noalloc -- nfa_panels_psi for callers that cannot allocate
+ * device memory (serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and the same result, bit for bit, with the work memory in a
+ * static device array of 4.6 MiB that each GPU the library runs on holds
+ * until the process ends.  Calls no hipMalloc or hipFree.
+ *   m : 1 <= m <= 65536 panels; more returns NFA_ERR_INVALID before any
+ *       device work.  Other arguments as nfa_panels_psi.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (other host threads, other streams) race and must be
+ * serialised by the caller.  Synchronous (the panels are sorted on the host
+ * as in nfa_panels_psi).  Errors: NFA_ERR_INVALID, NFA_ERR_HIP. */
+nfa_status nfa_panels_psi_noalloc(nfa_grid g, const double* panels, long long m, double* psi, nfa_stream s);
 
 nfa_status nfa_grid_set_body(nfa_grid g, const double* psi_nodes, double theta, int samples,
                              nfa_stream s);

@@ -32,6 +32,8 @@
 // contraction.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -328,10 +330,24 @@ std::vector<double> morton_order(const std::vector<double>& t, long long m) {
   return out;
 }
 
+// Work memory of nfa_panels_psi_noalloc, one copy per device for the life
+// of the process: the panels' bounding box, the sub-tile boxes and the
+// Morton-sorted panels of at most kScratchPanels panels.  The array's name is
+// a host-side stand-in in host code: kernels receive the device address
+// hipGetSymbolAddress gives for it (scratch_base), never the name.
+constexpr long long kScratchPanels = 1LL << 16;
+constexpr size_t kScratchBoxOff = 0;
+constexpr size_t kScratchTileOff = 256;
+constexpr size_t kScratchTriOff =
+    kScratchTileOff + ((sizeof(Box) * (kScratchPanels / kSub) + 255) / 256) * 256;
+constexpr size_t kScratchBytes = kScratchTriOff + 9 * sizeof(double) * kScratchPanels;
+
 }  // namespace
 }  // namespace nfa
 
 using namespace nfa;
+
+static __device__ __align__(256) unsigned char scratch[nfa::kScratchBytes];
 
 extern "C" nfa_status nfa_stretch_axis(double a, double b, int n, int nzones, const double* levels,
                                        const double* zones, double tol, int max_iter, double* nodes,
@@ -385,31 +401,93 @@ extern "C" nfa_status nfa_stretch_axis(double a, double b, int n, int nzones, co
   return NFA_NOT_CONVERGED;
 }
 
-extern "C" nfa_status nfa_panels_psi(nfa_grid g, const double* panels, long long m, double* psi, nfa_stream s) {
-  if (!g || !psi || (m > 0 && !panels)) return fail(NFA_ERR_INVALID, "nfa_panels_psi: NULL argument");
-  if (m < 1 || m > (1LL << 30)) return fail(NFA_ERR_INVALID, "nfa_panels_psi: needs 1 <= m <= 2^30 panels");
-  const hipStream_t st = S(s);
+namespace nfa {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array, looked up once per device
+// with that device current.
+nfa_status scratch_base(void** out) {
+  int dev = 0;
+  NFA_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(NFA_ERR_INVALID, "nfa_panels_psi_noalloc: device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    NFA_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(NFA_ERR_HIP, "nfa_panels_psi_noalloc: no device address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return NFA_OK;
+}
+
+nfa_status psi_check(nfa_grid g, const double* panels, long long m, double* psi, const char* who) {
+  if (!g || !psi || (m > 0 && !panels)) return fail(NFA_ERR_INVALID, std::string(who) + ": NULL argument");
+  if (m < 1 || m > (1LL << 30)) return fail(NFA_ERR_INVALID, std::string(who) + ": needs 1 <= m <= 2^30 panels");
+  return NFA_OK;
+}
+
+// The panels in Morton order of their centroids, read back from the device.
+nfa_status psi_sorted_panels(const double* panels, long long m, hipStream_t st, std::vector<double>& sorted) {
   std::vector<double> host(9 * m);
   NFA_HIP(hipMemcpyAsync(host.data(), panels, 9 * m * sizeof(double), hipMemcpyDeviceToHost, st));
   NFA_HIP(hipStreamSynchronize(st));
-  const std::vector<double> sorted = morton_order(host, m);
+  sorted = morton_order(host, m);
+  return NFA_OK;
+}
+
+// Uploads the sorted panels into tri and runs the three kernels; returns once
+// the stream has finished them.
+nfa_status psi_run(const Grid& g, const std::vector<double>& sorted, long long m, double* tri, Box* box, Box* tiles,
+                   double* psi, hipStream_t st) {
+  NFA_HIP(hipMemcpyAsync(tri, sorted.data(), 9 * m * sizeof(double), hipMemcpyHostToDevice, st));
+  k_panel_box<<<1, kPsiBlock, 0, st>>>(tri, m, box);
+  NFA_CHECK_LAUNCH();
+  const int nsubs = (int)((m + kSub - 1) / kSub);
+  k_tile_boxes<<<(nsubs + kPsiBlock - 1) / kPsiBlock, kPsiBlock, 0, st>>>(tri, (int)m, tiles);
+  NFA_CHECK_LAUNCH();
+  const int nx1 = g.nx + 1, ny1 = g.ny + 1, nz1 = g.nz + 1;
+  const long long nb = (long long)((nx1 + kBx - 1) / kBx) * ((ny1 + kBy - 1) / kBy) * ((nz1 + kBz - 1) / kBz);
+  k_psi<<<(unsigned)nb, kPsiBlock, 0, st>>>(nx1, ny1, nz1, g.d_xf.as<double>(), g.d_yf.as<double>(),
+                                           g.d_zf.as<double>(), tri, (int)m, tiles, box, psi);
+  NFA_CHECK_LAUNCH();
+  NFA_HIP(hipStreamSynchronize(st));
+  return NFA_OK;
+}
+
+}  // namespace
+}  // namespace nfa
+
+extern "C" nfa_status nfa_panels_psi(nfa_grid g, const double* panels, long long m, double* psi, nfa_stream s) {
+  if (const nfa_status e = psi_check(g, panels, m, psi, "nfa_panels_psi")) return e;
+  const hipStream_t st = S(s);
+  std::vector<double> sorted;
+  if (const nfa_status e = psi_sorted_panels(panels, m, st, sorted)) return e;
   DevBuf box, tri, tiles;
   NFA_HIP(box.alloc(sizeof(Box)));
   NFA_HIP(tri.alloc(9 * m * sizeof(double)));
-  NFA_HIP(hipMemcpyAsync(tri.p, sorted.data(), 9 * m * sizeof(double), hipMemcpyHostToDevice, st));
-  panels = tri.as<double>();
-  k_panel_box<<<1, kPsiBlock, 0, st>>>(panels, m, box.as<Box>());
-  NFA_CHECK_LAUNCH();
-  const int nsubs = (int)((m + kSub - 1) / kSub);
-  NFA_HIP(tiles.alloc((size_t)nsubs * sizeof(Box)));
-  k_tile_boxes<<<(nsubs + kPsiBlock - 1) / kPsiBlock, kPsiBlock, 0, st>>>(panels, (int)m, tiles.as<Box>());
-  NFA_CHECK_LAUNCH();
-  const int nx1 = g->nx + 1, ny1 = g->ny + 1, nz1 = g->nz + 1;
-  const long long nb = (long long)((nx1 + kBx - 1) / kBx) * ((ny1 + kBy - 1) / kBy) * ((nz1 + kBz - 1) / kBz);
-  k_psi<<<(unsigned)nb, kPsiBlock, 0, st>>>(nx1, ny1, nz1, g->d_xf.as<double>(), g->d_yf.as<double>(),
-                                           g->d_zf.as<double>(), panels, (int)m, tiles.as<Box>(), box.as<Box>(),
-                                           psi);
-  NFA_CHECK_LAUNCH();
-  NFA_HIP(hipStreamSynchronize(st));   // the work buffers are freed on return
-  return NFA_OK;
+  NFA_HIP(tiles.alloc((size_t)((m + kSub - 1) / kSub) * sizeof(Box)));
+  // the work buffers are freed on return, after the stream has finished
+  return psi_run(*g, sorted, m, tri.as<double>(), box.as<Box>(), tiles.as<Box>(), psi, st);
+}
+
+extern "C" nfa_status nfa_panels_psi_noalloc(nfa_grid g, const double* panels, long long m, double* psi,
+                                             nfa_stream s) {
+  if (const nfa_status e = psi_check(g, panels, m, psi, "nfa_panels_psi_noalloc")) return e;
+  if (m > kScratchPanels)
+    return fail(NFA_ERR_INVALID, "nfa_panels_psi_noalloc: at most " + std::to_string(kScratchPanels) +
+                                     " panels (the size of its static work memory); got " + std::to_string(m));
+  void* base = nullptr;
+  if (const nfa_status e = scratch_base(&base)) return e;
+  const hipStream_t st = S(s);
+  std::vector<double> sorted;
+  if (const nfa_status e = psi_sorted_panels(panels, m, st, sorted)) return e;
+  unsigned char* b = static_cast<unsigned char*>(base);
+  // every kernel writes its part of the work memory in full before reading it
+  return psi_run(*g, sorted, m, reinterpret_cast<double*>(b + kScratchTriOff),
+                 reinterpret_cast<Box*>(b + kScratchBoxOff), reinterpret_cast<Box*>(b + kScratchTileOff), psi, st);
 }

@@ -141,6 +141,7 @@ _sig("nfa_mg_export", c_int, [c_void_p, c_int, c_void_p, c_void_p])
 _sig("nfa_stretch_axis", c_int, [c_double, c_double, c_int, c_int, c_void_p, c_void_p, c_double, c_int, c_void_p,
                                  ctypes.POINTER(c_int)])
 _sig("nfa_panels_psi", c_int, [c_void_p, c_void_p, c_ll, c_void_p, c_void_p])
+_sig("nfa_panels_psi_noalloc", c_int, [c_void_p, c_void_p, c_ll, c_void_p, c_void_p])
 _sig("nfa_vof_create", c_int, [c_void_p, ctypes.POINTER(c_void_p)])
 _sig("nfa_vof_destroy", None, [c_void_p])
 _sig("nfa_vof_sweep", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int, c_int,
@@ -239,15 +240,17 @@ class Grid:
                                              (self.nz + 1, self.ny + 1, self.nx + 1), "psi")
         _check(lib.nfa_grid_set_body(self.h, ptr, theta, samples, _stream()), "nfa_grid_set_body")
 
-    def panels_psi(self, panels, out=None):
-        """Signed distance of a triangulated body at the nodes (nfa_panels_psi);
-        panels: (m, 3, 3) FP64 device tensor."""
+    def panels_psi(self, panels, out=None, noalloc=False):
+        """Signed distance of a triangulated body at the nodes (nfa_panels_psi,
+        or nfa_panels_psi_noalloc when noalloc: no device allocation, at most
+        65536 panels); panels: (m, 3, 3) FP64 device tensor."""
         if panels.ndim != 3 or tuple(panels.shape[1:]) != (3, 3):
             raise ValueError("panels must have shape (m, 3, 3)")
         shape = (self.nz + 1, self.ny + 1, self.nx + 1)
         out = torch.empty(shape, dtype=torch.float64, device=panels.device) if out is None else out
-        _check(lib.nfa_panels_psi(self.h, _dev(panels, torch.float64, None, "panels"), panels.shape[0],
-                                  _dev(out, torch.float64, shape, "psi"), _stream()), "nfa_panels_psi")
+        name = "nfa_panels_psi_noalloc" if noalloc else "nfa_panels_psi"
+        _check(getattr(lib, name)(self.h, _dev(panels, torch.float64, None, "panels"), panels.shape[0],
+                                  _dev(out, torch.float64, shape, "psi"), _stream()), name)
         return out
 
     def exit_velocity(self, uk_x, uc, dt, ut_x=None):
