@@ -16,14 +16,16 @@
  *   a2 = relu(conv2(pool(a1)))     32 -> 64   1/4
  *   b2 = relu(conv3(a2))           64 -> 32   1/4
  *   d1 = relu(conv4(up(b2) + a1))  32 -> 16   1/2
- *   z  = D^-1 (r/s + conv5(up(d1) + a0))      16 -> 1, full resolution
+ *   z  = D^-1 (r/s + head(up(d1) + a0))       16 -> 1, full resolution
  * with D^-1 the Jacobi inverse diagonal of the assembled operator, so the
- * network with conv5 = 0 is the Jacobi step.  Grid sizes must be multiples
- * of 4 in every direction.
+ * network with a zero head is the Jacobi step.  conv0..conv4 are 3x3x3; the
+ * head is 1x1x1, evaluated as head(a0) + up(head(d1)) (the sum up(d1) + a0 is
+ * not rounded to BF16).  Grid sizes must be multiples of 4 in every
+ * direction.
  *
- * Parameters: weights [27][cin][cout] (tap t = 9(dz+1) + 3(dy+1) + (dx+1))
- * then bias [cout] per convolution; FP32 master copies, BF16 used in the
- * convolutions.
+ * Parameters: weights [taps][cin][cout] (tap t = 9(dz+1) + 3(dy+1) + (dx+1);
+ * one tap for the head) then bias [cout] per convolution; FP32 master copies,
+ * BF16 used in the convolutions.
  *
  * Training loss for a (residual r, scalar e.A'e with e = A'^-1 r) pair: the
  * share of the A-norm error left by one optimal step along z,
@@ -48,7 +50,8 @@ typedef struct nfa_unet_s* nfa_unet;
 nfa_status nfa_unet_create(int nx, int ny, int nz, int levels, int seed, nfa_unet* out);
 /* Number of FP32 parameters of a network with `levels` levels (-1 if out of
  * range).  Parameter order: encoder e_0..e_{L-1}, bottleneck, decoder
- * d_{L-2}..d_1, head; each weights [27][cin][cout] then bias [cout]. */
+ * d_{L-2}..d_1, head; each weights [taps][cin][cout] then bias [cout], with
+ * 27 taps but 1 for the head. */
 long long nfa_unet_param_count(int levels);
 int nfa_unet_levels(nfa_unet u);
 /* HOST buffers of nfa_unet_param_count() floats.  Synchronous. */
@@ -58,11 +61,15 @@ nfa_status nfa_unet_set_params(nfa_unet u, const float* host);
 nfa_status nfa_unet_get_grads(nfa_unet u, float* host);
 
 /* z = network(r) on the operator's grid (same shape as the network).
- *   op : assembled operator (supplies rho and the Jacobi inverse diagonal).
- *   r  : DEVICE float cells (a residual: zero on slaves and inactive cells).
- *   z  : DEVICE float cells (output; zero on slaves and inactive cells).
+ *   op   : assembled operator (supplies rho and the Jacobi inverse diagonal).
+ *   r    : DEVICE float cells (a residual: zero on slaves and inactive cells).
+ *   z    : DEVICE float cells, 16-byte aligned (output; zero on slaves and
+ *          inactive cells).
+ *   keep : 1 stores every activation (for nfa_unet_export); 0 stores only what
+ *          later layers read (the preconditioner's form: the full-resolution
+ *          activations stay on chip).
  * ASYNC. */
-nfa_status nfa_unet_forward(nfa_unet u, nfa_poisson op, const float* r, float* z, nfa_stream s);
+nfa_status nfa_unet_forward(nfa_unet u, nfa_poisson op, const float* r, float* z, int keep, nfa_stream s);
 
 /* Forward, loss and backward for one pair; gradients replace the previous
  * ones.  eAe = e.A'e > 0.  loss: HOST out.  Synchronous. */
@@ -74,7 +81,8 @@ nfa_status nfa_unet_grad(nfa_unet u, nfa_poisson op, const float* r, double eAe,
 nfa_status nfa_unet_train_step(nfa_unet u, nfa_poisson op, const float* r, double eAe, float lr,
                                int t, double* loss, nfa_stream s);
 
-/* Activations of the last forward (DEVICE destination): BF16 raw uint16,
+/* Activations of the last forward with keep = 1 or training step (DEVICE
+ * destination): BF16 raw uint16,
  * channels-last; level l has n_l = cells / 8^l positions and c_l = 16, 32,
  * 64, 64, ... channels. */
 #define NFA_UNET_X0 0  /* n_0 x 2 */

@@ -13,10 +13,13 @@ density to a correction of the Jacobi step (deeper variants add levels of
     a2 = relu(conv2(pool(a1)))      1/4,  32 -> 64
     b2 = relu(conv3(a2))            1/4,  64 -> 32
     d1 = relu(conv4(up(b2) + a1))   1/2,  32 -> 16
-    y  = r / s + conv5(up(d1) + a0) full,  16 -> 1
+    y  = r / s + head(up(d1) + a0)  full,  16 -> 1, a 1x1x1 convolution
     z  = D^-1 y                     (Jacobi inverse diagonal of the operator)
 
-so the untrained network with conv5 = 0 is exactly the Jacobi preconditioner.
+so the untrained network with a zero head is exactly the Jacobi
+preconditioner.  The head is linear, so it is evaluated as
+head(a0) + up(head(d1)) without bias on the second term: the sum up(d1) + a0
+is not a storage point (it is never rounded to BF16).
 
 Training loss per (residual r, error e = A'^-1 r) pair: the share of the
 A-norm error that one flexible-CG step along z leaves,
@@ -47,7 +50,8 @@ def channels(levels):
 
 def shapes(levels=3):
     """(Cin, Cout) of the convolutions in parameter order: encoder e0..e_{L-1},
-    bottleneck b, decoder d_{L-2}..d_1, head."""
+    bottleneck b, decoder d_{L-2}..d_1, head.  Every convolution is 3x3x3
+    except the head, 1x1x1 (C4's head); `taps` gives the count."""
     c = channels(levels)
     out = [(2, c[0])] + [(c[l - 1], c[l]) for l in range(1, levels)]
     out.append((c[levels - 1], c[levels - 2]))
@@ -65,6 +69,11 @@ def bf16(x):
     u = x32.view(np.uint32).astype(np.uint64)
     u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def taps(levels=3):
+    """Taps of each convolution in parameter order: 27, ..., 27, 1 (head)."""
+    return [27] * (len(shapes(levels)) - 1) + [1]
 
 
 def _q(x, quant):
@@ -135,9 +144,9 @@ def init_params(seed=0, zero_last=True, levels=3):
     rng = np.random.default_rng(seed)
     params = []
     sh = shapes(levels)
-    for i, (ci, co) in enumerate(sh):
-        std = np.sqrt(2.0 / (27 * ci))
-        w = rng.standard_normal((27, ci, co)) * std
+    for i, ((ci, co), nt) in enumerate(zip(sh, taps(levels))):
+        std = np.sqrt(2.0 / (nt * ci))
+        w = rng.standard_normal((nt, ci, co)) * std
         if zero_last and i == len(sh) - 1:
             w[:] = 0.0
         params.append((w.astype(np.float32).astype(np.float64), np.zeros(co)))
@@ -172,8 +181,9 @@ def forward(params, x0, quant=True):
     for i, l in enumerate(range(L - 2, 0, -1)):
         s[l] = _q(up(d[l + 1]) + a[l], quant)
         d[l] = _q(relu(conv3d(s[l], *Dd[i])), quant)
-    s[0] = _q(up(d[1]) + a[0], quant)
-    u = conv3d(s[0], *Hd)[..., 0]
+    wh, bh = Hd
+    s[0] = up(d[1]) + a[0]
+    u = (bh[0] + a[0] @ wh[0][:, 0]) + up(d[1] @ wh[0][:, 0])
     y = x0[..., 0] + u
     return y, dict(P=P, L=L, x0=x0, a=a, p=p, d=d, s=s)
 
@@ -184,9 +194,9 @@ def backward(cache, dy, quant=True):
     L, P, a, p, d, s = cache["L"], cache["P"], cache["a"], cache["p"], cache["d"], cache["s"]
     E, B, Dd, Hd = P[:L], P[L], P[L + 1:2 * L - 1], P[2 * L - 1]
     gE, gD = [None] * L, [None] * (L - 2)
-    dy4 = dy[..., None]
-    gH = conv3d_wgrad(s[0], dy4)
-    skip = {0: _q(conv3d_dgrad(dy4, Hd[0]), quant)}
+    wh = Hd[0]
+    gH = ((s[0].reshape(-1, s[0].shape[-1]).T @ dy.reshape(-1))[None, :, None], np.array([np.sum(dy)]))
+    skip = {0: _q(dy[..., None] * wh[0][:, 0], quant)}
     for i, l in enumerate(range(1, L - 1)):
         di = L - 2 - l                      # index of d_l in decoder parameter order
         dd = _q(up_T(skip[l - 1]) * (d[l] > 0), quant)

@@ -1,20 +1,31 @@
 // libnfa: learned preconditioner (3-D U-Net) for flexible CG.
 //
-// Convolutions are implicit GEMMs on the BF16 matrix cores of gfx950
-// (v_mfma_f32_16x16x32_bf16, FP32 accumulation): for a 16-cell x-segment a
-// wavefront computes out[channel][position] = W^T [channel][k] x in[k][position]
-// with k = (tap, input channel), the weights pre-packed as per-lane A
-// fragments and the input gathered as B fragments (8 consecutive channels of
-// one tap per lane = one 16-byte load, channels-last activations).  The
-// data gradient is the same kernel run on the flipped, transposed weights;
-// the weight gradient is an MFMA GEMM over positions with per-workgroup
-// partials summed in a fixed order.  The 16 -> 1 head and the elementwise
-// glue (features, pooling, upsampling, ReLU masks, loss gradient, Adam) are
-// plain vector kernels.  Activations are stored as BF16 (round to nearest
-// even), exactly where the CPU oracle rounds.
+// Forward convolutions are implicit GEMMs on the BF16 matrix cores of gfx950
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation), tiled for LDS: a workgroup of
+// four wavefronts computes a brick of 16 x 4 x 4 output positions from the
+// brick's input halo (18 x 6 x 6 positions) staged once in LDS, channels in
+// groups of at most 32, so every one of the 27 taps reads its B fragments
+// (8 consecutive channels of one position per lane, one 16-byte LDS read)
+// from LDS.  A wavefront owns a 2 x 2 (y, z) block of 16-position x-rows and
+// all output channels: each A (weight) fragment, read through the L1 from a
+// packed per-lane layout, feeds four MFMAs.  The epilogues fuse what the
+// network does next to each convolution: bias, ReLU and the BF16 storage
+// rounding; the 2 x 2 x 2 average pool (the wavefront's 2 x 2 rows are summed
+// in registers, x pairs by a lane shuffle); and the 1 x 1 x 1 head projected
+// onto the outputs of the first encoder and of the last decoder convolution.
+// The first convolution forms its input features from r and log(1/rho) while
+// staging them.  At inference nothing of full resolution is stored but the
+// head's partial sum: the 16-channel activation a0 stays in registers.
+//
+// Training keeps every activation; the data gradient runs the earlier
+// direct-gather MFMA kernel on the flipped, transposed weights and the weight
+// gradient is an MFMA GEMM over positions with per-workgroup partials summed
+// in a fixed order.  Activations are stored as BF16 (round to nearest even),
+// exactly where the CPU oracle rounds.
 #include <cmath>
 #include <cstring>
 #include <random>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/nfa_unet.h"
@@ -30,6 +41,14 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr double kL0 = -3.5, kL1 = 3.4;   // log(1/rho) normalisation
+
+// f(std::integral_constant<int, I>) for I = B .. E-1, in order
+template <int B, int E, class F> __device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
 constexpr int kMaxLevels = 6;
 constexpr int kWgradBlocks = 64;
 
@@ -58,18 +77,6 @@ __device__ __forceinline__ void tap_offset(int t, int& dz, int& dy, int& dx) {
 // ------------------------------------------------------------ features
 __global__ void k_ell(long long n, const double* __restrict__ rho, bf16_t* __restrict__ ell) {
   GRID_STRIDE(c, n) ell[c] = f2bf((float)((log(1.0 / rho[c]) - kL0) / kL1));
-}
-
-__global__ void k_prep(long long n, const float* __restrict__ r, const bf16_t* __restrict__ ell,
-                       const double* __restrict__ rr, double nred, bf16_t* __restrict__ x0,
-                       const SolveScalars* __restrict__ sc) {
-  if (solve_done(sc)) return;
-  const double ms = *rr / nred;
-  const double inv = ms > 0 ? 1.0 / sqrt(ms) : 1.0;
-  GRID_STRIDE(c, n) {
-    x0[2 * c] = f2bf((float)((double)r[c] * inv));
-    x0[2 * c + 1] = ell[c];
-  }
 }
 
 // ------------------------------------------------------------ conv (MFMA)
@@ -166,6 +173,391 @@ __global__ __launch_bounds__(256) void k_conv(int D, int H, int W, const bf16_t*
     w.x = (unsigned)h[0] | ((unsigned)h[1] << 16);
     w.y = (unsigned)h[2] | ((unsigned)h[3] << 16);
     *reinterpret_cast<uint2*>(out + p * COUT + m * 16 + kq * 4) = w;
+  }
+}
+
+// ------------------------------------------------------------ tiled conv (MFMA)
+// out[p][co] = bf16(relu(bias[co] + sum_{t,ci} in'[p + off_t][ci] W[t][ci][co]))
+// on bricks of kTX x kTY x kTZ positions; in' = in, bf16(in + up(in2)) when
+// UPADD, or the features [bf16(r/s), ell] when FEAT (then CIN = 2).
+// A workgroup's brick is kTX x 4 SUB x 4 SUB positions; each wavefront takes
+// SUB x SUB blocks of 2 x 2 (y, z) rows one after the other from one staged halo.
+constexpr int kTX = 16, kHX = kTX + 2;
+template <int SUB> struct Brick {
+  static constexpr int TY = 4 * SUB, TZ = 4 * SUB, HY = TY + 2, HZ = TZ + 2, HALO = kHX * HY * HZ;
+};
+
+struct TconvArgs {
+  int D, H, W;             // grid of the convolution's level
+  int nbx, nby, nb, per;   // bricks along x and y, in all, per XCD range
+  const bf16_t* in;        // [n][CIN] (not FEAT)
+  const bf16_t* in2;       // UPADD: [n/8][CIN], the coarser level
+  const float* r;          // FEAT: residual, float cells
+  const bf16_t* ell;       // FEAT: normalised log(1/rho)
+  const double* rr;        // FEAT: ||r||^2 over the unknowns
+  double nred;             // FEAT: number of unknowns
+  bf16_t* x0;              // FEAT: features out [n][2], or null
+  const uint4* frag;       // A fragments (k_pack_tile)
+  const float* bias;       // [COUT]
+  bf16_t* out;             // [n][COUT], or null
+  bf16_t* pooled;          // [n/8][COUT] (2 x 2 x 2 average), or null
+  float* proj;             // [n] head projection w5 . out, or null
+  const float* wproj;      // [COUT] head weights (BF16 values)
+  const float* pbias;      // FEAT: head bias; proj = x0[.,0] + (b5 + w5 . out)
+  const SolveScalars* sc;
+};
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+// two floats rounded to BF16 (nearest even; v_cvt_pk_bf16_f32), packed low/high
+__device__ __forceinline__ unsigned pack_bf2(float lo, float hi) {
+  bf16x2 v;
+  v.x = (__bf16)lo;
+  v.y = (__bf16)hi;
+  return __builtin_bit_cast(unsigned, v);
+}
+__device__ __forceinline__ float lo_bf(unsigned w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float hi_bf(unsigned w) { return __uint_as_float(w & 0xFFFF0000u); }
+// bf16(a + b) for the two BF16 values packed in each of a and b
+__device__ __forceinline__ unsigned add_bf2(unsigned a, unsigned b) {
+  return pack_bf2(lo_bf(a) + lo_bf(b), hi_bf(a) + hi_bf(b));
+}
+
+// offset in staged positions of tap t from the centre (rows of kHX, planes of HY rows)
+template <int HY> __host__ __device__ constexpr int tap_halo(int t) {
+  return ((t / 9 - 1) * HY + ((t / 3) % 3 - 1)) * kHX + (t % 3 - 1);
+}
+
+// Staged position stride in bytes: the group's channels plus 16 bytes, so
+// that the eight lanes of one LDS pass (the same 16-byte chunk of eight
+// consecutive positions) fall on eight different 16-byte bank slots.
+template <int CG> constexpr int lds_stride() { return CG == 2 ? 4 : CG * 2 + 16; }
+
+template <int CIN, int COUT, bool UPADD, bool FEAT, int SUB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_tconv(const TconvArgs a) {
+  if (solve_done(a.sc)) return;
+  constexpr int kTY = Brick<SUB>::TY, kTZ = Brick<SUB>::TZ, kHY = Brick<SUB>::HY, kHZ = Brick<SUB>::HZ;
+  constexpr int kHalo = Brick<SUB>::HALO, HY = kHY;
+  static_assert(!FEAT || CIN == 2, "features have two channels");
+  static_assert(FEAT || CIN % 16 == 0, "input channels: 2 (features) or a multiple of 16");
+  constexpr int CG = CIN < 32 ? CIN : 32;          // channels per staged group
+  constexpr int NG = CIN / CG;
+  constexpr int KC = (27 * CIN + 31) / 32;         // K chunks of 32
+  constexpr int KCG = NG > 1 ? 27 : KC;            // chunks per group
+  constexpr int MT = COUT / 16;
+  constexpr int ST = lds_stride<CG>();
+  static_assert(SUB == 1 || NG == 1, "several blocks per wavefront need a single staged group");
+  __shared__ __align__(16) unsigned char lds[kHalo * ST];
+  // bricks in contiguous ranges per XCD (workgroups are dealt to the XCDs
+  // round robin), so that neighbouring bricks share an L2
+  const int b = (int)(blockIdx.x & 7) * a.per + (int)(blockIdx.x >> 3);
+  if (b >= a.nb) return;
+  const int bx = b % a.nbx, brest = b / a.nbx;
+  const int x0b = bx * kTX, y0b = (brest % a.nby) * kTY, z0b = (brest / a.nby) * kTZ;
+  const int D = a.D, H = a.H, W = a.W;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int n = lane & 15, kq = lane >> 4;
+
+  // loads that depend on nothing staged, issued first: this lane's biases and
+  // head weights, the residual scale, the first chunk's A fragments
+  float bi[MT][4], wp[MT][4];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      bi[m][i] = a.bias[m * 16 + 4 * kq + i];
+      wp[m][i] = a.proj ? a.wproj[m * 16 + 4 * kq + i] : 0.f;
+    }
+  const float pb = FEAT && a.proj ? a.pbias[0] : 0.f;
+  const double rr = FEAT ? *a.rr : 0.0;
+  const uint4* fr = a.frag + lane;
+  Frag An[MT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) An[m].u = fr[m * 64];
+
+
+  // ---- staging of channel group g's halo
+  auto stage = [&](auto gg) {
+    constexpr int g = decltype(gg)::value;
+    // ---- stage the halo of channel group g
+    if constexpr (FEAT) {
+      // one thread per (halo row, 4 aligned x positions): rows of the halo
+      // span x0b - 1 .. x0b + 16, read as x0b - 4 .. x0b + 19 (6 quads; W is a
+      // multiple of 4, so a quad is wholly inside the grid or wholly outside)
+      const double ms = rr / a.nred;
+      const double inv = ms > 0 ? 1.0 / sqrt(ms) : 1.0;
+      unsigned* l32 = reinterpret_cast<unsigned*>(lds);
+      constexpr int NQ = kHY * kHZ * 6;             // (row, quad) pairs
+      constexpr int NIT = (NQ + 255) / 256;
+      float4 rv[NIT];
+      uint2 ev[NIT];
+      long long p0[NIT];
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        const int tq = tid + it * 256;
+        const int quad = tq % 6, row = tq / 6;
+        const int hy = row % kHY, hz = row / kHY;
+        const int gy = y0b - 1 + hy, gz = z0b - 1 + hz, gx0 = x0b - 4 + 4 * quad;
+        const bool ok = tq < NQ && gx0 >= 0 && gx0 < W && gy >= 0 && gy < H && gz >= 0 && gz < D;
+        rv[it] = make_float4(0.f, 0.f, 0.f, 0.f);
+        ev[it] = make_uint2(0u, 0u);
+        p0[it] = ok ? ((long long)gz * H + gy) * W + gx0 : -1;
+        if (ok) {
+          rv[it] = *reinterpret_cast<const float4*>(a.r + p0[it]);
+          ev[it] = *reinterpret_cast<const uint2*>(a.ell + p0[it]);
+        }
+      }
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        const int tq = tid + it * 256;
+        if (tq < NQ) {
+          const int quad = tq % 6, row = tq / 6;
+          const int hy = row % kHY, hz = row / kHY;
+          const bool ok = p0[it] >= 0;
+          const float rs[4] = {rv[it].x, rv[it].y, rv[it].z, rv[it].w};
+          const unsigned es[4] = {ev[it].x & 0xFFFFu, ev[it].x >> 16, ev[it].y & 0xFFFFu, ev[it].y >> 16};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int hx = 4 * quad - 3 + i;
+            if (hx >= 0 && hx < kHX) {
+              const unsigned v = ok ? ((unsigned)f2bf((float)((double)rs[i] * inv)) | (es[i] << 16)) : 0u;
+              l32[(hz * kHY + hy) * kHX + hx] = v;
+              if (a.x0 && ok && hx >= 1 && hx <= kTX && hy >= 1 && hy <= kTY && hz >= 1 && hz <= kTZ)
+                reinterpret_cast<unsigned*>(a.x0)[p0[it] + i] = v;
+            }
+          }
+        }
+      }
+    } else {
+      // 16-byte chunks of the halo, row by row: a row is kHX positions of CG
+      // channels; element indices fit in 32 bits at every level
+      constexpr int CPP = CG / 8;                  // chunks per position
+      constexpr int RCH = kHX * CPP;               // chunks per halo row
+      constexpr int NE = kHY * kHZ * RCH;
+      constexpr int NIT = (NE + 255) / 256;
+      constexpr int BATCH = UPADD ? 6 : NIT;       // loads in flight per thread (registers)
+      const int H2 = H >> 1, W2 = W >> 1;
+#pragma unroll
+      for (int it0 = 0; it0 < NIT; it0 += BATCH) {
+        uint4 v[BATCH];
+        uint4 c[UPADD ? BATCH : 1];
+        int lo[BATCH];
+#pragma unroll
+        for (int ib = 0; ib < BATCH; ++ib) {
+          const int e = tid + (it0 + ib) * 256;
+          const int row = e / RCH, rc = e - row * RCH;
+          const int hx = rc / CPP, c8 = rc - hx * CPP;
+          const int hy = row % kHY, hz = row / kHY;
+          const int gx = x0b - 1 + hx, gy = y0b - 1 + hy, gz = z0b - 1 + hz;
+          const bool ok = it0 + ib < NIT && e < NE && (unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H &&
+                          (unsigned)gz < (unsigned)D;
+          lo[ib] = (it0 + ib < NIT && e < NE) ? (row * kHX + hx) * ST + c8 * 16 : -1;
+          v[ib] = make_uint4(0u, 0u, 0u, 0u);
+          if (ok) {
+            const unsigned pe = ((unsigned)(gz * H + gy) * (unsigned)W + (unsigned)gx) * CIN + g * CG + c8 * 8;
+            v[ib] = *reinterpret_cast<const uint4*>(a.in + pe);
+          }
+          if constexpr (UPADD) {
+            c[ib] = make_uint4(0u, 0u, 0u, 0u);
+            if (ok) {
+              const unsigned qe =
+                  ((unsigned)((gz >> 1) * H2 + (gy >> 1)) * (unsigned)W2 + (unsigned)(gx >> 1)) * CIN + g * CG + c8 * 8;
+              c[ib] = *reinterpret_cast<const uint4*>(a.in2 + qe);
+            }
+          }
+        }
+#pragma unroll
+        for (int ib = 0; ib < BATCH; ++ib) {
+          if (lo[ib] >= 0) {
+            uint4 w = v[ib];
+            if constexpr (UPADD) {
+              w.x = add_bf2(w.x, c[ib].x);
+              w.y = add_bf2(w.y, c[ib].y);
+              w.z = add_bf2(w.z, c[ib].z);
+              w.w = add_bf2(w.w, c[ib].w);
+            }
+            *reinterpret_cast<uint4*>(lds + lo[ib]) = w;
+          }
+        }
+      }
+    }
+  };
+
+  // features: the staged offsets of this lane's taps 16 kc + 4 kq + i (the
+  // padding taps beyond 26 read tap 26; A is zero there)
+  int foff[FEAT ? KC : 1][4];
+  if constexpr (FEAT) {
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int t = 16 * kc + 4 * kq + i;
+        foff[kc][i] = t < 27 ? (t / 9 - 1) * (kHY * kHX) + ((t / 3) % 3 - 1) * kHX + (t % 3 - 1) : tap_halo<HY>(26);
+      }
+  }
+
+  // ---- one block of 2 x 2 (y, z) rows of 16 positions per wavefront: (yw, zw)
+  // its offset in the brick; acc accumulates over the channel groups
+  int yw = 0, zw = 0, hb[4];
+  f32x4 acc[MT][4];
+  auto set_block = [&](int s) {
+    yw = 2 * (wv & 1) + 4 * (s % SUB);
+    zw = 2 * (wv >> 1) + 4 * (s / SUB);
+    // staged index of this lane's output position in each of the four rows
+#pragma unroll
+    for (int j = 0; j < 4; ++j) hb[j] = ((zw + (j >> 1) + 1) * kHY + (yw + (j & 1) + 1)) * kHX + (n + 1);
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  };
+  auto compute = [&](auto gg) {
+    constexpr int g = decltype(gg)::value;
+    // ---- K chunks of this group, unrolled so that every tap offset is an
+    // immediate; A from the packed fragments (the next chunk's loads in
+    // flight while this chunk multiplies), B from LDS
+    int bj[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bj[j] = hb[j] * ST;
+    auto load_b = [&](auto kcc, Frag (&B)[4]) {
+      constexpr int kc = decltype(kcc)::value;
+      if constexpr (FEAT) {
+        // lane's 8 K values: taps 16 kc + 4 kq + i (i < 4), two channels each
+        const unsigned* l32 = reinterpret_cast<const unsigned*>(lds);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          B[j].u = make_uint4(l32[hb[j] + foff[kc][0]], l32[hb[j] + foff[kc][1]], l32[hb[j] + foff[kc][2]],
+                              l32[hb[j] + foff[kc][3]]);
+      } else if constexpr (CG == 16) {
+        // a chunk holds two taps of 16 channels: lanes kq < 2 the even one
+        constexpr int t0 = 2 * kc, t1 = 2 * kc + 1 < 27 ? 2 * kc + 1 : 26;
+        const int sel = (kq >> 1) ? (tap_halo<HY>(t1) - tap_halo<HY>(t0)) * ST : 0;
+        const int lo = (kq & 1) * 16 + sel + tap_halo<HY>(t0) * ST;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) B[j].u = *reinterpret_cast<const uint4*>(lds + bj[j] + lo);
+      } else {
+        // a chunk is one tap of the group's 32 channels
+        constexpr int t = kc - (kc / KCG) * KCG;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          B[j].u = *reinterpret_cast<const uint4*>(lds + bj[j] + kq * 16 + tap_halo<HY>(t) * ST);
+      }
+    };
+    Frag Bn[4];
+    static_for<0, KC>([&](auto kcc) {
+      constexpr int kc = decltype(kcc)::value;
+      if constexpr (kc >= g * KCG && kc < (g + 1) * KCG) {
+        if constexpr (kc == g * KCG) load_b(kcc, Bn);
+        Frag A[MT], B[4];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) A[m] = An[m];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) B[j] = Bn[j];
+        if constexpr (kc + 1 < KC) {
+#pragma unroll
+          for (int m = 0; m < MT; ++m) An[m].u = fr[((kc + 1) * MT + m) * 64];
+        }
+        if constexpr (kc + 1 < (g + 1) * KCG && kc + 1 < KC) load_b(std::integral_constant<int, kc + 1>{}, Bn);
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[m].v, B[j].v, acc[m][j], 0, 0, 0);
+      }
+    });
+  };
+  auto finish = [&]() {
+  // ---- epilogue: lane holds channels m*16 + 4 kq + i of position n in row j;
+  // bias, ReLU, the BF16 storage rounding (packed words kept for the stores)
+  unsigned pk[MT][4][2];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      pk[m][j][0] = pack_bf2(fmaxf(acc[m][j][0] + bi[m][0], 0.f), fmaxf(acc[m][j][1] + bi[m][1], 0.f));
+      pk[m][j][1] = pack_bf2(fmaxf(acc[m][j][2] + bi[m][2], 0.f), fmaxf(acc[m][j][3] + bi[m][3], 0.f));
+      acc[m][j][0] = lo_bf(pk[m][j][0]);
+      acc[m][j][1] = hi_bf(pk[m][j][0]);
+      acc[m][j][2] = lo_bf(pk[m][j][1]);
+      acc[m][j][3] = hi_bf(pk[m][j][1]);
+    }
+  const int x = x0b + n;
+  if (a.out) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int y = y0b + yw + (j & 1), z = z0b + zw + (j >> 1);
+      if (x < W && y < H && z < D) {
+        const long long p = ((long long)z * H + y) * W + x;
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+          *reinterpret_cast<uint2*>(a.out + p * COUT + m * 16 + 4 * kq) = make_uint2(pk[m][j][0], pk[m][j][1]);
+      }
+    }
+  }
+  if (a.pooled) {
+    // the wavefront's four rows are one 2 x 2 (y, z) block; x pairs are lanes n, n^1
+    const int y = y0b + yw, z = z0b + zw;
+    const bool ok = (n & 1) == 0 && x < W && y < H && z < D;
+    const long long q = ((long long)(z >> 1) * (H >> 1) + (y >> 1)) * (W >> 1) + (x >> 1);
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      float v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float t = (acc[m][0][i] + acc[m][1][i]) + (acc[m][2][i] + acc[m][3][i]);
+        t += __shfl_xor(t, 1);
+        v[i] = t * 0.125f;
+      }
+      if (ok)
+        *reinterpret_cast<uint2*>(a.pooled + q * COUT + m * 16 + 4 * kq) =
+            make_uint2(pack_bf2(v[0], v[1]), pack_bf2(v[2], v[3]));
+    }
+  }
+  if (a.proj) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float t = 0.f;
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) t += wp[m][i] * acc[m][j][i];
+      t += __shfl_xor(t, 16);
+      t += __shfl_xor(t, 32);
+      const int y = y0b + yw + (j & 1), z = z0b + zw + (j >> 1);
+      if (kq == 0 && x < W && y < H && z < D) {
+        const long long p = ((long long)z * H + y) * W + x;
+        if constexpr (FEAT) {
+          const float x00 = lo_bf(reinterpret_cast<const unsigned*>(lds)[hb[j]]);
+          a.proj[p] = x00 + (pb + t);
+        } else {
+          a.proj[p] = t;
+        }
+      }
+    }
+  }
+  };
+
+  if constexpr (SUB == 1) {
+    set_block(0);
+    static_for<0, NG>([&](auto gg) {
+      if constexpr (decltype(gg)::value > 0) __syncthreads();
+      stage(gg);
+      __syncthreads();
+      compute(gg);
+    });
+    finish();
+  } else {
+    stage(std::integral_constant<int, 0>{});
+    __syncthreads();
+#pragma unroll 1
+    for (int s = 0; s < SUB * SUB; ++s) {
+      if (s > 0) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m) An[m].u = fr[m * 64];
+      }
+      set_block(s);
+      compute(std::integral_constant<int, 0>{});
+      finish();
+    }
   }
 }
 
@@ -286,34 +678,6 @@ __global__ void k_colsum_reduce(const float* __restrict__ partial, int nblk, int
 }
 
 // ------------------------------------------------------------ pooling / upsampling
-// coarse[p][c] = bf16(sum of the 8 fine children / 8), 8 channels per thread
-template <int C>
-__global__ void k_pool(int Dc, int Hc, int Wc, const bf16_t* __restrict__ fine, bf16_t* __restrict__ coarse) {
-  const long long n = (long long)Dc * Hc * Wc * (C / 8);
-  const int Hf = 2 * Hc, Wf = 2 * Wc;
-  GRID_STRIDE(e, n) {
-    const int g = (int)(e % (C / 8));
-    const long long p = e / (C / 8);
-    const int x = (int)(p % Wc);
-    const long long r = p / Wc;
-    const int y = (int)(r % Hc), z = (int)(r / Hc);
-    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int c = 0; c < 2; ++c)
-      for (int b = 0; b < 2; ++b)
-        for (int a = 0; a < 2; ++a) {
-          const long long f = ((long long)(2 * z + c) * Hf + (2 * y + b)) * Wf + (2 * x + a);
-          Frag v;
-          v.u = *reinterpret_cast<const uint4*>(fine + f * C + g * 8);
-#pragma unroll
-          for (int j = 0; j < 8; ++j) s[j] += bf2f(v.h[j]);
-        }
-    Frag o;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) o.h[j] = f2bf(s[j] * 0.125f);
-    *reinterpret_cast<uint4*>(coarse + p * C + g * 8) = o.u;
-  }
-}
-
 // coarse[p][c] = bf16((sum of the 8 fine children of grad) * (mask[p][c] > 0))
 template <int C>
 __global__ void k_upT_mask(int Dc, int Hc, int Wc, const bf16_t* __restrict__ fine,
@@ -371,101 +735,95 @@ __global__ void k_skip_poolT_mask(int D, int H, int W, const bf16_t* __restrict_
   }
 }
 
-// ------------------------------------------------------------ head (16 -> 1)
-// z = dinv * (x0[.,0] + b5 + sum_{t,ci} w5[t][ci] s0[p + off_t][ci]),  s0 = bf16(a0 + up(d1))
-__global__ __launch_bounds__(256) void k_head_fwd(int D, int H, int W, const bf16_t* __restrict__ x0,
-                                                  const bf16_t* __restrict__ a0,
-                                                  const bf16_t* __restrict__ d1,
-                                                  const float* __restrict__ w5, const float* __restrict__ b5,
-                                                  const float* __restrict__ dinv, float* __restrict__ z,
-                                                  const SolveScalars* __restrict__ sc) {
+// ------------------------------------------------------------ head (1 x 1 x 1, 16 -> 1)
+// z = dinv * (h0 + g1[parent]): h0 = x0[.,0] + (b5 + w5 . a0) from the first
+// encoder's epilogue, g1 = w5 . d1 from the last decoder's (one level
+// coarser, nearest upsampling); 4 x-consecutive cells per thread.
+__global__ __launch_bounds__(256) void k_head_out(int D, int H, int W, const float* __restrict__ h0,
+                                                  const float* __restrict__ g1, const float* __restrict__ dinv,
+                                                  float* __restrict__ z, const SolveScalars* __restrict__ sc) {
   if (solve_done(sc)) return;
-  __shared__ float w[27 * 16];
-  for (int e = threadIdx.x; e < 27 * 16; e += blockDim.x) w[e] = w5[e];
-  __syncthreads();
-  const long long n = (long long)D * H * W;
-  const int H2 = H >> 1, W2 = W >> 1;
-  GRID_STRIDE(p, n) {
-    const int x = (int)(p % W);
-    const long long r = p / W;
-    const int y = (int)(r % H), zc = (int)(r / H);
-    float u = b5[0];
-    for (int t = 0; t < 27; ++t) {
-      int dz, dy, dx;
-      tap_offset(t, dz, dy, dx);
-      const int zz = zc + dz, yy = y + dy, xx = x + dx;
-      if (zz < 0 || zz >= D || yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
-      const long long pp = ((long long)zz * H + yy) * W + xx;
-      const long long qq = ((long long)(zz >> 1) * H2 + (yy >> 1)) * W2 + (xx >> 1);
-      Frag a[2], b[2];
-      a[0].u = *reinterpret_cast<const uint4*>(a0 + pp * 16);
-      a[1].u = *reinterpret_cast<const uint4*>(a0 + pp * 16 + 8);
-      b[0].u = *reinterpret_cast<const uint4*>(d1 + qq * 16);
-      b[1].u = *reinterpret_cast<const uint4*>(d1 + qq * 16 + 8);
-#pragma unroll
-      for (int ci = 0; ci < 16; ++ci) {
-        const float s = bf2f(f2bf(bf2f(a[ci >> 3].h[ci & 7]) + bf2f(b[ci >> 3].h[ci & 7])));
-        u += w[t * 16 + ci] * s;
-      }
-    }
-    z[p] = dinv[p] * (bf2f(x0[2 * p]) + u);
+  const long long nq = (long long)D * H * W / 4;
+  const int W4 = W / 4, H2 = H >> 1, W2 = W >> 1;
+  GRID_STRIDE(e, nq) {
+    const int x4 = (int)(e % W4);
+    const long long rw = e / W4;
+    const int y = (int)(rw % H), zc = (int)(rw / H);
+    const long long q = ((long long)(zc >> 1) * H2 + (y >> 1)) * W2 + 2 * x4;
+    const float4 h = reinterpret_cast<const float4*>(h0)[e];
+    const float4 d = reinterpret_cast<const float4*>(dinv)[e];
+    const float ga = g1[q], gb = g1[q + 1];
+    float4 o;
+    o.x = d.x * (h.x + ga);
+    o.y = d.y * (h.y + ga);
+    o.z = d.z * (h.z + gb);
+    o.w = d.w * (h.w + gb);
+    reinterpret_cast<float4*>(z)[e] = o;
   }
 }
 
-// ds0[p][ci] = bf16(sum_t w5[t][ci] dy[p - off_t]),  dy = dinv * dz
-__global__ __launch_bounds__(256) void k_head_bwd_data(int D, int H, int W, const float* __restrict__ dz,
-                                                       const float* __restrict__ dinv,
-                                                       const float* __restrict__ w5,
-                                                       bf16_t* __restrict__ ds0) {
-  __shared__ float w[27 * 16];
-  for (int e = threadIdx.x; e < 27 * 16; e += blockDim.x) w[e] = w5[e];
-  __syncthreads();
-  const long long n = (long long)D * H * W;
+// data gradient of the head: ds0[p][ci] = bf16(w5[ci] dy[p]),  dy = dinv * dz
+__global__ void k_head_dgrad(long long n, const float* __restrict__ dz, const float* __restrict__ dinv,
+                             const float* __restrict__ w5, bf16_t* __restrict__ ds0) {
   GRID_STRIDE(p, n) {
-    const int x = (int)(p % W);
-    const long long r = p / W;
-    const int y = (int)(r % H), zc = (int)(r / H);
-    float acc[16];
-#pragma unroll
-    for (int ci = 0; ci < 16; ++ci) acc[ci] = 0.f;
-    for (int t = 0; t < 27; ++t) {
-      int dz_, dy_, dx_;
-      tap_offset(t, dz_, dy_, dx_);
-      const int zz = zc - dz_, yy = y - dy_, xx = x - dx_;
-      if (zz < 0 || zz >= D || yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
-      const long long pp = ((long long)zz * H + yy) * W + xx;
-      const float g = dinv[pp] * dz[pp];
-#pragma unroll
-      for (int ci = 0; ci < 16; ++ci) acc[ci] += w[t * 16 + ci] * g;
-    }
+    const float g = dinv[p] * dz[p];
     Frag o0, o1;
 #pragma unroll
     for (int ci = 0; ci < 8; ++ci) {
-      o0.h[ci] = f2bf(acc[ci]);
-      o1.h[ci] = f2bf(acc[8 + ci]);
+      o0.h[ci] = f2bf(w5[ci] * g);
+      o1.h[ci] = f2bf(w5[8 + ci] * g);
     }
     *reinterpret_cast<uint4*>(ds0 + p * 16) = o0.u;
     *reinterpret_cast<uint4*>(ds0 + p * 16 + 8) = o1.u;
   }
 }
 
-// the head's upstream gradient dy = dinv * dz as channel 0 of a 16-channel
-// BF16 tensor, so that the weight gradient runs on the MFMA kernel
-__global__ void k_pad_dy(long long n, const float* __restrict__ dz, const float* __restrict__ dinv,
-                         bf16_t* __restrict__ out) {
+// weight gradient of the head, per workgroup: partial[blk][ci] = sum_p dy[p]
+// (a0[p][ci] + d1[parent(p)][ci]) for ci < 16, partial[blk][16] = sum_p dy[p]
+constexpr int kHeadBlocks = 256;
+__global__ __launch_bounds__(256) void k_head_wgrad(int D, int H, int W, const float* __restrict__ dz,
+                                                    const float* __restrict__ dinv, const bf16_t* __restrict__ a0,
+                                                    const bf16_t* __restrict__ d1, float* __restrict__ partial) {
+  __shared__ float red[17][256];
+  float acc[17];
+#pragma unroll
+  for (int c = 0; c < 17; ++c) acc[c] = 0.f;
+  const long long n = (long long)D * H * W;
+  const int H2 = H >> 1, W2 = W >> 1;
   GRID_STRIDE(p, n) {
-    Frag a, b;
-    a.u = make_uint4(0u, 0u, 0u, 0u);
-    b.u = make_uint4(0u, 0u, 0u, 0u);
-    a.h[0] = f2bf(dinv[p] * dz[p]);
-    *reinterpret_cast<uint4*>(out + p * 16) = a.u;
-    *reinterpret_cast<uint4*>(out + p * 16 + 8) = b.u;
+    const float g = dinv[p] * dz[p];
+    const int x = (int)(p % W);
+    const long long rw = p / W;
+    const int y = (int)(rw % H), zc = (int)(rw / H);
+    const long long q = ((long long)(zc >> 1) * H2 + (y >> 1)) * W2 + (x >> 1);
+    Frag a[2], d[2];
+    a[0].u = *reinterpret_cast<const uint4*>(a0 + p * 16);
+    a[1].u = *reinterpret_cast<const uint4*>(a0 + p * 16 + 8);
+    d[0].u = *reinterpret_cast<const uint4*>(d1 + q * 16);
+    d[1].u = *reinterpret_cast<const uint4*>(d1 + q * 16 + 8);
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc[c] += g * (bf2f(a[c >> 3].h[c & 7]) + bf2f(d[c >> 3].h[c & 7]));
+    acc[16] += g;
+  }
+#pragma unroll
+  for (int c = 0; c < 17; ++c) red[c][threadIdx.x] = acc[c];
+  __syncthreads();
+  if (threadIdx.x < 17) {
+    float t = 0.f;
+    for (int k = 0; k < 256; ++k) t += red[threadIdx.x][k];
+    partial[blockIdx.x * 17 + threadIdx.x] = t;
   }
 }
 
-// g[t*16 + ci] = full[t][ci][0]
-__global__ void k_head_extract(const float* __restrict__ full, float* __restrict__ g) {
-  for (int e = threadIdx.x; e < 27 * 16; e += blockDim.x) g[e] = full[e * 16];
+// g[c] = sum_blk partial[blk][c] (fixed order, FP64): weights g[0..16), bias gb
+__global__ void k_head_wgrad_reduce(const float* __restrict__ partial, int nblk, float* __restrict__ gw,
+                                    float* __restrict__ gb) {
+  const int c = threadIdx.x;
+  if (c >= 17) return;
+  double t = 0.0;
+  for (int b = 0; b < nblk; ++b) t += partial[b * 17 + c];
+  if (c < 16) gw[c] = (float)t;
+  else gb[0] = (float)t;
 }
 
 // ------------------------------------------------------------ loss gradient
@@ -490,10 +848,12 @@ __global__ void k_adam(long long n, float* __restrict__ w, const float* __restri
   }
 }
 
-// forward fragments: frag[(ks*MT+mt)*64 + lane][j] = W[k][co], k = ks*32 + (lane/16)*8 + j,
-// co = mt*16 + lane%16 (0 beyond K)
-__global__ void k_pack_fwd(const float* __restrict__ w, int cin, int cout, bf16_t* __restrict__ frag) {
-  const int K = 27 * cin, KS = (K + 31) / 32, MT = cout / 16;
+// forward fragments of the tiled convolution: frag[(kc*MT+mt)*64 + lane][j] =
+// W[t][g*CG + c][co] for k = kc*32 + (lane/16)*8 + j taken in the order of the
+// staged channel groups, k = g*(27*CG) + t*CG + c (CG = min(cin, 32) channels
+// per group), co = mt*16 + lane%16; 0 beyond K = 27*cin
+__global__ void k_pack_tile(const float* __restrict__ w, int cin, int cout, bf16_t* __restrict__ frag) {
+  const int K = 27 * cin, KS = (K + 31) / 32, MT = cout / 16, CG = cin < 32 ? cin : 32;
   GRID_STRIDE(e, (long long)KS * MT * 64 * 8) {
     const int j = (int)(e % 8);
     const long long f = e / 8;
@@ -501,7 +861,13 @@ __global__ void k_pack_fwd(const float* __restrict__ w, int cin, int cout, bf16_
     const long long km = f / 64;
     const int mt = (int)(km % MT), ks = (int)(km / MT);
     const int k = ks * 32 + (lane >> 4) * 8 + j, co = mt * 16 + (lane & 15);
-    frag[e] = k < K ? f2bf(w[(long long)k * cout + co]) : (bf16_t)0;
+    bf16_t v = 0;
+    if (k < K) {
+      const int g = k / (27 * CG), kl = k % (27 * CG);
+      const int t = kl / CG, ci = g * CG + kl % CG;
+      v = f2bf(w[((long long)t * cin + ci) * cout + co]);
+    }
+    frag[e] = v;
   }
 }
 
@@ -526,14 +892,15 @@ __global__ void k_pack_bwd(const float* __restrict__ w, int cin, int cout, bf16_
 
 // head weights rounded to BF16 (kept as float)
 __global__ void k_pack_head(const float* __restrict__ w, float* __restrict__ wq) {
-  for (int e = threadIdx.x; e < 27 * 16; e += blockDim.x) wq[e] = bf2f(f2bf(w[e]));
+  for (int e = threadIdx.x; e < 16; e += blockDim.x) wq[e] = bf2f(f2bf(w[e]));
 }
 
 }  // namespace
 
 // ============================================================== host side
 // Channels per level 16, 32, 64, 64, ...; convolutions in parameter order:
-// encoder e_0..e_{L-1}, bottleneck b, decoder d_{L-2}..d_1, head (16 -> 1).
+// encoder e_0..e_{L-1}, bottleneck b, decoder d_{L-2}..d_1, head (16 -> 1,
+// 1 x 1 x 1); all others 3 x 3 x 3.
 inline int level_channels(int l) { return l == 0 ? 16 : l == 1 ? 32 : 64; }
 
 struct UNet {
@@ -544,13 +911,14 @@ struct UNet {
   std::vector<long long> off_w, off_b;
   long long nparam = 0;
   DevBuf params, grads, adam_m, adam_v;              // FP32, nparam
-  std::vector<DevBuf> frag_f, frag_b;                // packed BF16 weight fragments
-  DevBuf head_w;
+  std::vector<DevBuf> frag_t, frag_b;                // packed BF16 weight fragments (forward tiles, data gradient)
+  DevBuf head_w;                                     // 16 head weights, BF16 values
   DevBuf x0, ell;
   DevBuf a[kMaxLevels], p[kMaxLevels], d[kMaxLevels];            // activations (BF16)
   DevBuf skip[kMaxLevels], dd[kMaxLevels], da[kMaxLevels], dp[kMaxLevels];  // gradients (BF16)
+  DevBuf h0, g1;                                     // FP32 head partials: full resolution, level 1
   DevBuf zt, Az, dz;                                 // FP32 cells
-  DevBuf wpart, cpart, htmp, dypad;                  // FP32 partials, head scratch
+  DevBuf wpart, cpart, hpart;                        // FP32 partials of the weight gradients
   DevBuf scal;                                       // double: rr, a, c
   const void* ell_op = nullptr;
   int ell_version = -1;
@@ -586,8 +954,9 @@ long long count_params(int L, std::vector<long long>* off_w, std::vector<long lo
   layer_shapes(L, ci, co);
   long long o = 0;
   for (size_t l = 0; l < ci.size(); ++l) {
+    const long long taps = l + 1 == ci.size() ? 1 : 27;
     if (off_w) off_w->push_back(o);
-    o += 27LL * ci[l] * co[l];
+    o += taps * ci[l] * co[l];
     if (off_b) off_b->push_back(o);
     o += co[l];
   }
@@ -595,23 +964,44 @@ long long count_params(int L, std::vector<long long>* off_w, std::vector<long lo
 }
 
 inline int eblocks(long long n) { return blocks_for(n, kBlock, 8192); }
+inline long long tile_frag_bytes(int cin, int cout) { return (long long)((27 * cin + 31) / 32) * (cout / 16) * 64 * 16; }
 
 nfa_status pack_all(UNet& u, hipStream_t s) {
   const float* P = u.params.as<float>();
   for (int l = 0; l < u.nlayers - 1; ++l) {
     const int cin = u.cin[l], cout = u.cout[l];
-    const long long nf = (long long)((27 * cin + 31) / 32) * (cout / 16) * 64 * 8;
-    k_pack_fwd<<<eblocks(nf), kBlock, 0, s>>>(P + u.off_w[l], cin, cout, u.frag_f[l].as<bf16_t>());
+    k_pack_tile<<<eblocks(tile_frag_bytes(cin, cout) / 2), kBlock, 0, s>>>(P + u.off_w[l], cin, cout,
+                                                                            u.frag_t[l].as<bf16_t>());
     if (l > 0) {
       const long long nb = (long long)((27 * cout + 31) / 32) * (cin / 16) * 64 * 8;
       k_pack_bwd<<<eblocks(nb), kBlock, 0, s>>>(P + u.off_w[l], cin, cout, u.frag_b[l].as<bf16_t>());
     }
   }
-  k_pack_head<<<1, 512, 0, s>>>(P + u.off_w[u.Hd()], u.head_w.as<float>());
+  k_pack_head<<<1, 64, 0, s>>>(P + u.off_w[u.Hd()], u.head_w.as<float>());
   NFA_CHECK_LAUNCH();
   return NFA_OK;
 }
 
+// ---------------------------------------------------------------- forward convolutions
+template <int CIN, int COUT, bool UPADD, bool FEAT, int SUB = 1>
+void tconv_t(TconvArgs a, hipStream_t s) {
+  a.nbx = (a.W + kTX - 1) / kTX;
+  a.nby = (a.H + Brick<SUB>::TY - 1) / Brick<SUB>::TY;
+  a.nb = a.nbx * a.nby * ((a.D + Brick<SUB>::TZ - 1) / Brick<SUB>::TZ);
+  a.per = (a.nb + 7) / 8;
+  k_tconv<CIN, COUT, UPADD, FEAT, SUB><<<8 * a.per, 256, 0, s>>>(a);
+}
+
+nfa_status tconv(int cin, int cout, bool upadd, const TconvArgs& a, hipStream_t s) {
+#define T_(A, B, U) \
+  if (cin == A && cout == B && upadd == U) { tconv_t<A, B, U, false>(a, s); return NFA_OK; }
+  T_(16, 32, false) T_(32, 64, false) T_(64, 64, false) T_(64, 32, false)
+  T_(32, 16, true) T_(64, 32, true) T_(64, 64, true)
+#undef T_
+  return fail(NFA_ERR_INVALID, "learned preconditioner: no convolution kernel for this shape");
+}
+
+// data-gradient convolutions (direct gathers)
 template <int CIN, int COUT, bool UPADD>
 void conv_t(int D, int H, int W, const bf16_t* in, const bf16_t* in2, const DevBuf& frag, const float* bias,
             int relu, const bf16_t* mask, bf16_t* out, const SolveScalars* sc, hipStream_t s) {
@@ -625,10 +1015,9 @@ nfa_status conv(int cin, int cout, bool upadd, int D, int H, int W, const bf16_t
                 const SolveScalars* sc, hipStream_t s) {
 #define C_(A, B, U) \
   if (cin == A && cout == B && upadd == U) { conv_t<A, B, U>(D, H, W, in, in2, frag, bias, relu, mask, out, sc, s); return NFA_OK; }
-  C_(2, 16, false) C_(16, 32, false) C_(32, 64, false) C_(64, 64, false) C_(64, 32, false)
-  C_(32, 16, false) C_(32, 16, true) C_(64, 32, true) C_(64, 64, true) C_(16, 32, false) C_(32, 64, true)
+  C_(16, 32, false) C_(32, 64, false) C_(64, 64, false) C_(32, 16, false) C_(64, 32, false)
 #undef C_
-  return fail(NFA_ERR_INVALID, "learned preconditioner: no convolution kernel for this shape");
+  return fail(NFA_ERR_INVALID, "learned preconditioner: no data-gradient kernel for this shape");
 }
 
 template <int CIN, int COUT, bool UPADD>
@@ -657,15 +1046,6 @@ nfa_status wgrad(UNet& u, int layer, bool upadd, int level, const bf16_t* in, co
   return fail(NFA_ERR_INVALID, "learned preconditioner: no weight-gradient kernel for this shape");
 }
 
-void pool(int C, int level_out, const UNet& u, const bf16_t* fine, bf16_t* coarse, hipStream_t s) {
-  int D, H, W;
-  u.dims(level_out, D, H, W);
-  const long long n = (long long)D * H * W * (C / 8);
-  if (C == 16) k_pool<16><<<eblocks(n), kBlock, 0, s>>>(D, H, W, fine, coarse);
-  else if (C == 32) k_pool<32><<<eblocks(n), kBlock, 0, s>>>(D, H, W, fine, coarse);
-  else k_pool<64><<<eblocks(n), kBlock, 0, s>>>(D, H, W, fine, coarse);
-}
-
 void upT_mask(int C, int level_out, const UNet& u, const bf16_t* fine, const bf16_t* mask, bf16_t* coarse,
               hipStream_t s) {
   int D, H, W;
@@ -688,9 +1068,12 @@ void skip_poolT_mask(int C, int level, const UNet& u, const bf16_t* skip, const 
 
 #define B16(buf) (buf).as<bf16_t>()
 
-// forward on the operator's grid; rr / nred give the residual scale
+// forward on the operator's grid; rr / nred give the residual scale.  keep:
+// store every activation (training, export); otherwise only what a later
+// layer reads: the pooled encoder outputs, the skips, the decoder outputs
+// below level 1 and the two head partials.
 nfa_status forward(UNet& u, Poisson& op, const float* r, float* z, const double* rr, double nred,
-                   const SolveScalars* sc, hipStream_t s) {
+                   const SolveScalars* sc, bool keep, hipStream_t s) {
   Grid& g = *op.g;
   if (g.nx != u.nx || g.ny != u.ny || g.nz != u.nz)
     return fail(NFA_ERR_INVALID, "learned preconditioner: network and operator grids differ");
@@ -701,36 +1084,66 @@ nfa_status forward(UNet& u, Poisson& op, const float* r, float* z, const double*
   }
   const int L = u.L;
   const float* P = u.params.as<float>();
-  int D, H, W;
-  k_prep<<<eblocks(u.npos[0]), kBlock, 0, s>>>(u.npos[0], r, B16(u.ell), rr, nred, B16(u.x0), sc);
-  u.dims(0, D, H, W);
-  nfa_status e = conv(2, 16, false, D, H, W, B16(u.x0), nullptr, u.frag_f[0], P + u.off_b[0], 1, nullptr,
-                      B16(u.a[0]), sc, s);
+  TconvArgs a{};
+  a.sc = sc;
+  a.wproj = u.head_w.as<float>();
+  // first encoder: features formed while staging, pooled output, head partial
+  u.dims(0, a.D, a.H, a.W);
+  a.r = r;
+  a.ell = B16(u.ell);
+  a.rr = rr;
+  a.nred = nred;
+  a.x0 = keep ? B16(u.x0) : nullptr;
+  a.frag = reinterpret_cast<const uint4*>(u.frag_t[0].p);
+  a.bias = P + u.off_b[0];
+  a.out = keep ? B16(u.a[0]) : nullptr;
+  a.pooled = B16(u.p[0]);
+  a.proj = u.h0.as<float>();
+  a.pbias = P + u.off_b[u.Hd()];
+  tconv_t<2, 16, false, true, 2>(a, s);
+  a.r = nullptr;
+  a.ell = nullptr;
+  a.x0 = nullptr;
+  a.proj = nullptr;
+  a.pbias = nullptr;
+  nfa_status e = NFA_OK;
   for (int l = 1; l < L && e == NFA_OK; ++l) {
-    pool(level_channels(l - 1), l, u, B16(u.a[l - 1]), B16(u.p[l - 1]), s);
-    u.dims(l, D, H, W);
-    e = conv(u.cin[u.E(l)], u.cout[u.E(l)], false, D, H, W, B16(u.p[l - 1]), nullptr, u.frag_f[u.E(l)],
-             P + u.off_b[u.E(l)], 1, nullptr, B16(u.a[l]), sc, s);
+    u.dims(l, a.D, a.H, a.W);
+    a.in = B16(u.p[l - 1]);
+    a.frag = reinterpret_cast<const uint4*>(u.frag_t[u.E(l)].p);
+    a.bias = P + u.off_b[u.E(l)];
+    a.out = B16(u.a[l]);
+    a.pooled = l + 1 < L ? B16(u.p[l]) : nullptr;
+    e = tconv(u.cin[u.E(l)], u.cout[u.E(l)], false, a, s);
   }
   if (e != NFA_OK) return e;
-  u.dims(L - 1, D, H, W);
-  e = conv(u.cin[u.B()], u.cout[u.B()], false, D, H, W, B16(u.a[L - 1]), nullptr, u.frag_f[u.B()],
-           P + u.off_b[u.B()], 1, nullptr, B16(u.d[L - 1]), sc, s);
+  u.dims(L - 1, a.D, a.H, a.W);
+  a.in = B16(u.a[L - 1]);
+  a.frag = reinterpret_cast<const uint4*>(u.frag_t[u.B()].p);
+  a.bias = P + u.off_b[u.B()];
+  a.out = B16(u.d[L - 1]);
+  a.pooled = nullptr;
+  if ((e = tconv(u.cin[u.B()], u.cout[u.B()], false, a, s)) != NFA_OK) return e;
   for (int l = L - 2; l >= 1 && e == NFA_OK; --l) {
-    u.dims(l, D, H, W);
-    e = conv(u.cin[u.Dl(l)], u.cout[u.Dl(l)], true, D, H, W, B16(u.a[l]), B16(u.d[l + 1]), u.frag_f[u.Dl(l)],
-             P + u.off_b[u.Dl(l)], 1, nullptr, B16(u.d[l]), sc, s);
+    u.dims(l, a.D, a.H, a.W);
+    a.in = B16(u.a[l]);
+    a.in2 = B16(u.d[l + 1]);
+    a.frag = reinterpret_cast<const uint4*>(u.frag_t[u.Dl(l)].p);
+    a.bias = P + u.off_b[u.Dl(l)];
+    a.out = (l > 1 || keep) ? B16(u.d[l]) : nullptr;
+    a.proj = l == 1 ? u.g1.as<float>() : nullptr;
+    e = tconv(u.cin[u.Dl(l)], u.cout[u.Dl(l)], true, a, s);
   }
   if (e != NFA_OK) return e;
+  int D, H, W;
   u.dims(0, D, H, W);
-  k_head_fwd<<<eblocks(u.npos[0]), kBlock, 0, s>>>(D, H, W, B16(u.x0), B16(u.a[0]), B16(u.d[1]),
-                                                   u.head_w.as<float>(), P + u.off_b[u.Hd()],
-                                                   op.dinv32.as<float>(), z, sc);
+  k_head_out<<<eblocks(u.npos[0] / 4), kBlock, 0, s>>>(D, H, W, u.h0.as<float>(), u.g1.as<float>(),
+                                                       op.dinv32.as<float>(), z, sc);
   NFA_CHECK_LAUNCH();
   return NFA_OK;
 }
 
-// gradients of all parameters from dL/dz (in u.dz)
+// gradients of all parameters from dL/dz (in u.dz), after a forward with keep
 nfa_status backward(UNet& u, Poisson& op, hipStream_t s) {
   const int L = u.L;
   int D, H, W;
@@ -738,21 +1151,13 @@ nfa_status backward(UNet& u, Poisson& op, hipStream_t s) {
   float* G = u.grads.as<float>();
   const float* dinv = op.dinv32.as<float>();
   const long long n0 = u.npos[0];
-  // head: data gradient into skip[0], weights through the MFMA weight gradient
-  // with dy = dinv*dz as channel 0 of a 16-channel tensor
-  k_head_bwd_data<<<eblocks(n0), kBlock, 0, s>>>(D, H, W, u.dz.as<float>(), dinv, u.head_w.as<float>(),
-                                                 B16(u.skip[0]));
-  k_pad_dy<<<eblocks(n0), kBlock, 0, s>>>(n0, u.dz.as<float>(), dinv, B16(u.dypad));
-  {
-    dim3 grid(kWgradBlocks, 27);
-    k_wgrad<16, 16, true><<<grid, 256, 0, s>>>(D, H, W, B16(u.a[0]), B16(u.d[1]), B16(u.dypad),
-                                               u.wpart.as<float>());
-    k_wgrad_reduce<<<eblocks(27LL * 256), kBlock, 0, s>>>(u.wpart.as<float>(), kWgradBlocks, 256,
-                                                         u.htmp.as<float>());
-    k_head_extract<<<1, 512, 0, s>>>(u.htmp.as<float>(), G + u.off_w[u.Hd()]);
-    k_colsum<16><<<kWgradBlocks, 256, 0, s>>>(n0, B16(u.dypad), u.cpart.as<float>());
-    k_colsum_reduce<<<1, 64, 0, s>>>(u.cpart.as<float>(), kWgradBlocks, 16, 1, G + u.off_b[u.Hd()]);
-  }
+  // head (1 x 1 x 1): data gradient into skip[0]; weights and bias summed over
+  // positions against a0 + up(d1)
+  k_head_dgrad<<<eblocks(n0), kBlock, 0, s>>>(n0, u.dz.as<float>(), dinv, u.head_w.as<float>(), B16(u.skip[0]));
+  k_head_wgrad<<<kHeadBlocks, 256, 0, s>>>(D, H, W, u.dz.as<float>(), dinv, B16(u.a[0]), B16(u.d[1]),
+                                           u.hpart.as<float>());
+  k_head_wgrad_reduce<<<1, 64, 0, s>>>(u.hpart.as<float>(), kHeadBlocks, G + u.off_w[u.Hd()],
+                                       G + u.off_b[u.Hd()]);
   nfa_status e = NFA_OK;
   // decoder, fine to coarse
   for (int l = 1; l <= L - 2 && e == NFA_OK; ++l) {
@@ -799,7 +1204,7 @@ nfa_status grad_step(UNet& u, Poisson& op, const float* r, double eAe, double* l
   const long long n = u.npos[0];
   int nb = launch_dot<float>(r, r, n, parts, nullptr, s);
   launch_sum_partials(parts, nb, 1, scal, s);
-  nfa_status e = forward(u, op, r, u.zt.as<float>(), scal, (double)op.g->n_reduced, nullptr, s);
+  nfa_status e = forward(u, op, r, u.zt.as<float>(), scal, (double)op.g->n_reduced, nullptr, true, s);
   if (e != NFA_OK) return e;
   e = nfa_poisson_apply(&static_cast<nfa_poisson_s&>(op), u.zt.p, u.Az.p, NFA_F32, s);
   if (e != NFA_OK) return e;
@@ -825,7 +1230,7 @@ nfa_status unet_precond_apply(void* unet, Poisson& op, const float* r, float* z,
                               const SolveScalars* sc, hipStream_t s) {
   if (!unet) return fail(NFA_ERR_INVALID, "learned preconditioner: no network");
   UNet& u = *static_cast<nfa_unet_s*>(unet);
-  return forward(u, op, r, z, &sc->rr, (double)op.g->n_reduced, sc, s);
+  return forward(u, op, r, z, &sc->rr, (double)op.g->n_reduced, sc, false, s);
 }
 
 }  // namespace nfa
@@ -853,7 +1258,7 @@ extern "C" nfa_status nfa_unet_create(int nx, int ny, int nz, int levels, int se
   layer_shapes(levels, u->cin, u->cout);
   u->nlayers = (int)u->cin.size();
   u->nparam = count_params(levels, &u->off_w, &u->off_b);
-  u->frag_f.resize(u->nlayers);
+  u->frag_t.resize(u->nlayers);
   u->frag_b.resize(u->nlayers);
   auto bad = [&](hipError_t e) {
     delete u;
@@ -866,10 +1271,10 @@ extern "C" nfa_status nfa_unet_create(int nx, int ny, int nz, int levels, int se
   UALLOC(adam_m, u->nparam * 4);
   UALLOC(adam_v, u->nparam * 4);
   for (int l = 0; l < u->nlayers - 1; ++l) {
-    UALLOC(frag_f[l], (size_t)((27 * u->cin[l] + 31) / 32) * (u->cout[l] / 16) * 64 * 16);
+    UALLOC(frag_t[l], (size_t)tile_frag_bytes(u->cin[l], u->cout[l]));
     if (l > 0) UALLOC(frag_b[l], (size_t)((27 * u->cout[l] + 31) / 32) * (u->cin[l] / 16) * 64 * 16);
   }
-  UALLOC(head_w, 27 * 16 * 4);
+  UALLOC(head_w, 16 * 4);
   const long long n0 = u->npos[0];
   UALLOC(ell, n0 * 2);
   UALLOC(x0, n0 * 2 * 2);
@@ -893,8 +1298,9 @@ extern "C" nfa_status nfa_unet_create(int nx, int ny, int nz, int levels, int se
   UALLOC(dz, n0 * 4);
   UALLOC(wpart, 27LL * kWgradBlocks * 64 * 64 * 4);
   UALLOC(cpart, (size_t)kWgradBlocks * 64 * 4);
-  UALLOC(htmp, 27 * 256 * 4);
-  UALLOC(dypad, n0 * 16 * 2);
+  UALLOC(hpart, (size_t)kHeadBlocks * 17 * 4);
+  UALLOC(h0, n0 * 4);
+  UALLOC(g1, u->npos[1] * 4);
   UALLOC(scal, 8 * 8);
 #undef UALLOC
   // He-normal initial weights, zero biases, head zero (the Jacobi step)
@@ -943,14 +1349,17 @@ extern "C" nfa_status nfa_unet_get_grads(nfa_unet u, float* host) {
   return NFA_OK;
 }
 
-extern "C" nfa_status nfa_unet_forward(nfa_unet u, nfa_poisson op, const float* r, float* z, nfa_stream s) {
+extern "C" nfa_status nfa_unet_forward(nfa_unet u, nfa_poisson op, const float* r, float* z, int keep,
+                                       nfa_stream s) {
   if (!u || !op || !r || !z) return fail(NFA_ERR_INVALID, "nfa_unet_forward: NULL argument");
+  if ((reinterpret_cast<uintptr_t>(z) & 15) != 0)
+    return fail(NFA_ERR_INVALID, "nfa_unet_forward: z must be 16-byte aligned");
   if (const nfa_status e = require_assembled(*op, "nfa_unet_forward")) return e;
   const hipStream_t st = S(s);
   double* parts = op->partials.as<double>();
   const int nb = launch_dot<float>(r, r, u->npos[0], parts, nullptr, st);
   launch_sum_partials(parts, nb, 1, u->scal.as<double>(), st);
-  return forward(*u, *op, r, z, u->scal.as<double>(), (double)op->g->n_reduced, nullptr, st);
+  return forward(*u, *op, r, z, u->scal.as<double>(), (double)op->g->n_reduced, nullptr, keep != 0, st);
 }
 
 extern "C" nfa_status nfa_unet_grad(nfa_unet u, nfa_poisson op, const float* r, double eAe, double* loss,

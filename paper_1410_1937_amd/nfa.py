@@ -115,7 +115,7 @@ _sig("nfa_unet_levels", c_int, [c_void_p])
 _sig("nfa_unet_get_params", c_int, [c_void_p, c_void_p])
 _sig("nfa_unet_set_params", c_int, [c_void_p, c_void_p])
 _sig("nfa_unet_get_grads", c_int, [c_void_p, c_void_p])
-_sig("nfa_unet_forward", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p])
+_sig("nfa_unet_forward", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p])
 _sig("nfa_unet_grad", c_int, [c_void_p, c_void_p, c_void_p, c_double, ctypes.POINTER(c_double), c_void_p])
 _sig("nfa_unet_train_step", c_int, [c_void_p, c_void_p, c_void_p, c_double, ctypes.c_float, c_int,
                                     ctypes.POINTER(c_double), c_void_p])
@@ -594,6 +594,11 @@ def unet_channels(levels):
     return [16, 32, 64][:levels] + [64] * max(0, levels - 3)
 
 
+def unet_taps(levels=3):
+    """Taps per convolution in parameter order: 27 each, 1 for the head."""
+    return [27] * (len(unet_shapes(levels)) - 1) + [1]
+
+
 def unet_shapes(levels=3):
     c = unet_channels(levels)
     out = [(2, c[0])] + [(c[l - 1], c[l]) for l in range(1, levels)]
@@ -635,9 +640,9 @@ class UNet:
 
     def unflatten(self, flat):
         out, o = [], 0
-        for ci, co in unet_shapes(self.levels):
-            w = flat[o:o + 27 * ci * co].reshape(27, ci, co)
-            o += 27 * ci * co
+        for (ci, co), nt in zip(unet_shapes(self.levels), unet_taps(self.levels)):
+            w = flat[o:o + nt * ci * co].reshape(nt, ci, co)
+            o += nt * ci * co
             b = flat[o:o + co]
             o += co
             out.append((w, b))
@@ -647,10 +652,12 @@ class UNet:
     def flatten(params):
         return np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in params]).astype(np.float32)
 
-    def forward(self, op, r, out=None):
+    def forward(self, op, r, out=None, keep=False):
+        """z = network(r); keep=True also stores every activation for export()."""
         z = torch.empty_like(r) if out is None else out
         _check(lib.nfa_unet_forward(self.h, op.h, _dev(r, torch.float32, self.shape, "r"),
-                                    _dev(z, torch.float32, self.shape, "z"), _stream()), "nfa_unet_forward")
+                                    _dev(z, torch.float32, self.shape, "z"), int(bool(keep)), _stream()),
+               "nfa_unet_forward")
         return z
 
     def grad(self, op, r, eAe):

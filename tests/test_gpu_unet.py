@@ -41,7 +41,7 @@ def setup():
     net.set_params(nfa.UNet.flatten(params))
     r = (ob_rhs * ob.reduced).astype(np.float32)
     rt = torch.as_tensor(r, device="cuda")
-    z = host(net.forward(gop, rt)).astype(np.float64)
+    z = host(net.forward(gop, rt, keep=True)).astype(np.float64)
     return wl, (og, ob, oop, ob_rhs), (gg, gop), net, [(w.astype(np.float64), b.astype(np.float64)) for w, b in params], r, rt, z
 
 
@@ -65,8 +65,9 @@ def test_forward_layers_within_one_bf16_step(setup):
     _ulp_ok(b2, ou.bf16(ou.relu(ou.conv3d(a2, *P[3]))))
     d1 = _bf(net.export("d1"))
     _ulp_ok(d1, ou.bf16(ou.relu(ou.conv3d(ou.bf16(ou.up(b2) + a1), *P[4]))))
-    s0 = ou.bf16(ou.up(d1) + a0)
-    y = x0[..., 0] + ou.conv3d(s0, *P[5])[..., 0]
+    # the 1x1x1 head on up(d1) + a0, summed without rounding
+    w5, b5 = P[5]
+    y = x0[..., 0] + ((b5[0] + a0 @ w5[0][:, 0]) + ou.up(d1 @ w5[0][:, 0]))
     zref = oop.dinv * y
     assert np.max(np.abs(z - zref)) <= 1e-5 * np.max(np.abs(zref))
 
@@ -88,7 +89,7 @@ def test_untrained_network_is_jacobi_on_the_bf16_residual():
     gg, gop = gpu_for(wl)
     net = nfa.UNet(16, 16, 8, seed=0)
     r = (ob_rhs * ob.reduced).astype(np.float32)
-    z = host(net.forward(gop, torch.as_tensor(r, device="cuda")))
+    z = host(net.forward(gop, torch.as_tensor(r, device="cuda"), keep=True))
     x0 = _bf(net.export("x0"))
     assert np.array_equal(z, (gop.export("dinv32").cpu().numpy() * x0[..., 0].astype(np.float32)))
 

@@ -137,3 +137,21 @@ def test_adam_first_step_is_signed_learning_rate():
     w = np.array([1.0, 2.0, 3.0])
     w1, m, v = unet.adam(w, g, np.zeros(3), np.zeros(3), 1, lr=0.01)
     assert np.allclose(w1, w - 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+
+
+def test_head_is_the_centre_tap_of_a_three_by_three_convolution():
+    """C4's 1x1x1 head, evaluated as head(a0) + up(head(d1)) with the bias
+    once, equals a 3x3x3 convolution (pinned against scipy above) whose only
+    non-zero tap is the centre one, applied to up(d1) + a0."""
+    rng = np.random.default_rng(7)
+    params = unet.init_params(2, zero_last=False, levels=3)
+    params = [(w, rng.standard_normal(b.shape) * 0.1) for w, b in params]
+    assert params[-1][0].shape == (1, 16, 1)
+    x0 = rng.standard_normal((8, 12, 16, 2))
+    y, cache = unet.forward(params, x0, quant=False)
+    w5, b5 = params[-1]
+    w27 = np.zeros((27, 16, 1))
+    w27[13] = w5[0]
+    s0 = unet.up(cache["d"][1]) + cache["a"][0]
+    ref = x0[..., 0] + unet.conv3d(s0, w27, b5)[..., 0]
+    assert np.max(np.abs(y - ref)) <= 1e-12 * np.max(np.abs(ref))
