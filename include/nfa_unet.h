@@ -16,12 +16,11 @@
  *   a2 = relu(conv2(pool(a1)))     32 -> 64   1/4
  *   b2 = relu(conv3(a2))           64 -> 32   1/4
  *   d1 = relu(conv4(up(b2) + a1))  32 -> 16   1/2
- *   z  = D^-1 (r/s + head(up(d1) + a0))       16 -> 1, full resolution
+ *   d0 = relu(conv5(up(d1) + a0))  16 -> 16   full resolution
+ *   z  = D^-1 (r/s + head(d0))               16 -> 1, full resolution
  * with D^-1 the Jacobi inverse diagonal of the assembled operator, so the
- * network with a zero head is the Jacobi step.  conv0..conv4 are 3x3x3; the
- * head is 1x1x1, evaluated as head(a0) + up(head(d1)) (the sum up(d1) + a0 is
- * not rounded to BF16).  Grid sizes must be multiples of 4 in every
- * direction.
+ * network with a zero head is the Jacobi step.  conv0..conv5 are 3x3x3; the
+ * head is 1x1x1.  Grid sizes must be multiples of 4 in every direction.
  *
  * Parameters: weights [taps][cin][cout] (tap t = 9(dz+1) + 3(dy+1) + (dx+1);
  * one tap for the head) then bias [cout] per convolution; FP32 master copies,
@@ -42,15 +41,42 @@ extern "C" {
 
 typedef struct nfa_unet_s* nfa_unet;
 
+/* Bytes of device workspace a network with `levels` levels on an
+ * nx x ny x nz grid needs: its parameters, their gradients and the two Adam
+ * moments (FP32, nfa_unet_param_count each), the packed weight fragments,
+ * every activation and activation gradient (BF16, channels-last), the head
+ * terms and the weight-gradient partials.  0 for invalid sizes. */
+size_t nfa_unet_workspace_bytes(int nx, int ny, int nz, int levels);
+
 /* Network with `levels` resolution levels (3 = the network above; each
  * further level adds a 64-channel level with the same encoder / decoder
- * pattern; 3..6) and its activation workspace for an nx x ny x nz grid
- * (multiples of 2^(levels-1)); weights He-initialised from `seed`, head
- * zero.  Allocates device memory.  Errors: NFA_ERR_INVALID, NFA_ERR_HIP. */
-nfa_status nfa_unet_create(int nx, int ny, int nz, int levels, int seed, nfa_unet* out);
+ * pattern; 3..6) for an nx x ny x nz grid (multiples of 2^(levels-1));
+ * weights He-initialised from `seed`, biases and head zero, Adam moments zero.
+ *   workspace : DEVICE, 256-byte aligned, ws_bytes >=
+ *               nfa_unet_workspace_bytes(...), owned by the caller and kept
+ *               alive while the network exists: every device buffer of the
+ *               network is a slice of it, so forward, gradient and training
+ *               steps never allocate.  NULL: the library allocates the same
+ *               buffers itself, here.
+ * Errors: NFA_ERR_NOMEM (workspace too short; nothing created),
+ * NFA_ERR_INVALID, NFA_ERR_HIP. */
+nfa_status nfa_unet_create(int nx, int ny, int nz, int levels, int seed, void* workspace, size_t ws_bytes,
+                           nfa_unet* out);
+
+/* nfa_unet_bind -- keep the parameters (FP32 master copies; the BF16 ones
+ * the convolutions read are packed from them), their gradients and the Adam
+ * moments in four caller-owned DEVICE arrays of nfa_unet_param_count floats
+ * each (distinct, 4-byte aligned, kept alive while the network uses them).
+ *   copy = 1 : the network's current values are copied into them first (the
+ *              caller takes over the state, e.g. right after creation);
+ *   copy = 0 : their contents are the state (resuming saved training); the
+ *              packed weights are rebuilt from `params`.
+ * Later training steps update them in place.  Synchronous.  Errors:
+ * NFA_ERR_INVALID, NFA_ERR_HIP. */
+nfa_status nfa_unet_bind(nfa_unet u, float* params, float* grads, float* adam_m, float* adam_v, int copy);
 /* Number of FP32 parameters of a network with `levels` levels (-1 if out of
  * range).  Parameter order: encoder e_0..e_{L-1}, bottleneck, decoder
- * d_{L-2}..d_1, head; each weights [taps][cin][cout] then bias [cout], with
+ * d_{L-2}..d_0, head; each weights [taps][cin][cout] then bias [cout], with
  * 27 taps but 1 for the head. */
 long long nfa_unet_param_count(int levels);
 int nfa_unet_levels(nfa_unet u);
@@ -88,7 +114,7 @@ nfa_status nfa_unet_train_step(nfa_unet u, nfa_poisson op, const float* r, doubl
 #define NFA_UNET_X0 0  /* n_0 x 2 */
 #define NFA_UNET_A 16  /* + l: encoder a_l, n_l x c_l */
 #define NFA_UNET_P 32  /* + l: pool(a_l), n_{l+1} x c_l */
-#define NFA_UNET_D 48  /* + l (l >= 1): decoder d_l (d_{L-1}: bottleneck), n_l x c_{l-1} */
+#define NFA_UNET_D 48  /* + l: decoder d_l (d_{L-1}: bottleneck), n_l x c_{l-1} (d_0: n_0 x 16) */
 nfa_status nfa_unet_export(nfa_unet u, int what, void* dst, nfa_stream s); /* ASYNC */
 void nfa_unet_destroy(nfa_unet u);
 

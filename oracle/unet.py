@@ -13,13 +13,13 @@ density to a correction of the Jacobi step (deeper variants add levels of
     a2 = relu(conv2(pool(a1)))      1/4,  32 -> 64
     b2 = relu(conv3(a2))            1/4,  64 -> 32
     d1 = relu(conv4(up(b2) + a1))   1/2,  32 -> 16
-    y  = r / s + head(up(d1) + a0)  full,  16 -> 1, a 1x1x1 convolution
+    d0 = relu(conv5(up(d1) + a0))   full, 16 -> 16
+    y  = r / s + head(d0)           full, 16 -> 1, a 1x1x1 convolution
     z  = D^-1 y                     (Jacobi inverse diagonal of the operator)
 
 so the untrained network with a zero head is exactly the Jacobi
-preconditioner.  The head is linear, so it is evaluated as
-head(a0) + up(head(d1)) without bias on the second term: the sum up(d1) + a0
-is not a storage point (it is never rounded to BF16).
+preconditioner.  Every level decodes with a 3x3x3 convolution, the finest
+too, before the 1x1x1 head (C4).
 
 Training loss per (residual r, error e = A'^-1 r) pair: the share of the
 A-norm error that one flexible-CG step along z leaves,
@@ -50,12 +50,13 @@ def channels(levels):
 
 def shapes(levels=3):
     """(Cin, Cout) of the convolutions in parameter order: encoder e0..e_{L-1},
-    bottleneck b, decoder d_{L-2}..d_1, head.  Every convolution is 3x3x3
+    bottleneck b, decoder d_{L-2}..d_0, head.  Every convolution is 3x3x3
     except the head, 1x1x1 (C4's head); `taps` gives the count."""
     c = channels(levels)
     out = [(2, c[0])] + [(c[l - 1], c[l]) for l in range(1, levels)]
     out.append((c[levels - 1], c[levels - 2]))
     out += [(c[l], c[l - 1]) for l in range(levels - 2, 0, -1)]
+    out.append((c[0], c[0]))
     out.append((c[0], 1))
     return out
 
@@ -162,14 +163,14 @@ def features(r, inv_rho, mask):
 
 
 def _levels(params):
-    return len(params) // 2
+    return (len(params) - 1) // 2
 
 
 def forward(params, x0, quant=True):
     """Returns (y, cache); y = x0[..., 0] + head(up(d1) + a0) on (D, H, W)."""
     L = _levels(params)
     P = [(_q(w, quant), _q(b, False)) for w, b in params]
-    E, B, Dd, Hd = P[:L], P[L], P[L + 1:2 * L - 1], P[2 * L - 1]
+    E, B, Dd, Hd = P[:L], P[L], P[L + 1:2 * L], P[2 * L]
     x0 = _q(x0, quant)
     a = [_q(relu(conv3d(x0, *E[0])), quant)]
     p = []
@@ -178,12 +179,11 @@ def forward(params, x0, quant=True):
         a.append(_q(relu(conv3d(p[l - 1], *E[l])), quant))
     d = {L - 1: _q(relu(conv3d(a[L - 1], *B)), quant)}
     s = {}
-    for i, l in enumerate(range(L - 2, 0, -1)):
+    for i, l in enumerate(range(L - 2, -1, -1)):
         s[l] = _q(up(d[l + 1]) + a[l], quant)
         d[l] = _q(relu(conv3d(s[l], *Dd[i])), quant)
     wh, bh = Hd
-    s[0] = up(d[1]) + a[0]
-    u = (bh[0] + a[0] @ wh[0][:, 0]) + up(d[1] @ wh[0][:, 0])
+    u = bh[0] + d[0] @ wh[0][:, 0]
     y = x0[..., 0] + u
     return y, dict(P=P, L=L, x0=x0, a=a, p=p, d=d, s=s)
 
@@ -192,11 +192,13 @@ def backward(cache, dy, quant=True):
     """Gradients (dw, db) of every conv, in parameter order, for dL/dy on
     (D, H, W).  Stored gradient tensors are BF16 when quant (as on the GPU)."""
     L, P, a, p, d, s = cache["L"], cache["P"], cache["a"], cache["p"], cache["d"], cache["s"]
-    E, B, Dd, Hd = P[:L], P[L], P[L + 1:2 * L - 1], P[2 * L - 1]
-    gE, gD = [None] * L, [None] * (L - 2)
+    E, B, Dd, Hd = P[:L], P[L], P[L + 1:2 * L], P[2 * L]
+    gE, gD = [None] * L, [None] * (L - 1)
     wh = Hd[0]
-    gH = ((s[0].reshape(-1, s[0].shape[-1]).T @ dy.reshape(-1))[None, :, None], np.array([np.sum(dy)]))
-    skip = {0: _q(dy[..., None] * wh[0][:, 0], quant)}
+    gH = ((d[0].reshape(-1, d[0].shape[-1]).T @ dy.reshape(-1))[None, :, None], np.array([np.sum(dy)]))
+    dd0 = _q(dy[..., None] * wh[0][:, 0] * (d[0] > 0), quant)
+    gD[L - 2] = conv3d_wgrad(s[0], dd0)
+    skip = {0: _q(conv3d_dgrad(dd0, Dd[L - 2][0]), quant)}
     for i, l in enumerate(range(1, L - 1)):
         di = L - 2 - l                      # index of d_l in decoder parameter order
         dd = _q(up_T(skip[l - 1]) * (d[l] > 0), quant)

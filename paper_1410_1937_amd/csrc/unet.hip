@@ -736,73 +736,61 @@ __global__ void k_skip_poolT_mask(int D, int H, int W, const bf16_t* __restrict_
 }
 
 // ------------------------------------------------------------ head (1 x 1 x 1, 16 -> 1)
-// z = dinv * (h0 + g1[parent]): h0 = x0[.,0] + (b5 + w5 . a0) from the first
-// encoder's epilogue, g1 = w5 . d1 from the last decoder's (one level
-// coarser, nearest upsampling); 4 x-consecutive cells per thread.
-__global__ __launch_bounds__(256) void k_head_out(int D, int H, int W, const float* __restrict__ h0,
-                                                  const float* __restrict__ g1, const float* __restrict__ dinv,
+// z = dinv * (h0 + u0): h0 = x0[.,0] + b6 from the first encoder's epilogue,
+// u0 = w6 . d0 from the finest decoder's; 4 cells per thread.
+__global__ __launch_bounds__(256) void k_head_out(long long nq, const float* __restrict__ h0,
+                                                  const float* __restrict__ u0, const float* __restrict__ dinv,
                                                   float* __restrict__ z, const SolveScalars* __restrict__ sc) {
   if (solve_done(sc)) return;
-  const long long nq = (long long)D * H * W / 4;
-  const int W4 = W / 4, H2 = H >> 1, W2 = W >> 1;
   GRID_STRIDE(e, nq) {
-    const int x4 = (int)(e % W4);
-    const long long rw = e / W4;
-    const int y = (int)(rw % H), zc = (int)(rw / H);
-    const long long q = ((long long)(zc >> 1) * H2 + (y >> 1)) * W2 + 2 * x4;
     const float4 h = reinterpret_cast<const float4*>(h0)[e];
+    const float4 u = reinterpret_cast<const float4*>(u0)[e];
     const float4 d = reinterpret_cast<const float4*>(dinv)[e];
-    const float ga = g1[q], gb = g1[q + 1];
     float4 o;
-    o.x = d.x * (h.x + ga);
-    o.y = d.y * (h.y + ga);
-    o.z = d.z * (h.z + gb);
-    o.w = d.w * (h.w + gb);
+    o.x = d.x * (h.x + u.x);
+    o.y = d.y * (h.y + u.y);
+    o.z = d.z * (h.z + u.z);
+    o.w = d.w * (h.w + u.w);
     reinterpret_cast<float4*>(z)[e] = o;
   }
 }
 
-// data gradient of the head: ds0[p][ci] = bf16(w5[ci] dy[p]),  dy = dinv * dz
+// data gradient through the head into the finest decoder's pre-activation:
+// dd0[p][c] = bf16(w6[c] dy[p]) where d0[p][c] > 0, else 0;  dy = dinv * dz
 __global__ void k_head_dgrad(long long n, const float* __restrict__ dz, const float* __restrict__ dinv,
-                             const float* __restrict__ w5, bf16_t* __restrict__ ds0) {
+                             const float* __restrict__ w6, const bf16_t* __restrict__ d0, bf16_t* __restrict__ dd0) {
   GRID_STRIDE(p, n) {
     const float g = dinv[p] * dz[p];
-    Frag o0, o1;
+    Frag m0, m1, o0, o1;
+    m0.u = *reinterpret_cast<const uint4*>(d0 + p * 16);
+    m1.u = *reinterpret_cast<const uint4*>(d0 + p * 16 + 8);
 #pragma unroll
-    for (int ci = 0; ci < 8; ++ci) {
-      o0.h[ci] = f2bf(w5[ci] * g);
-      o1.h[ci] = f2bf(w5[8 + ci] * g);
+    for (int c = 0; c < 8; ++c) {
+      o0.h[c] = bf2f(m0.h[c]) > 0.f ? f2bf(w6[c] * g) : (bf16_t)0;
+      o1.h[c] = bf2f(m1.h[c]) > 0.f ? f2bf(w6[8 + c] * g) : (bf16_t)0;
     }
-    *reinterpret_cast<uint4*>(ds0 + p * 16) = o0.u;
-    *reinterpret_cast<uint4*>(ds0 + p * 16 + 8) = o1.u;
+    *reinterpret_cast<uint4*>(dd0 + p * 16) = o0.u;
+    *reinterpret_cast<uint4*>(dd0 + p * 16 + 8) = o1.u;
   }
 }
 
-// weight gradient of the head, per workgroup: partial[blk][ci] = sum_p dy[p]
-// (a0[p][ci] + d1[parent(p)][ci]) for ci < 16, partial[blk][16] = sum_p dy[p]
+// weight gradient of the head, per workgroup: partial[blk][c] = sum_p dy[p]
+// d0[p][c] for c < 16, partial[blk][16] = sum_p dy[p]
 constexpr int kHeadBlocks = 256;
-__global__ __launch_bounds__(256) void k_head_wgrad(int D, int H, int W, const float* __restrict__ dz,
-                                                    const float* __restrict__ dinv, const bf16_t* __restrict__ a0,
-                                                    const bf16_t* __restrict__ d1, float* __restrict__ partial) {
+__global__ __launch_bounds__(256) void k_head_wgrad(long long n, const float* __restrict__ dz,
+                                                    const float* __restrict__ dinv, const bf16_t* __restrict__ d0,
+                                                    float* __restrict__ partial) {
   __shared__ float red[17][256];
   float acc[17];
 #pragma unroll
   for (int c = 0; c < 17; ++c) acc[c] = 0.f;
-  const long long n = (long long)D * H * W;
-  const int H2 = H >> 1, W2 = W >> 1;
   GRID_STRIDE(p, n) {
     const float g = dinv[p] * dz[p];
-    const int x = (int)(p % W);
-    const long long rw = p / W;
-    const int y = (int)(rw % H), zc = (int)(rw / H);
-    const long long q = ((long long)(zc >> 1) * H2 + (y >> 1)) * W2 + (x >> 1);
-    Frag a[2], d[2];
-    a[0].u = *reinterpret_cast<const uint4*>(a0 + p * 16);
-    a[1].u = *reinterpret_cast<const uint4*>(a0 + p * 16 + 8);
-    d[0].u = *reinterpret_cast<const uint4*>(d1 + q * 16);
-    d[1].u = *reinterpret_cast<const uint4*>(d1 + q * 16 + 8);
+    Frag a[2];
+    a[0].u = *reinterpret_cast<const uint4*>(d0 + p * 16);
+    a[1].u = *reinterpret_cast<const uint4*>(d0 + p * 16 + 8);
 #pragma unroll
-    for (int c = 0; c < 16; ++c) acc[c] += g * (bf2f(a[c >> 3].h[c & 7]) + bf2f(d[c >> 3].h[c & 7]));
+    for (int c = 0; c < 16; ++c) acc[c] += g * bf2f(a[c >> 3].h[c & 7]);
     acc[16] += g;
   }
 #pragma unroll
@@ -899,7 +887,7 @@ __global__ void k_pack_head(const float* __restrict__ w, float* __restrict__ wq)
 
 // ============================================================== host side
 // Channels per level 16, 32, 64, 64, ...; convolutions in parameter order:
-// encoder e_0..e_{L-1}, bottleneck b, decoder d_{L-2}..d_1, head (16 -> 1,
+// encoder e_0..e_{L-1}, bottleneck b, decoder d_{L-2}..d_0, head (16 -> 1,
 // 1 x 1 x 1); all others 3 x 3 x 3.
 inline int level_channels(int l) { return l == 0 ? 16 : l == 1 ? 32 : 64; }
 
@@ -916,7 +904,7 @@ struct UNet {
   DevBuf x0, ell;
   DevBuf a[kMaxLevels], p[kMaxLevels], d[kMaxLevels];            // activations (BF16)
   DevBuf skip[kMaxLevels], dd[kMaxLevels], da[kMaxLevels], dp[kMaxLevels];  // gradients (BF16)
-  DevBuf h0, g1;                                     // FP32 head partials: full resolution, level 1
+  DevBuf h0, u0, zero16;                             // FP32 head terms: x0[.,0] + b, w . d0; 16 zeros
   DevBuf zt, Az, dz;                                 // FP32 cells
   DevBuf wpart, cpart, hpart;                        // FP32 partials of the weight gradients
   DevBuf scal;                                       // double: rr, a, c
@@ -925,7 +913,7 @@ struct UNet {
   int E(int l) const { return l; }
   int B() const { return L; }
   int Dl(int l) const { return L + 1 + (L - 2 - l); }
-  int Hd() const { return 2 * L - 1; }
+  int Hd() const { return 2 * L; }
   void dims(int l, int& D, int& H, int& W) const { D = nz >> l; H = ny >> l; W = nx >> l; }
 };
 
@@ -945,7 +933,9 @@ void layer_shapes(int L, std::vector<int>& ci, std::vector<int>& co) {
   ci.push_back(level_channels(L - 1));
   co.push_back(level_channels(L - 2));
   for (int l = L - 2; l >= 1; --l) { ci.push_back(level_channels(l)); co.push_back(level_channels(l - 1)); }
-  ci.push_back(16);
+  ci.push_back(16);   // decoder d_0
+  co.push_back(16);
+  ci.push_back(16);   // head
   co.push_back(1);
 }
 
@@ -996,7 +986,7 @@ nfa_status tconv(int cin, int cout, bool upadd, const TconvArgs& a, hipStream_t 
 #define T_(A, B, U) \
   if (cin == A && cout == B && upadd == U) { tconv_t<A, B, U, false>(a, s); return NFA_OK; }
   T_(16, 32, false) T_(32, 64, false) T_(64, 64, false) T_(64, 32, false)
-  T_(32, 16, true) T_(64, 32, true) T_(64, 64, true)
+  T_(32, 16, true) T_(64, 32, true) T_(64, 64, true) T_(16, 16, true)
 #undef T_
   return fail(NFA_ERR_INVALID, "learned preconditioner: no convolution kernel for this shape");
 }
@@ -1015,7 +1005,7 @@ nfa_status conv(int cin, int cout, bool upadd, int D, int H, int W, const bf16_t
                 const SolveScalars* sc, hipStream_t s) {
 #define C_(A, B, U) \
   if (cin == A && cout == B && upadd == U) { conv_t<A, B, U>(D, H, W, in, in2, frag, bias, relu, mask, out, sc, s); return NFA_OK; }
-  C_(16, 32, false) C_(32, 64, false) C_(64, 64, false) C_(32, 16, false) C_(64, 32, false)
+  C_(16, 32, false) C_(32, 64, false) C_(64, 64, false) C_(32, 16, false) C_(64, 32, false) C_(16, 16, false)
 #undef C_
   return fail(NFA_ERR_INVALID, "learned preconditioner: no data-gradient kernel for this shape");
 }
@@ -1041,7 +1031,7 @@ nfa_status wgrad(UNet& u, int layer, bool upadd, int level, const bf16_t* in, co
 #define W_(A, B, U) \
   if (cin == A && cout == B && upadd == U) { wgrad_t<A, B, U>(u, gw, gb, D, H, W, in, in2, dout, s); return NFA_OK; }
   W_(2, 16, false) W_(16, 32, false) W_(32, 64, false) W_(64, 64, false) W_(64, 32, false)
-  W_(32, 16, true) W_(64, 32, true) W_(64, 64, true)
+  W_(32, 16, true) W_(64, 32, true) W_(64, 64, true) W_(16, 16, true)
 #undef W_
   return fail(NFA_ERR_INVALID, "learned preconditioner: no weight-gradient kernel for this shape");
 }
@@ -1087,7 +1077,8 @@ nfa_status forward(UNet& u, Poisson& op, const float* r, float* z, const double*
   TconvArgs a{};
   a.sc = sc;
   a.wproj = u.head_w.as<float>();
-  // first encoder: features formed while staging, pooled output, head partial
+  // first encoder: features formed while staging, pooled output, and the
+  // head's constant part x0[.,0] + b (a projection on zero weights)
   u.dims(0, a.D, a.H, a.W);
   a.r = r;
   a.ell = B16(u.ell);
@@ -1096,11 +1087,13 @@ nfa_status forward(UNet& u, Poisson& op, const float* r, float* z, const double*
   a.x0 = keep ? B16(u.x0) : nullptr;
   a.frag = reinterpret_cast<const uint4*>(u.frag_t[0].p);
   a.bias = P + u.off_b[0];
-  a.out = keep ? B16(u.a[0]) : nullptr;
+  a.out = B16(u.a[0]);
   a.pooled = B16(u.p[0]);
   a.proj = u.h0.as<float>();
+  a.wproj = u.zero16.as<float>();
   a.pbias = P + u.off_b[u.Hd()];
   tconv_t<2, 16, false, true, 2>(a, s);
+  a.wproj = u.head_w.as<float>();
   a.r = nullptr;
   a.ell = nullptr;
   a.x0 = nullptr;
@@ -1124,20 +1117,18 @@ nfa_status forward(UNet& u, Poisson& op, const float* r, float* z, const double*
   a.out = B16(u.d[L - 1]);
   a.pooled = nullptr;
   if ((e = tconv(u.cin[u.B()], u.cout[u.B()], false, a, s)) != NFA_OK) return e;
-  for (int l = L - 2; l >= 1 && e == NFA_OK; --l) {
+  for (int l = L - 2; l >= 0 && e == NFA_OK; --l) {
     u.dims(l, a.D, a.H, a.W);
     a.in = B16(u.a[l]);
     a.in2 = B16(u.d[l + 1]);
     a.frag = reinterpret_cast<const uint4*>(u.frag_t[u.Dl(l)].p);
     a.bias = P + u.off_b[u.Dl(l)];
-    a.out = (l > 1 || keep) ? B16(u.d[l]) : nullptr;
-    a.proj = l == 1 ? u.g1.as<float>() : nullptr;
+    a.out = (l > 0 || keep) ? B16(u.d[l]) : nullptr;
+    a.proj = l == 0 ? u.u0.as<float>() : nullptr;   // the head on d0, fused
     e = tconv(u.cin[u.Dl(l)], u.cout[u.Dl(l)], true, a, s);
   }
   if (e != NFA_OK) return e;
-  int D, H, W;
-  u.dims(0, D, H, W);
-  k_head_out<<<eblocks(u.npos[0] / 4), kBlock, 0, s>>>(D, H, W, u.h0.as<float>(), u.g1.as<float>(),
+  k_head_out<<<eblocks(u.npos[0] / 4), kBlock, 0, s>>>(u.npos[0] / 4, u.h0.as<float>(), u.u0.as<float>(),
                                                        op.dinv32.as<float>(), z, sc);
   NFA_CHECK_LAUNCH();
   return NFA_OK;
@@ -1151,14 +1142,19 @@ nfa_status backward(UNet& u, Poisson& op, hipStream_t s) {
   float* G = u.grads.as<float>();
   const float* dinv = op.dinv32.as<float>();
   const long long n0 = u.npos[0];
-  // head (1 x 1 x 1): data gradient into skip[0]; weights and bias summed over
-  // positions against a0 + up(d1)
-  k_head_dgrad<<<eblocks(n0), kBlock, 0, s>>>(n0, u.dz.as<float>(), dinv, u.head_w.as<float>(), B16(u.skip[0]));
-  k_head_wgrad<<<kHeadBlocks, 256, 0, s>>>(D, H, W, u.dz.as<float>(), dinv, B16(u.a[0]), B16(u.d[1]),
-                                           u.hpart.as<float>());
+  // head (1 x 1 x 1) on d0: its gradient into d0's pre-activation; weights and
+  // bias summed over positions against d0
+  k_head_dgrad<<<eblocks(n0), kBlock, 0, s>>>(n0, u.dz.as<float>(), dinv, u.head_w.as<float>(), B16(u.d[0]),
+                                              B16(u.dd[0]));
+  k_head_wgrad<<<kHeadBlocks, 256, 0, s>>>(n0, u.dz.as<float>(), dinv, B16(u.d[0]), u.hpart.as<float>());
   k_head_wgrad_reduce<<<1, 64, 0, s>>>(u.hpart.as<float>(), kHeadBlocks, G + u.off_w[u.Hd()],
                                        G + u.off_b[u.Hd()]);
-  nfa_status e = NFA_OK;
+  // finest decoder: weights against up(d1) + a0, data gradient into skip[0]
+  nfa_status e = wgrad(u, u.Dl(0), true, 0, B16(u.a[0]), B16(u.d[1]), B16(u.dd[0]), s);
+  if (e != NFA_OK) return e;
+  e = conv(u.cout[u.Dl(0)], u.cin[u.Dl(0)], false, D, H, W, B16(u.dd[0]), nullptr, u.frag_b[u.Dl(0)], nullptr, 0,
+           nullptr, B16(u.skip[0]), nullptr, s);
+  if (e != NFA_OK) return e;
   // decoder, fine to coarse
   for (int l = 1; l <= L - 2 && e == NFA_OK; ++l) {
     const int ly = u.Dl(l);
@@ -1242,67 +1238,114 @@ extern "C" long long nfa_unet_param_count(int levels) {
   return count_params(levels, nullptr, nullptr);
 }
 
-extern "C" nfa_status nfa_unet_create(int nx, int ny, int nz, int levels, int seed, nfa_unet* out) {
-  if (!out) return fail(NFA_ERR_INVALID, "nfa_unet_create: out is NULL");
-  *out = nullptr;
-  if (levels < 3 || levels > kMaxLevels) return fail(NFA_ERR_INVALID, "nfa_unet_create: levels must be in [3, 6]");
+namespace nfa {
+namespace {
+nfa_status unet_check(int nx, int ny, int nz, int levels, const char* who) {
+  if (levels < 3 || levels > kMaxLevels) return fail(NFA_ERR_INVALID, std::string(who) + ": levels must be in [3, 6]");
   const int q = 1 << (levels - 1);
   if (nx < q || ny < q || nz < q || nx % q || ny % q || nz % q)
-    return fail(NFA_ERR_INVALID, "nfa_unet_create: grid sizes must be multiples of 2^(levels-1)");
+    return fail(NFA_ERR_INVALID, std::string(who) + ": grid sizes must be multiples of 2^(levels-1)");
+  return NFA_OK;
+}
+
+void unet_shape(UNet& u, int nx, int ny, int nz, int levels) {
+  u.nx = nx;
+  u.ny = ny;
+  u.nz = nz;
+  u.L = levels;
+  for (int l = 0; l < levels; ++l) u.npos[l] = (long long)(nx >> l) * (ny >> l) * (nz >> l);
+  layer_shapes(levels, u.cin, u.cout);
+  u.nlayers = (int)u.cin.size();
+  u.off_w.clear();
+  u.off_b.clear();
+  u.nparam = count_params(levels, &u.off_w, &u.off_b);
+  u.frag_t.resize(u.nlayers);
+  u.frag_b.resize(u.nlayers);
+}
+
+// Every device buffer of a network, in one fixed order: parameters, their
+// gradients and Adam moments (FP32, nparam each), packed weight fragments,
+// activations and their gradients (BF16), head terms and partial sums.
+hipError_t unet_buffers(UNet& u, Carver& c) {
+  hipError_t e = hipSuccess;
+#define TAKE(buf, bytes) if ((e = c.take(u.buf, (size_t)(bytes))) != hipSuccess) return e
+  TAKE(params, u.nparam * 4);
+  TAKE(grads, u.nparam * 4);
+  TAKE(adam_m, u.nparam * 4);
+  TAKE(adam_v, u.nparam * 4);
+  for (int l = 0; l < u.nlayers - 1; ++l) {
+    TAKE(frag_t[l], tile_frag_bytes(u.cin[l], u.cout[l]));
+    if (l > 0) TAKE(frag_b[l], (long long)((27 * u.cout[l] + 31) / 32) * (u.cin[l] / 16) * 64 * 16);
+  }
+  TAKE(head_w, 16 * 4);
+  const long long n0 = u.npos[0];
+  TAKE(ell, n0 * 2);
+  TAKE(x0, n0 * 2 * 2);
+  for (int l = 0; l < u.L; ++l) {
+    const long long nl = u.npos[l];
+    const int ch = level_channels(l);
+    TAKE(a[l], nl * ch * 2);
+    TAKE(da[l], nl * ch * 2);
+    if (l + 1 < u.L) {
+      TAKE(p[l], u.npos[l + 1] * ch * 2);
+      TAKE(dp[l], u.npos[l + 1] * ch * 2);
+      TAKE(skip[l], nl * ch * 2);
+    }
+    // decoder outputs: d_l has level l-1's channels, d_0 16
+    const int cd = l >= 1 ? level_channels(l - 1) : 16;
+    TAKE(d[l], nl * cd * 2);
+    TAKE(dd[l], nl * cd * 2);
+  }
+  TAKE(zt, n0 * 4);
+  TAKE(Az, n0 * 4);
+  TAKE(dz, n0 * 4);
+  TAKE(wpart, 27LL * kWgradBlocks * 64 * 64 * 4);
+  TAKE(cpart, (long long)kWgradBlocks * 64 * 4);
+  TAKE(hpart, (long long)kHeadBlocks * 17 * 4);
+  TAKE(h0, n0 * 4);
+  TAKE(u0, n0 * 4);
+  TAKE(zero16, 16 * 4);
+  TAKE(scal, 8 * 8);
+#undef TAKE
+  return hipSuccess;
+}
+}  // namespace
+}  // namespace nfa
+
+extern "C" size_t nfa_unet_workspace_bytes(int nx, int ny, int nz, int levels) {
+  if (unet_check(nx, ny, nz, levels, "nfa_unet_workspace_bytes") != NFA_OK) return 0;
+  UNet u;
+  unet_shape(u, nx, ny, nz, levels);
+  Carver c;
+  c.measure = true;
+  (void)unet_buffers(u, c);
+  return c.used;
+}
+
+extern "C" nfa_status nfa_unet_create(int nx, int ny, int nz, int levels, int seed, void* workspace,
+                                      size_t ws_bytes, nfa_unet* out) {
+  if (!out) return fail(NFA_ERR_INVALID, "nfa_unet_create: out is NULL");
+  *out = nullptr;
+  if (const nfa_status e = unet_check(nx, ny, nz, levels, "nfa_unet_create")) return e;
+  if (workspace) {
+    const size_t need = nfa_unet_workspace_bytes(nx, ny, nz, levels);
+    if (ws_bytes < need)
+      return fail(NFA_ERR_NOMEM, "nfa_unet_create: workspace of " + std::to_string(ws_bytes) +
+                                     " bytes, the network needs " + std::to_string(need));
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+      return fail(NFA_ERR_INVALID, "nfa_unet_create: workspace must be 256-byte aligned");
+  }
   auto* u = new nfa_unet_s();
-  u->nx = nx;
-  u->ny = ny;
-  u->nz = nz;
-  u->L = levels;
-  for (int l = 0; l < levels; ++l) u->npos[l] = (long long)(nx >> l) * (ny >> l) * (nz >> l);
-  layer_shapes(levels, u->cin, u->cout);
-  u->nlayers = (int)u->cin.size();
-  u->nparam = count_params(levels, &u->off_w, &u->off_b);
-  u->frag_t.resize(u->nlayers);
-  u->frag_b.resize(u->nlayers);
+  unet_shape(*u, nx, ny, nz, levels);
   auto bad = [&](hipError_t e) {
     delete u;
     return fail(NFA_ERR_HIP, std::string("nfa_unet_create: ") + hipGetErrorString(e));
   };
-  hipError_t e;
-#define UALLOC(buf, bytes) if ((e = u->buf.alloc(bytes)) != hipSuccess) return bad(e)
-  UALLOC(params, u->nparam * 4);
-  UALLOC(grads, u->nparam * 4);
-  UALLOC(adam_m, u->nparam * 4);
-  UALLOC(adam_v, u->nparam * 4);
-  for (int l = 0; l < u->nlayers - 1; ++l) {
-    UALLOC(frag_t[l], (size_t)tile_frag_bytes(u->cin[l], u->cout[l]));
-    if (l > 0) UALLOC(frag_b[l], (size_t)((27 * u->cout[l] + 31) / 32) * (u->cin[l] / 16) * 64 * 16);
-  }
-  UALLOC(head_w, 16 * 4);
-  const long long n0 = u->npos[0];
-  UALLOC(ell, n0 * 2);
-  UALLOC(x0, n0 * 2 * 2);
-  for (int l = 0; l < levels; ++l) {
-    const long long nl = u->npos[l];
-    const int c = level_channels(l);
-    UALLOC(a[l], nl * c * 2);
-    UALLOC(da[l], nl * c * 2);
-    if (l + 1 < levels) {
-      UALLOC(p[l], u->npos[l + 1] * c * 2);
-      UALLOC(dp[l], u->npos[l + 1] * c * 2);
-      UALLOC(skip[l], nl * c * 2);
-    }
-    if (l >= 1) {
-      UALLOC(d[l], nl * level_channels(l - 1) * 2);
-      UALLOC(dd[l], nl * level_channels(l - 1) * 2);
-    }
-  }
-  UALLOC(zt, n0 * 4);
-  UALLOC(Az, n0 * 4);
-  UALLOC(dz, n0 * 4);
-  UALLOC(wpart, 27LL * kWgradBlocks * 64 * 64 * 4);
-  UALLOC(cpart, (size_t)kWgradBlocks * 64 * 4);
-  UALLOC(hpart, (size_t)kHeadBlocks * 17 * 4);
-  UALLOC(h0, n0 * 4);
-  UALLOC(g1, u->npos[1] * 4);
-  UALLOC(scal, 8 * 8);
-#undef UALLOC
+  Carver c;
+  c.base = static_cast<unsigned char*>(workspace);
+  c.cap = ws_bytes;
+  hipError_t e = unet_buffers(*u, c);
+  if (e != hipSuccess) return bad(e);
   // He-normal initial weights, zero biases, head zero (the Jacobi step)
   std::vector<float> h(u->nparam, 0.0f);
   std::mt19937_64 rng((unsigned long long)seed);
@@ -1316,11 +1359,32 @@ extern "C" nfa_status nfa_unet_create(int nx, int ny, int nz, int levels, int se
     delete u;
     return st;
   }
+  if ((e = hipMemset(u->zero16.p, 0, 16 * 4)) != hipSuccess) return bad(e);
   if ((e = hipMemset(u->adam_m.p, 0, u->nparam * 4)) != hipSuccess) return bad(e);
   if ((e = hipMemset(u->adam_v.p, 0, u->nparam * 4)) != hipSuccess) return bad(e);
   if ((e = hipMemset(u->grads.p, 0, u->nparam * 4)) != hipSuccess) return bad(e);
   if ((e = hipDeviceSynchronize()) != hipSuccess) return bad(e);
   *out = u;
+  return NFA_OK;
+}
+
+extern "C" nfa_status nfa_unet_bind(nfa_unet u, float* params, float* grads, float* adam_m, float* adam_v,
+                                    int copy) {
+  if (!u || !params || !grads || !adam_m || !adam_v) return fail(NFA_ERR_INVALID, "nfa_unet_bind: NULL argument");
+  float* dst[4] = {params, grads, adam_m, adam_v};
+  DevBuf* src[4] = {&u->params, &u->grads, &u->adam_m, &u->adam_v};
+  for (int i = 0; i < 4; ++i)
+    for (int k = i + 1; k < 4; ++k)
+      if (dst[i] == dst[k]) return fail(NFA_ERR_INVALID, "nfa_unet_bind: the four arrays must differ");
+  const size_t bytes = (size_t)u->nparam * 4;
+  NFA_HIP(hipDeviceSynchronize());
+  for (int i = 0; i < 4; ++i) {
+    if (copy && src[i]->p != dst[i]) NFA_HIP(hipMemcpy(dst[i], src[i]->p, bytes, hipMemcpyDeviceToDevice));
+    src[i]->borrow(dst[i], bytes);
+  }
+  const nfa_status st = pack_all(*u, nullptr);
+  if (st != NFA_OK) return st;
+  NFA_HIP(hipDeviceSynchronize());
   return NFA_OK;
 }
 
@@ -1392,7 +1456,7 @@ extern "C" nfa_status nfa_unet_export(nfa_unet u, int what, void* dst, nfa_strea
   if (what == NFA_UNET_X0) b = &u->x0;
   else if (what >= NFA_UNET_A && what < NFA_UNET_A + u->L) b = &u->a[what - NFA_UNET_A];
   else if (what >= NFA_UNET_P && what < NFA_UNET_P + u->L - 1) b = &u->p[what - NFA_UNET_P];
-  else if (what > NFA_UNET_D && what < NFA_UNET_D + u->L) b = &u->d[what - NFA_UNET_D];
+  else if (what >= NFA_UNET_D && what < NFA_UNET_D + u->L) b = &u->d[what - NFA_UNET_D];
   else return fail(NFA_ERR_INVALID, "nfa_unet_export: unknown item");
   NFA_HIP(hipMemcpyAsync(dst, b->p, b->bytes, hipMemcpyDeviceToDevice, S(s)));
   return NFA_OK;

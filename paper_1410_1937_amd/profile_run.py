@@ -7,7 +7,7 @@ sweeps), and finally a plain device-to-device copy of known size whose
 counter readings calibrate the FETCH_SIZE / WRITE_SIZE counters to bytes.
 With --mg N it runs N mixed-precision iterations preconditioned by the
 multigrid V-cycle (hierarchy set-up included).  With --unet L it also runs --unet-reps forward passes of an L-level learned
-preconditioner on the same grid (the committed weights for L = 5).  With
+preconditioner on the same grid (the committed weights for L = 3).  With
 --vof N it runs N split VOF advection steps (alternating sweep order) of the
 FP64 volume fraction through the workload's face velocities.  With --psi L
 it computes the signed distance of an L-times subdivided icosphere (the
@@ -60,7 +60,7 @@ def main(argv=None):
         import os
         import numpy as np
         net = nfa.UNet(g.nx, g.ny, g.nz, levels=args.unet)
-        wpath = os.path.join(os.path.dirname(nfa.__file__), "weights", f"unet_l{args.unet}_hull.npy")
+        wpath = os.path.join(os.path.dirname(nfa.__file__), "weights", f"unet_l{args.unet}_c4.npy")
         if os.path.exists(wpath):
             net.set_params(np.load(wpath))
         r = (b / torch.linalg.vector_norm(b)).float().contiguous()

@@ -55,8 +55,8 @@ def main(argv=None):
     op = nfa.Poisson(g)
     net = None
     if args.precond == "unet":
-        net = nfa.UNet(g.nx, g.ny, g.nz, levels=5)
-        net.set_params(np.load(os.path.join(os.path.dirname(nfa.__file__), "weights", "unet_l5_hull.npy")))
+        net = nfa.UNet(g.nx, g.ny, g.nz, levels=3)
+        net.set_params(np.load(os.path.join(os.path.dirname(nfa.__file__), "weights", "unet_l3_c4.npy")))
     x = torch.zeros(op.shape, dtype=torch.float64, device=dev)
     rows = []
     with pool:

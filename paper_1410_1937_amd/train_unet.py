@@ -1,29 +1,28 @@
-"""Train the learned preconditioner on the GPU with the library's own kernels.
+"""Train the learned preconditioner on the GPU with the library's own kernels,
+and evaluate it on the held-out steps of the advected-surface sequence.
 
-Data.  Problems on 256 x 128 x 96 grids: the 200-step advected free surface
-around the Wigley-like hull (fixtures.C4Sequence; steps 0-159 train,
-160-199 test) and, so that the weights transfer to the breaking-wave
-workload, snapshots of that workload's geometry (sphere, free surface,
-droplets and bubbles; fixtures.c3 at this size, one seed per snapshot).
-For every problem the plain FP64 Jacobi-PCG solver gives x* (relative
-residual 1e-10); residual/error pairs (r_k, e_k = x* - x_k) are taken along
-its iteration after k = 0, 4, 16, 64, 256 steps, plus two smooth synthetic
-errors e with r = A'e.  After the first phase, each round adds the pairs met
-by flexible CG preconditioned with the current network (after 8, 32 and 96
-iterations), so that the network also learns the residuals it leaves
-behind, then training continues on the union.
-
-Training longer than a few epochs lowers the one-step loss but costs the
-network its use inside flexible CG (it stalls after a few iterations on
-held-out steps), so the committed weights come from a short run:
-
-    python -m paper_1410_1937_amd.train_unet --max-steps 13000 --rounds 1 --breaking 0 --stride 4 --levels 5
+Data (the 3.1M-cell advected-surface sequence, 256 x 128 x 96 around the
+Wigley-like hull, fixtures.C4Sequence): for every training step n in
+0..159 (every --stride-th) the plain FP64 Jacobi-PCG solver gives x* to
+relative residual 1e-10; the residual/error pairs (r_k, e_k = x* - x_k) are
+taken along its iteration after k = 0, 4, 16, 64, 256 steps, plus four smooth
+synthetic errors e with r = A'e.  Optionally (--breaking) snapshots of the
+breaking-wave geometry at the same size, and (--rounds > 1) pairs met by
+flexible CG with the current network, are added.
 
 Each training step runs nfa_unet_train_step: forward, the A-norm step loss
-1 - (z.r)^2/((z.A'z)(e.A'e)), backward and one Adam step.  The weights are
-written as a raw float32 .npy (no pickling) with a JSON record of the run.
+1 - (z.r)^2/((z.A'z)(e.A'e)), backward and one Adam step, with a cosine
+learning-rate decay over the step budget.  The weights are written as a raw
+float32 .npy (no pickling) with a JSON record of the run and of the held-out
+evaluation: on every step 160..199, iterations and milliseconds to the FP64
+relative residual 1e-8 for FP64 Jacobi-PCG, mixed Jacobi-PCG, mixed FCG with
+the trained network and with the untrained one (the Jacobi step), the
+stagnation monitor on; the relative residual after 100 FCG iterations with
+the monitor off; and the one-step A-norm loss on the held-out step's own
+pairs (k = 0, 16, 64, 256), trained against untrained.
 
-    python -m paper_1410_1937_amd.train_unet --minutes 6 --levels 5 --out paper_1410_1937_amd/weights/unet
+    python -m paper_1410_1937_amd.train_unet --levels 3 --max-steps 3000 \
+        --out paper_1410_1937_amd/weights/unet_l3_c4
 """
 from __future__ import annotations
 
@@ -42,6 +41,8 @@ from paper_1410_1937_amd import nfa
 
 KS = (0, 4, 16, 64, 256)
 ONPOLICY_KS = (8, 32, 96)
+SYNTH = 4
+EVAL_KS = (0, 16, 64, 256)
 
 
 def log(*a):
@@ -73,7 +74,7 @@ def operator_for(xf, yf, zf, bc, psi, theta):
     return g, nfa.Poisson(g)
 
 
-def build_problem(name, op, phi, uvw, smooth_src=None, synth=2, seed=0):
+def build_problem(name, op, phi, uvw, smooth_src=None, synth=SYNTH, seed=0):
     phi_t = torch.as_tensor(phi, device="cuda").float().contiguous()
     op.assemble(phi_t)
     b = op.rhs(*(torch.as_tensor(a, device="cuda") for a in uvw))
@@ -141,24 +142,81 @@ def train(problems, net, minutes, lr0, step0, rng, max_steps=0):
     return step, hist
 
 
-def evaluate(problems, net, tol=1e-8):
+SOLVERS = (("fp64_jacobi", dict(precision="f64")),
+           ("mixed_jacobi", dict(precision="mixed")),
+           ("mixed_unet", dict(precision="mixed", precond="unet")),
+           ("mixed_unet_untrained", dict(precision="mixed", precond="unet")))
+
+
+def evaluate(seq, op, net, untrained, steps, tol=1e-8):
+    """Every held-out step: each solver to the FP64 tolerance (second of two
+    runs timed), and the relative residual after 100 FCG iterations with the
+    monitor off for the trained and the untrained network."""
     rows = []
-    for p in problems:
-        p.activate()
-        row = {"problem": p.name}
-        for name, kw in (("fp64_jacobi", dict(precision="f64")),
-                         ("mixed_jacobi", dict(precision="mixed")),
-                         ("mixed_unet", dict(precision="mixed", precond="unet", unet=net)),
-                         ("mixed_unet_no_monitor", dict(precision="mixed", precond="unet", unet=net,
-                                                        fallback_ratio=2.0, max_iters=3000))):
-            p.op.solve(p.b, tol=tol, **kw)
-            _, r = p.op.solve(p.b, tol=tol, **kw)
-            row[name] = {"iterations": r.iterations, "ms": r.ms, "relres": r.relres, "fallback": r.fallback}
+    for n in steps:
+        phi, uvw = seq.step(n)
+        op.assemble(torch.as_tensor(phi, device="cuda").float().contiguous())
+        b = op.rhs(*(torch.as_tensor(a, device="cuda") for a in uvw))
+        row = {"step": n}
+        for name, kw in SOLVERS:
+            kw = dict(kw)
+            if name == "mixed_unet":
+                kw["unet"] = net
+            elif name == "mixed_unet_untrained":
+                kw["unet"] = untrained
+            op.solve(b, tol=tol, **kw)
+            _, r = op.solve(b, tol=tol, **kw)
+            row[name] = {"iterations": r.iterations, "ms": r.ms, "relres": r.relres, "fallback": r.fallback,
+                         "status": r.status}
+        for name, nn in (("trained", net), ("untrained", untrained)):
+            _, r = op.solve(b, tol=1e-30, precision="mixed", precond="unet", unet=nn, fallback_ratio=2.0,
+                            max_iters=100, history=256)
+            row[f"relres_after_100_{name}"] = float(r.history[-1])
+        # one-step A-norm loss on this held-out step's pairs (r_k, e_k) of the
+        # plain solver: the share of the error one step along z leaves
+        xs, _ = op.solve(b, tol=1e-10, precision="f64")
+        x = torch.zeros_like(b)
+        done = 0
+        losses = {"trained": [], "untrained": []}
+        for k in EVAL_KS:
+            if k > done:
+                x, _ = op.solve(b, x=x, tol=1e-30, precision="f64", max_iters=k - done, warm_start=True)
+                done = k
+            rk, _ = op.residual(b, x)
+            eAe = float(torch.dot((xs - x).ravel(), rk.ravel()))
+            r32 = rk.float().contiguous()
+            for name, nn in (("trained", net), ("untrained", untrained)):
+                losses[name].append(nn.grad(op, r32, eAe))
+        row["step_loss_trained"] = losses["trained"]
+        row["step_loss_untrained"] = losses["untrained"]
         rows.append(row)
-        log(f"[train] eval {p.name}: " + ", ".join(
+        log(f"[eval] step {n}: " + ", ".join(
             f"{k} {v['iterations']} its {v['ms']:.1f} ms{' (fallback)' if v['fallback'] else ''}"
-            for k, v in row.items() if k != "problem"))
+            for k, v in row.items() if isinstance(v, dict))
+            + f"; after 100 its trained {row['relres_after_100_trained']:.2e} "
+              f"untrained {row['relres_after_100_untrained']:.2e}; step loss trained "
+              f"{np.mean(row['step_loss_trained']):.3f} untrained {np.mean(row['step_loss_untrained']):.3f}")
     return rows
+
+
+def summarize(rows):
+    out = {}
+    for name, _ in SOLVERS:
+        its = np.array([r[name]["iterations"] for r in rows], dtype=float)
+        ms = np.array([r[name]["ms"] for r in rows], dtype=float)
+        out[name] = {"iterations_mean": float(its.mean()), "iterations_median": float(np.median(its)),
+                     "ms_mean": float(ms.mean()), "ms_median": float(np.median(ms)),
+                     "fallbacks": int(sum(r[name]["fallback"] for r in rows)),
+                     "max_relres": float(max(r[name]["relres"] for r in rows)),
+                     "all_converged": bool(all(r[name]["status"] == 0 for r in rows))}
+    for tag in ("trained", "untrained"):
+        v = np.array([r[f"relres_after_100_{tag}"] for r in rows])
+        out[f"relres_after_100_{tag}"] = {"geomean": float(np.exp(np.mean(np.log(v)))),
+                                          "median": float(np.median(v))}
+        sl = np.array([r[f"step_loss_{tag}"] for r in rows])
+        out[f"step_loss_{tag}"] = {"mean": float(sl.mean()),
+                                   "mean_per_k": {str(k): float(v) for k, v in zip(EVAL_KS, sl.mean(axis=0))}}
+    return out
 
 
 def main(argv=None):
@@ -166,14 +224,14 @@ def main(argv=None):
     ap.add_argument("--minutes", type=float, default=6.0, help="total training time budget")
     ap.add_argument("--max-steps", type=int, default=0,
                     help="total optimizer steps (replaces the time budget when > 0)")
-    ap.add_argument("--rounds", type=int, default=3, help="training phases (the first without on-policy pairs)")
+    ap.add_argument("--rounds", type=int, default=1, help="training phases (the first without on-policy pairs)")
     ap.add_argument("--hull-steps", type=int, default=160)
-    ap.add_argument("--stride", type=int, default=4, help="use every stride-th hull time step")
-    ap.add_argument("--breaking", type=int, default=8, help="breaking-wave geometry snapshots")
+    ap.add_argument("--stride", type=int, default=1, help="use every stride-th hull time step")
+    ap.add_argument("--breaking", type=int, default=0, help="breaking-wave geometry snapshots")
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--levels", type=int, default=5)
-    ap.add_argument("--eval", type=int, default=2, help="held-out problems of each kind to evaluate")
+    ap.add_argument("--levels", type=int, default=3)
+    ap.add_argument("--eval-steps", default="160-199", help="held-out steps to evaluate (a-b, or empty)")
     ap.add_argument("--init", default=None, help="start from these weights (.npy)")
     ap.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "weights", "unet"))
     args = ap.parse_args(argv)
@@ -186,19 +244,13 @@ def main(argv=None):
     for n in range(0, args.hull_steps, args.stride):
         phi, uvw = seq.step(n)
         problems.append(build_problem(f"hull_{n}", op_hull, phi, uvw, seq.smooth_field, seed=n))
-    wl0 = fx.c3(seed=100, nx=nx, ny=ny, nz=nz)
-    _, op_brk = operator_for(wl0.xf, wl0.yf, wl0.zf, wl0.bc, wl0.psi, wl0.theta)
+    if args.breaking > 0:
+        wl0 = fx.c3(seed=100, nx=nx, ny=ny, nz=nz)
+        _, op_brk = operator_for(wl0.xf, wl0.yf, wl0.zf, wl0.bc, wl0.psi, wl0.theta)
     for q in range(args.breaking):
         wl = fx.c3(seed=100 + q, nx=nx, ny=ny, nz=nz)
         problems.append(build_problem(f"breaking_{100 + q}", op_brk, wl.phi, (wl.u, wl.v, wl.w),
                                       seq.smooth_field, seed=100 + q))
-    held = []
-    for n in range(160, 160 + 4 * args.eval, 4):
-        phi, uvw = seq.step(n)
-        held.append(build_problem(f"hull_{n}", op_hull, phi, uvw))
-    for q in range(args.eval):
-        wl = fx.c3(seed=200 + q, nx=nx, ny=ny, nz=nz)
-        held.append(build_problem(f"breaking_{200 + q}", op_brk, wl.phi, (wl.u, wl.v, wl.w)))
     t_data = time.time() - t0
     net = nfa.UNet(nx, ny, nz, seed=args.seed, levels=args.levels)
     if args.init:
@@ -215,19 +267,26 @@ def main(argv=None):
                         args.max_steps // max(1, args.rounds))
         hist += h
     t_train = time.time() - t1
+    n_pairs = sum(len(p.samples) for p in problems)
     params = net.get_params()
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     np.save(args.out + ".npy", params)
-    evals = evaluate(held, net) if args.eval > 0 else []
+    steps = []
+    if args.eval_steps:
+        a_, b_ = (int(v) for v in args.eval_steps.split("-"))
+        steps = list(range(a_, b_ + 1))
     untrained = nfa.UNet(nx, ny, nz, seed=args.seed, levels=args.levels)
-    ev_un = evaluate(held[:1], untrained) if args.eval > 0 else []
-    rec = {"levels": args.levels, "grid": [nx, ny, nz], "problems": [p.name for p in problems],
-           "held_out": [p.name for p in held], "pairs": sum(len(p.samples) for p in problems),
+    del problems
+    torch.cuda.empty_cache()
+    t2 = time.time()
+    evals = evaluate(seq, op_hull, net, untrained, steps) if steps else []
+    rec = {"levels": args.levels, "grid": [nx, ny, nz], "train_steps": list(range(0, args.hull_steps, args.stride)),
+           "pairs_per_step": len(KS) + SYNTH, "pairs": n_pairs,
            "optimizer_steps": step, "rounds": args.rounds, "lr": args.lr, "minutes_budget": args.minutes,
            "max_steps": args.max_steps, "stride": args.stride, "hull_steps": args.hull_steps,
-           "breaking": args.breaking,
-           "data_seconds": t_data, "train_seconds": t_train, "epoch_loss": hist, "eval": evals,
-           "eval_untrained": ev_un, "param_count": int(params.size)}
+           "breaking": args.breaking, "data_seconds": t_data, "train_seconds": t_train,
+           "eval_seconds": time.time() - t2, "epoch_loss": hist, "param_count": int(params.size),
+           "eval_summary": summarize(evals) if evals else {}, "eval": evals}
     with open(args.out + ".json", "w") as f:
         json.dump(rec, f, indent=1)
     log(f"[train] wrote {args.out}.npy and .json")

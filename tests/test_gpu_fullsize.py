@@ -64,8 +64,8 @@ def test_heaving_sphere_sequence_warm_started():
     print("[c5] building oracle geometry", flush=True)
     og, ob, oop, ob_rhs = oracle_for(wl)
     gg, gop = gpu_for(wl, phi_dtype=torch.float32)
-    net = nfa.UNet(*gop.shape[::-1], levels=5)
-    wpath = os.path.join(os.path.dirname(nfa.__file__), "weights", "unet_l5_hull.npy")
+    net = nfa.UNet(*gop.shape[::-1], levels=3)
+    wpath = os.path.join(os.path.dirname(nfa.__file__), "weights", "unet_l3_c4.npy")
     net.set_params(np.load(wpath))
     x = torch.zeros(gop.shape, dtype=torch.float64, device="cuda")
     for n in range(3):

@@ -65,9 +65,11 @@ def test_forward_layers_within_one_bf16_step(setup):
     _ulp_ok(b2, ou.bf16(ou.relu(ou.conv3d(a2, *P[3]))))
     d1 = _bf(net.export("d1"))
     _ulp_ok(d1, ou.bf16(ou.relu(ou.conv3d(ou.bf16(ou.up(b2) + a1), *P[4]))))
-    # the 1x1x1 head on up(d1) + a0, summed without rounding
-    w5, b5 = P[5]
-    y = x0[..., 0] + ((b5[0] + a0 @ w5[0][:, 0]) + ou.up(d1 @ w5[0][:, 0]))
+    d0 = _bf(net.export("d0"))
+    _ulp_ok(d0, ou.bf16(ou.relu(ou.conv3d(ou.bf16(ou.up(d1) + a0), *P[5]))))
+    # the 1x1x1 head on d0
+    w6, b6 = P[6]
+    y = x0[..., 0] + (b6[0] + d0 @ w6[0][:, 0])
     zref = oop.dinv * y
     assert np.max(np.abs(z - zref)) <= 1e-5 * np.max(np.abs(zref))
 
@@ -164,14 +166,14 @@ def test_flexible_cg_with_the_network_meets_the_fp64_tolerance():
 
 
 def test_trained_network_gains_over_the_untrained_one_on_a_held_out_step():
-    """What the trained weights gain: on held-out step 160 of the advected-
-    surface sequence (256x128x96), the relative residual after 100 flexible-CG
-    iterations with the trained network against the untrained one (which is the
-    Jacobi step), stagnation monitor off; then the full solve with the monitor
-    on meets the FP64 tolerance (the trained network does not carry the solve to
-    1e-8 by itself: the monitor hands it to Jacobi-PCG).  The gain belongs to
-    these weights: rerunning their training recipe does not reliably give a
-    network that keeps it inside flexible CG."""
+    """What the committed weights (3 levels, trained on steps 0-159 of the
+    advected-surface sequence) gain on held-out step 160 of that sequence
+    (256x128x96): the share of the A-norm error one step along z leaves, for
+    residual/error pairs of the plain solver after k = 0, 16 and 64 iterations,
+    trained against untrained (the Jacobi step), and the full mixed FCG solve
+    with the stagnation monitor meeting the FP64 tolerance (the network does
+    not carry the solve to 1e-8 by itself: the monitor hands it to Jacobi-PCG,
+    see the evaluation record beside the weights)."""
     import os
     from paper_1410_1937_amd import nfa
     wl = fx.c4_step(160)
@@ -179,18 +181,25 @@ def test_trained_network_gains_over_the_untrained_one_on_a_held_out_step():
     og, ob, oop, ob_rhs = oracle_for(wl)
     gg, gop = gpu_for(wl, phi_dtype=torch.float32)
     b = torch.as_tensor(ob_rhs, device="cuda")
-    wpath = os.path.join(os.path.dirname(nfa.__file__), "weights", "unet_l5_hull.npy")
-    after = {}
-    for tag in ("untrained", "trained"):
-        net = nfa.UNet(256, 128, 96, levels=5)
-        if tag == "trained":
-            net.set_params(np.load(wpath))
-        _, res = gop.solve(b, tol=1e-30, precision="mixed", precond="unet", unet=net, fallback_ratio=2.0,
-                           max_iters=100, history=256)
-        after[tag] = float(res.history[-1])
-        print(f"[learned] {tag}: relres after {len(res.history) - 1} FCG iterations {after[tag]:.3e}", flush=True)
-    assert after["trained"] <= 0.2 * after["untrained"], after
-    x, res = gop.solve(b, tol=1e-8, precision="mixed", precond="unet", unet=net)
+    wpath = os.path.join(os.path.dirname(nfa.__file__), "weights", "unet_l3_c4.npy")
+    trained = nfa.UNet(256, 128, 96, levels=3)
+    trained.set_params(np.load(wpath))
+    untrained = nfa.UNet(256, 128, 96, levels=3)
+    xs, _ = gop.solve(b, tol=1e-10, precision="f64")
+    x = torch.zeros_like(b)
+    done = 0
+    loss = {"trained": [], "untrained": []}
+    for k in (0, 16, 64):
+        if k > done:
+            x, _ = gop.solve(b, x=x, tol=1e-30, precision="f64", max_iters=k - done, warm_start=True)
+            done = k
+        r, _ = gop.residual(b, x)
+        eAe = float(torch.dot((xs - x).ravel(), r.ravel()))
+        for tag, net in (("trained", trained), ("untrained", untrained)):
+            loss[tag].append(net.grad(gop, r.float().contiguous(), eAe))
+    print(f"[learned] step loss trained {loss['trained']} untrained {loss['untrained']}", flush=True)
+    assert all(t <= 0.75 * u for t, u in zip(loss["trained"], loss["untrained"])), loss
+    x, res = gop.solve(b, tol=1e-8, precision="mixed", precond="unet", unet=trained)
     print(f"[learned] full solve: {res.iterations} its, fallback {res.fallback}, relres {res.relres:.3e}", flush=True)
     assert res.status == 0 and res.relres <= 1e-8
     assert solvers.true_relres(oop, ob_rhs, host(x)) <= 1.01e-8

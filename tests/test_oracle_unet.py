@@ -51,9 +51,10 @@ def test_layer_adjoints():
 
 
 def test_layer_shapes_for_three_and_five_levels():
-    assert unet.shapes(3) == [(2, 16), (16, 32), (32, 64), (64, 32), (32, 16), (16, 1)]
+    assert unet.shapes(3) == [(2, 16), (16, 32), (32, 64), (64, 32), (32, 16), (16, 16), (16, 1)]
     assert unet.shapes(5) == [(2, 16), (16, 32), (32, 64), (64, 64), (64, 64), (64, 64), (64, 64),
-                              (64, 32), (32, 16), (16, 1)]
+                              (64, 32), (32, 16), (16, 16), (16, 1)]
+    assert unet.taps(3) == [27] * 6 + [1]
 
 
 def test_untrained_network_is_the_jacobi_step():
@@ -140,9 +141,10 @@ def test_adam_first_step_is_signed_learning_rate():
 
 
 def test_head_is_the_centre_tap_of_a_three_by_three_convolution():
-    """C4's 1x1x1 head, evaluated as head(a0) + up(head(d1)) with the bias
-    once, equals a 3x3x3 convolution (pinned against scipy above) whose only
-    non-zero tap is the centre one, applied to up(d1) + a0."""
+    """C4's 1x1x1 head on the finest decoder output d0 = relu(conv(up(d1) +
+    a0)) equals a 3x3x3 convolution (pinned against scipy above) whose only
+    non-zero tap is the centre one; d0 itself is that convolution of the
+    skip sum."""
     rng = np.random.default_rng(7)
     params = unet.init_params(2, zero_last=False, levels=3)
     params = [(w, rng.standard_normal(b.shape) * 0.1) for w, b in params]
@@ -153,5 +155,7 @@ def test_head_is_the_centre_tap_of_a_three_by_three_convolution():
     w27 = np.zeros((27, 16, 1))
     w27[13] = w5[0]
     s0 = unet.up(cache["d"][1]) + cache["a"][0]
-    ref = x0[..., 0] + unet.conv3d(s0, w27, b5)[..., 0]
+    d0 = unet.relu(unet.conv3d(s0, *params[-2]))
+    assert np.max(np.abs(d0 - cache["d"][0])) <= 1e-12 * np.max(np.abs(d0))
+    ref = x0[..., 0] + unet.conv3d(d0, w27, b5)[..., 0]
     assert np.max(np.abs(y - ref)) <= 1e-12 * np.max(np.abs(ref))
