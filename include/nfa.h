@@ -27,8 +27,12 @@
  *    current HIP device; HOST pointers are ordinary host memory.
  *  - Ownership: the caller owns every buffer it passes and keeps it alive
  *    until the call returns (or, for asynchronous calls, until the stream
- *    has passed it).  Handles own their device memory, allocated when the
- *    handle is created or its body set, never by apply/assemble/solve.
+ *    has passed it).  The operator's and the network's device memory is a
+ *    caller-owned workspace (nfa_poisson_workspace_bytes,
+ *    nfa_unet_workspace_bytes; the network's parameter state in caller arrays
+ *    through nfa_unet_bind).  Grids and multigrid handles allocate their own
+ *    when they are created or a body is set.  Nothing allocates device memory
+ *    on the assemble / apply / rhs / solve path.
  *  - Streams: `nfa_stream` is a hipStream_t (NULL = default stream); work is
  *    ordered on it.  Calls marked ASYNC return before the device finishes.
  *  - Errors: a negative status means nothing was launched (argument errors)
@@ -197,10 +201,25 @@ typedef struct {
   int phi_dtype;     /* NFA_F64 or NFA_F32 */
 } nfa_assemble_params;
 
-/* nfa_poisson_create -- operator + solver workspace on grid g (the grid
- * must outlive it; set the body first).  Allocates all device memory the
- * operator, the FP64 and FP32 solvers need.  Errors: NFA_ERR_HIP. */
-nfa_status nfa_poisson_create(nfa_grid g, nfa_poisson* out);
+/* nfa_poisson_workspace_bytes -- bytes of device workspace an operator on
+ * grid g needs: its coefficients in FP64 and FP32 (3 face arrays and the
+ * Jacobi inverse diagonal), the density, the work vectors of the FP64 and
+ * FP32 solvers, reduction partials and the residual history (about 200 bytes
+ * per cell).  0 for a NULL grid. */
+size_t nfa_poisson_workspace_bytes(nfa_grid g);
+
+/* nfa_poisson_create -- operator + solver state on grid g (the grid must
+ * outlive it; set the body first).
+ *   workspace : DEVICE, 256-byte aligned, ws_bytes >= nfa_poisson_workspace_bytes(g),
+ *               owned by the caller (a torch tensor, say) and kept alive and
+ *               untouched while the operator exists; every device buffer of the
+ *               operator and its solvers is a slice of it, so assemble, apply,
+ *               rhs, project and solve never allocate device memory.  NULL:
+ *               the library allocates the same buffers itself, here.
+ * The handle itself, two pinned host scalars and two HIP events are the
+ * library's.  Errors: NFA_ERR_NOMEM (workspace shorter than needed; nothing is
+ * created), NFA_ERR_INVALID (misaligned workspace, grid too wide), NFA_ERR_HIP. */
+nfa_status nfa_poisson_create(nfa_grid g, void* workspace, size_t ws_bytes, nfa_poisson* out);
 
 /* nfa_poisson_assemble -- coefficients for one projection (eq. density,
  * Density Smoothing, eq. integral2): rho = rho_g + (rho_l - rho_g)
@@ -306,21 +325,21 @@ void nfa_solve_opts_default(nfa_solve_opts* opts);
 typedef struct nfa_mg_s* nfa_mg;
 /* nfa_mg_create -- allocates the hierarchy of op's grid (op must outlive it):
  * per coarse cell 27 FP64 stencil entries, a float4 and two FP32 vectors
- * (about 2.5 GB per 10^7 cells of level 1), plus side lists sized for the
- * grid's current merge set.  Errors: NFA_ERR_INVALID (a single-cell grid),
- * NFA_ERR_HIP. */
+ * (about 2.5 GB per 10^7 cells of level 1), side lists sized for the grid's
+ * current merge set (at most 12 rows per merged cell, a bound its rows never
+ * exceed), and the merged rows' correction-term lists of the grid's current
+ * body (16 bytes a term, a few per merged cell; the roots they need are
+ * gathered on the device).  Set the body first; a handle serves that body
+ * only.  Errors: NFA_ERR_INVALID (a single-cell grid), NFA_ERR_HIP. */
 nfa_status nfa_mg_create(nfa_poisson op, nfa_mg* out);
 void nfa_mg_destroy(nfa_mg mg);
 /* nfa_mg_setup -- builds every level from op's current FP64 coefficients
  * (call after each nfa_poisson_assemble; nfa_poisson_solve with NFA_PC_MG
  * calls it when the operator has changed).  Synchronous (the side lists
- * are scanned and the coarsest inverse formed on the host).  Allocates only
- * when a side list outgrows what creation reserved (merge set grown since)
- * and, on the first set-up after the grid's body was set, for the merged
- * rows' correction terms (16 bytes a term, a few per merged cell; the roots
- * they need are gathered on the device and read back).
- * Errors: NFA_ERR_INVALID (not assembled), NFA_ERR_NUMERIC (coarsest matrix
- * not positive definite), NFA_ERR_HIP. */
+ * are scanned and the coarsest inverse formed on the host).  Allocates no
+ * device memory.  Errors: NFA_ERR_INVALID (not assembled, or the grid's body
+ * set after the handle was created), NFA_ERR_NUMERIC (coarsest matrix not
+ * positive definite), NFA_ERR_HIP. */
 nfa_status nfa_mg_setup(nfa_mg mg, nfa_stream s);
 /* nfa_mg_set_tail -- the single-workgroup part of the cycle starts at the
  * first level with at most max_cells cells whose two vectors and float4
@@ -342,9 +361,9 @@ nfa_status nfa_mg_set_params(nfa_mg mg, double omega, double alpha);
 /* nfa_mg_set_coef -- the precision in which the cycle's level-0 sweeps read
  * the face coefficients and D^-1: NFA_F32 (the operator's FP32 copies) or
  * NFA_BF16 (those rounded to BF16, nearest even; made at set-up, half the
- * bytes; the first such set-up allocates 8 bytes per cell for them).  The
- * operator of the CG itself is unaffected.  Takes effect at the next
- * set-up.  Errors: NFA_ERR_INVALID. */
+ * bytes; the first call asking for them allocates their 8 bytes per cell).
+ * The operator of the CG itself is unaffected.  Takes effect at the next
+ * set-up.  Errors: NFA_ERR_INVALID, NFA_ERR_HIP. */
 nfa_status nfa_mg_set_coef(nfa_mg mg, int dtype);
 /* nfa_mg_side_rows -- rows of level >= 1 (below the coarsest) held in the
  * side list by the last set-up (couplings beyond the 7 points). */
@@ -370,20 +389,24 @@ nfa_status nfa_poisson_solve(nfa_poisson op, const double* b, double* x, const n
 /* Timing of the operator sweeps inside solves.  nfa_poisson_profile(op, 1)
  * brackets the first 4096 timed launches of each later solve (sweep A of
  * every iteration; with NFA_PC_MG also the fused level-0 down and up sweeps
- * of each V-cycle) with HIP events on the solve's stream (creating the
+ * of each V-cycle; with NFA_PC_UNET each network application) with HIP events on the solve's stream (creating the
  * events here, not in the solve) and resets the counters;
  * nfa_poisson_profile(op, 0) stops.  Only launches of iterations that ran
  * are counted. */
 #define NFA_PROF_MG_DOWN 2
 #define NFA_PROF_MG_UP 3
+#define NFA_PROF_F32_FLEX 4 /* sweep A of the flexible (FCG) FP32 iteration */
+#define NFA_PROF_UNET 5     /* one application of the learned preconditioner */
 typedef struct {
   long long launches; /* stencil launches timed */
   double ms;          /* their summed duration */
   long long cells;    /* cells swept per launch */
 } nfa_kernel_stats;
 nfa_status nfa_poisson_profile(nfa_poisson op, int enable);
-/* dtype NFA_F64 or NFA_F32: sweep A of that precision; NFA_PROF_MG_DOWN /
- * NFA_PROF_MG_UP: the V-cycle's fused level-0 sweeps (FP32).  Synchronous. */
+/* dtype NFA_F64 or NFA_F32: sweep A of that precision (NFA_F32: the PCG
+ * form); NFA_PROF_F32_FLEX: the flexible FP32 sweep A; NFA_PROF_MG_DOWN /
+ * NFA_PROF_MG_UP: the V-cycle's fused level-0 sweeps (FP32); NFA_PROF_UNET:
+ * whole applications of the learned preconditioner.  Synchronous. */
 nfa_status nfa_poisson_profile_read(nfa_poisson op, int dtype, nfa_kernel_stats* out);
 
 /* nfa_poisson_residual -- r = b' - A'x in FP64 (the true residual that

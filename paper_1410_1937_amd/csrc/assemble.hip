@@ -11,7 +11,10 @@
 // bitwise the expression written.
 #include <cmath>
 
+#include <string>
+
 #include "device_util.h"
+
 #include "nfa_internal.h"
 #include "vecops.h"
 
@@ -259,50 +262,70 @@ __global__ void k_copy(long long n, const T* a, T* b) {
 
 using namespace nfa;
 
-extern "C" nfa_status nfa_poisson_create(nfa_grid g, nfa_poisson* out) {
+namespace nfa {
+namespace {
+// Every device buffer of an operator: coefficients in both precisions and the
+// work vectors of the FP64 and FP32 solvers, in one fixed order.
+hipError_t poisson_buffers(Poisson& op, const Grid& g, Carver& c) {
+  const long long n = g.n;
+  const long long nzy = (long long)g.nz * g.ny;
+  hipError_t e = hipSuccess;
+  DevBuf* f64[] = {&op.rho, &op.rho_tmp, &op.tx64, &op.dinv64, &op.r, &op.z, &op.p, &op.p2, &op.q, &op.tmp};
+  for (DevBuf* b : f64)
+    if ((e = c.take(*b, n * 8)) != hipSuccess) return e;
+  if ((e = c.take(op.txb64, nzy * 8)) != hipSuccess || (e = c.take(op.ty64, g.nfy() * 8)) != hipSuccess ||
+      (e = c.take(op.tz64, g.nfz() * 8)) != hipSuccess)
+    return e;
+  DevBuf* f32[] = {&op.tx32, &op.dinv32, &op.x32, &op.r32, &op.z32, &op.p32, &op.p32b, &op.q32};
+  for (DevBuf* b : f32)
+    if ((e = c.take(*b, n * 4)) != hipSuccess) return e;
+  if ((e = c.take(op.txb32, nzy * 4)) != hipSuccess || (e = c.take(op.ty32, g.nfy() * 4)) != hipSuccess ||
+      (e = c.take(op.tz32, g.nfz() * 4)) != hipSuccess)
+    return e;
+  if ((e = c.take(op.partials, (size_t)kMaxPartials * 4 * 8)) != hipSuccess ||
+      (e = c.take(op.scal, 4 * sizeof(SolveScalars))) != hipSuccess ||
+      (e = c.take(op.hist, (size_t)(kHistCap + 2) * 8)) != hipSuccess)
+    return e;
+  return hipSuccess;
+}
+}  // namespace
+}  // namespace nfa
+
+extern "C" size_t nfa_poisson_workspace_bytes(nfa_grid g) {
+  if (!g) return 0;
+  Poisson tmp;
+  Carver c;
+  c.measure = true;
+  (void)poisson_buffers(tmp, *g, c);
+  return c.used;
+}
+
+extern "C" nfa_status nfa_poisson_create(nfa_grid g, void* workspace, size_t ws_bytes, nfa_poisson* out) {
   if (!g || !out) return fail(NFA_ERR_INVALID, "nfa_poisson_create: NULL argument");
   *out = nullptr;
   // one FP64 partial per 64x4 column tile of the stencil sweep (z chunks are
   // enlarged until the count fits)
   if ((long long)((g->nx + 63) / 64) * ((g->ny + 3) / 4) > kMaxPartials)
     return fail(NFA_ERR_INVALID, "nfa_poisson_create: nx*ny too large for the reduction buffer");
+  if (workspace) {
+    const size_t need = nfa_poisson_workspace_bytes(g);
+    if (ws_bytes < need)
+      return fail(NFA_ERR_NOMEM, "nfa_poisson_create: workspace of " + std::to_string(ws_bytes) +
+                                     " bytes, the operator needs " + std::to_string(need));
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+      return fail(NFA_ERR_INVALID, "nfa_poisson_create: workspace must be 256-byte aligned");
+  }
   auto* op = new nfa_poisson_s();
   op->g = g;
-  const long long n = g->n;
   auto bad = [&](hipError_t e) {
     delete op;
     return fail(NFA_ERR_HIP, std::string("nfa_poisson_create: ") + hipGetErrorString(e));
   };
-  hipError_t e;
-#define ALLOC(buf, bytes) if ((e = op->buf.alloc(bytes)) != hipSuccess) return bad(e)
-  ALLOC(rho, n * 8);
-  ALLOC(rho_tmp, n * 8);
-  ALLOC(tx64, n * 8);
-  ALLOC(txb64, (long long)g->nz * g->ny * 8);
-  ALLOC(ty64, g->nfy() * 8);
-  ALLOC(tz64, g->nfz() * 8);
-  ALLOC(dinv64, n * 8);
-  ALLOC(tx32, n * 4);
-  ALLOC(txb32, (long long)g->nz * g->ny * 4);
-  ALLOC(ty32, g->nfy() * 4);
-  ALLOC(tz32, g->nfz() * 4);
-  ALLOC(dinv32, n * 4);
-  ALLOC(r, n * 8);
-  ALLOC(z, n * 8);
-  ALLOC(p, n * 8);
-  ALLOC(p2, n * 8);
-  ALLOC(q, n * 8);
-  ALLOC(tmp, n * 8);
-  ALLOC(x32, n * 4);
-  ALLOC(r32, n * 4);
-  ALLOC(z32, n * 4);
-  ALLOC(p32, n * 4);
-  ALLOC(p32b, n * 4);
-  ALLOC(q32, n * 4);
-  ALLOC(partials, (size_t)kMaxPartials * 4 * 8);
-  ALLOC(scal, 4 * sizeof(SolveScalars));
-  ALLOC(hist, (size_t)(kHistCap + 2) * 8);
-#undef ALLOC
+  Carver c;
+  c.base = static_cast<unsigned char*>(workspace);
+  c.cap = ws_bytes;
+  hipError_t e = poisson_buffers(*op, *g, c);
+  if (e != hipSuccess) return bad(e);
   if ((e = hipHostMalloc((void**)&op->h_scal, 2 * sizeof(SolveScalars), hipHostMallocDefault)) != hipSuccess)
     return bad(e);
   for (int i = 0; i < 2; ++i)

@@ -1249,13 +1249,12 @@ nfa_status build_side_list(nfa_mg_s& mg, Level& C, hipStream_t st) {
   C.m = (int)m;
   if (m == 0) return NFA_OK;
   if (m > C.xcap) {
-    const long long cap = std::min<long long>(C.d.n, m + m / 2 + 256);
-    if (C.xcell.alloc(cap * sizeof(int)) != hipSuccess || C.xval.alloc(cap * kXSlots * sizeof(float)) != hipSuccess) {
-      C.xcap = 0;
-      C.m = 0;
-      return fail(NFA_ERR_HIP, "multigrid: out of device memory for the side list");
-    }
-    C.xcap = cap;
+    // creation reserves min(n, 12 slaves + 256) rows; the rows a merge set
+    // couples beyond 7 points are at most 8 per slave on level 1 (the root's
+    // block and the blocks of the slave's neighbours and its own) and, on a
+    // coarser level, the blocks that hold such rows of the level below
+    C.m = 0;
+    return fail(NFA_ERR_NOMEM, "multigrid: side list longer than its reserved bound");
   }
   NFA_HIP(hipMemcpyAsync(cnt + nb, h.data(), nb * sizeof(int), hipMemcpyHostToDevice, st));
   k_xscatter<<<(int)nb, kBlock, 0, st>>>(C.d.n, C.S.as<float4>(), C.A64.as<double>(), cnt + nb, C.xcell.as<int>(),
@@ -1266,6 +1265,137 @@ nfa_status build_side_list(nfa_mg_s& mg, Level& C, hipStream_t st) {
 }
 
 }  // namespace
+
+// The merge fix-ups' term lists of the grid's current body, built when the
+// handle is created (the roots they need are gathered on the device).
+nfa_status build_fixups(nfa_mg_s& mg, hipStream_t st) {
+  Grid& g = *mg.op->g;
+  // Every term is
+  // s T_f (z(y1) - z(y2)) with a face coefficient, a sign and one or two
+  // unknowns (y2 < 0: none); z is an unknown's value after pre-smoothing
+  // (down) or before post-smoothing (up).
+  const long long plane = (long long)g.nx * g.ny;
+  // face f of cell c: coefficient array and index, whether it lies inside the domain, the neighbour
+  auto face = [&](long long c, int f, int* arr, long long* idx, bool* in, long long* nb) {
+    const int i = (int)(c % g.nx), j = (int)((c / g.nx) % g.ny), k = (int)(c / plane);
+    const long long yi = ((long long)k * (g.ny + 1) + j) * g.nx + i;
+    switch (f) {
+      case 0: *arr = 0; *idx = c; *in = i > 0; *nb = c - 1; break;
+      case 1:
+        if (i < g.nx - 1) { *arr = 0; *idx = c + 1; } else { *arr = 1; *idx = (long long)k * g.ny + j; }
+        *in = i < g.nx - 1; *nb = c + 1; break;
+      case 2: *arr = 2; *idx = yi; *in = j > 0; *nb = c - g.nx; break;
+      case 3: *arr = 2; *idx = yi + g.nx; *in = j < g.ny - 1; *nb = c + g.nx; break;
+      case 4: *arr = 3; *idx = c; *in = k > 0; *nb = c - plane; break;
+      default: *arr = 3; *idx = c + plane; *in = k < g.nz - 1; *nb = c + plane; break;
+    }
+  };
+  // each root's slaves, ascending
+  std::map<int, std::vector<int>> members;
+  for (size_t t = 0; t < g.h_scell.size(); ++t) members[g.h_sroot[t]].push_back(g.h_scell[t]);
+  for (auto& m : members) std::sort(m.second.begin(), m.second.end());
+  auto upload = [&](DevBuf& b, const std::vector<int>& v) -> hipError_t {
+    hipError_t e2 = b.alloc(std::max<size_t>(1, v.size()) * sizeof(int));
+    if (e2 != hipSuccess || v.empty()) return e2;
+    return hipMemcpy(b.p, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice);
+  };
+  // the roots the terms need (of the neighbours of the listed rows and of
+  // the slaves), gathered on the device
+  std::vector<int> need;
+  for (const std::vector<int>* list : {&g.h_fix, &g.h_scell})
+    for (int c : *list)
+      for (int f = 0; f < 6; ++f) {
+        int arr; long long idx, nb; bool in;
+        face(c, f, &arr, &idx, &in, &nb);
+        if (in) need.push_back((int)nb);
+      }
+  std::sort(need.begin(), need.end());
+  need.erase(std::unique(need.begin(), need.end()), need.end());
+  std::vector<int> need_root(need.size());
+  if (!need.empty()) {
+    DevBuf d_need, d_out;
+    NFA_HIP(upload(d_need, need));
+    NFA_HIP(d_out.alloc(need.size() * sizeof(int)));
+    k_gather_int<<<blocks_for((long long)need.size()), kBlock, 0, st>>>((int)need.size(), d_need.as<int>(),
+                                                                        g.root.as<int>(), d_out.as<int>());
+    NFA_CHECK_LAUNCH();
+    NFA_HIP(hipMemcpyAsync(need_root.data(), d_out.p, need.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+    NFA_HIP(hipStreamSynchronize(st));
+  }
+  auto root_of = [&](long long x) {
+    return need_root[std::lower_bound(need.begin(), need.end(), (int)x) - need.begin()];
+  };
+  // terms of a row's faces to slaves: s T_f z(root of the slave)
+  auto slave_faces = [&](int c, int sign, std::vector<FixTerm>& out) {
+    for (int f = 0; f < 6; ++f) {
+      int arr; long long idx, nb; bool in;
+      face(c, f, &arr, &idx, &in, &nb);
+      if (!in) continue;
+      const int rt = root_of(nb);
+      if (rt >= 0 && rt != nb) out.push_back({arr | sign, (int)idx, rt, -1});
+    }
+  };
+  // terms of slave m's row with merged values: s T_f (z(root) - z(root of the neighbour))
+  auto slave_row = [&](int m, int rm, int sign, std::vector<FixTerm>& out) {
+    for (int f = 0; f < 6; ++f) {
+      int arr; long long idx, nb; bool in;
+      face(m, f, &arr, &idx, &in, &nb);
+      const int rt = in ? root_of(nb) : -1;
+      if (rt == rm) continue;   // T (z(r) - z(r)) = 0
+      out.push_back({arr | sign, (int)idx, rm, rt});
+    }
+  };
+  // down: q~ - q per entry, entries grouped by level-1 cell in a fixed
+  // order (the listed rows ascending, then the slaves by their root's cell)
+  const Dims& C = mg.lv[1].d;
+  auto blk0 = [&](long long c) {
+    const long long i = c % g.nx, j = (c / g.nx) % g.ny, k = c / plane;
+    return (int)(((k >> 1) * C.ny + (j >> 1)) * C.nx + (i >> 1));
+  };
+  std::vector<std::pair<int, int>> ent;
+  for (int c : g.h_fix) ent.push_back({blk0(c), c});
+  for (size_t t = 0; t < g.h_scell.size(); ++t) ent.push_back({blk0(g.h_sroot[t]), -(int)t - 1});
+  std::stable_sort(ent.begin(), ent.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+  std::vector<int> fb, fo;
+  std::vector<FixTerm> dt;
+  for (size_t e = 0; e < ent.size(); ++e) {
+    if (e == 0 || ent[e].first != ent[e - 1].first) {
+      fb.push_back(ent[e].first);
+      fo.push_back((int)dt.size());
+    }
+    const int code = ent[e].second;
+    if (code >= 0) slave_faces(code, 0, dt);   // an unknown's faces to slaves
+    else slave_row(g.h_scell[-code - 1], g.h_sroot[-code - 1], 4, dt);   // minus a slave's row
+  }
+  fo.push_back((int)dt.size());
+  // up: dq per listed row, its faces to slaves, then (a root) its slaves' rows
+  std::vector<int> uo(1, 0);
+  std::vector<FixTerm> ut;
+  for (int c : g.h_fix) {
+    slave_faces(c, 4, ut);
+    auto it = members.find(c);
+    if (it != members.end())
+      for (int m : it->second) slave_row(m, c, 0, ut);
+    uo.push_back((int)ut.size());
+  }
+  auto upload_terms = [&](DevBuf& b, const std::vector<FixTerm>& v) -> hipError_t {
+    hipError_t e2 = b.alloc(std::max<size_t>(1, v.size()) * sizeof(FixTerm));
+    if (e2 != hipSuccess || v.empty()) return e2;
+    return hipMemcpy(b.p, v.data(), v.size() * sizeof(FixTerm), hipMemcpyHostToDevice);
+  };
+  NFA_HIP(upload(mg.fblk, fb));
+  NFA_HIP(upload(mg.foff, fo));
+  NFA_HIP(upload_terms(mg.fterm, dt));
+  NFA_HIP(mg.fval.alloc(std::max<size_t>(1, dt.size()) * sizeof(float)));
+  mg.nfblk = (int)fb.size();
+  mg.nfterm = (int)dt.size();
+  NFA_HIP(upload(mg.uoff, uo));
+  NFA_HIP(upload_terms(mg.uterm, ut));
+  NFA_HIP(mg.uval.alloc(std::max<size_t>(1, ut.size()) * sizeof(float)));
+  mg.nuterm = (int)ut.size();
+  mg.body_version = g.body_version;
+  return NFA_OK;
+}
 
 nfa_status mg_setup(nfa_mg_s& mg, hipStream_t st) {
   Poisson& op = *mg.op;
@@ -1292,14 +1422,7 @@ nfa_status mg_setup(nfa_mg_s& mg, hipStream_t st) {
     if (e != NFA_OK) return e;
   }
   if (mg.coef16) {
-    if (!mg.d16.p) {   // the BF16 copies are allocated by the first set-up that needs them
-      if (mg.tx16.alloc(g.n * 2) != hipSuccess || mg.txb16.alloc((size_t)g.nz * g.ny * 2) != hipSuccess ||
-          mg.ty16.alloc(g.nfy() * 2) != hipSuccess || mg.tz16.alloc(g.nfz() * 2) != hipSuccess ||
-          mg.d16.alloc(g.n * 2) != hipSuccess) {
-        mg.d16.release();
-        return fail(NFA_ERR_HIP, "multigrid: out of device memory for the BF16 coefficients");
-      }
-    }
+    if (!mg.d16.p) return fail(NFA_ERR_INVALID, "multigrid: BF16 coefficients not allocated");
     const Coeffs<float> c32 = op.c32();
     const float* src[5] = {c32.tx, c32.txb, c32.ty, c32.tz, c32.dinv};
     DevBuf* dst[5] = {&mg.tx16, &mg.txb16, &mg.ty16, &mg.tz16, &mg.d16};
@@ -1308,132 +1431,8 @@ nfa_status mg_setup(nfa_mg_s& mg, hipStream_t st) {
       k_to_bf16<<<blocks_for(cnt[t]), kBlock, 0, st>>>(cnt[t], src[t], dst[t]->as<unsigned short>());
     NFA_CHECK_LAUNCH();
   }
-  if (mg.body_version != g.body_version) {
-    // The merge fix-ups' terms, listed once per body.  Every term is
-    // s T_f (z(y1) - z(y2)) with a face coefficient, a sign and one or two
-    // unknowns (y2 < 0: none); z is an unknown's value after pre-smoothing
-    // (down) or before post-smoothing (up).
-    const long long plane = (long long)g.nx * g.ny;
-    // face f of cell c: coefficient array and index, whether it lies inside the domain, the neighbour
-    auto face = [&](long long c, int f, int* arr, long long* idx, bool* in, long long* nb) {
-      const int i = (int)(c % g.nx), j = (int)((c / g.nx) % g.ny), k = (int)(c / plane);
-      const long long yi = ((long long)k * (g.ny + 1) + j) * g.nx + i;
-      switch (f) {
-        case 0: *arr = 0; *idx = c; *in = i > 0; *nb = c - 1; break;
-        case 1:
-          if (i < g.nx - 1) { *arr = 0; *idx = c + 1; } else { *arr = 1; *idx = (long long)k * g.ny + j; }
-          *in = i < g.nx - 1; *nb = c + 1; break;
-        case 2: *arr = 2; *idx = yi; *in = j > 0; *nb = c - g.nx; break;
-        case 3: *arr = 2; *idx = yi + g.nx; *in = j < g.ny - 1; *nb = c + g.nx; break;
-        case 4: *arr = 3; *idx = c; *in = k > 0; *nb = c - plane; break;
-        default: *arr = 3; *idx = c + plane; *in = k < g.nz - 1; *nb = c + plane; break;
-      }
-    };
-    // each root's slaves, ascending
-    std::map<int, std::vector<int>> members;
-    for (size_t t = 0; t < g.h_scell.size(); ++t) members[g.h_sroot[t]].push_back(g.h_scell[t]);
-    for (auto& m : members) std::sort(m.second.begin(), m.second.end());
-    auto upload = [&](DevBuf& b, const std::vector<int>& v) -> hipError_t {
-      hipError_t e2 = b.alloc(std::max<size_t>(1, v.size()) * sizeof(int));
-      if (e2 != hipSuccess || v.empty()) return e2;
-      return hipMemcpy(b.p, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice);
-    };
-    // the roots the terms need (of the neighbours of the listed rows and of
-    // the slaves), gathered on the device
-    std::vector<int> need;
-    for (const std::vector<int>* list : {&g.h_fix, &g.h_scell})
-      for (int c : *list)
-        for (int f = 0; f < 6; ++f) {
-          int arr; long long idx, nb; bool in;
-          face(c, f, &arr, &idx, &in, &nb);
-          if (in) need.push_back((int)nb);
-        }
-    std::sort(need.begin(), need.end());
-    need.erase(std::unique(need.begin(), need.end()), need.end());
-    std::vector<int> need_root(need.size());
-    if (!need.empty()) {
-      DevBuf d_need, d_out;
-      NFA_HIP(upload(d_need, need));
-      NFA_HIP(d_out.alloc(need.size() * sizeof(int)));
-      k_gather_int<<<blocks_for((long long)need.size()), kBlock, 0, st>>>((int)need.size(), d_need.as<int>(),
-                                                                          g.root.as<int>(), d_out.as<int>());
-      NFA_CHECK_LAUNCH();
-      NFA_HIP(hipMemcpyAsync(need_root.data(), d_out.p, need.size() * sizeof(int), hipMemcpyDeviceToHost, st));
-      NFA_HIP(hipStreamSynchronize(st));
-    }
-    auto root_of = [&](long long x) {
-      return need_root[std::lower_bound(need.begin(), need.end(), (int)x) - need.begin()];
-    };
-    // terms of a row's faces to slaves: s T_f z(root of the slave)
-    auto slave_faces = [&](int c, int sign, std::vector<FixTerm>& out) {
-      for (int f = 0; f < 6; ++f) {
-        int arr; long long idx, nb; bool in;
-        face(c, f, &arr, &idx, &in, &nb);
-        if (!in) continue;
-        const int rt = root_of(nb);
-        if (rt >= 0 && rt != nb) out.push_back({arr | sign, (int)idx, rt, -1});
-      }
-    };
-    // terms of slave m's row with merged values: s T_f (z(root) - z(root of the neighbour))
-    auto slave_row = [&](int m, int rm, int sign, std::vector<FixTerm>& out) {
-      for (int f = 0; f < 6; ++f) {
-        int arr; long long idx, nb; bool in;
-        face(m, f, &arr, &idx, &in, &nb);
-        const int rt = in ? root_of(nb) : -1;
-        if (rt == rm) continue;   // T (z(r) - z(r)) = 0
-        out.push_back({arr | sign, (int)idx, rm, rt});
-      }
-    };
-    // down: q~ - q per entry, entries grouped by level-1 cell in a fixed
-    // order (the listed rows ascending, then the slaves by their root's cell)
-    const Dims& C = mg.lv[1].d;
-    auto blk0 = [&](long long c) {
-      const long long i = c % g.nx, j = (c / g.nx) % g.ny, k = c / plane;
-      return (int)(((k >> 1) * C.ny + (j >> 1)) * C.nx + (i >> 1));
-    };
-    std::vector<std::pair<int, int>> ent;
-    for (int c : g.h_fix) ent.push_back({blk0(c), c});
-    for (size_t t = 0; t < g.h_scell.size(); ++t) ent.push_back({blk0(g.h_sroot[t]), -(int)t - 1});
-    std::stable_sort(ent.begin(), ent.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
-    std::vector<int> fb, fo;
-    std::vector<FixTerm> dt;
-    for (size_t e = 0; e < ent.size(); ++e) {
-      if (e == 0 || ent[e].first != ent[e - 1].first) {
-        fb.push_back(ent[e].first);
-        fo.push_back((int)dt.size());
-      }
-      const int code = ent[e].second;
-      if (code >= 0) slave_faces(code, 0, dt);   // an unknown's faces to slaves
-      else slave_row(g.h_scell[-code - 1], g.h_sroot[-code - 1], 4, dt);   // minus a slave's row
-    }
-    fo.push_back((int)dt.size());
-    // up: dq per listed row, its faces to slaves, then (a root) its slaves' rows
-    std::vector<int> uo(1, 0);
-    std::vector<FixTerm> ut;
-    for (int c : g.h_fix) {
-      slave_faces(c, 4, ut);
-      auto it = members.find(c);
-      if (it != members.end())
-        for (int m : it->second) slave_row(m, c, 0, ut);
-      uo.push_back((int)ut.size());
-    }
-    auto upload_terms = [&](DevBuf& b, const std::vector<FixTerm>& v) -> hipError_t {
-      hipError_t e2 = b.alloc(std::max<size_t>(1, v.size()) * sizeof(FixTerm));
-      if (e2 != hipSuccess || v.empty()) return e2;
-      return hipMemcpy(b.p, v.data(), v.size() * sizeof(FixTerm), hipMemcpyHostToDevice);
-    };
-    NFA_HIP(upload(mg.fblk, fb));
-    NFA_HIP(upload(mg.foff, fo));
-    NFA_HIP(upload_terms(mg.fterm, dt));
-    NFA_HIP(mg.fval.alloc(std::max<size_t>(1, dt.size()) * sizeof(float)));
-    mg.nfblk = (int)fb.size();
-    mg.nfterm = (int)dt.size();
-    NFA_HIP(upload(mg.uoff, uo));
-    NFA_HIP(upload_terms(mg.uterm, ut));
-    NFA_HIP(mg.uval.alloc(std::max<size_t>(1, ut.size()) * sizeof(float)));
-    mg.nuterm = (int)ut.size();
-    mg.body_version = g.body_version;
-  }
+  if (mg.body_version != g.body_version)
+    return fail(NFA_ERR_INVALID, "multigrid: the grid's body was set after the handle was created; create it again");
   // the coarsest level: dense, regularized, inverted on the host
   const Level& Z = mg.lv[mg.L - 1];
   const int N = (int)Z.d.n;
@@ -1689,6 +1688,11 @@ extern "C" nfa_status nfa_mg_create(nfa_poisson op, nfa_mg* out) {
   mg->ncoarse = (int)mg->lv[mg->L - 1].d.n;
   if ((e = mg->minv.alloc((size_t)mg->ncoarse * mg->ncoarse * 8)) != hipSuccess) return bad(e);
   plan_tail(*mg);
+  const nfa_status fe = build_fixups(*mg, nullptr);
+  if (fe != NFA_OK) {
+    delete mg;
+    return fe;
+  }
   *out = mg;
   return NFA_OK;
 }
@@ -1732,6 +1736,15 @@ extern "C" nfa_status nfa_mg_set_coef(nfa_mg mg, int dtype) {
   if (!mg) return fail(NFA_ERR_INVALID, "nfa_mg_set_coef: NULL handle");
   if (dtype != NFA_F32 && dtype != NFA_BF16) return fail(NFA_ERR_INVALID, "nfa_mg_set_coef: NFA_F32 or NFA_BF16");
   const bool c16 = dtype == NFA_BF16;
+  if (c16 && !mg->d16.p) {   // the BF16 copies are allocated here, not by a set-up
+    const Grid& g = *mg->op->g;
+    if (mg->tx16.alloc(g.n * 2) != hipSuccess || mg->txb16.alloc((size_t)g.nz * g.ny * 2) != hipSuccess ||
+        mg->ty16.alloc(g.nfy() * 2) != hipSuccess || mg->tz16.alloc(g.nfz() * 2) != hipSuccess ||
+        mg->d16.alloc(g.n * 2) != hipSuccess) {
+      mg->d16.release();
+      return fail(NFA_ERR_HIP, "nfa_mg_set_coef: out of device memory for the BF16 coefficients");
+    }
+  }
   if (c16 != mg->coef16) {
     mg->coef16 = c16;
     mg->built_version = -1;   // the BF16 copies are made by the next set-up

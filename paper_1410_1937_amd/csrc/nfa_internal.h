@@ -28,25 +28,58 @@ nfa_status fail(nfa_status st, const std::string& msg);
 inline hipStream_t S(nfa_stream s) { return reinterpret_cast<hipStream_t>(s); }
 
 // ------------------------------------------------------- device buffers
-// Library-owned device memory, allocated only when a handle is created or
-// its body set, never on the solve/apply path.
+// A device buffer of a handle: either a slice of a caller-owned workspace
+// (borrowed) or memory the library allocated when the handle was created or
+// its body set (owned); never allocated on the solve/apply path.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool owned = false;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), owned(o.owned) { o.p = nullptr; o.bytes = 0; o.owned = false; }
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && owned) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    owned = false;
   }
   hipError_t alloc(size_t b) {
     release();
     if (b == 0) return hipSuccess;
     hipError_t e = hipMalloc(&p, b);
-    if (e == hipSuccess) bytes = b;
+    if (e == hipSuccess) {
+      bytes = b;
+      owned = true;
+    }
     return e;
   }
+  void borrow(void* q, size_t b) {
+    release();
+    p = q;
+    bytes = b;
+  }
   template <class T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+// Lays a handle's buffers out in one caller-owned workspace as 256-byte
+// aligned slices, or allocates each (no workspace), or only adds up the bytes
+// a workspace needs (measure).
+struct Carver {
+  unsigned char* base = nullptr;
+  size_t cap = 0, used = 0;
+  bool measure = false;
+  hipError_t take(DevBuf& b, size_t bytes) {
+    const size_t off = (used + 255) & ~size_t(255);
+    used = off + bytes;
+    if (measure) return hipSuccess;
+    if (!base) return b.alloc(bytes);
+    if (used > cap) return hipErrorOutOfMemory;
+    b.borrow(base + off, bytes);
+    return hipSuccess;
+  }
 };
 
 // ------------------------------------------------------------ launch
@@ -132,15 +165,16 @@ struct Poisson {
   hipEvent_t ev[2] = {nullptr, nullptr};
   // optional timing of selected launches inside solves (HIP events), by
   // kind: 0 / 1 sweep A in FP64 / FP32, 2 / 3 the multigrid cycle's fused
-  // level-0 down / up sweep (FP32)
+  // level-0 down / up sweep (FP32), 4 the flexible FP32 sweep A, 5 one whole
+  // application of the learned preconditioner
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;              // 2 per recorded launch
   std::vector<int> prof_kind;                   // kind per recorded launch
   std::vector<int> prof_seq;                    // iteration (since the last harvest) per recorded launch
   int prof_used = 0;
   int prof_iter = 0;                            // iterations enqueued since the last harvest
-  long long prof_launches[4] = {0, 0, 0, 0};
-  double prof_ms[4] = {0.0, 0.0, 0.0, 0.0};
+  long long prof_launches[6] = {0, 0, 0, 0, 0, 0};
+  double prof_ms[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   Coeffs<double> c64() const {
     return {tx64.as<double>(), txb64.as<double>(), ty64.as<double>(), tz64.as<double>(), dinv64.as<double>()};
   }
@@ -149,7 +183,7 @@ struct Poisson {
   }
 };
 
-constexpr int kProfMgDown = 2, kProfMgUp = 3, kProfKinds = 4;
+constexpr int kProfMgDown = 2, kProfMgUp = 3, kProfF32Flex = 4, kProfUnet = 5, kProfKinds = 6;
 
 // The operator holds coefficients of its grid's current body: assembled, and
 // no nfa_grid_set_body since (a new body changes the apertures, the active

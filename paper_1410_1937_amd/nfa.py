@@ -20,6 +20,7 @@ NFA_OK = 0
 NFA_NOT_CONVERGED = 1
 NFA_F64, NFA_F32, NFA_BF16 = 0, 1, 2
 NFA_PROF_MG_DOWN, NFA_PROF_MG_UP = 2, 3
+NFA_PROF_F32_FLEX, NFA_PROF_UNET = 4, 5
 NFA_PC_JACOBI, NFA_PC_UNET, NFA_PC_TEST_SABOTAGE, NFA_PC_JACOBI_FCG, NFA_PC_MG = 1, 2, 3, 4, 5
 NFA_PREC_F64, NFA_PREC_MIXED = 0, 1
 
@@ -93,7 +94,8 @@ _sig("nfa_grid_set_body", c_int, [c_void_p, c_void_p, c_double, c_int, c_void_p]
 _sig("nfa_grid_get_info", c_int, [c_void_p, ctypes.POINTER(GridInfo)])
 _sig("nfa_grid_export", c_int, [c_void_p, c_int, c_void_p, c_void_p])
 _sig("nfa_grid_destroy", None, [c_void_p])
-_sig("nfa_poisson_create", c_int, [c_void_p, ctypes.POINTER(c_void_p)])
+_sig("nfa_poisson_create", c_int, [c_void_p, c_void_p, ctypes.c_size_t, ctypes.POINTER(c_void_p)])
+_sig("nfa_poisson_workspace_bytes", ctypes.c_size_t, [c_void_p])
 _sig("nfa_poisson_assemble", c_int, [c_void_p, c_void_p, ctypes.POINTER(AssembleParams), c_void_p])
 _sig("nfa_poisson_apply", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p])
 _sig("nfa_poisson_rhs", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_void_p,
@@ -109,7 +111,10 @@ _sig("nfa_poisson_export", c_int, [c_void_p, c_int, c_void_p, c_void_p])
 _sig("nfa_poisson_destroy", None, [c_void_p])
 _sig("nfa_poisson_profile", c_int, [c_void_p, c_int])
 _sig("nfa_poisson_residual", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double), c_void_p])
-_sig("nfa_unet_create", c_int, [c_int, c_int, c_int, c_int, c_int, ctypes.POINTER(c_void_p)])
+_sig("nfa_unet_create", c_int, [c_int, c_int, c_int, c_int, c_int, c_void_p, ctypes.c_size_t,
+                                ctypes.POINTER(c_void_p)])
+_sig("nfa_unet_workspace_bytes", ctypes.c_size_t, [c_int, c_int, c_int, c_int])
+_sig("nfa_unet_bind", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int])
 _sig("nfa_unet_param_count", c_ll, [c_int])
 _sig("nfa_unet_levels", c_int, [c_void_p])
 _sig("nfa_unet_get_params", c_int, [c_void_p, c_void_p])
@@ -394,9 +399,14 @@ class Poisson:
     """Assembled pressure operator and its solvers on a Grid."""
 
     def __init__(self, grid: Grid):
+        """The operator's device memory is one torch tensor (the workspace),
+        owned here and handed to the library."""
         self.grid = grid
+        nbytes = int(lib.nfa_poisson_workspace_bytes(grid.h))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         h = c_void_p()
-        _check(lib.nfa_poisson_create(grid.h, ctypes.byref(h)), "nfa_poisson_create")
+        _check(lib.nfa_poisson_create(grid.h, c_void_p(self.workspace.data_ptr()), nbytes, ctypes.byref(h)),
+               "nfa_poisson_create")
         self.h = h
         self.shape = grid.shape
 
@@ -569,7 +579,8 @@ class Poisson:
 
     def profile_read(self, dtype):
         ks = KernelStats()
-        code = {"f64": NFA_F64, "f32": NFA_F32, "mg_down": NFA_PROF_MG_DOWN, "mg_up": NFA_PROF_MG_UP}[dtype]
+        code = {"f64": NFA_F64, "f32": NFA_F32, "mg_down": NFA_PROF_MG_DOWN, "mg_up": NFA_PROF_MG_UP,
+                "f32_flex": NFA_PROF_F32_FLEX, "unet": NFA_PROF_UNET}[dtype]
         _check(lib.nfa_poisson_profile_read(self.h, code, ctypes.byref(ks)), "nfa_poisson_profile_read")
         return {"launches": ks.launches, "ms": ks.ms, "cells": ks.cells}
 
@@ -604,6 +615,7 @@ def unet_shapes(levels=3):
     out = [(2, c[0])] + [(c[l - 1], c[l]) for l in range(1, levels)]
     out.append((c[levels - 1], c[levels - 2]))
     out += [(c[l], c[l - 1]) for l in range(levels - 2, 0, -1)]
+    out.append((c[0], c[0]))
     out.append((c[0], 1))
     return out
 
@@ -612,11 +624,40 @@ class UNet:
     """The learned preconditioner (see include/nfa_unet.h)."""
 
     def __init__(self, nx, ny, nz, seed=0, levels=3):
+        """Device memory: one workspace tensor for the network, and four FP32
+        tensors (params, grads, adam_m, adam_v) bound as its parameter state;
+        all owned here."""
+        nbytes = int(lib.nfa_unet_workspace_bytes(nx, ny, nz, levels))
+        if nbytes == 0:
+            raise NFAError("nfa_unet_workspace_bytes: invalid network size")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         h = c_void_p()
-        _check(lib.nfa_unet_create(nx, ny, nz, levels, seed, ctypes.byref(h)), "nfa_unet_create")
+        _check(lib.nfa_unet_create(nx, ny, nz, levels, seed, c_void_p(self.workspace.data_ptr()), nbytes,
+                                   ctypes.byref(h)), "nfa_unet_create")
         self.h = h
         self.shape = (nz, ny, nx)
         self.levels = levels
+        n = self.param_count()
+        self.params, self.grads, self.adam_m, self.adam_v = (
+            torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(4))
+        self._bind(copy=True)
+
+    def _bind(self, copy):
+        _check(lib.nfa_unet_bind(self.h, *(c_void_p(t.data_ptr()) for t in
+                                           (self.params, self.grads, self.adam_m, self.adam_v)), int(copy)),
+               "nfa_unet_bind")
+
+    def state(self):
+        """Parameters and Adam moments as host arrays (a training checkpoint)."""
+        torch.cuda.synchronize()
+        return {k: getattr(self, k).cpu().numpy() for k in ("params", "adam_m", "adam_v")}
+
+    def load_state(self, state):
+        """Resume from state(): the arrays become the bound parameter state."""
+        for k in ("params", "adam_m", "adam_v"):
+            getattr(self, k).copy_(torch.as_tensor(np.asarray(state[k], dtype=np.float32)))
+        torch.cuda.synchronize()
+        self._bind(copy=False)
 
     def param_count(self):
         return int(lib.nfa_unet_param_count(self.levels))
@@ -681,7 +722,7 @@ class UNet:
             kind, l = what[0], int(what[1:])
             code = {"a": 16, "p": 32, "d": 48}[kind] + l
             level = l + 1 if kind == "p" else l
-            ch = c[l - 1] if kind == "d" else c[l]
+            ch = (c[l - 1] if l > 0 else c[0]) if kind == "d" else c[l]
         nz, ny, nx = self.shape
         f = 2 ** level
         out = torch.empty((nz // f, ny // f, nx // f, ch), dtype=torch.bfloat16, device="cuda")
