@@ -8,14 +8,18 @@ solve to FP64 true relative residual 1e-8, project the face fluxes and
 compute the post-projection divergence.  The body geometry is static in the
 body-fixed frame and is set up once, outside the timed region.
 
-`value` is the chosen form: mixed precision (FP32 recurrence, FP64 solution
-and true residual) with the aggregation-multigrid V-cycle as the flexible CG
-preconditioner, its hierarchy rebuilt from each assembly inside the step;
-the plain FP64 Jacobi-PCG projection is timed beside it.  One extra,
-instrumented step measures, with HIP events, the average durations of sweep
-A of the fused CG iteration (new direction, operator apply, deferred x
-update) and of the V-cycle's fused level-0 down and up sweeps; the roofline
-is that of the one with the largest summed time.
+`value` is the metric's form, mixed precision plus the learned
+preconditioner: FP32 flexible CG preconditioned by the 3-level U-Net (the
+weights trained on the advected-surface sequence, applied to this larger
+grid), FP64 solution and true residual, the stagnation monitor handing the
+solve to Jacobi-PCG when the network stalls.  Beside it, each with its own
+label: the plain FP64 Jacobi-PCG projection (the metric's denominator), mixed
+Jacobi-PCG, and mixed precision with the aggregation-multigrid V-cycle in the
+same flexible slot (its hierarchy rebuilt from each assembly inside the
+step).  One extra, instrumented step of the `value` form measures, with HIP
+events on the solve's stream, the average durations of sweep A of the CG
+iteration (each form) and of whole network applications; the roofline is that
+of the one with the largest summed time.
 The CPU baseline is the FP64 oracle on the host cores, timed on a bounded
 sample (a few iterations on the full grid) and scaled to one projection.
 Beside the metric it times one Runge-Kutta cycle (two projections), one
@@ -24,6 +28,9 @@ set-up geometry (signed distance of a panelled sphere at the grid nodes, one
 stretched axis).
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu-baseline]
+
+The `value` form runs exactly --steps timed steps after --warmup; the forms
+beside it run min(--steps, 5) after min(--warmup, 1).
 """
 from __future__ import annotations
 
@@ -34,10 +41,13 @@ import subprocess
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
 WORKLOAD = "c3"
 WORKLOAD_DESC = ("512x256x192 stretched cartesian grid (25,165,824 cells), tanh clustering "
                  "(max cell-size ratio 8), free surface + 200 droplets/bubbles, rho 1000/1.2 "
@@ -78,6 +88,16 @@ def measured_traffic(kernel: str):
     return None
 
 
+def host_cpu() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(iters_fp64: int, sample_iters: int = 4) -> dict:
     """Run the oracle leg in a child process pinned to one thread."""
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
@@ -110,7 +130,8 @@ print(json.dumps({{"setup_s": t_setup, "iter_s": t_it / max(1, res.iterations), 
             "sample": (f"FP64 NumPy oracle on the full workload: geometry+assembly+rhs "
                        f"({r['setup_s']:.1f} s) plus {r['iters']} Jacobi-PCG iterations "
                        f"({r['iter_s']:.2f} s each), scaled to the {iters_fp64} iterations the "
-                       f"FP64 projection needs; 1 thread of {os.cpu_count()} host cores")}
+                       f"FP64 projection needs; 1 thread of {os.cpu_count()} host cores ({host_cpu()})"),
+            "host_cpu": host_cpu(), "host_cores": os.cpu_count()}
 
 
 def main():
@@ -143,15 +164,21 @@ def main():
     phi = torch.as_tensor(wl.phi, device=dev).to(torch.float32).contiguous()
     u, v, w = (torch.as_tensor(a, device=dev) for a in (wl.u, wl.v, wl.w))
     x = torch.zeros(op.shape, dtype=torch.float64, device=dev)
-    solver = dict(precision="mixed", precond="mg")
+    net = nfa.UNet(g.nx, g.ny, g.nz, levels=3)
+    wpath = os.path.join(ROOT, "paper_1410_1937_amd", "weights", "unet_l3_c4.npy")
+    net.set_params(np.load(wpath))
+    forms = {
+        "learned": dict(precision="mixed", precond="unet", unet=net),
+        "multigrid": dict(precision="mixed", precond="mg"),
+        "mixed_jacobi": dict(precision="mixed"),
+        "fp64": dict(precision="f64"),
+    }
+    solver = forms["multigrid"]          # the Runge-Kutta cycle's solver
 
     def step(kind):
         op.assemble(phi, wl.rho_l, wl.rho_g, wl.smooth)
         b = op.rhs(u, v, w, wl.dt, wl.body_vel)
-        if kind == "chosen":
-            p, res = op.solve(b, x=x, tol=1e-8, **solver)
-        else:
-            p, res = op.solve(b, x=x, tol=1e-8, precision="f64")
+        p, res = op.solve(b, x=x, tol=1e-8, **forms[kind])
         F = op.project(u, v, w, p, wl.dt)
         op.divergence(*F, wl.body_vel)
         if res.status != 0 or not res.relres <= 1e-8:
@@ -161,63 +188,79 @@ def main():
     def timed(kind, steps, warmup):
         for i in range(warmup):
             r = step(kind)
-            log(f"[bench] warmup {kind} {i}: {r.iterations} its, relres {r.relres:.2e}")
+            log(f"[bench] warmup {kind} {i}: {r.iterations} its, relres {r.relres:.2e}, fallback {r.fallback}")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         its = []
         for i in range(steps):
             r = step(kind)
             its.append(r.iterations)
-            log(f"[bench] step {kind} {i}: {r.iterations} its, outer {r.outer}, relres {r.relres:.2e}")
+            log(f"[bench] step {kind} {i}: {r.iterations} its, outer {r.outer}, relres {r.relres:.2e}, "
+                f"fallback {r.fallback}")
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / steps, its, r
 
-    ms_chosen, its_chosen, r_chosen = timed("chosen", args.steps, args.warmup)
-    log(f"[bench] chosen: {ms_chosen:.1f} ms/projection")
-    ms_fp64, its_fp64, r_fp64 = (None, [None], None)
-    if not args.skip_fp64:
-        ms_fp64, its_fp64, r_fp64 = timed("fp64", args.steps, args.warmup)
-        log(f"[bench] plain FP64: {ms_fp64:.1f} ms/projection")
+    results = {}
+    for kind in forms:
+        if kind == "fp64" and args.skip_fp64:
+            continue
+        k_steps, k_warm = (args.steps, args.warmup) if kind == "learned" else (min(args.steps, 5), min(args.warmup, 1))
+        ms, its, r = timed(kind, k_steps, k_warm)
+        results[kind] = (ms, its, r, k_steps)
+        log(f"[bench] {kind}: {ms:.1f} ms/projection")
+    ms_chosen, its_chosen, r_chosen, _ = results["learned"]
 
-    # instrumented step: HIP events around sweep A of every iteration and
-    # the two level-0 operator applies of every V-cycle; the roofline is
-    # that of the one with the larger summed time (the dominant kernel)
+    # instrumented step of the value form: HIP events around sweep A of every
+    # iteration and around every network application; the roofline is that of
+    # the one with the largest summed time (the dominant kernel)
     op.profile(True)
-    step("chosen")
-    kinds = {k: op.profile_read(k) for k in ("f32", "f64", "mg_down", "mg_up")}
+    step("learned")
+    kinds = {k: op.profile_read(k) for k in ("f32", "f32_flex", "f64", "unet")}
     op.profile(False)
     # sweep A moves, per cell: z, p_old, tx, ty, tz, x read; p_new, q, x
     # written (9 words: 36 B in FP32, 72 B in FP64); its flexible form also
-    # reads r for p.r (10 words, 40 B in FP32).  The fused level-0
-    # down sweep reads r, D^-1, tx, ty, tz (4 B each) and the unknown flag
-    # (1 B) and writes one level-1 value per 8 cells (0.5 B): 21.5 B; the up
-    # sweep reads the same plus one level-1 value per 8 cells and the CG's q
-    # (for z.q) and writes z: 29.5 B.  Neighbour re-reads are cache hits and
-    # not counted.
+    # reads r for p.r (10 words, 40 B in FP32).  Neighbour re-reads are cache
+    # hits and not counted.  A network application performs 2 x 27 x cin x
+    # cout multiply-adds per position of each 3x3x3 convolution, 2 x 16 for
+    # the 1x1x1 head.
     wx = next((w for w in (4, 2) if wl.shape[2] % (w * 128) == 0), 1)
-    l0 = "k_l0_x4" if wl.shape[2] % 4 == 0 else "k_l0"
-    flex = solver["precond"] != "jacobi"
-    meta = {"f32": (40, "k_cg_a<float, 4, 1, true>") if flex else (36, "k_cg_a<float, 4, 1, false>"),
-            "f64": (72, f"k_cg_a<double, 2, {wx}, false>"),
-            "mg_down": (21.5, f"{l0}<false, float>"), "mg_up": (29.5, f"{l0}<true, float>")}
+    unet_flop = 0
+    shapes = nfa.unet_shapes(3)
+    levels_of = [0, 1, 2, 2, 1, 0, 0]       # the level each convolution of the 3-level network runs on
+    for (ci, co), lv, nt in zip(shapes, levels_of, nfa.unet_taps(3)):
+        unet_flop += 2 * nt * ci * co * (wl.ncells // 8 ** lv)
+    meta = {"f32": ("hbm", 36, "k_cg_a<float, 4, 1, false>"), "f32_flex": ("hbm", 40, "k_cg_a<float, 4, 1, true>"),
+            "f64": ("hbm", 72, f"k_cg_a<double, 2, {wx}, false>"),
+            "unet": ("mfma", None, "network application (k_tconv x6, k_head_out)")}
     entries = {}
     for k, ks in kinds.items():
         if ks["launches"] == 0:
             continue
-        bpc, kname = meta[k]
+        bound, bpc, kname = meta[k]
         avg_ms = ks["ms"] / ks["launches"]
-        bpl = int(bpc * ks["cells"])
-        gbs = bpl / (avg_ms * 1e-3) / 1e9
-        entries[k] = {"kernel": kname, "avg_launch_ms": round(avg_ms, 5), "launches": ks["launches"],
-                      "ms_per_step": round(ks["ms"], 3), "algorithmic_bytes_per_launch": bpl,
-                      "achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        if bound == "hbm":
+            bpl = int(bpc * ks["cells"])
+            ach = bpl / (avg_ms * 1e-3) / 1e9
+            entries[k] = {"kernel": kname, "bound": "hbm", "avg_launch_ms": round(avg_ms, 5),
+                          "launches": ks["launches"], "ms_per_step": round(ks["ms"], 3),
+                          "algorithmic_bytes_per_launch": bpl, "achieved": round(ach, 1), "unit": "GB/s",
+                          "peak": HBM_PEAK_GBS, "frac": round(ach / HBM_PEAK_GBS, 4)}
+        else:
+            ach = unet_flop / (avg_ms * 1e-3) / 1e12
+            entries[k] = {"kernel": kname, "bound": "mfma", "avg_launch_ms": round(avg_ms, 5),
+                          "launches": ks["launches"], "ms_per_step": round(ks["ms"], 3),
+                          "algorithmic_flop_per_launch": unet_flop, "achieved": round(ach, 1),
+                          "unit": "TFLOP/s", "peak": BF16_PEAK_TFLOPS, "frac": round(ach / BF16_PEAK_TFLOPS, 4)}
     dom = max(entries, key=lambda k: entries[k]["ms_per_step"])
     e = entries[dom]
-    roofline = {"bound": "hbm", "achieved": e["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": e["frac"], "traffic": measured_traffic(e["kernel"]), "kernel": e["kernel"],
-                "avg_launch_ms": e["avg_launch_ms"], "launches": e["launches"],
-                "algorithmic_bytes_per_launch": e["algorithmic_bytes_per_launch"],
+    roofline = {"bound": e["bound"], "achieved": e["achieved"], "peak": e["peak"], "unit": e["unit"],
+                "frac": e["frac"], "traffic": measured_traffic(e["kernel"]) if e["bound"] == "hbm" else None,
+                "kernel": e["kernel"], "avg_launch_ms": e["avg_launch_ms"], "launches": e["launches"],
                 "other_timed_kernels": [entries[k] for k in entries if k != dom]}
+    if e["bound"] == "hbm":
+        roofline["algorithmic_bytes_per_launch"] = e["algorithmic_bytes_per_launch"]
+    else:
+        roofline["algorithmic_flop_per_launch"] = e["algorithmic_flop_per_launch"]
 
     # attainable HBM bandwidth beside the peak: the library's plain streaming
     # copy over 1 GiB (4x the Infinity Cache), bytes read + written per second
@@ -313,6 +356,7 @@ def main():
         del tri, psi
 
     cpu = None
+    ms_fp64, its_fp64, r_fp64, _ = results.get("fp64", (None, [None], None, 0))
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle)")
         try:
@@ -321,6 +365,18 @@ def main():
             cpu = {"error": str(e)[-500:]}
 
     n = wl.ncells
+
+    def form(kind, label):
+        if kind not in results:
+            return None
+        ms, its, r, k = results[kind]
+        out = {"solver": label, "ms_per_projection": round(ms, 3), "steps_timed": k, "iterations": its[-1],
+               "fp64_residuals": r.outer, "fallback": r.fallback, "relres": r.relres,
+               "cell_updates_per_s": round(n * its[-1] / (ms * 1e-3), 1)}
+        if ms_fp64:
+            out["speedup_vs_plain_fp64"] = round(ms_fp64 / ms, 3)
+        return out
+
     line = {
         "metric": "ms/projection to rel. residual 1e-8 @25M cells: mixed+learned vs plain FP64",
         "value": round(ms_chosen, 3),
@@ -332,19 +388,22 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "bf16+f32+f64",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_DESC, "cells": n, "tol": 1e-8,
-                   "solver": ("FP32 flexible CG preconditioned by one symmetric aggregation-multigrid "
-                              "V-cycle (2x2x2 Galerkin levels, damped Jacobi, FP64 dense coarsest "
-                              "solve; hierarchy rebuilt every step) with FP64 residual replacement "
-                              "(true residual recomputed in FP64 every 10x reduction)"),
+                   "solver": ("mixed + learned: FP32 flexible CG (FCG(1)) preconditioned by the 3-level U-Net "
+                              "(16/32/64 channels, BF16 MFMA convolutions, FP32 accumulation; weights trained on "
+                              "the 256x128x96 advected-surface sequence), FP64 solution and residual replacement, "
+                              "stagnation monitor 0.99 over 10 iterations handing over to Jacobi-PCG"),
                    "step": "assemble + rhs + solve + project + divergence",
                    "iterations": its_chosen[-1], "fp64_residuals": r_chosen.outer,
                    "fallback": r_chosen.fallback},
-        "plain_fp64": None if ms_fp64 is None else {
-            "ms_per_projection": round(ms_fp64, 3), "iterations": its_fp64[-1],
-            "speedup_of_value": round(ms_fp64 / ms_chosen, 3)},
+        "speedup_vs_plain_fp64": round(ms_fp64 / ms_chosen, 3) if ms_fp64 else None,
+        "plain_fp64": form("fp64", "FP64 Jacobi-PCG (the metric's denominator)"),
+        "mixed_jacobi": form("mixed_jacobi", "FP32 Jacobi-PCG with FP64 residual replacement"),
+        "multigrid": form("multigrid", "FP32 flexible CG preconditioned by one aggregation-multigrid V-cycle "
+                                       "(hierarchy rebuilt every step), FP64 residual replacement; not the "
+                                       "metric's form"),
         "cell_updates_per_s": round(n * its_chosen[-1] / (ms_chosen * 1e-3), 1),
         "rk2_cycle": rk2,
         "vof_step": vof,

@@ -46,7 +46,7 @@ int timed_cg_a(Poisson& op, CG<T>& B, int j, bool flex, hipStream_t st) {
   const bool rec = prof_begin(op, st);
   const int np = launch_cg_a<T>(*op.g, B.C, B.z, B.p[j & 1], B.p[(j + 1) & 1], B.x, B.r, B.q,
                                 op.partials.as<double>(), op.scal.as<SolveScalars>(), flex, B.vec, st);
-  prof_end(op, rec, sizeof(T) == 8 ? 0 : 1, st);
+  prof_end(op, rec, sizeof(T) == 8 ? 0 : (flex ? kProfF32Flex : 1), st);
   return np;
 }
 
@@ -108,7 +108,9 @@ void enqueue_iter(Poisson& op, CG<T>& B, int j, int pc, void* unet, nfa_status* 
                                             sc, st);
       if (e != NFA_OK && *pst == NFA_OK) *pst = e;
     } else {
+      const bool rec = prof_begin(op, st);
       const nfa_status e = unet_precond_apply(unet, op, (const float*)B.r, (float*)B.z, sc, st);
+      prof_end(op, rec, kProfUnet, st);
       if (e != NFA_OK && *pst == NFA_OK) *pst = e;
     }
     if (nzq > 0) {
