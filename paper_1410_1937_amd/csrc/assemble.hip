@@ -402,7 +402,7 @@ extern "C" nfa_status nfa_poisson_apply(nfa_poisson op, const void* x, void* y, 
       launch_merge_copy<double>(g, op->tmp.as<double>(), st, nullptr);
       src = op->tmp.as<double>();
     }
-    launch_stencil<double>(g, op->c64(), src, nullptr, (double*)y, nullptr, nullptr, ST_APPLY, st);
+    launch_stencil<double>(g, op->c64(), src, nullptr, (double*)y, st);
     launch_merge_gather<double>(g, (double*)y, st, nullptr);
   } else if (dtype == NFA_F32) {
     const float* src = (const float*)x;
@@ -411,7 +411,7 @@ extern "C" nfa_status nfa_poisson_apply(nfa_poisson op, const void* x, void* y, 
       launch_merge_copy<float>(g, op->tmp.as<float>(), st, nullptr);
       src = op->tmp.as<float>();
     }
-    launch_stencil<float>(g, op->c32(), src, nullptr, (float*)y, nullptr, nullptr, ST_APPLY, st);
+    launch_stencil<float>(g, op->c32(), src, nullptr, (float*)y, st);
     launch_merge_gather<float>(g, (float*)y, st, nullptr);
   } else {
     return fail(NFA_ERR_INVALID, "nfa_poisson_apply: dtype must be NFA_F64 or NFA_F32");

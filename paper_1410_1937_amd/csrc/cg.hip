@@ -32,6 +32,7 @@
 // off), so q is bitwise the value of the plain sweep.
 #include "device_util.h"
 #include "nfa_internal.h"
+#include "sweep_tile.h"
 #include "vecops.h"
 
 #include <map>
@@ -41,59 +42,16 @@
 namespace nfa {
 namespace {
 
-template <class T, int V> struct alignas(sizeof(T) * V) Pack {
-  T v[V];
-};
+using namespace tile;
 
-template <class T, int V> __device__ __forceinline__ Pack<T, V> ld(const T* p) {
-  return *reinterpret_cast<const Pack<T, V>*>(p);
-}
-template <class T, int V> __device__ __forceinline__ void st(T* p, const Pack<T, V>& a) {
-  *reinterpret_cast<Pack<T, V>*>(p) = a;
-}
-// Streaming accesses of the sweeps (each element touched once per sweep) may
-// carry the non-temporal hint.  Where it pays was measured per sweep and
-// precision on the 512 x 256 x 192 grid (sweep A: loads and stores in FP32,
-// stores only in FP64; sweep B: loads in FP32, loads and stores in FP64);
-// neighbour and halo reads always use ordinary loads.
-template <bool NT, class T, int V> __device__ __forceinline__ Pack<T, V> ld_stream(const T* p) {
-  Pack<T, V> r;
-  if constexpr (!NT) {
-    r = ld<T, V>(p);
-  } else if constexpr (V == 1) {
-    r.v[0] = __builtin_nontemporal_load(p);
-  } else {
-    typedef T vt __attribute__((ext_vector_type(V)));
-    const vt a = __builtin_nontemporal_load(reinterpret_cast<const vt*>(p));
-#pragma unroll
-    for (int e = 0; e < V; ++e) r.v[e] = a[e];
-  }
-  return r;
-}
-template <bool NT, class T, int V> __device__ __forceinline__ void st_stream(T* p, const Pack<T, V>& a) {
-  if constexpr (!NT) {
-    st<T, V>(p, a);
-  } else if constexpr (V == 1) {
-    __builtin_nontemporal_store(a.v[0], p);
-  } else {
-    typedef T vt __attribute__((ext_vector_type(V)));
-    vt b;
-#pragma unroll
-    for (int e = 0; e < V; ++e) b[e] = a.v[e];
-    __builtin_nontemporal_store(b, reinterpret_cast<vt*>(p));
-  }
-}
+// Where the non-temporal hint pays was measured per sweep and precision on the
+// 512 x 256 x 192 grid (sweep A: loads and stores in FP32, stores only in
+// FP64; sweep B: loads in FP32, loads and stores in FP64).
 template <class T> struct StreamHints {
   static constexpr bool a_load = sizeof(T) == 4, a_store = true;
   static constexpr bool b_load = true, b_store = sizeof(T) == 8;
 };
 
-template <class T, int V> __device__ __forceinline__ Pack<T, V> zero() {
-  Pack<T, V> a;
-#pragma unroll
-  for (int e = 0; e < V; ++e) a.v[e] = T(0);
-  return a;
-}
 // new direction z + beta p_old of V cells
 template <class T, int V>
 __device__ __forceinline__ Pack<T, V> dir(const T* z, const T* po, long long c, T beta) {
@@ -103,9 +61,6 @@ __device__ __forceinline__ Pack<T, V> dir(const T* z, const T* po, long long c, 
   for (int e = 0; e < V; ++e) r.v[e] = a.v[e] + beta * b.v[e];
   return r;
 }
-
-constexpr int AX = 64;
-constexpr int kTileWaves = 16;
 
 template <class T, int V, int WX, bool FLEX>
 __global__ __launch_bounds__(AX* kTileWaves) void k_cg_a(
@@ -328,18 +283,15 @@ inline int vblocks(long long n) {
 
 }  // namespace
 
-template <class T> constexpr int vec_width() { return 16 / (int)sizeof(T); }
-
 template <class T>
 bool cg_vectorizable(const Grid& g, const void* const* ptrs, int nptr) {
-  constexpr int V = vec_width<T>();
+  constexpr int V = tile::vec_width<T>();
   if (g.nx % V != 0) return false;
   for (int i = 0; i < nptr; ++i)
     if (reinterpret_cast<uintptr_t>(ptrs[i]) % 16 != 0) return false;
   return true;
 }
 
-// resident workgroups per CU of a kernel (cached per kernel)
 int resident_blocks(const void* fn, int threads) {
   static std::mutex mu;
   static std::map<const void*, int> cache;
@@ -356,24 +308,13 @@ int resident_blocks(const void* fn, int threads) {
   return nb;
 }
 
-// Tile width in wavefronts for sweep A: the widest of 4, 2, 1 whose tile
-// width divides nx (FP64, where a row of 2-double vectors spans several
-// wavefronts); FP32 uses one wavefront across and 16 rows.
-template <class T> int cg_a_wx(const Grid& g, int V) {
-  if (sizeof(T) != 8 || V == 1) return 1;
-  for (int wx : {4, 2}) {
-    if (g.nx % (wx * AX * V) == 0) return wx;
-  }
-  return 1;
-}
-
 // sweep A; returns the number of workgroup partials per component
 template <class T>
 int launch_cg_a(const Grid& g, const Coeffs<T>& C, const T* z, const T* pold, T* pnew, T* x,
                 const T* r, T* q, double* partials, const SolveScalars* sc, bool flex, bool vec,
                 hipStream_t s) {
-  const int V = vec ? vec_width<T>() : 1;
-  const int wx = cg_a_wx<T>(g, V);
+  const int V = vec ? tile::vec_width<T>() : 1;
+  const int wx = tile_wx<T>(g, V);
   const int ay = kTileWaves / wx;
   const int tiles_x = (g.nx + AX * wx * V - 1) / (AX * wx * V);
   const long long ncol = (long long)tiles_x * ((g.ny + ay - 1) / ay);
@@ -394,8 +335,8 @@ int launch_cg_a(const Grid& g, const Coeffs<T>& C, const T* z, const T* pold, T*
     else CGA(VV, 1, FF);           \
   } while (0)
   if (vec) {
-    if (flex) CGA_W(vec_width<T>(), true);
-    else CGA_W(vec_width<T>(), false);
+    if (flex) CGA_W(tile::vec_width<T>(), true);
+    else CGA_W(tile::vec_width<T>(), false);
   } else {
     if (flex) CGA(1, 1, true);
     else CGA(1, 1, false);
@@ -409,7 +350,7 @@ int launch_cg_a(const Grid& g, const Coeffs<T>& C, const T* z, const T* pold, T*
 template <class T>
 int launch_cg_b(const Grid& g, T* r, const T* q, const T* dinv, T* z, double* partials,
                 const SolveScalars* sc, bool flex, bool vec, hipStream_t s) {
-  constexpr int VW = vec_width<T>();
+  constexpr int VW = tile::vec_width<T>();
   const long long nv = vec ? g.n / VW : g.n;
   const int nb = vblocks(nv);
 #define CGB(VV, FF) k_cg_b<T, VV, FF><<<nb, kBlock, 0, s>>>(nv, r, q, dinv, z, partials, sc)

@@ -210,12 +210,10 @@ inline void prof_end(Poisson& op, bool rec, int kind, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------- kernels
-// Stencil sweeps (stencil.hip).  mode: 0 q = A p (+ partial p.q if partials),
-// 1 q = b - A p (+ partial q.q).  Returns the number of partials written.
-enum { ST_APPLY = 0, ST_RESIDUAL = 1 };
+// Stencil sweep (stencil.hip): q = A p, or q = b - A p when b is given
+// (FP64 only: a FP32 sweep ignores b).
 template <class T>
-int launch_stencil(const Grid& g, const Coeffs<T>& c, const T* p, const double* b, T* q,
-                   double* partials, const SolveScalars* sc, int mode, hipStream_t s);
+void launch_stencil(const Grid& g, const Coeffs<T>& c, const T* p, const double* b, T* q, hipStream_t s);
 
 // Merge kernels (stencil.hip): slaves copy their root (primal vectors);
 // roots add their slaves, slaves -> 0 (dual vectors).

@@ -78,7 +78,7 @@ nfa_status read_scalars(Poisson& op, hipStream_t st, SolveScalars* out) {
 nfa_status residual64(Poisson& op, const double* b, const double* x, double* r, int phase,
                       hipStream_t st) {
   Grid& g = *op.g;
-  launch_stencil<double>(g, op.c64(), x, b, r, nullptr, nullptr, ST_RESIDUAL, st);
+  launch_stencil<double>(g, op.c64(), x, b, r, st);
   launch_merge_gather<double>(g, r, st, nullptr);
   if (phase >= 0) {
     double* parts = op.partials.as<double>();

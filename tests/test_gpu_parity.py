@@ -285,3 +285,23 @@ def test_a_new_body_leaves_the_operator_stale_until_it_is_assembled_again():
     og, ob, oop, _ = oracle_for(wl2)
     assert np.array_equal(host(gop.apply(x)), oop.apply(host(x)))
     assert np.array_equal(host(gop.export("dinv")), oop.dinv)
+
+
+def test_apply_on_unaligned_views_takes_the_scalar_sweep():
+    """Inputs and outputs that are not 16-byte aligned run the one-cell-per-lane
+    form of the operator sweep; it is bitwise the vector form's result."""
+    wl = CASES["wx4_sphere_neumann"]
+    og, ob, oop, _ = oracle_for(wl)
+    gg, gop = gpu_for(wl)
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal(og.shape)
+    n = x.size
+    buf = torch.zeros(n + 1, dtype=torch.float64, device="cuda")
+    buf[1:] = torch.as_tensor(x.reshape(-1), device="cuda")
+    xv = buf[1:].view(og.shape)
+    assert xv.data_ptr() % 16 != 0
+    out = torch.zeros(n + 1, dtype=torch.float64, device="cuda")
+    yv = out[1:].view(og.shape)
+    gop.apply(xv, out=yv)
+    assert np.array_equal(host(yv), oop.apply(x))
+    assert np.array_equal(host(yv), host(gop.apply(torch.as_tensor(x, device="cuda"))))
