@@ -115,6 +115,13 @@ nfa_status nfa_unet_train_step(nfa_unet u, nfa_poisson op, const float* r, doubl
 #define NFA_UNET_A 16  /* + l: encoder a_l, n_l x c_l */
 #define NFA_UNET_P 32  /* + l: pool(a_l), n_{l+1} x c_l */
 #define NFA_UNET_D 48  /* + l: decoder d_l (d_{L-1}: bottleneck), n_l x c_{l-1} (d_0: n_0 x 16) */
+/* Gradients of the last nfa_unet_grad / nfa_unet_train_step (the chain rule
+ * through the layers above, in the same order): */
+#define NFA_UNET_DZ 64     /* dL/dz, FP32, n_0 */
+#define NFA_UNET_DD 80     /* + l: at decoder l's pre-activation (l = L-1: the bottleneck), shaped as d_l */
+#define NFA_UNET_SKIP 96   /* + l, l <= L-2: at decoder l's input up(d_{l+1}) + a_l, n_l x c_l */
+#define NFA_UNET_DA 112    /* + l: at encoder l's pre-activation, n_l x c_l */
+#define NFA_UNET_DP 128    /* + l, l <= L-2: at the pooled p_l, n_{l+1} x c_l */
 nfa_status nfa_unet_export(nfa_unet u, int what, void* dst, nfa_stream s); /* ASYNC */
 void nfa_unet_destroy(nfa_unet u);
 

@@ -1457,6 +1457,11 @@ extern "C" nfa_status nfa_unet_export(nfa_unet u, int what, void* dst, nfa_strea
   else if (what >= NFA_UNET_A && what < NFA_UNET_A + u->L) b = &u->a[what - NFA_UNET_A];
   else if (what >= NFA_UNET_P && what < NFA_UNET_P + u->L - 1) b = &u->p[what - NFA_UNET_P];
   else if (what >= NFA_UNET_D && what < NFA_UNET_D + u->L) b = &u->d[what - NFA_UNET_D];
+  else if (what == NFA_UNET_DZ) b = &u->dz;
+  else if (what >= NFA_UNET_DD && what < NFA_UNET_DD + u->L) b = &u->dd[what - NFA_UNET_DD];
+  else if (what >= NFA_UNET_SKIP && what < NFA_UNET_SKIP + u->L - 1) b = &u->skip[what - NFA_UNET_SKIP];
+  else if (what >= NFA_UNET_DA && what < NFA_UNET_DA + u->L) b = &u->da[what - NFA_UNET_DA];
+  else if (what >= NFA_UNET_DP && what < NFA_UNET_DP + u->L - 1) b = &u->dp[what - NFA_UNET_DP];
   else return fail(NFA_ERR_INVALID, "nfa_unet_export: unknown item");
   NFA_HIP(hipMemcpyAsync(dst, b->p, b->bytes, hipMemcpyDeviceToDevice, S(s)));
   return NFA_OK;

@@ -714,16 +714,23 @@ class UNet:
         return loss.value
 
     def export(self, what):
-        """'x0', 'a<l>', 'p<l>' or 'd<l>' as a channels-last bfloat16 tensor."""
+        """Activations 'x0', 'a<l>', 'p<l>', 'd<l>' of the last forward with keep,
+        or gradients 'dz' (FP32 cells), 'dd<l>', 'skip<l>', 'da<l>', 'dp<l>' of
+        the last grad / train_step, as channels-last bfloat16 tensors."""
         c = unet_channels(self.levels)
+        nz, ny, nx = self.shape
+        if what == "dz":
+            out = torch.empty(self.shape, dtype=torch.float32, device="cuda")
+            _check(lib.nfa_unet_export(self.h, 64, c_void_p(out.data_ptr()), _stream()), "nfa_unet_export")
+            return out
         if what == "x0":
             code, level, ch = 0, 0, 2
         else:
-            kind, l = what[0], int(what[1:])
-            code = {"a": 16, "p": 32, "d": 48}[kind] + l
-            level = l + 1 if kind == "p" else l
-            ch = (c[l - 1] if l > 0 else c[0]) if kind == "d" else c[l]
-        nz, ny, nx = self.shape
+            kind = what.rstrip("0123456789")
+            l = int(what[len(kind):])
+            code = {"a": 16, "p": 32, "d": 48, "dd": 80, "skip": 96, "da": 112, "dp": 128}[kind] + l
+            level = l + 1 if kind in ("p", "dp") else l
+            ch = (c[l - 1] if l > 0 else c[0]) if kind in ("d", "dd") else c[l]
         f = 2 ** level
         out = torch.empty((nz // f, ny // f, nx // f, ch), dtype=torch.bfloat16, device="cuda")
         _check(lib.nfa_unet_export(self.h, code, c_void_p(out.data_ptr()), _stream()), "nfa_unet_export")

@@ -1,9 +1,11 @@
 """The learned preconditioner on the GPU against the FP64 oracle (needs an
-MI355X).  Layers are checked one at a time, each fed with the GPU's own
-BF16 input, to within one BF16 rounding step of the oracle (FP32 against
-FP64 accumulation can move a value across a rounding boundary); the whole
-forward pass, the loss, the parameter gradients and the Adam update within
-the tolerances stated below."""
+MI355X).  Layers of the forward pass and stages of the backward pass are
+checked one at a time, each fed with the GPU's own BF16 operands, to within
+one BF16 rounding step of the oracle (FP32 against FP64 accumulation can move
+a value across a rounding boundary), and each layer's weight gradient against
+the FP64 sum over its own operands; the whole forward pass, the loss, the
+end-to-end parameter gradients and the Adam update within the tolerances
+stated below."""
 import numpy as np
 import pytest
 
@@ -122,6 +124,63 @@ def test_gradients_loss_and_adam_match_oracle(setup):
     g_flat = net.get_grads().astype(np.float64)     # same inputs -> same gradients
     expect, _, _ = ou.adam(p_before, g_flat, np.zeros_like(p_before), np.zeros_like(p_before), 1, lr=1e-3)
     assert np.max(np.abs(net.get_params() - expect)) <= 1e-6
+
+
+def test_backward_stages_and_weight_gradients_one_layer_at_a_time():
+    """Every stage of the GPU backward pass, fed with the GPU's own BF16
+    operands (activations of the forward, gradients of the stage before),
+    against the oracle's same stage: data gradients within one BF16 step,
+    weight and bias gradients (FP32 sums of exact BF16 products) within 1e-4
+    of the FP64 sums, and dL/dz against the closed form of the step loss."""
+    from paper_1410_1937_amd import nfa
+    wl = fx.small(7, 32, 16, 12, body="sphere")
+    og, ob, oop, ob_rhs = oracle_for(wl)
+    gg, gop = gpu_for(wl)
+    net = nfa.UNet(32, 16, 12, seed=3)
+    rng = np.random.default_rng(15)
+    params = ou.init_params(13, zero_last=False)
+    params = [(w.astype(np.float32), (rng.standard_normal(b.shape) * 0.05).astype(np.float32)) for w, b in params]
+    net.set_params(nfa.UNet.flatten(params))
+    W = [ou.bf16(w.astype(np.float64)) for w, _ in params]
+    r = (ob_rhs * ob.reduced).astype(np.float32)
+    rt = torch.as_tensor(r, device="cuda")
+    e = solvers.pcg(oop, r.astype(np.float64), tol=1e-12).x
+    eAe = float(np.sum(e * r))
+    net.grad(gop, rt, eAe)
+    z = host(net.forward(gop, rt, keep=True)).astype(np.float64)   # same parameters: same activations
+    X = {k: _bf(net.export(k)) for k in ("x0", "a0", "a1", "a2", "p0", "p1", "d0", "d1", "d2",
+                                         "dd0", "dd1", "dd2", "skip0", "skip1", "da0", "da1", "da2",
+                                         "dp0", "dp1")}
+    dz = host(net.export("dz")).astype(np.float64)
+    _, dz_ref = ou.step_loss(z, r.astype(np.float64), oop.apply(z), eAe)
+    assert np.linalg.norm(dz - dz_ref) <= 1e-4 * np.linalg.norm(dz_ref)
+    dy = oop.dinv * dz
+    q = ou.bf16
+    _ulp_ok(X["dd0"], q(dy[..., None] * W[6][0][:, 0] * (X["d0"] > 0)))
+    _ulp_ok(X["skip0"], q(ou.conv3d_dgrad(X["dd0"], W[5])))
+    _ulp_ok(X["dd1"], q(ou.up_T(X["skip0"]) * (X["d1"] > 0)))
+    _ulp_ok(X["skip1"], q(ou.conv3d_dgrad(X["dd1"], W[4])))
+    _ulp_ok(X["dd2"], q(ou.up_T(X["skip1"]) * (X["d2"] > 0)))
+    _ulp_ok(X["da2"], q(ou.conv3d_dgrad(X["dd2"], W[3]) * (X["a2"] > 0)))
+    _ulp_ok(X["dp1"], q(ou.conv3d_dgrad(X["da2"], W[2])))
+    _ulp_ok(X["da1"], q((X["skip1"] + ou.pool_T(X["dp1"])) * (X["a1"] > 0)))
+    _ulp_ok(X["dp0"], q(ou.conv3d_dgrad(X["da1"], W[1])))
+    _ulp_ok(X["da0"], q((X["skip0"] + ou.pool_T(X["dp0"])) * (X["a0"] > 0)))
+    # weight and bias gradients of each layer from its own operands
+    s0 = q(ou.up(X["d1"]) + X["a0"])
+    s1 = q(ou.up(X["d2"]) + X["a1"])
+    operands = [(X["x0"], X["da0"]), (X["p0"], X["da1"]), (X["p1"], X["da2"]), (X["a2"], X["dd2"]),
+                (s1, X["dd1"]), (s0, X["dd0"])]
+    g = net.unflatten(net.get_grads())
+    for layer, (xin, dout) in enumerate(operands):
+        rw, rb = ou.conv3d_wgrad(xin, dout)
+        gw, gb = (a.astype(np.float64) for a in g[layer])
+        assert np.linalg.norm(gw - rw) <= 1e-4 * np.linalg.norm(rw), layer
+        assert np.linalg.norm(gb - rb) <= 1e-4 * np.linalg.norm(rb) + 1e-30, layer
+    gw, gb = (a.astype(np.float64) for a in g[6])
+    rw = (X["d0"].reshape(-1, 16).T @ dy.reshape(-1))[None, :, None]
+    assert np.linalg.norm(gw - rw) <= 1e-4 * np.linalg.norm(rw)
+    assert abs(gb[0] - dy.sum()) <= 1e-4 * np.abs(dy).sum()
 
 
 @pytest.mark.parametrize("levels", [4, 5])
