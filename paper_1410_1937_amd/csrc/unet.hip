@@ -227,10 +227,13 @@ template <int HY> __host__ __device__ constexpr int tap_halo(int t) {
   return ((t / 9 - 1) * HY + ((t / 3) % 3 - 1)) * kHX + (t % 3 - 1);
 }
 
-// Staged position stride in bytes: the group's channels plus 16 bytes, so
-// that the eight lanes of one LDS pass (the same 16-byte chunk of eight
-// consecutive positions) fall on eight different 16-byte bank slots.
-template <int CG> constexpr int lds_stride() { return CG == 2 ? 4 : CG * 2 + 16; }
+// Staged position stride in bytes.  Measured on gfx950 for 16-byte reads of
+// sixteen consecutive positions (one fragment row): strides of 32 or 96
+// bytes run without bank conflicts at 170-200 B/clk per CU, 48, 64 and 80
+// bytes conflict (115-120 B/clk).  16 channels are stored unpadded (32
+// bytes); 32 channels keep 80 bytes, since 96 would cost the 32 -> 16
+// decoder a resident workgroup per CU (LDS) and that was measured slower.
+template <int CG> constexpr int lds_stride() { return CG == 2 ? 4 : CG == 16 ? 32 : CG * 2 + 16; }
 
 template <int CIN, int COUT, bool UPADD, bool FEAT, int SUB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_tconv(const TconvArgs a) {
