@@ -235,8 +235,13 @@ template <int HY> __host__ __device__ constexpr int tap_halo(int t) {
 // decoder a resident workgroup per CU (LDS) and that was measured slower.
 template <int CG> constexpr int lds_stride() { return CG == 2 ? 4 : CG == 16 ? 32 : CG * 2 + 16; }
 
+// Resident wavefronts per SIMD the compiler must allow (registers): the
+// 16 -> 16 decoder fits six without spills, 5-8 % faster than five; for the
+// feature encoder six were slower, for 16 -> 32 they spill
+template <int CIN, int COUT> constexpr int tconv_min_waves() { return CIN == 16 && COUT == 16 ? 6 : 2; }
+
 template <int CIN, int COUT, bool UPADD, bool FEAT, int SUB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_tconv(const TconvArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tconv_min_waves<CIN, COUT>()))) void k_tconv(const TconvArgs a) {
   if (solve_done(a.sc)) return;
   constexpr int kTY = Brick<SUB>::TY, kTZ = Brick<SUB>::TZ, kHY = Brick<SUB>::HY, kHZ = Brick<SUB>::HZ;
   constexpr int kHalo = Brick<SUB>::HALO, HY = kHY;
