@@ -192,18 +192,19 @@ struct TconvArgs {
   int nbx, nby, nb, per;   // bricks along x and y, in all, per XCD range
   const bf16_t* in;        // [n][CIN] (not FEAT)
   const bf16_t* in2;       // UPADD: [n/8][CIN], the coarser level
-  const float* r;          // FEAT: residual, float cells
+  const float* r;          // FEAT, head: residual, float cells
   const bf16_t* ell;       // FEAT: normalised log(1/rho)
-  const double* rr;        // FEAT: ||r||^2 over the unknowns
-  double nred;             // FEAT: number of unknowns
+  const double* rr;        // FEAT, head: ||r||^2 over the unknowns
+  double nred;             // FEAT, head: number of unknowns
   bf16_t* x0;              // FEAT: features out [n][2], or null
   const uint4* frag;       // A fragments (k_pack_tile)
   const float* bias;       // [COUT]
   bf16_t* out;             // [n][COUT], or null
   bf16_t* pooled;          // [n/8][COUT] (2 x 2 x 2 average), or null
-  float* proj;             // [n] head projection w5 . out, or null
+  float* z;                // head on this layer's output (16 channels): z = dinv (x0[.,0] + (b + w . out)), or null
   const float* wproj;      // [COUT] head weights (BF16 values)
-  const float* pbias;      // FEAT: head bias; proj = x0[.,0] + (b5 + w5 . out)
+  const float* pbias;      // head bias b
+  const float* dinv;       // head: FP32 D^-1 of the operator
   const SolveScalars* sc;
 };
 
@@ -235,13 +236,8 @@ template <int HY> __host__ __device__ constexpr int tap_halo(int t) {
 // decoder a resident workgroup per CU (LDS) and that was measured slower.
 template <int CG> constexpr int lds_stride() { return CG == 2 ? 4 : CG == 16 ? 32 : CG * 2 + 16; }
 
-// Resident wavefronts per SIMD the compiler must allow (registers): the
-// 16 -> 16 decoder fits six without spills, 5-8 % faster than five; for the
-// feature encoder six were slower, for 16 -> 32 they spill
-template <int CIN, int COUT> constexpr int tconv_min_waves() { return CIN == 16 && COUT == 16 ? 6 : 2; }
-
 template <int CIN, int COUT, bool UPADD, bool FEAT, int SUB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tconv_min_waves<CIN, COUT>()))) void k_tconv(const TconvArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_tconv(const TconvArgs a) {
   if (solve_done(a.sc)) return;
   constexpr int kTY = Brick<SUB>::TY, kTZ = Brick<SUB>::TZ, kHY = Brick<SUB>::HY, kHZ = Brick<SUB>::HZ;
   constexpr int kHalo = Brick<SUB>::HALO, HY = kHY;
@@ -273,10 +269,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tconv_min_w
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       bi[m][i] = a.bias[m * 16 + 4 * kq + i];
-      wp[m][i] = a.proj ? a.wproj[m * 16 + 4 * kq + i] : 0.f;
+      wp[m][i] = a.z ? a.wproj[m * 16 + 4 * kq + i] : 0.f;
     }
-  const float pb = FEAT && a.proj ? a.pbias[0] : 0.f;
-  const double rr = FEAT ? *a.rr : 0.0;
+  const float pb = a.z ? a.pbias[0] : 0.f;
+  const double rr = (FEAT || a.z) ? *a.rr : 0.0;
   const uint4* fr = a.frag + lane;
   Frag An[MT];
 #pragma unroll
@@ -407,6 +403,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tconv_min_w
   // its offset in the brick; acc accumulates over the channel groups
   int yw = 0, zw = 0, hb[4];
   f32x4 acc[MT][4];
+  long long hp = -1;       // head: output position of this lane, its residual and D^-1
+  float hr = 0.f, hd = 0.f;
   auto set_block = [&](int s) {
     yw = 2 * (wv & 1) + 4 * (s % SUB);
     zw = 2 * (wv >> 1) + 4 * (s / SUB);
@@ -520,7 +518,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tconv_min_w
             make_uint2(pack_bf2(v[0], v[1]), pack_bf2(v[2], v[3]));
     }
   }
-  if (a.proj) {
+  if (a.z) {
+    // the 1 x 1 x 1 head: x0[.,0] is the BF16 scaled residual formed exactly as
+    // the first encoder's staging forms it
+    const double ms = rr / a.nred;
+    const double inv = ms > 0 ? 1.0 / sqrt(ms) : 1.0;
+    // w . out of row j summed over the lane quarters; quarter kq then
+    // finishes row kq, so all 64 lanes form one output each
+    float tk = 0.f;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       float t = 0.f;
@@ -530,22 +535,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tconv_min_w
         for (int i = 0; i < 4; ++i) t += wp[m][i] * acc[m][j][i];
       t += __shfl_xor(t, 16);
       t += __shfl_xor(t, 32);
-      const int y = y0b + yw + (j & 1), z = z0b + zw + (j >> 1);
-      if (kq == 0 && x < W && y < H && z < D) {
-        const long long p = ((long long)z * H + y) * W + x;
-        if constexpr (FEAT) {
-          const float x00 = lo_bf(reinterpret_cast<const unsigned*>(lds)[hb[j]]);
-          a.proj[p] = x00 + (pb + t);
-        } else {
-          a.proj[p] = t;
-        }
-      }
+      if (kq == j) tk = t;
+    }
+    if (hp >= 0) {
+      const float x00 = __uint_as_float((unsigned)f2bf((float)((double)hr * inv)) << 16);
+      a.z[hp] = hd * ((x00 + pb) + tk);
     }
   }
   };
 
   if constexpr (SUB == 1) {
     set_block(0);
+    if (a.z) {
+      // the head's inputs at this lane's output position (row kq of the
+      // block), fetched before the staging so that their latency is hidden
+      const int x = x0b + n, y = y0b + yw + (kq & 1), z = z0b + zw + (kq >> 1);
+      if (x < W && y < H && z < D) {
+        hp = ((long long)z * H + y) * W + x;
+        hr = a.r[hp];
+        hd = a.dinv[hp];
+      }
+    }
     static_for<0, NG>([&](auto gg) {
       if constexpr (decltype(gg)::value > 0) __syncthreads();
       stage(gg);
@@ -744,25 +754,6 @@ __global__ void k_skip_poolT_mask(int D, int H, int W, const bf16_t* __restrict_
 }
 
 // ------------------------------------------------------------ head (1 x 1 x 1, 16 -> 1)
-// z = dinv * (h0 + u0): h0 = x0[.,0] + b6 from the first encoder's epilogue,
-// u0 = w6 . d0 from the finest decoder's; 4 cells per thread.
-__global__ __launch_bounds__(256) void k_head_out(long long nq, const float* __restrict__ h0,
-                                                  const float* __restrict__ u0, const float* __restrict__ dinv,
-                                                  float* __restrict__ z, const SolveScalars* __restrict__ sc) {
-  if (solve_done(sc)) return;
-  GRID_STRIDE(e, nq) {
-    const float4 h = reinterpret_cast<const float4*>(h0)[e];
-    const float4 u = reinterpret_cast<const float4*>(u0)[e];
-    const float4 d = reinterpret_cast<const float4*>(dinv)[e];
-    float4 o;
-    o.x = d.x * (h.x + u.x);
-    o.y = d.y * (h.y + u.y);
-    o.z = d.z * (h.z + u.z);
-    o.w = d.w * (h.w + u.w);
-    reinterpret_cast<float4*>(z)[e] = o;
-  }
-}
-
 // data gradient through the head into the finest decoder's pre-activation:
 // dd0[p][c] = bf16(w6[c] dy[p]) where d0[p][c] > 0, else 0;  dy = dinv * dz
 __global__ void k_head_dgrad(long long n, const float* __restrict__ dz, const float* __restrict__ dinv,
@@ -912,7 +903,6 @@ struct UNet {
   DevBuf x0, ell;
   DevBuf a[kMaxLevels], p[kMaxLevels], d[kMaxLevels];            // activations (BF16)
   DevBuf skip[kMaxLevels], dd[kMaxLevels], da[kMaxLevels], dp[kMaxLevels];  // gradients (BF16)
-  DevBuf h0, u0, zero16;                             // FP32 head terms: x0[.,0] + b, w . d0; 16 zeros
   DevBuf zt, Az, dz;                                 // FP32 cells
   DevBuf wpart, cpart, hpart;                        // FP32 partials of the weight gradients
   DevBuf scal;                                       // double: rr, a, c
@@ -1068,8 +1058,9 @@ void skip_poolT_mask(int C, int level, const UNet& u, const bf16_t* skip, const 
 
 // forward on the operator's grid; rr / nred give the residual scale.  keep:
 // store every activation (training, export); otherwise only what a later
-// layer reads: the pooled encoder outputs, the skips, the decoder outputs
-// below level 1 and the two head partials.
+// layer reads: the pooled encoder outputs, the skips and the decoder outputs
+// of the coarser levels.  The finest decoder's epilogue applies the head and
+// writes z.
 nfa_status forward(UNet& u, Poisson& op, const float* r, float* z, const double* rr, double nred,
                    const SolveScalars* sc, bool keep, hipStream_t s) {
   Grid& g = *op.g;
@@ -1084,9 +1075,7 @@ nfa_status forward(UNet& u, Poisson& op, const float* r, float* z, const double*
   const float* P = u.params.as<float>();
   TconvArgs a{};
   a.sc = sc;
-  a.wproj = u.head_w.as<float>();
-  // first encoder: features formed while staging, pooled output, and the
-  // head's constant part x0[.,0] + b (a projection on zero weights)
+  // first encoder: features formed while staging, pooled output
   u.dims(0, a.D, a.H, a.W);
   a.r = r;
   a.ell = B16(u.ell);
@@ -1097,16 +1086,9 @@ nfa_status forward(UNet& u, Poisson& op, const float* r, float* z, const double*
   a.bias = P + u.off_b[0];
   a.out = B16(u.a[0]);
   a.pooled = B16(u.p[0]);
-  a.proj = u.h0.as<float>();
-  a.wproj = u.zero16.as<float>();
-  a.pbias = P + u.off_b[u.Hd()];
   tconv_t<2, 16, false, true, 2>(a, s);
-  a.wproj = u.head_w.as<float>();
-  a.r = nullptr;
   a.ell = nullptr;
   a.x0 = nullptr;
-  a.proj = nullptr;
-  a.pbias = nullptr;
   nfa_status e = NFA_OK;
   for (int l = 1; l < L && e == NFA_OK; ++l) {
     u.dims(l, a.D, a.H, a.W);
@@ -1132,12 +1114,15 @@ nfa_status forward(UNet& u, Poisson& op, const float* r, float* z, const double*
     a.frag = reinterpret_cast<const uint4*>(u.frag_t[u.Dl(l)].p);
     a.bias = P + u.off_b[u.Dl(l)];
     a.out = (l > 0 || keep) ? B16(u.d[l]) : nullptr;
-    a.proj = l == 0 ? u.u0.as<float>() : nullptr;   // the head on d0, fused
+    if (l == 0) {   // the head on d0, fused into its epilogue
+      a.z = z;
+      a.wproj = u.head_w.as<float>();
+      a.pbias = P + u.off_b[u.Hd()];
+      a.dinv = op.dinv32.as<float>();
+    }
     e = tconv(u.cin[u.Dl(l)], u.cout[u.Dl(l)], true, a, s);
   }
   if (e != NFA_OK) return e;
-  k_head_out<<<eblocks(u.npos[0] / 4), kBlock, 0, s>>>(u.npos[0] / 4, u.h0.as<float>(), u.u0.as<float>(),
-                                                       op.dinv32.as<float>(), z, sc);
   NFA_CHECK_LAUNCH();
   return NFA_OK;
 }
@@ -1310,9 +1295,6 @@ hipError_t unet_buffers(UNet& u, Carver& c) {
   TAKE(wpart, 27LL * kWgradBlocks * 64 * 64 * 4);
   TAKE(cpart, (long long)kWgradBlocks * 64 * 4);
   TAKE(hpart, (long long)kHeadBlocks * 17 * 4);
-  TAKE(h0, n0 * 4);
-  TAKE(u0, n0 * 4);
-  TAKE(zero16, 16 * 4);
   TAKE(scal, 8 * 8);
 #undef TAKE
   return hipSuccess;
@@ -1367,7 +1349,6 @@ extern "C" nfa_status nfa_unet_create(int nx, int ny, int nz, int levels, int se
     delete u;
     return st;
   }
-  if ((e = hipMemset(u->zero16.p, 0, 16 * 4)) != hipSuccess) return bad(e);
   if ((e = hipMemset(u->adam_m.p, 0, u->nparam * 4)) != hipSuccess) return bad(e);
   if ((e = hipMemset(u->adam_v.p, 0, u->nparam * 4)) != hipSuccess) return bad(e);
   if ((e = hipMemset(u->grads.p, 0, u->nparam * 4)) != hipSuccess) return bad(e);
