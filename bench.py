@@ -231,7 +231,7 @@ def main():
         unet_flop += 2 * nt * ci * co * (wl.ncells // 8 ** lv)
     meta = {"f32": ("hbm", 36, "k_cg_a<float, 4, 1, false>"), "f32_flex": ("hbm", 40, "k_cg_a<float, 4, 1, true>"),
             "f64": ("hbm", 72, f"k_cg_a<double, 2, {wx}, false>"),
-            "unet": ("mfma", None, "network application (k_tconv x6, k_head_out)")}
+            "unet": ("mfma", None, "network application (k_tconv x6; the head in the last one)")}
     entries = {}
     for k, ks in kinds.items():
         if ks["launches"] == 0:

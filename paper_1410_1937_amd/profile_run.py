@@ -3,8 +3,9 @@
 Sets up the 512 x 256 x 192 breaking-wave projection problem
 (fixtures.c3), then runs a fixed number of mixed-precision and FP64
 Jacobi-PCG iterations (tolerance unreachable, so every iteration runs both
-sweeps), and finally a plain device-to-device copy of known size whose
-counter readings calibrate the FETCH_SIZE / WRITE_SIZE counters to bytes.
+sweeps), and finally three plain device-to-device copies of known size (the library's
+k_stream_copy, 1 GiB each by default) whose counter readings calibrate the
+FETCH_SIZE / WRITE_SIZE counters to bytes.
 With --mg N it runs N mixed-precision iterations preconditioned by the
 multigrid V-cycle (hierarchy set-up included).  With --unet L it also runs --unet-reps forward passes of an L-level learned
 preconditioner on the same grid (the committed weights for L = 3).  With
@@ -14,7 +15,9 @@ it computes the signed distance of an L-times subdivided icosphere (the
 workload's sphere) at the grid nodes three times.  Each phase prints a line
 when it ends.
 
-    rocprofv3 --pmc FETCH_SIZE -d OUT -- python3 -m paper_1410_1937_amd.profile_run --iters 8
+    rocprofv3 --pmc FETCH_SIZE -d F -o run -- python3 -m paper_1410_1937_amd.profile_run --iters 8
+    rocprofv3 --pmc WRITE_SIZE -d W -o run -- python3 -m paper_1410_1937_amd.profile_run --iters 8
+    python3 -m paper_1410_1937_amd.profile_summary traffic F/run_results.db W/run_results.db
     rocprofv3 --kernel-trace --stats -d OUT -- python3 -m paper_1410_1937_amd.profile_run --iters 0 --unet 5
     rocprofv3 --kernel-trace --stats -d OUT -- python3 -m paper_1410_1937_amd.profile_run --iters 0 --vof 6
 """
@@ -27,7 +30,7 @@ import sys
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--iters", type=int, default=8, help="iterations per precision")
-    ap.add_argument("--copy-mib", type=int, default=256, help="size of the calibration copy")
+    ap.add_argument("--copy-mib", type=int, default=1024, help="size of the calibration copy (4x the 256 MiB Infinity Cache by default)")
     ap.add_argument("--mg", type=int, default=0, help="mixed-precision multigrid-preconditioned iterations")
     ap.add_argument("--unet", type=int, default=0, help="levels of the learned preconditioner to run (0: none)")
     ap.add_argument("--unet-reps", type=int, default=5)
@@ -89,9 +92,9 @@ def main(argv=None):
     src = torch.ones(n, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     for _ in range(3):
-        dst.copy_(src)
+        nfa.stream_copy(dst, src)     # k_stream_copy, one dispatch of known size
     torch.cuda.synchronize()
-    print(f"[profile_run] copy: 3 x {args.copy_mib} MiB read + written", flush=True)
+    print(f"[profile_run] copy: 3 x {args.copy_mib} MiB read + written (k_stream_copy)", flush=True)
     return 0
 
 
