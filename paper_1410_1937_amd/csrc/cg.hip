@@ -6,11 +6,14 @@
 //             x += alpha_prev p_old           (update deferred from the
 //                                              previous iteration)
 //             partials p.q (and p.r for flexible CG)
-//   sweep B:  r -= alpha q,  z = D^-1 r       partials r.z, r.r
-//             (flexible CG: r -= alpha q, partial r.r; the preconditioner
-//              runs as its own pass)
-// so the direction update and the x update cost no extra pass: 112 B/cell per
-// iteration in FP64 (72 + 40), 56 B/cell in FP32, against 128 / 64 B for the
+//   sweep B:  z -= alpha D^-1 q               partials r.z, r.r
+//             (Jacobi-PCG carries the preconditioned residual z = D^-1 r as
+//             its state: r = z / D^-1 where D^-1 > 0 and 0 elsewhere is
+//             formed for the partials only, so r is neither read nor written;
+//             flexible CG: r -= alpha q, partial r.r, and the preconditioner
+//             runs as its own pass)
+// so the direction update and the x update cost no extra pass: 104 B/cell per
+// iteration in FP64 (72 + 32), 52 B/cell in FP32, against 128 / 64 B for the
 // textbook three-pass form.  p is double-buffered (the neighbours of a cell
 // must see the old direction).
 //
@@ -205,13 +208,14 @@ __global__ __launch_bounds__(AX* kTileWaves) void k_cg_a(
 
 constexpr int kCgbBlocks = 2048;
 
-// r -= alpha q; (PCG) z = dinv r, partials r.z, r.r; (FCG) partial r.r
-template <class T, int V, bool FLEX>
-__global__ __launch_bounds__(kBlock) void k_cg_b(long long nvec, T* __restrict__ r,
-                                                 const T* __restrict__ q,
-                                                 const T* __restrict__ dinv, T* __restrict__ z,
-                                                 double* __restrict__ partials,
-                                                 const SolveScalars* __restrict__ sc) {
+// Jacobi-PCG sweep B: z -= alpha (D^-1 q); partials r.z = sum z^2 / D^-1 and
+// r.r = sum (z / D^-1)^2 over the cells with D^-1 > 0 (slaves and inactive
+// cells have D^-1 = 0: their z is left as it is and overwritten by the merge
+// copy that follows), r formed in FP64
+template <class T, int V>
+__global__ __launch_bounds__(kBlock) void k_cg_bz(long long nvec, T* __restrict__ z, const T* __restrict__ q,
+                                                  const T* __restrict__ dinv, double* __restrict__ partials,
+                                                  const SolveScalars* __restrict__ sc) {
   if (solve_done(sc)) return;
   __shared__ double lds[2 * kBlock / 64];
   const T alpha = (T)sc->alpha;
@@ -219,35 +223,51 @@ __global__ __launch_bounds__(kBlock) void k_cg_b(long long nvec, T* __restrict__
   for (long long iv = blockIdx.x * (long long)blockDim.x + threadIdx.x; iv < nvec;
        iv += (long long)gridDim.x * blockDim.x) {
     const long long c = iv * V;
+    Pack<T, V> zv = ld_stream<StreamHints<T>::b_load, T, V>(z + c);
+    const Pack<T, V> qv = ld_stream<StreamHints<T>::b_load, T, V>(q + c);
+    const Pack<T, V> dv = ld_stream<StreamHints<T>::b_load, T, V>(dinv + c);
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      zv.v[e] = zv.v[e] - alpha * (dv.v[e] * qv.v[e]);
+      if (dv.v[e] > T(0)) {
+        const double rd = (double)zv.v[e] / (double)dv.v[e];
+        rz += rd * (double)zv.v[e];
+        rr += rd * rd;
+      }
+    }
+    st_stream<StreamHints<T>::b_store, T, V>(z + c, zv);
+  }
+  const double t0 = block_sum(rz, lds);
+  const double t1 = block_sum(rr, lds + kBlock / 64);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = t0;
+    partials[kMaxPartials + blockIdx.x] = t1;
+  }
+}
+
+// flexible CG sweep B: r -= alpha q; partial r.r (the preconditioner runs as
+// its own pass)
+template <class T, int V>
+__global__ __launch_bounds__(kBlock) void k_cg_b(long long nvec, T* __restrict__ r, const T* __restrict__ q,
+                                                 double* __restrict__ partials, const SolveScalars* __restrict__ sc) {
+  if (solve_done(sc)) return;
+  __shared__ double lds[kBlock / 64];
+  const T alpha = (T)sc->alpha;
+  double rr = 0.0;
+  for (long long iv = blockIdx.x * (long long)blockDim.x + threadIdx.x; iv < nvec;
+       iv += (long long)gridDim.x * blockDim.x) {
+    const long long c = iv * V;
     Pack<T, V> rv = ld_stream<StreamHints<T>::b_load, T, V>(r + c);
     const Pack<T, V> qv = ld_stream<StreamHints<T>::b_load, T, V>(q + c);
 #pragma unroll
-    for (int e = 0; e < V; ++e) rv.v[e] = rv.v[e] - alpha * qv.v[e];
+    for (int e = 0; e < V; ++e) {
+      rv.v[e] = rv.v[e] - alpha * qv.v[e];
+      rr += (double)rv.v[e] * (double)rv.v[e];
+    }
     st_stream<StreamHints<T>::b_store, T, V>(r + c, rv);
-    if (!FLEX) {
-      const Pack<T, V> dv = ld_stream<StreamHints<T>::b_load, T, V>(dinv + c);
-      Pack<T, V> zv;
-#pragma unroll
-      for (int e = 0; e < V; ++e) {
-        zv.v[e] = dv.v[e] * rv.v[e];
-        rz += (double)rv.v[e] * (double)zv.v[e];
-      }
-      st_stream<StreamHints<T>::b_store, T, V>(z + c, zv);
-    }
-#pragma unroll
-    for (int e = 0; e < V; ++e) rr += (double)rv.v[e] * (double)rv.v[e];
   }
-  if (FLEX) {
-    const double t = block_sum(rr, lds);
-    if (threadIdx.x == 0) partials[blockIdx.x] = t;
-  } else {
-    const double t0 = block_sum(rz, lds);
-    const double t1 = block_sum(rr, lds + kBlock / 64);
-    if (threadIdx.x == 0) {
-      partials[blockIdx.x] = t0;
-      partials[kMaxPartials + blockIdx.x] = t1;
-    }
-  }
+  const double t = block_sum(rr, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
 // x += alpha_pend p (the x update left pending when the iteration stopped)
@@ -353,14 +373,16 @@ int launch_cg_b(const Grid& g, T* r, const T* q, const T* dinv, T* z, double* pa
   constexpr int VW = tile::vec_width<T>();
   const long long nv = vec ? g.n / VW : g.n;
   const int nb = vblocks(nv);
-#define CGB(VV, FF) k_cg_b<T, VV, FF><<<nb, kBlock, 0, s>>>(nv, r, q, dinv, z, partials, sc)
+#define CGB(VV) k_cg_b<T, VV><<<nb, kBlock, 0, s>>>(nv, r, q, partials, sc)
+#define CGBZ(VV) k_cg_bz<T, VV><<<nb, kBlock, 0, s>>>(nv, z, q, dinv, partials, sc)
   if (vec) {
-    if (flex) CGB(VW, true);
-    else CGB(VW, false);
+    if (flex) CGB(VW);
+    else CGBZ(VW);
   } else {
-    if (flex) CGB(1, true);
-    else CGB(1, false);
+    if (flex) CGB(1);
+    else CGBZ(1);
   }
+#undef CGBZ
 #undef CGB
   return nb;
 }
