@@ -107,6 +107,23 @@ nfa_status nfa_unet_grad(nfa_unet u, nfa_poisson op, const float* r, double eAe,
 nfa_status nfa_unet_train_step(nfa_unet u, nfa_poisson op, const float* r, double eAe, float lr,
                                int t, double* loss, nfa_stream s);
 
+/* Gradients of every parameter for a loss of the caller's: dz (DEVICE, FP32,
+ * one value per cell in the grid's layout) is dL/dz at the output z of the
+ * last nfa_unet_forward, which must have run with keep = 1 on this operator
+ * (its D^-1 scales the output) with the current parameters; otherwise
+ * NFA_ERR_INVALID.  The gradients replace the previous ones (read them with
+ * nfa_unet_get_grads or from the array bound by nfa_unet_bind).  The same
+ * chain rule as nfa_unet_grad, which is forward + the step loss's dL/dz +
+ * this call.  ASYNC. */
+nfa_status nfa_unet_backward(nfa_unet u, nfa_poisson op, const float* dz, nfa_stream s);
+
+/* One Adam step on the current gradients g:  m = b1 m + (1 - b1) g,
+ * v = b2 v + (1 - b2) g^2,  w -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t))
+ * + eps), elementwise in FP32, then the packed BF16 weights are rebuilt.
+ * t >= 1 counts steps from 1; 0 <= b1, b2 < 1; eps > 0.  nfa_unet_train_step
+ * uses b1 = 0.9, b2 = 0.999, eps = 1e-8.  ASYNC. */
+nfa_status nfa_unet_adam_step(nfa_unet u, float lr, float b1, float b2, float eps, int t, nfa_stream s);
+
 /* Activations of the last forward with keep = 1 or training step (DEVICE
  * destination): BF16 raw uint16,
  * channels-last; level l has n_l = cells / 8^l positions and c_l = 16, 32,
@@ -115,9 +132,10 @@ nfa_status nfa_unet_train_step(nfa_unet u, nfa_poisson op, const float* r, doubl
 #define NFA_UNET_A 16  /* + l: encoder a_l, n_l x c_l */
 #define NFA_UNET_P 32  /* + l: pool(a_l), n_{l+1} x c_l */
 #define NFA_UNET_D 48  /* + l: decoder d_l (d_{L-1}: bottleneck), n_l x c_{l-1} (d_0: n_0 x 16) */
-/* Gradients of the last nfa_unet_grad / nfa_unet_train_step (the chain rule
- * through the layers above, in the same order): */
-#define NFA_UNET_DZ 64     /* dL/dz, FP32, n_0 */
+/* Gradients of the last nfa_unet_grad, nfa_unet_train_step or
+ * nfa_unet_backward (the chain rule through the layers above, in the same
+ * order): */
+#define NFA_UNET_DZ 64     /* dL/dz of the step loss, FP32, n_0 (nfa_unet_grad / nfa_unet_train_step only) */
 #define NFA_UNET_DD 80     /* + l: at decoder l's pre-activation (l = L-1: the bottleneck), shaped as d_l */
 #define NFA_UNET_SKIP 96   /* + l, l <= L-2: at decoder l's input up(d_{l+1}) + a_l, n_l x c_l */
 #define NFA_UNET_DA 112    /* + l: at encoder l's pre-activation, n_l x c_l */

@@ -908,6 +908,12 @@ struct UNet {
   DevBuf scal;                                       // double: rr, a, c
   const void* ell_op = nullptr;
   int ell_version = -1;
+  // what the activations of the last forward belong to (nfa_unet_backward)
+  long long param_version = 0;        // counts parameter changes (pack_all)
+  const void* fwd_op = nullptr;
+  int fwd_version = -1;
+  long long fwd_params = -1;
+  bool fwd_kept = false;
   int E(int l) const { return l; }
   int B() const { return L; }
   int Dl(int l) const { return L + 1 + (L - 2 - l); }
@@ -955,6 +961,7 @@ inline int eblocks(long long n) { return blocks_for(n, kBlock, 8192); }
 inline long long tile_frag_bytes(int cin, int cout) { return (long long)((27 * cin + 31) / 32) * (cout / 16) * 64 * 16; }
 
 nfa_status pack_all(UNet& u, hipStream_t s) {
+  ++u.param_version;
   const float* P = u.params.as<float>();
   for (int l = 0; l < u.nlayers - 1; ++l) {
     const int cin = u.cin[l], cout = u.cout[l];
@@ -1073,6 +1080,10 @@ nfa_status forward(UNet& u, Poisson& op, const float* r, float* z, const double*
   }
   const int L = u.L;
   const float* P = u.params.as<float>();
+  u.fwd_op = &op;
+  u.fwd_version = op.version;
+  u.fwd_params = u.param_version;
+  u.fwd_kept = keep;
   TconvArgs a{};
   a.sc = sc;
   // first encoder: features formed while staging, pooled output
@@ -1127,8 +1138,8 @@ nfa_status forward(UNet& u, Poisson& op, const float* r, float* z, const double*
   return NFA_OK;
 }
 
-// gradients of all parameters from dL/dz (in u.dz), after a forward with keep
-nfa_status backward(UNet& u, Poisson& op, hipStream_t s) {
+// gradients of all parameters from dL/dz, after a forward with keep
+nfa_status backward(UNet& u, Poisson& op, const float* dz, hipStream_t s) {
   const int L = u.L;
   int D, H, W;
   u.dims(0, D, H, W);
@@ -1137,9 +1148,9 @@ nfa_status backward(UNet& u, Poisson& op, hipStream_t s) {
   const long long n0 = u.npos[0];
   // head (1 x 1 x 1) on d0: its gradient into d0's pre-activation; weights and
   // bias summed over positions against d0
-  k_head_dgrad<<<eblocks(n0), kBlock, 0, s>>>(n0, u.dz.as<float>(), dinv, u.head_w.as<float>(), B16(u.d[0]),
+  k_head_dgrad<<<eblocks(n0), kBlock, 0, s>>>(n0, dz, dinv, u.head_w.as<float>(), B16(u.d[0]),
                                               B16(u.dd[0]));
-  k_head_wgrad<<<kHeadBlocks, 256, 0, s>>>(n0, u.dz.as<float>(), dinv, B16(u.d[0]), u.hpart.as<float>());
+  k_head_wgrad<<<kHeadBlocks, 256, 0, s>>>(n0, dz, dinv, B16(u.d[0]), u.hpart.as<float>());
   k_head_wgrad_reduce<<<1, 64, 0, s>>>(u.hpart.as<float>(), kHeadBlocks, G + u.off_w[u.Hd()],
                                        G + u.off_b[u.Hd()]);
   // finest decoder: weights against up(d1) + a0, data gradient into skip[0]
@@ -1203,7 +1214,7 @@ nfa_status grad_step(UNet& u, Poisson& op, const float* r, double eAe, double* l
   launch_sum_partials(parts, nb, 1, scal + 2, s);
   k_loss_grad<<<eblocks(n), kBlock, 0, s>>>(n, r, u.Az.as<float>(), scal + 1, eAe, u.dz.as<float>());
   NFA_CHECK_LAUNCH();
-  if ((e = backward(u, op, s)) != NFA_OK) return e;
+  if ((e = backward(u, op, u.dz.as<float>(), s)) != NFA_OK) return e;
   double h[3];
   NFA_HIP(hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, s));
   NFA_HIP(hipStreamSynchronize(s));
@@ -1421,20 +1432,41 @@ extern "C" nfa_status nfa_unet_grad(nfa_unet u, nfa_poisson op, const float* r, 
   return grad_step(*u, *op, r, eAe, loss, S(s));
 }
 
+namespace nfa {
+namespace {
+nfa_status adam_step(UNet& u, float lr, float b1, float b2, float eps, int t, hipStream_t st) {
+  const float bc1 = 1.0f - std::pow(b1, (float)t), bc2 = 1.0f - std::pow(b2, (float)t);
+  k_adam<<<eblocks(u.nparam), kBlock, 0, st>>>(u.nparam, u.params.as<float>(), u.grads.as<float>(),
+                                               u.adam_m.as<float>(), u.adam_v.as<float>(), lr, b1, b2, eps, bc1, bc2);
+  NFA_CHECK_LAUNCH();
+  return pack_all(u, st);
+}
+}  // namespace
+}  // namespace nfa
+
+extern "C" nfa_status nfa_unet_backward(nfa_unet u, nfa_poisson op, const float* dz, nfa_stream s) {
+  if (!u || !op || !dz) return fail(NFA_ERR_INVALID, "nfa_unet_backward: NULL argument");
+  if (const nfa_status e = require_assembled(*op, "nfa_unet_backward")) return e;
+  if (!u->fwd_kept || u->fwd_op != (const void*)op || u->fwd_version != op->version ||
+      u->fwd_params != u->param_version)
+    return fail(NFA_ERR_INVALID,
+                "nfa_unet_backward: needs a forward with keep = 1 on this operator, with the current parameters");
+  return backward(*u, *op, dz, S(s));
+}
+
+extern "C" nfa_status nfa_unet_adam_step(nfa_unet u, float lr, float b1, float b2, float eps, int t, nfa_stream s) {
+  if (!u || t < 1 || !(b1 >= 0.f && b1 < 1.f) || !(b2 >= 0.f && b2 < 1.f) || !(eps > 0.f))
+    return fail(NFA_ERR_INVALID, "nfa_unet_adam_step: bad argument");
+  return adam_step(*u, lr, b1, b2, eps, t, S(s));
+}
+
 extern "C" nfa_status nfa_unet_train_step(nfa_unet u, nfa_poisson op, const float* r, double eAe, float lr,
                                           int t, double* loss, nfa_stream s) {
   if (!u || !op || !r || t < 1) return fail(NFA_ERR_INVALID, "nfa_unet_train_step: bad argument");
   const hipStream_t st = S(s);
   nfa_status e = grad_step(*u, *op, r, eAe, loss, st);
   if (e != NFA_OK) return e;
-  const float b1 = 0.9f, b2 = 0.999f;
-  const float bc1 = 1.0f - std::pow(b1, (float)t), bc2 = 1.0f - std::pow(b2, (float)t);
-  k_adam<<<eblocks(u->nparam), kBlock, 0, st>>>(u->nparam, u->params.as<float>(), u->grads.as<float>(),
-                                                u->adam_m.as<float>(), u->adam_v.as<float>(), lr, b1, b2, 1e-8f,
-                                                bc1, bc2);
-  NFA_CHECK_LAUNCH();
-  e = pack_all(*u, st);
-  if (e != NFA_OK) return e;
+  if ((e = adam_step(*u, lr, 0.9f, 0.999f, 1e-8f, t, st)) != NFA_OK) return e;
   NFA_HIP(hipStreamSynchronize(st));
   return NFA_OK;
 }

@@ -124,6 +124,9 @@ _sig("nfa_unet_forward", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, 
 _sig("nfa_unet_grad", c_int, [c_void_p, c_void_p, c_void_p, c_double, ctypes.POINTER(c_double), c_void_p])
 _sig("nfa_unet_train_step", c_int, [c_void_p, c_void_p, c_void_p, c_double, ctypes.c_float, c_int,
                                     ctypes.POINTER(c_double), c_void_p])
+_sig("nfa_unet_backward", c_int, [c_void_p, c_void_p, c_void_p, c_void_p])
+_sig("nfa_unet_adam_step", c_int, [c_void_p, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, c_int,
+                                   c_void_p])
 _sig("nfa_unet_export", c_int, [c_void_p, c_int, c_void_p, c_void_p])
 _sig("nfa_unet_destroy", None, [c_void_p])
 _sig("nfa_poisson_profile_read", c_int, [c_void_p, c_int, ctypes.POINTER(KernelStats)])
@@ -712,6 +715,17 @@ class UNet:
         _check(lib.nfa_unet_train_step(self.h, op.h, _dev(r, torch.float32, self.shape, "r"), float(eAe),
                                        float(lr), int(t), ctypes.byref(loss), _stream()), "nfa_unet_train_step")
         return loss.value
+
+    def backward(self, op, dz):
+        """Gradients for dL/dz = dz (FP32 cells) at the output of the last
+        forward with keep=True on `op` (nfa_unet_backward)."""
+        _check(lib.nfa_unet_backward(self.h, op.h, _dev(dz, torch.float32, self.shape, "dz"), _stream()),
+               "nfa_unet_backward")
+
+    def adam_step(self, lr, t, b1=0.9, b2=0.999, eps=1e-8):
+        """One Adam step on the current gradients (nfa_unet_adam_step)."""
+        _check(lib.nfa_unet_adam_step(self.h, float(lr), float(b1), float(b2), float(eps), int(t), _stream()),
+               "nfa_unet_adam_step")
 
     def export(self, what):
         """Activations 'x0', 'a<l>', 'p<l>', 'd<l>' of the last forward with keep,

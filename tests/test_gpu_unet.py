@@ -183,6 +183,49 @@ def test_backward_stages_and_weight_gradients_one_layer_at_a_time():
     assert abs(gb[0] - dy.sum()) <= 1e-4 * np.abs(dy).sum()
 
 
+def test_backward_and_adam_step_compose_to_the_training_step():
+    """nfa_unet_backward on the step loss's dL/dz after a forward with keep
+    gives nfa_unet_grad's gradients bit for bit, and nfa_unet_adam_step after
+    it nfa_unet_train_step's parameters; backward is refused after a forward
+    without keep; for a loss of the caller's, L = |z|^2 / 2 (dL/dz = z), the
+    head bias gradient is sum D^-1 z (z = D^-1 (x0 + b + w . d0))."""
+    from paper_1410_1937_amd import nfa
+    wl = fx.small(7, 32, 16, 12, body="sphere")
+    og, ob, oop, ob_rhs = oracle_for(wl)
+    gg, gop = gpu_for(wl)
+    rng = np.random.default_rng(17)
+    params = ou.init_params(19, zero_last=False)
+    flat = nfa.UNet.flatten([(w.astype(np.float32), (rng.standard_normal(b.shape) * 0.05).astype(np.float32))
+                             for w, b in params])
+    r = (ob_rhs * ob.reduced).astype(np.float32)
+    rt = torch.as_tensor(r, device="cuda")
+    e = solvers.pcg(oop, r.astype(np.float64), tol=1e-12).x
+    eAe = float(np.sum(e * r))
+    a, b = nfa.UNet(32, 16, 12, seed=3), nfa.UNet(32, 16, 12, seed=3)
+    a.set_params(flat)
+    b.set_params(flat)
+    a.grad(gop, rt, eAe)
+    g1 = a.get_grads()
+    dz = a.export("dz").clone()
+    b.forward(gop, rt, keep=True)
+    b.backward(gop, dz)
+    assert np.array_equal(b.get_grads(), g1)
+    b.forward(gop, rt)
+    with pytest.raises(nfa.NFAError):
+        b.backward(gop, dz)
+    a.train_step(gop, rt, eAe, 1e-3, 1)
+    b.grad(gop, rt, eAe)
+    b.adam_step(1e-3, 1)
+    assert np.array_equal(b.get_params(), a.get_params())
+    z = b.forward(gop, rt, keep=True)
+    b.backward(gop, z.contiguous())
+    gb = b.unflatten(b.get_grads())[-1][1]
+    zz = host(z).astype(np.float64)
+    dinv = host(gop.export("dinv32")).astype(np.float64)
+    ref = float(np.sum(dinv * zz))
+    assert abs(float(gb[0]) - ref) <= 1e-4 * float(np.sum(np.abs(dinv * zz)))
+
+
 @pytest.mark.parametrize("levels", [4, 5])
 def test_deeper_network_forward_and_gradients(levels):
     from paper_1410_1937_amd import nfa
