@@ -23,6 +23,9 @@ pairs (k = 0, 16, 64, 256), trained against untrained.
 
     python -m paper_1410_1937_amd.train_unet --levels 3 --max-steps 3000 \
         --out paper_1410_1937_amd/weights/unet_l3_c4
+
+Besides the weights it writes <out>.state.npz (parameters, Adam moments and the
+step count, arrays only), from which --resume continues training.
 """
 from __future__ import annotations
 
@@ -233,6 +236,9 @@ def main(argv=None):
     ap.add_argument("--levels", type=int, default=3)
     ap.add_argument("--eval-steps", default="160-199", help="held-out steps to evaluate (a-b, or empty)")
     ap.add_argument("--init", default=None, help="start from these weights (.npy)")
+    ap.add_argument("--resume", default=None,
+                    help="continue from a checkpoint written by an earlier run (<out>.state.npz: parameters, Adam "
+                         "moments and step count; the learning-rate schedule restarts over the new budget)")
     ap.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "weights", "unet"))
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
@@ -253,10 +259,15 @@ def main(argv=None):
                                       seq.smooth_field, seed=100 + q))
     t_data = time.time() - t0
     net = nfa.UNet(nx, ny, nz, seed=args.seed, levels=args.levels)
+    step, hist = 0, []
     if args.init:
         net.set_params(np.load(args.init))
+    if args.resume:
+        with np.load(args.resume) as ck:       # plain arrays, no pickled objects
+            net.load_state({k: ck[k] for k in ("params", "adam_m", "adam_v")})
+            step = int(ck["step"])
+        log(f"[train] resumed from {args.resume} at step {step}")
     rng = np.random.default_rng(args.seed)
-    step, hist = 0, []
     t1 = time.time()
     per_round = args.minutes / max(1, args.rounds)
     for rnd in range(args.rounds):
@@ -271,6 +282,7 @@ def main(argv=None):
     params = net.get_params()
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     np.save(args.out + ".npy", params)
+    np.savez(args.out + ".state.npz", step=np.int64(step), **net.state())
     steps = []
     if args.eval_steps:
         a_, b_ = (int(v) for v in args.eval_steps.split("-"))
