@@ -133,6 +133,7 @@ struct Grid {
 struct SolveScalars {
   double rz, pq, rr, bb, alpha, beta, tol2, pr, zq, rr_outer;
   double alpha_pend; // x += alpha_pend p still owed by the fused sweep
+  double rz_prev;    // r.z before the last update: the denominator of beta
   double ratio;      // stagnation threshold (mean reduction per iteration)
   int iter, done, breakdown, stalled, max_iter, window;
 };

@@ -147,8 +147,11 @@ def test_mixed_solve_meets_fp64_tolerance(case):
     err64 = rel_l2(host(x64), xr)
     print(f"[{name}] mixed: {res.iterations} its ({r64.iterations} FP64), {res.outer} FP64 residuals, "
           f"rel L2 err {err:.2e} (FP64 at the same tol: {err64:.2e})")
-    # the FP32 recurrence loses orthogonality sooner than FP64 on this operator
-    assert res.iterations <= 2.5 * r64.iterations + 10
+    # the FP32 recursion with its residual replaced every 10x continues as CG
+    # (the next direction keeps the recursion's beta with the replaced r.z on
+    # top), so it needs about FP64's iterations; 1.3-1.6x when beta was taken
+    # against the last r.z instead
+    assert res.iterations <= 1.15 * r64.iterations + 10
     assert err <= 1e-5
 
 
