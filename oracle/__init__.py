@@ -14,10 +14,12 @@ Modules
               its group Jacobi diagonal, right-hand side, projection and
               divergence (eqs. density, pois, poisson1, integral2, runge1,
               diverge; Density Smoothing)
-    solvers   Jacobi-preconditioned CG with true-residual restarts, flexible
-              CG with the stagnation fallback, the FP64 true residual.  There
-              is no mixed-precision solver here: a mixed-precision GPU result
-              is judged by this module's FP64 true residual of its solution
+    solvers   Jacobi-preconditioned CG with true-residual restarts, the
+              same CG with residual replacement (the continuation rule of the
+              GPU's mixed-precision solve, in FP64), flexible CG with the
+              stagnation fallback, the FP64 true residual.  There is no FP32
+              solver here: a mixed-precision GPU result is judged by this
+              module's FP64 true residual of its solution
     unet      the learned preconditioner: 3-D convolutions, pooling,
               upsampling, forward/backward, step loss and Adam, in FP64 on
               BF16-rounded storage points

@@ -12,6 +12,13 @@ Stopping: recursive ||r||/||b'|| <= tol, then the true residual b' - A'x is
 recomputed; if it is above tol the iteration restarts from x (at most three
 times).  The reported relative residual is always the true one.
 
+Residual replacement (the scheme the GPU's mixed-precision solve runs, here
+in FP64): whenever the recursive residual has fallen by `drop` since the last
+replacement, it is replaced by the true residual b' - A'x and CG goes on with
+the same direction; the next direction's beta divides the replaced residual's
+r.z by the r.z the recursion's own beta divides by, so in exact arithmetic
+the iteration is CG's.
+
 Flexible CG follows Notay's truncated FCG(m): the new direction is the
 preconditioned residual A'-orthogonalised against the last m directions, and
 the step is alpha = (p.r)/(p.q).  A stagnation monitor switches once to
@@ -96,6 +103,50 @@ def pcg(op, b, x0=None, tol=1e-10, maxit=100000, precond="jacobi", max_restarts=
             rz = rz_new
             p = z + beta * p
         restarts += 1
+
+
+def pcg_replaced(op, b, tol=1e-8, drop=0.1, maxit=100000):
+    """Jacobi-PCG (Introduction) with residual replacement every `drop` of
+    reduction.  Returns the Result with `restarts` = the number of true
+    residuals formed after the first."""
+    b = np.asarray(b, dtype=np.float64)
+    bnorm = norm(b)
+    x = np.zeros_like(b)
+    if bnorm == 0.0:
+        return Result(x, 0, 0.0, [0.0])
+    M = lambda v: op.expand(op.dinv * v)
+    r = b - op.apply(x)
+    p = np.zeros_like(b)
+    history, it, replaced = [], 0, -1
+    rz_prev = None            # r.z before the last update: beta's denominator
+    while True:
+        replaced += 1
+        rn = norm(r)
+        history.append(rn / bnorm)
+        if rn / bnorm <= tol or it >= maxit:
+            return Result(x, it, rn / bnorm, history, restarts=replaced)
+        z = M(r)
+        rz = dot(r, z)
+        rr_ref = rn * rn
+        beta = 0.0 if rz_prev is None else rz / rz_prev
+        while it < maxit:
+            p = z + beta * p
+            q = op.apply(p)
+            pq = dot(p, q)
+            if pq <= 0.0:
+                break
+            alpha = rz / pq
+            x = x + alpha * p
+            r = r - alpha * q
+            it += 1
+            z = M(r)
+            rzn = dot(r, z)
+            beta = rzn / rz
+            rz_prev, rz = rz, rzn
+            rr = dot(r, r)
+            if rr <= drop * drop * rr_ref or math.sqrt(rr) / bnorm <= tol:
+                break
+        r = b - op.apply(x)
 
 
 def fcg(op, b, precond, x0=None, tol=1e-8, maxit=100000, m=1, ratio=0.99, window=10,
