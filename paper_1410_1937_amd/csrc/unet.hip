@@ -31,6 +31,7 @@
 #include "../../include/nfa_unet.h"
 #include "device_util.h"
 #include "nfa_internal.h"
+#include "sweep_tile.h"
 #include "vecops.h"
 
 namespace nfa {
@@ -579,6 +580,213 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   }
 }
 
+// ------------------------------------------------------------ persistent, pipelined form
+// The same convolution for 16 input channels without skip addition or head
+// (the encoder 16 -> COUT, pooled output optional) on a persistent grid: each
+// workgroup walks a strided run of bricks inside its XCD's range.  Its A
+// fragments sit in LDS for the whole run.  Each brick's halo is loaded into
+// registers while the previous brick multiplies (only LDS reads in the
+// multiply loop, so the in-order vector memory counter never makes them wait
+// for the halo loads), then written to LDS between two barriers.  Bitwise the
+// result of k_tconv.  Measured at 25M cells: the 16 -> 32 encoder 165 -> 123
+// us; the 16 -> 16 decoder with its skip sum and head gained nothing (it is
+// bound by the VALU work of forming bf16(up(d1) + a0) for every halo copy,
+// not by the latency of loading it) and keeps k_tconv.
+template <int COUT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_tconv_pipe(const TconvArgs a) {
+  constexpr bool UPADD = false;
+  if (solve_done(a.sc)) return;
+  constexpr int CIN = 16, CG = 16;
+  constexpr int KC = (27 * CIN + 31) / 32;         // 14 chunks: two taps of 16 channels each
+  constexpr int MT = COUT / 16;
+  constexpr int ST = lds_stride<CG>();
+  constexpr int kTY = Brick<1>::TY, kTZ = Brick<1>::TZ, kHY = Brick<1>::HY, kHZ = Brick<1>::HZ;
+  constexpr int kHalo = Brick<1>::HALO, HY = kHY;
+  constexpr int CPP = CG / 8;                      // 16-byte chunks per staged position
+  constexpr int RCH = kHX * CPP;                   // chunks per halo row
+  constexpr int NE = kHY * kHZ * RCH;
+  constexpr int NIT = (NE + 255) / 256;
+  __shared__ __align__(16) unsigned char lds[kHalo * ST];
+  __shared__ __align__(16) uint4 afr[KC * MT * 64];
+  const int D = a.D, H = a.H, W = a.W;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int n = lane & 15, kq = lane >> 4;
+  for (int e = tid; e < KC * MT * 64; e += 256) afr[e] = a.frag[e];
+  float bi[MT][4];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bi[m][i] = a.bias[m * 16 + 4 * kq + i];
+  // this workgroup's bricks: XCD x owns [x per, (x+1) per); its G8 workgroups
+  // take them round robin
+  const int G8 = (int)(gridDim.x >> 3);
+  const int xcd = (int)(blockIdx.x & 7), j0 = (int)(blockIdx.x >> 3);
+  const int bend = min(a.nb, (xcd + 1) * a.per);
+  const int H2 = H >> 1, W2 = W >> 1;
+  // the wavefront's 2 x 2 block of rows and the staged index of its lane's
+  // output position in each
+  const int yw = 2 * (wv & 1), zw = 2 * (wv >> 1);
+  int hb[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) hb[j] = ((zw + (j >> 1) + 1) * kHY + (yw + (j & 1) + 1)) * kHX + (n + 1);
+
+  // per-thread staging table: for chunk e = tid + it*256 of the halo, its
+  // element offset from the brick's first output position (fine level), the
+  // offset of its coarse position from the brick's coarse origin (UPADD),
+  // its halo coordinates (packed) and its LDS offset; bricks start at even
+  // coordinates, so the coarse offsets are brick-independent
+  int rel[NIT], qrel[UPADD ? NIT : 1], hpk[NIT], ldo[NIT];
+  const int plane2 = H2 * W2;
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int e = tid + it * 256;
+    const int row = e / RCH, rc = e - row * RCH;
+    const int hx = rc / CPP, c8 = rc - hx * CPP;
+    const int hy = row % kHY, hz = row / kHY;
+    rel[it] = (((hz - 1) * H + (hy - 1)) * W + (hx - 1)) * CIN + c8 * 8;
+    if constexpr (UPADD) qrel[it] = (((hz - 1) >> 1) * plane2 + ((hy - 1) >> 1) * W2 + ((hx - 1) >> 1)) * CIN + c8 * 8;
+    hpk[it] = e < NE ? (hx | (hy << 8) | (hz << 16)) : -1;
+    ldo[it] = (row * kHX + hx) * ST + c8 * 16;
+  }
+  uint4 v[NIT];
+  uint4 c[UPADD ? NIT : 1];
+  // issue the loads of brick b's halo into registers
+  auto issue = [&](int b) {
+    const int bx = b % a.nbx, brest = b / a.nbx;
+    const int x0b = bx * kTX, y0b = (brest % a.nby) * kTY, z0b = (brest / a.nby) * kTZ;
+    const long long base = (((long long)z0b * H + y0b) * W + x0b) * CIN;
+    const long long qbase = ((((long long)(z0b >> 1)) * H2 + (y0b >> 1)) * W2 + (x0b >> 1)) * CIN;
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int pk = hpk[it];
+      const int gx = x0b - 1 + (pk & 255), gy = y0b - 1 + ((pk >> 8) & 255), gz = z0b - 1 + (pk >> 16);
+      const bool ok = pk >= 0 && (unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H && (unsigned)gz < (unsigned)D;
+      v[it] = make_uint4(0u, 0u, 0u, 0u);
+      if (ok) v[it] = *reinterpret_cast<const uint4*>(a.in + (base + rel[it]));
+      if constexpr (UPADD) {
+        c[it] = make_uint4(0u, 0u, 0u, 0u);
+        if (ok) c[it] = *reinterpret_cast<const uint4*>(a.in2 + (qbase + qrel[it]));
+      }
+    }
+  };
+  // write the registers of the last issue into LDS
+  auto commit = [&]() {
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      if (hpk[it] >= 0) {
+        uint4 w = v[it];
+        if constexpr (UPADD) {
+          w.x = add_bf2(w.x, c[it].x);
+          w.y = add_bf2(w.y, c[it].y);
+          w.z = add_bf2(w.z, c[it].z);
+          w.w = add_bf2(w.w, c[it].w);
+        }
+        *reinterpret_cast<uint4*>(lds + ldo[it]) = w;
+      }
+    }
+  };
+
+  int b = xcd * a.per + j0;
+  if (b < bend) issue(b);
+  while (b < bend) {
+    const int bx = b % a.nbx, brest = b / a.nbx;
+    const int x0b = bx * kTX, y0b = (brest % a.nby) * kTY, z0b = (brest / a.nby) * kTZ;
+    commit();
+    __syncthreads();
+    const int bn = b + G8;
+    if (bn < bend) issue(bn);
+    // ---- the brick's K chunks (two taps of 16 channels each), A from LDS
+    f32x4 acc[MT][4];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    int bj[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bj[j] = hb[j] * ST;
+    auto load_b = [&](auto kcc, Frag (&B)[4]) {
+      constexpr int kc = decltype(kcc)::value;
+      constexpr int t0 = 2 * kc, t1 = 2 * kc + 1 < 27 ? 2 * kc + 1 : 26;
+      const int sel = (kq >> 1) ? (tap_halo<HY>(t1) - tap_halo<HY>(t0)) * ST : 0;
+      const int lo = (kq & 1) * 16 + sel + tap_halo<HY>(t0) * ST;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) B[j].u = *reinterpret_cast<const uint4*>(lds + bj[j] + lo);
+    };
+    Frag An[MT], Bn[4];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) An[m].u = afr[m * 64 + lane];
+    load_b(std::integral_constant<int, 0>{}, Bn);
+    static_for<0, KC>([&](auto kcc) {
+      constexpr int kc = decltype(kcc)::value;
+      Frag A[MT], B[4];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) A[m] = An[m];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) B[j] = Bn[j];
+      if constexpr (kc + 1 < KC) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m) An[m].u = afr[((kc + 1) * MT + m) * 64 + lane];
+        load_b(std::integral_constant<int, kc + 1>{}, Bn);
+      }
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[m].v, B[j].v, acc[m][j], 0, 0, 0);
+      // keep the one-chunk-ahead schedule: without this fence the scheduler
+      // hoists every chunk's LDS reads and the registers triple
+      __builtin_amdgcn_sched_barrier(0);
+    });
+    // ---- epilogue (as in k_tconv): bias, ReLU, BF16 rounding; output,
+    // pooled average
+    unsigned pk[MT][4][2];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        pk[m][j][0] = pack_bf2(fmaxf(acc[m][j][0] + bi[m][0], 0.f), fmaxf(acc[m][j][1] + bi[m][1], 0.f));
+        pk[m][j][1] = pack_bf2(fmaxf(acc[m][j][2] + bi[m][2], 0.f), fmaxf(acc[m][j][3] + bi[m][3], 0.f));
+        acc[m][j][0] = lo_bf(pk[m][j][0]);
+        acc[m][j][1] = hi_bf(pk[m][j][0]);
+        acc[m][j][2] = lo_bf(pk[m][j][1]);
+        acc[m][j][3] = hi_bf(pk[m][j][1]);
+      }
+    const int x = x0b + n;
+    if (a.out) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int y = y0b + yw + (j & 1), z = z0b + zw + (j >> 1);
+        if (x < W && y < H && z < D) {
+          const long long p = ((long long)z * H + y) * W + x;
+#pragma unroll
+          for (int m = 0; m < MT; ++m)
+            *reinterpret_cast<uint2*>(a.out + p * COUT + m * 16 + 4 * kq) = make_uint2(pk[m][j][0], pk[m][j][1]);
+        }
+      }
+    }
+    if (a.pooled) {
+      const int y = y0b + yw, z = z0b + zw;
+      const bool ok = (n & 1) == 0 && x < W && y < H && z < D;
+      const long long q = ((long long)(z >> 1) * (H >> 1) + (y >> 1)) * (W >> 1) + (x >> 1);
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        float pv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          float t = (acc[m][0][i] + acc[m][1][i]) + (acc[m][2][i] + acc[m][3][i]);
+          t += __shfl_xor(t, 1);
+          pv[i] = t * 0.125f;
+        }
+        if (ok)
+          *reinterpret_cast<uint2*>(a.pooled + q * COUT + m * 16 + 4 * kq) =
+              make_uint2(pack_bf2(pv[0], pv[1]), pack_bf2(pv[2], pv[3]));
+      }
+    }
+    b = bn;
+    __syncthreads();   // every wavefront is done with this brick's LDS before the next commit
+  }
+}
+
 // ------------------------------------------------------------ weight gradient (MFMA)
 // partial[t][blk][ci][co] = sum over this workgroup's positions m of
 //   in'[m + off_t][ci] * dout[m][co]
@@ -987,10 +1195,23 @@ void tconv_t(TconvArgs a, hipStream_t s) {
   k_tconv<CIN, COUT, UPADD, FEAT, SUB><<<8 * a.per, 256, 0, s>>>(a);
 }
 
+// persistent launch of k_tconv_pipe: as many workgroups as fit on the device
+// at once (a multiple of 8, so that each XCD gets the same number)
+template <int COUT> void tconv_pipe_t(TconvArgs a, hipStream_t s) {
+  a.nbx = (a.W + kTX - 1) / kTX;
+  a.nby = (a.H + Brick<1>::TY - 1) / Brick<1>::TY;
+  a.nb = a.nbx * a.nby * ((a.D + Brick<1>::TZ - 1) / Brick<1>::TZ);
+  a.per = (a.nb + 7) / 8;
+  const int res = resident_blocks(reinterpret_cast<const void*>(&k_tconv_pipe<COUT>), 256);
+  const int g8 = std::max(1, std::min(res / 8, a.per));
+  k_tconv_pipe<COUT><<<8 * g8, 256, 0, s>>>(a);
+}
+
 nfa_status tconv(int cin, int cout, bool upadd, const TconvArgs& a, hipStream_t s) {
+  if (cin == 16 && cout == 32 && !upadd) { tconv_pipe_t<32>(a, s); return NFA_OK; }
 #define T_(A, B, U) \
   if (cin == A && cout == B && upadd == U) { tconv_t<A, B, U, false>(a, s); return NFA_OK; }
-  T_(16, 32, false) T_(32, 64, false) T_(64, 64, false) T_(64, 32, false)
+  T_(32, 64, false) T_(64, 64, false) T_(64, 32, false)
   T_(32, 16, true) T_(64, 32, true) T_(64, 64, true) T_(16, 16, true)
 #undef T_
   return fail(NFA_ERR_INVALID, "learned preconditioner: no convolution kernel for this shape");
