@@ -278,7 +278,9 @@ typedef struct {
   int precond;           /* NFA_PC_* */
   int precision;         /* NFA_PREC_* */
   double replace_drop;   /* mixed: FP64 residual replacement each time the FP32
-                            recursive residual has dropped by this factor (0.1) */
+                            recursive residual has dropped by this factor (0.1);
+                            CG goes on with the same direction and its own beta,
+                            so the iteration count stays near FP64's */
   int fcg_m;             /* flexible CG truncation; 1 (FCG(1)) is supported */
   double fallback_ratio; /* switch to Jacobi-PCG when the mean reduction per
                             iteration over a window exceeds this (0.99) */

@@ -76,6 +76,30 @@ def test_forward_layers_within_one_bf16_step(setup):
     assert np.max(np.abs(z - zref)) <= 1e-5 * np.max(np.abs(zref))
 
 
+def test_pipelined_encoder_over_many_bricks_per_workgroup():
+    """The persistent 16 -> 32 encoder walks several bricks per workgroup when
+    the level has more bricks than resident workgroups: on 264 x 136 x 76
+    cells its level-1 grid, 132 x 68 x 38, has 9 x 17 x 10 bricks, ragged in
+    every direction.  Fed the GPU's own pooled input, its output and its
+    pooled output are within one BF16 step of the oracle's layer."""
+    from paper_1410_1937_amd import nfa
+    wl = fx.small(12, 264, 136, 76, body="sphere")
+    gg, gop = gpu_for(wl)
+    net = nfa.UNet(264, 136, 76, seed=5)
+    rng = np.random.default_rng(21)
+    params = ou.init_params(23, zero_last=False)
+    params = [(w.astype(np.float32), (rng.standard_normal(b.shape) * 0.05).astype(np.float32)) for w, b in params]
+    net.set_params(nfa.UNet.flatten(params))
+    r = torch.as_tensor(rng.standard_normal((76, 136, 264)).astype(np.float32), device="cuda")
+    net.forward(gop, r, keep=True)
+    p0 = _bf(net.export("p0"))
+    a1 = _bf(net.export("a1"))
+    w1 = ou.bf16(params[1][0].astype(np.float64))
+    ref = ou.bf16(ou.relu(ou.conv3d(p0, w1, params[1][1].astype(np.float64))))
+    _ulp_ok(a1, ref)
+    _ulp_ok(_bf(net.export("p1")), ou.bf16(ou.pool(a1)))
+
+
 def test_whole_forward_matches_oracle(setup):
     wl, (og, ob, oop, _), (gg, gop), net, params, r, rt, z = setup
     x0, s = ou.features(r.astype(np.float64), 1.0 / oop.rho, ob.reduced)
