@@ -78,16 +78,21 @@ __device__ __forceinline__ void finalize_block(const double* partials, int n, in
   if (phase != PH_BB && phase != PH_RR && phase != PH_RRO && phase != PH_INIT && phase != PH_RELIABLE &&
       phase != PH_RELIABLE_F && sc->done)
     return;
-  __shared__ double lds[1024 / 64];
+  __shared__ double lds[2][1024 / 64];
   __shared__ double val[4];
-  for (int c = 0; c < ncomp; ++c) {
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += 1024) acc += partials[(size_t)c * kMaxPartials + i];
-    const double t = block_sum(acc, lds);
-    if (threadIdx.x == 0) val[c] = t;
-    __syncthreads();
+  // both components' partials in one pass (their loads in flight together)
+  double acc0 = 0.0, acc1 = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) {
+    acc0 += partials[i];
+    if (ncomp > 1) acc1 += partials[(size_t)kMaxPartials + i];
   }
-  if (threadIdx.x == 0) apply_phase(phase, ncomp, val, sc, hist);
+  const double t0 = block_sum(acc0, lds[0]);
+  const double t1 = ncomp > 1 ? block_sum(acc1, lds[1]) : 0.0;
+  if (threadIdx.x == 0) {
+    val[0] = t0;
+    val[1] = t1;
+    apply_phase(phase, ncomp, val, sc, hist);
+  }
 }
 
 __global__ __launch_bounds__(1024) void k_finalize(const double* partials, int n, int ncomp, int phase,
@@ -115,13 +120,18 @@ __global__ __launch_bounds__(1024) void k_finalize_merge(const double* partials,
   const int stride = (gridDim.x - 1) * blockDim.x;
   for (int t = (blockIdx.x - 1) * blockDim.x + threadIdx.x; t < cnt; t += stride) {
     if (GATHER) {
-      const int r = ia[t];
+      // the members' values are loaded together (groups have at most a few
+      // dozen members; the first 16 in one round), then added in order
+      const int r = ia[t], m0 = ib[t], m1 = ib[t + 1];
       T acc = v[r];
-      for (int m = ib[t]; m < ib[t + 1]; ++m) {
-        const int cm = ic[m];
-        acc = acc + v[cm];
-        v[cm] = T(0);
-      }
+      T mv[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) mv[k] = m0 + k < m1 ? v[ic[m0 + k]] : T(0);
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (m0 + k < m1) acc = acc + mv[k];
+      for (int m = m0 + 16; m < m1; ++m) acc = acc + v[ic[m]];
+      for (int m = m0; m < m1; ++m) v[ic[m]] = T(0);
       v[r] = acc;
     } else {
       v[ia[t]] = v[ib[t]];
