@@ -270,13 +270,13 @@ hipError_t poisson_buffers(Poisson& op, const Grid& g, Carver& c) {
   const long long n = g.n;
   const long long nzy = (long long)g.nz * g.ny;
   hipError_t e = hipSuccess;
-  DevBuf* f64[] = {&op.rho, &op.rho_tmp, &op.tx64, &op.dinv64, &op.r, &op.z, &op.p, &op.p2, &op.q, &op.tmp};
+  DevBuf* f64[] = {&op.rho, &op.rho_tmp, &op.tx64, &op.dinv64, &op.r, &op.z, &op.p, &op.p2, &op.p3, &op.q, &op.tmp};
   for (DevBuf* b : f64)
     if ((e = c.take(*b, n * 8)) != hipSuccess) return e;
   if ((e = c.take(op.txb64, nzy * 8)) != hipSuccess || (e = c.take(op.ty64, g.nfy() * 8)) != hipSuccess ||
       (e = c.take(op.tz64, g.nfz() * 8)) != hipSuccess)
     return e;
-  DevBuf* f32[] = {&op.tx32, &op.dinv32, &op.x32, &op.r32, &op.z32, &op.p32, &op.p32b, &op.q32};
+  DevBuf* f32[] = {&op.tx32, &op.dinv32, &op.x32, &op.r32, &op.z32, &op.p32, &op.p32b, &op.p32c, &op.q32};
   for (DevBuf* b : f32)
     if ((e = c.take(*b, n * 4)) != hipSuccess) return e;
   if ((e = c.take(op.txb32, nzy * 4)) != hipSuccess || (e = c.take(op.ty32, g.nfy() * 4)) != hipSuccess ||

@@ -6,16 +6,23 @@
 //             x += alpha_prev p_old           (update deferred from the
 //                                              previous iteration)
 //             partials p.q (and p.r for flexible CG)
+//             (Jacobi-PCG defers further: every other sweep A leaves x
+//             alone, and the next one applies both owed steps,
+//             x = (x + alpha_(k-2) p_(k-2)) + alpha_(k-1) p_(k-1), bitwise
+//             the two updates one after the other; p is kept in three
+//             buffers for it)
 //   sweep B:  z -= alpha D^-1 q               partials r.z, r.r
 //             (Jacobi-PCG carries the preconditioned residual z = D^-1 r as
 //             its state: r = z / D^-1 where D^-1 > 0 and 0 elsewhere is
 //             formed for the partials only, so r is neither read nor written;
 //             flexible CG: r -= alpha q, partial r.r, and the preconditioner
 //             runs as its own pass)
-// so the direction update and the x update cost no extra pass: 104 B/cell per
-// iteration in FP64 (72 + 32), 52 B/cell in FP32, against 128 / 64 B for the
-// textbook three-pass form.  p is double-buffered (the neighbours of a cell
-// must see the old direction).
+// so the direction update and the x update cost no extra pass: Jacobi-PCG
+// moves 100 B/cell per iteration in FP64 (sweep A 56 or 80, 68 on average,
+// + 32), 50 B/cell in FP32 (28 or 40, 34 on average, + 16), against 128 / 64
+// B for the textbook three-pass form.  p is double-buffered in flexible CG and
+// triple-buffered in Jacobi-PCG (the neighbours of a cell must see the old
+// direction).
 //
 // Launch shape of sweep A: a workgroup is a tile of WX wavefronts across x
 // by AY rows in y (WX * AY = 16 wavefronts).  Each lane owns V consecutive x
@@ -65,10 +72,13 @@ __device__ __forceinline__ Pack<T, V> dir(const T* z, const T* po, long long c, 
   return r;
 }
 
-template <class T, int V, int WX, bool FLEX>
+// XM: the x update of this sweep: 0 none (the step on p_old stays owed), 1
+// x += alpha_pend p_old, 2 x = (x + alpha_pend2 p_old2) + alpha_pend p_old
+template <class T, int V, int WX, bool FLEX, int XM>
 __global__ __launch_bounds__(AX* kTileWaves) void k_cg_a(
     int nx, int ny, int nz, int tiles_x, long long ncol, long long per_block,
-    const T* __restrict__ z, const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ x,
+    const T* __restrict__ z, const T* __restrict__ pold, const T* __restrict__ pold2, T* __restrict__ pnew,
+    T* __restrict__ x,
     const T* __restrict__ r, const T* __restrict__ tx, const T* __restrict__ txb,
     const T* __restrict__ ty, const T* __restrict__ tz, T* __restrict__ q,
     double* __restrict__ partials, const SolveScalars* __restrict__ sc) {
@@ -80,6 +90,7 @@ __global__ __launch_bounds__(AX* kTileWaves) void k_cg_a(
   __shared__ double lds[2 * kTileWaves];
   const T beta = (T)sc->beta;
   const T apend = (T)sc->alpha_pend;
+  const T apend2 = (T)sc->alpha_pend2;
   const int lane = threadIdx.x;
   const int wx = threadIdx.y % WX, row = threadIdx.y / WX;
   const int col = wx * AX + lane;
@@ -182,10 +193,18 @@ __global__ __launch_bounds__(AX* kTileWaves) void k_cg_a(
         }
         st_stream<StreamHints<T>::a_store, T, V>(q + c, qv);
         st_stream<StreamHints<T>::a_store, T, V>(pnew + c, pc);
-        Pack<T, V> xv = ld_stream<StreamHints<T>::a_load, T, V>(x + c);
+        if constexpr (XM == 1) {
+          Pack<T, V> xv = ld_stream<StreamHints<T>::a_load, T, V>(x + c);
 #pragma unroll
-        for (int e = 0; e < V; ++e) xv.v[e] = xv.v[e] + apend * poc.v[e];
-        st_stream<StreamHints<T>::a_store, T, V>(x + c, xv);
+          for (int e = 0; e < V; ++e) xv.v[e] = xv.v[e] + apend * poc.v[e];
+          st_stream<StreamHints<T>::a_store, T, V>(x + c, xv);
+        } else if constexpr (XM == 2) {
+          Pack<T, V> xv = ld_stream<StreamHints<T>::a_load, T, V>(x + c);
+          const Pack<T, V> p2 = ld_stream<StreamHints<T>::a_load, T, V>(pold2 + c);
+#pragma unroll
+          for (int e = 0; e < V; ++e) xv.v[e] = (xv.v[e] + apend2 * p2.v[e]) + apend * poc.v[e];
+          st_stream<StreamHints<T>::a_store, T, V>(x + c, xv);
+        }
         if (FLEX) {
           const Pack<T, V> rv = ld_stream<StreamHints<T>::a_load, T, V>(r + c);
 #pragma unroll
@@ -270,14 +289,17 @@ __global__ __launch_bounds__(kBlock) void k_cg_b(long long nvec, T* __restrict__
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-// x += alpha_pend p (the x update left pending when the iteration stopped)
+// the x updates still owed when the iteration stopped: x += alpha_pend p, or
+// with p2 (Jacobi-PCG) x = (x + alpha_pend2 p2) + alpha_pend p, the order of
+// sweep A's two-step update
 template <class T>
-__global__ void k_cg_fixup(long long n, T* __restrict__ x, const T* __restrict__ p,
+__global__ void k_cg_fixup(long long n, T* __restrict__ x, const T* __restrict__ p, const T* __restrict__ p2,
                            const SolveScalars* __restrict__ sc) {
   const T a = (T)sc->alpha_pend;
+  const T a2 = (T)sc->alpha_pend2;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
-    x[i] = x[i] + a * p[i];
+    x[i] = p2 ? (x[i] + a2 * p2[i]) + a * p[i] : x[i] + a * p[i];
 }
 
 // x64 += x32 * inv_scale; x32 = 0
@@ -330,9 +352,9 @@ int resident_blocks(const void* fn, int threads) {
 
 // sweep A; returns the number of workgroup partials per component
 template <class T>
-int launch_cg_a(const Grid& g, const Coeffs<T>& C, const T* z, const T* pold, T* pnew, T* x,
-                const T* r, T* q, double* partials, const SolveScalars* sc, bool flex, bool vec,
-                hipStream_t s) {
+int launch_cg_a(const Grid& g, const Coeffs<T>& C, const T* z, const T* pold, const T* pold2, T* pnew,
+                T* x, const T* r, T* q, double* partials, const SolveScalars* sc, bool flex, int xm,
+                bool vec, hipStream_t s) {
   const int V = vec ? tile::vec_width<T>() : 1;
   const int wx = tile_wx<T>(g, V);
   const int ay = kTileWaves / wx;
@@ -340,28 +362,29 @@ int launch_cg_a(const Grid& g, const Coeffs<T>& C, const T* z, const T* pold, T*
   const long long ncol = (long long)tiles_x * ((g.ny + ay - 1) / ay);
   dim3 blk(AX, kTileWaves);
   int nb = 0;
-#define CGA(VV, WW, FF)                                                                          \
+#define CGA(VV, WW, FF, XX)                                                                      \
   do {                                                                                           \
-    const void* fn = reinterpret_cast<const void*>(&k_cg_a<T, VV, WW, FF>);                      \
+    const void* fn = reinterpret_cast<const void*>(&k_cg_a<T, VV, WW, FF, XX>);                  \
     nb = resident_blocks(fn, AX * kTileWaves);                                                   \
     const long long per = (ncol * g.nz + nb - 1) / nb;                                           \
-    k_cg_a<T, VV, WW, FF><<<nb, blk, 0, s>>>(g.nx, g.ny, g.nz, tiles_x, ncol, per, z, pold, pnew, \
-                                             x, r, C.tx, C.txb, C.ty, C.tz, q, partials, sc);    \
+    k_cg_a<T, VV, WW, FF, XX><<<nb, blk, 0, s>>>(g.nx, g.ny, g.nz, tiles_x, ncol, per, z, pold, pold2, \
+                                                 pnew, x, r, C.tx, C.txb, C.ty, C.tz, q, partials, sc); \
   } while (0)
-#define CGA_W(VV, FF)              \
-  do {                             \
-    if (wx == 4) CGA(VV, 4, FF);   \
-    else if (wx == 2) CGA(VV, 2, FF); \
-    else CGA(VV, 1, FF);           \
+#define CGA_X(VV, WW)                                 \
+  do {                                                \
+    if (flex) CGA(VV, WW, true, 1);                   \
+    else if (xm == 2) CGA(VV, WW, false, 2);          \
+    else CGA(VV, WW, false, 0);                       \
   } while (0)
+  // flexible CG updates x every sweep; Jacobi-PCG every other one (xm 0 / 2)
   if (vec) {
-    if (flex) CGA_W(tile::vec_width<T>(), true);
-    else CGA_W(tile::vec_width<T>(), false);
+    if (wx == 4) CGA_X(tile::vec_width<T>(), 4);
+    else if (wx == 2) CGA_X(tile::vec_width<T>(), 2);
+    else CGA_X(tile::vec_width<T>(), 1);
   } else {
-    if (flex) CGA(1, 1, true);
-    else CGA(1, 1, false);
+    CGA_X(1, 1);
   }
-#undef CGA_W
+#undef CGA_X
 #undef CGA
   return nb;
 }
@@ -387,8 +410,9 @@ int launch_cg_b(const Grid& g, T* r, const T* q, const T* dinv, T* z, double* pa
   return nb;
 }
 
-template <class T> void launch_cg_fixup(const Grid& g, T* x, const T* p, const SolveScalars* sc, hipStream_t s) {
-  k_cg_fixup<T><<<vblocks(g.n), kBlock, 0, s>>>(g.n, x, p, sc);
+template <class T>
+void launch_cg_fixup(const Grid& g, T* x, const T* p, const T* p2, const SolveScalars* sc, hipStream_t s) {
+  k_cg_fixup<T><<<vblocks(g.n), kBlock, 0, s>>>(g.n, x, p, p2, sc);
 }
 void launch_fold(const Grid& g, double* x, float* d, double inv_scale, hipStream_t s) {
   k_fold<<<vblocks(g.n), kBlock, 0, s>>>(g.n, x, d, inv_scale);
@@ -399,16 +423,19 @@ void launch_cast(const Grid& g, const double* r, float* r32, double scale, hipSt
 
 template bool cg_vectorizable<double>(const Grid&, const void* const*, int);
 template bool cg_vectorizable<float>(const Grid&, const void* const*, int);
-template int launch_cg_a<double>(const Grid&, const Coeffs<double>&, const double*, const double*, double*,
-                                 double*, const double*, double*, double*, const SolveScalars*, bool, bool,
-                                 hipStream_t);
-template int launch_cg_a<float>(const Grid&, const Coeffs<float>&, const float*, const float*, float*, float*,
-                                const float*, float*, double*, const SolveScalars*, bool, bool, hipStream_t);
+template int launch_cg_a<double>(const Grid&, const Coeffs<double>&, const double*, const double*, const double*,
+                                 double*, double*, const double*, double*, double*, const SolveScalars*, bool,
+                                 int, bool, hipStream_t);
+template int launch_cg_a<float>(const Grid&, const Coeffs<float>&, const float*, const float*, const float*,
+                                float*, float*, const float*, float*, double*, const SolveScalars*, bool, int,
+                                bool, hipStream_t);
 template int launch_cg_b<double>(const Grid&, double*, const double*, const double*, double*, double*,
                                  const SolveScalars*, bool, bool, hipStream_t);
 template int launch_cg_b<float>(const Grid&, float*, const float*, const float*, float*, double*,
                                 const SolveScalars*, bool, bool, hipStream_t);
-template void launch_cg_fixup<double>(const Grid&, double*, const double*, const SolveScalars*, hipStream_t);
-template void launch_cg_fixup<float>(const Grid&, float*, const float*, const SolveScalars*, hipStream_t);
+template void launch_cg_fixup<double>(const Grid&, double*, const double*, const double*, const SolveScalars*,
+                                      hipStream_t);
+template void launch_cg_fixup<float>(const Grid&, float*, const float*, const float*, const SolveScalars*,
+                                     hipStream_t);
 
 }  // namespace nfa

@@ -132,7 +132,8 @@ struct Grid {
 // Device-side scalars of an iterative solve (one cache line each group).
 struct SolveScalars {
   double rz, pq, rr, bb, alpha, beta, tol2, pr, zq, rr_outer;
-  double alpha_pend; // x += alpha_pend p still owed by the fused sweep
+  double alpha_pend; // x += alpha_pend p_(k-1) still owed by the fused sweep
+  double alpha_pend2; // x += alpha_pend2 p_(k-2) also owed (Jacobi-PCG: after a sweep A that skipped x)
   double rz_prev;    // r.z before the last update: the denominator of beta
   double ratio;      // stagnation threshold (mean reduction per iteration)
   int iter, done, breakdown, stalled, max_iter, window;
@@ -157,8 +158,8 @@ struct Poisson {
   DevBuf rho, rho_tmp;                          // double cells
   DevBuf tx64, txb64, ty64, tz64, dinv64;       // FP64 coefficients
   DevBuf tx32, txb32, ty32, tz32, dinv32;       // FP32 coefficients
-  DevBuf r, z, p, p2, q, tmp;                   // double work vectors (p double-buffered)
-  DevBuf x32, r32, z32, p32, p32b, q32;         // float work vectors
+  DevBuf r, z, p, p2, p3, q, tmp;               // double work vectors (p in three buffers)
+  DevBuf x32, r32, z32, p32, p32b, p32c, q32;   // float work vectors
   DevBuf partials;                              // double block partials
   DevBuf scal;                                  // SolveScalars (device)
   DevBuf hist;                                  // double per-iteration ||r||^2 (kHistCap)

@@ -42,6 +42,7 @@ __device__ __forceinline__ void apply_phase(int phase, int ncomp, const double* 
     sc->beta = 0.0;
     sc->rz_prev = sc->rz;
     sc->alpha_pend = 0.0;
+    sc->alpha_pend2 = 0.0;
     sc->done = 0;
     sc->breakdown = 0;
     sc->stalled = 0;
@@ -50,12 +51,28 @@ __device__ __forceinline__ void apply_phase(int phase, int ncomp, const double* 
     if (hist && sc->iter <= sc->max_iter && sc->iter <= kHistCap) hist[sc->iter] = sc->rr;
     break;
   case PH_PQ:
+    // Jacobi-PCG, after a sweep A that applied every owed x update
     sc->pq = val[0];
+    sc->alpha_pend2 = 0.0;
     if (!(val[0] > 0.0) || !isfinite(val[0])) {
       sc->breakdown = isfinite(val[0]) ? 1 : 2;
       sc->done = 1;
       sc->alpha_pend = 0.0;
     } else {
+      sc->alpha = sc->rz / val[0];
+    }
+    break;
+  case PH_PQ_SKIP:
+    // Jacobi-PCG, after a sweep A that left x alone: the step owed on the
+    // old direction moves one place back (the next sweep A applies both);
+    // on a breakdown it stays owed on the old direction alone
+    sc->pq = val[0];
+    if (!(val[0] > 0.0) || !isfinite(val[0])) {
+      sc->breakdown = isfinite(val[0]) ? 1 : 2;
+      sc->done = 1;
+      sc->alpha_pend2 = 0.0;
+    } else {
+      sc->alpha_pend2 = sc->alpha_pend;
       sc->alpha = sc->rz / val[0];
     }
     break;
@@ -88,6 +105,7 @@ __device__ __forceinline__ void apply_phase(int phase, int ncomp, const double* 
       sc->breakdown = isfinite(val[0]) && isfinite(val[1]) ? 1 : 2;
       sc->done = 1;
       sc->alpha_pend = 0.0;
+      sc->alpha_pend2 = 0.0;
     } else {
       sc->alpha = val[1] / val[0];
     }
@@ -104,6 +122,7 @@ __device__ __forceinline__ void apply_phase(int phase, int ncomp, const double* 
     sc->rz = val[0];
     sc->rr = val[1];
     sc->alpha_pend = 0.0;
+    sc->alpha_pend2 = 0.0;
     sc->done = 0;
     sc->breakdown = 0;
     sc->stalled = 0;
@@ -113,6 +132,7 @@ __device__ __forceinline__ void apply_phase(int phase, int ncomp, const double* 
   case PH_RELIABLE_F:  // flexible CG: residual replaced, (r.r)
     sc->rr = val[0];
     sc->alpha_pend = 0.0;
+    sc->alpha_pend2 = 0.0;
     sc->done = 0;
     sc->breakdown = 0;
     sc->stalled = 0;

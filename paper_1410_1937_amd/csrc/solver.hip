@@ -31,7 +31,7 @@ template <class T> struct CG {
   T* r;
   T* z;
   T* q;
-  T* p[2];
+  T* p[3];      // directions: flexible CG alternates p[0], p[1]; Jacobi-PCG rotates all three
   Coeffs<T> C;
   bool vec;
 };
@@ -42,10 +42,13 @@ inline double sq(double a) { return a * a; }
 
 // Sweep A wrapped in a timing event pair when profiling is on.
 template <class T>
-int timed_cg_a(Poisson& op, CG<T>& B, int j, bool flex, hipStream_t st) {
+int timed_cg_a(Poisson& op, CG<T>& B, int j, bool flex, int xm, hipStream_t st) {
   const bool rec = prof_begin(op, st);
-  const int np = launch_cg_a<T>(*op.g, B.C, B.z, B.p[j & 1], B.p[(j + 1) & 1], B.x, B.r, B.q,
-                                op.partials.as<double>(), op.scal.as<SolveScalars>(), flex, B.vec, st);
+  const T* pold = flex ? B.p[j & 1] : B.p[j % 3];
+  const T* pold2 = flex ? nullptr : B.p[(j + 2) % 3];
+  T* pnew = flex ? B.p[(j + 1) & 1] : B.p[(j + 1) % 3];
+  const int np = launch_cg_a<T>(*op.g, B.C, B.z, pold, pold2, pnew, B.x, B.r, B.q, op.partials.as<double>(),
+                                op.scal.as<SolveScalars>(), flex, xm, B.vec, st);
   prof_end(op, rec, sizeof(T) == 8 ? 0 : (flex ? kProfF32Flex : 1), st);
   return np;
 }
@@ -123,8 +126,12 @@ void enqueue_iter(Poisson& op, CG<T>& B, int j, int pc, void* unet, nfa_status* 
       launch_finalize(parts, nzq, 1, PH_ZQ, sc, hist, st);
     }
   }
-  const int na = timed_cg_a<T>(op, B, j, flex, st);
-  launch_finalize_merge<T>(g, true, B.q, parts, na, flex ? 2 : 1, flex ? PH_PQF : PH_PQ, sc, hist, st);
+  // Jacobi-PCG: iterations 0, 2, 4 ... of a phase leave x alone, the odd ones
+  // apply the two owed steps
+  const int xm = flex ? 1 : ((j & 1) ? 2 : 0);
+  const int na = timed_cg_a<T>(op, B, j, flex, xm, st);
+  launch_finalize_merge<T>(g, true, B.q, parts, na, flex ? 2 : 1, flex ? PH_PQF : (xm == 0 ? PH_PQ_SKIP : PH_PQ),
+                           sc, hist, st);
   const int nb = launch_cg_b<T>(g, B.r, B.q, B.C.dinv, B.z, parts, sc, flex, B.vec, st);
   if (flex)
     launch_finalize(parts, nb, 1, PH_UPDF, sc, hist, st);
@@ -185,13 +192,13 @@ nfa_status cg_solve(Poisson& op, const double* b, double* x64, const nfa_solve_o
   CG<T> B;
   if constexpr (mixed) {
     B = CG<T>{op.x32.as<float>(), op.r32.as<float>(), op.z32.as<float>(), op.q32.as<float>(),
-              {op.p32.as<float>(), op.p32b.as<float>()}, op.c32(), false};
+              {op.p32.as<float>(), op.p32b.as<float>(), op.p32c.as<float>()}, op.c32(), false};
   } else {
     B = CG<T>{x64, op.r.as<double>(), op.z.as<double>(), op.q.as<double>(),
-              {op.p.as<double>(), op.p2.as<double>()}, op.c64(), false};
+              {op.p.as<double>(), op.p2.as<double>(), op.p3.as<double>()}, op.c64(), false};
   }
-  const void* ptrs[] = {B.x, B.r, B.z, B.q, B.p[0], B.p[1], B.C.tx, B.C.ty, B.C.tz, B.C.dinv};
-  B.vec = cg_vectorizable<T>(g, ptrs, 10);
+  const void* ptrs[] = {B.x, B.r, B.z, B.q, B.p[0], B.p[1], B.p[2], B.C.tx, B.C.ty, B.C.tz, B.C.dinv};
+  B.vec = cg_vectorizable<T>(g, ptrs, 11);
   int pc = o->precond;
   const double delta = mixed ? o->replace_drop : 0.0;
   double* r64 = op.r.as<double>();
@@ -248,8 +255,11 @@ nfa_status cg_solve(Poisson& op, const double* b, double* x64, const nfa_solve_o
     if ((e = read_scalars(op, st, &S)) != NFA_OK) return e;
     harvest_profile(op, S.iter - last_harvest);
     last_harvest = S.iter;
+    // J iterations of this phase are complete; the step on their last
+    // direction (and in Jacobi-PCG possibly the one before) is still owed
     const int J = S.iter - iter_phase;
-    launch_cg_fixup<T>(g, B.x, B.p[J & 1], sc, st);
+    if (pc == NFA_PC_JACOBI) launch_cg_fixup<T>(g, B.x, B.p[J % 3], B.p[(J + 2) % 3], sc, st);
+    else launch_cg_fixup<T>(g, B.x, B.p[J & 1], nullptr, sc, st);
     if (mixed) launch_fold(g, x64, op.x32.as<float>(), 1.0 / scale, st);
     if ((e = residual64(op, b, x64, r64, PH_RRO, st)) != NFA_OK) return e;
     SolveScalars S2{};

@@ -7,7 +7,7 @@ namespace nfa {
 
 // finalize phases: what a reduction feeds into the solver state
 enum { PH_BB = 0, PH_RR = 1, PH_INIT = 2, PH_PQ = 3, PH_UPD = 4, PH_RRO = 5, PH_ZQ = 6, PH_PR = 7,
-       PH_PQF = 8, PH_UPDF = 9, PH_RELIABLE = 10, PH_RELIABLE_F = 11 };
+       PH_PQF = 8, PH_UPDF = 9, PH_RELIABLE = 10, PH_RELIABLE_F = 11, PH_PQ_SKIP = 12 };
 
 void launch_finalize(const double* partials, int n, int ncomp, int phase, SolveScalars* sc,
                      double* hist, hipStream_t s);
@@ -36,13 +36,14 @@ template <class T> void launch_sabotage(const unsigned char* red, T* z, long lon
 // fused CG sweeps (cg.hip)
 template <class T> bool cg_vectorizable(const Grid& g, const void* const* ptrs, int nptr);
 template <class T>
-int launch_cg_a(const Grid& g, const Coeffs<T>& C, const T* z, const T* pold, T* pnew, T* x,
-                const T* r, T* q, double* partials, const SolveScalars* sc, bool flex, bool vec,
-                hipStream_t s);
+int launch_cg_a(const Grid& g, const Coeffs<T>& C, const T* z, const T* pold, const T* pold2, T* pnew,
+                T* x, const T* r, T* q, double* partials, const SolveScalars* sc, bool flex, int xm,
+                bool vec, hipStream_t s);
 template <class T>
 int launch_cg_b(const Grid& g, T* r, const T* q, const T* dinv, T* z, double* partials,
                 const SolveScalars* sc, bool flex, bool vec, hipStream_t s);
-template <class T> void launch_cg_fixup(const Grid& g, T* x, const T* p, const SolveScalars* sc, hipStream_t s);
+template <class T>
+void launch_cg_fixup(const Grid& g, T* x, const T* p, const T* p2, const SolveScalars* sc, hipStream_t s);
 void launch_fold(const Grid& g, double* x, float* d, double inv_scale, hipStream_t s);
 void launch_cast(const Grid& g, const double* r, float* r32, double scale, hipStream_t s);
 
