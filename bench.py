@@ -215,12 +215,14 @@ def main():
     # the one with the largest summed time (the dominant kernel)
     op.profile(True)
     step("learned")
-    kinds = {k: op.profile_read(k) for k in ("f32", "f32_flex", "f64", "unet")}
+    kinds = {k: op.profile_read(k) for k in ("f32", "f32_x2", "f32_flex", "f64", "f64_x2", "unet")}
     op.profile(False)
-    # sweep A moves, per cell: z, p_old, tx, ty, tz, x read; p_new, q, x
-    # written (9 words: 36 B in FP32, 72 B in FP64); its flexible form also
-    # reads r for p.r (10 words, 40 B in FP32).  Neighbour re-reads are cache
-    # hits and not counted.  A network application performs 2 x 27 x cin x
+    # sweep A moves, per cell: z, p_old, tx, ty, tz read, p_new and q written
+    # (7 words); Jacobi-PCG updates x every other iteration, so its sweep A
+    # alternates between these 7 words (28 B in FP32, 56 B in FP64) and 10
+    # (x and the older direction read, x written: 40 / 80 B); the flexible
+    # form updates x every time and reads r for p.r (10 words, 40 B in FP32).
+    # Neighbour re-reads are cache hits and not counted.  A network application performs 2 x 27 x cin x
     # cout multiply-adds per position of each 3x3x3 convolution, 2 x 16 for
     # the 1x1x1 head.
     wx = next((w for w in (4, 2) if wl.shape[2] % (w * 128) == 0), 1)
@@ -229,8 +231,10 @@ def main():
     levels_of = [0, 1, 2, 2, 1, 0, 0]       # the level each convolution of the 3-level network runs on
     for (ci, co), lv, nt in zip(shapes, levels_of, nfa.unet_taps(3)):
         unet_flop += 2 * nt * ci * co * (wl.ncells // 8 ** lv)
-    meta = {"f32": ("hbm", 36, "k_cg_a<float, 4, 1, false>"), "f32_flex": ("hbm", 40, "k_cg_a<float, 4, 1, true>"),
-            "f64": ("hbm", 72, f"k_cg_a<double, 2, {wx}, false>"),
+    meta = {"f32": ("hbm", 28, "k_cg_a<float, 4, 1, false, 0>"), "f32_x2": ("hbm", 40, "k_cg_a<float, 4, 1, false, 2>"),
+            "f32_flex": ("hbm", 40, "k_cg_a<float, 4, 1, true, 1>"),
+            "f64": ("hbm", 56, f"k_cg_a<double, 2, {wx}, false, 0>"),
+            "f64_x2": ("hbm", 80, f"k_cg_a<double, 2, {wx}, false, 2>"),
             "unet": ("mfma", None, "network application (k_tconv x6; the head in the last one)")}
     entries = {}
     for k, ks in kinds.items():

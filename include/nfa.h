@@ -399,14 +399,19 @@ nfa_status nfa_poisson_solve(nfa_poisson op, const double* b, double* x, const n
 #define NFA_PROF_MG_UP 3
 #define NFA_PROF_F32_FLEX 4 /* sweep A of the flexible (FCG) FP32 iteration */
 #define NFA_PROF_UNET 5     /* one application of the learned preconditioner */
+#define NFA_PROF_F64_X2 6   /* FP64 Jacobi-PCG sweep A applying two owed x steps */
+#define NFA_PROF_F32_X2 7   /* FP32 Jacobi-PCG sweep A applying two owed x steps */
 typedef struct {
   long long launches; /* stencil launches timed */
   double ms;          /* their summed duration */
   long long cells;    /* cells swept per launch */
 } nfa_kernel_stats;
 nfa_status nfa_poisson_profile(nfa_poisson op, int enable);
-/* dtype NFA_F64 or NFA_F32: sweep A of that precision (NFA_F32: the PCG
- * form); NFA_PROF_F32_FLEX: the flexible FP32 sweep A; NFA_PROF_MG_DOWN /
+/* dtype NFA_F64 or NFA_F32: the Jacobi-PCG sweep A of that precision that
+ * leaves x alone (every other iteration); NFA_PROF_F64_X2 / NFA_PROF_F32_X2:
+ * the one in between, which applies the two owed x steps (Jacobi-PCG defers
+ * the x update over two iterations); NFA_PROF_F32_FLEX: the flexible FP32
+ * sweep A (x updated every iteration); NFA_PROF_MG_DOWN /
  * NFA_PROF_MG_UP: the V-cycle's fused level-0 sweeps (FP32); NFA_PROF_UNET:
  * whole applications of the learned preconditioner.  Synchronous. */
 nfa_status nfa_poisson_profile_read(nfa_poisson op, int dtype, nfa_kernel_stats* out);

@@ -166,17 +166,18 @@ struct Poisson {
   SolveScalars* h_scal = nullptr;               // pinned host mirror (2 slots)
   hipEvent_t ev[2] = {nullptr, nullptr};
   // optional timing of selected launches inside solves (HIP events), by
-  // kind: 0 / 1 sweep A in FP64 / FP32, 2 / 3 the multigrid cycle's fused
-  // level-0 down / up sweep (FP32), 4 the flexible FP32 sweep A, 5 one whole
-  // application of the learned preconditioner
+  // kind: 0 / 1 the Jacobi-PCG sweep A that leaves x alone in FP64 / FP32,
+  // 6 / 7 the one that applies the two owed x steps, 2 / 3 the multigrid
+  // cycle's fused level-0 down / up sweep (FP32), 4 the flexible FP32 sweep A,
+  // 5 one whole application of the learned preconditioner
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;              // 2 per recorded launch
   std::vector<int> prof_kind;                   // kind per recorded launch
   std::vector<int> prof_seq;                    // iteration (since the last harvest) per recorded launch
   int prof_used = 0;
   int prof_iter = 0;                            // iterations enqueued since the last harvest
-  long long prof_launches[6] = {0, 0, 0, 0, 0, 0};
-  double prof_ms[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  long long prof_launches[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double prof_ms[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   Coeffs<double> c64() const {
     return {tx64.as<double>(), txb64.as<double>(), ty64.as<double>(), tz64.as<double>(), dinv64.as<double>()};
   }
@@ -185,7 +186,8 @@ struct Poisson {
   }
 };
 
-constexpr int kProfMgDown = 2, kProfMgUp = 3, kProfF32Flex = 4, kProfUnet = 5, kProfKinds = 6;
+constexpr int kProfMgDown = 2, kProfMgUp = 3, kProfF32Flex = 4, kProfUnet = 5, kProfF64X2 = 6, kProfF32X2 = 7,
+              kProfKinds = 8;
 
 // The operator holds coefficients of its grid's current body: assembled, and
 // no nfa_grid_set_body since (a new body changes the apertures, the active

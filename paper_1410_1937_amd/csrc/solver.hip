@@ -49,7 +49,8 @@ int timed_cg_a(Poisson& op, CG<T>& B, int j, bool flex, int xm, hipStream_t st) 
   T* pnew = flex ? B.p[(j + 1) & 1] : B.p[(j + 1) % 3];
   const int np = launch_cg_a<T>(*op.g, B.C, B.z, pold, pold2, pnew, B.x, B.r, B.q, op.partials.as<double>(),
                                 op.scal.as<SolveScalars>(), flex, xm, B.vec, st);
-  prof_end(op, rec, sizeof(T) == 8 ? 0 : (flex ? kProfF32Flex : 1), st);
+  const int kind = sizeof(T) == 8 ? (xm == 2 ? kProfF64X2 : 0) : (flex ? kProfF32Flex : (xm == 2 ? kProfF32X2 : 1));
+  prof_end(op, rec, kind, st);
   return np;
 }
 

@@ -21,6 +21,7 @@ NFA_NOT_CONVERGED = 1
 NFA_F64, NFA_F32, NFA_BF16 = 0, 1, 2
 NFA_PROF_MG_DOWN, NFA_PROF_MG_UP = 2, 3
 NFA_PROF_F32_FLEX, NFA_PROF_UNET = 4, 5
+NFA_PROF_F64_X2, NFA_PROF_F32_X2 = 6, 7
 NFA_PC_JACOBI, NFA_PC_UNET, NFA_PC_TEST_SABOTAGE, NFA_PC_JACOBI_FCG, NFA_PC_MG = 1, 2, 3, 4, 5
 NFA_PREC_F64, NFA_PREC_MIXED = 0, 1
 
@@ -583,7 +584,8 @@ class Poisson:
     def profile_read(self, dtype):
         ks = KernelStats()
         code = {"f64": NFA_F64, "f32": NFA_F32, "mg_down": NFA_PROF_MG_DOWN, "mg_up": NFA_PROF_MG_UP,
-                "f32_flex": NFA_PROF_F32_FLEX, "unet": NFA_PROF_UNET}[dtype]
+                "f32_flex": NFA_PROF_F32_FLEX, "unet": NFA_PROF_UNET, "f64_x2": NFA_PROF_F64_X2,
+                "f32_x2": NFA_PROF_F32_X2}[dtype]
         _check(lib.nfa_poisson_profile_read(self.h, code, ctypes.byref(ks)), "nfa_poisson_profile_read")
         return {"launches": ks.launches, "ms": ks.ms, "cells": ks.cells}
 
