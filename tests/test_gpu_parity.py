@@ -209,6 +209,31 @@ def test_failure_paths():
     assert res2.iterations == 0 and res2.relres <= 1e-8
 
 
+@pytest.mark.parametrize("name", ["wx4_sphere_neumann", "wx2_sphere_dirichlet_top"])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 7, 8])
+def test_solve_cut_off_after_n_iterations_returns_the_oracle_iterate(name, n):
+    """Jacobi-PCG defers its x update over two iterations (every other sweep
+    leaves x alone and the next applies both owed steps); a solve stopped
+    after n iterations, n odd or even, must return PCG's n-th iterate.
+    Compared through the residual b' - A'x of the oracle's operator, which
+    does not depend on the gauge."""
+    wl = CASES[name]
+    og, ob, oop, ob_rhs = oracle_for(wl)
+    gg, gop = gpu_for(wl)
+    b = _gpu_b(wl, gop)
+    ref = solvers.pcg(oop, ob_rhs, tol=1e-30, maxit=n)
+    assert ref.iterations == n
+    r_ref = ob_rhs - oop.apply(ref.x)
+    x, res = gop.solve(b, tol=1e-30, precision="f64", max_iters=n)
+    assert res.status == 1 and res.iterations == n
+    assert rel_l2(ob_rhs - oop.apply(host(x)), r_ref) <= 1e-11
+    # the FP32 recursion folds its increment (the owed steps applied) into
+    # the FP64 solution when it stops: the same iterate to FP32 rounding
+    xm, resm = gop.solve(b, tol=1e-30, precision="mixed", max_iters=n)
+    assert resm.status == 1 and resm.iterations == n
+    assert rel_l2(ob_rhs - oop.apply(host(xm)), r_ref) <= 1e-4
+
+
 def test_solves_are_bitwise_reproducible():
     wl = fx.small(4, 50, 30, 22, body="sphere")
     gg, gop = gpu_for(wl)
