@@ -291,15 +291,17 @@ __global__ __launch_bounds__(kBlock) void k_cg_b(long long nvec, T* __restrict__
 
 // the x updates still owed when the iteration stopped: x += alpha_pend p, or
 // with p2 (Jacobi-PCG) x = (x + alpha_pend2 p2) + alpha_pend p, the order of
-// sweep A's two-step update
+// sweep A's two-step update.  p2 is not read when nothing is owed on it: a
+// phase stopped before its second iteration has never written that buffer.
 template <class T>
 __global__ void k_cg_fixup(long long n, T* __restrict__ x, const T* __restrict__ p, const T* __restrict__ p2,
                            const SolveScalars* __restrict__ sc) {
   const T a = (T)sc->alpha_pend;
   const T a2 = (T)sc->alpha_pend2;
+  const bool two = p2 && a2 != T(0);
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
-    x[i] = p2 ? (x[i] + a2 * p2[i]) + a * p[i] : x[i] + a * p[i];
+    x[i] = two ? (x[i] + a2 * p2[i]) + a * p[i] : x[i] + a * p[i];
 }
 
 // x64 += x32 * inv_scale; x32 = 0
