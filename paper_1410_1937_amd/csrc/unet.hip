@@ -787,6 +787,226 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   }
 }
 
+// ------------------------------------------------------------ z-marching form of the finest decoder
+// The 16 -> 16 decoder with the skip sum bf16(a0 + up(d1)) and the head in
+// its epilogue, on runs of ZB bricks stacked in z, one run per workgroup.
+// Consecutive bricks of a run share two halo planes: after the first brick
+// they are moved inside LDS (planes 4, 5 -> 0, 1) and only the four new planes
+// are loaded and summed, a third fewer per output than separate bricks.  The
+// brick, its LDS layout, the multiply and the epilogue are those of k_tconv,
+// so the result is bitwise its.  Per brick: the new planes' loads and the
+// moved planes' LDS reads are issued first, one barrier ends every
+// wavefront's reads of the previous brick, the LDS writes follow, and a
+// second barrier opens the multiply.
+template <int ZB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_tconv_zm(const TconvArgs a) {
+  if (solve_done(a.sc)) return;
+  constexpr int CIN = 16;
+  constexpr int KC = (27 * CIN + 31) / 32;          // 14 chunks: two taps of 16 channels each
+  constexpr int kTY = Brick<1>::TY, kTZ = Brick<1>::TZ, kHY = Brick<1>::HY, HY = kHY;
+  constexpr int kHalo = Brick<1>::HALO;
+  constexpr int ST = lds_stride<CIN>();             // 32 bytes per staged position
+  constexpr int CPP = CIN / 8;                      // 16-byte chunks per position
+  constexpr int RCH = kHX * CPP;                    // chunks per halo row
+  constexpr int PLANE = kHX * kHY;                  // positions per halo plane
+  constexpr int NSH = 2 * PLANE * ST / 16;          // chunks of the two moved planes
+  constexpr int NITS = (NSH + 255) / 256;
+  __shared__ __align__(16) unsigned char lds[kHalo * ST];
+  // runs in contiguous ranges per XCD (workgroups are dealt to the XCDs round robin)
+  const int item = (int)(blockIdx.x & 7) * a.per + (int)(blockIdx.x >> 3);
+  if (item >= a.nb) return;
+  const int D = a.D, H = a.H, W = a.W, H2 = H >> 1, W2 = W >> 1;
+  const int nbz = (D + kTZ - 1) / kTZ;
+  const int bx = item % a.nbx, rest = item / a.nbx;
+  const int x0b = bx * kTX, y0b = (rest % a.nby) * kTY;
+  const int zb0 = (rest / a.nby) * ZB;              // the run's first brick in z
+  const int nrun = min(ZB, nbz - zb0);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int n = lane & 15, kq = lane >> 4;
+  float bi[4], wp[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    bi[i] = a.bias[4 * kq + i];
+    wp[i] = a.z ? a.wproj[4 * kq + i] : 0.f;
+  }
+  const float pb = a.z ? a.pbias[0] : 0.f;
+  const double rr = a.z ? *a.rr : 0.0;
+  // the wavefront's 2 x 2 block of rows and the staged offset of its lane's
+  // output position in each
+  const int yw = 2 * (wv & 1), zw = 2 * (wv >> 1);
+  int bj[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) bj[j] = (((zw + (j >> 1) + 1) * kHY + (yw + (j & 1) + 1)) * kHX + (n + 1)) * ST;
+
+  // halo planes [P0, 6) of the brick whose first output plane is z0b: loads
+  // into registers (issue), then bf16(a0 + up(d1)) into LDS (commit)
+  constexpr int NE0 = 6 * kHY * RCH, NIT0 = (NE0 + 255) / 256;
+  uint4 v[NIT0], c[NIT0];
+  int lo[NIT0];
+  auto issue = [&](auto p0c, int z0b) {
+    constexpr int P0 = decltype(p0c)::value;
+    constexpr int NE = (6 - P0) * kHY * RCH;
+    constexpr int NIT = (NE + 255) / 256;
+    // the slots' offsets are the same for every brick; formed again here
+    // from an opaque copy of the thread index, since held across the run
+    // they would cost more registers than the arithmetic costs issue slots
+    int t0 = tid;
+    asm volatile("" : "+v"(t0));
+#pragma unroll
+    for (int it = 0; it < NIT0; ++it) {
+      const int e = t0 + it * 256;
+      const bool in = it < NIT && e < NE;
+      const int r0 = e / RCH, rc = e - r0 * RCH;
+      const int row = r0 + P0 * kHY;
+      const int hx = rc / CPP, c8 = rc - hx * CPP;
+      const int hy = row % kHY, hz = row / kHY;
+      const int gx = x0b - 1 + hx, gy = y0b - 1 + hy, gz = z0b - 1 + hz;
+      const bool ok = in && (unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H && (unsigned)gz < (unsigned)D;
+      lo[it] = in ? (row * kHX + hx) * ST + c8 * 16 : -1;
+      v[it] = make_uint4(0u, 0u, 0u, 0u);
+      c[it] = make_uint4(0u, 0u, 0u, 0u);
+      if (ok) {
+        const unsigned pe = ((unsigned)(gz * H + gy) * (unsigned)W + (unsigned)gx) * CIN + c8 * 8;
+        const unsigned qe =
+            ((unsigned)((gz >> 1) * H2 + (gy >> 1)) * (unsigned)W2 + (unsigned)(gx >> 1)) * CIN + c8 * 8;
+        v[it] = *reinterpret_cast<const uint4*>(a.in + pe);
+        c[it] = *reinterpret_cast<const uint4*>(a.in2 + qe);
+      }
+    }
+  };
+  auto commit = [&]() {
+#pragma unroll
+    for (int it = 0; it < NIT0; ++it) {
+      if (lo[it] >= 0) {
+        uint4 w = v[it];
+        w.x = add_bf2(w.x, c[it].x);
+        w.y = add_bf2(w.y, c[it].y);
+        w.z = add_bf2(w.z, c[it].z);
+        w.w = add_bf2(w.w, c[it].w);
+        *reinterpret_cast<uint4*>(lds + lo[it]) = w;
+      }
+    }
+  };
+
+  for (int i = 0; i < nrun; ++i) {
+    const int z0b = (zb0 + i) * kTZ;
+    // the head's inputs at this lane's output position (row kq of the block)
+    long long hp = -1;
+    float hr = 0.f, hd = 0.f;
+    if (a.z) {
+      const int x = x0b + n, y = y0b + yw + (kq & 1), z = z0b + zw + (kq >> 1);
+      if (x < W && y < H && z < D) {
+        hp = ((long long)z * H + y) * W + x;
+        hr = a.r[hp];
+        hd = a.dinv[hp];
+      }
+    }
+    if (i == 0) {
+      issue(std::integral_constant<int, 0>{}, z0b);
+      commit();
+    } else {
+      uint4 sh[NITS];
+      issue(std::integral_constant<int, 2>{}, z0b);
+#pragma unroll
+      for (int k = 0; k < NITS; ++k) {
+        const int e = tid + k * 256;
+        sh[k] = make_uint4(0u, 0u, 0u, 0u);
+        if (e < NSH) sh[k] = *reinterpret_cast<const uint4*>(lds + 4 * PLANE * ST + e * 16);
+      }
+      __syncthreads();   // every wavefront is done reading the previous brick
+#pragma unroll
+      for (int k = 0; k < NITS; ++k) {
+        const int e = tid + k * 256;
+        if (e < NSH) *reinterpret_cast<uint4*>(lds + e * 16) = sh[k];
+      }
+      commit();
+    }
+    __syncthreads();
+    // keep each phase's registers to itself: without these fences the
+    // scheduler overlaps the staging and the multiply and the registers double
+    __builtin_amdgcn_sched_barrier(0);
+
+    // ---- K chunks, unrolled so that every tap offset is an immediate; A from
+    // the packed fragments one chunk ahead, B from LDS one chunk ahead
+    f32x4 acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    auto load_b = [&](auto kcc, Frag (&B)[4]) {
+      constexpr int kc = decltype(kcc)::value;
+      constexpr int t0 = 2 * kc, t1 = 2 * kc + 1 < 27 ? 2 * kc + 1 : 26;
+      const int sel = (kq >> 1) ? (tap_halo<HY>(t1) - tap_halo<HY>(t0)) * ST : 0;
+      const int lb = (kq & 1) * 16 + sel + tap_halo<HY>(t0) * ST;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) B[j].u = *reinterpret_cast<const uint4*>(lds + bj[j] + lb);
+    };
+    // the A fragments are the same for every brick: reloaded (L1 / L2 hits)
+    // from an opaque copy of the lane index rather than held across the run,
+    // which costs 56 registers (193 against 121, two resident wavefronts per
+    // SIMD against four)
+    int lv = lane;
+    asm volatile("" : "+v"(lv));
+    const uint4* fr = a.frag + lv;
+    Frag An, Bn[4];
+    An.u = fr[0];
+    load_b(std::integral_constant<int, 0>{}, Bn);
+    static_for<0, KC>([&](auto kcc) {
+      constexpr int kc = decltype(kcc)::value;
+      Frag A = An, B[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) B[j] = Bn[j];
+      if constexpr (kc + 1 < KC) {
+        An.u = fr[(kc + 1) * 64];
+        load_b(std::integral_constant<int, kc + 1>{}, Bn);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.v, B[j].v, acc[j], 0, 0, 0);
+    });
+
+    // ---- epilogue: bias, ReLU, the BF16 storage rounding; the output (when
+    // kept) and the head z = dinv (x0[.,0] + (b + w . out))
+    unsigned pk[4][2];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      pk[j][0] = pack_bf2(fmaxf(acc[j][0] + bi[0], 0.f), fmaxf(acc[j][1] + bi[1], 0.f));
+      pk[j][1] = pack_bf2(fmaxf(acc[j][2] + bi[2], 0.f), fmaxf(acc[j][3] + bi[3], 0.f));
+      acc[j][0] = lo_bf(pk[j][0]);
+      acc[j][1] = hi_bf(pk[j][0]);
+      acc[j][2] = lo_bf(pk[j][1]);
+      acc[j][3] = hi_bf(pk[j][1]);
+    }
+    const int x = x0b + n;
+    if (a.out) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int y = y0b + yw + (j & 1), z = z0b + zw + (j >> 1);
+        if (x < W && y < H && z < D) {
+          const long long p = ((long long)z * H + y) * W + x;
+          *reinterpret_cast<uint2*>(a.out + p * 16 + 4 * kq) = make_uint2(pk[j][0], pk[j][1]);
+        }
+      }
+    }
+    if (a.z) {
+      const double ms = rr / a.nred;
+      const double inv = ms > 0 ? 1.0 / sqrt(ms) : 1.0;
+      float tk = 0.f;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float t = 0.f;
+#pragma unroll
+        for (int i2 = 0; i2 < 4; ++i2) t += wp[i2] * acc[j][i2];
+        t += __shfl_xor(t, 16);
+        t += __shfl_xor(t, 32);
+        if (kq == j) tk = t;
+      }
+      if (hp >= 0) {
+        const float x00 = __uint_as_float((unsigned)f2bf((float)((double)hr * inv)) << 16);
+        a.z[hp] = hd * ((x00 + pb) + tk);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 // ------------------------------------------------------------ weight gradient (MFMA)
 // partial[t][blk][ci][co] = sum over this workgroup's positions m of
 //   in'[m + off_t][ci] * dout[m][co]
@@ -1207,8 +1427,19 @@ template <int COUT> void tconv_pipe_t(TconvArgs a, hipStream_t s) {
   k_tconv_pipe<COUT><<<8 * g8, 256, 0, s>>>(a);
 }
 
+// runs of ZB bricks in z, one per workgroup
+template <int ZB> void tconv_zm_t(TconvArgs a, hipStream_t s) {
+  a.nbx = (a.W + kTX - 1) / kTX;
+  a.nby = (a.H + Brick<1>::TY - 1) / Brick<1>::TY;
+  const int nbz = (a.D + Brick<1>::TZ - 1) / Brick<1>::TZ;
+  a.nb = a.nbx * a.nby * ((nbz + ZB - 1) / ZB);
+  a.per = (a.nb + 7) / 8;
+  k_tconv_zm<ZB><<<8 * a.per, 256, 0, s>>>(a);
+}
+
 nfa_status tconv(int cin, int cout, bool upadd, const TconvArgs& a, hipStream_t s) {
   if (cin == 16 && cout == 32 && !upadd) { tconv_pipe_t<32>(a, s); return NFA_OK; }
+  if (cin == 16 && cout == 16 && upadd && !a.pooled) { tconv_zm_t<8>(a, s); return NFA_OK; }
 #define T_(A, B, U) \
   if (cin == A && cout == B && upadd == U) { tconv_t<A, B, U, false>(a, s); return NFA_OK; }
   T_(32, 64, false) T_(64, 64, false) T_(64, 32, false)

@@ -100,6 +100,35 @@ def test_pipelined_encoder_over_many_bricks_per_workgroup():
     _ulp_ok(_bf(net.export("p1")), ou.bf16(ou.pool(a1)))
 
 
+def test_finest_decoder_over_runs_of_bricks_in_z():
+    """The finest decoder walks runs of up to eight bricks up each column,
+    moving the two halo planes that consecutive bricks share inside LDS: on
+    40 x 20 x 76 cells a column holds 19 bricks (runs of 8, 8 and 3) and the
+    bricks are ragged in x.  Fed the GPU's own skip and coarser decoder
+    output, its output is within one BF16 step of the oracle's layer and the
+    head's z follows from it."""
+    from paper_1410_1937_amd import nfa
+    wl = fx.small(13, 40, 20, 76, body="sphere")
+    og, ob, oop, ob_rhs = oracle_for(wl)
+    gg, gop = gpu_for(wl)
+    net = nfa.UNet(40, 20, 76, seed=6)
+    rng = np.random.default_rng(31)
+    params = ou.init_params(29, zero_last=False)
+    params = [(w.astype(np.float32), (rng.standard_normal(b.shape) * 0.05).astype(np.float32)) for w, b in params]
+    net.set_params(nfa.UNet.flatten(params))
+    P = [(ou.bf16(w.astype(np.float64)), b.astype(np.float64)) for w, b in params]
+    r = (ob_rhs * ob.reduced).astype(np.float32)
+    z = host(net.forward(gop, torch.as_tensor(r, device="cuda"), keep=True)).astype(np.float64)
+    a0 = _bf(net.export("a0"))
+    d1 = _bf(net.export("d1"))
+    d0 = _bf(net.export("d0"))
+    _ulp_ok(d0, ou.bf16(ou.relu(ou.conv3d(ou.bf16(ou.up(d1) + a0), *P[5]))))
+    x0 = _bf(net.export("x0"))
+    w6, b6 = P[6]
+    zref = oop.dinv * (x0[..., 0] + (b6[0] + d0 @ w6[0][:, 0]))
+    assert np.max(np.abs(z - zref)) <= 1e-5 * np.max(np.abs(zref))
+
+
 def test_whole_forward_matches_oracle(setup):
     wl, (og, ob, oop, _), (gg, gop), net, params, r, rt, z = setup
     x0, s = ou.features(r.astype(np.float64), 1.0 / oop.rho, ob.reduced)
