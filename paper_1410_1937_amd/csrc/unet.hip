@@ -787,25 +787,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   }
 }
 
-// ------------------------------------------------------------ z-marching form of the finest decoder
-// The 16 -> 16 decoder with the skip sum bf16(a0 + up(d1)) and the head in
-// its epilogue, on runs of ZB bricks stacked in z, one run per workgroup.
-// Consecutive bricks of a run share two halo planes: after the first brick
-// they are moved inside LDS (planes 4, 5 -> 0, 1) and only the four new planes
-// are loaded and summed, a third fewer per output than separate bricks.  The
-// brick, its LDS layout, the multiply and the epilogue are those of k_tconv,
-// so the result is bitwise its.  Per brick: the new planes' loads and the
-// moved planes' LDS reads are issued first, one barrier ends every
+// ------------------------------------------------------------ z-marching form of the decoders
+// The CIN -> 16 decoders with the skip sum bf16(a_l + up(d_(l+1))) (and, on
+// the finest level, the head in the epilogue), on runs of ZB bricks stacked
+// in z, one run per workgroup.  Consecutive bricks of a run share two halo
+// planes: after the first brick they are moved inside LDS (planes 4, 5 ->
+// 0, 1) and only the four new planes are loaded and summed, a third fewer
+// per output than separate bricks.  The brick, its LDS layout, the multiply
+// and the epilogue are those of k_tconv, so the result is bitwise its.  Per
+// brick: the moved planes' LDS reads (and the new planes' loads, when they
+// fit in one batch of registers) are issued first, one barrier ends every
 // wavefront's reads of the previous brick, the LDS writes follow, and a
 // second barrier opens the multiply.
-template <int ZB>
+template <int CIN, int ZB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_tconv_zm(const TconvArgs a) {
   if (solve_done(a.sc)) return;
-  constexpr int CIN = 16;
-  constexpr int KC = (27 * CIN + 31) / 32;          // 14 chunks: two taps of 16 channels each
+  static_assert(CIN == 16 || CIN == 32, "one staged group of 16 or 32 channels");
+  constexpr int KC = (27 * CIN + 31) / 32;          // K chunks: two taps of 16 channels, or one of 32
   constexpr int kTY = Brick<1>::TY, kTZ = Brick<1>::TZ, kHY = Brick<1>::HY, HY = kHY;
   constexpr int kHalo = Brick<1>::HALO;
-  constexpr int ST = lds_stride<CIN>();             // 32 bytes per staged position
+  constexpr int ST = lds_stride<CIN>();             // bytes per staged position
   constexpr int CPP = CIN / 8;                      // 16-byte chunks per position
   constexpr int RCH = kHX * CPP;                    // chunks per halo row
   constexpr int PLANE = kHX * kHY;                  // positions per halo plane
@@ -838,13 +839,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
   for (int j = 0; j < 4; ++j) bj[j] = (((zw + (j >> 1) + 1) * kHY + (yw + (j & 1) + 1)) * kHX + (n + 1)) * ST;
 
-  // halo planes [P0, 6) of the brick whose first output plane is z0b: loads
-  // into registers (issue), then bf16(a0 + up(d1)) into LDS (commit)
-  constexpr int NE0 = 6 * kHY * RCH, NIT0 = (NE0 + 255) / 256;
-  uint4 v[NIT0], c[NIT0];
-  int lo[NIT0];
-  auto issue = [&](auto p0c, int z0b) {
-    constexpr int P0 = decltype(p0c)::value;
+  // halo planes [P0, 6) of the brick whose first output plane is z0b, in
+  // batches of BATCH chunks per thread: loads into registers (issue), then
+  // the skip sum into LDS (commit)
+  constexpr int BATCH = 6;
+  uint4 v[BATCH], c[BATCH];
+  int lo[BATCH];
+  auto issue = [&](auto p0c, auto b0c, int z0b) {
+    constexpr int P0 = decltype(p0c)::value, B0 = decltype(b0c)::value;
     constexpr int NE = (6 - P0) * kHY * RCH;
     constexpr int NIT = (NE + 255) / 256;
     // the slots' offsets are the same for every brick; formed again here
@@ -853,7 +855,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     int t0 = tid;
     asm volatile("" : "+v"(t0));
 #pragma unroll
-    for (int it = 0; it < NIT0; ++it) {
+    for (int ib = 0; ib < BATCH; ++ib) {
+      const int it = B0 + ib;
       const int e = t0 + it * 256;
       const bool in = it < NIT && e < NE;
       const int r0 = e / RCH, rc = e - r0 * RCH;
@@ -862,30 +865,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       const int hy = row % kHY, hz = row / kHY;
       const int gx = x0b - 1 + hx, gy = y0b - 1 + hy, gz = z0b - 1 + hz;
       const bool ok = in && (unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H && (unsigned)gz < (unsigned)D;
-      lo[it] = in ? (row * kHX + hx) * ST + c8 * 16 : -1;
-      v[it] = make_uint4(0u, 0u, 0u, 0u);
-      c[it] = make_uint4(0u, 0u, 0u, 0u);
+      lo[ib] = in ? (row * kHX + hx) * ST + c8 * 16 : -1;
+      v[ib] = make_uint4(0u, 0u, 0u, 0u);
+      c[ib] = make_uint4(0u, 0u, 0u, 0u);
       if (ok) {
         const unsigned pe = ((unsigned)(gz * H + gy) * (unsigned)W + (unsigned)gx) * CIN + c8 * 8;
         const unsigned qe =
             ((unsigned)((gz >> 1) * H2 + (gy >> 1)) * (unsigned)W2 + (unsigned)(gx >> 1)) * CIN + c8 * 8;
-        v[it] = *reinterpret_cast<const uint4*>(a.in + pe);
-        c[it] = *reinterpret_cast<const uint4*>(a.in2 + qe);
+        v[ib] = *reinterpret_cast<const uint4*>(a.in + pe);
+        c[ib] = *reinterpret_cast<const uint4*>(a.in2 + qe);
       }
     }
   };
   auto commit = [&]() {
 #pragma unroll
-    for (int it = 0; it < NIT0; ++it) {
-      if (lo[it] >= 0) {
-        uint4 w = v[it];
-        w.x = add_bf2(w.x, c[it].x);
-        w.y = add_bf2(w.y, c[it].y);
-        w.z = add_bf2(w.z, c[it].z);
-        w.w = add_bf2(w.w, c[it].w);
-        *reinterpret_cast<uint4*>(lds + lo[it]) = w;
+    for (int ib = 0; ib < BATCH; ++ib) {
+      if (lo[ib] >= 0) {
+        uint4 w = v[ib];
+        w.x = add_bf2(w.x, c[ib].x);
+        w.y = add_bf2(w.y, c[ib].y);
+        w.z = add_bf2(w.z, c[ib].z);
+        w.w = add_bf2(w.w, c[ib].w);
+        *reinterpret_cast<uint4*>(lds + lo[ib]) = w;
       }
     }
+  };
+  // every batch of planes [P0, 6): issue, commit
+  auto stage = [&](auto p0c, int z0b) {
+    constexpr int P0 = decltype(p0c)::value;
+    constexpr int NIT = ((6 - P0) * kHY * RCH + 255) / 256;
+    static_for<0, (NIT + BATCH - 1) / BATCH>([&](auto bb) {
+      issue(p0c, std::integral_constant<int, decltype(bb)::value * BATCH>{}, z0b);
+      commit();
+    });
   };
 
   for (int i = 0; i < nrun; ++i) {
@@ -901,12 +913,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         hd = a.dinv[hp];
       }
     }
+    constexpr int NIT4 = ((6 - 2) * kHY * RCH + 255) / 256;   // slots of the four new planes
     if (i == 0) {
-      issue(std::integral_constant<int, 0>{}, z0b);
-      commit();
+      stage(std::integral_constant<int, 0>{}, z0b);
     } else {
       uint4 sh[NITS];
-      issue(std::integral_constant<int, 2>{}, z0b);
+      if constexpr (NIT4 <= BATCH) issue(std::integral_constant<int, 2>{}, std::integral_constant<int, 0>{}, z0b);
 #pragma unroll
       for (int k = 0; k < NITS; ++k) {
         const int e = tid + k * 256;
@@ -919,7 +931,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         const int e = tid + k * 256;
         if (e < NSH) *reinterpret_cast<uint4*>(lds + e * 16) = sh[k];
       }
-      commit();
+      if constexpr (NIT4 <= BATCH) commit();
+      else stage(std::integral_constant<int, 2>{}, z0b);
     }
     __syncthreads();
     // keep each phase's registers to itself: without these fences the
@@ -933,11 +946,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
     auto load_b = [&](auto kcc, Frag (&B)[4]) {
       constexpr int kc = decltype(kcc)::value;
-      constexpr int t0 = 2 * kc, t1 = 2 * kc + 1 < 27 ? 2 * kc + 1 : 26;
-      const int sel = (kq >> 1) ? (tap_halo<HY>(t1) - tap_halo<HY>(t0)) * ST : 0;
-      const int lb = (kq & 1) * 16 + sel + tap_halo<HY>(t0) * ST;
+      if constexpr (CIN == 16) {
+        // a chunk holds two taps of 16 channels: lanes kq < 2 the even one
+        constexpr int t0 = 2 * kc, t1 = 2 * kc + 1 < 27 ? 2 * kc + 1 : 26;
+        const int sel = (kq >> 1) ? (tap_halo<HY>(t1) - tap_halo<HY>(t0)) * ST : 0;
+        const int lb = (kq & 1) * 16 + sel + tap_halo<HY>(t0) * ST;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) B[j].u = *reinterpret_cast<const uint4*>(lds + bj[j] + lb);
+        for (int j = 0; j < 4; ++j) B[j].u = *reinterpret_cast<const uint4*>(lds + bj[j] + lb);
+      } else {
+        // a chunk is one tap of the 32 channels
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          B[j].u = *reinterpret_cast<const uint4*>(lds + bj[j] + kq * 16 + tap_halo<HY>(kc) * ST);
+      }
     };
     // the A fragments are the same for every brick: reloaded (L1 / L2 hits)
     // from an opaque copy of the lane index rather than held across the run,
@@ -1428,18 +1449,19 @@ template <int COUT> void tconv_pipe_t(TconvArgs a, hipStream_t s) {
 }
 
 // runs of ZB bricks in z, one per workgroup
-template <int ZB> void tconv_zm_t(TconvArgs a, hipStream_t s) {
+template <int CIN, int ZB> void tconv_zm_t(TconvArgs a, hipStream_t s) {
   a.nbx = (a.W + kTX - 1) / kTX;
   a.nby = (a.H + Brick<1>::TY - 1) / Brick<1>::TY;
   const int nbz = (a.D + Brick<1>::TZ - 1) / Brick<1>::TZ;
   a.nb = a.nbx * a.nby * ((nbz + ZB - 1) / ZB);
   a.per = (a.nb + 7) / 8;
-  k_tconv_zm<ZB><<<8 * a.per, 256, 0, s>>>(a);
+  k_tconv_zm<CIN, ZB><<<8 * a.per, 256, 0, s>>>(a);
 }
 
 nfa_status tconv(int cin, int cout, bool upadd, const TconvArgs& a, hipStream_t s) {
   if (cin == 16 && cout == 32 && !upadd) { tconv_pipe_t<32>(a, s); return NFA_OK; }
-  if (cin == 16 && cout == 16 && upadd && !a.pooled) { tconv_zm_t<8>(a, s); return NFA_OK; }
+  if (cin == 16 && cout == 16 && upadd && !a.pooled) { tconv_zm_t<16, 8>(a, s); return NFA_OK; }
+  if (cin == 32 && cout == 16 && upadd && !a.pooled) { tconv_zm_t<32, 8>(a, s); return NFA_OK; }
 #define T_(A, B, U) \
   if (cin == A && cout == B && upadd == U) { tconv_t<A, B, U, false>(a, s); return NFA_OK; }
   T_(32, 64, false) T_(64, 64, false) T_(64, 32, false)

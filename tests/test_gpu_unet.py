@@ -100,13 +100,14 @@ def test_pipelined_encoder_over_many_bricks_per_workgroup():
     _ulp_ok(_bf(net.export("p1")), ou.bf16(ou.pool(a1)))
 
 
-def test_finest_decoder_over_runs_of_bricks_in_z():
-    """The finest decoder walks runs of up to eight bricks up each column,
-    moving the two halo planes that consecutive bricks share inside LDS: on
-    40 x 20 x 76 cells a column holds 19 bricks (runs of 8, 8 and 3) and the
-    bricks are ragged in x.  Fed the GPU's own skip and coarser decoder
-    output, its output is within one BF16 step of the oracle's layer and the
-    head's z follows from it."""
+def test_decoders_over_runs_of_bricks_in_z():
+    """The 16- and 32-channel decoders walk runs of up to eight bricks up each
+    column, moving the two halo planes that consecutive bricks share inside
+    LDS: on 40 x 20 x 76 cells a finest-level column holds 19 bricks (runs of
+    8, 8 and 3), a level-1 column 10 (8 and 2, the last brick half outside
+    the grid), and the bricks are ragged in x.  Fed the GPU's own skip and
+    coarser decoder output, each output is within one BF16 step of the
+    oracle's layer and the head's z follows from the finest one."""
     from paper_1410_1937_amd import nfa
     wl = fx.small(13, 40, 20, 76, body="sphere")
     og, ob, oop, ob_rhs = oracle_for(wl)
@@ -120,8 +121,11 @@ def test_finest_decoder_over_runs_of_bricks_in_z():
     r = (ob_rhs * ob.reduced).astype(np.float32)
     z = host(net.forward(gop, torch.as_tensor(r, device="cuda"), keep=True)).astype(np.float64)
     a0 = _bf(net.export("a0"))
+    a1 = _bf(net.export("a1"))
+    d2 = _bf(net.export("d2"))
     d1 = _bf(net.export("d1"))
     d0 = _bf(net.export("d0"))
+    _ulp_ok(d1, ou.bf16(ou.relu(ou.conv3d(ou.bf16(ou.up(d2) + a1), *P[4]))))
     _ulp_ok(d0, ou.bf16(ou.relu(ou.conv3d(ou.bf16(ou.up(d1) + a0), *P[5]))))
     x0 = _bf(net.export("x0"))
     w6, b6 = P[6]
