@@ -1460,7 +1460,10 @@ template <int CIN, int ZB> void tconv_zm_t(TconvArgs a, hipStream_t s) {
 
 nfa_status tconv(int cin, int cout, bool upadd, const TconvArgs& a, hipStream_t s) {
   if (cin == 16 && cout == 32 && !upadd) { tconv_pipe_t<32>(a, s); return NFA_OK; }
-  if (cin == 16 && cout == 16 && upadd && !a.pooled) { tconv_zm_t<16, 8>(a, s); return NFA_OK; }
+  // run lengths measured at 25M cells: the finest decoder 654 / 637 / 613 / 635
+  // us with runs of 4 / 8 / 16 / 24 bricks, the 32 -> 16 one 192 / 186 / 284 /
+  // 206 us (runs of 16 leave its level too few workgroups)
+  if (cin == 16 && cout == 16 && upadd && !a.pooled) { tconv_zm_t<16, 16>(a, s); return NFA_OK; }
   if (cin == 32 && cout == 16 && upadd && !a.pooled) { tconv_zm_t<32, 8>(a, s); return NFA_OK; }
 #define T_(A, B, U) \
   if (cin == A && cout == B && upadd == U) { tconv_t<A, B, U, false>(a, s); return NFA_OK; }

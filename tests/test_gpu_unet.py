@@ -101,11 +101,11 @@ def test_pipelined_encoder_over_many_bricks_per_workgroup():
 
 
 def test_decoders_over_runs_of_bricks_in_z():
-    """The 16- and 32-channel decoders walk runs of up to eight bricks up each
-    column, moving the two halo planes that consecutive bricks share inside
-    LDS: on 40 x 20 x 76 cells a finest-level column holds 19 bricks (runs of
-    8, 8 and 3), a level-1 column 10 (8 and 2, the last brick half outside
-    the grid), and the bricks are ragged in x.  Fed the GPU's own skip and
+    """The 16- and 32-channel decoders walk runs of up to 16 and 8 bricks up
+    each column, moving the two halo planes that consecutive bricks share
+    inside LDS: on 40 x 20 x 76 cells a finest-level column holds 19 bricks
+    (runs of 16 and 3), a level-1 column 10 (8 and 2, the last brick half
+    outside the grid), and the bricks are ragged in x.  Fed the GPU's own skip and
     coarser decoder output, each output is within one BF16 step of the
     oracle's layer and the head's z follows from the finest one."""
     from paper_1410_1937_amd import nfa
