@@ -204,8 +204,9 @@ typedef struct {
 /* nfa_poisson_workspace_bytes -- bytes of device workspace an operator on
  * grid g needs: its coefficients in FP64 and FP32 (3 face arrays and the
  * Jacobi inverse diagonal), the density, the work vectors of the FP64 and
- * FP32 solvers, reduction partials and the residual history (about 200 bytes
- * per cell).  0 for a NULL grid. */
+ * FP32 solvers, reduction partials and the residual history (about 150 bytes
+ * per cell: eleven FP64 and nine FP32 cell arrays and the face arrays).  0 for
+ * a NULL grid. */
 size_t nfa_poisson_workspace_bytes(nfa_grid g);
 
 /* nfa_poisson_create -- operator + solver state on grid g (the grid must
