@@ -813,9 +813,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   constexpr int NSH = 2 * PLANE * ST / 16;          // chunks of the two moved planes
   constexpr int NITS = (NSH + 255) / 256;
   __shared__ __align__(16) unsigned char lds[kHalo * ST];
+  // the 16-channel form keeps its A fragments in LDS for the whole run (the
+  // multiply then waits on LDS reads only); the 32-channel one reads them
+  // through the caches, since 27.6 KB more LDS would cost it a workgroup per CU
+  constexpr bool AL = CIN == 16;
+  __shared__ __align__(16) uint4 afr[AL ? KC * 64 : 1];
   // runs in contiguous ranges per XCD (workgroups are dealt to the XCDs round robin)
   const int item = (int)(blockIdx.x & 7) * a.per + (int)(blockIdx.x >> 3);
   if (item >= a.nb) return;
+  if constexpr (AL) {
+    for (int e = threadIdx.x; e < KC * 64; e += 256) afr[e] = a.frag[e];
+  }
   const int D = a.D, H = a.H, W = a.W, H2 = H >> 1, W2 = W >> 1;
   const int nbz = (D + kTZ - 1) / kTZ;
   const int bx = item % a.nbx, rest = item / a.nbx;
@@ -967,8 +975,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     int lv = lane;
     asm volatile("" : "+v"(lv));
     const uint4* fr = a.frag + lv;
+    auto load_a = [&](int kc) { return AL ? afr[kc * 64 + lane] : fr[kc * 64]; };
     Frag An, Bn[4];
-    An.u = fr[0];
+    An.u = load_a(0);
     load_b(std::integral_constant<int, 0>{}, Bn);
     static_for<0, KC>([&](auto kcc) {
       constexpr int kc = decltype(kcc)::value;
@@ -976,7 +985,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
       for (int j = 0; j < 4; ++j) B[j] = Bn[j];
       if constexpr (kc + 1 < KC) {
-        An.u = fr[(kc + 1) * 64];
+        An.u = load_a(kc + 1);
         load_b(std::integral_constant<int, kc + 1>{}, Bn);
       }
 #pragma unroll
