@@ -252,6 +252,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   constexpr int ST = lds_stride<CG>();
   static_assert(SUB == 1 || NG == 1, "several blocks per wavefront need a single staged group");
   __shared__ __align__(16) unsigned char lds[kHalo * ST];
+  // the first encoder's A fragments (2 KB) sit in LDS: its wavefronts take
+  // four blocks per brick, each reloading them
+  __shared__ __align__(16) uint4 afr[FEAT ? KC * MT * 64 : 1];
   // bricks in contiguous ranges per XCD (workgroups are dealt to the XCDs
   // round robin), so that neighbouring bricks share an L2
   const int b = (int)(blockIdx.x & 7) * a.per + (int)(blockIdx.x >> 3);
@@ -278,6 +281,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   Frag An[MT];
 #pragma unroll
   for (int m = 0; m < MT; ++m) An[m].u = fr[m * 64];
+  if constexpr (FEAT) {
+    for (int e = threadIdx.x; e < KC * MT * 64; e += 256) afr[e] = a.frag[e];
+  }
+  auto load_a = [&](int idx) -> uint4 {
+    if constexpr (FEAT) return afr[idx * 64 + lane];
+    else return fr[idx * 64];
+  };
 
 
   // ---- staging of channel group g's halo
@@ -461,7 +471,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         for (int j = 0; j < 4; ++j) B[j] = Bn[j];
         if constexpr (kc + 1 < KC) {
 #pragma unroll
-          for (int m = 0; m < MT; ++m) An[m].u = fr[((kc + 1) * MT + m) * 64];
+          for (int m = 0; m < MT; ++m) An[m].u = load_a((kc + 1) * MT + m);
         }
         if constexpr (kc + 1 < (g + 1) * KCG && kc + 1 < KC) load_b(std::integral_constant<int, kc + 1>{}, Bn);
 #pragma unroll
@@ -571,7 +581,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int s = 0; s < SUB * SUB; ++s) {
       if (s > 0) {
 #pragma unroll
-        for (int m = 0; m < MT; ++m) An[m].u = fr[m * 64];
+        for (int m = 0; m < MT; ++m) An[m].u = load_a(m);
       }
       set_block(s);
       compute(std::integral_constant<int, 0>{});
