@@ -599,9 +599,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // multiply loop, so the in-order vector memory counter never makes them wait
 // for the halo loads), then written to LDS between two barriers.  Bitwise the
 // result of k_tconv.  Measured at 25M cells: the 16 -> 32 encoder 165 -> 123
-// us; the 16 -> 16 decoder with its skip sum and head gained nothing (it is
-// bound by the VALU work of forming bf16(up(d1) + a0) for every halo copy,
-// not by the latency of loading it) and keeps k_tconv.
+// us; the 16 -> 16 decoder with its skip sum and head gained nothing in this
+// form (the skip sums of every halo copy dominate it) and runs on the
+// z-marching form below, which stages a third fewer of them.
 template <int COUT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_tconv_pipe(const TconvArgs a) {
   constexpr bool UPADD = false;
