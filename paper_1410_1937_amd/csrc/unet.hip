@@ -809,8 +809,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // fit in one batch of registers) are issued first, one barrier ends every
 // wavefront's reads of the previous brick, the LDS writes follow, and a
 // second barrier opens the multiply.
+// Registers are held to five wavefronts per SIMD (100 for the 16-channel
+// form, no spills); LDS then allows four and three workgroups per CU.
+// Measured at 25M cells: the finest decoder 559-575 against 578-585 us with
+// the registers unbounded (121).
 template <int CIN, int ZB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_tconv_zm(const TconvArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_tconv_zm(const TconvArgs a) {
   if (solve_done(a.sc)) return;
   static_assert(CIN == 16 || CIN == 32, "one staged group of 16 or 32 channels");
   constexpr int KC = (27 * CIN + 31) / 32;          // K chunks: two taps of 16 channels, or one of 32
@@ -978,10 +982,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
           B[j].u = *reinterpret_cast<const uint4*>(lds + bj[j] + kq * 16 + tap_halo<HY>(kc) * ST);
       }
     };
-    // the A fragments are the same for every brick: reloaded (L1 / L2 hits)
-    // from an opaque copy of the lane index rather than held across the run,
-    // which costs 56 registers (193 against 121, two resident wavefronts per
-    // SIMD against four)
+    // the A fragments are the same for every brick: reloaded (from LDS, or
+    // L1 / L2 hits) from an opaque copy of the lane index rather than held
+    // across the run, which cost 56 registers (193 against 121 before the
+    // register bound)
     int lv = lane;
     asm volatile("" : "+v"(lv));
     const uint4* fr = a.frag + lv;
