@@ -18,7 +18,7 @@ Modules
               same CG with residual replacement (the continuation rule of the
               GPU's mixed-precision solve, in FP64), flexible CG with the
               stagnation fallback, the FP64 true residual.  There is no FP32
-              solver here: a mixed-precision GPU result is judged by this
+              solver here: a mixed-precision GPU result is checked against this
               module's FP64 true residual of its solution
     unet      the learned preconditioner: 3-D convolutions, pooling,
               upsampling, forward/backward, step loss and Adam, in FP64 on
