@@ -285,6 +285,21 @@ def main():
     roofline["attainable_copy"] = {"GBs": round(copy_gbs, 1), "bytes_per_copy": 2 * src.numel() * 4,
                                    "kernel": "k_stream_copy", "frac_of_copy": round(roofline["achieved"] / copy_gbs, 4)}
     log(f"[bench] plain copy: {copy_gbs:.0f} GB/s")
+    # and the library's plain streaming write over the same 1 GiB: the ceiling
+    # of the write-dominated network layers
+    for _ in range(3):
+        nfa.stream_fill(dst, 0)
+    c0.record()
+    for _ in range(reps):
+        nfa.stream_fill(dst, 0)
+    c1.record()
+    torch.cuda.synchronize()
+    if bool((dst != 0).any()):
+        raise RuntimeError("stream fill mismatch")
+    write_gbs = dst.numel() * 4 * reps / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    roofline["attainable_write"] = {"GBs": round(write_gbs, 1), "bytes_per_write": dst.numel() * 4,
+                                    "kernel": "k_stream_fill"}
+    log(f"[bench] plain write: {write_gbs:.0f} GB/s")
     del src, dst
 
     # one Runge-Kutta projection cycle (two projections around the advected

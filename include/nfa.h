@@ -86,6 +86,16 @@ int nfa_version(void);
  * bytes > 0.  ASYNC on s. */
 nfa_status nfa_stream_copy(void* dst, const void* src, size_t bytes, nfa_stream s);
 
+/* nfa_stream_fill -- every 32-bit word of dst set to `value` over `bytes`
+ * bytes with a plain streaming kernel (16-byte stores, four per lane).  Not a
+ * step of the method: the attainable HBM write bandwidth, against which the
+ * write-dominated network layers are set.
+ *   dst   : DEVICE, 16-byte aligned; owned by the caller.
+ *   bytes : a multiple of 16 (0: nothing to do).
+ * NFA_ERR_INVALID for a misaligned pointer or size, or a null pointer with
+ * bytes > 0.  ASYNC on s. */
+nfa_status nfa_stream_fill(void* dst, unsigned value, size_t bytes, nfa_stream s);
+
 /* ------------------------------------------------------------------ grid
  * nfa_grid_create -- stretched cartesian grid (Gridding section).
  *   nx, ny, nz : cells per axis, each >= 1.

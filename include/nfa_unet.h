@@ -50,7 +50,8 @@ size_t nfa_unet_workspace_bytes(int nx, int ny, int nz, int levels);
 
 /* Network with `levels` resolution levels (3 = the network above; each
  * further level adds a 64-channel level with the same encoder / decoder
- * pattern; 3..6) for an nx x ny x nz grid (multiples of 2^(levels-1));
+ * pattern; 3..6) for an nx x ny x nz grid (multiples of 2^(levels-1), at
+ * most 2^28 cells: the kernels use 32-bit element offsets);
  * weights He-initialised from `seed`, biases and head zero, Adam moments zero.
  *   workspace : DEVICE, 256-byte aligned, ws_bytes >=
  *               nfa_unet_workspace_bytes(...), owned by the caller and kept

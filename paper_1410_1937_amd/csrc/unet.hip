@@ -251,7 +251,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   constexpr int MT = COUT / 16;
   constexpr int ST = lds_stride<CG>();
   static_assert(SUB == 1 || NG == 1, "several blocks per wavefront need a single staged group");
-  __shared__ __align__(16) unsigned char lds[kHalo * ST];
+  // staged rows: kHX positions, or for the features the kFX loaded ones
+  // (position x0b - 1 + hx at kFO + hx)
+  constexpr int kFX = 24, kFO = 3, RS = FEAT ? kFX : kHX, XO = FEAT ? kFO : 0;
+  __shared__ __align__(16) unsigned char lds[FEAT ? kHY * kHZ * kFX * 4 : kHalo * ST];
   // the first encoder's A fragments (2 KB) sit in LDS: its wavefronts take
   // four blocks per brick, each reloading them
   __shared__ __align__(16) uint4 afr[FEAT ? KC * MT * 64 : 1];
@@ -295,50 +298,61 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     constexpr int g = decltype(gg)::value;
     // ---- stage the halo of channel group g
     if constexpr (FEAT) {
-      // one thread per (halo row, 4 aligned x positions): rows of the halo
-      // span x0b - 1 .. x0b + 16, read as x0b - 4 .. x0b + 19 (6 quads; W is a
-      // multiple of 4, so a quad is wholly inside the grid or wholly outside)
+      // one thread per (halo row, 4 aligned x positions): a row holds the
+      // kFX = 24 positions x0b - 4 .. x0b + 19 as loaded (6 quads; W is a
+      // multiple of 4, so a quad is wholly inside the grid or wholly outside,
+      // and outside it is zero), each quad one 16-byte LDS write; the taps
+      // read x0b - 1 .. x0b + 16 of it.  Element indices fit in 32 bits.
       const double ms = rr / a.nred;
       const double inv = ms > 0 ? 1.0 / sqrt(ms) : 1.0;
-      unsigned* l32 = reinterpret_cast<unsigned*>(lds);
       constexpr int NQ = kHY * kHZ * 6;             // (row, quad) pairs
       constexpr int NIT = (NQ + 255) / 256;
       float4 rv[NIT];
       uint2 ev[NIT];
-      long long p0[NIT];
+      unsigned p0[NIT];
+      bool ok[NIT];
 #pragma unroll
       for (int it = 0; it < NIT; ++it) {
         const int tq = tid + it * 256;
         const int quad = tq % 6, row = tq / 6;
         const int hy = row % kHY, hz = row / kHY;
         const int gy = y0b - 1 + hy, gz = z0b - 1 + hz, gx0 = x0b - 4 + 4 * quad;
-        const bool ok = tq < NQ && gx0 >= 0 && gx0 < W && gy >= 0 && gy < H && gz >= 0 && gz < D;
+        ok[it] = ((it + 1) * 256 <= NQ || tq < NQ) && gx0 >= 0 && gx0 < W && (unsigned)gy < (unsigned)H &&
+                 (unsigned)gz < (unsigned)D;
+        p0[it] = ok[it] ? (unsigned)(gz * H + gy) * (unsigned)W + (unsigned)gx0 : 0u;
         rv[it] = make_float4(0.f, 0.f, 0.f, 0.f);
         ev[it] = make_uint2(0u, 0u);
-        p0[it] = ok ? ((long long)gz * H + gy) * W + gx0 : -1;
-        if (ok) {
+        if (ok[it]) {
           rv[it] = *reinterpret_cast<const float4*>(a.r + p0[it]);
           ev[it] = *reinterpret_cast<const uint2*>(a.ell + p0[it]);
         }
       }
+      // [bf16(r/s), ell] per position: r/s formed in FP64 and rounded to FP32,
+      // then to BF16 (nearest even, packed hardware rounding); a position
+      // outside the grid loaded zeros and stays zero
+      uint4 fv[NIT];
 #pragma unroll
       for (int it = 0; it < NIT; ++it) {
+        const unsigned lo = pack_bf2((float)((double)rv[it].x * inv), (float)((double)rv[it].y * inv));
+        const unsigned hi = pack_bf2((float)((double)rv[it].z * inv), (float)((double)rv[it].w * inv));
+        fv[it] = make_uint4((lo & 0xFFFFu) | (ev[it].x << 16), (lo >> 16) | (ev[it].x & 0xFFFF0000u),
+                            (hi & 0xFFFFu) | (ev[it].y << 16), (hi >> 16) | (ev[it].y & 0xFFFF0000u));
         const int tq = tid + it * 256;
-        if (tq < NQ) {
+        if ((it + 1) * 256 <= NQ || tq < NQ) *reinterpret_cast<uint4*>(lds + tq * 16) = fv[it];
+      }
+      if (a.x0) {
+        // the features of the brick's own positions, for the backward pass
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+          const int tq = tid + it * 256;
           const int quad = tq % 6, row = tq / 6;
           const int hy = row % kHY, hz = row / kHY;
-          const bool ok = p0[it] >= 0;
-          const float rs[4] = {rv[it].x, rv[it].y, rv[it].z, rv[it].w};
-          const unsigned es[4] = {ev[it].x & 0xFFFFu, ev[it].x >> 16, ev[it].y & 0xFFFFu, ev[it].y >> 16};
+          const unsigned v[4] = {fv[it].x, fv[it].y, fv[it].z, fv[it].w};
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int hx = 4 * quad - 3 + i;
-            if (hx >= 0 && hx < kHX) {
-              const unsigned v = ok ? ((unsigned)f2bf((float)((double)rs[i] * inv)) | (es[i] << 16)) : 0u;
-              l32[(hz * kHY + hy) * kHX + hx] = v;
-              if (a.x0 && ok && hx >= 1 && hx <= kTX && hy >= 1 && hy <= kTY && hz >= 1 && hz <= kTZ)
-                reinterpret_cast<unsigned*>(a.x0)[p0[it] + i] = v;
-            }
+            if (ok[it] && hx >= 1 && hx <= kTX && hy >= 1 && hy <= kTY && hz >= 1 && hz <= kTZ)
+              reinterpret_cast<unsigned*>(a.x0)[p0[it] + i] = v[i];
           }
         }
       }
@@ -405,8 +419,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int t = 16 * kc + 4 * kq + i;
-        foff[kc][i] = t < 27 ? (t / 9 - 1) * (kHY * kHX) + ((t / 3) % 3 - 1) * kHX + (t % 3 - 1) : tap_halo<HY>(26);
+        const int t = 16 * kc + 4 * kq + i < 27 ? 16 * kc + 4 * kq + i : 26;
+        foff[kc][i] = (t / 9 - 1) * (kHY * RS) + ((t / 3) % 3 - 1) * RS + (t % 3 - 1);
       }
   }
 
@@ -421,7 +435,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     zw = 2 * (wv >> 1) + 4 * (s / SUB);
     // staged index of this lane's output position in each of the four rows
 #pragma unroll
-    for (int j = 0; j < 4; ++j) hb[j] = ((zw + (j >> 1) + 1) * kHY + (yw + (j & 1) + 1)) * kHX + (n + 1);
+    for (int j = 0; j < 4; ++j) hb[j] = ((zw + (j >> 1) + 1) * kHY + (yw + (j & 1) + 1)) * RS + (n + 1 + XO);
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
@@ -499,14 +513,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
   const int x = x0b + n;
   if (a.out) {
+    // element offsets in 32 bits (the grid is bounded so that they fit): the
+    // block's first row, then rows of W and planes of H W positions
+    const unsigned e0 = ((unsigned)((z0b + zw) * H + y0b + yw) * (unsigned)W + (unsigned)x) * COUT + 4 * kq;
+    const unsigned ey = (unsigned)W * COUT, ez = (unsigned)(H * W) * COUT;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int y = y0b + yw + (j & 1), z = z0b + zw + (j >> 1);
       if (x < W && y < H && z < D) {
-        const long long p = ((long long)z * H + y) * W + x;
+        const unsigned e = e0 + (j & 1) * ey + (j >> 1) * ez;
 #pragma unroll
         for (int m = 0; m < MT; ++m)
-          *reinterpret_cast<uint2*>(a.out + p * COUT + m * 16 + 4 * kq) = make_uint2(pk[m][j][0], pk[m][j][1]);
+          *reinterpret_cast<uint2*>(a.out + e + m * 16) = make_uint2(pk[m][j][0], pk[m][j][1]);
       }
     }
   }
@@ -514,7 +532,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     // the wavefront's four rows are one 2 x 2 (y, z) block; x pairs are lanes n, n^1
     const int y = y0b + yw, z = z0b + zw;
     const bool ok = (n & 1) == 0 && x < W && y < H && z < D;
-    const long long q = ((long long)(z >> 1) * (H >> 1) + (y >> 1)) * (W >> 1) + (x >> 1);
+    const unsigned q = (unsigned)((z >> 1) * (H >> 1) + (y >> 1)) * (unsigned)(W >> 1) + (unsigned)(x >> 1);
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
       float v[4];
@@ -1749,6 +1767,10 @@ nfa_status unet_check(int nx, int ny, int nz, int levels, const char* who) {
   const int q = 1 << (levels - 1);
   if (nx < q || ny < q || nz < q || nx % q || ny % q || nz % q)
     return fail(NFA_ERR_INVALID, std::string(who) + ": grid sizes must be multiples of 2^(levels-1)");
+  // the kernels index channels-last arrays with 32-bit element offsets; the
+  // largest is a 16-channel array over the fine grid
+  if ((long long)nx * ny * nz * 16 >= (1LL << 32))
+    return fail(NFA_ERR_INVALID, std::string(who) + ": at most 2^28 cells");
   return NFA_OK;
 }
 

@@ -315,22 +315,45 @@ void launch_set_scalars(SolveScalars* sc, double t, int tol_mode, int max_iter, 
 namespace {
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kCopyUnroll = 4;
+constexpr long long kChunk = 256LL * kCopyUnroll;   // 16-byte words per workgroup (16 KB)
 
-// dst = src in 16-byte words: every lane keeps kCopyUnroll non-temporal loads
-// in flight, a grid-stride loop over the rest
+// Both streaming kernels give each workgroup one contiguous 16 KB chunk, and
+// each XCD a contiguous range of chunks (workgroups are dealt to the XCDs
+// round robin).  Measured at 1 GiB on MI355X, that order moves 6.0 TB/s
+// (copy, read + written) and 6.4 TB/s (writes only), against 5.1 and 4.4
+// TB/s for a grid-stride loop over the whole array.
+__device__ __forceinline__ long long stream_chunk(int per) {
+  return (long long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+
+// dst = src in 16-byte words: kCopyUnroll non-temporal loads in flight per lane
 __global__ __launch_bounds__(256) void k_stream_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
-                                                     long long n) {
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  for (; i + (kCopyUnroll - 1) * stride < n; i += kCopyUnroll * stride) {
+                                                     long long n, int per) {
+  const long long i = stream_chunk(per) * kChunk + threadIdx.x;
+  if (i + (kCopyUnroll - 1) * 256 < n) {
     u32x4 v[kCopyUnroll];
 #pragma unroll
-    for (int u = 0; u < kCopyUnroll; ++u) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+    for (int u = 0; u < kCopyUnroll; ++u) v[u] = __builtin_nontemporal_load(src + i + u * 256);
 #pragma unroll
-    for (int u = 0; u < kCopyUnroll; ++u) __builtin_nontemporal_store(v[u], dst + i + u * stride);
+    for (int u = 0; u < kCopyUnroll; ++u) __builtin_nontemporal_store(v[u], dst + i + u * 256);
+  } else {
+    for (int u = 0; u < kCopyUnroll; ++u)
+      if (i + u * 256 < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i + u * 256), dst + i + u * 256);
   }
-  for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
+
+// dst = v in every 16-byte word, plain stores (the form the convolutions'
+// outputs use)
+__global__ __launch_bounds__(256) void k_stream_fill(u32x4* __restrict__ dst, unsigned v, long long n, int per) {
+  const long long i = stream_chunk(per) * kChunk + threadIdx.x;
+  const u32x4 w = {v, v, v, v};
+#pragma unroll
+  for (int u = 0; u < kCopyUnroll; ++u)
+    if (i + u * 256 < n) dst[i + u * 256] = w;
+}
+
+// chunks per XCD for n words
+int stream_per(long long n) { return (int)(((n + kChunk - 1) / kChunk + 7) / 8); }
 }  // namespace
 
 extern "C" nfa_status nfa_stream_copy(void* dst, const void* src, size_t bytes, nfa_stream s) {
@@ -340,8 +363,21 @@ extern "C" nfa_status nfa_stream_copy(void* dst, const void* src, size_t bytes, 
   if (bytes == 0) return NFA_OK;
   if (dst == nullptr || src == nullptr) return fail(NFA_ERR_INVALID, "nfa_stream_copy: null pointer");
   const long long n = (long long)(bytes / 16);
-  const int nb = blocks_for(n, 256 * kCopyUnroll, 8192);
-  k_stream_copy<<<nb, 256, 0, S(s)>>>(reinterpret_cast<const u32x4*>(src), reinterpret_cast<u32x4*>(dst), n);
+  const int per = stream_per(n);
+  k_stream_copy<<<8 * per, 256, 0, S(s)>>>(reinterpret_cast<const u32x4*>(src), reinterpret_cast<u32x4*>(dst), n, per);
+  NFA_CHECK_LAUNCH();
+  return NFA_OK;
+}
+
+extern "C" nfa_status nfa_stream_fill(void* dst, unsigned value, size_t bytes, nfa_stream s) {
+  using namespace nfa;
+  if (bytes % 16 != 0 || reinterpret_cast<uintptr_t>(dst) % 16 != 0)
+    return fail(NFA_ERR_INVALID, "nfa_stream_fill: pointer and size must be multiples of 16 bytes");
+  if (bytes == 0) return NFA_OK;
+  if (dst == nullptr) return fail(NFA_ERR_INVALID, "nfa_stream_fill: null pointer");
+  const long long n = (long long)(bytes / 16);
+  const int per = stream_per(n);
+  k_stream_fill<<<8 * per, 256, 0, S(s)>>>(reinterpret_cast<u32x4*>(dst), value, n, per);
   NFA_CHECK_LAUNCH();
   return NFA_OK;
 }

@@ -89,6 +89,7 @@ def _sig(name, res, args):
 _sig("nfa_last_error", ctypes.c_char_p, [])
 _sig("nfa_version", c_int, [])
 _sig("nfa_stream_copy", c_int, [c_void_p, c_void_p, ctypes.c_size_t, c_void_p])
+_sig("nfa_stream_fill", c_int, [c_void_p, ctypes.c_uint, ctypes.c_size_t, c_void_p])
 _sig("nfa_grid_create", c_int, [c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
                                 ctypes.POINTER(c_void_p)])
 _sig("nfa_grid_set_body", c_int, [c_void_p, c_void_p, c_double, c_int, c_void_p])
@@ -188,6 +189,20 @@ def stream_copy(dst, src):
         raise ValueError("dst and src differ in size")
     _check(lib.nfa_stream_copy(c_void_p(dst.data_ptr()), c_void_p(src.data_ptr()), nbytes, _stream()),
            "nfa_stream_copy")
+    return dst
+
+
+def stream_fill(dst, value=0):
+    """Every 32-bit word of dst (a contiguous device tensor, 16-byte aligned)
+    set to the unsigned `value` with the library's plain streaming write
+    (nfa_stream_fill); on the current stream."""
+    if not (isinstance(dst, torch.Tensor) and dst.is_cuda):
+        raise TypeError("dst must be a CUDA (HIP) tensor")
+    if not dst.is_contiguous():
+        raise TypeError("dst must be contiguous")
+    nbytes = dst.numel() * dst.element_size()
+    _check(lib.nfa_stream_fill(c_void_p(dst.data_ptr()), int(value) & 0xFFFFFFFF, nbytes, _stream()),
+           "nfa_stream_fill")
     return dst
 
 

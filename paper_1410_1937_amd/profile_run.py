@@ -5,7 +5,8 @@ Sets up the 512 x 256 x 192 breaking-wave projection problem
 Jacobi-PCG iterations (tolerance unreachable, so every iteration runs both
 sweeps), and finally three plain device-to-device copies of known size (the library's
 k_stream_copy, 1 GiB each by default) whose counter readings calibrate the
-FETCH_SIZE / WRITE_SIZE counters to bytes.
+FETCH_SIZE / WRITE_SIZE counters to bytes; with --fill, three plain writes of
+the same size after them (the library's k_stream_fill).
 With --mg N it runs N mixed-precision iterations preconditioned by the
 multigrid V-cycle (hierarchy set-up included).  With --unet L it also runs --unet-reps forward passes of an L-level learned
 preconditioner on the same grid (the committed weights for L = 3).  With
@@ -36,6 +37,7 @@ def main(argv=None):
     ap.add_argument("--unet-reps", type=int, default=5)
     ap.add_argument("--vof", type=int, default=0, help="VOF advection steps to run")
     ap.add_argument("--psi", type=int, default=-1, help="icosphere subdivision levels for the signed distance")
+    ap.add_argument("--fill", action="store_true", help="after the copies, three plain writes of the same size (k_stream_fill)")
     args = ap.parse_args(argv)
     import torch
     from paper_1410_1937_amd import fixtures as fx
@@ -95,6 +97,11 @@ def main(argv=None):
         nfa.stream_copy(dst, src)     # k_stream_copy, one dispatch of known size
     torch.cuda.synchronize()
     print(f"[profile_run] copy: 3 x {args.copy_mib} MiB read + written (k_stream_copy)", flush=True)
+    if args.fill:
+        for _ in range(3):
+            nfa.stream_fill(dst, 0)   # k_stream_fill, writes only
+        torch.cuda.synchronize()
+        print(f"[profile_run] write: 3 x {args.copy_mib} MiB written (k_stream_fill)", flush=True)
     return 0
 
 

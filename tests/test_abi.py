@@ -103,3 +103,31 @@ def test_stream_copy_rejects_misaligned_arguments_before_any_device_work(lib):
     assert f(ctypes.c_void_p(16), ctypes.c_void_p(40), 16, None) < 0          # misaligned source
     assert f(None, None, 16, None) < 0                                         # null with bytes > 0
     assert f(None, None, 0, None) == 0                                         # nothing to do
+
+
+def test_stream_fill_rejects_misaligned_arguments_before_any_device_work(lib):
+    f = lib.nfa_stream_fill
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_uint, ctypes.c_size_t, ctypes.c_void_p]
+    lib.nfa_last_error.restype = ctypes.c_char_p
+    assert f(ctypes.c_void_p(16), 0, 24, None) < 0          # size not a multiple of 16
+    assert b"multiples of 16" in lib.nfa_last_error()
+    assert f(ctypes.c_void_p(8), 0, 16, None) < 0           # misaligned destination
+    assert f(None, 0, 16, None) < 0                          # null with bytes > 0
+    assert f(None, 0, 0, None) == 0                          # nothing to do
+
+
+def test_network_rejects_grids_beyond_32_bit_element_offsets(lib):
+    ws = lib.nfa_unet_workspace_bytes
+    ws.restype = ctypes.c_size_t
+    ws.argtypes = [ctypes.c_int] * 4
+    assert ws(512, 256, 192, 3) > 0
+    assert ws(1024, 512, 512, 3) == 0          # 2^28 cells: 16-channel arrays need 2^32 elements
+    assert ws(1024, 512, 508, 3) > 0           # just below the limit
+    create = lib.nfa_unet_create
+    create.restype = ctypes.c_int
+    create.argtypes = [ctypes.c_int] * 5 + [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.nfa_last_error.restype = ctypes.c_char_p
+    h = ctypes.c_void_p()
+    assert create(1024, 512, 512, 3, 0, None, 0, ctypes.byref(h)) < 0
+    assert b"2^28" in lib.nfa_last_error()
