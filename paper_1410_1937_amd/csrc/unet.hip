@@ -1148,6 +1148,117 @@ __global__ __launch_bounds__(256) void k_wgrad(int D, int H, int W, const bf16_t
   }
 }
 
+// The same weight gradient for the shapes with one 16 x 16 output tile
+// (CIN <= 16, COUT = 16), the taps of one z offset (nine) per pass over the
+// positions: their accumulators stay in registers, dout and the positions'
+// coordinates are taken once per chunk of 32 positions and pass, and the
+// input's nine shifted reads of a chunk hit the caches (one workgroup per tap
+// reads dout and the input from memory 27 times).  partial[t][blk][ci][co] as
+// k_wgrad.
+constexpr int kWgrad27Blocks = 1024;
+template <int CIN, bool UPADD>
+__global__ __launch_bounds__(256) void k_wgrad27(int D, int H, int W, const bf16_t* __restrict__ in,
+                                                 const bf16_t* __restrict__ in2,
+                                                 const bf16_t* __restrict__ dout, float* __restrict__ partial) {
+  static_assert(CIN <= 16, "one 16-channel input tile");
+  constexpr int COUT = 16;
+  __shared__ float red[4][256];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  // positions fit in 32 bits (the network's grids have at most 2^28 cells)
+  const unsigned N = (unsigned)D * (unsigned)H * (unsigned)W;
+  const unsigned nchunk = (N + 31u) / 32u;
+  const int H2 = H >> 1, W2 = W >> 1;
+#pragma unroll 1
+  for (int g = 0; g < 3; ++g) {
+    const int dz = g - 1;
+    f32x4 acc[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (unsigned chunk = blockIdx.x * 4u + wv; chunk < nchunk; chunk += gridDim.x * 4u) {
+      const unsigned m0 = chunk * 32u + kq * 8u;
+      // this lane's 8 positions: dout (co = col), and the coordinates in the
+      // plane z + dz (-4 when outside the grid: every tap then falls outside)
+      Frag A;
+      int xs[8], ys[8], zs[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const unsigned m = m0 + j;
+        const bool mok = m < N;
+        A.h[j] = mok ? dout[(size_t)m * COUT + col] : (bf16_t)0;
+        const unsigned r2 = m / (unsigned)W;
+        const int zz = (int)(r2 / (unsigned)H) + dz;
+        const bool zok = mok && (unsigned)zz < (unsigned)D;
+        xs[j] = zok ? (int)(m - r2 * (unsigned)W) : -4;
+        ys[j] = (int)(r2 % (unsigned)H);
+        zs[j] = zz;
+      }
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const int dy = k / 3 - 1, dx = k % 3 - 1;
+        Frag B;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int yy = ys[j] + dy, xx = xs[j] + dx;
+          const bool ok = col < CIN && (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W;
+          bf16_t v = 0;
+          if (ok) {
+            // element offsets in 32 bits (at most 2^28 cells of 16 channels)
+            const unsigned pe = ((unsigned)(zs[j] * H + yy) * (unsigned)W + (unsigned)xx) * CIN + col;
+            v = in[pe];
+            if constexpr (UPADD) {
+              const unsigned qe =
+                  ((unsigned)((zs[j] >> 1) * H2 + (yy >> 1)) * (unsigned)W2 + (unsigned)(xx >> 1)) * CIN + col;
+              v = f2bf(bf2f(v) + bf2f(in2[qe]));
+            }
+          }
+          B.h[j] = v;
+        }
+        acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.v, B.v, acc[k], 0, 0, 0);
+        // at most three taps' loads in flight: the registers stay bounded
+        if (k % 3 == 2) __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    // D[co][ci] per tap: lane holds co = 4 kq + i, ci = col; the four
+    // wavefronts' tiles added in order
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) red[wv][i * 64 + lane] = acc[k][i];
+      __syncthreads();
+      const int e = threadIdx.x, ln = e & 63, i = e >> 6;
+      const int co = 4 * (ln >> 4) + i, ci = ln & 15;
+      const float sum = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+      if (ci < CIN)
+        partial[((size_t)(9 * g + k) * gridDim.x + blockIdx.x) * (CIN * COUT) + ci * COUT + co] = sum;
+      __syncthreads();
+    }
+  }
+}
+
+// out[p][c] = bf16(a[p][c] + up(d)[p][c]), the decoder's skip sum (as the
+// weight-gradient kernels form it on the fly), 8 channels per thread
+template <int C>
+__global__ void k_skipsum(int D, int H, int W, const bf16_t* __restrict__ a, const bf16_t* __restrict__ d,
+                          bf16_t* __restrict__ out) {
+  const long long n = (long long)D * H * W * (C / 8);
+  const int H2 = H >> 1, W2 = W >> 1;
+  GRID_STRIDE(e, n) {
+    const int g = (int)(e % (C / 8));
+    const long long p = e / (C / 8);
+    const int x = (int)(p % W);
+    const long long r = p / W;
+    const int y = (int)(r % H), z = (int)(r / H);
+    const long long q = ((long long)(z >> 1) * H2 + (y >> 1)) * W2 + (x >> 1);
+    Frag va, vd, o;
+    va.u = *reinterpret_cast<const uint4*>(a + p * C + g * 8);
+    vd.u = *reinterpret_cast<const uint4*>(d + q * C + g * 8);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) o.h[j] = f2bf(bf2f(va.h[j]) + bf2f(vd.h[j]));
+    *reinterpret_cast<uint4*>(out + p * C + g * 8) = o.u;
+  }
+}
+
 // g[t][ci][co] = sum_blk partial[t][blk][ci][co] (fixed order)
 __global__ void k_wgrad_reduce(const float* __restrict__ partial, int nblk, int per_tap, float* __restrict__ g) {
   GRID_STRIDE(e, 27LL * per_tap) {
@@ -1158,30 +1269,62 @@ __global__ void k_wgrad_reduce(const float* __restrict__ partial, int nblk, int 
   }
 }
 
-// column sums of dout [n][C] -> partial[blk][C]
+// column sums of dout [n][C] -> partial[blk][C] (C = 16, 32 or 64): a
+// thread sums 8 channels of one position per 16-byte load, four positions
+// in flight, on a grid-stride walk over the positions; fixed order throughout
+constexpr int kColsumBlocks = 1024;
 template <int C>
 __global__ __launch_bounds__(256) void k_colsum(long long n, const bf16_t* __restrict__ dout, float* __restrict__ partial) {
-  __shared__ float red[256];
-  const int ch = threadIdx.x % C, lanes = 256 / C, sub = threadIdx.x / C;
-  float s = 0.f;
-  for (long long m = (long long)blockIdx.x * lanes + sub; m < n; m += (long long)gridDim.x * lanes)
-    s += bf2f(dout[m * C + ch]);
-  red[threadIdx.x] = s;
+  static_assert(C == 16 || C == 32 || C == 64, "channels: 16, 32 or 64");
+  constexpr int TPP = C / 8;               // threads per position
+  constexpr int PPW = 256 / TPP;           // positions per workgroup and step
+  __shared__ float red[8][256];
+  const int g = threadIdx.x % TPP, sub = threadIdx.x / TPP;
+  const long long step = (long long)gridDim.x * PPW;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  long long m = (long long)blockIdx.x * PPW + sub;
+  for (; m + 3 * step < n; m += 4 * step) {
+    Frag v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u].u = *reinterpret_cast<const uint4*>(dout + (m + u * step) * C + g * 8);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s[j] += bf2f(v[u].h[j]);
+  }
+  for (; m < n; m += step) {
+    Frag v;
+    v.u = *reinterpret_cast<const uint4*>(dout + m * C + g * 8);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s[j] += bf2f(v.h[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) red[j][threadIdx.x] = s[j];
   __syncthreads();
   if (threadIdx.x < C) {
+    // channel c = 8 gg + j: the threads (q, gg) of every position slot q
+    const int gg = threadIdx.x / 8, j = threadIdx.x % 8;
     float a = 0.f;
-    for (int q = 0; q < lanes; ++q) a += red[q * C + threadIdx.x];
+    for (int q = 0; q < PPW; ++q) a += red[j][q * TPP + gg];
     partial[blockIdx.x * C + threadIdx.x] = a;
   }
 }
 
-// g[c] = sum_b partial[b*width + c] for c < C
-__global__ void k_colsum_reduce(const float* __restrict__ partial, int nblk, int width, int C,
-                                float* __restrict__ g) {
-  for (int c = threadIdx.x; c < C; c += blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += partial[b * width + c];
-    g[c] = (float)s;
+// g[c] = sum_b partial[b*width + c] for c < C (C divides 256), in FP64: the
+// 256 / C threads of a channel take every (256 / C)-th partial, then their
+// sums are added in thread order
+__global__ __launch_bounds__(256) void k_colsum_reduce(const float* __restrict__ partial, int nblk, int width, int C,
+                                                       float* __restrict__ g) {
+  __shared__ double red[256];
+  const int S = 256 / C, c = threadIdx.x % C, sub = threadIdx.x / C;
+  double acc = 0.0;
+  for (int b = sub; b < nblk; b += S) acc += partial[(long long)b * width + c];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < C) {
+    double a = 0.0;
+    for (int q = 0; q < S; ++q) a += red[q * C + threadIdx.x];
+    g[threadIdx.x] = (float)a;
   }
 }
 
@@ -1536,12 +1679,18 @@ nfa_status conv(int cin, int cout, bool upadd, int D, int H, int W, const bf16_t
 template <int CIN, int COUT, bool UPADD>
 void wgrad_t(UNet& u, float* gw, float* gb, int D, int H, int W, const bf16_t* in, const bf16_t* in2,
              const bf16_t* dout, hipStream_t s) {
-  dim3 grid(kWgradBlocks, 27);
-  k_wgrad<CIN, COUT, UPADD><<<grid, 256, 0, s>>>(D, H, W, in, in2, dout, u.wpart.as<float>());
-  k_wgrad_reduce<<<eblocks(27LL * CIN * COUT), kBlock, 0, s>>>(u.wpart.as<float>(), kWgradBlocks, CIN * COUT, gw);
+  if constexpr (COUT == 16 && CIN <= 16) {
+    static_assert((long long)kWgrad27Blocks * CIN * COUT <= (long long)kWgradBlocks * 64 * 64, "partials buffer");
+    k_wgrad27<CIN, UPADD><<<kWgrad27Blocks, 256, 0, s>>>(D, H, W, in, in2, dout, u.wpart.as<float>());
+    k_wgrad_reduce<<<eblocks(27LL * CIN * COUT), kBlock, 0, s>>>(u.wpart.as<float>(), kWgrad27Blocks, CIN * COUT, gw);
+  } else {
+    dim3 grid(kWgradBlocks, 27);
+    k_wgrad<CIN, COUT, UPADD><<<grid, 256, 0, s>>>(D, H, W, in, in2, dout, u.wpart.as<float>());
+    k_wgrad_reduce<<<eblocks(27LL * CIN * COUT), kBlock, 0, s>>>(u.wpart.as<float>(), kWgradBlocks, CIN * COUT, gw);
+  }
   const long long n = (long long)D * H * W;
-  k_colsum<COUT><<<kWgradBlocks, 256, 0, s>>>(n, dout, u.cpart.as<float>());
-  k_colsum_reduce<<<1, 64, 0, s>>>(u.cpart.as<float>(), kWgradBlocks, COUT, COUT, gb);
+  k_colsum<COUT><<<kColsumBlocks, 256, 0, s>>>(n, dout, u.cpart.as<float>());
+  k_colsum_reduce<<<1, 256, 0, s>>>(u.cpart.as<float>(), kColsumBlocks, COUT, COUT, gb);
 }
 
 nfa_status wgrad(UNet& u, int layer, bool upadd, int level, const bf16_t* in, const bf16_t* in2,
@@ -1554,7 +1703,7 @@ nfa_status wgrad(UNet& u, int layer, bool upadd, int level, const bf16_t* in, co
 #define W_(A, B, U) \
   if (cin == A && cout == B && upadd == U) { wgrad_t<A, B, U>(u, gw, gb, D, H, W, in, in2, dout, s); return NFA_OK; }
   W_(2, 16, false) W_(16, 32, false) W_(32, 64, false) W_(64, 64, false) W_(64, 32, false)
-  W_(32, 16, true) W_(64, 32, true) W_(64, 64, true) W_(16, 16, true)
+  W_(32, 16, true) W_(64, 32, true) W_(64, 64, true) W_(16, 16, true) W_(16, 16, false)
 #undef W_
   return fail(NFA_ERR_INVALID, "learned preconditioner: no weight-gradient kernel for this shape");
 }
@@ -1671,8 +1820,13 @@ nfa_status backward(UNet& u, Poisson& op, const float* dz, hipStream_t s) {
   k_head_wgrad<<<kHeadBlocks, 256, 0, s>>>(n0, dz, dinv, B16(u.d[0]), u.hpart.as<float>());
   k_head_wgrad_reduce<<<1, 64, 0, s>>>(u.hpart.as<float>(), kHeadBlocks, G + u.off_w[u.Hd()],
                                        G + u.off_b[u.Hd()]);
-  // finest decoder: weights against up(d1) + a0, data gradient into skip[0]
-  nfa_status e = wgrad(u, u.Dl(0), true, 0, B16(u.a[0]), B16(u.d[1]), B16(u.dd[0]), s);
+  // finest decoder: weights against up(d1) + a0, formed once into skip[0]
+  // (free until the data gradient below writes it), then the data gradient
+  // into skip[0]
+  if (u.cin[u.Dl(0)] != 16 || level_channels(0) != 16)
+    return fail(NFA_ERR_INVALID, "learned preconditioner: the finest decoder takes 16 channels");
+  k_skipsum<16><<<eblocks(n0 * 2), kBlock, 0, s>>>(D, H, W, B16(u.a[0]), B16(u.d[1]), B16(u.skip[0]));
+  nfa_status e = wgrad(u, u.Dl(0), false, 0, B16(u.skip[0]), nullptr, B16(u.dd[0]), s);
   if (e != NFA_OK) return e;
   e = conv(u.cout[u.Dl(0)], u.cin[u.Dl(0)], false, D, H, W, B16(u.dd[0]), nullptr, u.frag_b[u.Dl(0)], nullptr, 0,
            nullptr, B16(u.skip[0]), nullptr, s);
@@ -1826,7 +1980,7 @@ hipError_t unet_buffers(UNet& u, Carver& c) {
   TAKE(Az, n0 * 4);
   TAKE(dz, n0 * 4);
   TAKE(wpart, 27LL * kWgradBlocks * 64 * 64 * 4);
-  TAKE(cpart, (long long)kWgradBlocks * 64 * 4);
+  TAKE(cpart, (long long)kColsumBlocks * 64 * 4);
   TAKE(hpart, (long long)kHeadBlocks * 17 * 4);
   TAKE(scal, 8 * 8);
 #undef TAKE

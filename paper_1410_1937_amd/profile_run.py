@@ -9,7 +9,8 @@ FETCH_SIZE / WRITE_SIZE counters to bytes; with --fill, three plain writes of
 the same size after them (the library's k_stream_fill).
 With --mg N it runs N mixed-precision iterations preconditioned by the
 multigrid V-cycle (hierarchy set-up included).  With --unet L it also runs --unet-reps forward passes of an L-level learned
-preconditioner on the same grid (the committed weights for L = 3).  With
+preconditioner on the same grid (the committed weights for L = 3), then
+--unet-train training steps of it.  With
 --vof N it runs N split VOF advection steps (alternating sweep order) of the
 FP64 volume fraction through the workload's face velocities.  With --psi L
 it computes the signed distance of an L-times subdivided icosphere (the
@@ -35,6 +36,8 @@ def main(argv=None):
     ap.add_argument("--mg", type=int, default=0, help="mixed-precision multigrid-preconditioned iterations")
     ap.add_argument("--unet", type=int, default=0, help="levels of the learned preconditioner to run (0: none)")
     ap.add_argument("--unet-reps", type=int, default=5)
+    ap.add_argument("--unet-train", type=int, default=0,
+                    help="after the forward passes, this many training steps of the same network (nfa_unet_train_step)")
     ap.add_argument("--vof", type=int, default=0, help="VOF advection steps to run")
     ap.add_argument("--psi", type=int, default=-1, help="icosphere subdivision levels for the signed distance")
     ap.add_argument("--fill", action="store_true", help="after the copies, three plain writes of the same size (k_stream_fill)")
@@ -73,6 +76,15 @@ def main(argv=None):
             net.forward(op, r)
         torch.cuda.synchronize()
         print(f"[profile_run] unet L{args.unet}: {args.unet_reps} forward passes", flush=True)
+        # training steps on the same residual: forward with the activations
+        # kept, the A-norm step loss and its gradient, the backward pass and
+        # Adam (eAe only scales the loss, so any positive value runs the
+        # same kernels)
+        for t in range(1, args.unet_train + 1):
+            net.train_step(op, r, 1.0, 1e-5, t)
+        torch.cuda.synchronize()
+        if args.unet_train:
+            print(f"[profile_run] unet L{args.unet}: {args.unet_train} training steps", flush=True)
     if args.vof:
         vf = nfa.Vof(g)
         phi = torch.as_tensor(wl.phi, device=dev)
