@@ -1236,6 +1236,76 @@ __global__ __launch_bounds__(256) void k_wgrad27(int D, int H, int W, const bf16
   }
 }
 
+// The first encoder's weight gradient (CIN = 2, COUT = 16) with the 54
+// (tap, channel) pairs as the MFMA's columns, 16 to a tile: column n of tile
+// T is tap 8 T + n / 2, channel n % 2 (taps past 26 are zero), so a chunk of
+// 32 positions takes four multiplies instead of one per tap; one pass over
+// the positions.  partial[t][blk][ci][co] as k_wgrad.
+template <int BLK>
+__global__ __launch_bounds__(256) void k_wgrad_c2(int D, int H, int W, const bf16_t* __restrict__ in,
+                                                  const bf16_t* __restrict__ dout, float* __restrict__ partial) {
+  constexpr int CIN = 2, COUT = 16;
+  __shared__ float red[4][256];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  const unsigned N = (unsigned)D * (unsigned)H * (unsigned)W;
+  const unsigned nchunk = (N + 31u) / 32u;
+  // this lane's column in each tile: tap offsets and channel
+  int tdz[4], tdy[4], tdx[4];
+  bool tok[4];
+  const int ci = col & 1;
+#pragma unroll
+  for (int T = 0; T < 4; ++T) {
+    const int t = 8 * T + (col >> 1);
+    tok[T] = t < 27;
+    tdz[T] = t / 9 - 1;
+    tdy[T] = (t / 3) % 3 - 1;
+    tdx[T] = t % 3 - 1;
+  }
+  f32x4 acc[4];
+#pragma unroll
+  for (int T = 0; T < 4; ++T) acc[T] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (unsigned chunk = blockIdx.x * 4u + wv; chunk < nchunk; chunk += gridDim.x * 4u) {
+    const unsigned m0 = chunk * 32u + kq * 8u;
+    Frag A;
+    int xs[8], ys[8], zs[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const unsigned m = m0 + j;
+      const bool mok = m < N;
+      A.h[j] = mok ? dout[(size_t)m * COUT + col] : (bf16_t)0;
+      const unsigned r2 = m / (unsigned)W;
+      xs[j] = mok ? (int)(m - r2 * (unsigned)W) : -4;     // -4: every tap falls outside
+      ys[j] = (int)(r2 % (unsigned)H);
+      zs[j] = (int)(r2 / (unsigned)H);
+    }
+#pragma unroll
+    for (int T = 0; T < 4; ++T) {
+      Frag B;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int zz = zs[j] + tdz[T], yy = ys[j] + tdy[T], xx = xs[j] + tdx[T];
+        const bool ok = tok[T] && (unsigned)zz < (unsigned)D && (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W;
+        B.h[j] = ok ? in[((unsigned)(zz * H + yy) * (unsigned)W + (unsigned)xx) * CIN + ci] : (bf16_t)0;
+      }
+      acc[T] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.v, B.v, acc[T], 0, 0, 0);
+    }
+  }
+  // D[co][n] per tile: lane holds co = 4 kq + i, column n = col; the four
+  // wavefronts' tiles added in order
+#pragma unroll
+  for (int T = 0; T < 4; ++T) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) red[wv][i * 64 + lane] = acc[T][i];
+    __syncthreads();
+    const int e = threadIdx.x, ln = e & 63, i = e >> 6;
+    const int co = 4 * (ln >> 4) + i, n = ln & 15, t = 8 * T + (n >> 1);
+    const float sum = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+    if (t < 27) partial[((size_t)t * BLK + blockIdx.x) * (CIN * COUT) + (n & 1) * COUT + co] = sum;
+    __syncthreads();
+  }
+}
+
 // out[p][c] = bf16(a[p][c] + up(d)[p][c]), the decoder's skip sum (as the
 // weight-gradient kernels form it on the fly), 8 channels per thread
 template <int C>
@@ -1679,7 +1749,11 @@ nfa_status conv(int cin, int cout, bool upadd, int D, int H, int W, const bf16_t
 template <int CIN, int COUT, bool UPADD>
 void wgrad_t(UNet& u, float* gw, float* gb, int D, int H, int W, const bf16_t* in, const bf16_t* in2,
              const bf16_t* dout, hipStream_t s) {
-  if constexpr (COUT == 16 && CIN <= 16) {
+  if constexpr (CIN == 2 && COUT == 16 && !UPADD) {
+    static_assert((long long)kWgrad27Blocks * CIN * COUT <= (long long)kWgradBlocks * 64 * 64, "partials buffer");
+    k_wgrad_c2<kWgrad27Blocks><<<kWgrad27Blocks, 256, 0, s>>>(D, H, W, in, dout, u.wpart.as<float>());
+    k_wgrad_reduce<<<eblocks(27LL * CIN * COUT), kBlock, 0, s>>>(u.wpart.as<float>(), kWgrad27Blocks, CIN * COUT, gw);
+  } else if constexpr (COUT == 16 && CIN <= 16) {
     static_assert((long long)kWgrad27Blocks * CIN * COUT <= (long long)kWgradBlocks * 64 * 64, "partials buffer");
     k_wgrad27<CIN, UPADD><<<kWgrad27Blocks, 256, 0, s>>>(D, H, W, in, in2, dout, u.wpart.as<float>());
     k_wgrad_reduce<<<eblocks(27LL * CIN * COUT), kBlock, 0, s>>>(u.wpart.as<float>(), kWgrad27Blocks, CIN * COUT, gw);
@@ -1703,7 +1777,7 @@ nfa_status wgrad(UNet& u, int layer, bool upadd, int level, const bf16_t* in, co
 #define W_(A, B, U) \
   if (cin == A && cout == B && upadd == U) { wgrad_t<A, B, U>(u, gw, gb, D, H, W, in, in2, dout, s); return NFA_OK; }
   W_(2, 16, false) W_(16, 32, false) W_(32, 64, false) W_(64, 64, false) W_(64, 32, false)
-  W_(32, 16, true) W_(64, 32, true) W_(64, 64, true) W_(16, 16, true) W_(16, 16, false)
+  W_(32, 16, true) W_(64, 32, true) W_(64, 64, true) W_(16, 16, true) W_(16, 16, false) W_(32, 16, false)
 #undef W_
   return fail(NFA_ERR_INVALID, "learned preconditioner: no weight-gradient kernel for this shape");
 }
@@ -1835,7 +1909,16 @@ nfa_status backward(UNet& u, Poisson& op, const float* dz, hipStream_t s) {
   for (int l = 1; l <= L - 2 && e == NFA_OK; ++l) {
     const int ly = u.Dl(l);
     upT_mask(level_channels(l - 1), l, u, B16(u.skip[l - 1]), B16(u.d[l]), B16(u.dd[l]), s);
-    e = wgrad(u, ly, true, l, B16(u.a[l]), B16(u.d[l + 1]), B16(u.dd[l]), s);
+    if (u.cin[ly] == 32 && level_channels(l) == 32) {
+      // the skip sum up(d_(l+1)) + a_l formed once into skip[l] (free until
+      // the data gradient below writes it), then the weights against it
+      int Dl, Hl, Wl;
+      u.dims(l, Dl, Hl, Wl);
+      k_skipsum<32><<<eblocks(u.npos[l] * 4), kBlock, 0, s>>>(Dl, Hl, Wl, B16(u.a[l]), B16(u.d[l + 1]), B16(u.skip[l]));
+      e = wgrad(u, ly, false, l, B16(u.skip[l]), nullptr, B16(u.dd[l]), s);
+    } else {
+      e = wgrad(u, ly, true, l, B16(u.a[l]), B16(u.d[l + 1]), B16(u.dd[l]), s);
+    }
     if (e != NFA_OK) break;
     u.dims(l, D, H, W);
     e = conv(u.cout[ly], u.cin[ly], false, D, H, W, B16(u.dd[l]), nullptr, u.frag_b[ly], nullptr, 0, nullptr,
