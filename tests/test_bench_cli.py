@@ -20,7 +20,7 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 
 def test_measured_traffic_follows_the_committed_summary():
-    v = bench.measured_traffic("k_cg_a<float, 4, 1, true>")
+    v = bench.measured_traffic("k_cg_a<float, 4, 1, true, 1>")
     text = open(os.path.join(ROOT, "profiles", "mg_solve_c3_traffic.md")).read()
     src = "paper_1410_1937_amd/csrc/cg.hip"
     sha = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
