@@ -183,17 +183,21 @@ def test_gradients_loss_and_adam_match_oracle(setup):
     assert np.max(np.abs(net.get_params() - expect)) <= 1e-6
 
 
-def test_backward_stages_and_weight_gradients_one_layer_at_a_time():
+@pytest.mark.parametrize("shape", [(32, 16, 12), (20, 12, 8)])
+def test_backward_stages_and_weight_gradients_one_layer_at_a_time(shape):
     """Every stage of the GPU backward pass, fed with the GPU's own BF16
     operands (activations of the forward, gradients of the stage before),
     against the oracle's same stage: data gradients within one BF16 step,
     weight and bias gradients (FP32 sums of exact BF16 products) within 1e-4
-    of the FP64 sums, and dL/dz against the closed form of the step loss."""
+    of the FP64 sums, and dL/dz against the closed form of the step loss.
+    On 20 x 12 x 8 the rows (20, 10 and 5 cells on the three levels) are not
+    multiples of the weight gradients' 8-position runs, which then cross rows."""
     from paper_1410_1937_amd import nfa
-    wl = fx.small(7, 32, 16, 12, body="sphere")
+    nx, ny, nz = shape
+    wl = fx.small(7, nx, ny, nz, body="sphere")
     og, ob, oop, ob_rhs = oracle_for(wl)
     gg, gop = gpu_for(wl)
-    net = nfa.UNet(32, 16, 12, seed=3)
+    net = nfa.UNet(nx, ny, nz, seed=3)
     rng = np.random.default_rng(15)
     params = ou.init_params(13, zero_last=False)
     params = [(w.astype(np.float32), (rng.standard_normal(b.shape) * 0.05).astype(np.float32)) for w, b in params]
