@@ -1148,20 +1148,20 @@ __global__ __launch_bounds__(256) void k_wgrad(int D, int H, int W, const bf16_t
   }
 }
 
-// The same weight gradient for the shapes with one 16 x 16 output tile
-// (CIN <= 16, COUT = 16), the taps of one z offset (nine) per pass over the
-// positions: their accumulators stay in registers, dout and the positions'
-// coordinates are taken once per chunk of 32 positions and pass, and the
-// input's nine shifted reads of a chunk hit the caches (one workgroup per tap
-// reads dout and the input from memory 27 times).  partial[t][blk][ci][co] as
-// k_wgrad.
+// The same weight gradient for the shapes with at most two 16 x 16 output
+// tiles (CIN, COUT in {16, 32}, (CIN / 16) (COUT / 16) <= 2), the taps of one z
+// offset (nine) per pass over the positions: their accumulators stay in
+// registers, dout and the positions' coordinates are taken once per chunk of
+// 32 positions and pass, and the input's nine shifted reads of a chunk hit the
+// caches (one workgroup per tap reads dout and the input from memory 27
+// times).  partial[t][blk][ci][co] as k_wgrad, over gridDim.x blocks.
 constexpr int kWgrad27Blocks = 1024;
-template <int CIN, bool UPADD>
+template <int CIN, int COUT, bool UPADD>
 __global__ __launch_bounds__(256) void k_wgrad27(int D, int H, int W, const bf16_t* __restrict__ in,
                                                  const bf16_t* __restrict__ in2,
                                                  const bf16_t* __restrict__ dout, float* __restrict__ partial) {
-  static_assert(CIN <= 16, "one 16-channel input tile");
-  constexpr int COUT = 16;
+  constexpr int MT = COUT / 16, NT = (CIN + 15) / 16;
+  static_assert(COUT % 16 == 0 && MT * NT <= 2, "at most two 16 x 16 output tiles");
   __shared__ float red[4][256];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int col = lane & 15, kq = lane >> 4;
@@ -1172,20 +1172,26 @@ __global__ __launch_bounds__(256) void k_wgrad27(int D, int H, int W, const bf16
 #pragma unroll 1
   for (int g = 0; g < 3; ++g) {
     const int dz = g - 1;
-    f32x4 acc[9];
+    f32x4 acc[9][MT][NT];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < 9; ++k)
+#pragma unroll
+      for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b) acc[k][a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (unsigned chunk = blockIdx.x * 4u + wv; chunk < nchunk; chunk += gridDim.x * 4u) {
       const unsigned m0 = chunk * 32u + kq * 8u;
-      // this lane's 8 positions: dout (co = col), and the coordinates in the
-      // plane z + dz (-4 when outside the grid: every tap then falls outside)
-      Frag A;
+      // this lane's 8 positions: dout (co = a 16 + col), and the coordinates
+      // in the plane z + dz (-4 when outside the grid: every tap then falls
+      // outside)
+      Frag A[MT];
       int xs[8], ys[8], zs[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const unsigned m = m0 + j;
         const bool mok = m < N;
-        A.h[j] = mok ? dout[(size_t)m * COUT + col] : (bf16_t)0;
+#pragma unroll
+        for (int a = 0; a < MT; ++a) A[a].h[j] = mok ? dout[(size_t)m * COUT + a * 16 + col] : (bf16_t)0;
         const unsigned r2 = m / (unsigned)W;
         const int zz = (int)(r2 / (unsigned)H) + dz;
         const bool zok = mok && (unsigned)zz < (unsigned)D;
@@ -1196,43 +1202,53 @@ __global__ __launch_bounds__(256) void k_wgrad27(int D, int H, int W, const bf16
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
         const int dy = k / 3 - 1, dx = k % 3 - 1;
-        Frag B;
+        Frag B[NT];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const int yy = ys[j] + dy, xx = xs[j] + dx;
-          const bool ok = col < CIN && (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W;
-          bf16_t v = 0;
-          if (ok) {
-            // element offsets in 32 bits (at most 2^28 cells of 16 channels)
-            const unsigned pe = ((unsigned)(zs[j] * H + yy) * (unsigned)W + (unsigned)xx) * CIN + col;
-            v = in[pe];
-            if constexpr (UPADD) {
-              const unsigned qe =
-                  ((unsigned)((zs[j] >> 1) * H2 + (yy >> 1)) * (unsigned)W2 + (unsigned)(xx >> 1)) * CIN + col;
-              v = f2bf(bf2f(v) + bf2f(in2[qe]));
+          const bool ok = (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W;
+          // element offsets in 32 bits (at most 2^28 cells of 16 channels)
+          const unsigned pe = ok ? ((unsigned)(zs[j] * H + yy) * (unsigned)W + (unsigned)xx) * CIN : 0u;
+          const unsigned qe =
+              ok && UPADD ? ((unsigned)((zs[j] >> 1) * H2 + (yy >> 1)) * (unsigned)W2 + (unsigned)(xx >> 1)) * CIN : 0u;
+#pragma unroll
+          for (int b = 0; b < NT; ++b) {
+            const int ci = b * 16 + col;
+            bf16_t v = 0;
+            if (ok && ci < CIN) {
+              v = in[pe + ci];
+              if constexpr (UPADD) v = f2bf(bf2f(v) + bf2f(in2[qe + ci]));
             }
+            B[b].h[j] = v;
           }
-          B.h[j] = v;
         }
-        acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.v, B.v, acc[k], 0, 0, 0);
+#pragma unroll
+        for (int a = 0; a < MT; ++a)
+#pragma unroll
+          for (int b = 0; b < NT; ++b)
+            acc[k][a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a].v, B[b].v, acc[k][a][b], 0, 0, 0);
         // at most three taps' loads in flight: the registers stay bounded
         if (k % 3 == 2) __builtin_amdgcn_sched_barrier(0);
       }
     }
-    // D[co][ci] per tap: lane holds co = 4 kq + i, ci = col; the four
-    // wavefronts' tiles added in order
+    // D[co][ci] per tap and tile: lane holds co = a 16 + 4 kq + i, ci = b 16
+    // + col; the four wavefronts' tiles added in order
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
+    for (int k = 0; k < 9; ++k)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) red[wv][i * 64 + lane] = acc[k][i];
-      __syncthreads();
-      const int e = threadIdx.x, ln = e & 63, i = e >> 6;
-      const int co = 4 * (ln >> 4) + i, ci = ln & 15;
-      const float sum = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
-      if (ci < CIN)
-        partial[((size_t)(9 * g + k) * gridDim.x + blockIdx.x) * (CIN * COUT) + ci * COUT + co] = sum;
-      __syncthreads();
-    }
+      for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) red[wv][i * 64 + lane] = acc[k][a][b][i];
+          __syncthreads();
+          const int e = threadIdx.x, ln = e & 63, i = e >> 6;
+          const int co = a * 16 + 4 * (ln >> 4) + i, ci = b * 16 + (ln & 15);
+          const float sum = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+          if (ci < CIN)
+            partial[((size_t)(9 * g + k) * gridDim.x + blockIdx.x) * (CIN * COUT) + ci * COUT + co] = sum;
+          __syncthreads();
+        }
   }
 }
 
@@ -1333,9 +1349,17 @@ __global__ void k_skipsum(int D, int H, int W, const bf16_t* __restrict__ a, con
 __global__ void k_wgrad_reduce(const float* __restrict__ partial, int nblk, int per_tap, float* __restrict__ g) {
   GRID_STRIDE(e, 27LL * per_tap) {
     const long long t = e / per_tap, k = e % per_tap;
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += partial[(t * nblk + b) * per_tap + k];
-    g[e] = (float)s;
+    const float* src = partial + t * nblk * per_tap + k;
+    // eight running sums (block b into sum b % 8, their loads independent),
+    // added in a fixed order
+    double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int b = 0;
+    for (; b + 8 <= nblk; b += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s[u] += src[(long long)(b + u) * per_tap];
+    }
+    for (; b < nblk; ++b) s[0] += src[(long long)b * per_tap];
+    g[e] = (float)(((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])));
   }
 }
 
@@ -1753,10 +1777,13 @@ void wgrad_t(UNet& u, float* gw, float* gb, int D, int H, int W, const bf16_t* i
     static_assert((long long)kWgrad27Blocks * CIN * COUT <= (long long)kWgradBlocks * 64 * 64, "partials buffer");
     k_wgrad_c2<kWgrad27Blocks><<<kWgrad27Blocks, 256, 0, s>>>(D, H, W, in, dout, u.wpart.as<float>());
     k_wgrad_reduce<<<eblocks(27LL * CIN * COUT), kBlock, 0, s>>>(u.wpart.as<float>(), kWgrad27Blocks, CIN * COUT, gw);
-  } else if constexpr (COUT == 16 && CIN <= 16) {
-    static_assert((long long)kWgrad27Blocks * CIN * COUT <= (long long)kWgradBlocks * 64 * 64, "partials buffer");
-    k_wgrad27<CIN, UPADD><<<kWgrad27Blocks, 256, 0, s>>>(D, H, W, in, in2, dout, u.wpart.as<float>());
-    k_wgrad_reduce<<<eblocks(27LL * CIN * COUT), kBlock, 0, s>>>(u.wpart.as<float>(), kWgrad27Blocks, CIN * COUT, gw);
+  } else if constexpr ((COUT == 16 || COUT == 32) && (CIN == 16 || CIN == 32) && (CIN / 16) * (COUT / 16) <= 2) {
+    // as many workgroups as the partials buffer takes (27 x 64 x 64 x 64 floats)
+    constexpr int BLK = kWgrad27Blocks * 256 / (CIN * COUT) < kWgrad27Blocks ? kWgrad27Blocks * 256 / (CIN * COUT)
+                                                                            : kWgrad27Blocks;
+    static_assert((long long)BLK * CIN * COUT <= (long long)kWgradBlocks * 64 * 64, "partials buffer");
+    k_wgrad27<CIN, COUT, UPADD><<<BLK, 256, 0, s>>>(D, H, W, in, in2, dout, u.wpart.as<float>());
+    k_wgrad_reduce<<<eblocks(27LL * CIN * COUT), kBlock, 0, s>>>(u.wpart.as<float>(), BLK, CIN * COUT, gw);
   } else {
     dim3 grid(kWgradBlocks, 27);
     k_wgrad<CIN, COUT, UPADD><<<grid, 256, 0, s>>>(D, H, W, in, in2, dout, u.wpart.as<float>());
